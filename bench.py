@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Benchmark of the FR-DG residual + Jacobian-block assembly on one MI355X.
+
+Workload: 2-D compressible Navier-Stokes (gamma 1.4, Re 1000, Pr 0.72), FR-DG
+degree 3 on a 128x128 periodic quad mesh with 5% sinusoidal vertex jitter,
+Rusanov + BR1 fluxes, smooth random state (rho = 1 + 0.1 s, Mach 0.2).  One
+step = R(U) plus the five 64x64 Jacobian blocks of every element (FP32 block
+storage), inputs resident in HBM.  Prints one JSON line.
+
+Options: --gpus N (only 1: this build drives one GPU), --steps K, --warmup W.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Jacobian+RHS DOF/s (% roofline); Newton-GMRES s/step learned vs plain PC"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload():
+    from paper_2105_08632_amd import inputs as I
+    p = 3
+    m = I.quad_mesh(128, degree=p, jitter=0.05)
+    ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
+    U = I.ns2d_state(m, p, seeds=(2, 3, 4), mach=0.2)
+    return m, ph, p, U
+
+
+def jac_bytes_per_element(ns, nv, nd, nf, nface, bytes_out=4):
+    """Algorithmic HBM bytes of one element's block assembly: the blocks
+    written once, the state and the geometry read once."""
+    b = ns * nv
+    out = (1 + nface) * b * b * bytes_out
+    state = ns * nv * 4
+    geom = (2 * ns * nd * nd + ns + nf * nd + nf + nf) * 4 + nface * 4
+    return out + state + geom
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fr_kernels.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2105_08632_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_alg):
+    """HBM bytes per launch of the block-assembly kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "jac_ns2d_p3_128_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(m, ph, p, U, budget_s):
+    """The FP64 oracle (as is) on a bounded sample: the full-mesh residual,
+    then the five Jacobian blocks of a seeded sample of elements."""
+    from oracle import oracle as O
+    o = O.Oracle(m, ph, p)
+    t0 = time.perf_counter()
+    o.rhs(U)
+    t_rhs = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    b = 16 * 4
+    cal = rng.choice(m.n_elem, 16, replace=False)
+    t0 = time.perf_counter()
+    o.jac_blocks(U, cal, b, 4)
+    t_cal = (time.perf_counter() - t0) / len(cal)
+    n = int(max(16, min(m.n_elem, budget_s / max(t_cal, 1e-6))))
+    sample = rng.choice(m.n_elem, n, replace=False)
+    t0 = time.perf_counter()
+    o.jac_blocks(U, sample, b, 4)
+    t_blk = time.perf_counter() - t0
+    t = t_blk + t_rhs * n / m.n_elem
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n * b / t, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"full-mesh R ({t_rhs:.2f} s, scaled to the sample) + 5 Jacobian blocks of {n} of "
+                      f"{m.n_elem} elements ({t_blk:.1f} s); FP64, complex-step columns"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py drives exactly one GPU: this build has no multi-GPU path "
+              "(the element-partitioned design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_08632_amd import fr
+
+    m, ph, p, U = workload()
+    dev = torch.device("cuda:0")
+    Ud = torch.from_numpy(U).to(torch.float32).to(dev).contiguous()
+    ctx = fr.Context(m, ph, "f32")
+    R = ctx.empty_state()
+    B = ctx.block_tensor("f32")
+    dof = ctx.ndof
+
+    def step():
+        ctx.rhs(Ud, R)
+        ctx.jacobian_blocks(Ud, B, "f32")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ctx.set_kernel_timing(True)
+    ctx.kernel_time(0)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    jac_ms, jac_n = ctx.kernel_time(0)
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / args.steps
+
+    per_launch = jac_bytes_per_element(ctx.ns, ctx.nv, 2, ctx.nf, ctx.nface) * ctx.ne
+    avg_jac_s = jac_ms / max(jac_n, 1) / 1e3
+    achieved = per_launch / avg_jac_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch),
+            "kernel": "k_jac (Jacobian block assembly)", "kernel_ms": round(avg_jac_s * 1e3, 4),
+            "alg_bytes_per_launch": per_launch}
+    out = {"metric": METRIC, "value": dof * args.steps / wall, "unit": "DOF/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "2D Navier-Stokes FR-DG p=3, 128x128 jittered periodic quads, "
+                                  "R(U) + 5 Jacobian blocks 64x64 per element (FP32 blocks, FP64 residual)",
+                      "n_elem": ctx.ne, "dof": dof, "gpu_ms_per_step": round(gpu_ms / args.steps, 4)},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m, ph, p, U, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,141 @@
+/* fr.h - C ABI of the MI355X (gfx950) flux-reconstruction library libfr.so.
+ *
+ * The library evaluates the FR-DG spatial residual of a system of
+ * conservation laws, dU/dt = R(U) (Saez-Mischlich, Sierra-Ausin, Gressier,
+ * "The Spectral Difference Raviart-Thomas method for two and three-
+ * dimensional elements and its connection with the Flux Reconstruction
+ * formulation", section 2: FR method, eq. "flux_fr", eq. "divergence_fr"
+ * and the method-of-lines form), its right-hand-side Jacobian dR/dU over the
+ * face-neighbour stencil (section 3, eq. "jacobian_rhs"; section 4 for the
+ * viscous two-layer stencil), exact Jacobian-vector products, and a
+ * block-Jacobi preconditioner for implicit steps.
+ *
+ * Conventions
+ *  - Element types, vertex and face numbering:
+ *      quad [-1,1]^2: v0=(-1,-1) v1=(1,-1) v2=(1,1) v3=(-1,1);
+ *                     faces 0:eta=-1 1:xi=+1 2:eta=+1 3:xi=-1
+ *      hex  [-1,1]^3: v0..v3 as the quad at zeta=-1, v4..v7 at zeta=+1;
+ *                     faces 0:zeta=-1 1:eta=-1 2:xi=+1 3:eta=+1 4:xi=-1 5:zeta=+1
+ *      tri: v0=(-1,-1) v1=(1,-1) v2=(-1,1); faces 0:v0v1 1:v1v2 2:v2v0
+ *  - Solution points of quads/hexes are the tensor Gauss-Legendre points,
+ *    index rho = i + (p+1) j (+ (p+1)^2 k), xi_i ascending (appendix A);
+ *    triangles use the caller's points (tri_sol_pts).
+ *  - State vectors are element-major U[n][rho][alpha] (alpha = conserved
+ *    variable), in the context precision.  DOF index = (n*Ns + rho)*Nv + alpha.
+ *  - Jacobian blocks: for element n, 1 + n_faces blocks of b x b, b = Ns*Nv:
+ *    slot 0 = dR_n/dU_n, slot 1+f = dR_n/dU_{nbr(n,f)}.  Each block is stored
+ *    column-major: blocks[((n*(1+nface) + slot)*b + c)*b + r] with
+ *    r = rho*Nv + alpha (row of R_n), c = sigma*Nv + beta (column of U_k).
+ *    For viscous systems the exact derivative includes every path through the
+ *    neighbours' corrected gradients; blocks of the second face layer (which
+ *    a viscous residual also depends on) are not returned.  fr_jvp is exact.
+ *  - Pointers named U, R, v, Jv, blocks, r, z are DEVICE pointers owned by
+ *    the caller, aligned to the element size.  Mesh arrays are HOST pointers,
+ *    copied during fr_ctx_create.
+ *  - All compute calls are asynchronous on the context stream (the HIP stream
+ *    given at creation; NULL = the default stream).  They allocate nothing.
+ *
+ * Errors: every function returns an fr_status; argument errors return before
+ * anything is launched.  fr_last_error() returns a message for the last
+ * failure of a context (or of creation when ctx is NULL).  No call aborts.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FR_OK = 0,
+  FR_E_INVALID = -1,       /* bad argument or mesh */
+  FR_E_UNSUPPORTED = -2,   /* valid but not provided (element/degree/precision) */
+  FR_E_NOMEM = -3,         /* device allocation failed (creation only) */
+  FR_E_DEVICE = -4,        /* HIP launch or runtime error */
+  FR_E_SINGULAR = -5,      /* a diagonal block has a zero pivot */
+  FR_E_NOT_CONVERGED = -6  /* Newton/GMRES did not reach its tolerance */
+} fr_status;
+
+typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2 } fr_elem_type;
+typedef enum { FR_ADVECTION = 0, FR_EULER = 1, FR_NAVIER_STOKES = 2 } fr_system;
+typedef enum { FR_F64 = 0, FR_F32 = 1, FR_BF16 = 2 } fr_precision;
+
+/* Mesh: the paper's tessellation of the domain into conforming elements
+ * (section 2) with its face-neighbour stencil (section 3).  All elements of
+ * a context share one polynomial degree and one element type. */
+typedef struct {
+  int32_t ndim;               /* 2 or 3 */
+  int64_t n_elem;
+  int32_t degree;             /* p in 1..4 */
+  const int8_t* elem_type;    /* [n_elem] fr_elem_type */
+  const double* elem_xyz;     /* [n_elem][max_vert][ndim] vertex coordinates, unwrapped per element */
+  int32_t max_vert;
+  const int64_t* nbr;         /* [n_elem][max_face] element across each local face (periodic: always set) */
+  const int8_t* nbr_face;     /* [n_elem][max_face] local face index of that face in the neighbour */
+  int32_t max_face;
+  const double* tri_sol_pts;  /* triangles: [Ns][2] reference solution points; else NULL */
+} fr_mesh_desc;
+
+/* Field variables and fluxes (section 2; eq. "flux_advection",
+ * "fluxOperatorEuler", "fluxOperatorNavierStokes"). */
+typedef struct {
+  int32_t system;             /* fr_system */
+  int32_t nvars;              /* 1 (advection), ndim+2 (Euler / Navier-Stokes) */
+  double adv_vel[3];          /* advection velocity */
+  double gamma;               /* ratio of specific heats */
+  double mu;                  /* dynamic viscosity (advection: diffusivity) */
+  double prandtl;
+  double ldg_beta;            /* common-solution / viscous-flux weight; 0 = BR1 */
+  double ldg_penalty;         /* LDG penalty eta; 0 for BR1 */
+} fr_physics;
+
+typedef struct {
+  int32_t ndim, n_sol, n_flux, n_face, nvars, block_dim;
+  int64_t n_elem, n_dof;
+  int64_t blocks_per_elem;    /* 1 + n_face */
+  int32_t precision;          /* fr_precision of states */
+} fr_info;
+
+typedef struct fr_ctx_s fr_ctx;
+typedef struct fr_precond_s fr_precond;
+
+/* Creates a context: builds reference operators and geometry on the host,
+ * uploads them and allocates the workspaces.  precision: FR_F64 or FR_F32
+ * (state vectors and arithmetic).  stream: a hipStream_t or NULL. */
+fr_status fr_ctx_create(const fr_mesh_desc* mesh, const fr_physics* phys, fr_precision precision, void* stream,
+                        fr_ctx** out);
+fr_status fr_ctx_destroy(fr_ctx* ctx);
+fr_status fr_ctx_info(const fr_ctx* ctx, fr_info* info);
+const char* fr_last_error(const fr_ctx* ctx);
+/* Waits for the context stream and reports any asynchronous HIP error. */
+fr_status fr_ctx_sync(fr_ctx* ctx);
+
+/* R = R(U): the FR-DG residual, eq. "divergence_fr" and the method of
+ * lines.  U, R: [n_dof] device arrays in the context precision. */
+fr_status fr_rhs(fr_ctx* ctx, const void* U, void* R);
+
+/* Jacobian blocks dR_n/dU_k, k in {n} and the face neighbours of n (eq.
+ * "jacobian_rhs").  out_prec: FR_F64 (F64 contexts) or FR_F32 / FR_BF16
+ * (F32 contexts; computed in FP32, stored rounded to nearest even).
+ * blocks: n_elem * blocks_per_elem * b * b values, layout above. */
+fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precision out_prec);
+
+/* Jv = dR/dU(U) v exactly (forward-mode tangent of every step, including the
+ * viscous second layer).  R_out (may be NULL) receives R(U). */
+fr_status fr_jvp(fr_ctx* ctx, const void* U, const void* v, void* Jv, void* R_out);
+
+/* Profiling.  When enabled, the dominant kernel of fr_jacobian_blocks
+ * (which = 0: block assembly) and of fr_rhs / fr_jvp (which = 1: the flux /
+ * divergence pass) is bracketed by HIP events on the context stream.
+ * fr_kernel_time waits for the recorded events, returns the summed kernel
+ * time in milliseconds and the number of launches since the previous query,
+ * and resets both.  Enabling creates the events (not a hot call). */
+fr_status fr_set_kernel_timing(fr_ctx* ctx, int enable);
+fr_status fr_kernel_time(fr_ctx* ctx, int which, double* ms_total, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,310 @@
+// C ABI of libfr.so (declared in include/fr.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fr.h"
+#include "fr_ctx.hpp"
+#include "fr_host.hpp"
+
+// ------------------------------------------------------------ registry
+#define FR_DECL(et, p) void fr_reg_##et##_##p(KernelSet*);
+FR_DECL(quad, 1) FR_DECL(quad, 2) FR_DECL(quad, 3) FR_DECL(quad, 4)
+FR_DECL(hex, 1) FR_DECL(hex, 2) FR_DECL(hex, 3) FR_DECL(hex, 4)
+FR_DECL(tri, 1) FR_DECL(tri, 2) FR_DECL(tri, 3) FR_DECL(tri, 4)
+
+static KernelSet g_table[3][5][6];
+static std::once_flag g_once;
+
+static void fill_table() {
+  fr_reg_quad_1(g_table[ET_QUAD][1]); fr_reg_quad_2(g_table[ET_QUAD][2]);
+  fr_reg_quad_3(g_table[ET_QUAD][3]); fr_reg_quad_4(g_table[ET_QUAD][4]);
+  fr_reg_hex_1(g_table[ET_HEX][1]); fr_reg_hex_2(g_table[ET_HEX][2]);
+  fr_reg_hex_3(g_table[ET_HEX][3]); fr_reg_hex_4(g_table[ET_HEX][4]);
+  fr_reg_tri_1(g_table[ET_TRI][1]); fr_reg_tri_2(g_table[ET_TRI][2]);
+  fr_reg_tri_3(g_table[ET_TRI][3]); fr_reg_tri_4(g_table[ET_TRI][4]);
+}
+
+bool fr_find_kernels(int type, int p, int system, int prec, KernelSet* out) {
+  std::call_once(g_once, fill_table);
+  if (type < 0 || type > 2 || p < 1 || p > 4 || system < 0 || system > 2 || prec < 0 || prec > 1) return false;
+  *out = g_table[type][p][system * 2 + prec];
+  return out->rhs != nullptr;
+}
+
+static thread_local std::string g_create_err;
+
+// ------------------------------------------------------------ helpers
+template <class R>
+static void pack_ops(const frh::RefOps& ref, std::vector<char>& blob, std::vector<size_t>& offs) {
+  auto put = [&](const void* src, size_t bytes) {
+    size_t o = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(o + bytes);
+    std::memcpy(blob.data() + o, src, bytes);
+    offs.push_back(o);
+  };
+  auto putR = [&](const std::vector<double>& v) {
+    std::vector<R> t(v.begin(), v.end());
+    put(t.data(), t.size() * sizeof(R));
+  };
+  auto putI = [&](const std::vector<int>& v) { put(v.data(), v.size() * sizeof(int)); };
+  putR(ref.M0); putR(ref.D); putR(ref.Cor); putR(ref.nref); putI(ref.fface);
+  putI(ref.m0c); putR(ref.m0v); putI(ref.dcc); putR(ref.dcv); putI(ref.gc); putR(ref.gv);
+  putI(ref.crc); putR(ref.crv); putI(ref.ddc); putR(ref.ddv);
+}
+
+template <class R> static OpsD<R> ops_view(char* base, const std::vector<size_t>& o) {
+  OpsD<R> v;
+  v.M0 = (const R*)(base + o[0]); v.D = (const R*)(base + o[1]); v.Cor = (const R*)(base + o[2]);
+  v.nref = (const R*)(base + o[3]); v.fface = (const int*)(base + o[4]);
+  v.m0c = (const int*)(base + o[5]); v.m0v = (const R*)(base + o[6]);
+  v.dcc = (const int*)(base + o[7]); v.dcv = (const R*)(base + o[8]);
+  v.gc = (const int*)(base + o[9]); v.gv = (const R*)(base + o[10]);
+  v.crc = (const int*)(base + o[11]); v.crv = (const R*)(base + o[12]);
+  v.ddc = (const int*)(base + o[13]); v.ddv = (const R*)(base + o[14]);
+  return v;
+}
+
+template <class R>
+static void pack_geo(const frh::Geometry& g, std::vector<char>& blob, std::vector<size_t>& offs) {
+  auto put = [&](const void* src, size_t bytes) {
+    size_t o = (blob.size() + 255) & ~(size_t)255;
+    blob.resize(o + bytes);
+    std::memcpy(blob.data() + o, src, bytes);
+    offs.push_back(o);
+  };
+  auto putR = [&](const std::vector<double>& v) {
+    std::vector<R> t(v.begin(), v.end());
+    put(t.data(), t.size() * sizeof(R));
+  };
+  putR(g.S); putR(g.Jinv); putR(g.rdet); putR(g.nrm); putR(g.magN);
+  put(g.nbfp.data(), g.nbfp.size() * sizeof(int));
+  put(g.nbr.data(), g.nbr.size() * sizeof(int));
+}
+
+template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>& o, int ne) {
+  GeoD<R> v;
+  v.ne = ne;
+  v.S = (const R*)(base + o[0]); v.Jinv = (const R*)(base + o[1]); v.rdet = (const R*)(base + o[2]);
+  v.nrm = (const R*)(base + o[3]); v.magN = (const R*)(base + o[4]);
+  v.nbfp = (const int*)(base + o[5]); v.nbr = (const int*)(base + o[6]);
+  return v;
+}
+
+static fr_status fail(fr_ctx_s* c, fr_status s, const std::string& m) {
+  if (c) c->err = m; else g_create_err = m;
+  return s;
+}
+
+static void release(fr_ctx_s* c) {
+  if (!c) return;
+  if (c->ops_mem) (void)hipFree(c->ops_mem);
+  if (c->geo_mem) (void)hipFree(c->geo_mem);
+  if (c->work_mem) (void)hipFree(c->work_mem);
+  for (int w = 0; w < 2; ++w)
+    for (int k = 0; k < fr_ctx_s::kEvPool; ++k)
+      for (int j = 0; j < 2; ++j)
+        if (c->ev[w][k][j]) (void)hipEventDestroy(c->ev[w][k][j]);
+  delete c;
+}
+
+static void drain(fr_ctx_s* c, int w) {
+  if (c->ev_n[w] == 0) return;
+  (void)hipEventSynchronize(c->ev[w][c->ev_n[w] - 1][1]);
+  for (int k = 0; k < c->ev_n[w]; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[w][k][0], c->ev[w][k][1]) == hipSuccess) c->ev_ms[w] += ms;
+  }
+  c->ev_count[w] += c->ev_n[w];
+  c->ev_n[w] = 0;
+}
+
+void fr_time_begin(fr_ctx_s* c, int w) {
+  if (c->ev_n[w] == fr_ctx_s::kEvPool) drain(c, w);
+  (void)hipEventRecord(c->ev[w][c->ev_n[w]][0], c->stream);
+}
+void fr_time_end(fr_ctx_s* c, int w) {
+  (void)hipEventRecord(c->ev[w][c->ev_n[w]][1], c->stream);
+  ++c->ev_n[w];
+}
+
+// ------------------------------------------------------------ ABI
+extern "C" {
+
+fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precision prec, void* stream, fr_ctx** out) {
+  if (!m || !ph || !out) return fail(nullptr, FR_E_INVALID, "null argument");
+  *out = nullptr;
+  if (m->ndim != 2 && m->ndim != 3) return fail(nullptr, FR_E_INVALID, "ndim must be 2 or 3");
+  if (m->n_elem <= 0 || m->n_elem > (int64_t)1 << 26) return fail(nullptr, FR_E_INVALID, "n_elem out of range");
+  if (!m->elem_type || !m->elem_xyz || !m->nbr || !m->nbr_face) return fail(nullptr, FR_E_INVALID, "null mesh array");
+  if (m->degree < 1 || m->degree > 4) return fail(nullptr, FR_E_UNSUPPORTED, "degree must be in 1..4");
+  if (prec != FR_F64 && prec != FR_F32) return fail(nullptr, FR_E_UNSUPPORTED, "state precision must be FR_F64 or FR_F32");
+  const int type = m->elem_type[0];
+  for (int64_t e = 0; e < m->n_elem; ++e)
+    if (m->elem_type[e] != type) return fail(nullptr, FR_E_UNSUPPORTED, "one element type per context");
+  if (type < 0 || type > 2) return fail(nullptr, FR_E_INVALID, "unknown element type");
+  if ((type == FR_HEX) != (m->ndim == 3)) return fail(nullptr, FR_E_INVALID, "element type does not match ndim");
+  if (ph->system < 0 || ph->system > 2) return fail(nullptr, FR_E_INVALID, "unknown system");
+  const int nv = (ph->system == FR_ADVECTION) ? 1 : m->ndim + 2;
+  if (ph->nvars != nv) return fail(nullptr, FR_E_INVALID, "nvars does not match the system");
+  if (ph->system != FR_ADVECTION && !(ph->gamma > 1.0)) return fail(nullptr, FR_E_INVALID, "gamma must exceed 1");
+  if (ph->system == FR_NAVIER_STOKES && !(ph->prandtl > 0.0)) return fail(nullptr, FR_E_INVALID, "prandtl must be positive");
+
+  frh::RefOps ref;
+  std::string err;
+  if (!frh::build_ref(type, m->degree, ph->ldg_beta, m->tri_sol_pts, ref, err)) return fail(nullptr, FR_E_INVALID, err);
+  if (m->max_vert < ref.nvert || m->max_face < ref.nface) return fail(nullptr, FR_E_INVALID, "max_vert/max_face too small");
+  frh::Geometry geo;
+  if (!frh::build_geometry(ref, m->ndim, m->n_elem, m->elem_xyz, m->max_vert, m->nbr, m->nbr_face, m->max_face, geo, err))
+    return fail(nullptr, FR_E_INVALID, err);
+  const bool visc = (ph->system == FR_NAVIER_STOKES) || (ph->system == FR_ADVECTION && ph->mu != 0.0);
+  if (visc && !frh::check_stencil(m->n_elem, ref.nface, geo.nbr.data(), err)) return fail(nullptr, FR_E_UNSUPPORTED, err);
+  if (m->n_elem * ref.nf > ((int64_t)1 << 31) - 1) return fail(nullptr, FR_E_UNSUPPORTED, "mesh too large for 32-bit face indices");
+
+  fr_ctx_s* c = new fr_ctx_s();
+  c->nd = m->ndim; c->type = type; c->p = m->degree; c->system = ph->system; c->nv = nv; c->prec = prec;
+  c->ne = m->n_elem; c->ns = ref.ns; c->nf = ref.nf; c->nface = ref.nface; c->nfp = ref.nfp; c->b = ref.ns * nv;
+  c->visc = visc;
+  for (int i = 0; i < 3; ++i) c->ph.c[i] = ph->adv_vel[i];
+  c->ph.gamma = ph->gamma; c->ph.mu = ph->mu; c->ph.prandtl = ph->prandtl;
+  c->ph.beta = ph->ldg_beta; c->ph.eta = ph->ldg_penalty;
+  c->stream = (hipStream_t)stream;
+  if (!fr_find_kernels(type, m->degree, ph->system, prec, &c->ks)) {
+    release(c);
+    return fail(nullptr, FR_E_UNSUPPORTED, "no kernels for this element type / degree / system / precision");
+  }
+  std::vector<char> ob, gb;
+  std::vector<size_t> oo, go;
+  // FP64 operators and geometry always (residual); FP32 copies for FP32 contexts
+  pack_ops<double>(ref, ob, oo); pack_geo<double>(geo, gb, go);
+  std::vector<size_t> oo32, go32;
+  if (prec == FR_F32) {
+    std::vector<char> o2, g2;
+    pack_ops<float>(ref, o2, oo32); pack_geo<float>(geo, g2, go32);
+    size_t obase = (ob.size() + 255) & ~(size_t)255, gbase = (gb.size() + 255) & ~(size_t)255;
+    ob.resize(obase + o2.size()); std::memcpy(ob.data() + obase, o2.data(), o2.size());
+    gb.resize(gbase + g2.size()); std::memcpy(gb.data() + gbase, g2.data(), g2.size());
+    for (auto& v : oo32) v += obase;
+    for (auto& v : go32) v += gbase;
+  }
+
+  if (hipMalloc(&c->ops_mem, ob.size()) != hipSuccess || hipMalloc(&c->geo_mem, gb.size()) != hipSuccess) {
+    release(c);
+    return fail(nullptr, FR_E_NOMEM, "device allocation failed (operators/geometry)");
+  }
+  if (hipMemcpy(c->ops_mem, ob.data(), ob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->geo_mem, gb.data(), gb.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    release(c);
+    return fail(nullptr, FR_E_DEVICE, "upload failed");
+  }
+  c->opsd = ops_view<double>((char*)c->ops_mem, oo);
+  c->geod = geo_view<double>((char*)c->geo_mem, go, (int)c->ne);
+  if (prec == FR_F32) {
+    c->opsf = ops_view<float>((char*)c->ops_mem, oo32);
+    c->geof = geo_view<float>((char*)c->geo_mem, go32, (int)c->ne);
+  }
+  // workspaces: traces / gradients for the residual, their dual versions for the JVP
+  const size_t rs = (prec == FR_F64) ? 8 : 4;
+  const size_t nuf = (size_t)c->ne * c->nf * nv, nq = (size_t)c->ne * c->ns * c->nd * nv, nqf = (size_t)c->ne * c->nf * c->nd * nv;
+  const bool f32 = prec == FR_F32;
+  size_t sizes[9] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
+                     2 * nuf * rs, visc ? 2 * nq * rs : 0, visc ? 2 * nqf * rs : 0,
+                     f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0};
+  size_t off[9], tot = 0;
+  for (int i = 0; i < 9; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
+  if (hipMalloc(&c->work_mem, tot) != hipSuccess) {
+    release(c);
+    return fail(nullptr, FR_E_NOMEM, "device allocation failed (workspaces)");
+  }
+  char* w = (char*)c->work_mem;
+  c->UF = w + off[0]; c->Q = w + off[1]; c->QF = w + off[2];
+  c->UFd = w + off[3]; c->Qd = w + off[4]; c->QFd = w + off[5];
+  if (f32) { c->UF64 = w + off[6]; c->Q64 = w + off[7]; c->QF64 = w + off[8]; }
+  else { c->UF64 = c->UF; c->Q64 = c->Q; c->QF64 = c->QF; }
+  *out = c;
+  return FR_OK;
+}
+
+fr_status fr_ctx_destroy(fr_ctx* c) {
+  if (!c) return FR_E_INVALID;
+  (void)hipStreamSynchronize(c->stream);
+  release(c);
+  return FR_OK;
+}
+
+fr_status fr_ctx_info(const fr_ctx* c, fr_info* info) {
+  if (!c || !info) return FR_E_INVALID;
+  info->ndim = c->nd; info->n_sol = c->ns; info->n_flux = c->nf; info->n_face = c->nface; info->nvars = c->nv;
+  info->block_dim = c->b; info->n_elem = c->ne; info->n_dof = c->ne * (int64_t)c->b;
+  info->blocks_per_elem = 1 + c->nface; info->precision = c->prec;
+  return FR_OK;
+}
+
+const char* fr_last_error(const fr_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+fr_status fr_ctx_sync(fr_ctx* c) {
+  if (!c) return FR_E_INVALID;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, FR_E_DEVICE, std::string("device: ") + hipGetErrorString(e));
+  return FR_OK;
+}
+
+fr_status fr_set_kernel_timing(fr_ctx* c, int enable) {
+  if (!c) return FR_E_INVALID;
+  if (enable && !c->ev[0][0][0])
+    for (int w = 0; w < 2; ++w)
+      for (int k = 0; k < fr_ctx_s::kEvPool; ++k)
+        for (int j = 0; j < 2; ++j)
+          if (hipEventCreate(&c->ev[w][k][j]) != hipSuccess) return fail(c, FR_E_DEVICE, "hipEventCreate failed");
+  c->timing = enable != 0;
+  return FR_OK;
+}
+
+fr_status fr_kernel_time(fr_ctx* c, int which, double* ms_total, int64_t* count) {
+  if (!c || which < 0 || which > 1 || !ms_total || !count) return FR_E_INVALID;
+  drain(c, which);
+  *ms_total = c->ev_ms[which];
+  *count = c->ev_count[which];
+  c->ev_ms[which] = 0.0;
+  c->ev_count[which] = 0;
+  return FR_OK;
+}
+
+static bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+fr_status fr_rhs(fr_ctx* c, const void* U, void* R) {
+  if (!c) return FR_E_INVALID;
+  const size_t a = c->prec == FR_F64 ? 8 : 4;
+  if (!U || !R || !aligned(U, a) || !aligned(R, a)) return fail(c, FR_E_INVALID, "fr_rhs: null or misaligned pointer");
+  if (U == R) return fail(c, FR_E_INVALID, "fr_rhs: U and R must not alias");
+  int rc = c->ks.rhs(c, U, R);
+  return rc ? (fr_status)rc : FR_OK;
+}
+
+fr_status fr_jvp(fr_ctx* c, const void* U, const void* v, void* Jv, void* Rout) {
+  if (!c) return FR_E_INVALID;
+  const size_t a = c->prec == FR_F64 ? 8 : 4;
+  if (!U || !v || !Jv || !aligned(U, a) || !aligned(v, a) || !aligned(Jv, a) || (Rout && !aligned(Rout, a)))
+    return fail(c, FR_E_INVALID, "fr_jvp: null or misaligned pointer");
+  if (Jv == U || Jv == v || (Rout && (Rout == U || Rout == v || Rout == Jv)))
+    return fail(c, FR_E_INVALID, "fr_jvp: outputs must not alias inputs");
+  int rc = c->ks.jvp(c, U, v, Jv, Rout);
+  return rc ? (fr_status)rc : FR_OK;
+}
+
+fr_status fr_jacobian_blocks(fr_ctx* c, const void* U, void* blocks, fr_precision out_prec) {
+  if (!c) return FR_E_INVALID;
+  const size_t a = c->prec == FR_F64 ? 8 : 4;
+  const size_t ob = out_prec == FR_F64 ? 8 : (out_prec == FR_F32 ? 4 : 2);
+  if (!U || !blocks || !aligned(U, a) || !aligned(blocks, ob))
+    return fail(c, FR_E_INVALID, "fr_jacobian_blocks: null or misaligned pointer");
+  if (out_prec < FR_F64 || out_prec > FR_BF16) return fail(c, FR_E_INVALID, "fr_jacobian_blocks: bad precision");
+  int rc = c->ks.jac(c, U, blocks, (int)out_prec);
+  return rc ? (fr_status)rc : FR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// Library-internal context shared by the C ABI and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "fr_kernels.hpp"
+
+struct fr_ctx_s;
+
+// Type-erased launchers of one (element type, degree, system, precision).
+struct KernelSet {
+  int (*rhs)(fr_ctx_s*, const void* U, void* R);
+  int (*jvp)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
+  int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec);
+};
+
+struct fr_ctx_s {
+  int nd = 0, type = 0, p = 0, system = 0, nv = 0, prec = 0;
+  int64_t ne = 0;
+  int ns = 0, nf = 0, nface = 0, nfp = 0, b = 0;
+  bool visc = false;
+  PhysP ph{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  KernelSet ks{};
+  // device allocations owned by the context
+  void* ops_mem = nullptr;
+  void* geo_mem = nullptr;
+  void* work_mem = nullptr;
+  OpsD<float> opsf{}; OpsD<double> opsd{};
+  GeoD<float> geof{}; GeoD<double> geod{};
+  // workspaces: traces and gradients, real and dual
+  void* UF = nullptr; void* Q = nullptr; void* QF = nullptr;        // context precision
+  void* UF64 = nullptr; void* Q64 = nullptr; void* QF64 = nullptr;  // FP64 residual
+  void* UFd = nullptr; void* Qd = nullptr; void* QFd = nullptr;
+  // optional timing of the dominant kernels with HIP events on the context stream
+  static constexpr int kEvPool = 64;
+  bool timing = false;
+  hipEvent_t ev[2][kEvPool][2] = {};
+  int ev_n[2] = {0, 0};
+  double ev_ms[2] = {0.0, 0.0};
+  long ev_count[2] = {0, 0};
+};
+
+// Brackets a kernel launch with timing events (which: 0 = Jacobian assembly,
+// 1 = residual divergence pass).  Pools are drained when full.
+void fr_time_begin(fr_ctx_s* c, int which);
+void fr_time_end(fr_ctx_s* c, int which);
+
+// Registry lookup implemented by the per-instantiation translation units.
+bool fr_find_kernels(int type, int p, int system, int prec, KernelSet* out);
+
+#define FR_LAUNCH_CHECK(ctx)                                         \
+  do {                                                               \
+    hipError_t e_ = hipGetLastError();                               \
+    if (e_ != hipSuccess) {                                          \
+      (ctx)->err = std::string("kernel launch: ") + hipGetErrorString(e_); \
+      return -4;                                                     \
+    }                                                                \
+  } while (0)

@@ -1,0 +1,549 @@
+// Host-side set-up of the HIP path (see fr_host.hpp).
+//
+// Reference data are built here by a route of their own:
+//   * Gauss-Legendre nodes and weights by the Golub-Welsch method (the
+//     eigen-decomposition of the symmetric Jacobi matrix of the Legendre
+//     recurrence, solved with cyclic Jacobi rotations);
+//   * the nodal basis in barycentric form and its differentiation matrix;
+//   * FR-DG correction functions through the nodal-DG lifting identity: on
+//     Gauss-Legendre solution points the divergence of the correction
+//     function of an end point is l_i(+-1)/w_i (the DG-recovering choice of
+//     the paper's FR section), tensorised along the normal line.
+//   * triangles: orthonormal Dubiner basis from a Gauss-Jacobi quadrature mass
+//     matrix, nodal basis by the inverse Vandermonde, lifting M^{-1} E.
+#include "fr_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+
+namespace frh {
+
+// ---------------------------------------------------------------- 1-D
+static void sym_eigen(int n, std::vector<double>& A, std::vector<double>& V) {
+  V.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * n + q] * A[p * n + q];
+    if (off < 1e-34) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {  // A <- A R
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- R^T A
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+// Golub-Welsch for the Legendre weight on [-1, 1]: nodes ascending.
+static void gl_golub_welsch(int n, std::vector<double>& x, std::vector<double>& w) {
+  std::vector<double> A(n * n, 0.0), V;
+  for (int k = 1; k < n; ++k) {
+    double b = k / std::sqrt(4.0 * k * k - 1.0);
+    A[(k - 1) * n + k] = b;
+    A[k * n + k - 1] = b;
+  }
+  sym_eigen(n, A, V);
+  std::vector<std::pair<double, double>> xw(n);
+  for (int i = 0; i < n; ++i) xw[i] = {A[i * n + i], 2.0 * V[0 * n + i] * V[0 * n + i]};
+  std::sort(xw.begin(), xw.end());
+  x.resize(n); w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    // symmetrise (the rule is exactly symmetric about 0)
+    x[i] = 0.5 * (xw[i].first - xw[n - 1 - i].first);
+    w[i] = 0.5 * (xw[i].second + xw[n - 1 - i].second);
+  }
+}
+
+struct Bary {
+  std::vector<double> x, bw;
+  explicit Bary(const std::vector<double>& xs) : x(xs), bw(xs.size(), 1.0) {
+    for (size_t j = 0; j < x.size(); ++j)
+      for (size_t k = 0; k < x.size(); ++k)
+        if (k != j) bw[j] /= (x[j] - x[k]);
+  }
+  // all basis values at t
+  void eval(double t, std::vector<double>& l) const {
+    const size_t n = x.size();
+    l.assign(n, 0.0);
+    for (size_t j = 0; j < n; ++j)
+      if (t == x[j]) { l[j] = 1.0; return; }
+    double den = 0.0;
+    for (size_t j = 0; j < n; ++j) den += bw[j] / (t - x[j]);
+    for (size_t j = 0; j < n; ++j) l[j] = bw[j] / (t - x[j]) / den;
+  }
+  // D_ij = l_j'(x_i)
+  std::vector<double> diff() const {
+    const size_t n = x.size();
+    std::vector<double> D(n * n, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (size_t j = 0; j < n; ++j)
+        if (j != i) { D[i * n + j] = (bw[j] / bw[i]) / (x[i] - x[j]); s += D[i * n + j]; }
+      D[i * n + i] = -s;
+    }
+    return D;
+  }
+};
+
+static bool compress(const std::vector<double>& M, int rows, int cols, int width, std::vector<int>& c,
+                     std::vector<double>& v) {
+  c.assign(rows * width, 0); v.assign(rows * width, 0.0);
+  for (int r = 0; r < rows; ++r) {
+    int k = 0;
+    for (int j = 0; j < cols; ++j) {
+      double a = M[(size_t)r * cols + j];
+      if (a == 0.0) continue;
+      if (k >= width) return false;
+      c[r * width + k] = j; v[r * width + k] = a; ++k;
+    }
+  }
+  return true;
+}
+
+static void finish_ops(RefOps& R, double beta) {
+  const int nd = R.nd, ns = R.ns, nf = R.nf;
+  R.Dc.assign(nd * ns * ns, 0.0);
+  R.G.assign(nd * ns * ns, 0.0);
+  for (int d = 0; d < nd; ++d)
+    for (int r = 0; r < ns; ++r)
+      for (int s = 0; s < ns; ++s) {
+        double cm = 0.0;
+        for (int g = 0; g < nf; ++g) cm += R.Cor[r * nf + g] * R.nref[g * nd + d] * R.M0[g * ns + s];
+        double dd = R.D[(d * ns + r) * ns + s];
+        R.Dc[(d * ns + r) * ns + s] = dd - cm;
+        R.G[(d * ns + r) * ns + s] = dd - (0.5 + beta) * cm;
+      }
+}
+
+static void build_tensor(RefOps& R, int type, int p) {
+  const int n1 = p + 1;
+  const int nd = (type == QUAD) ? 2 : 3;
+  R.type = type; R.p = p; R.nd = nd;
+  R.ns = (nd == 2) ? n1 * n1 : n1 * n1 * n1;
+  R.nface = 2 * nd;
+  R.nfp = (nd == 2) ? n1 : n1 * n1;
+  R.nf = R.nface * R.nfp;
+  R.nvert = (nd == 2) ? 4 : 8;
+  R.wl = n1; R.wc = 2 * nd;
+  std::vector<double> x, w;
+  gl_golub_welsch(n1, x, w);
+  Bary B(x);
+  std::vector<double> D1 = B.diff(), lp, lm;
+  B.eval(1.0, lp); B.eval(-1.0, lm);
+  std::vector<double> hp(n1), hm(n1);
+  for (int i = 0; i < n1; ++i) { hp[i] = lp[i] / w[i]; hm[i] = lm[i] / w[i]; }
+
+  auto sidx = [&](int r, int d) { return d == 0 ? r % n1 : (d == 1 ? (r / n1) % n1 : r / (n1 * n1)); };
+  R.sp.assign(R.ns * nd, 0.0); R.wsol.assign(R.ns, 1.0);
+  for (int r = 0; r < R.ns; ++r)
+    for (int d = 0; d < nd; ++d) { R.sp[r * nd + d] = x[sidx(r, d)]; R.wsol[r] *= w[sidx(r, d)]; }
+
+  // faces: normal axis / sign, and per flux point the tangential node indices
+  struct F { int ax, sg; };
+  std::vector<F> faces;
+  if (nd == 2) {
+    faces = {{1, -1}, {0, +1}, {1, +1}, {0, -1}};
+    R.face_verts = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
+  } else {
+    faces = {{2, -1}, {1, -1}, {0, +1}, {1, +1}, {0, -1}, {2, +1}};
+    R.face_verts = {{0, 1, 2, 3}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}, {4, 5, 6, 7}};
+  }
+  R.fp.assign(R.nf * nd, 0.0); R.nref.assign(R.nf * nd, 0.0); R.fface.assign(R.nf, 0);
+  std::vector<int> fidx(R.nf * 3, -1);  // node index per axis (-1 on the normal axis)
+  for (int f = 0; f < R.nface; ++f) {
+    int ax = faces[f].ax, sg = faces[f].sg;
+    for (int t = 0; t < R.nfp; ++t) {
+      int g = f * R.nfp + t;
+      R.fface[g] = f;
+      R.nref[g * nd + ax] = sg;
+      int ta = t % n1, tb = t / n1;
+      if (nd == 2) {
+        int other = 1 - ax;
+        int i = (f == 0 || f == 1) ? ta : (n1 - 1 - ta);   // counter-clockwise along the edge
+        fidx[g * 3 + other] = i;
+      } else {
+        int k = 0;
+        for (int d = 0; d < 3; ++d)
+          if (d != ax) fidx[g * 3 + d] = (k++ == 0) ? ta : tb;
+      }
+      for (int d = 0; d < nd; ++d) R.fp[g * nd + d] = (d == ax) ? sg : x[fidx[g * 3 + d]];
+    }
+  }
+  R.M0.assign(R.nf * R.ns, 0.0);
+  R.Cor.assign(R.ns * R.nf, 0.0);
+  for (int g = 0; g < R.nf; ++g) {
+    int f = R.fface[g], ax = faces[f].ax, sg = faces[f].sg;
+    const std::vector<double>& le = (sg > 0) ? lp : lm;
+    const std::vector<double>& he = (sg > 0) ? hp : hm;
+    for (int r = 0; r < R.ns; ++r) {
+      bool on = true;
+      for (int d = 0; d < nd; ++d)
+        if (d != ax && sidx(r, d) != fidx[g * 3 + d]) on = false;
+      if (!on) continue;
+      R.M0[g * R.ns + r] = le[sidx(r, ax)];
+      R.Cor[r * R.nf + g] = he[sidx(r, ax)];
+    }
+  }
+  R.D.assign(nd * R.ns * R.ns, 0.0);
+  for (int d = 0; d < nd; ++d)
+    for (int r = 0; r < R.ns; ++r)
+      for (int s = 0; s < R.ns; ++s) {
+        bool on = true;
+        for (int e = 0; e < nd; ++e)
+          if (e != d && sidx(r, e) != sidx(s, e)) on = false;
+        if (on) R.D[(d * R.ns + r) * R.ns + s] = D1[sidx(r, d) * n1 + sidx(s, d)];
+      }
+}
+
+// ---------------------------------------------------------------- triangles
+// Orthonormal Dubiner basis psi_ij(r,s) and its gradient, by the collapsed
+// coordinates with the scaled recurrences (regular at the top vertex).
+static void dubiner_tri(int i, int j, double r, double s, double& v, double& dr, double& ds) {
+  // Q_k(x,t) = t^k P_k(x/t), x = (1+2r+s)/2, t = (1-s)/2; dQ/dx, dQ/dt
+  double x = 0.5 * (1.0 + 2.0 * r + s), t = 0.5 * (1.0 - s);
+  double q0 = 1.0, q1 = x, qx0 = 0.0, qx1 = 1.0, qt0 = 0.0, qt1 = 0.0;
+  double Q = 1.0, Qx = 0.0, Qt = 0.0;
+  if (i >= 1) { Q = q1; Qx = qx1; Qt = qt1; }
+  for (int k = 2; k <= i; ++k) {
+    double a = (2.0 * k - 1.0) / k, b = (k - 1.0) / k;
+    double q2 = a * x * q1 - b * t * t * q0;
+    double qx2 = a * (q1 + x * qx1) - b * t * t * qx0;
+    double qt2 = a * x * qt1 - b * (2.0 * t * q0 + t * t * qt0);
+    q0 = q1; q1 = q2; qx0 = qx1; qx1 = qx2; qt0 = qt1; qt1 = qt2;
+    Q = q2; Qx = qx2; Qt = qt2;
+  }
+  // Jacobi P_j^{(al,0)}(s) and derivative
+  const double al = 2.0 * i + 1.0;
+  double p0 = 1.0, p1 = 0.5 * (al + 2.0) * s + 0.5 * al, d0 = 0.0, d1 = 0.5 * (al + 2.0);
+  double Pj = 1.0, dPj = 0.0;
+  if (j >= 1) { Pj = p1; dPj = d1; }
+  for (int k = 2; k <= j; ++k) {
+    double a1 = 2.0 * k * (k + al) * (2.0 * k + al - 2.0);
+    double a2 = (2.0 * k + al - 1.0) * (al * al);
+    double a3 = (2.0 * k + al - 2.0) * (2.0 * k + al - 1.0) * (2.0 * k + al);
+    double a4 = 2.0 * (k + al - 1.0) * (k - 1.0) * (2.0 * k + al);
+    double p2 = ((a2 + a3 * s) * p1 - a4 * p0) / a1;
+    double dd2 = ((a2 + a3 * s) * d1 + a3 * p1 - a4 * d0) / a1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = dd2;
+    Pj = p2; dPj = dd2;
+  }
+  double c = std::sqrt((2.0 * i + 1.0) * (i + j + 1.0) / 2.0);
+  // dx/dr = 1, dx/ds = 1/2, dt/dr = 0, dt/ds = -1/2
+  v = c * Q * Pj;
+  dr = c * Qx * Pj;
+  ds = c * ((0.5 * Qx - 0.5 * Qt) * Pj + Q * dPj);
+}
+
+static bool invert_dense(std::vector<double> A, int n, std::vector<double>& inv) {
+  inv.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    for (int k = 0; k < n; ++k) { std::swap(A[c * n + k], A[piv * n + k]); std::swap(inv[c * n + k], inv[piv * n + k]); }
+    double d = A[c * n + c];
+    for (int k = 0; k < n; ++k) { A[c * n + k] /= d; inv[c * n + k] /= d; }
+    for (int r = 0; r < n; ++r)
+      if (r != c) {
+        double f = A[r * n + c];
+        if (f == 0.0) continue;
+        for (int k = 0; k < n; ++k) { A[r * n + k] -= f * A[c * n + k]; inv[r * n + k] -= f * inv[c * n + k]; }
+      }
+  }
+  return true;
+}
+
+static bool build_tri(RefOps& R, int p, const double* pts, std::string& err) {
+  const int n1 = p + 1, ns = (p + 1) * (p + 2) / 2;
+  R.type = TRI; R.p = p; R.nd = 2; R.ns = ns; R.nface = 3; R.nfp = n1; R.nf = 3 * n1; R.nvert = 3;
+  R.wl = ns; R.wc = R.nf;
+  R.face_verts = {{0, 1}, {1, 2}, {2, 0}};
+  R.sp.assign(pts, pts + 2 * ns);
+  std::vector<std::pair<int, int>> modes;
+  for (int i = 0; i <= p; ++i)
+    for (int j = 0; i + j <= p; ++j) modes.push_back({i, j});
+  // V[r][m] = psi_m(x_r); nodal l_s = sum_m Vinv[m][s] psi_m
+  std::vector<double> V(ns * ns), Vr(ns * ns), Vs(ns * ns), Vinv;
+  for (int r = 0; r < ns; ++r)
+    for (int m = 0; m < ns; ++m)
+      dubiner_tri(modes[m].first, modes[m].second, pts[2 * r], pts[2 * r + 1], V[r * ns + m], Vr[r * ns + m], Vs[r * ns + m]);
+  if (!invert_dense(V, ns, Vinv)) { err = "triangle solution points are not unisolvent"; return false; }
+  auto nodal = [&](double r, double s, std::vector<double>& l) {
+    l.assign(ns, 0.0);
+    for (int m = 0; m < ns; ++m) {
+      double v, a, b;
+      dubiner_tri(modes[m].first, modes[m].second, r, s, v, a, b);
+      for (int q = 0; q < ns; ++q) l[q] += Vinv[m * ns + q] * v;
+    }
+  };
+  // derivative matrices D_d[r][s] = sum_m dpsi_m/dxi_d(x_r) Vinv[m][s]
+  R.D.assign(2 * ns * ns, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int s = 0; s < ns; ++s) {
+      double a = 0.0, b = 0.0;
+      for (int m = 0; m < ns; ++m) { a += Vr[r * ns + m] * Vinv[m * ns + s]; b += Vs[r * ns + m] * Vinv[m * ns + s]; }
+      R.D[(0 * ns + r) * ns + s] = a;
+      R.D[(1 * ns + r) * ns + s] = b;
+    }
+  // mass matrix by a collapsed Gauss-Jacobi rule of degree >= 2p
+  std::vector<double> ga, wa;
+  gl_golub_welsch(p + 2, ga, wa);
+  std::vector<double> Mm(ns * ns, 0.0), l;
+  for (int ia = 0; ia < p + 2; ++ia)
+    for (int ib = 0; ib < p + 2; ++ib) {
+      double a = ga[ia], b = ga[ib];
+      double r = 0.5 * (1.0 + a) * (1.0 - b) - 1.0, s = b;
+      double wt = wa[ia] * wa[ib] * 0.5 * (1.0 - b);
+      nodal(r, s, l);
+      for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < ns; ++j) Mm[i * ns + j] += wt * l[i] * l[j];
+    }
+  std::vector<double> Minv;
+  if (!invert_dense(Mm, ns, Minv)) { err = "singular triangle mass matrix"; return false; }
+  std::vector<double> x, w;
+  gl_golub_welsch(n1, x, w);
+  const double E[3][2][2] = {{{-1, -1}, {1, -1}}, {{1, -1}, {-1, 1}}, {{-1, 1}, {-1, -1}}};
+  const double nr[3][2] = {{0, -1}, {M_SQRT1_2, M_SQRT1_2}, {-1, 0}};
+  const double elen[3] = {2.0, 2.0 * M_SQRT2, 2.0};
+  R.fp.assign(R.nf * 2, 0.0); R.nref.assign(R.nf * 2, 0.0); R.fface.assign(R.nf, 0);
+  std::vector<double> fw(R.nf);
+  R.M0.assign(R.nf * ns, 0.0);
+  for (int f = 0; f < 3; ++f)
+    for (int t = 0; t < n1; ++t) {
+      int g = f * n1 + t;
+      double sp = 0.5 * (x[t] + 1.0);
+      R.fp[g * 2] = E[f][0][0] + sp * (E[f][1][0] - E[f][0][0]);
+      R.fp[g * 2 + 1] = E[f][0][1] + sp * (E[f][1][1] - E[f][0][1]);
+      R.nref[g * 2] = nr[f][0]; R.nref[g * 2 + 1] = nr[f][1];
+      R.fface[g] = f;
+      fw[g] = w[t] * elen[f] / 2.0;
+      nodal(R.fp[g * 2], R.fp[g * 2 + 1], l);
+      for (int s = 0; s < ns; ++s) R.M0[g * ns + s] = l[s];
+    }
+  R.Cor.assign(ns * R.nf, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int g = 0; g < R.nf; ++g) {
+      double acc = 0.0;
+      for (int j = 0; j < ns; ++j) acc += Minv[r * ns + j] * R.M0[g * ns + j] * fw[g];
+      R.Cor[r * R.nf + g] = acc;
+    }
+  R.wsol.assign(ns, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int j = 0; j < ns; ++j) R.wsol[r] += Mm[r * ns + j];
+  return true;
+}
+
+bool build_ref(int type, int p, double beta, const double* tri_pts, RefOps& R, std::string& err) {
+  if (p < 1 || p > 4) { err = "degree must be in 1..4"; return false; }
+  if (type == QUAD || type == HEX) build_tensor(R, type, p);
+  else if (type == TRI) {
+    if (!tri_pts) { err = "triangles need tri_sol_pts"; return false; }
+    if (!build_tri(R, p, tri_pts, err)) return false;
+  } else { err = "unknown element type"; return false; }
+  finish_ops(R, beta);
+  bool ok = compress(R.M0, R.nf, R.ns, R.wl, R.m0c, R.m0v) &&
+            compress(R.Dc, R.nd * R.ns, R.ns, R.wl, R.dcc, R.dcv) &&
+            compress(R.G, R.nd * R.ns, R.ns, R.wl, R.gc, R.gv) &&
+            compress(R.Cor, R.ns, R.nf, R.wc, R.crc, R.crv) &&
+            compress(R.D, R.nd * R.ns, R.ns, R.wl, R.ddc, R.ddv);
+  if (!ok) { err = "operator sparsity exceeds the element's row width"; return false; }
+  return true;
+}
+
+// ---------------------------------------------------------------- geometry
+static void shape(int type, const double* xi, double* N, double* dN) {
+  if (type == QUAD) {
+    static const double V[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+    for (int v = 0; v < 4; ++v) {
+      N[v] = 0.25 * (1 + V[v][0] * xi[0]) * (1 + V[v][1] * xi[1]);
+      dN[v * 2] = 0.25 * V[v][0] * (1 + V[v][1] * xi[1]);
+      dN[v * 2 + 1] = 0.25 * (1 + V[v][0] * xi[0]) * V[v][1];
+    }
+  } else if (type == HEX) {
+    static const double V[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                   {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+    for (int v = 0; v < 8; ++v) {
+      double a = 1 + V[v][0] * xi[0], b = 1 + V[v][1] * xi[1], c = 1 + V[v][2] * xi[2];
+      N[v] = 0.125 * a * b * c;
+      dN[v * 3] = 0.125 * V[v][0] * b * c;
+      dN[v * 3 + 1] = 0.125 * a * V[v][1] * c;
+      dN[v * 3 + 2] = 0.125 * a * b * V[v][2];
+    }
+  } else {
+    N[0] = -0.5 * (xi[0] + xi[1]); N[1] = 0.5 * (1 + xi[0]); N[2] = 0.5 * (1 + xi[1]);
+    dN[0] = -0.5; dN[1] = -0.5; dN[2] = 0.5; dN[3] = 0; dN[4] = 0; dN[5] = 0.5;
+  }
+}
+
+static void mapping(const RefOps& R, int nd, const double* X /*[nvert][nd]*/, const double* xi, double* x, double* J) {
+  double N[8], dN[24];
+  shape(R.type, xi, N, dN);
+  for (int i = 0; i < nd; ++i) {
+    x[i] = 0.0;
+    for (int j = 0; j < nd; ++j) J[i * nd + j] = 0.0;
+  }
+  for (int v = 0; v < R.nvert; ++v)
+    for (int i = 0; i < nd; ++i) {
+      x[i] += N[v] * X[v * nd + i];
+      for (int j = 0; j < nd; ++j) J[i * nd + j] += X[v * nd + i] * dN[v * nd + j];
+    }
+}
+
+static double adj(int nd, const double* J, double* S) {
+  if (nd == 2) {
+    S[0] = J[3]; S[1] = -J[1]; S[2] = -J[2]; S[3] = J[0];
+    return J[0] * J[3] - J[1] * J[2];
+  }
+  S[0] = J[4] * J[8] - J[5] * J[7]; S[1] = J[2] * J[7] - J[1] * J[8]; S[2] = J[1] * J[5] - J[2] * J[4];
+  S[3] = J[5] * J[6] - J[3] * J[8]; S[4] = J[0] * J[8] - J[2] * J[6]; S[5] = J[2] * J[3] - J[0] * J[5];
+  S[6] = J[3] * J[7] - J[4] * J[6]; S[7] = J[1] * J[6] - J[0] * J[7]; S[8] = J[0] * J[4] - J[1] * J[3];
+  return J[0] * S[0] + J[1] * S[3] + J[2] * S[6];
+}
+
+bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
+                    const int8_t* nbr_face, int max_face, Geometry& G, std::string& err) {
+  const int ns = R.ns, nf = R.nf;
+  G.nd = nd; G.ns = ns; G.nf = nf; G.nface = R.nface; G.ne = ne;
+  G.S.assign((size_t)ne * ns * nd * nd, 0.0);
+  G.Jinv.assign((size_t)ne * ns * nd * nd, 0.0);
+  G.rdet.assign((size_t)ne * ns, 0.0);
+  G.nrm.assign((size_t)ne * nf * nd, 0.0);
+  G.magN.assign((size_t)ne * nf, 0.0);
+  G.nbfp.assign((size_t)ne * nf, -1);
+  G.nbr.assign((size_t)ne * R.nface, -1);
+  std::vector<double> fx((size_t)ne * nf * nd);
+  char buf[256];
+  for (int64_t e = 0; e < ne; ++e) {
+    const double* X = xyz + (size_t)e * max_vert * nd;
+    double x[3], J[9], S[9];
+    for (int r = 0; r < ns; ++r) {
+      mapping(R, nd, X, &R.sp[r * nd], x, J);
+      double dj = adj(nd, J, S);
+      if (!(dj > 0.0)) {
+        std::snprintf(buf, sizeof buf, "element %lld: non-positive Jacobian determinant", (long long)e);
+        err = buf; return false;
+      }
+      size_t k = (size_t)e * ns + r;
+      G.rdet[k] = 1.0 / dj;
+      for (int i = 0; i < nd * nd; ++i) { G.S[k * nd * nd + i] = S[i]; G.Jinv[k * nd * nd + i] = S[i] / dj; }
+    }
+    for (int g = 0; g < nf; ++g) {
+      mapping(R, nd, X, &R.fp[g * nd], x, J);
+      adj(nd, J, S);
+      double N[3] = {0, 0, 0}, mg = 0.0;
+      for (int i = 0; i < nd; ++i) {
+        for (int d = 0; d < nd; ++d) N[i] += S[d * nd + i] * R.nref[g * nd + d];
+        mg += N[i] * N[i];
+      }
+      mg = std::sqrt(mg);
+      size_t k = (size_t)e * nf + g;
+      G.magN[k] = mg;
+      for (int i = 0; i < nd; ++i) { G.nrm[k * nd + i] = N[i] / mg; fx[k * nd + i] = x[i]; }
+    }
+    for (int f = 0; f < R.nface; ++f) {
+      int64_t m = nbr[e * max_face + f];
+      if (m < 0 || m >= ne) {
+        std::snprintf(buf, sizeof buf, "element %lld face %d: neighbour out of range", (long long)e, f);
+        err = buf; return false;
+      }
+      G.nbr[e * R.nface + f] = (int)m;
+    }
+  }
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int f = 0; f < R.nface; ++f) {
+      int64_t m = nbr[e * max_face + f];
+      int f2 = nbr_face[e * max_face + f];
+      if (f2 < 0 || f2 >= R.nface) { err = "neighbour face index out of range"; return false; }
+      double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0}, sz = 0.0;
+      const std::vector<int>& v1 = R.face_verts[f];
+      const std::vector<int>& v2 = R.face_verts[f2];
+      for (int v : v1)
+        for (int i = 0; i < nd; ++i) c1[i] += xyz[((size_t)e * max_vert + v) * nd + i] / v1.size();
+      for (int v : v2)
+        for (int i = 0; i < nd; ++i) c2[i] += xyz[((size_t)m * max_vert + v) * nd + i] / v2.size();
+      for (int i = 0; i < nd; ++i) {
+        double d = xyz[((size_t)e * max_vert + v1[0]) * nd + i] - c1[i];
+        sz += d * d;
+      }
+      sz = std::sqrt(sz);
+      for (int a = 0; a < R.nfp; ++a) {
+        int g = f * R.nfp + a;
+        int best = -1; double bd = 1e300;
+        for (int b = 0; b < R.nfp; ++b) {
+          int g2 = f2 * R.nfp + b;
+          double d2 = 0.0;
+          for (int i = 0; i < nd; ++i) {
+            double t = (fx[((size_t)e * nf + g) * nd + i] - c1[i]) - (fx[((size_t)m * nf + g2) * nd + i] - c2[i]);
+            d2 += t * t;
+          }
+          if (d2 < bd) { bd = d2; best = g2; }
+        }
+        if (std::sqrt(bd) > 1e-8 * sz) {
+          std::snprintf(buf, sizeof buf, "element %lld face %d: neighbour face points do not coincide", (long long)e, f);
+          err = buf; return false;
+        }
+        G.nbfp[(size_t)e * nf + g] = (int)(m * nf + best);
+      }
+    }
+  }
+  // the pairing must be an involution
+  for (int64_t e = 0; e < ne; ++e)
+    for (int g = 0; g < nf; ++g) {
+      int pg = G.nbfp[(size_t)e * nf + g];
+      if (G.nbfp[(size_t)pg] != (int)(e * nf + g)) { err = "face-point pairing is not symmetric"; return false; }
+    }
+  return true;
+}
+
+bool check_stencil(int64_t ne, int nface, const int* nbr, std::string& err) {
+  char buf[256];
+  for (int64_t n = 0; n < ne; ++n) {
+    std::vector<int> first = {(int)n};
+    for (int f = 0; f < nface; ++f) first.push_back(nbr[n * nface + f]);
+    for (size_t i = 0; i < first.size(); ++i)
+      for (size_t j = i + 1; j < first.size(); ++j)
+        if (first[i] == first[j]) {
+          std::snprintf(buf, sizeof buf, "element %lld: face neighbours are not distinct", (long long)n);
+          err = buf; return false;
+        }
+    for (int f = 0; f < nface; ++f) {
+      int m = nbr[n * nface + f];
+      int back = 0;
+      for (int f2 = 0; f2 < nface; ++f2) {
+        int k = nbr[(int64_t)m * nface + f2];
+        if (k == (int)n) { ++back; continue; }
+        for (int x : first)
+          if (k == x) {
+            std::snprintf(buf, sizeof buf, "element %lld: second face layer folds onto the first", (long long)n);
+            err = buf; return false;
+          }
+      }
+      if (back != 1) { err = "neighbour relation is not symmetric"; return false; }
+    }
+  }
+  return true;
+}
+
+}  // namespace frh

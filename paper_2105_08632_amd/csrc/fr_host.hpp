@@ -1,0 +1,47 @@
+// Host-side set-up of the HIP path: reference operators per (element type,
+// degree) and per-element geometry.  Runs once per context; nothing here is
+// on the timed path.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace frh {
+
+enum { QUAD = 0, TRI = 1, HEX = 2 };
+
+struct RefOps {
+  int type = -1, p = 0, nd = 0, ns = 0, nf = 0, nface = 0, nfp = 0, nvert = 0;
+  int wl = 0, wc = 0;                 // compressed row widths
+  std::vector<double> sp, fp;         // reference solution / flux points
+  std::vector<double> nref;           // [nf][nd]
+  std::vector<int> fface;             // [nf]
+  std::vector<double> M0, D, Cor;     // [nf][ns], [nd][ns][ns], [ns][nf]
+  std::vector<double> Dc, G;          // [nd][ns][ns]
+  std::vector<int> m0c, dcc, gc, crc, ddc; // compressed rows
+  std::vector<double> m0v, dcv, gv, crv, ddv;
+  std::vector<double> wsol;           // quadrature weights at solution points
+  std::vector<std::vector<int>> face_verts;
+};
+
+// Builds the FR-DG reference operators.  beta enters G (self gradient).
+// tri_pts: [ns][2] solution points for triangles (may be null otherwise).
+bool build_ref(int type, int p, double beta, const double* tri_pts, RefOps& out, std::string& err);
+
+struct Geometry {
+  int nd = 0, ns = 0, nf = 0, nface = 0;
+  int64_t ne = 0;
+  std::vector<double> S, Jinv, rdet, nrm, magN;   // per element, element-major
+  std::vector<int> nbfp, nbr;
+};
+
+// Metric terms at solution / flux points and the flux-point pairing across
+// faces, found by matching physical positions relative to the face centroid.
+bool build_geometry(const RefOps& ref, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
+                    const int8_t* nbr_face, int max_face, Geometry& g, std::string& err);
+
+// Checks the truncated viscous Jacobian's assumptions: distinct face
+// neighbours and a second face layer that does not fold back onto the first.
+bool check_stencil(int64_t ne, int nface, const int* nbr, std::string& err);
+
+}  // namespace frh

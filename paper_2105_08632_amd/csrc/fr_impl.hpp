@@ -1,0 +1,130 @@
+// __global__ kernels and their launchers for one (element type, degree,
+// system, precision).  Included by the per-instantiation .hip files.
+#pragma once
+#include <type_traits>
+
+#include "fr_ctx.hpp"
+
+constexpr int kThreads = 256;
+constexpr int kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
+template <class E, int NV, class T, class R, class IO>
+__global__ void __launch_bounds__(kThreads) k_trace(OpsD<R> op, int ne, const IO* U, const IO* V, T* UF) {
+  __shared__ __align__(16) char lds[trace_lds<E, NV, T, R>()];
+  trace_body<E, NV, T, R, IO>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, ne, U, V, UF, DevSync());
+}
+
+template <class E, int NV, class T, class R, class IO>
+__global__ void __launch_bounds__(kThreads) k_grad(OpsD<R> op, GeoD<R> geo, double beta, const IO* U, const IO* V,
+                                                   const T* UF, T* Q, T* QF) {
+  __shared__ __align__(16) char lds[grad_lds<E, NV, T, R>()];
+  grad_body<E, NV, T, R, IO>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, beta, U, V, UF, Q, QF, DevSync());
+}
+
+template <class E, int NV, int SYS, class T, class R, class IO>
+__global__ void __launch_bounds__(kThreads) k_div(OpsD<R> op, GeoD<R> geo, PhysP ph, const IO* U, const IO* V,
+                                                  const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan) {
+  __shared__ __align__(16) char lds[div_lds<E, NV, SYS, T, R>()];
+  div_body<E, NV, SYS, T, R, IO>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, V, UF, Q, QF, Rout,
+                                 Rtan, DevSync());
+}
+
+template <class E, int NV, int SYS, class R, class OT>
+__global__ void __launch_bounds__(kThreads) k_jac(OpsD<R> op, GeoD<R> geo, PhysP ph, const R* U, const R* Q,
+                                                  const R* UF, const R* QF, OT* B) {
+  __shared__ __align__(16) char lds[jac_lds<E, NV, SYS, R>()];
+  jac_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, Q, UF, QF, B, DevSync());
+}
+
+template <class R> OpsD<R>& ctx_ops(fr_ctx_s* c);
+template <> inline OpsD<float>& ctx_ops<float>(fr_ctx_s* c) { return c->opsf; }
+template <> inline OpsD<double>& ctx_ops<double>(fr_ctx_s* c) { return c->opsd; }
+template <class R> GeoD<R>& ctx_geo(fr_ctx_s* c);
+template <> inline GeoD<float>& ctx_geo<float>(fr_ctx_s* c) { return c->geof; }
+template <> inline GeoD<double>& ctx_geo<double>(fr_ctx_s* c) { return c->geod; }
+
+template <int ET, int P, int SYS, class R> struct Impl {
+  typedef Elem<ET, P> E;
+  static constexpr int NV = (SYS == SYS_ADV) ? 1 : E::ND + 2;
+  static constexpr bool VISC = SysTraits<SYS>::kVisc;
+
+  // T: scalar of the evaluation (real or dual), RC: its base precision
+  // (operators and geometry), IO: precision of U, V and the outputs.
+  template <class T, class RC, class IO>
+  static int residual(fr_ctx_s* c, const IO* U, const IO* V, T* UF, T* Q, T* QF, IO* Rout, IO* Rtan) {
+    OpsD<RC> op = ctx_ops<RC>(c);
+    GeoD<RC> geo = ctx_geo<RC>(c);
+    const int ne = (int)c->ne;
+    const int TE = rhs_tile<E>();
+    const int nt = (ne + TE - 1) / TE;
+    hipLaunchKernelGGL((k_trace<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
+    FR_LAUNCH_CHECK(c);
+    if (c->visc) {
+      hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta, U,
+                         V, (const T*)UF, Q, QF);
+      FR_LAUNCH_CHECK(c);
+    }
+    if (c->timing) fr_time_begin(c, 1);
+    hipLaunchKernelGGL((k_div<E, NV, SYS, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph, U, V,
+                       (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan);
+    FR_LAUNCH_CHECK(c);
+    if (c->timing) fr_time_end(c, 1);
+    return 0;
+  }
+
+  // The residual is always evaluated in FP64 (the FR divergence of a flux with
+  // a large mean, e.g. the pressure at low Mach number, loses about
+  // log10(|D| |F| / |R|) digits); FP32 contexts read and write FP32 states.
+  static int rhs(fr_ctx_s* c, const void* U, void* Rout) {
+    return residual<double, double, R>(c, (const R*)U, (const R*)nullptr, (double*)c->UF64, (double*)c->Q64,
+                                       (double*)c->QF64, (R*)Rout, (R*)nullptr);
+  }
+
+  static int jvp(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
+    return residual<Dual<R>, R, R>(c, (const R*)U, (const R*)V, (Dual<R>*)c->UFd, (Dual<R>*)c->Qd,
+                                   (Dual<R>*)c->QFd, (R*)Rv, (R*)Jv);
+  }
+
+  template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B) {
+    if constexpr (jac_lds<E, NV, SYS, R>() > kMaxLds) {
+      c->err = "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
+      return -2;
+    } else {
+    OpsD<R> op = ctx_ops<R>(c);
+    GeoD<R> geo = ctx_geo<R>(c);
+    const int ne = (int)c->ne;
+    const int TE = rhs_tile<E>();
+    const int nt = (ne + TE - 1) / TE;
+    R* UF = (R*)c->UF;
+    R* Q = (R*)c->Q;
+    R* QF = (R*)c->QF;
+    hipLaunchKernelGGL((k_trace<E, NV, R, R, R>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, (const R*)nullptr, UF);
+    FR_LAUNCH_CHECK(c);
+    if (c->visc) {
+      hipLaunchKernelGGL((k_grad<E, NV, R, R, R>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta, U,
+                         (const R*)nullptr, (const R*)UF, Q, QF);
+      FR_LAUNCH_CHECK(c);
+    }
+    if (c->timing) fr_time_begin(c, 0);
+    hipLaunchKernelGGL((k_jac<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo, c->ph, U,
+                       (const R*)Q, (const R*)UF, (const R*)QF, B);
+    FR_LAUNCH_CHECK(c);
+    if (c->timing) fr_time_end(c, 0);
+    return 0;
+    }
+  }
+
+  // out_prec: 0 = f64, 1 = f32, 2 = bf16
+  static int jac(fr_ctx_s* c, const void* U, void* B, int out_prec) {
+    if constexpr (std::is_same<R, double>::value) {
+      if (out_prec == 0) return jac_t<double>(c, (const R*)U, (double*)B);
+    } else {
+      if (out_prec == 1) return jac_t<float>(c, (const R*)U, (float*)B);
+      if (out_prec == 2) return jac_t<bf16_t>(c, (const R*)U, (bf16_t*)B);
+    }
+    c->err = "unsupported block precision for this context precision";
+    return -2;
+  }
+
+  static KernelSet set() { return KernelSet{&rhs, &jvp, &jac}; }
+};

@@ -1,0 +1,713 @@
+// Device code of the FR-DG residual, its tangent (JVP) and the Jacobian-block
+// assembly.  Kernel bodies are written against (tile, thread id, thread
+// count, LDS pointer, barrier) so the same body serves every launch shape.
+//
+// Per element the residual follows the paper's FR formulation:
+//   u^f  = M0 u                                   (eq. "interpolate_sol_to_flux")
+//   C    = u^f + (1/2 + beta) (u^f_nbr - u^f)      (eq. "common_var_for_grad")
+//   q~_d = D_d u + sum_f Cor_f nref_{f,d} (C_f - u^f_f),  q = J^{-T} q~
+//   F~_d = sum_k S_dk f_k(u, q),  S = detJ J^{-1}  (eq. "transformed_quantities")
+//   div  = sum_d D_d F~_d + sum_f Cor_f (|N_f| F(u_L,u_R,q_L,q_R,n_f) - nref_f.M0 F~)
+//                                                  (eq. "divergence_fr")
+//   R    = -div / detJ                             (method of lines)
+// Cor_f is the divergence of the FR-DG correction function of flux point f.
+#pragma once
+#include <type_traits>
+
+#include "dual.hpp"
+#include "physics.hpp"
+
+enum { ET_QUAD = 0, ET_TRI = 1, ET_HEX = 2 };
+
+template <int ET, int P> struct Elem;
+template <int P> struct Elem<ET_QUAD, P> {
+  static constexpr int ET = ET_QUAD, DEG = P, ND = 2, NS = (P + 1) * (P + 1), NFACE = 4, NFP = P + 1,
+                       NF = 4 * (P + 1), NVERT = 4;
+  static constexpr int WL = P + 1;   // non-zeros per row of a line operator (M0, D_d, Dc_d, G_d)
+  static constexpr int WC = 4;       // non-zeros per row of the correction matrix
+};
+template <int P> struct Elem<ET_HEX, P> {
+  static constexpr int ET = ET_HEX, DEG = P, ND = 3, NS = (P + 1) * (P + 1) * (P + 1), NFACE = 6,
+                       NFP = (P + 1) * (P + 1), NF = 6 * (P + 1) * (P + 1), NVERT = 8;
+  static constexpr int WL = P + 1;
+  static constexpr int WC = 6;
+};
+template <int P> struct Elem<ET_TRI, P> {
+  static constexpr int ET = ET_TRI, DEG = P, ND = 2, NS = (P + 1) * (P + 2) / 2, NFACE = 3, NFP = P + 1,
+                       NF = 3 * (P + 1), NVERT = 3;
+  static constexpr int WL = (P + 1) * (P + 2) / 2;
+  static constexpr int WC = 3 * (P + 1);
+};
+
+// Reference operators of one (element type, degree), row-major.  The
+// compressed rows (col, val) list the non-zeros of each row padded to the
+// fixed width of the element (zeros past the end).
+template <class R> struct OpsD {
+  const R* M0;      // [NF][NS]      l_sigma(x_f)
+  const R* D;       // [ND][NS][NS]  d l_sigma/d xi_d (x_rho)
+  const R* Cor;     // [NS][NF]      div g_f (x_rho)
+  const R* nref;    // [NF][ND]      unit reference normals
+  const int* fface; // [NF]          face of each flux point
+  const int* m0c; const R* m0v;    // [NF][WL]
+  const int* dcc; const R* dcv;    // [ND][NS][WL]  Dc_d = D_d - Cor diag(nref_d) M0
+  const int* gc;  const R* gv;     // [ND][NS][WL]  G_d  = D_d - (1/2+beta) Cor diag(nref_d) M0
+  const int* ddc; const R* ddv;    // [ND][NS][WL]  D_d
+  const int* crc; const R* crv;    // [NS][WC]      Cor rows
+};
+
+// Per-element geometry of one group, element-major.
+template <class R> struct GeoD {
+  int ne;
+  const R* S;       // [ne][NS][ND][ND]  detJ J^{-1}
+  const R* Jinv;    // [ne][NS][ND][ND]  J^{-1}: (J^{-1})_{d e} = d xi_d / d x_e
+  const R* rdet;    // [ne][NS]          1/detJ
+  const R* nrm;     // [ne][NF][ND]      unit physical normal (outward)
+  const R* magN;    // [ne][NF]          |S^T nref|
+  const int* nbfp;  // [ne][NF]          m*NF + g' of the flux point paired with g
+  const int* nbr;   // [ne][NFACE]       face neighbours
+};
+
+struct DevSync {
+  __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+
+// LDS bump allocator (16-byte aligned slices).
+struct Lds {
+  char* p;
+  template <class X> FR_HD X* take(int n) {
+    X* r = reinterpret_cast<X*>(p);
+    int bytes = (int)((sizeof(X) * (size_t)n + 15) & ~(size_t)15);
+    p += bytes;
+    return r;
+  }
+};
+template <class X> constexpr int lds_bytes(int n) { return (int)((sizeof(X) * (size_t)n + 15) & ~(size_t)15); }
+
+// Input element i of U (and of the tangent direction V for dual scalars),
+// converted from the I/O type to the compute type.
+template <class T, class R, class IO> struct MakeIn {
+  static FR_HD T get(const IO* U, const IO*, long i) { return T(R(U[i])); }
+};
+template <class R, class IO> struct MakeIn<Dual<R>, R, IO> {
+  static FR_HD Dual<R> get(const IO* U, const IO* V, long i) { return Dual<R>(R(U[i]), R(V[i])); }
+};
+template <class T, class R, class IO> FR_HD T make_in(const IO* U, const IO* V, long i) {
+  return MakeIn<T, R, IO>::get(U, V, i);
+}
+
+template <class E> constexpr int rhs_tile() {
+  return E::NS >= 64 ? 2 : (E::NS >= 25 ? 4 : (E::NS >= 9 ? 8 : 16));
+}
+
+// --------------------------------------------------------------------------
+// Pass 1: face traces u^f = M0 u for a tile of elements.
+template <class E, int NV, class T, class R> constexpr int trace_lds() {
+  return lds_bytes<int>(E::NF * E::WL) + lds_bytes<R>(E::NF * E::WL) + lds_bytes<T>(rhs_tile<E>() * E::NS * NV);
+}
+template <class E, int NV, class T, class R, class IO, class Sync>
+FR_HD void trace_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, int ne, const IO* U, const IO* V,
+                      T* UF, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, WL = E::WL, TE = rhs_tile<E>();
+  Lds L{lds};
+  int* m0c = L.take<int>(NF * WL);
+  R* m0v = L.take<R>(NF * WL);
+  T* su = L.take<T>(TE * NS * NV);
+  const int e0 = tile * TE;
+  const int nte = (ne - e0) < TE ? (ne - e0) : TE;
+  for (int i = tid; i < NF * WL; i += nth) { m0c[i] = op.m0c[i]; m0v[i] = op.m0v[i]; }
+  for (int i = tid; i < nte * NS * NV; i += nth) su[i] = make_in<T, R, IO>(U, V, (long)e0 * NS * NV + i);
+  sync();
+  for (int i = tid; i < nte * NF * NV; i += nth) {
+    int e = i / (NF * NV), g = (i / NV) % NF, a = i % NV;
+    T acc = T(R(0));
+    for (int w = 0; w < WL; ++w) acc += m0v[g * WL + w] * su[(e * NS + m0c[g * WL + w]) * NV + a];
+    UF[(long)e0 * NF * NV + i] = acc;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pass 2 (viscous systems): corrected physical gradient q at solution points
+// and its face trace q^f = M0 q.
+template <class E, int NV, class T, class R> constexpr int grad_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  return lds_bytes<int>(NF * WL) + lds_bytes<R>(NF * WL) + lds_bytes<int>(ND * NS * WL) + lds_bytes<R>(ND * NS * WL) +
+         lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NF * ND) + lds_bytes<T>(TE * NS * NV) +
+         lds_bytes<T>(TE * NF * NV) + lds_bytes<T>(TE * NS * ND * NV);
+}
+template <class E, int NV, class T, class R, class IO, class Sync>
+FR_HD void grad_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, double beta,
+                     const IO* U, const IO* V, const T* UF, T* Q, T* QF, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  Lds L{lds};
+  int* m0c = L.take<int>(NF * WL);
+  R* m0v = L.take<R>(NF * WL);
+  int* ddc = L.take<int>(ND * NS * WL);
+  R* ddv = L.take<R>(ND * NS * WL);
+  int* crc = L.take<int>(NS * WC);
+  R* crv = L.take<R>(NS * WC);
+  R* snr = L.take<R>(NF * ND);
+  T* su = L.take<T>(TE * NS * NV);
+  T* sdf = L.take<T>(TE * NF * NV);
+  T* sq = L.take<T>(TE * NS * ND * NV);
+  const int e0 = tile * TE;
+  const int nte = (geo.ne - e0) < TE ? (geo.ne - e0) : TE;
+  const R cb = R(0.5 + beta);
+  for (int i = tid; i < NF * WL; i += nth) { m0c[i] = op.m0c[i]; m0v[i] = op.m0v[i]; }
+  for (int i = tid; i < ND * NS * WL; i += nth) { ddc[i] = op.ddc[i]; ddv[i] = op.ddv[i]; }
+  for (int i = tid; i < NS * WC; i += nth) { crc[i] = op.crc[i]; crv[i] = op.crv[i]; }
+  for (int i = tid; i < NF * ND; i += nth) snr[i] = op.nref[i];
+  for (int i = tid; i < nte * NS * NV; i += nth) su[i] = make_in<T, R, IO>(U, V, (long)e0 * NS * NV + i);
+  // (C - u^f) = (1/2 + beta)(u^f_nbr - u^f)
+  for (int i = tid; i < nte * NF * NV; i += nth) {
+    int e = i / (NF * NV), g = (i / NV) % NF, a = i % NV;
+    long n = e0 + e;
+    long pg = geo.nbfp[n * NF + g];
+    sdf[i] = cb * (UF[pg * NV + a] - UF[(n * NF + g) * NV + a]);
+  }
+  sync();
+  for (int i = tid; i < nte * NS * NV; i += nth) {
+    int e = i / (NS * NV), r = (i / NV) % NS, a = i % NV;
+    long n = e0 + e;
+    T qt[ND];
+    for (int d = 0; d < ND; ++d) {
+      T acc = T(R(0));
+      for (int w = 0; w < WL; ++w) acc += ddv[(d * NS + r) * WL + w] * su[(e * NS + ddc[(d * NS + r) * WL + w]) * NV + a];
+      for (int w = 0; w < WC; ++w) {
+        int g = crc[r * WC + w];
+        acc += (crv[r * WC + w] * snr[g * ND + d]) * sdf[(e * NF + g) * NV + a];
+      }
+      qt[d] = acc;
+    }
+    const R* Ji = geo.Jinv + (n * NS + r) * ND * ND;
+    for (int d2 = 0; d2 < ND; ++d2) {
+      T acc = T(R(0));
+      for (int d = 0; d < ND; ++d) acc += Ji[d * ND + d2] * qt[d];
+      sq[((e * NS + r) * ND + d2) * NV + a] = acc;
+      Q[((n * NS + r) * ND + d2) * NV + a] = acc;
+    }
+  }
+  sync();
+  for (int i = tid; i < nte * NF * ND * NV; i += nth) {
+    int e = i / (NF * ND * NV), g = (i / (ND * NV)) % NF, d = (i / NV) % ND, a = i % NV;
+    T acc = T(R(0));
+    for (int w = 0; w < WL; ++w) acc += m0v[g * WL + w] * sq[((e * NS + m0c[g * WL + w]) * ND + d) * NV + a];
+    QF[(long)e0 * NF * ND * NV + i] = acc;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pass 3: transformed flux, common flux, FR divergence, R = -div/detJ.
+template <class E, int NV, int SYS, class T, class R> constexpr int div_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  return lds_bytes<int>(NF * WL) + lds_bytes<R>(NF * WL) + lds_bytes<int>(ND * NS * WL) + lds_bytes<R>(ND * NS * WL) +
+         lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NF * ND) + lds_bytes<T>(TE * NS * ND * NV) +
+         lds_bytes<T>(TE * NF * NV);
+}
+template <class E, int NV, int SYS, class T, class R, class IO, class Sync>
+FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
+                    const IO* U, const IO* V, const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  constexpr bool VISC = SysTraits<SYS>::kVisc;
+  Lds L{lds};
+  int* m0c = L.take<int>(NF * WL);
+  R* m0v = L.take<R>(NF * WL);
+  int* ddc = L.take<int>(ND * NS * WL);
+  R* ddv = L.take<R>(ND * NS * WL);
+  int* crc = L.take<int>(NS * WC);
+  R* crv = L.take<R>(NS * WC);
+  R* snr = L.take<R>(NF * ND);
+  T* sFt = L.take<T>(TE * NS * ND * NV);
+  T* sJ = L.take<T>(TE * NF * NV);
+  const int e0 = tile * TE;
+  const int nte = (geo.ne - e0) < TE ? (geo.ne - e0) : TE;
+  const bool visc = VISC && (SYS != SYS_ADV || ph.mu != 0.0);
+  for (int i = tid; i < NF * WL; i += nth) { m0c[i] = op.m0c[i]; m0v[i] = op.m0v[i]; }
+  for (int i = tid; i < ND * NS * WL; i += nth) { ddc[i] = op.ddc[i]; ddv[i] = op.ddv[i]; }
+  for (int i = tid; i < NS * WC; i += nth) { crc[i] = op.crc[i]; crv[i] = op.crv[i]; }
+  for (int i = tid; i < NF * ND; i += nth) snr[i] = op.nref[i];
+  // transformed flux at solution points
+  for (int i = tid; i < nte * NS; i += nth) {
+    int e = i / NS, r = i % NS;
+    long n = e0 + e;
+    T u[NV], f[ND][NV];
+    for (int a = 0; a < NV; ++a) u[a] = make_in<T, R, IO>(U, V, (n * NS + r) * NV + a);
+    flux_inviscid<SYS, ND, NV, T>(ph, u, f);
+    if (visc) {
+      T q[ND][NV], fv[ND][NV];
+      for (int d = 0; d < ND; ++d)
+        for (int a = 0; a < NV; ++a) q[d][a] = Q[((n * NS + r) * ND + d) * NV + a];
+      flux_viscous<SYS, ND, NV, T>(ph, u, q, fv);
+      for (int d = 0; d < ND; ++d)
+        for (int a = 0; a < NV; ++a) f[d][a] += fv[d][a];
+    }
+    const R* Sm = geo.S + (n * NS + r) * ND * ND;
+    for (int d = 0; d < ND; ++d)
+      for (int a = 0; a < NV; ++a) {
+        T acc = T(R(0));
+        for (int k = 0; k < ND; ++k) acc += Sm[d * ND + k] * f[k][a];
+        sFt[((e * NS + r) * ND + d) * NV + a] = acc;
+      }
+  }
+  sync();
+  // common flux minus interpolated normal flux at flux points
+  const R cL = R(0.5 + ph.beta), cR = R(0.5 - ph.beta), eta = R(ph.eta);
+  for (int i = tid; i < nte * NF; i += nth) {
+    int e = i / NF, g = i % NF;
+    long n = e0 + e;
+    long pg = geo.nbfp[n * NF + g];
+    T uL[NV], uR[NV], F[NV];
+    for (int a = 0; a < NV; ++a) { uL[a] = UF[(n * NF + g) * NV + a]; uR[a] = UF[pg * NV + a]; }
+    R nn[ND];
+    for (int d = 0; d < ND; ++d) nn[d] = geo.nrm[(n * NF + g) * ND + d];
+    common_inviscid<SYS, ND, NV, T>(ph, uL, uR, nn, F);
+    if (visc) {
+      T qL[ND][NV], qR[ND][NV], fL[ND][NV], fR[ND][NV];
+      for (int d = 0; d < ND; ++d)
+        for (int a = 0; a < NV; ++a) {
+          qL[d][a] = QF[((n * NF + g) * ND + d) * NV + a];
+          qR[d][a] = QF[(pg * ND + d) * NV + a];
+        }
+      flux_viscous<SYS, ND, NV, T>(ph, uL, qL, fL);
+      flux_viscous<SYS, ND, NV, T>(ph, uR, qR, fR);
+      for (int a = 0; a < NV; ++a) {
+        T acc = eta * (uL[a] - uR[a]);
+        for (int d = 0; d < ND; ++d) acc += nn[d] * (cL * fL[d][a] + cR * fR[d][a]);
+        F[a] += acc;
+      }
+    }
+    R mg = geo.magN[n * NF + g];
+    for (int a = 0; a < NV; ++a) {
+      T fn = T(R(0));
+      for (int d = 0; d < ND; ++d) {
+        T t = T(R(0));
+        for (int w = 0; w < WL; ++w) t += m0v[g * WL + w] * sFt[((e * NS + m0c[g * WL + w]) * ND + d) * NV + a];
+        fn += snr[g * ND + d] * t;
+      }
+      sJ[(e * NF + g) * NV + a] = mg * F[a] - fn;
+    }
+  }
+  sync();
+  for (int i = tid; i < nte * NS * NV; i += nth) {
+    int e = i / (NS * NV), r = (i / NV) % NS, a = i % NV;
+    long n = e0 + e;
+    T acc = T(R(0));
+    for (int d = 0; d < ND; ++d)
+      for (int w = 0; w < WL; ++w)
+        acc += ddv[(d * NS + r) * WL + w] * sFt[((e * NS + ddc[(d * NS + r) * WL + w]) * ND + d) * NV + a];
+    for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * sJ[(e * NF + crc[r * WC + w]) * NV + a];
+    T res = -(geo.rdet[n * NS + r] * acc);
+    long o = (n * NS + r) * NV + a;
+    if (Rout) Rout[o] = IO(val(res));
+    if constexpr (!std::is_same<T, R>::value) {
+      if (Rtan) Rtan[o] = IO(res.d);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Jacobian blocks dR_n/dU_k for k in {n} U face-neighbours(n).
+//
+// Every step between U and R is either a linear reference operator acting on
+// each conserved variable separately, or a pointwise map.  The chain rule
+// therefore gives, for each pair (alpha, beta) of output/input variables,
+// an independent product of scalar operators:
+//   X_d[tau][sigma] = a_d(tau) delta_{tau sigma} [k = n] + sum_e b_de(tau) Gam_e[tau][sigma]
+//   Y[g][sigma]     = fuL(g) DL[g][sigma] + fuR(g) DR[g][sigma]
+//                     + sum_d' fqL_d'(g) SL_d'[g][sigma] + fqR_d'(g) SR_d'[g][sigma]
+//   J[(rho,alpha),(sigma,beta)] = -rdet(rho) (sum_d Dc_d X_d + Cor Y)[rho][sigma]
+// with a_d = dF~_d/du, b_de = dF~_d/dq~_e (solution points), fuL/fuR/fqL/fqR
+// the |N|-scaled derivatives of the common flux (flux points), all taken at
+// entry (alpha, beta); Gam_e = dq~_e/du_k (scalar), SL/SR = derivatives of
+// the own / neighbour physical face gradient w.r.t. u_k, DL/DR the face
+// interpolation of u_k, and Dc_d = D_d - Cor diag(nref_d) M0.  Second-layer
+// blocks of the viscous stencil are not produced (their paths reach R_n only
+// through the neighbour's gradient, with k outside the face stencil).
+// Blocks are written column-major: B[n][k][c][r], r = rho*NV + alpha,
+// c = sigma*NV + beta.
+
+template <class E, int NV, int SYS> struct JacSizes {
+  static constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, NFP = E::NFP, WL = E::WL, WC = E::WC;
+  static constexpr int NV2 = NV * NV;
+  static constexpr bool VISC = SysTraits<SYS>::kVisc;
+  static constexpr int NQ = VISC ? ND : 0;
+};
+
+template <class E, int NV, int SYS, class R> constexpr int jac_lds() {
+  typedef JacSizes<E, NV, SYS> Z;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP, WL = Z::WL, WC = Z::WC,
+                NV2 = Z::NV2;
+  int b = 0;
+  // operators
+  b += lds_bytes<R>(NF * NS) + lds_bytes<R>(NS * NF) + lds_bytes<R>(NF * ND) + lds_bytes<int>(NF);
+  b += lds_bytes<int>(NF * WL) + lds_bytes<R>(NF * WL);
+  b += 2 * (lds_bytes<int>(ND * NS * WL) + lds_bytes<R>(ND * NS * WL));
+  b += lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC);
+  // element data
+  b += lds_bytes<R>(NS * NV) + lds_bytes<R>(NS * ND * NV) + 2 * lds_bytes<R>(NF * NV) + 2 * lds_bytes<R>(NF * ND * NV);
+  b += 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF);
+  b += lds_bytes<R>(NFACE * NFP * NFP * ND);
+  // tables
+  b += lds_bytes<R>(ND * NS * NV2) + lds_bytes<R>(ND * ND * NS * NV2) + 2 * lds_bytes<R>(NF * NV2) +
+       2 * lds_bytes<R>(ND * NF * NV2);
+  // scratch shared by the table build and the per-block sensitivities
+  int t1 = lds_bytes<R>(ND * ND * NS * NV2) + 4 * lds_bytes<R>(NF * NV2);
+  int t2 = 2 * lds_bytes<R>(ND * NS * NS) + 2 * lds_bytes<R>(ND * NF * NS) + 2 * lds_bytes<R>(NF * NS) +
+           lds_bytes<R>(NV * ND * NS * NS) + lds_bytes<R>(NV * NF * NS);
+  b += t1 > t2 ? t1 : t2;
+  return b;
+}
+
+template <class OT> FR_HD OT to_out(float x);
+template <> FR_HD float to_out<float>(float x) { return x; }
+template <class OT> FR_HD OT to_out(double x);
+template <> FR_HD double to_out<double>(double x) { return x; }
+template <> FR_HD float to_out<float>(double x) { return (float)x; }
+// bf16 storage: round-to-nearest-even of the fp32 value.
+struct bf16_t { unsigned short bits; };
+template <> FR_HD bf16_t to_out<bf16_t>(float x) {
+  unsigned int u;
+  __builtin_memcpy(&u, &x, 4);
+  unsigned int lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  bf16_t r; r.bits = (unsigned short)(u >> 16);
+  return r;
+}
+template <> FR_HD bf16_t to_out<bf16_t>(double x) { return to_out<bf16_t>((float)x); }
+
+template <class E, int NV, int SYS, class R, class OT, class Sync>
+FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
+                    const R* U, const R* Q, const R* UF, const R* QF, OT* B, Sync sync) {
+  typedef JacSizes<E, NV, SYS> Z;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP, WL = Z::WL, WC = Z::WC,
+                NV2 = Z::NV2;
+  constexpr int BB = NS * NV;                 // block dimension
+  const bool visc = Z::VISC && (SYS != SYS_ADV || ph.mu != 0.0);
+  const R cb = R(0.5 + ph.beta), cL = R(0.5 + ph.beta), cR = R(0.5 - ph.beta), eta = R(ph.eta);
+  typedef MDual<R, NV> MD;
+
+  Lds L{lds};
+  R* sM0 = L.take<R>(NF * NS);
+  R* sCor = L.take<R>(NS * NF);
+  R* snr = L.take<R>(NF * ND);
+  int* sff = L.take<int>(NF);
+  int* m0c = L.take<int>(NF * WL);
+  R* m0v = L.take<R>(NF * WL);
+  int* dcc = L.take<int>(ND * NS * WL);
+  R* dcv = L.take<R>(ND * NS * WL);
+  int* gcc = L.take<int>(ND * NS * WL);
+  R* gcv = L.take<R>(ND * NS * WL);
+  int* crc = L.take<int>(NS * WC);
+  R* crv = L.take<R>(NS * WC);
+  R* su = L.take<R>(NS * NV);
+  R* sq = L.take<R>(NS * ND * NV);
+  R* suL = L.take<R>(NF * NV);
+  R* suR = L.take<R>(NF * NV);
+  R* sqL = L.take<R>(NF * ND * NV);
+  R* sqR = L.take<R>(NF * ND * NV);
+  R* sJi = L.take<R>(NS * ND * ND);
+  R* sS = L.take<R>(NS * ND * ND);
+  R* srd = L.take<R>(NS);
+  R* snn = L.take<R>(NF * ND);
+  R* smg = L.take<R>(NF);
+  int* spg = L.take<int>(NF);
+  R* sW = L.take<R>(NFACE * NFP * NFP * ND);
+  R* ta = L.take<R>(ND * NS * NV2);        // a[d][tau][ab]
+  R* tb = L.take<R>(ND * ND * NS * NV2);   // b[d][e][tau][ab]
+  R* tuL = L.take<R>(NF * NV2);            // fuL[g][ab]
+  R* tuR = L.take<R>(NF * NV2);
+  R* tqL = L.take<R>(ND * NF * NV2);       // fqL[d'][g][ab]
+  R* tqR = L.take<R>(ND * NF * NV2);
+  char* scratch = L.p;
+  // table-build scratch
+  Lds L1{scratch};
+  R* bh = L1.take<R>(ND * ND * NS * NV2);  // df_k/dq_d' [d'][k][tau][ab]
+  R* rL = L1.take<R>(NF * NV2);
+  R* rR = L1.take<R>(NF * NV2);
+  R* vL = L1.take<R>(NF * NV2);
+  R* vR = L1.take<R>(NF * NV2);
+  // per-block scratch (aliases the table-build scratch)
+  Lds L2{scratch};
+  R* gam = L2.take<R>(ND * NS * NS);       // Gam_e[tau][sigma]
+  R* gamp = L2.take<R>(ND * NS * NS);      // physical: sum_e Jinv[tau][e][d'] Gam_e
+  R* SL = L2.take<R>(ND * NF * NS);
+  R* SR = L2.take<R>(ND * NF * NS);
+  R* DL = L2.take<R>(NF * NS);
+  R* DR = L2.take<R>(NF * NS);
+  R* X = L2.take<R>(NV * ND * NS * NS);    // [alpha][d][tau][sigma] for one beta
+  R* Y = L2.take<R>(NV * NF * NS);         // [alpha][g][sigma]
+
+  // ---- load operators and element data
+  for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
+  for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
+  for (int i = tid; i < NF * ND; i += nth) snr[i] = op.nref[i];
+  for (int i = tid; i < NF; i += nth) sff[i] = op.fface[i];
+  for (int i = tid; i < NF * WL; i += nth) { m0c[i] = op.m0c[i]; m0v[i] = op.m0v[i]; }
+  for (int i = tid; i < ND * NS * WL; i += nth) { dcc[i] = op.dcc[i]; dcv[i] = op.dcv[i]; gcc[i] = op.gc[i]; gcv[i] = op.gv[i]; }
+  for (int i = tid; i < NS * WC; i += nth) { crc[i] = op.crc[i]; crv[i] = op.crv[i]; }
+  const long nl = n;
+  for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
+  if (visc)
+    for (int i = tid; i < NS * ND * NV; i += nth) sq[i] = Q[nl * NS * ND * NV + i];
+  for (int i = tid; i < NF; i += nth) spg[i] = geo.nbfp[nl * NF + i];
+  for (int i = tid; i < NS * ND * ND; i += nth) { sJi[i] = geo.Jinv[nl * NS * ND * ND + i]; sS[i] = geo.S[nl * NS * ND * ND + i]; }
+  for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
+  for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
+  for (int i = tid; i < NF; i += nth) smg[i] = geo.magN[nl * NF + i];
+  sync();
+  for (int i = tid; i < NF * NV; i += nth) {
+    int g = i / NV, a = i % NV;
+    suL[i] = UF[(nl * NF + g) * NV + a];
+    suR[i] = UF[(long)spg[g] * NV + a];
+  }
+  if (visc)
+    for (int i = tid; i < NF * ND * NV; i += nth) {
+      int g = i / (ND * NV), r = i % (ND * NV);
+      sqL[i] = QF[(nl * NF + g) * ND * NV + r];
+      sqR[i] = QF[(long)spg[g] * ND * NV + r];
+    }
+  // W_d'[f][g][g'] for the neighbour gradient's dependence on u_n (self block):
+  // sum_tau' M0[g2][tau'] Cor[tau'][g'] sum_e Jinv_m[tau'][e][d'] nref[g'][e],
+  // g on face f, g2 its partner in m, g' on the shared face f2 of m.
+  if (visc)
+    for (int i = tid; i < NFACE * NFP * NFP * ND; i += nth) {
+      int f = i / (NFP * NFP * ND), gi = (i / (NFP * ND)) % NFP, gj = (i / ND) % NFP, d2 = i % ND;
+      int g = f * NFP + gi;
+      int m = geo.nbr[nl * NFACE + f];
+      int g2 = spg[g] - m * NF;
+      int f2 = op.fface[g2];
+      int gp = f2 * NFP + gj;
+      R acc = R(0);
+      for (int w = 0; w < WL; ++w) {
+        int t = op.m0c[g2 * WL + w];
+        R mv = op.m0v[g2 * WL + w];
+        if (mv == R(0)) continue;
+        R je = R(0);
+        for (int e = 0; e < ND; ++e) je += geo.Jinv[(((long)m * NS + t) * ND + e) * ND + d2] * op.nref[gp * ND + e];
+        acc += mv * op.Cor[t * NF + gp] * je;
+      }
+      sW[i] = cb * acc;
+    }
+  sync();
+
+  // ---- pointwise Jacobian tables (forward mode, NV seeds per pass)
+  {
+    constexpr int NPS = 1 + Z::NQ;                       // passes per solution point
+    constexpr int NPF = Z::VISC ? 4 + 2 * ND : 2;        // passes per flux point
+    const int nsp = visc ? NPS : 1, nfp = visc ? NPF : 2;
+    for (int it = tid; it < NS * nsp + NF * nfp; it += nth) {
+      if (it < NS * nsp) {
+        int t = it / nsp, ps = it % nsp;
+        MD u[NV], f[ND][NV];
+        MD q[ND][NV];
+        for (int a = 0; a < NV; ++a) { u[a] = MD(su[t * NV + a]); if (ps == 0) u[a].d[a] = R(1); }
+        for (int d = 0; d < ND; ++d)
+          for (int a = 0; a < NV; ++a) {
+            q[d][a] = MD(visc ? sq[(t * ND + d) * NV + a] : R(0));
+            if (ps == 1 + d) q[d][a].d[a] = R(1);
+          }
+        if (ps == 0) {
+          flux_inviscid<SYS, ND, NV, MD>(ph, u, f);
+          if (visc) {
+            MD fv[ND][NV];
+            flux_viscous<SYS, ND, NV, MD>(ph, u, q, fv);
+            for (int d = 0; d < ND; ++d)
+              for (int a = 0; a < NV; ++a) f[d][a] += fv[d][a];
+          }
+          for (int d = 0; d < ND; ++d)
+            for (int a = 0; a < NV; ++a)
+              for (int c = 0; c < NV; ++c) {
+                R acc = R(0);
+                for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d[c];
+                ta[(d * NS + t) * NV2 + a * NV + c] = acc;
+              }
+        } else {
+          int d2 = ps - 1;
+          flux_viscous<SYS, ND, NV, MD>(ph, u, q, f);
+          for (int k = 0; k < ND; ++k)
+            for (int a = 0; a < NV; ++a)
+              for (int c = 0; c < NV; ++c) bh[((d2 * ND + k) * NS + t) * NV2 + a * NV + c] = f[k][a].d[c];
+        }
+      } else {
+        int j = it - NS * nsp;
+        int g = j / nfp, ps = j % nfp;
+        R nn[ND];
+        for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
+        if (ps < 2) {
+          MD uL[NV], uR[NV], F[NV];
+          for (int a = 0; a < NV; ++a) {
+            uL[a] = MD(suL[g * NV + a]); uR[a] = MD(suR[g * NV + a]);
+            if (ps == 0) uL[a].d[a] = R(1); else uR[a].d[a] = R(1);
+          }
+          common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
+          R* o = ps == 0 ? rL : rR;
+          for (int a = 0; a < NV; ++a)
+            for (int c = 0; c < NV; ++c) o[g * NV2 + a * NV + c] = F[a].d[c];
+        } else {
+          int pp = ps - 2;
+          int side = (pp == 0 || (pp >= 2 && pp < 2 + ND)) ? 0 : 1;   // 0: L, 1: R
+          int qd = (pp >= 2) ? ((pp - 2) % ND) : -1;                   // seeded gradient direction
+          if (pp == 1) { side = 1; qd = -1; }
+          if (pp >= 2 + ND) side = 1;
+          const R* us = side ? suR : suL;
+          const R* qs = side ? sqR : sqL;
+          MD u[NV], q[ND][NV], fv[ND][NV];
+          for (int a = 0; a < NV; ++a) { u[a] = MD(us[g * NV + a]); if (qd < 0) u[a].d[a] = R(1); }
+          for (int d = 0; d < ND; ++d)
+            for (int a = 0; a < NV; ++a) {
+              q[d][a] = MD(qs[(g * ND + d) * NV + a]);
+              if (qd == d) q[d][a].d[a] = R(1);
+            }
+          flux_viscous<SYS, ND, NV, MD>(ph, u, q, fv);
+          R wgt = side ? cR : cL;
+          R mg = smg[g];
+          for (int a = 0; a < NV; ++a)
+            for (int c = 0; c < NV; ++c) {
+              R acc = R(0);
+              for (int d = 0; d < ND; ++d) acc += nn[d] * fv[d][a].d[c];
+              acc *= wgt;
+              if (qd < 0) (side ? vR : vL)[g * NV2 + a * NV + c] = acc;
+              else (side ? tqR : tqL)[(qd * NF + g) * NV2 + a * NV + c] = mg * acc;
+            }
+        }
+      }
+    }
+    sync();
+    // b_de = sum_k S_dk sum_d' (df_k/dq_d') Jinv[e][d']
+    if (visc)
+      for (int i = tid; i < ND * ND * NS * NV2; i += nth) {
+        int d = i / (ND * NS * NV2), e = (i / (NS * NV2)) % ND, t = (i / NV2) % NS, ab = i % NV2;
+        R acc = R(0);
+        for (int k = 0; k < ND; ++k) {
+          R s = sS[(t * ND + d) * ND + k];
+          for (int d2 = 0; d2 < ND; ++d2) acc += s * bh[((d2 * ND + k) * NS + t) * NV2 + ab] * sJi[(t * ND + e) * ND + d2];
+        }
+        tb[i] = acc;
+      }
+    for (int i = tid; i < NF * NV2; i += nth) {
+      int g = i / NV2, ab = i % NV2;
+      int a = ab / NV, c = ab % NV;
+      R mg = smg[g];
+      R id = (a == c) ? eta : R(0);
+      R l = rL[i] + (visc ? vL[i] + id : R(0));
+      R r = rR[i] + (visc ? vR[i] - id : R(0));
+      tuL[i] = mg * l;
+      tuR[i] = mg * r;
+    }
+    sync();
+  }
+
+  // ---- blocks
+  OT* Bn = B + nl * (long)(1 + NFACE) * BB * BB;
+  for (int k = 0; k <= NFACE; ++k) {
+    const int f = k - 1;                 // face of the neighbour block (k >= 1)
+    const int m = (k == 0) ? n : geo.nbr[nl * NFACE + f];
+    // Gam_e[tau][sigma] = d q~_e(tau) / d u_k(sigma)
+    for (int i = tid; i < ND * NS * NS; i += nth) {
+      int e = i / (NS * NS), t = (i / NS) % NS, s = i % NS;
+      R v = R(0);
+      if (visc) {
+        if (k == 0) {
+          for (int w = 0; w < WL; ++w)
+            if (gcc[(e * NS + t) * WL + w] == s) v += gcv[(e * NS + t) * WL + w];
+        } else {
+          for (int gi = 0; gi < NFP; ++gi) {
+            int g = f * NFP + gi;
+            R c = sCor[t * NF + g] * snr[g * ND + e];
+            if (c != R(0)) v += c * op.M0[(spg[g] - m * NF) * NS + s];
+          }
+          v *= cb;
+        }
+      }
+      gam[i] = v;
+    }
+    for (int i = tid; i < NF * NS; i += nth) {
+      int g = i / NS, s = i % NS;
+      DL[i] = (k == 0) ? sM0[i] : R(0);
+      DR[i] = (k > 0 && sff[g] == f) ? sM0[(spg[g] - m * NF) * NS + s] : R(0);
+    }
+    sync();
+    if (visc) {
+      for (int i = tid; i < ND * NS * NS; i += nth) {
+        int d2 = i / (NS * NS), t = (i / NS) % NS, s = i % NS;
+        R acc = R(0);
+        for (int e = 0; e < ND; ++e) acc += sJi[(t * ND + e) * ND + d2] * gam[(e * NS + t) * NS + s];
+        gamp[i] = acc;
+      }
+      // SR: derivative of the neighbour's physical face gradient
+      for (int i = tid; i < ND * NF * NS; i += nth) {
+        int d2 = i / (NF * NS), g = (i / NS) % NF, s = i % NS;
+        int fg = sff[g];
+        R acc = R(0);
+        if (k == 0) {
+          int mm = geo.nbr[nl * NFACE + fg];
+          int g2 = spg[g] - mm * NF;
+          int f2 = sff[g2];
+          int gi = g - fg * NFP;
+          for (int gj = 0; gj < NFP; ++gj) {
+            int gp = f2 * NFP + gj;
+            int back = geo.nbfp[(long)mm * NF + gp] - n * NF;   // partner of gp in n
+            acc += sW[((fg * NFP + gi) * NFP + gj) * ND + d2] * sM0[back * NS + s];
+          }
+        } else if (fg == f) {
+          int g2 = spg[g] - m * NF;
+          for (int w = 0; w < WL; ++w) {
+            int t = m0c[g2 * WL + w];
+            R mv = m0v[g2 * WL + w];
+            if (mv == R(0)) continue;
+            R gsum = R(0);
+            for (int e = 0; e < ND; ++e) {
+              R ge = R(0);
+              for (int w2 = 0; w2 < WL; ++w2)
+                if (gcc[(e * NS + t) * WL + w2] == s) ge += gcv[(e * NS + t) * WL + w2];
+              gsum += geo.Jinv[(((long)m * NS + t) * ND + e) * ND + d2] * ge;
+            }
+            acc += mv * gsum;
+          }
+        }
+        SR[i] = acc;
+      }
+      sync();
+      for (int i = tid; i < ND * NF * NS; i += nth) {
+        int d2 = i / (NF * NS), g = (i / NS) % NF, s = i % NS;
+        R acc = R(0);
+        for (int w = 0; w < WL; ++w) acc += m0v[g * WL + w] * gamp[(d2 * NS + m0c[g * WL + w]) * NS + s];
+        SL[i] = acc;
+      }
+    }
+    sync();
+    OT* Bk = Bn + (long)k * BB * BB;
+    for (int beta = 0; beta < NV; ++beta) {
+      // X[alpha][d][tau][sigma], Y[alpha][g][sigma]
+      for (int i = tid; i < NV * ND * NS * NS; i += nth) {
+        int a = i / (ND * NS * NS), d = (i / (NS * NS)) % ND, t = (i / NS) % NS, s = i % NS;
+        int ab = a * NV + beta;
+        R v = (k == 0 && t == s) ? ta[(d * NS + t) * NV2 + ab] : R(0);
+        if (visc)
+          for (int e = 0; e < ND; ++e) v += tb[((d * ND + e) * NS + t) * NV2 + ab] * gam[(e * NS + t) * NS + s];
+        X[i] = v;
+      }
+      for (int i = tid; i < NV * NF * NS; i += nth) {
+        int a = i / (NF * NS), g = (i / NS) % NF, s = i % NS;
+        int ab = a * NV + beta;
+        R v = tuL[g * NV2 + ab] * DL[g * NS + s] + tuR[g * NV2 + ab] * DR[g * NS + s];
+        if (visc)
+          for (int d2 = 0; d2 < ND; ++d2)
+            v += tqL[(d2 * NF + g) * NV2 + ab] * SL[(d2 * NF + g) * NS + s] +
+                 tqR[(d2 * NF + g) * NV2 + ab] * SR[(d2 * NF + g) * NS + s];
+        Y[i] = v;
+      }
+      sync();
+      // columns c = sigma*NV + beta, rows r = rho*NV + alpha
+      for (int i = tid; i < NS * NS * NV; i += nth) {
+        int s = i / (NS * NV), r = (i / NV) % NS, a = i % NV;
+        R acc = R(0);
+        for (int d = 0; d < ND; ++d)
+          for (int w = 0; w < WL; ++w)
+            acc += dcv[(d * NS + r) * WL + w] * X[((a * ND + d) * NS + dcc[(d * NS + r) * WL + w]) * NS + s];
+        for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * Y[(a * NF + crc[r * WC + w]) * NS + s];
+        Bk[(long)(s * NV + beta) * BB + r * NV + a] = to_out<OT>(-(srd[r] * acc));
+      }
+      sync();
+    }
+  }
+}

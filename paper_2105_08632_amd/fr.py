@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libfr.so (include/fr.h).
+
+Argument marshalling only: every step of the residual, Jacobian and JVP runs
+in the library's HIP kernels.  Device arrays are torch tensors on the GPU
+(PyTorch provides the memory and the stream).  A missing library is an
+error; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfr.so")
+
+FR_F64, FR_F32, FR_BF16 = 0, 1, 2
+_PREC = {"f64": FR_F64, "f32": FR_F32, "bf16": FR_BF16}
+_STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_UNSUPPORTED", -3: "FR_E_NOMEM", -4: "FR_E_DEVICE",
+           -5: "FR_E_SINGULAR", -6: "FR_E_NOT_CONVERGED"}
+
+EXPORTED = ["fr_ctx_create", "fr_ctx_destroy", "fr_ctx_info", "fr_last_error", "fr_ctx_sync", "fr_rhs",
+            "fr_jacobian_blocks", "fr_jvp", "fr_set_kernel_timing", "fr_kernel_time"]
+
+
+class FrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n_elem", C.c_int64), ("degree", C.c_int32),
+                ("elem_type", C.c_void_p), ("elem_xyz", C.c_void_p), ("max_vert", C.c_int32),
+                ("nbr", C.c_void_p), ("nbr_face", C.c_void_p), ("max_face", C.c_int32),
+                ("tri_sol_pts", C.c_void_p)]
+
+
+class _Phys(C.Structure):
+    _fields_ = [("system", C.c_int32), ("nvars", C.c_int32), ("adv_vel", C.c_double * 3),
+                ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
+                ("ldg_beta", C.c_double), ("ldg_penalty", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n_sol", C.c_int32), ("n_flux", C.c_int32), ("n_face", C.c_int32),
+                ("nvars", C.c_int32), ("block_dim", C.c_int32), ("n_elem", C.c_int64), ("n_dof", C.c_int64),
+                ("blocks_per_elem", C.c_int64), ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libfr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2105_08632_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.fr_ctx_create.argtypes = [C.POINTER(_Mesh), C.POINTER(_Phys), C.c_int, P, C.POINTER(P)]
+        L.fr_ctx_destroy.argtypes = [P]
+        L.fr_ctx_info.argtypes = [P, C.POINTER(_Info)]
+        L.fr_last_error.argtypes = [P]
+        L.fr_last_error.restype = C.c_char_p
+        L.fr_ctx_sync.argtypes = [P]
+        L.fr_rhs.argtypes = [P, P, P]
+        L.fr_jacobian_blocks.argtypes = [P, P, P, C.c_int]
+        L.fr_jvp.argtypes = [P, P, P, P, P]
+        L.fr_set_kernel_timing.argtypes = [P, C.c_int]
+        L.fr_kernel_time.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        for name in EXPORTED:
+            getattr(L, name).restype = C.c_int if name != "fr_last_error" else C.c_char_p
+        _lib = L
+        _extend(L)
+    return _lib
+
+
+_extensions = []
+
+
+def _extend(L):
+    for f in _extensions:
+        f(L)
+
+
+def _check(rc: int, ctx=None):
+    if rc != 0:
+        msg = lib().fr_last_error(ctx).decode()
+        raise FrError(rc, msg)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Context:
+    """One mesh + physics + precision on one HIP stream."""
+
+    def __init__(self, mesh, phys, precision: str = "f64", stream=None, tri_pts=None):
+        import torch
+        L = lib()
+        self.mesh, self.phys = mesh, phys
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self._keep = [np.ascontiguousarray(mesh.elem_type, dtype=np.int8),
+                      np.ascontiguousarray(mesh.xyz, dtype=np.float64),
+                      np.ascontiguousarray(mesh.nbr, dtype=np.int64),
+                      np.ascontiguousarray(mesh.nbr_face, dtype=np.int8)]
+        tp = None if tri_pts is None else np.ascontiguousarray(tri_pts, dtype=np.float64)
+        self._keep.append(tp)
+        m = _Mesh(mesh.ndim, mesh.n_elem, int(mesh.degree[0]),
+                  self._keep[0].ctypes.data, self._keep[1].ctypes.data, mesh.max_vert,
+                  self._keep[2].ctypes.data, self._keep[3].ctypes.data, mesh.max_face,
+                  None if tp is None else tp.ctypes.data)
+        ph = _Phys(phys.system, phys.nvars, (C.c_double * 3)(*[float(x) for x in phys.adv_vel]),
+                   phys.gamma, phys.mu, phys.prandtl, phys.beta, phys.eta)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.fr_ctx_create(C.byref(m), C.byref(ph), _PREC[precision], C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise FrError(rc, L.fr_last_error(None).decode())
+        self.h = h
+        info = _Info()
+        _check(L.fr_ctx_info(h, C.byref(info)), h)
+        self.info = info
+        self.ns, self.nf, self.nface = info.n_sol, info.n_flux, info.n_face
+        self.nv, self.b, self.ne, self.ndof = info.nvars, info.block_dim, info.n_elem, info.n_dof
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, x):
+        if x.dtype != self.dtype or not x.is_cuda or not x.is_contiguous() or x.numel() != self.ndof:
+            raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor with {self.ndof} entries")
+        return x
+
+    def empty_state(self):
+        import torch
+        return torch.empty(self.ne, self.ns, self.nv, dtype=self.dtype, device="cuda")
+
+    def rhs(self, U, out=None):
+        U = self._vec(U)
+        out = self.empty_state() if out is None else self._vec(out)
+        _check(lib().fr_rhs(self.h, _ptr(U), _ptr(out)), self.h)
+        return out
+
+    def jvp(self, U, v, out=None, R_out=None):
+        U, v = self._vec(U), self._vec(v)
+        out = self.empty_state() if out is None else self._vec(out)
+        Rp = None if R_out is None else _ptr(self._vec(R_out))
+        _check(lib().fr_jvp(self.h, _ptr(U), _ptr(v), _ptr(out), Rp), self.h)
+        return out
+
+    def block_tensor(self, out_prec: str):
+        import torch
+        dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[out_prec]
+        return torch.empty(self.ne, 1 + self.nface, self.b, self.b, dtype=dt, device="cuda")
+
+    def jacobian_blocks(self, U, out=None, out_prec: str | None = None):
+        """Blocks [n, slot, c, r] (each block column-major: index [c][r])."""
+        U = self._vec(U)
+        if out_prec is None:
+            out_prec = self.precision
+        if out is None:
+            out = self.block_tensor(out_prec)
+        _check(lib().fr_jacobian_blocks(self.h, _ptr(U), _ptr(out), _PREC[out_prec]), self.h)
+        return out
+
+    def sync(self):
+        _check(lib().fr_ctx_sync(self.h), self.h)
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(lib().fr_set_kernel_timing(self.h, int(enable)), self.h)
+
+    def kernel_time(self, which: int = 0):
+        """(total ms, launches) of the timed kernel since the last query."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(lib().fr_kernel_time(self.h, which, C.byref(ms), C.byref(n)), self.h)
+        return ms.value, n.value

@@ -1,0 +1,168 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Error metric: normwise relative, max|x - x_ref| / max|x_ref| per array, the
+oracle evaluated on exactly the inputs the GPU saw (states rounded to the
+device precision first).  Bars: 1e-12 (FP64), 1e-5 (FP32), 2e-2 (BF16).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_08632_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}
+
+
+def _ctx(m, ph, prec):
+    from paper_2105_08632_amd import fr
+    return fr.Context(m, ph, prec)
+
+
+def rel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.max(np.abs(x - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def _dev(a, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda().contiguous()
+
+
+def _blocks_rowmajor(B):
+    """[n, slot, c, r] (column-major blocks) -> numpy [n, slot, r, c] fp64."""
+    return B.float().double().cpu().numpy().transpose(0, 1, 3, 2) if B.dtype == torch.bfloat16 else \
+        B.double().cpu().numpy().transpose(0, 1, 3, 2)
+
+
+def check_case(m, ph, p, U, prec, elems, blocks=True, jvp=True):
+    Ud = _dev(U, prec)
+    Uq = Ud.double().cpu().numpy()            # the rounded input the GPU sees
+    o = O.Oracle(m, ph, p)
+    ctx = _ctx(m, ph, prec)
+    R = ctx.rhs(Ud)
+    torch.cuda.synchronize()
+    ctx.sync()
+    e_r = rel(R.double().cpu().numpy().reshape(-1), o.rhs(Uq))
+    out = {"R": e_r}
+    if jvp:
+        v = I.random_direction(U.size, 11).reshape(U.shape)
+        vd = _dev(v, prec)
+        vq = vd.double().cpu().numpy()
+        Jv = ctx.jvp(Ud, vd)
+        out["Jv"] = rel(Jv.double().cpu().numpy().reshape(-1), o.jvp(Uq, vq))
+    if blocks:
+        B = ctx.jacobian_blocks(Ud)
+        Bn = _blocks_rowmajor(B)
+        Bo = o.jac_blocks(Uq, elems, ctx.b, ctx.nface)
+        out["blocks"] = max(rel(Bn[e], Bo[i]) for i, e in enumerate(elems))
+    ctx.sync()
+    return out
+
+
+def _assert(out, prec, tag=""):
+    for k, v in out.items():
+        assert v <= TOL[prec], (tag, k, v, out)
+
+
+def test_advection_cfg0_fp64_full_jacobian():
+    """8x8 periodic quads, p=2, c=(1,0.5): R and the full 576x576 Jacobian."""
+    p = 2
+    m = I.quad_mesh(8, degree=p)
+    ph = I.advection_physics((1.0, 0.5))
+    U = I.advection_state(m, p, seed=1)
+    o = O.Oracle(m, ph, p)
+    ctx = _ctx(m, ph, "f64")
+    Ud = _dev(U, "f64")
+    R = ctx.rhs(Ud).cpu().numpy().reshape(-1)
+    assert rel(R, o.rhs(U)) <= 1e-12
+    B = _blocks_rowmajor(ctx.jacobian_blocks(Ud))
+    b = 9
+    J = np.zeros((576, 576))
+    for n in range(m.n_elem):
+        for s, k in enumerate([n] + [int(x) for x in m.nbr[n]]):
+            J[n * b:(n + 1) * b, k * b:(k + 1) * b] += B[n, s]
+    Jo = o.jac_full(U.reshape(-1))
+    assert rel(J, Jo) <= 1e-12
+    # R(U) = J U for the linear residual, with the assembled GPU Jacobian
+    assert rel(J @ U.reshape(-1), R) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("system", ["adv", "euler", "ns"])
+def test_quad_fp64(p, system):
+    N = 5
+    m = I.quad_mesh(N, degree=p, jitter=0.05, K=1)
+    if system == "adv":
+        ph, U = I.advection_physics((1.0, 0.5)), I.advection_state(m, p, seed=3)
+    elif system == "euler":
+        ph, U = I.euler_physics(2), I.ns2d_state(m, p)
+    else:
+        ph, U = I.ns_physics(2, 100.0, 0.72), I.ns2d_state(m, p)
+    out = check_case(m, ph, p, U, "f64", [0, 7, m.n_elem - 1])
+    _assert(out, "f64", (p, system))
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_quad_ns_fp32(p):
+    m = I.quad_mesh(6, degree=p, jitter=0.05, K=1)
+    out = check_case(m, I.ns_physics(2, 1000.0, 0.72), p, I.ns2d_state(m, p), "f32", [0, 13, 35])
+    _assert(out, "f32", p)
+
+
+def test_ragged_tile_tail():
+    """A mesh whose element count is not a multiple of any tile size."""
+    p = 2
+    m = I.quad_mesh(7, degree=p, jitter=0.05, K=1)       # 49 elements
+    out = check_case(m, I.ns_physics(2, 100.0, 0.72), p, I.ns2d_state(m, p), "f64", [48])
+    _assert(out, "f64")
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_hex_ns_fp64(p):
+    m = I.hex_mesh(4, degree=p, jitter=0.05, K=1)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    out = check_case(m, I.ns_physics(3, 50.0, 0.71), p, U, "f64", [0, 21], blocks=(p == 1))
+    _assert(out, "f64", p)
+
+
+def test_cfg1_full_size_fp32():
+    """2D NS, p=3, 128x128 jittered periodic quads, FP32: R and the JVP over
+    the whole mesh, Jacobian blocks on a seeded sample of elements."""
+    p = 3
+    m = I.quad_mesh(128, degree=p, jitter=0.05)
+    ph = I.ns_physics(2, 1000.0, 0.72)
+    U = I.ns2d_state(m, p)
+    elems = list(np.random.default_rng(0).choice(m.n_elem, 12, replace=False)) + [0, m.n_elem - 1]
+    out = check_case(m, ph, p, U, "f32", elems)
+    _assert(out, "f32")
+
+
+def test_bf16_blocks():
+    p = 3
+    m = I.quad_mesh(6, degree=p, jitter=0.05, K=1)
+    ph = I.ns_physics(2, 1000.0, 0.72)
+    U = I.ns2d_state(m, p)
+    Ud = _dev(U, "f32")
+    ctx = _ctx(m, ph, "f32")
+    B = _blocks_rowmajor(ctx.jacobian_blocks(Ud, out_prec="bf16"))
+    Bo = O.Oracle(m, ph, p).jac_blocks(Ud.double().cpu().numpy(), [0, 20], 64, 4)
+    err = max(rel(B[e], Bo[i]) for i, e in enumerate([0, 20]))
+    assert err <= 2e-2
+    assert err > 1e-6     # really stored in bf16
+
+
+def test_errors_are_reported():
+    from paper_2105_08632_amd import fr
+    m = I.quad_mesh(3, degree=2, jitter=0.0)
+    # viscous Jacobian needs a second layer that does not fold onto the first
+    with pytest.raises(fr.FrError) as ei:
+        fr.Context(m, I.ns_physics(2, 100.0, 0.72), "f64")
+    assert ei.value.status == -2
+    ctx = fr.Context(I.quad_mesh(4, degree=2), I.advection_physics(), "f32")
+    with pytest.raises(fr.FrError):
+        ctx.jacobian_blocks(ctx.empty_state().zero_(), out_prec="f64")
+    with pytest.raises(ValueError):
+        ctx.rhs(torch.zeros(3, device="cuda"))
