@@ -126,6 +126,56 @@ fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precis
  * viscous second layer).  R_out (may be NULL) receives R(U). */
 fr_status fr_jvp(fr_ctx* ctx, const void* U, const void* v, void* Jv, void* R_out);
 
+/* ---- Implicit steps (backward Euler) -------------------------------------
+ * The paper integrates explicitly; these calls use the same residual and
+ * Jacobian for an implicit step U - U^n - dt R(U) = 0. */
+
+typedef enum { FR_PC_BLOCK_JACOBI = 0, FR_PC_MLP = 1 } fr_pc_kind;
+
+/* Block preconditioner over the diagonal Jacobian blocks of the face stencil
+ * (eq. "jacobian_rhs", k = n).  FR_PC_BLOCK_JACOBI: A_n = shift I + scale
+ * dR_n/dU_n is inverted in FP64 by Gauss-Jordan elimination with partial
+ * pivoting (blocks up to 128 x 128); FR_PC_MLP: the learned approximate
+ * inverse (weights loaded with fr_mlp_load), with block-Jacobi as fallback.
+ * Storage for the inverses is allocated here, not in setup/apply. */
+fr_status fr_precond_create(fr_ctx* ctx, fr_pc_kind kind, fr_precond** out);
+/* Assembles and inverts the diagonal blocks at state U (device, context
+ * precision).  Backward Euler: shift = 1, scale = -dt.  Returns
+ * FR_E_SINGULAR (message names the element) on a zero or non-finite pivot. */
+fr_status fr_precond_setup(fr_precond* pc, const void* U, double shift, double scale);
+/* z_n = A_n^{-1} r_n for every element (device vectors, context precision;
+ * r and z must not alias). */
+fr_status fr_apply_precond(fr_precond* pc, const void* r, void* z);
+fr_status fr_precond_destroy(fr_precond* pc);
+
+typedef struct fr_solver_s fr_solver;
+typedef struct {
+  double dt;              /* time step */
+  double newton_rtol;     /* stop when |F(U_k)|_2 <= rtol |F(U^n)|_2 */
+  int32_t newton_maxit;
+  double gmres_rtol;      /* relative true linear residual per Newton iteration */
+  int32_t gmres_maxit;    /* GMRES iterations per Newton iteration (all restarts) */
+} fr_newton_opts;
+typedef struct {
+  int32_t newton_iters, gmres_iters, pc_setups, converged;
+  double res0, res;       /* |F(U^n)|_2 and the final |F(U)|_2 */
+  double last_linear_rel; /* last GMRES true relative residual */
+  double ms;              /* wall time of the step on the context stream */
+  double res_hist[32];    /* |F|_2 after each Newton iteration (first 32) */
+  int32_t gmres_hist[32]; /* GMRES iterations of each Newton iteration */
+} fr_newton_stats;
+
+/* Krylov workspace for GMRES(restart), restart <= 31 (FP64 contexts). */
+fr_status fr_solver_create(fr_ctx* ctx, int restart, fr_solver** out);
+fr_status fr_solver_destroy(fr_solver* s);
+/* One backward-Euler step from Un to U (device FP64 vectors): Newton on
+ * F(U) = U - Un - dt R(U), each correction from right-preconditioned
+ * GMRES(restart) on (I - dt dR/dU) dU = -F with exact Jacobian-vector
+ * products; the preconditioner (or NULL) is set up once at Un.  Returns
+ * FR_E_NOT_CONVERGED if newton_maxit iterations do not reach newton_rtol. */
+fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un, void* U, const fr_newton_opts* opts,
+                         fr_newton_stats* stats);
+
 /* Profiling.  When enabled, the dominant kernel of fr_jacobian_blocks
  * (which = 0: block assembly) and of fr_rhs / fr_jvp (which = 1: the flux /
  * divergence pass) is bracketed by HIP events on the context stream.

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fr.h"
+#include "fr.h"
 #include "fr_ctx.hpp"
 #include "fr_host.hpp"
 
@@ -303,7 +303,7 @@ fr_status fr_jacobian_blocks(fr_ctx* c, const void* U, void* blocks, fr_precisio
   if (!U || !blocks || !aligned(U, a) || !aligned(blocks, ob))
     return fail(c, FR_E_INVALID, "fr_jacobian_blocks: null or misaligned pointer");
   if (out_prec < FR_F64 || out_prec > FR_BF16) return fail(c, FR_E_INVALID, "fr_jacobian_blocks: bad precision");
-  int rc = c->ks.jac(c, U, blocks, (int)out_prec);
+  int rc = c->ks.jac(c, U, blocks, (int)out_prec, 1 + c->nface);
   return rc ? (fr_status)rc : FR_OK;
 }
 

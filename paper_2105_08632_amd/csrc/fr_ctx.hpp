@@ -13,7 +13,7 @@ struct fr_ctx_s;
 struct KernelSet {
   int (*rhs)(fr_ctx_s*, const void* U, void* R);
   int (*jvp)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
-  int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec);
+  int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec, int nblk);
 };
 
 struct fr_ctx_s {

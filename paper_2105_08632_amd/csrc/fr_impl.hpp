@@ -31,9 +31,10 @@ __global__ void __launch_bounds__(kThreads) k_div(OpsD<R> op, GeoD<R> geo, PhysP
 
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__(kThreads) k_jac(OpsD<R> op, GeoD<R> geo, PhysP ph, const R* U, const R* Q,
-                                                  const R* UF, const R* QF, OT* B) {
+                                                  const R* UF, const R* QF, OT* B, int nblk) {
   __shared__ __align__(16) char lds[jac_lds<E, NV, SYS, R>()];
-  jac_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, Q, UF, QF, B, DevSync());
+  jac_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, Q, UF, QF, B, nblk,
+                              DevSync());
 }
 
 template <class R> OpsD<R>& ctx_ops(fr_ctx_s* c);
@@ -85,7 +86,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
                                    (Dual<R>*)c->QFd, (R*)Rv, (R*)Jv);
   }
 
-  template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B) {
+  template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B, int nblk) {
     if constexpr (jac_lds<E, NV, SYS, R>() > kMaxLds) {
       c->err = "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
       return -2;
@@ -107,7 +108,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
     }
     if (c->timing) fr_time_begin(c, 0);
     hipLaunchKernelGGL((k_jac<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo, c->ph, U,
-                       (const R*)Q, (const R*)UF, (const R*)QF, B);
+                       (const R*)Q, (const R*)UF, (const R*)QF, B, nblk);
     FR_LAUNCH_CHECK(c);
     if (c->timing) fr_time_end(c, 0);
     return 0;
@@ -115,12 +116,12 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   // out_prec: 0 = f64, 1 = f32, 2 = bf16
-  static int jac(fr_ctx_s* c, const void* U, void* B, int out_prec) {
+  static int jac(fr_ctx_s* c, const void* U, void* B, int out_prec, int nblk) {
     if constexpr (std::is_same<R, double>::value) {
-      if (out_prec == 0) return jac_t<double>(c, (const R*)U, (double*)B);
+      if (out_prec == 0) return jac_t<double>(c, (const R*)U, (double*)B, nblk);
     } else {
-      if (out_prec == 1) return jac_t<float>(c, (const R*)U, (float*)B);
-      if (out_prec == 2) return jac_t<bf16_t>(c, (const R*)U, (bf16_t*)B);
+      if (out_prec == 1) return jac_t<float>(c, (const R*)U, (float*)B, nblk);
+      if (out_prec == 2) return jac_t<bf16_t>(c, (const R*)U, (bf16_t*)B, nblk);
     }
     c->err = "unsupported block precision for this context precision";
     return -2;

@@ -346,6 +346,7 @@ template <class E, int NV, int SYS, class R> constexpr int jac_lds() {
   b += lds_bytes<R>(NS * NV) + lds_bytes<R>(NS * ND * NV) + 2 * lds_bytes<R>(NF * NV) + 2 * lds_bytes<R>(NF * ND * NV);
   b += 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF);
   b += lds_bytes<R>(NFACE * NFP * NFP * ND);
+  b += lds_bytes<R>(NFACE * NS * ND * ND) + lds_bytes<int>(NFACE * NFP) + lds_bytes<int>(NFACE) + lds_bytes<int>(NFACE);
   // tables
   b += lds_bytes<R>(ND * NS * NV2) + lds_bytes<R>(ND * ND * NS * NV2) + 2 * lds_bytes<R>(NF * NV2) +
        2 * lds_bytes<R>(ND * NF * NV2);
@@ -374,9 +375,11 @@ template <> FR_HD bf16_t to_out<bf16_t>(float x) {
 }
 template <> FR_HD bf16_t to_out<bf16_t>(double x) { return to_out<bf16_t>((float)x); }
 
+// nblk = 1 + NFACE writes every block; nblk = 1 only the diagonal block (for
+// block-Jacobi preconditioners), element stride nblk * b * b.
 template <class E, int NV, int SYS, class R, class OT, class Sync>
 FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
-                    const R* U, const R* Q, const R* UF, const R* QF, OT* B, Sync sync) {
+                    const R* U, const R* Q, const R* UF, const R* QF, OT* B, int nblk, Sync sync) {
   typedef JacSizes<E, NV, SYS> Z;
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP, WL = Z::WL, WC = Z::WC,
                 NV2 = Z::NV2;
@@ -411,6 +414,10 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
   R* smg = L.take<R>(NF);
   int* spg = L.take<int>(NF);
   R* sW = L.take<R>(NFACE * NFP * NFP * ND);
+  R* sJm = L.take<R>(NFACE * NS * ND * ND);   // neighbours' J^{-1} at their solution points
+  int* sback = L.take<int>(NFACE * NFP);     // partner in n of each point of the neighbour's shared face
+  int* snb = L.take<int>(NFACE);             // neighbour element of each face
+  int* snf = L.take<int>(NFACE);             // the neighbour's face index of the shared face
   R* ta = L.take<R>(ND * NS * NV2);        // a[d][tau][ab]
   R* tb = L.take<R>(ND * ND * NS * NV2);   // b[d][e][tau][ab]
   R* tuL = L.take<R>(NF * NV2);            // fuL[g][ab]
@@ -453,6 +460,7 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
   for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
   for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
   for (int i = tid; i < NF; i += nth) smg[i] = geo.magN[nl * NF + i];
+  for (int i = tid; i < NFACE; i += nth) snb[i] = geo.nbr[nl * NFACE + i];
   sync();
   for (int i = tid; i < NF * NV; i += nth) {
     int g = i / NV, a = i % NV;
@@ -465,6 +473,16 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
       sqL[i] = QF[(nl * NF + g) * ND * NV + r];
       sqR[i] = QF[(long)spg[g] * ND * NV + r];
     }
+  for (int i = tid; i < NFACE; i += nth) snf[i] = sff[spg[i * NFP] - snb[i] * NF];
+  for (int i = tid; i < NFACE * NS * ND * ND; i += nth) {
+    int f = i / (NS * ND * ND), r = i % (NS * ND * ND);
+    sJm[i] = geo.Jinv[(long)snb[f] * NS * ND * ND + r];
+  }
+  sync();
+  for (int i = tid; i < NFACE * NFP; i += nth) {
+    int f = i / NFP, gj = i % NFP;
+    sback[i] = geo.nbfp[(long)snb[f] * NF + snf[f] * NFP + gj] - n * NF;
+  }
   // W_d'[f][g][g'] for the neighbour gradient's dependence on u_n (self block):
   // sum_tau' M0[g2][tau'] Cor[tau'][g'] sum_e Jinv_m[tau'][e][d'] nref[g'][e],
   // g on face f, g2 its partner in m, g' on the shared face f2 of m.
@@ -472,18 +490,16 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
     for (int i = tid; i < NFACE * NFP * NFP * ND; i += nth) {
       int f = i / (NFP * NFP * ND), gi = (i / (NFP * ND)) % NFP, gj = (i / ND) % NFP, d2 = i % ND;
       int g = f * NFP + gi;
-      int m = geo.nbr[nl * NFACE + f];
+      int m = snb[f];
       int g2 = spg[g] - m * NF;
-      int f2 = op.fface[g2];
-      int gp = f2 * NFP + gj;
+      int gp = snf[f] * NFP + gj;
       R acc = R(0);
       for (int w = 0; w < WL; ++w) {
-        int t = op.m0c[g2 * WL + w];
-        R mv = op.m0v[g2 * WL + w];
-        if (mv == R(0)) continue;
+        int t = m0c[g2 * WL + w];
+        R mv = m0v[g2 * WL + w];
         R je = R(0);
-        for (int e = 0; e < ND; ++e) je += geo.Jinv[(((long)m * NS + t) * ND + e) * ND + d2] * op.nref[gp * ND + e];
-        acc += mv * op.Cor[t * NF + gp] * je;
+        for (int e = 0; e < ND; ++e) je += sJm[((f * NS + t) * ND + e) * ND + d2] * snr[gp * ND + e];
+        acc += mv * sCor[t * NF + gp] * je;
       }
       sW[i] = cb * acc;
     }
@@ -597,10 +613,10 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
   }
 
   // ---- blocks
-  OT* Bn = B + nl * (long)(1 + NFACE) * BB * BB;
-  for (int k = 0; k <= NFACE; ++k) {
+  OT* Bn = B + nl * (long)nblk * BB * BB;
+  for (int k = 0; k < nblk; ++k) {
     const int f = k - 1;                 // face of the neighbour block (k >= 1)
-    const int m = (k == 0) ? n : geo.nbr[nl * NFACE + f];
+    const int m = (k == 0) ? n : snb[f];
     // Gam_e[tau][sigma] = d q~_e(tau) / d u_k(sigma)
     for (int i = tid; i < ND * NS * NS; i += nth) {
       int e = i / (NS * NS), t = (i / NS) % NS, s = i % NS;
@@ -613,7 +629,7 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
           for (int gi = 0; gi < NFP; ++gi) {
             int g = f * NFP + gi;
             R c = sCor[t * NF + g] * snr[g * ND + e];
-            if (c != R(0)) v += c * op.M0[(spg[g] - m * NF) * NS + s];
+            if (c != R(0)) v += c * sM0[(spg[g] - m * NF) * NS + s];
           }
           v *= cb;
         }
@@ -639,15 +655,9 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
         int fg = sff[g];
         R acc = R(0);
         if (k == 0) {
-          int mm = geo.nbr[nl * NFACE + fg];
-          int g2 = spg[g] - mm * NF;
-          int f2 = sff[g2];
           int gi = g - fg * NFP;
-          for (int gj = 0; gj < NFP; ++gj) {
-            int gp = f2 * NFP + gj;
-            int back = geo.nbfp[(long)mm * NF + gp] - n * NF;   // partner of gp in n
-            acc += sW[((fg * NFP + gi) * NFP + gj) * ND + d2] * sM0[back * NS + s];
-          }
+          for (int gj = 0; gj < NFP; ++gj)
+            acc += sW[((fg * NFP + gi) * NFP + gj) * ND + d2] * sM0[sback[fg * NFP + gj] * NS + s];
         } else if (fg == f) {
           int g2 = spg[g] - m * NF;
           for (int w = 0; w < WL; ++w) {
@@ -659,7 +669,7 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
               R ge = R(0);
               for (int w2 = 0; w2 < WL; ++w2)
                 if (gcc[(e * NS + t) * WL + w2] == s) ge += gcv[(e * NS + t) * WL + w2];
-              gsum += geo.Jinv[(((long)m * NS + t) * ND + e) * ND + d2] * ge;
+              gsum += sJm[((f * NS + t) * ND + e) * ND + d2] * ge;
             }
             acc += mv * gsum;
           }

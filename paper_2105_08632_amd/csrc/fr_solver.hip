@@ -1,0 +1,553 @@
+// Block-Jacobi preconditioner, Krylov vector kernels and the backward-Euler
+// Newton-GMRES step.
+//
+// The preconditioner inverts the diagonal Jacobian blocks A_n = shift I +
+// scale dR_n/dU_n in FP64 (Gauss-Jordan elimination with partial pivoting,
+// one workgroup per element, the block resident in LDS) and applies the
+// explicit inverses as a batched matrix-vector product.  The Newton step
+// solves U - U^n - dt R(U) = 0 with restarted, right-preconditioned GMRES
+// (classical Gram-Schmidt applied twice, Givens rotations on the host),
+// Jacobian-vector products from the exact tangent kernels, and the true
+// linear residual recomputed at every restart.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fr.h"
+#include "fr_ctx.hpp"
+#include "fr_solver.hpp"
+
+// ------------------------------------------------------------ LU / inverse
+constexpr int kInvThreads = 256;
+
+// A = shift I + scale J (J column-major b x b, input type IT), inverted in
+// place by Gauss-Jordan elimination with row pivoting; the inverse (column-
+// major) is written to Ainv.  bad[n] = 1 when a pivot is zero or not finite.
+template <class IT, int BMAX>
+__global__ void __launch_bounds__(kInvThreads) k_block_inverse(const IT* J, long jstride, int b, double shift,
+                                                               double scale, double* Ainv, int* bad) {
+  __shared__ double A[BMAX * BMAX];   // row-major in LDS: A[r*b + c]
+  __shared__ int perm[BMAX];
+  __shared__ double red_v[kInvThreads];
+  __shared__ int red_i[kInvThreads];
+  __shared__ int s_bad;
+  const int n = blockIdx.x, tid = threadIdx.x;
+  const IT* Jn = J + (long)n * jstride;
+  for (int i = tid; i < b * b; i += kInvThreads) {
+    int c = i / b, r = i % b;                       // source is column-major
+    double v = scale * (double)Jn[i];
+    if (r == c) v += shift;
+    A[r * b + c] = v;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    // pivot: largest |A[i][k]|, i >= k
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < b; i += kInvThreads) {
+      double v = fabs(A[i * b + k]);
+      if (v > best) { best = v; bi = i; }
+    }
+    red_v[tid] = best; red_i[tid] = bi;
+    __syncthreads();
+    for (int s = kInvThreads / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        double o = red_v[tid + s];
+        int oi = red_i[tid + s];
+        if (o > red_v[tid] || (o == red_v[tid] && oi < red_i[tid])) { red_v[tid] = o; red_i[tid] = oi; }
+      }
+      __syncthreads();
+    }
+    const int p = red_i[0];
+    if (tid == 0) {
+      perm[k] = p;
+      double pv = A[p * b + k];
+      if (!(fabs(pv) > 0.0) || !isfinite(pv)) s_bad = 1;
+    }
+    __syncthreads();
+    if (p != k)
+      for (int c = tid; c < b; c += kInvThreads) {
+        double t = A[k * b + c]; A[k * b + c] = A[p * b + c]; A[p * b + c] = t;
+      }
+    __syncthreads();
+    const double piv = A[k * b + k];
+    const double ip = (s_bad || piv == 0.0) ? 0.0 : 1.0 / piv;
+    __syncthreads();
+    // row k <- row k / pivot, with A[k][k] replaced by 1 before scaling
+    for (int c = tid; c < b; c += kInvThreads) A[k * b + c] = (c == k ? 1.0 : A[k * b + c]) * ip;
+    __syncthreads();
+    // eliminate column k from every other row
+    for (int i = tid; i < b * b; i += kInvThreads) {
+      int r = i / b, c = i % b;
+      if (r == k) continue;
+      double f = A[r * b + k];
+      if (c == k) continue;
+      A[r * b + c] -= f * A[k * b + c];
+    }
+    __syncthreads();
+    for (int r = tid; r < b; r += kInvThreads)
+      if (r != k) A[r * b + k] = -A[r * b + k] * A[k * b + k];
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = b - 1; k >= 0; --k) {
+    int p = perm[k];
+    if (p != k)
+      for (int r = tid; r < b; r += kInvThreads) {
+        double t = A[r * b + k]; A[r * b + k] = A[r * b + p]; A[r * b + p] = t;
+      }
+    __syncthreads();
+  }
+  double* out = Ainv + (long)n * b * b;
+  for (int i = tid; i < b * b; i += kInvThreads) {
+    int c = i / b, r = i % b;
+    out[i] = A[r * b + c];                           // column-major
+  }
+  if (tid == 0) bad[n] = s_bad;
+}
+
+// z_n = Ainv_n r_n, one wavefront per element, lanes over rows, columns
+// streamed (column-major inverse: each column is a contiguous run).
+template <class VT>
+__global__ void __launch_bounds__(256) k_block_apply(long ne, int b, const double* Ainv, const VT* r, VT* z) {
+  const int lane = threadIdx.x & 63;
+  const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= ne) return;
+  const double* M = Ainv + n * b * b;
+  const VT* rn = r + n * b;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int r0 = lane, r1 = lane + 64;
+  for (int c = 0; c < b; ++c) {
+    double rc = (double)rn[c];
+    if (r0 < b) acc0 += M[(long)c * b + r0] * rc;
+    if (r1 < b) acc1 += M[(long)c * b + r1] * rc;
+  }
+  if (r0 < b) z[n * b + r0] = (VT)acc0;
+  if (r1 < b) z[n * b + r1] = (VT)acc1;
+}
+
+// ------------------------------------------------------------ vector kernels
+// out = a x + b y
+__global__ void k_axpby(long n, double a, const double* x, double b, const double* y, double* out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+constexpr int kDotBlocks = 1024;
+constexpr int kDotThreads = 256;
+
+// partial[blk][j] = sum over the block's slice of V_j . w, j < k (V_j = V + j*ld)
+__global__ void __launch_bounds__(kDotThreads) k_multi_dot(long n, int k, const double* V, long ld, const double* w,
+                                                           double* partial) {
+  __shared__ double red[kDotThreads];
+  for (int j = 0; j < k; ++j) {
+    double acc = 0.0;
+    const double* Vj = V + (long)j * ld;
+    for (long i = (long)blockIdx.x * kDotThreads + threadIdx.x; i < n; i += (long)gridDim.x * kDotThreads)
+      acc += Vj[i] * w[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long)blockIdx.x * 32 + j] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[j] = sum over blocks of partial[blk][j]
+__global__ void k_reduce_partials(int k, int nblk, const double* partial, double* out) {
+  __shared__ double red[256];
+  for (int j = 0; j < k; ++j) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[(long)b * 32 + j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+    __syncthreads();
+  }
+}
+
+// w -= sum_j h[j] V_j
+__global__ void k_multi_axpy(long n, int k, const double* h, const double* V, long ld, double* w) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc -= h[j] * V[(long)j * ld + i];
+    w[i] = acc;
+  }
+}
+
+__global__ void k_fill(long n, double v, double* x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+
+// x += sum_j y[j] Z_j
+__global__ void k_multi_axpy_add(long n, int k, const double* y, const double* Z, long ld, double* x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    double acc = x[i];
+    for (int j = 0; j < k; ++j) acc += y[j] * Z[(long)j * ld + i];
+    x[i] = acc;
+  }
+}
+
+// ------------------------------------------------------------ helpers
+static fr_status sfail(fr_ctx_s* c, fr_status s, const std::string& m) {
+  c->err = m;
+  return s;
+}
+#define HIPCHK(ctx, x)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) return sfail((ctx), FR_E_DEVICE, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static int grid_for(long n, int threads) {
+  long g = (n + threads - 1) / threads;
+  return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
+}
+
+fr_status pc_lu_setup(fr_precond_s* pc, const void* U, double shift, double scale) {
+  fr_ctx_s* c = pc->ctx;
+  const int b = c->b;
+  const long ne = c->ne;
+  // diagonal blocks in the context precision, then FP64 inversion
+  void* J = pc->jbuf;
+  int rc = c->ks.jac(c, U, J, c->prec == 0 ? 0 : 1, 1);
+  if (rc) return (fr_status)rc;
+  if (b <= 64) {
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_block_inverse<double, 64>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const double*)J,
+                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+    else
+      hipLaunchKernelGGL((k_block_inverse<float, 64>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const float*)J,
+                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+  } else if (b <= 128) {
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_block_inverse<double, 128>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const double*)J,
+                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+    else
+      hipLaunchKernelGGL((k_block_inverse<float, 128>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const float*)J,
+                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+  } else {
+    return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi inverse supports blocks up to 128 x 128");
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(pc->bad_host, pc->bad, ne * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (long n = 0; n < ne; ++n)
+    if (pc->bad_host[n]) {
+      c->err = "diagonal block of element " + std::to_string(n) + " is singular";
+      return FR_E_SINGULAR;
+    }
+  return FR_OK;
+}
+
+fr_status pc_lu_apply(fr_precond_s* pc, const void* r, void* z) {
+  fr_ctx_s* c = pc->ctx;
+  const long ne = c->ne;
+  const int grid = (int)((ne + 3) / 4);
+  if (c->prec == 0)
+    hipLaunchKernelGGL((k_block_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv,
+                       (const double*)r, (double*)z);
+  else
+    hipLaunchKernelGGL((k_block_apply<float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv,
+                       (const float*)r, (float*)z);
+  HIPCHK(c, hipGetLastError());
+  return FR_OK;
+}
+
+// ------------------------------------------------------------ solver
+struct fr_solver_s {
+  fr_ctx_s* ctx = nullptr;
+  int m = 30;
+  long N = 0;
+  void* mem = nullptr;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *x = nullptr, *F = nullptr, *R = nullptr, *tmp = nullptr;
+  double *partial = nullptr, *dots = nullptr, *hcol = nullptr;
+  double* host = nullptr;   // pinned scalars
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+static fr_status dots(fr_solver_s* s, int k, const double* V, const double* w, double* out_host) {
+  fr_ctx_s* c = s->ctx;
+  hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks), dim3(kDotThreads), 0, c->stream, s->N, k, V, s->N, w, s->partial);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->stream, k, kDotBlocks, s->partial, s->dots);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(s->host, s->dots, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(out_host, s->host, k * sizeof(double));
+  return FR_OK;
+}
+
+static fr_status axpby(fr_solver_s* s, double a, const double* x, double b, const double* y, double* out) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(s->N, 256)), dim3(256), 0, s->ctx->stream, s->N, a, x, b, y, out);
+  HIPCHK(s->ctx, hipGetLastError());
+  return FR_OK;
+}
+
+// out = A v = v - dt J(U) v (R(U) written to R_out when not null)
+static fr_status apply_A(fr_solver_s* s, const double* U, double dt, const double* v, double* out, double* R_out) {
+  fr_ctx_s* c = s->ctx;
+  int rc = c->ks.jvp(c, U, v, s->tmp, R_out);
+  if (rc) return (fr_status)rc;
+  return axpby(s, 1.0, v, -dt, s->tmp, out);
+}
+
+static fr_status precond(fr_solver_s* s, fr_precond_s* pc, const double* v, double* z) {
+  if (!pc) {
+    HIPCHK(s->ctx, hipMemcpyAsync(z, v, s->N * sizeof(double), hipMemcpyDeviceToDevice, s->ctx->stream));
+    return FR_OK;
+  }
+  return fr_apply_precond(pc, v, z);
+}
+
+// GMRES(m) on A x = rhs from x = 0; returns iterations, true residual norm.
+static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt, const double* rhs, double rtol,
+                       int maxit, double* x, int* iters, double* res_true, double* res0_out) {
+  fr_ctx_s* c = s->ctx;
+  const int m = s->m;
+  const long N = s->N;
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hj(m + 1), hj2(m + 1), y(m);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 0.0, x);
+  // r0 = rhs (x = 0)
+  HIPCHK(c, hipMemcpyAsync(s->w, rhs, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double nrm;
+  fr_status st = dots(s, 1, s->w, s->w, &nrm);
+  if (st) return st;
+  const double b0 = std::sqrt(nrm);
+  *res0_out = b0;
+  *iters = 0;
+  *res_true = 0.0;
+  if (b0 == 0.0) { *res_true = 0.0; return FR_OK; }
+  double beta = b0;
+  int total = 0;
+  while (true) {
+    // v_0 = r / beta
+    if ((st = axpby(s, 1.0 / beta, s->w, 0.0, nullptr, s->V))) return st;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    double est = beta;
+    for (; j < m && total < maxit; ++j, ++total) {
+      double* vj = s->V + (long)j * N;
+      double* zj = s->Z + (long)j * N;
+      if ((st = precond(s, pc, vj, zj))) return st;
+      if ((st = apply_A(s, U, dt, zj, s->w, nullptr))) return st;
+      // classical Gram-Schmidt, twice
+      if ((st = dots(s, j + 1, s->V, s->w, hj.data()))) return st;
+      HIPCHK(c, hipMemcpyAsync(s->hcol, hj.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j + 1, s->hcol, s->V, N, s->w);
+      if ((st = dots(s, j + 1, s->V, s->w, hj2.data()))) return st;
+      HIPCHK(c, hipMemcpyAsync(s->hcol, hj2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j + 1, s->hcol, s->V, N, s->w);
+      HIPCHK(c, hipGetLastError());
+      for (int i = 0; i <= j; ++i) H[i * m + j] = hj[i] + hj2[i];
+      double hn;
+      if ((st = dots(s, 1, s->w, s->w, &hn))) return st;
+      hn = std::sqrt(hn);
+      H[(j + 1) * m + j] = hn;
+      if (hn > 0.0 && (st = axpby(s, 1.0 / hn, s->w, 0.0, nullptr, s->V + (long)(j + 1) * N))) return st;
+      // Givens rotations
+      for (int i = 0; i < j; ++i) {
+        double a = H[i * m + j], bb = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * bb;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+      }
+      double a = H[j * m + j], bb = H[(j + 1) * m + j];
+      double r = std::hypot(a, bb);
+      cs[j] = r > 0 ? a / r : 1.0;
+      sn[j] = r > 0 ? bb / r : 0.0;
+      H[j * m + j] = r;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      est = std::fabs(g[j + 1]);
+      if (est <= rtol * b0 || hn == 0.0) { ++j; ++total; break; }
+    }
+    // y = H^{-1} g, x += Z y
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < j; ++k) acc -= H[i * m + k] * y[k];
+      y[i] = acc / H[i * m + i];
+    }
+    HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), j * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, x);
+    HIPCHK(c, hipGetLastError());
+    // true residual r = rhs - A x
+    if ((st = apply_A(s, U, dt, x, s->w, nullptr))) return st;
+    if ((st = axpby(s, 1.0, rhs, -1.0, s->w, s->w))) return st;
+    if ((st = dots(s, 1, s->w, s->w, &nrm))) return st;
+    beta = std::sqrt(nrm);
+    *iters = total;
+    const double prev = *res_true > 0 ? *res_true : b0;
+    *res_true = beta;
+    if (beta <= rtol * b0 || total >= maxit || beta > 0.99 * prev) break;
+  }
+  return FR_OK;
+}
+
+extern "C" {
+
+fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
+  if (!c || !out) return FR_E_INVALID;
+  *out = nullptr;
+  if (kind != FR_PC_BLOCK_JACOBI && kind != FR_PC_MLP) return sfail(c, FR_E_INVALID, "unknown preconditioner kind");
+  if (c->b > 128) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi inverse supports blocks up to 128 x 128");
+  fr_precond_s* pc = new fr_precond_s();
+  pc->ctx = c; pc->kind = kind;
+  const size_t bb = (size_t)c->b * c->b, ne = (size_t)c->ne;
+  const size_t rs = c->prec == 0 ? 8 : 4;
+  size_t off_inv = (ne * bb * rs + 255) & ~(size_t)255;
+  size_t off_bad = off_inv + ((ne * bb * 8 + 255) & ~(size_t)255);
+  size_t tot = off_bad + ne * sizeof(int);
+  if (hipMalloc(&pc->mem, tot) != hipSuccess) { delete pc; return sfail(c, FR_E_NOMEM, "preconditioner storage"); }
+  pc->jbuf = pc->mem;
+  pc->inv = (double*)((char*)pc->mem + off_inv);
+  pc->bad = (int*)((char*)pc->mem + off_bad);
+  if (hipHostMalloc((void**)&pc->bad_host, ne * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(pc->mem); delete pc; return sfail(c, FR_E_NOMEM, "pinned flags");
+  }
+  if (kind == FR_PC_MLP) {
+    fr_status st = pc_mlp_create(pc);
+    if (st) { (void)hipFree(pc->mem); (void)hipHostFree(pc->bad_host); delete pc; return st; }
+  }
+  *out = pc;
+  return FR_OK;
+}
+
+fr_status fr_precond_setup(fr_precond* pc, const void* U, double shift, double scale) {
+  if (!pc || !U) return FR_E_INVALID;
+  fr_status st = (pc->kind == FR_PC_MLP) ? pc_mlp_setup(pc, U, shift, scale) : pc_lu_setup(pc, U, shift, scale);
+  pc->ready = (st == FR_OK);
+  return st;
+}
+
+fr_status fr_apply_precond(fr_precond* pc, const void* r, void* z) {
+  if (!pc || !r || !z || r == z) return FR_E_INVALID;
+  if (!pc->ready) return sfail(pc->ctx, FR_E_INVALID, "fr_apply_precond before a successful fr_precond_setup");
+  return (pc->kind == FR_PC_MLP) ? pc_mlp_apply(pc, r, z) : pc_lu_apply(pc, r, z);
+}
+
+fr_status fr_precond_destroy(fr_precond* pc) {
+  if (!pc) return FR_E_INVALID;
+  (void)hipStreamSynchronize(pc->ctx->stream);
+  if (pc->mlp) pc_mlp_destroy(pc);
+  (void)hipFree(pc->mem);
+  (void)hipHostFree(pc->bad_host);
+  delete pc;
+  return FR_OK;
+}
+
+fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
+  if (!c || !out || restart < 1 || restart > 31) return FR_E_INVALID;
+  if (c->prec != 0) return sfail(c, FR_E_UNSUPPORTED, "Newton-GMRES runs on FP64 contexts");
+  fr_solver_s* s = new fr_solver_s();
+  s->ctx = c; s->m = restart; s->N = c->ne * (long)c->b;
+  const long N = s->N;
+  size_t doubles = (size_t)N * (2 * (restart + 1) + 5) + kDotBlocks * 32 + 64 + 64;
+  if (hipMalloc(&s->mem, doubles * sizeof(double)) != hipSuccess) { delete s; return sfail(c, FR_E_NOMEM, "solver workspace"); }
+  double* p = (double*)s->mem;
+  s->V = p; p += N * (restart + 1);
+  s->Z = p; p += N * (restart + 1);
+  s->w = p; p += N; s->x = p; p += N; s->F = p; p += N; s->R = p; p += N; s->tmp = p; p += N;
+  s->partial = p; p += kDotBlocks * 32;
+  s->dots = p; p += 64;
+  s->hcol = p; p += 64;
+  if (hipHostMalloc((void**)&s->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(s->mem); delete s; return sfail(c, FR_E_NOMEM, "pinned host scalars");
+  }
+  if (hipEventCreate(&s->e0) != hipSuccess || hipEventCreate(&s->e1) != hipSuccess) {
+    (void)hipFree(s->mem); (void)hipHostFree(s->host); delete s; return sfail(c, FR_E_DEVICE, "events");
+  }
+  *out = s;
+  return FR_OK;
+}
+
+fr_status fr_solver_destroy(fr_solver* s) {
+  if (!s) return FR_E_INVALID;
+  (void)hipStreamSynchronize(s->ctx->stream);
+  (void)hipFree(s->mem);
+  (void)hipHostFree(s->host);
+  (void)hipEventDestroy(s->e0);
+  (void)hipEventDestroy(s->e1);
+  delete s;
+  return FR_OK;
+}
+
+fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_, const fr_newton_opts* o,
+                         fr_newton_stats* st) {
+  if (!s || !Un_ || !U_ || !o || !st) return FR_E_INVALID;
+  fr_ctx_s* c = s->ctx;
+  if (pc && pc->ctx != c) return sfail(c, FR_E_INVALID, "preconditioner belongs to another context");
+  const double* Un = (const double*)Un_;
+  double* U = (double*)U_;
+  const long N = s->N;
+  std::memset(st, 0, sizeof(*st));
+  hipEvent_t e0 = s->e0, e1 = s->e1;
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  HIPCHK(c, hipMemcpyAsync(U, Un, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  fr_status rs;
+  if (pc) {
+    if ((rs = fr_precond_setup(pc, Un, 1.0, -o->dt))) return rs;
+    st->pc_setups = 1;
+  }
+  double f0 = 0.0;
+  for (int it = 0; it <= o->newton_maxit; ++it) {
+    // F = U - Un - dt R(U)
+    int rc = c->ks.rhs(c, U, s->R);
+    if (rc) return (fr_status)rc;
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 1.0, U, -1.0, Un, s->F);
+    if ((rs = axpby(s, 1.0, s->F, -o->dt, s->R, s->F))) return rs;
+    double fn;
+    if ((rs = dots(s, 1, s->F, s->F, &fn))) return rs;
+    fn = std::sqrt(fn);
+    if (it == 0) f0 = fn;
+    if (it < 32) st->res_hist[it] = fn;
+    st->res0 = f0;
+    st->res = fn;
+    st->newton_iters = it;
+    if (fn <= o->newton_rtol * f0 || f0 == 0.0) { st->converged = 1; break; }
+    if (it == o->newton_maxit) break;
+    // solve (I - dt J) dU = -F
+    if ((rs = axpby(s, -1.0, s->F, 0.0, nullptr, s->F))) return rs;
+    int gi = 0;
+    double rt = 0.0, r0 = 0.0;
+    if ((rs = gmres(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0))) return rs;
+    st->gmres_iters += gi;
+    if (it < 32) st->gmres_hist[it] = gi;
+    st->last_linear_rel = r0 > 0 ? rt / r0 : 0.0;
+    // backtracking on |F|: U + lambda dU, lambda = 1, 1/2, ... (at most 5 halvings)
+    double lam = 1.0;
+    for (int ls = 0; ls < 6; ++ls) {
+      if ((rs = axpby(s, 1.0, U, lam, s->x, s->tmp))) return rs;
+      rc = c->ks.rhs(c, s->tmp, s->R);
+      if (rc) return (fr_status)rc;
+      hipLaunchKernelGGL(k_axpby, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 1.0, s->tmp, -1.0, Un, s->w);
+      if ((rs = axpby(s, 1.0, s->w, -o->dt, s->R, s->w))) return rs;
+      double ft;
+      if ((rs = dots(s, 1, s->w, s->w, &ft))) return rs;
+      ft = std::sqrt(ft);
+      if (std::isfinite(ft) && (ft < fn || ls == 5)) break;
+      lam *= 0.5;
+    }
+    if ((rs = axpby(s, 1.0, U, lam, s->x, U))) return rs;
+  }
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  st->ms = ms;
+  return st->converged ? FR_OK : sfail(c, FR_E_NOT_CONVERGED, "Newton did not reach its tolerance");
+}
+
+}  // extern "C"

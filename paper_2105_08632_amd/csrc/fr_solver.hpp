@@ -1,0 +1,27 @@
+// Preconditioner object shared by the solver and the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fr.h"
+#include "fr_ctx.hpp"
+
+struct fr_precond_s {
+  fr_ctx_s* ctx = nullptr;
+  int kind = 0;              // fr_pc_kind
+  void* mem = nullptr;
+  void* jbuf = nullptr;      // diagonal blocks, context precision
+  double* inv = nullptr;     // [ne][b][b] column-major inverses (FP64)
+  int* bad = nullptr;        // [ne] singular-pivot flags
+  int* bad_host = nullptr;   // pinned copy
+  bool ready = false;
+  void* mlp = nullptr;       // learned-preconditioner state (FR_PC_MLP)
+};
+
+// learned preconditioner (fr_mlp.hip)
+fr_status pc_mlp_create(fr_precond_s* pc);
+fr_status pc_mlp_setup(fr_precond_s* pc, const void* U, double shift, double scale);
+fr_status pc_mlp_apply(fr_precond_s* pc, const void* r, void* z);
+void pc_mlp_destroy(fr_precond_s* pc);
+
+fr_status pc_lu_setup(fr_precond_s* pc, const void* U, double shift, double scale);
+fr_status pc_lu_apply(fr_precond_s* pc, const void* r, void* z);

@@ -190,3 +190,106 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         _check(lib().fr_kernel_time(self.h, which, C.byref(ms), C.byref(n)), self.h)
         return ms.value, n.value
+
+
+# ---------------------------------------------------------------- implicit step
+FR_PC_BLOCK_JACOBI, FR_PC_MLP = 0, 1
+
+
+class _NewtonOpts(C.Structure):
+    _fields_ = [("dt", C.c_double), ("newton_rtol", C.c_double), ("newton_maxit", C.c_int32),
+                ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int32)]
+
+
+class _NewtonStats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("pc_setups", C.c_int32),
+                ("converged", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
+                ("last_linear_rel", C.c_double), ("ms", C.c_double),
+                ("res_hist", C.c_double * 32), ("gmres_hist", C.c_int32 * 32)]
+
+
+def _solver_symbols(L):
+    P = C.c_void_p
+    L.fr_precond_create.argtypes = [P, C.c_int, C.POINTER(P)]
+    L.fr_precond_setup.argtypes = [P, P, C.c_double, C.c_double]
+    L.fr_apply_precond.argtypes = [P, P, P]
+    L.fr_precond_destroy.argtypes = [P]
+    L.fr_solver_create.argtypes = [P, C.c_int, C.POINTER(P)]
+    L.fr_solver_destroy.argtypes = [P]
+    L.fr_newton_step.argtypes = [P, P, P, P, C.POINTER(_NewtonOpts), C.POINTER(_NewtonStats)]
+    for n in ("fr_precond_create", "fr_precond_setup", "fr_apply_precond", "fr_precond_destroy",
+              "fr_solver_create", "fr_solver_destroy", "fr_newton_step"):
+        getattr(L, n).restype = C.c_int
+
+
+_extensions.append(_solver_symbols)
+EXPORTED += ["fr_precond_create", "fr_precond_setup", "fr_apply_precond", "fr_precond_destroy",
+             "fr_solver_create", "fr_solver_destroy", "fr_newton_step"]
+
+
+class Precond:
+    """Block preconditioner (block-Jacobi FP64 inverse, or the learned MLP)."""
+
+    def __init__(self, ctx: Context, kind: int = FR_PC_BLOCK_JACOBI):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().fr_precond_create(ctx.h, kind, C.byref(h)), ctx.h)
+        self.h = h
+
+    def setup(self, U, shift: float, scale: float):
+        _check(lib().fr_precond_setup(self.h, _ptr(self.ctx._vec(U)), shift, scale), self.ctx.h)
+
+    def apply(self, r, z=None):
+        z = self.ctx.empty_state() if z is None else self.ctx._vec(z)
+        _check(lib().fr_apply_precond(self.h, _ptr(self.ctx._vec(r)), _ptr(z)), self.ctx.h)
+        return z
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fr_precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Backward-Euler Newton-GMRES(restart) on an FP64 context."""
+
+    def __init__(self, ctx: Context, restart: int = 30):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().fr_solver_create(ctx.h, restart, C.byref(h)), ctx.h)
+        self.h = h
+
+    def newton_step(self, Un, U=None, pc: Precond | None = None, dt: float = 1e-3, newton_rtol: float = 1e-8,
+                    newton_maxit: int = 20, gmres_rtol: float = 1e-3, gmres_maxit: int = 300,
+                    check: bool = True) -> dict:
+        U = self.ctx.empty_state() if U is None else self.ctx._vec(U)
+        o = _NewtonOpts(dt, newton_rtol, newton_maxit, gmres_rtol, gmres_maxit)
+        st = _NewtonStats()
+        rc = lib().fr_newton_step(self.h, None if pc is None else pc.h, _ptr(self.ctx._vec(Un)), _ptr(U),
+                                  C.byref(o), C.byref(st))
+        if check:
+            _check(rc, self.ctx.h)
+        out = {k: getattr(st, k) for k, _ in _NewtonStats._fields_ if not k.endswith("_hist")}
+        n = min(32, st.newton_iters + 1)
+        out["res_hist"] = list(st.res_hist[:n])
+        out["gmres_hist"] = list(st.gmres_hist[:n])
+        out["status"] = rc
+        out["U"] = U
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fr_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

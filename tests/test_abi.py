@@ -22,7 +22,7 @@ def _declared():
 
 def test_header_declares_the_hot_calls():
     names = _declared()
-    for hot in ("fr_rhs", "fr_jacobian_blocks", "fr_jvp"):
+    for hot in ("fr_rhs", "fr_jacobian_blocks", "fr_jvp", "fr_apply_precond", "fr_newton_step"):
         assert hot in names, hot
 
 
