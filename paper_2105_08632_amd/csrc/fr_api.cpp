@@ -200,6 +200,22 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     release(c);
     return fail(nullptr, FR_E_DEVICE, "upload failed");
   }
+  if (type != FR_TRI) {
+    const double beta = ph->ldg_beta;
+    for (int i = 0; i <= m->degree; ++i) {
+      for (int j = 0; j <= m->degree; ++j) {
+        double d = ref.D1[i * (m->degree + 1) + j];
+        double cm = ref.hp[i] * ref.lp[j] - ref.hm[i] * ref.lm[j];
+        c->o1d.Dc1[i][j] = d - cm;
+        c->o1d.G1[i][j] = d - (0.5 + beta) * cm;
+        c->o1f.Dc1[i][j] = (float)(d - cm);
+        c->o1f.G1[i][j] = (float)(d - (0.5 + beta) * cm);
+      }
+      c->o1d.hp[i] = ref.hp[i]; c->o1d.hm[i] = ref.hm[i]; c->o1d.lp[i] = ref.lp[i]; c->o1d.lm[i] = ref.lm[i];
+      c->o1f.hp[i] = (float)ref.hp[i]; c->o1f.hm[i] = (float)ref.hm[i];
+      c->o1f.lp[i] = (float)ref.lp[i]; c->o1f.lm[i] = (float)ref.lm[i];
+    }
+  }
   c->opsd = ops_view<double>((char*)c->ops_mem, oo);
   c->geod = geo_view<double>((char*)c->geo_mem, go, (int)c->ne);
   if (prec == FR_F32) {

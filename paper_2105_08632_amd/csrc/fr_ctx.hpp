@@ -5,7 +5,7 @@
 #include <cstdint>
 #include <string>
 
-#include "fr_kernels.hpp"
+#include "fr_jac_tp.hpp"
 
 struct fr_ctx_s;
 
@@ -30,6 +30,7 @@ struct fr_ctx_s {
   void* geo_mem = nullptr;
   void* work_mem = nullptr;
   OpsD<float> opsf{}; OpsD<double> opsd{};
+  Ops1D<float> o1f{}; Ops1D<double> o1d{};
   GeoD<float> geof{}; GeoD<double> geod{};
   // workspaces: traces and gradients, real and dual
   void* UF = nullptr; void* Q = nullptr; void* QF = nullptr;        // context precision

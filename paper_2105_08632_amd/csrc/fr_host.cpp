@@ -152,6 +152,7 @@ static void build_tensor(RefOps& R, int type, int p) {
   B.eval(1.0, lp); B.eval(-1.0, lm);
   std::vector<double> hp(n1), hm(n1);
   for (int i = 0; i < n1; ++i) { hp[i] = lp[i] / w[i]; hm[i] = lm[i] / w[i]; }
+  R.D1 = D1; R.hp = hp; R.hm = hm; R.lp = lp; R.lm = lm;
 
   auto sidx = [&](int r, int d) { return d == 0 ? r % n1 : (d == 1 ? (r / n1) % n1 : r / (n1 * n1)); };
   R.sp.assign(R.ns * nd, 0.0); R.wsol.assign(R.ns, 1.0);

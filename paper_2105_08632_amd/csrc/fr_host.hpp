@@ -21,6 +21,9 @@ struct RefOps {
   std::vector<int> m0c, dcc, gc, crc, ddc; // compressed rows
   std::vector<double> m0v, dcv, gv, crv, ddv;
   std::vector<double> wsol;           // quadrature weights at solution points
+  // 1-D factors of tensor elements (n1 = p + 1): derivative matrix, lifting
+  // h+-_i = l_i(+-1)/w_i and end values l_i(+-1)
+  std::vector<double> D1, hp, hm, lp, lm;
   std::vector<std::vector<int>> face_verts;
 };
 

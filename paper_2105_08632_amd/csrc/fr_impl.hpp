@@ -37,6 +37,18 @@ __global__ void __launch_bounds__(kThreads) k_jac(OpsD<R> op, GeoD<R> geo, PhysP
                               DevSync());
 }
 
+template <class E, int NV, int SYS, class R, class OT>
+__global__ void __launch_bounds__((jac_tp_threads<E, NV, SYS, R>())) k_jac_tp(OpsD<R> op, Ops1D<R> o1, GeoD<R> geo, PhysP ph, const R* U,
+                                                     const R* Q, const R* UF, const R* QF, OT* B, int nblk) {
+  __shared__ __align__(16) char lds[jac_tp_lds<E, NV, SYS, R>()];
+  jac_tp_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, o1, geo, ph, U, Q, UF, QF, B, nblk,
+                                 DevSync());
+}
+
+template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);
+template <> inline Ops1D<float>& ctx_o1<float>(fr_ctx_s* c) { return c->o1f; }
+template <> inline Ops1D<double>& ctx_o1<double>(fr_ctx_s* c) { return c->o1d; }
+
 template <class R> OpsD<R>& ctx_ops(fr_ctx_s* c);
 template <> inline OpsD<float>& ctx_ops<float>(fr_ctx_s* c) { return c->opsf; }
 template <> inline OpsD<double>& ctx_ops<double>(fr_ctx_s* c) { return c->opsd; }
@@ -86,8 +98,10 @@ template <int ET, int P, int SYS, class R> struct Impl {
                                    (Dual<R>*)c->QFd, (R*)Rv, (R*)Jv);
   }
 
+  static constexpr bool kTensorPath = (ET != ET_TRI) && (jac_tp_lds<E, NV, SYS, R>() <= kMaxLds);
+
   template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B, int nblk) {
-    if constexpr (jac_lds<E, NV, SYS, R>() > kMaxLds) {
+    if constexpr (!kTensorPath && jac_lds<E, NV, SYS, R>() > kMaxLds) {
       c->err = "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
       return -2;
     } else {
@@ -107,8 +121,13 @@ template <int ET, int P, int SYS, class R> struct Impl {
       FR_LAUNCH_CHECK(c);
     }
     if (c->timing) fr_time_begin(c, 0);
-    hipLaunchKernelGGL((k_jac<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo, c->ph, U,
-                       (const R*)Q, (const R*)UF, (const R*)QF, B, nblk);
+    if constexpr (kTensorPath)
+      hipLaunchKernelGGL((k_jac_tp<E, NV, SYS, R, OT>), dim3(ne), dim3(jac_tp_threads<E, NV, SYS, R>()), 0, c->stream,
+                         op, ctx_o1<R>(c), geo,
+                         c->ph, U, (const R*)Q, (const R*)UF, (const R*)QF, B, nblk);
+    else
+      hipLaunchKernelGGL((k_jac<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo, c->ph, U,
+                         (const R*)Q, (const R*)UF, (const R*)QF, B, nblk);
     FR_LAUNCH_CHECK(c);
     if (c->timing) fr_time_end(c, 0);
     return 0;
