@@ -48,7 +48,7 @@ def jac_bytes_per_element(ns, nv, nd, nf, nface, bytes_out=4):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fr_kernels.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp"):
+    for f in ("fr_kernels.hpp", "fr_jac_tp.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2105_08632_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -56,7 +56,7 @@ def kernel_source_hash():
 def measured_traffic(per_launch_alg):
     """HBM bytes per launch of the block-assembly kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "jac_ns2d_p3_128_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_jac_tp_ns2d_p3_128_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the timed region, launch a plain device copy of MIB MiB three times "
+                         "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py drives exactly one GPU: this build has no multi-GPU path "
@@ -155,6 +158,12 @@ def main():
                                   "R(U) + 5 Jacobian blocks 64x64 per element (FP32 blocks, FP64 residual)",
                       "n_elem": ctx.ne, "dof": dof, "gpu_ms_per_step": round(gpu_ms / args.steps, 4)},
            "roofline": roof}
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, ph, p, U, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -83,6 +83,8 @@ static void pack_geo(const frh::Geometry& g, std::vector<char>& blob, std::vecto
   putR(g.S); putR(g.Jinv); putR(g.rdet); putR(g.nrm); putR(g.magN);
   put(g.nbfp.data(), g.nbfp.size() * sizeof(int));
   put(g.nbr.data(), g.nbr.size() * sizeof(int));
+  put(g.nbface.data(), g.nbface.size() * sizeof(int));
+  put(g.back.data(), g.back.size() * sizeof(int));
 }
 
 template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>& o, int ne) {
@@ -91,6 +93,7 @@ template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>
   v.S = (const R*)(base + o[0]); v.Jinv = (const R*)(base + o[1]); v.rdet = (const R*)(base + o[2]);
   v.nrm = (const R*)(base + o[3]); v.magN = (const R*)(base + o[4]);
   v.nbfp = (const int*)(base + o[5]); v.nbr = (const int*)(base + o[6]);
+  v.nbface = (const int*)(base + o[7]); v.back = (const int*)(base + o[8]);
   return v;
 }
 

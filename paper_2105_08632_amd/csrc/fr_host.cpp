@@ -515,6 +515,19 @@ bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int 
       int pg = G.nbfp[(size_t)e * nf + g];
       if (G.nbfp[(size_t)pg] != (int)(e * nf + g)) { err = "face-point pairing is not symmetric"; return false; }
     }
+  // per face: the neighbour's local face index and, for each point of that
+  // neighbour face, the partner point in this element
+  G.nbface.assign((size_t)ne * R.nface, 0);
+  G.back.assign((size_t)ne * R.nface * R.nfp, 0);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int f = 0; f < R.nface; ++f) {
+      int pg = G.nbfp[(size_t)e * nf + f * R.nfp];
+      int64_t m = pg / nf;
+      int f2 = R.fface[pg - m * nf];
+      G.nbface[e * R.nface + f] = f2;
+      for (int j = 0; j < R.nfp; ++j)
+        G.back[((size_t)e * R.nface + f) * R.nfp + j] = (int)(G.nbfp[(size_t)m * nf + f2 * R.nfp + j] - e * nf);
+    }
   return true;
 }
 

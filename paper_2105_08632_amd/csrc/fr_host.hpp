@@ -36,6 +36,7 @@ struct Geometry {
   int64_t ne = 0;
   std::vector<double> S, Jinv, rdet, nrm, magN;   // per element, element-major
   std::vector<int> nbfp, nbr;
+  std::vector<int> nbface, back;      // [ne][nface], [ne][nface][nfp]
 };
 
 // Metric terms at solution / flux points and the flux-point pairing across

@@ -94,6 +94,7 @@ template <class E, int NV, int SYS, class R> constexpr int jac_tp_fixed() {
   b += 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF);
   b += lds_bytes<R>(NFACE * NS * ND * ND) + lds_bytes<int>(NFACE * NFP) + 2 * lds_bytes<int>(NFACE);
   b += lds_bytes<R>(NFACE * NFP * ND);                                         // W (diagonal on tensor faces)
+  b += lds_bytes<Ops1D<R>>(1);
   b += lds_bytes<R>(NV * Z::TBS) + lds_bytes<R>(NV * Z::TFS);
   return b;
 }
@@ -245,6 +246,7 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
   int* snb = L.take<int>(NFACE);
   int* snf = L.take<int>(NFACE);
   R* sW = L.take<R>(NFACE * NFP * ND);
+  Ops1D<R>* sO1 = L.take<Ops1D<R>>(1);     // 1-D factors for the per-thread indexed reads below
   constexpr int GS = Z::GS, SS = Z::SS, TBS = Z::TBS, TFS = Z::TFS;
   R* tb = L.take<R>(NV * TBS);             // [alpha] [beta][tau][d][b_d0.., a_d]
   R* tf = L.take<R>(NV * TFS);             // [alpha] [beta][g][fuL, fuR, fqL_d.., fqR_d..]
@@ -272,7 +274,10 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
   for (int i = tid; i < NS * ND * ND; i += nth) { sJi[i] = geo.Jinv[nl * NS * ND * ND + i]; sS[i] = geo.S[nl * NS * ND * ND + i]; }
   for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
   for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
-  for (int i = tid; i < NFACE; i += nth) snb[i] = geo.nbr[nl * NFACE + i];
+  for (int i = tid; i < NFACE; i += nth) { snb[i] = geo.nbr[nl * NFACE + i]; snf[i] = geo.nbface[nl * NFACE + i]; }
+  for (int i = tid; i < NFACE * NFP; i += nth) sback[i] = geo.back[nl * NFACE * NFP + i];
+  for (int i = tid; i < (int)(sizeof(Ops1D<R>) / sizeof(R)); i += nth)
+    reinterpret_cast<R*>(sO1)[i] = reinterpret_cast<const R*>(&o1)[i];
   sync();
   for (int i = tid; i < NF * NV; i += nth) {
     int g = i / NV, a = i % NV;
@@ -285,16 +290,11 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
       sqL[i] = QF[(nl * NF + g) * ND * NV + r];
       sqR[i] = QF[(long)spg[g] * ND * NV + r];
     }
-  for (int i = tid; i < NFACE; i += nth) snf[i] = op.fface[spg[i * NFP] - snb[i] * NF];
   for (int i = tid; i < NFACE * NS * ND * ND; i += nth) {
     int f = i / (NS * ND * ND), r = i % (NS * ND * ND);
     sJm[i] = geo.Jinv[(long)snb[f] * NS * ND * ND + r];
   }
   sync();
-  for (int i = tid; i < NFACE * NFP; i += nth) {
-    int f = i / NFP, gj = i % NFP;
-    sback[i] = geo.nbfp[(long)snb[f] * NF + snf[f] * NFP + gj] - n * NF;
-  }
   // W_d'(g) = (1/2+beta) sum_tau' M0[g2][tau'] Cor[tau'][g2] sum_e Jinv_m[tau'][e][d'] nref[g2][e]:
   // the neighbour's face gradient at g2 (partner of g) w.r.t. u_n, which on
   // tensor elements only reaches through the same face point.
@@ -440,7 +440,7 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
         bool on = true;
         for (int d = 0; d < ND; ++d)
           if (d != e && X::co(t, d) != X::co(s, d)) on = false;
-        if (on) v = o1.G1[X::co(t, e)][X::co(s, e)];
+        if (on) v = sO1->G1[X::co(t, e)][X::co(s, e)];
       } else {
         int f = k - 1, m = snb[f];
         if (X::fax(f) == e) {
@@ -493,7 +493,7 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
               bool on = true;
               for (int d = 0; d < ND; ++d)
                 if (d != e && X::co(t, d) != X::co(s, d)) on = false;
-              if (on) acc += sJm[((fg * NS + t) * ND + e) * ND + d2] * o1.G1[X::co(t, e)][X::co(s, e)];
+              if (on) acc += sJm[((fg * NS + t) * ND + e) * ND + d2] * sO1->G1[X::co(t, e)][X::co(s, e)];
             }
             sr += mv * acc;
           }

@@ -65,6 +65,8 @@ template <class R> struct GeoD {
   const R* magN;    // [ne][NF]          |S^T nref|
   const int* nbfp;  // [ne][NF]          m*NF + g' of the flux point paired with g
   const int* nbr;   // [ne][NFACE]       face neighbours
+  const int* nbface;  // [ne][NFACE]     the neighbour's local index of the shared face
+  const int* back;    // [ne][NFACE][NFP] this element's point paired with each point of that neighbour face
 };
 
 struct DevSync {
