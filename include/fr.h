@@ -136,7 +136,8 @@ typedef enum { FR_PC_BLOCK_JACOBI = 0, FR_PC_MLP = 1 } fr_pc_kind;
  * (eq. "jacobian_rhs", k = n).  FR_PC_BLOCK_JACOBI: A_n = shift I + scale
  * dR_n/dU_n is inverted in FP64 by Gauss-Jordan elimination with partial
  * pivoting (blocks up to 128 x 128); FR_PC_MLP: the learned approximate
- * inverse (weights loaded with fr_mlp_load), with block-Jacobi as fallback.
+ * inverse (network attached with fr_precond_set_mlp), with block-Jacobi as
+ * the per-element fallback.
  * Storage for the inverses is allocated here, not in setup/apply. */
 fr_status fr_precond_create(fr_ctx* ctx, fr_pc_kind kind, fr_precond** out);
 /* Assembles and inverts the diagonal blocks at state U (device, context
@@ -147,6 +148,52 @@ fr_status fr_precond_setup(fr_precond* pc, const void* U, double shift, double s
  * r and z must not alias). */
 fr_status fr_apply_precond(fr_precond* pc, const void* r, void* z);
 fr_status fr_precond_destroy(fr_precond* pc);
+
+/* ---- Learned block preconditioner ---------------------------------------
+ * A multilayer perceptron maps the normalised diagonal block A^_n = A_n / s_n
+ * (s_n = max |A_n,ij|) to an approximate inverse M_n ~ A^_n^{-1}; the
+ * preconditioner applies z_n = M_n r_n / s_n.  Layers b^2 -> H -> H -> b^2,
+ * ReLU after each hidden layer, BF16 weights and activations with FP32
+ * accumulation (matrix cores).  Blocks and outputs are vec() of the
+ * column-major b x b matrix (b^2 BF16 values per sample, samples contiguous).
+ * Training minimises L = (1/B) sum_n ||A^_n M_n - I||_F^2 with Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8).  The paper defines only the Jacobian
+ * these blocks come from (eq. "jacobian_rhs"); the network is this library's.
+ *
+ * Parameters: one FP32 vector [W1 (H x b^2), b1 (H), W2 (H x H), b2 (H),
+ * W3 (b^2 x H), b3 (b^2)], row o of each W holding the weights into output o;
+ * n_params = 2 H b^2 + H^2 + 2 H + b^2.  All buffers are device memory owned
+ * by the caller except the network's own state, allocated in fr_mlp_create. */
+typedef struct fr_mlp_s fr_mlp;
+/* b <= 64 with b^2 a multiple of 128, hidden a multiple of 128, max_batch =
+ * samples per internal pass (activation workspace sized for it).  Weights
+ * are initialised from seed (He-normal hidden layers, small output layer,
+ * zero biases).  Work runs on hip_stream. */
+fr_status fr_mlp_create(int b, int hidden, uint64_t seed, int max_batch, void* hip_stream, fr_mlp** out);
+fr_status fr_mlp_destroy(fr_mlp* m);
+const char* fr_mlp_last_error(const fr_mlp* m);
+fr_status fr_mlp_info(const fr_mlp* m, int64_t* n_params, int* b, int* hidden, int* max_batch);
+/* Copy the FP32 parameter vector in / out (device pointers, n_params floats). */
+fr_status fr_mlp_set_params(fr_mlp* m, const float* params);
+fr_status fr_mlp_get_params(fr_mlp* m, float* params);
+/* Y = network(X) for nb samples (BF16, nb x b^2 each; any nb). */
+fr_status fr_mlp_forward(fr_mlp* m, const void* X, int64_t nb, void* Y);
+/* Loss L (device float) and its gradient (device, n_params floats,
+ * overwritten) for one batch, nb <= max_batch; resid (device, nb floats, or
+ * NULL) receives ||A^_n M_n - I||_F per sample. */
+fr_status fr_mlp_loss_grad(fr_mlp* m, const void* X, int64_t nb, float* loss, float* grad, float* resid);
+/* One Adam step at learning rate lr on the batch; loss (device float or NULL)
+ * receives the batch loss before the step. */
+fr_status fr_mlp_train_step(fr_mlp* m, const void* X, int64_t nb, float lr, float* loss);
+/* Attach a network to an FR_PC_MLP preconditioner.  In fr_precond_setup every
+ * element with ||I - A^_n M_n||_F > theta (or non-finite) falls back to the
+ * FP64 block-Jacobi inverse. */
+fr_status fr_precond_set_mlp(fr_precond* pc, fr_mlp* m, double theta);
+/* Training samples: assembles A_n = shift I + scale dR_n/dU_n at U and
+ * writes X (BF16, n_elem x b^2) and s (FP32, n_elem). */
+fr_status fr_precond_mlp_inputs(fr_precond* pc, const void* U, double shift, double scale, void* X, float* s);
+/* Number of elements that fell back to block-Jacobi in the last setup. */
+fr_status fr_precond_info(const fr_precond* pc, int64_t* n_fallback);
 
 typedef struct fr_solver_s fr_solver;
 typedef struct {

@@ -28,13 +28,13 @@ constexpr int kInvThreads = 256;
 // major) is written to Ainv.  bad[n] = 1 when a pivot is zero or not finite.
 template <class IT, int BMAX>
 __global__ void __launch_bounds__(kInvThreads) k_block_inverse(const IT* J, long jstride, int b, double shift,
-                                                               double scale, double* Ainv, int* bad) {
+                                                               double scale, double* Ainv, int* bad, const int* list) {
   __shared__ double A[BMAX * BMAX];   // row-major in LDS: A[r*b + c]
   __shared__ int perm[BMAX];
   __shared__ double red_v[kInvThreads];
   __shared__ int red_i[kInvThreads];
   __shared__ int s_bad;
-  const int n = blockIdx.x, tid = threadIdx.x;
+  const int n = list ? list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const IT* Jn = J + (long)n * jstride;
   for (int i = tid; i < b * b; i += kInvThreads) {
     int c = i / b, r = i % b;                       // source is column-major
@@ -215,32 +215,43 @@ static int grid_for(long n, int threads) {
   return (int)(g > 4096 ? 4096 : (g < 1 ? 1 : g));
 }
 
-fr_status pc_lu_setup(fr_precond_s* pc, const void* U, double shift, double scale) {
+// Inverts A_n = shift I + scale J_n for the listed elements (all when list
+// is null) from the diagonal blocks in pc->jbuf; flags land in pc->bad.
+fr_status pc_invert(fr_precond_s* pc, double shift, double scale, const int* list, long count) {
   fr_ctx_s* c = pc->ctx;
   const int b = c->b;
-  const long ne = c->ne;
-  // diagonal blocks in the context precision, then FP64 inversion
-  void* J = pc->jbuf;
-  int rc = c->ks.jac(c, U, J, c->prec == 0 ? 0 : 1, 1);
-  if (rc) return (fr_status)rc;
+  const long bb = (long)b * b;
+  if (count <= 0) return FR_OK;
+  const void* J = pc->jbuf;
   if (b <= 64) {
     if (c->prec == 0)
-      hipLaunchKernelGGL((k_block_inverse<double, 64>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const double*)J,
-                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+      hipLaunchKernelGGL((k_block_inverse<double, 64>), dim3(count), dim3(kInvThreads), 0, c->stream,
+                         (const double*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
     else
-      hipLaunchKernelGGL((k_block_inverse<float, 64>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const float*)J,
-                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+      hipLaunchKernelGGL((k_block_inverse<float, 64>), dim3(count), dim3(kInvThreads), 0, c->stream,
+                         (const float*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
   } else if (b <= 128) {
     if (c->prec == 0)
-      hipLaunchKernelGGL((k_block_inverse<double, 128>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const double*)J,
-                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+      hipLaunchKernelGGL((k_block_inverse<double, 128>), dim3(count), dim3(kInvThreads), 0, c->stream,
+                         (const double*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
     else
-      hipLaunchKernelGGL((k_block_inverse<float, 128>), dim3(ne), dim3(kInvThreads), 0, c->stream, (const float*)J,
-                         (long)b * b, b, shift, scale, pc->inv, pc->bad);
+      hipLaunchKernelGGL((k_block_inverse<float, 128>), dim3(count), dim3(kInvThreads), 0, c->stream,
+                         (const float*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
   } else {
     return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi inverse supports blocks up to 128 x 128");
   }
   HIPCHK(c, hipGetLastError());
+  return FR_OK;
+}
+
+fr_status pc_lu_setup(fr_precond_s* pc, const void* U, double shift, double scale) {
+  fr_ctx_s* c = pc->ctx;
+  const long ne = c->ne;
+  // diagonal blocks in the context precision, then FP64 inversion
+  int rc = c->ks.jac(c, U, pc->jbuf, c->prec == 0 ? 0 : 1, 1);
+  if (rc) return (fr_status)rc;
+  fr_status st = pc_invert(pc, shift, scale, nullptr, ne);
+  if (st) return st;
   HIPCHK(c, hipMemcpyAsync(pc->bad_host, pc->bad, ne * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (long n = 0; n < ne; ++n)

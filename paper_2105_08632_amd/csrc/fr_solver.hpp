@@ -23,5 +23,6 @@ fr_status pc_mlp_setup(fr_precond_s* pc, const void* U, double shift, double sca
 fr_status pc_mlp_apply(fr_precond_s* pc, const void* r, void* z);
 void pc_mlp_destroy(fr_precond_s* pc);
 
+fr_status pc_invert(fr_precond_s* pc, double shift, double scale, const int* list, long count);
 fr_status pc_lu_setup(fr_precond_s* pc, const void* U, double shift, double scale);
 fr_status pc_lu_apply(fr_precond_s* pc, const void* r, void* z);

@@ -293,3 +293,126 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned preconditioner
+def _mlp_symbols(L):
+    P = C.c_void_p
+    L.fr_mlp_create.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_int, P, C.POINTER(P)]
+    L.fr_mlp_destroy.argtypes = [P]
+    L.fr_mlp_last_error.argtypes = [P]
+    L.fr_mlp_last_error.restype = C.c_char_p
+    L.fr_mlp_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.fr_mlp_set_params.argtypes = [P, P]
+    L.fr_mlp_get_params.argtypes = [P, P]
+    L.fr_mlp_forward.argtypes = [P, P, C.c_int64, P]
+    L.fr_mlp_loss_grad.argtypes = [P, P, C.c_int64, P, P, P]
+    L.fr_mlp_train_step.argtypes = [P, P, C.c_int64, C.c_float, P]
+    L.fr_precond_set_mlp.argtypes = [P, P, C.c_double]
+    L.fr_precond_mlp_inputs.argtypes = [P, P, C.c_double, C.c_double, P, P]
+    L.fr_precond_info.argtypes = [P, C.POINTER(C.c_int64)]
+    for n in ("fr_mlp_create", "fr_mlp_destroy", "fr_mlp_info", "fr_mlp_set_params", "fr_mlp_get_params",
+              "fr_mlp_forward", "fr_mlp_loss_grad", "fr_mlp_train_step", "fr_precond_set_mlp",
+              "fr_precond_mlp_inputs", "fr_precond_info"):
+        getattr(L, n).restype = C.c_int
+
+
+_extensions.append(_mlp_symbols)
+EXPORTED += ["fr_mlp_create", "fr_mlp_destroy", "fr_mlp_last_error", "fr_mlp_info", "fr_mlp_set_params",
+             "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_loss_grad", "fr_mlp_train_step", "fr_precond_set_mlp",
+             "fr_precond_mlp_inputs", "fr_precond_info"]
+
+
+def _mcheck(rc: int, h):
+    if rc != 0:
+        raise FrError(rc, lib().fr_mlp_last_error(h).decode())
+
+
+class Mlp:
+    """The learned block-inverse network (b^2 -> hidden -> hidden -> b^2)."""
+
+    def __init__(self, b: int, hidden: int = 256, seed: int = 0, max_batch: int = 4096, stream=None):
+        import torch
+        self._torch = torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        h = C.c_void_p()
+        rc = lib().fr_mlp_create(b, hidden, seed, max_batch, s.cuda_stream, C.byref(h))
+        if rc != 0:
+            raise FrError(rc, f"fr_mlp_create(b={b}, hidden={hidden}, max_batch={max_batch})")
+        self.h = h
+        n = C.c_int64()
+        lib().fr_mlp_info(h, C.byref(n), None, None, None)
+        self.b, self.hidden, self.max_batch, self.n_params = b, hidden, max_batch, n.value
+        self._loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def params(self):
+        t = self._torch.empty(self.n_params, dtype=self._torch.float32, device="cuda")
+        _mcheck(lib().fr_mlp_get_params(self.h, _ptr(t)), self.h)
+        return t
+
+    def set_params(self, p):
+        p = p.to(self._torch.float32).contiguous()
+        assert p.numel() == self.n_params and p.is_cuda
+        _mcheck(lib().fr_mlp_set_params(self.h, _ptr(p)), self.h)
+
+    def _x(self, X):
+        assert X.dtype == self._torch.bfloat16 and X.is_cuda and X.is_contiguous()
+        assert X.shape[-1] == self.b * self.b
+        return X
+
+    def forward(self, X, out=None):
+        X = self._x(X)
+        Y = self._torch.empty_like(X) if out is None else out
+        _mcheck(lib().fr_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y)), self.h)
+        return Y
+
+    def loss_grad(self, X):
+        X = self._x(X)
+        g = self._torch.empty(self.n_params, dtype=self._torch.float32, device="cuda")
+        res = self._torch.empty(X.shape[0], dtype=self._torch.float32, device="cuda")
+        _mcheck(lib().fr_mlp_loss_grad(self.h, _ptr(X), X.shape[0], _ptr(self._loss), _ptr(g), _ptr(res)), self.h)
+        return self._loss.clone(), g, res
+
+    def train_step(self, X, lr: float):
+        """One Adam step; returns the batch loss as a device tensor (no sync)."""
+        X = self._x(X)
+        loss = self._torch.empty(1, dtype=self._torch.float32, device="cuda")
+        _mcheck(lib().fr_mlp_train_step(self.h, _ptr(X), X.shape[0], lr, _ptr(loss)), self.h)
+        return loss
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fr_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _precond_set_mlp(self, mlp: Mlp, theta: float):
+    _check(lib().fr_precond_set_mlp(self.h, mlp.h, theta), self.ctx.h)
+    self.mlp = mlp
+
+
+def _precond_mlp_inputs(self, U, shift: float, scale: float, X=None, s=None):
+    import torch
+    ne, b = self.ctx.ne, self.ctx.b
+    X = torch.empty((ne, b * b), dtype=torch.bfloat16, device="cuda") if X is None else X
+    s = torch.empty(ne, dtype=torch.float32, device="cuda") if s is None else s
+    _check(lib().fr_precond_mlp_inputs(self.h, _ptr(self.ctx._vec(U)), shift, scale, _ptr(X), _ptr(s)), self.ctx.h)
+    return X, s
+
+
+def _precond_n_fallback(self) -> int:
+    n = C.c_int64()
+    _check(lib().fr_precond_info(self.h, C.byref(n)), self.ctx.h)
+    return n.value
+
+
+Precond.set_mlp = _precond_set_mlp
+Precond.mlp_inputs = _precond_mlp_inputs
+Precond.n_fallback = property(_precond_n_fallback)
