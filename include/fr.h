@@ -202,6 +202,7 @@ typedef struct {
   int32_t newton_maxit;
   double gmres_rtol;      /* relative true linear residual per Newton iteration */
   int32_t gmres_maxit;    /* GMRES iterations per Newton iteration (all restarts) */
+  int32_t pc_refresh;     /* 0: preconditioner set up once at U^n; 1: at every Newton iterate */
 } fr_newton_opts;
 typedef struct {
   int32_t newton_iters, gmres_iters, pc_setups, converged;
@@ -218,7 +219,8 @@ fr_status fr_solver_destroy(fr_solver* s);
 /* One backward-Euler step from Un to U (device FP64 vectors): Newton on
  * F(U) = U - Un - dt R(U), each correction from right-preconditioned
  * GMRES(restart) on (I - dt dR/dU) dU = -F with exact Jacobian-vector
- * products; the preconditioner (or NULL) is set up once at Un.  Returns
+ * products; the preconditioner (or NULL) is set up at Un, and again at
+ * every Newton iterate when opts->pc_refresh is set.  Returns
  * FR_E_NOT_CONVERGED if newton_maxit iterations do not reach newton_rtol. */
 fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un, void* U, const fr_newton_opts* opts,
                          fr_newton_stats* stats);

@@ -341,6 +341,7 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
   if (b0 == 0.0) { *res_true = 0.0; return FR_OK; }
   double beta = b0;
   int total = 0;
+  std::vector<double> hist{b0};   // true residual at the start of each cycle
   while (true) {
     // v_0 = r / beta
     if ((st = axpby(s, 1.0 / beta, s->w, 0.0, nullptr, s->V))) return st;
@@ -399,9 +400,12 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
     if ((st = dots(s, 1, s->w, s->w, &nrm))) return st;
     beta = std::sqrt(nrm);
     *iters = total;
-    const double prev = *res_true > 0 ? *res_true : b0;
     *res_true = beta;
-    if (beta <= rtol * b0 || total >= maxit || beta > 0.99 * prev) break;
+    // stagnation: less than 1% reduction over the last four restart cycles
+    hist.push_back(beta);
+    const size_t nh = hist.size();
+    const bool stalled = nh >= 5 && beta > 0.99 * hist[nh - 5];
+    if (beta <= rtol * b0 || total >= maxit || stalled) break;
   }
   return FR_OK;
 }
@@ -529,6 +533,10 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
     st->newton_iters = it;
     if (fn <= o->newton_rtol * f0 || f0 == 0.0) { st->converged = 1; break; }
     if (it == o->newton_maxit) break;
+    if (pc && o->pc_refresh && it > 0) {
+      if ((rs = fr_precond_setup(pc, U, 1.0, -o->dt))) return rs;
+      st->pc_setups += 1;
+    }
     // solve (I - dt J) dU = -F
     if ((rs = axpby(s, -1.0, s->F, 0.0, nullptr, s->F))) return rs;
     int gi = 0;
