@@ -65,6 +65,105 @@ def measured_traffic(per_launch_alg):
     return d.get("hbm_bytes_per_launch")
 
 
+def _dt(m, U, cfl, gamma=1.4):
+    """Backward-Euler step for an acoustic CFL: cfl * h / max(|v| + c)."""
+    rho = U[..., 0]
+    v = U[..., 1:3] / rho[..., None]
+    pr = (gamma - 1.0) * (U[..., 3] - 0.5 * rho * np.sum(v * v, axis=-1))
+    smax = np.max(np.linalg.norm(v, axis=-1) + np.sqrt(gamma * pr / rho))
+    return cfl / round(np.sqrt(m.n_elem)) / smax
+
+
+def train_mlp(torch, fr, I, steps, log):
+    """The learned preconditioner, trained on the library's own diagonal
+    blocks I - dt dR_n/dU_n from 128x128 NS p=3 states (seeds 11-18), at
+    Re 500 and 1000 (so the 256x256 mesh's cell Reynolds numbers are inside
+    the training set) and CFL 2..100; Adam, batch 1024."""
+    t0 = time.perf_counter()
+    m1 = I.quad_mesh(128, degree=3, jitter=0.05)
+    blocks = []
+    for Re in (500.0, 1000.0):
+        ph = I.ns_physics(2, reynolds=Re, prandtl=0.72)
+        for i in range(8):
+            U = I.ns2d_state(m1, 3, seeds=(11 + i, 111 + i, 211 + i))
+            ctx = fr.Context(m1, ph, "f64")
+            pc = fr.Precond(ctx, fr.FR_PC_MLP)
+            Ud = torch.from_numpy(U).cuda()
+            for c in (2.0, 5.0, 10.0, 25.0, 50.0, 100.0):
+                X, _ = pc.mlp_inputs(Ud, 1.0, -_dt(m1, U, c))
+                blocks.append(X.clone())
+            del pc, ctx
+    train = torch.cat(blocks)
+    del blocks
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = fr.Mlp(64, 256, seed=5, max_batch=4096)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    t0 = time.perf_counter()
+    loss = None
+    for it in range(steps):
+        idx = torch.randint(0, train.shape[0], (1024,), device="cuda", generator=g)
+        lr = 1e-3 if it < 0.6 * steps else (3e-4 if it < 0.85 * steps else 1e-4)
+        loss = net.train_step(train[idx].contiguous(), lr)
+        if it % 4000 == 0:
+            log(f"mlp step {it} loss {float(loss.item()):.3f}")
+    torch.cuda.synchronize()
+    info = {"samples": int(train.shape[0]), "steps": steps, "batch": 1024, "data_s": round(t_data, 2),
+            "train_s": round(time.perf_counter() - t0, 2), "final_batch_loss": round(float(loss.item()), 4)}
+    del train
+    return net, info
+
+
+def newton_bench(torch, fr, I, train_steps, log):
+    """Seconds per backward-Euler Newton step (to |F| <= 1e-8 |F0|, GMRES(30),
+    forcing 1e-3) on 256x256 NS p=3: FP64 block-Jacobi LU vs the learned
+    preconditioner, each set up at U^n (setup time included)."""
+    net, info = train_mlp(torch, fr, I, train_steps, log)
+    ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
+    m = I.quad_mesh(256, degree=3, jitter=0.05)
+    out = {"workload": "2D NS p=3, 256x256 jittered periodic quads (4.19 M DOF), backward Euler, Newton to "
+                       "1e-8 relative, GMRES(30) forcing 1e-3, preconditioner set up at U^n",
+           "mlp_training": info}
+    runs = {"lu": [], "mlp": []}
+    held = []
+    cfl = 5.0
+    for s in (8, 9, 10):
+        U = I.ns2d_state(m, 3, seeds=(s, 100 + s, 200 + s))
+        ctx = fr.Context(m, ph, "f64")
+        Ud = torch.from_numpy(U).cuda()
+        dt = _dt(m, U, cfl)
+        sol = fr.Solver(ctx, restart=30)
+        pcm = fr.Precond(ctx, fr.FR_PC_MLP)
+        pcm.set_mlp(net, 1e30)
+        Xh, _ = pcm.mlp_inputs(Ud, 1.0, -dt)
+        held.append(float(torch.cat([net.loss_grad(Xh[i:i + 4096].contiguous())[2]
+                                     for i in range(0, Xh.shape[0], 4096)]).mean().item()))
+        del Xh
+        for name, pc in (("lu", fr.Precond(ctx)), ("mlp", pcm)):
+            r = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False)
+            runs[name].append(r)
+            log(f"newton cfl {cfl} seed {s} {name}: conv {r['converged']} newton {r['newton_iters']} "
+                f"gmres {r['gmres_iters']} s {r['ms'] / 1e3:.3f}")
+        if s == 8:
+            hard = {}
+            for name, pc in (("lu", fr.Precond(ctx)), ("mlp", pcm)):
+                r = sol.newton_step(Ud, pc=pc, dt=_dt(m, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False)
+                hard[name] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
+                              "gmres_iters": r["gmres_iters"], "final_rel_residual": r["res"] / r["res0"],
+                              "s": round(r["ms"] / 1e3, 3)}
+                log(f"newton cfl 100 {name}: conv {r['converged']} rel {r['res'] / r['res0']:.2e}")
+            out["cfl100"] = hard
+        del sol, pcm, ctx
+    for name, rs in runs.items():
+        out[name] = {"s_per_step_median": round(float(np.median([r["ms"] for r in rs])) / 1e3, 4),
+                     "converged": [bool(r["converged"]) for r in rs],
+                     "newton_iters": [r["newton_iters"] for r in rs], "gmres_iters": [r["gmres_iters"] for r in rs]}
+    out["cfl"] = cfl
+    out["mlp_heldout_resid_mean"] = round(float(np.mean(held)), 3)
+    out["learned_over_lu_time"] = round(out["mlp"]["s_per_step_median"] / out["lu"]["s_per_step_median"], 3)
+    return out
+
+
 def cpu_baseline(m, ph, p, U, budget_s):
     """The FP64 oracle (as is) on a bounded sample: the full-mesh residual,
     then the five Jacobian blocks of a seeded sample of elements."""
@@ -98,6 +197,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-GMRES part of the metric")
+    ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -164,6 +265,11 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not args.no_newton:
+        del B, R
+        torch.cuda.empty_cache()
+        from paper_2105_08632_amd import inputs as I
+        out["newton"] = newton_bench(torch, fr, I, args.mlp_steps, lambda s: print(s, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(m, ph, p, U, args.cpu_seconds)
     print(json.dumps(out), flush=True)
