@@ -107,6 +107,65 @@ def quad_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0), degree: int = 1,
                 xyz, nbr, nbr_face, h)
 
 
+def tri_points(p: int, shrink: float = 0.8) -> np.ndarray:
+    """Solution points [Ns, 2] on the reference triangle (-1,-1), (1,-1),
+    (-1,1): the equispaced degree-p lattice contracted toward the centroid by
+    `shrink`.  The set is symmetric under the triangle's symmetries,
+    unisolvent (an affine image of the lattice) and interior.  The paper
+    names Williams-Shunn points but does not tabulate them; FR-DG depends on
+    the set only through the nonlinear flux, so results are for this set."""
+    pts = np.array([(-1.0 + 2.0 * i / p, -1.0 + 2.0 * j / p)
+                    for j in range(p + 1) for i in range(p + 1 - j)])
+    c = np.array([-1.0 / 3.0, -1.0 / 3.0])
+    return c + shrink * (pts - c)
+
+
+def tri_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0), degree: int = 1,
+             jitter: float = 0.0, K: int | None = None, seed: int = 0) -> Mesh:
+    """N x N periodic cells on [origin, origin+L]^2, each split into two
+    triangles along a diagonal drawn per cell from `seed`; vertices jittered
+    as in quad_mesh (straight edges, affine triangles).  Triangle vertices are
+    counter-clockwise; local face f joins vertices f and f+1 (mod 3)."""
+    if N < 3:
+        raise ValueError("tri_mesh needs N >= 3 (distinct periodic edges)")
+    h = L / N
+    if K is None:
+        K = max(N // 4, 1)
+    rng = np.random.default_rng(seed)
+    diag = rng.integers(0, 2, size=N * N)
+    n = 2 * N * N
+    xyz = np.zeros((n, 3, 2))
+    verts = []          # lattice (i, j) of each element's vertices
+    for j in range(N):
+        for i in range(N):
+            c = i + N * j
+            A, B, C, D = (i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)
+            tris = ((A, B, C), (A, C, D)) if diag[c] == 0 else ((A, B, D), (B, C, D))
+            for t, tri in enumerate(tris):
+                e = 2 * c + t
+                verts.append(tri)
+                for v, (vi, vj) in enumerate(tri):
+                    xs, ys = vi / N, vj / N
+                    jx, jy = _jitter2(xs, ys, 1.0 / N, jitter, K)
+                    xyz[e, v, 0] = origin[0] + L * (xs + jx)
+                    xyz[e, v, 1] = origin[1] + L * (ys + jy)
+    edges = {}
+    for e, tri in enumerate(verts):
+        for f in range(3):
+            a, b = tri[f], tri[(f + 1) % 3]
+            key = frozenset(((a[0] % N, a[1] % N), (b[0] % N, b[1] % N)))
+            edges.setdefault(key, []).append((e, f))
+    nbr = np.full((n, 3), -1, dtype=np.int64)
+    nbr_face = np.full((n, 3), -1, dtype=np.int8)
+    for key, lst in edges.items():
+        if len(lst) != 2:
+            raise RuntimeError("tri_mesh: non-conforming edge")
+        (e1, f1), (e2, f2) = lst
+        nbr[e1, f1], nbr_face[e1, f1] = e2, f2
+        nbr[e2, f2], nbr_face[e2, f2] = e1, f1
+    return Mesh(2, np.full(n, TRI, np.int8), np.full(n, degree, np.int8), xyz, nbr, nbr_face, h)
+
+
 def hex_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0, 0.0), degree: int = 1,
              jitter: float = 0.0, K: int | None = None) -> Mesh:
     """N^3 periodic hexes on [origin, origin+L]^3 (optionally jittered with
@@ -198,11 +257,11 @@ def smooth_random_field(x: np.ndarray, rng: np.random.Generator, L: float = 1.0,
     return s / np.max(np.abs(s))
 
 
-def advection_state(mesh: Mesh, p: int, seed: int = 1) -> np.ndarray:
+def advection_state(mesh: Mesh, p: int, seed: int = 1, tri_pts: np.ndarray | None = None) -> np.ndarray:
     """Scalar field: sum of three random-amplitude sinusoids (a_k ~ U(0.5,1.5),
     integer wave vectors in [-3,3]^2, random phases) at the solution points."""
     rng = np.random.default_rng(seed)
-    x = sol_points_phys(mesh, p)
+    x = sol_points_phys(mesh, p, tri_pts)
     u = np.zeros(x.shape[:2])
     for _ in range(3):
         a = rng.uniform(0.5, 1.5)
@@ -223,10 +282,10 @@ def conservative(rho, vel, p, gamma):
 
 
 def ns2d_state(mesh: Mesh, p: int, seeds=(2, 3, 4), mach: float = 0.2,
-               gamma: float = 1.4) -> np.ndarray:
+               gamma: float = 1.4, tri_pts: np.ndarray | None = None) -> np.ndarray:
     """rho = 1 + 0.1 s_rho, v = smooth random field of unit peak speed,
     uniform pressure p0 = rho0 V0^2/(gamma Ma^2)."""
-    x = sol_points_phys(mesh, p)
+    x = sol_points_phys(mesh, p, tri_pts)
     rho = 1.0 + 0.1 * smooth_random_field(x, np.random.default_rng(seeds[0]))
     vx = smooth_random_field(x, np.random.default_rng(seeds[1]))
     vy = smooth_random_field(x, np.random.default_rng(seeds[2]))

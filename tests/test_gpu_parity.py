@@ -16,9 +16,9 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 2e-2}
 
 
-def _ctx(m, ph, prec):
+def _ctx(m, ph, prec, tri_pts=None):
     from paper_2105_08632_amd import fr
-    return fr.Context(m, ph, prec)
+    return fr.Context(m, ph, prec, tri_pts=tri_pts)
 
 
 def rel(x, ref):
@@ -37,11 +37,11 @@ def _blocks_rowmajor(B):
         B.double().cpu().numpy().transpose(0, 1, 3, 2)
 
 
-def check_case(m, ph, p, U, prec, elems, blocks=True, jvp=True):
+def check_case(m, ph, p, U, prec, elems, blocks=True, jvp=True, tri_pts=None):
     Ud = _dev(U, prec)
     Uq = Ud.double().cpu().numpy()            # the rounded input the GPU sees
-    o = O.Oracle(m, ph, p)
-    ctx = _ctx(m, ph, prec)
+    o = O.Oracle(m, ph, p, tri_pts)
+    ctx = _ctx(m, ph, prec, tri_pts)
     R = ctx.rhs(Ud)
     torch.cuda.synchronize()
     ctx.sync()
@@ -166,3 +166,25 @@ def test_errors_are_reported():
         ctx.jacobian_blocks(ctx.empty_state().zero_(), out_prec="f64")
     with pytest.raises(ValueError):
         ctx.rhs(torch.zeros(3, device="cuda"))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("system", ["euler", "ns"])
+def test_tri_fp64(system, p):
+    """Periodic split-cell triangles (random diagonals, jittered vertices)."""
+    tp = I.tri_points(p)
+    m = I.tri_mesh(5, degree=p, jitter=0.05, K=1, seed=6)
+    ph = I.euler_physics(2) if system == "euler" else I.ns_physics(2, 100.0, 0.72)
+    U = I.ns2d_state(m, p, tri_pts=tp)
+    out = check_case(m, ph, p, U, "f64", [0, 7, m.n_elem - 1], tri_pts=tp)
+    _assert(out, "f64", (p, system))
+
+
+def test_tri_ns_fp32():
+    p = 3
+    tp = I.tri_points(p)
+    m = I.tri_mesh(6, degree=p, jitter=0.05, K=1, seed=7)
+    ph = I.ns_physics(2, 1000.0, 0.72)
+    U = I.ns2d_state(m, p, tri_pts=tp)
+    out = check_case(m, ph, p, U, "f32", [0, 11, m.n_elem - 1], tri_pts=tp)
+    _assert(out, "f32", p)
