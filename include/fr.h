@@ -203,6 +203,8 @@ typedef struct {
   double gmres_rtol;      /* relative true linear residual per Newton iteration */
   int32_t gmres_maxit;    /* GMRES iterations per Newton iteration (all restarts) */
   int32_t pc_refresh;     /* 0: preconditioner set up once at U^n; 1: at every Newton iterate */
+  int32_t use_graph;      /* 1: each GMRES restart cycle is a replayed hipGraph (device-resident
+                             Arnoldi, one host read per cycle); 0: host-driven Arnoldi */
 } fr_newton_opts;
 typedef struct {
   int32_t newton_iters, gmres_iters, pc_setups, converged;
@@ -211,6 +213,7 @@ typedef struct {
   double ms;              /* wall time of the step on the context stream */
   double res_hist[32];    /* |F|_2 after each Newton iteration (first 32) */
   int32_t gmres_hist[32]; /* GMRES iterations of each Newton iteration */
+  int32_t cycles;         /* restart cycles replayed from the captured graph */
 } fr_newton_stats;
 
 /* Krylov workspace for GMRES(restart), restart <= 31 (FP64 contexts). */

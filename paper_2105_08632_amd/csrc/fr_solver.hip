@@ -199,6 +199,42 @@ __global__ void k_multi_axpy_add(long n, int k, const double* y, const double* Z
   }
 }
 
+// ---- device-resident Arnoldi step pieces (graph-capturable: every scalar
+// stays on the device)
+// H[i][j] = a[i] + b[i], i <= j (the two classical Gram-Schmidt passes)
+__global__ void k_arnoldi_col(int j, int m, const double* a, const double* b, double* H) {
+  const int i = threadIdx.x;
+  if (i <= j) H[i * m + j] = a[i] + b[i];
+}
+
+// hn = sqrt(*dn); H[j+1][j] = hn; v = w / hn (0 on breakdown)
+__global__ void k_norm_scale(long n, int j, int m, const double* dn, const double* w, double* v, double* H) {
+  const double hn = sqrt(fmax(*dn, 0.0));
+  if (blockIdx.x == 0 && threadIdx.x == 0) H[(j + 1) * m + j] = hn;
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) v[i] = w[i] * inv;
+}
+
+// Givens rotations on Hessenberg column j (one thread): previous rotations,
+// then the new one; g is the rotated right-hand side, est[j] = |g[j+1]|.
+__global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* est) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < j; ++i) {
+    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+    H[i * m + j] = cs[i] * a + sn[i] * b;
+    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = H[j * m + j], b = H[(j + 1) * m + j];
+  const double r = hypot(a, b);
+  cs[j] = r > 0.0 ? a / r : 1.0;
+  sn[j] = r > 0.0 ? b / r : 0.0;
+  H[j * m + j] = r;
+  H[(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  est[j] = fabs(g[j + 1]);
+}
+
 // ------------------------------------------------------------ helpers
 static fr_status sfail(fr_ctx_s* c, fr_status s, const std::string& m) {
   c->err = m;
@@ -286,6 +322,14 @@ struct fr_solver_s {
   double *partial = nullptr, *dots = nullptr, *hcol = nullptr;
   double* host = nullptr;   // pinned scalars
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // captured restart cycle: Hessenberg state on the device, [H | cs | sn | g | est]
+  double *dH = nullptr, *dcs = nullptr, *dsn = nullptr, *dg = nullptr, *dest = nullptr;
+  double *dh1 = nullptr, *dh2 = nullptr, *dn = nullptr;
+  double* hstate = nullptr;      // pinned copy of the state block
+  hipStream_t cs = nullptr;      // the solver's own (capturable) stream
+  hipEvent_t join0 = nullptr, join1 = nullptr;
+  hipGraphExec_t cycle = nullptr;
+  const void* key_U = nullptr; const void* key_pc = nullptr; double key_dt = 0.0;
 };
 
 static fr_status dots(fr_solver_s* s, int k, const double* V, const double* w, double* out_host) {
@@ -410,6 +454,130 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
   return FR_OK;
 }
 
+// ---- GMRES with a captured restart cycle
+// One cycle = m Arnoldi steps with every scalar on the device (precondition,
+// Jacobian-vector product, two classical Gram-Schmidt passes, normalisation,
+// Givens rotation): recorded once into a hipGraph per (iterate buffer,
+// preconditioner, dt) and replayed for each restart; the host reads the
+// small Hessenberg state once per cycle.  The cycle always runs m steps; the
+// solution update uses the steps up to the first one whose residual
+// estimate meets the tolerance.
+static fr_status record_cycle(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
+  fr_ctx_s* c = s->ctx;
+  const int m = s->m;
+  const long N = s->N;
+  const int grid = grid_for(N, 256);
+  fr_status st = FR_OK;
+  for (int j = 0; j < m && st == FR_OK; ++j) {
+    double* vj = s->V + (long)j * N;
+    double* zj = s->Z + (long)j * N;
+    if (pc) st = fr_apply_precond(pc, vj, zj);
+    else hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(256), 0, c->stream, N, 1.0, vj, 0.0, nullptr, zj);
+    if (st == FR_OK) st = apply_A(s, U, dt, zj, s->w, nullptr);
+    if (st) break;
+    for (int pass = 0; pass < 2; ++pass) {
+      double* h = pass == 0 ? s->dh1 : s->dh2;
+      hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks), dim3(kDotThreads), 0, c->stream, N, j + 1, s->V, N, s->w,
+                         s->partial);
+      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->stream, j + 1, kDotBlocks, s->partial, h);
+      hipLaunchKernelGGL(k_multi_axpy, dim3(grid), dim3(256), 0, c->stream, N, j + 1, h, s->V, N, s->w);
+    }
+    hipLaunchKernelGGL(k_arnoldi_col, dim3(1), dim3(32), 0, c->stream, j, m, s->dh1, s->dh2, s->dH);
+    hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks), dim3(kDotThreads), 0, c->stream, N, 1, s->w, N, s->w, s->partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->stream, 1, kDotBlocks, s->partial, s->dn);
+    hipLaunchKernelGGL(k_norm_scale, dim3(grid), dim3(256), 0, c->stream, N, j, m, s->dn, s->w,
+                       s->V + (long)(j + 1) * N, s->dH);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, j, m, s->dH, s->dcs, s->dsn, s->dg, s->dest);
+    if (hipGetLastError() != hipSuccess) st = sfail(c, FR_E_DEVICE, "launch while recording the GMRES cycle");
+  }
+  return st;
+}
+
+static fr_status ensure_cycle(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
+  fr_ctx_s* c = s->ctx;
+  if (s->cycle && s->key_U == U && s->key_pc == pc && s->key_dt == dt) return FR_OK;
+  if (s->cycle) { (void)hipGraphExecDestroy(s->cycle); s->cycle = nullptr; }
+  const bool timing = c->timing;
+  c->timing = false;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  fr_status st = record_cycle(s, pc, U, dt);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->timing = timing;
+  if (st == FR_OK && e != hipSuccess) st = sfail(c, FR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (st == FR_OK && hipGraphInstantiate(&s->cycle, g, nullptr, nullptr, 0) != hipSuccess) {
+    s->cycle = nullptr;
+    st = sfail(c, FR_E_DEVICE, "hipGraphInstantiate of the GMRES cycle");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (st) return st;
+  s->key_U = U; s->key_pc = pc; s->key_dt = dt;
+  return FR_OK;
+}
+
+static fr_status gmres_graph(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt, const double* rhs,
+                             double rtol, int maxit, double* x, int* iters, double* res_true, double* res0_out,
+                             int* cycles) {
+  fr_ctx_s* c = s->ctx;
+  const int m = s->m;
+  const long N = s->N;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 0.0, x);
+  HIPCHK(c, hipMemcpyAsync(s->w, rhs, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  double nrm;
+  fr_status st = dots(s, 1, s->w, s->w, &nrm);
+  if (st) return st;
+  const double b0 = std::sqrt(nrm);
+  *res0_out = b0;
+  *iters = 0;
+  *res_true = 0.0;
+  if (b0 == 0.0) return FR_OK;
+  if ((st = ensure_cycle(s, pc, U, dt))) return st;
+  double beta = b0;
+  int total = 0, work = 0;
+  std::vector<double> hist{b0}, g0(m + 1, 0.0), y(m);
+  const size_t nstate = (size_t)(m + 1) * m + (m + 1) + m;    // H, g, est
+  while (true) {
+    if ((st = axpby(s, 1.0 / beta, s->w, 0.0, nullptr, s->V))) return st;
+    g0[0] = beta;
+    HIPCHK(c, hipMemcpyAsync(s->dg, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipGraphLaunch(s->cycle, c->stream));
+    *cycles += 1;
+    work += m;
+    HIPCHK(c, hipMemcpyAsync(s->hstate, s->dH, nstate * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double* H = s->hstate;
+    const double* g = H + (size_t)(m + 1) * m;
+    const double* est = g + (m + 1);
+    int jj = m;
+    for (int j = 0; j < m; ++j) {
+      if (H[j * m + j] == 0.0) { jj = j; break; }          // breakdown: the Krylov space is exhausted
+      if (est[j] <= rtol * b0) { jj = j + 1; break; }
+    }
+    for (int i = jj - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < jj; ++k) acc -= H[i * m + k] * y[k];
+      y[i] = acc / H[i * m + i];
+    }
+    total += jj;
+    if (jj > 0) {
+      HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), jj * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, jj, s->hcol, s->Z, N, x);
+      HIPCHK(c, hipGetLastError());
+    }
+    if ((st = apply_A(s, U, dt, x, s->w, nullptr))) return st;
+    if ((st = axpby(s, 1.0, rhs, -1.0, s->w, s->w))) return st;
+    if ((st = dots(s, 1, s->w, s->w, &nrm))) return st;
+    beta = std::sqrt(nrm);
+    *iters = total;
+    *res_true = beta;
+    hist.push_back(beta);
+    const size_t nh = hist.size();
+    const bool stalled = nh >= 5 && beta > 0.99 * hist[nh - 5];
+    if (beta <= rtol * b0 || work >= maxit || stalled || jj == 0) break;
+  }
+  return FR_OK;
+}
+
 extern "C" {
 
 fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
@@ -483,6 +651,23 @@ fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
   if (hipEventCreate(&s->e0) != hipSuccess || hipEventCreate(&s->e1) != hipSuccess) {
     (void)hipFree(s->mem); (void)hipHostFree(s->host); delete s; return sfail(c, FR_E_DEVICE, "events");
   }
+  const int m = restart;
+  const size_t nstate = (size_t)(m + 1) * m + (m + 1) + m + 2 * m + 3 * 32;
+  if (hipMalloc(&s->dH, nstate * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&s->hstate, nstate * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->cs, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->join0, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->join1, hipEventDisableTiming) != hipSuccess) {
+    fr_solver_destroy(s);
+    return sfail(c, FR_E_NOMEM, "solver cycle state");
+  }
+  s->dg = s->dH + (size_t)(m + 1) * m;
+  s->dest = s->dg + (m + 1);
+  s->dcs = s->dest + m;
+  s->dsn = s->dcs + m;
+  s->dh1 = s->dsn + m;
+  s->dh2 = s->dh1 + 32;
+  s->dn = s->dh2 + 32;
   *out = s;
   return FR_OK;
 }
@@ -490,17 +675,23 @@ fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
 fr_status fr_solver_destroy(fr_solver* s) {
   if (!s) return FR_E_INVALID;
   (void)hipStreamSynchronize(s->ctx->stream);
+  if (s->cs) (void)hipStreamSynchronize(s->cs);
+  if (s->cycle) (void)hipGraphExecDestroy(s->cycle);
   (void)hipFree(s->mem);
+  (void)hipFree(s->dH);
   (void)hipHostFree(s->host);
+  (void)hipHostFree(s->hstate);
   (void)hipEventDestroy(s->e0);
   (void)hipEventDestroy(s->e1);
+  if (s->join0) (void)hipEventDestroy(s->join0);
+  if (s->join1) (void)hipEventDestroy(s->join1);
+  if (s->cs) (void)hipStreamDestroy(s->cs);
   delete s;
   return FR_OK;
 }
 
-fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_, const fr_newton_opts* o,
-                         fr_newton_stats* st) {
-  if (!s || !Un_ || !U_ || !o || !st) return FR_E_INVALID;
+static fr_status newton_body(fr_solver_s* s, fr_precond_s* pc, const void* Un_, void* U_, const fr_newton_opts* o,
+                             fr_newton_stats* st) {
   fr_ctx_s* c = s->ctx;
   if (pc && pc->ctx != c) return sfail(c, FR_E_INVALID, "preconditioner belongs to another context");
   const double* Un = (const double*)Un_;
@@ -541,7 +732,11 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
     if ((rs = axpby(s, -1.0, s->F, 0.0, nullptr, s->F))) return rs;
     int gi = 0;
     double rt = 0.0, r0 = 0.0;
-    if ((rs = gmres(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0))) return rs;
+    if (o->use_graph)
+      rs = gmres_graph(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0, &st->cycles);
+    else
+      rs = gmres(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0);
+    if (rs) return rs;
     st->gmres_iters += gi;
     if (it < 32) st->gmres_hist[it] = gi;
     st->last_linear_rel = r0 > 0 ? rt / r0 : 0.0;
@@ -567,6 +762,30 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
   (void)hipEventElapsedTime(&ms, e0, e1);
   st->ms = ms;
   return st->converged ? FR_OK : sfail(c, FR_E_NOT_CONVERGED, "Newton did not reach its tolerance");
+}
+
+// The step runs on the solver's own stream (capturable), joined to the
+// context stream by events at entry and exit.
+fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_, const fr_newton_opts* o,
+                         fr_newton_stats* st) {
+  if (!s || !Un_ || !U_ || !o || !st) return FR_E_INVALID;
+  fr_ctx_s* c = s->ctx;
+  if (pc && pc->ctx != c) return sfail(c, FR_E_INVALID, "preconditioner belongs to another context");
+  const hipStream_t orig = c->stream;
+  HIPCHK(c, hipEventRecord(s->join0, orig));
+  HIPCHK(c, hipStreamWaitEvent(s->cs, s->join0, 0));
+  c->stream = s->cs;
+  fr_status r = newton_body(s, pc, Un_, U_, o, st);
+  // the captured cycle refers to this call's buffers and preconditioner
+  if (s->cycle) {
+    (void)hipStreamSynchronize(s->cs);
+    (void)hipGraphExecDestroy(s->cycle);
+    s->cycle = nullptr;
+  }
+  c->stream = orig;
+  (void)hipEventRecord(s->join1, s->cs);
+  (void)hipStreamWaitEvent(orig, s->join1, 0);
+  return r;
 }
 
 }  // extern "C"

@@ -198,14 +198,15 @@ FR_PC_BLOCK_JACOBI, FR_PC_MLP = 0, 1
 
 class _NewtonOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("newton_rtol", C.c_double), ("newton_maxit", C.c_int32),
-                ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int32), ("pc_refresh", C.c_int32)]
+                ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int32), ("pc_refresh", C.c_int32),
+                ("use_graph", C.c_int32)]
 
 
 class _NewtonStats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("gmres_iters", C.c_int32), ("pc_setups", C.c_int32),
                 ("converged", C.c_int32), ("res0", C.c_double), ("res", C.c_double),
                 ("last_linear_rel", C.c_double), ("ms", C.c_double),
-                ("res_hist", C.c_double * 32), ("gmres_hist", C.c_int32 * 32)]
+                ("res_hist", C.c_double * 32), ("gmres_hist", C.c_int32 * 32), ("cycles", C.c_int32)]
 
 
 def _solver_symbols(L):
@@ -267,9 +268,9 @@ class Solver:
 
     def newton_step(self, Un, U=None, pc: Precond | None = None, dt: float = 1e-3, newton_rtol: float = 1e-8,
                     newton_maxit: int = 20, gmres_rtol: float = 1e-3, gmres_maxit: int = 300,
-                    check: bool = True, pc_refresh: bool = False) -> dict:
+                    check: bool = True, pc_refresh: bool = False, use_graph: bool = False) -> dict:
         U = self.ctx.empty_state() if U is None else self.ctx._vec(U)
-        o = _NewtonOpts(dt, newton_rtol, newton_maxit, gmres_rtol, gmres_maxit, int(pc_refresh))
+        o = _NewtonOpts(dt, newton_rtol, newton_maxit, gmres_rtol, gmres_maxit, int(pc_refresh), int(use_graph))
         st = _NewtonStats()
         rc = lib().fr_newton_step(self.h, None if pc is None else pc.h, _ptr(self.ctx._vec(Un)), _ptr(U),
                                   C.byref(o), C.byref(st))

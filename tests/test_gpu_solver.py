@@ -89,3 +89,46 @@ def test_preconditioner_reduces_gmres_iterations():
     assert 2 * a["gmres_iters"] < b["gmres_iters"]
     assert a["res"] <= 1e-8 * a["res0"]
     assert a["res_hist"][-1] == a["res"]
+
+
+@pytest.mark.parametrize("use_pc", [True, False])
+def test_graph_newton_matches_dense_newton(use_pc):
+    """The GMRES restart cycle captured as a hipGraph and replayed: same root
+    as the oracle's dense Newton."""
+    fr, m, ph, U, ctx, Ud = _setup(N=4, p=1)
+    dt = _dt(m, U, 20.0)
+    sol = fr.Solver(ctx, restart=30)
+    pc = fr.Precond(ctx) if use_pc else None
+    res = sol.newton_step(Ud, pc=pc, dt=dt, newton_rtol=1e-10, gmres_rtol=1e-4, gmres_maxit=400, use_graph=True)
+    assert res["converged"] == 1 and res["cycles"] >= res["newton_iters"]
+    Ug = res["U"].cpu().numpy().reshape(-1)
+    o = O.Oracle(m, ph, 1)
+    Ud_np = U.reshape(-1)
+    Uref, hist = ON.backward_euler_dense(o, Ud_np, dt, rtol=1e-12)
+    F = Ug - Ud_np - dt * o.rhs(Ug)
+    assert np.linalg.norm(F) <= 1e-9 * hist[0]
+    assert np.max(np.abs(Ug - Uref)) <= 1e-8 * np.max(np.abs(Uref - Ud_np))
+
+
+def test_graph_replays_match_host_driven_gmres():
+    """Several Newton steps in a row, eager residual evaluations and
+    synchronisations in between; every graph-driven step agrees with the
+    host-driven one from the same state."""
+    fr, m, ph, U, ctx, Ud = _setup(N=8, p=3, Re=1000.0)
+    dt = _dt(m, U, 1.0)
+    sol = fr.Solver(ctx, restart=30)
+    pc = fr.Precond(ctx)
+    cur = Ud.clone()
+    for step in range(3):
+        ctx.rhs(cur)
+        torch.cuda.synchronize()
+        a = sol.newton_step(cur, pc=pc, dt=dt, gmres_maxit=500, use_graph=True)
+        ctx.rhs(cur)
+        b = sol.newton_step(cur, pc=pc, dt=dt, gmres_maxit=500, use_graph=False)
+        torch.cuda.synchronize()
+        assert a["converged"] == 1 and b["converged"] == 1, (step, a, b)
+        assert a["newton_iters"] == b["newton_iters"]
+        assert abs(a["gmres_iters"] - b["gmres_iters"]) <= max(2, 0.1 * b["gmres_iters"])
+        du = (b["U"] - cur).abs().max().item()
+        assert (a["U"] - b["U"]).abs().max().item() <= 1e-7 * du, step
+        cur = b["U"].clone()
