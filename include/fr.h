@@ -228,6 +228,31 @@ fr_status fr_solver_destroy(fr_solver* s);
 fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un, void* U, const fr_newton_opts* opts,
                          fr_newton_stats* stats);
 
+/* ---- Batches of meshes ---------------------------------------------------
+ * Many independent meshes (FP32 contexts, one system: 2-D Euler or
+ * Navier-Stokes; triangles and quadrilaterals of degree 1..4 mixed freely,
+ * at most 64 meshes) evaluated together: each phase of fr_rhs /
+ * fr_jacobian_blocks is one persistent launch over a work list of (mesh,
+ * tile) items, longest first.  Every mesh's result is bitwise identical to
+ * the same mesh evaluated alone.  Runs on the first context's stream; the
+ * contexts' workspaces are used, so their own calls must not overlap with
+ * the batch's. */
+typedef struct fr_batch_s fr_batch;
+fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out);
+fr_status fr_batch_destroy(fr_batch* b);
+const char* fr_batch_last_error(const fr_batch* b);
+/* U[i] / R[i]: device state and residual of mesh i (layouts as fr_rhs). */
+fr_status fr_batch_rhs(fr_batch* b, const void* const* U, void* const* R);
+/* blocks[i]: mesh i's FP32 blocks (layout as fr_jacobian_blocks). */
+fr_status fr_batch_jacobian_blocks(fr_batch* b, const void* const* U, void* const* blocks);
+/* Autotuner: times candidate persistent-grid sizes and, per (type, degree),
+ * the tiles (residual) or elements (assembly) per work item on these
+ * arrays (reps timed repetitions each) and keeps the fastest. */
+fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void* const* blocks, int reps);
+/* The current table: workgroups per launch and units per work item, indexed
+ * by 8 * type + degree (32 entries each). */
+fr_status fr_batch_tuning(const fr_batch* b, int* grid_res, int* grid_jac, int* k_res, int* k_jac);
+
 /* Profiling.  When enabled, the dominant kernel of fr_jacobian_blocks
  * (which = 0: block assembly) and of fr_rhs / fr_jvp (which = 1: the flux /
  * divergence pass) is bracketed by HIP events on the context stream.

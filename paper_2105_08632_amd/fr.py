@@ -417,3 +417,87 @@ def _precond_n_fallback(self) -> int:
 Precond.set_mlp = _precond_set_mlp
 Precond.mlp_inputs = _precond_mlp_inputs
 Precond.n_fallback = property(_precond_n_fallback)
+
+
+# ---------------------------------------------------------------- batches of meshes
+def _batch_symbols(L):
+    P = C.c_void_p
+    PP = C.POINTER(C.c_void_p)
+    L.fr_batch_create.argtypes = [PP, C.c_int, C.POINTER(P)]
+    L.fr_batch_destroy.argtypes = [P]
+    L.fr_batch_last_error.argtypes = [P]
+    L.fr_batch_last_error.restype = C.c_char_p
+    L.fr_batch_rhs.argtypes = [P, PP, PP]
+    L.fr_batch_jacobian_blocks.argtypes = [P, PP, PP]
+    L.fr_batch_tune.argtypes = [P, PP, PP, PP, C.c_int]
+    L.fr_batch_tuning.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    for n in ("fr_batch_create", "fr_batch_destroy", "fr_batch_rhs", "fr_batch_jacobian_blocks", "fr_batch_tune",
+              "fr_batch_tuning"):
+        getattr(L, n).restype = C.c_int
+
+
+_extensions.append(_batch_symbols)
+EXPORTED += ["fr_batch_create", "fr_batch_destroy", "fr_batch_last_error", "fr_batch_rhs",
+             "fr_batch_jacobian_blocks", "fr_batch_tune", "fr_batch_tuning"]
+
+
+def _ptrs(ts):
+    return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+class Batch:
+    """Many FP32 meshes evaluated together: one persistent launch per phase."""
+
+    def __init__(self, ctxs):
+        self.ctxs = list(ctxs)
+        hs = (C.c_void_p * len(self.ctxs))(*[c.h.value for c in self.ctxs])
+        h = C.c_void_p()
+        rc = lib().fr_batch_create(hs, len(self.ctxs), C.byref(h))
+        if rc != 0:
+            msgs = [lib().fr_last_error(c.h).decode() for c in self.ctxs]
+            raise FrError(rc, next((m for m in msgs if m), "fr_batch_create"))
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise FrError(rc, lib().fr_batch_last_error(self.h).decode())
+
+    def rhs(self, Us, Rs=None):
+        Us = [c._vec(u) for c, u in zip(self.ctxs, Us)]
+        Rs = [c.empty_state() for c in self.ctxs] if Rs is None else Rs
+        self._check(lib().fr_batch_rhs(self.h, _ptrs(Us), _ptrs(Rs)))
+        return Rs
+
+    def jacobian_blocks(self, Us, Bs=None):
+        Us = [c._vec(u) for c, u in zip(self.ctxs, Us)]
+        Bs = [c.block_tensor("f32") for c in self.ctxs] if Bs is None else Bs
+        self._check(lib().fr_batch_jacobian_blocks(self.h, _ptrs(Us), _ptrs(Bs)))
+        return Bs
+
+    def tune(self, Us, reps: int = 3) -> dict:
+        Us = [c._vec(u) for c, u in zip(self.ctxs, Us)]
+        Rs = [c.empty_state() for c in self.ctxs]
+        Bs = [c.block_tensor("f32") for c in self.ctxs]
+        self._check(lib().fr_batch_tune(self.h, _ptrs(Us), _ptrs(Rs), _ptrs(Bs), reps))
+        return self.tuning()
+
+    def tuning(self) -> dict:
+        gr, gj = C.c_int(), C.c_int()
+        kr, kj = (C.c_int * 32)(), (C.c_int * 32)()
+        self._check(lib().fr_batch_tuning(self.h, C.byref(gr), C.byref(gj), kr, kj))
+        codes = sorted({8 * int(c.mesh.elem_type[0]) + int(c.mesh.degree[0]) for c in self.ctxs})
+        name = {0: "quad", 1: "tri"}
+        return {"grid_res": gr.value, "grid_jac": gj.value,
+                "tiles_per_item": {f"{name[k // 8]}p{k % 8}": kr[k] for k in codes},
+                "elems_per_item": {f"{name[k // 8]}p{k % 8}": kj[k] for k in codes}}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -376,3 +376,30 @@ def ns_physics(ndim: int, reynolds: float, prandtl: float, gamma: float = 1.4,
     """Dynamic viscosity mu = rho V L / Re."""
     return Physics(NAVIER_STOKES, ndim + 2, gamma=gamma,
                    mu=rho_ref * v_ref * L_ref / reynolds, prandtl=prandtl)
+
+
+def mixed_batch(seed: int = 7, count: int = 64, n_min: int = 500, n_max: int = 5000, gamma: float = 1.4):
+    """A batch of independent periodic 2-D Euler meshes shaped like the mixed
+    workload: element-count targets ~ U{n_min..n_max}, degree ~ U{1..4}, a
+    split fraction s ~ U(0.3, 0.7).  Each mesh is one element type: with
+    probability s its n x n cells are split into triangles, else they stay
+    quadrilaterals (n = round(sqrt(target / (1 + s)))); vertices jittered by
+    5%; state = the isentropic vortex of the paper's Euler test.  Returns
+    [(mesh, p, tri_pts or None, U)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        target = int(rng.integers(n_min, n_max + 1))
+        p = int(rng.integers(1, 5))
+        s = float(rng.uniform(0.3, 0.7))
+        tri = bool(rng.uniform() < s)
+        n = max(3, int(round(np.sqrt(target / (1.0 + s)))))
+        msd = int(rng.integers(0, 2**31 - 1))
+        if tri:
+            m = tri_mesh(n, degree=p, jitter=0.05, seed=msd)
+            tp = tri_points(p)
+        else:
+            m = quad_mesh(n, degree=p, jitter=0.05)
+            tp = None
+        out.append((m, p, tp, isentropic_vortex_state(m, p, gamma=gamma, tri_pts=tp)))
+    return out

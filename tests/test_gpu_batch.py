@@ -1,0 +1,83 @@
+"""Batches of meshes (mixed triangles / quadrilaterals and degrees) in one
+persistent launch per phase: every mesh's residual and Jacobian blocks are
+bitwise equal to the same mesh evaluated alone, before and after the
+autotuner changes the work decomposition; one small mesh is also checked
+against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_08632_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _meshes(system):
+    spec = [("tri", 1, 4), ("quad", 2, 5), ("tri", 3, 3), ("quad", 4, 4), ("tri", 4, 3), ("quad", 1, 6),
+            ("quad", 3, 4), ("tri", 2, 5)]
+    out = []
+    for i, (kind, p, n) in enumerate(spec):
+        if kind == "tri":
+            m, tp = I.tri_mesh(n, degree=p, jitter=0.05, K=1, seed=10 + i), I.tri_points(p)
+        else:
+            m, tp = I.quad_mesh(n, degree=p, jitter=0.05, K=1), None
+        ph = I.euler_physics(2) if system == "euler" else I.ns_physics(2, 200.0, 0.72)
+        # smooth random state (the isentropic vortex core is narrower than one element of these small meshes)
+        U = I.ns2d_state(m, p, seeds=(20 + i, 30 + i, 40 + i), tri_pts=tp)
+        out.append((m, p, tp, ph, U))
+    return out
+
+
+@pytest.mark.parametrize("system", ["euler", "ns"])
+def test_batch_matches_meshes_alone(system):
+    from paper_2105_08632_amd import fr
+    cases = _meshes(system)
+    ctxs = [fr.Context(m, ph, "f32", tri_pts=tp) for (m, p, tp, ph, U) in cases]
+    Us = [torch.from_numpy(U).float().cuda().contiguous() for (m, p, tp, ph, U) in cases]
+    alone_R = [c.rhs(u).clone() for c, u in zip(ctxs, Us)]
+    alone_B = [c.jacobian_blocks(u, out_prec="f32").clone() for c, u in zip(ctxs, Us)]
+    torch.cuda.synchronize()
+    b = fr.Batch(ctxs)
+    for rnd in range(2):
+        Rs = b.rhs(Us)
+        Bs = b.jacobian_blocks(Us)
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert torch.equal(Rs[i], alone_R[i]), (rnd, i)
+            assert torch.equal(Bs[i], alone_B[i]), (rnd, i)
+        if rnd == 0:
+            info = b.tune(Us, reps=1)
+            assert info["grid_res"] > 0 and info["grid_jac"] > 0
+
+
+def test_batch_mesh_against_oracle():
+    """A quadrilateral and a triangle mesh inside a batch against the FP64
+    oracle (FP32 bar 1e-5)."""
+    from paper_2105_08632_amd import fr
+    cases = _meshes("euler")[:2]
+    ctxs = [fr.Context(m, ph, "f32", tri_pts=tp) for (m, p, tp, ph, U) in cases]
+    Us = [torch.from_numpy(U).float().cuda().contiguous() for (m, p, tp, ph, U) in cases]
+    b = fr.Batch(ctxs)
+    Rs = b.rhs(Us)
+    Bs = b.jacobian_blocks(Us)
+    torch.cuda.synchronize()
+    for i, (m, p, tp, ph, U) in enumerate(cases):
+        Uq = Us[i].double().cpu().numpy()
+        o = O.Oracle(m, ph, p, tp)
+        Rr = o.rhs(Uq)
+        R = Rs[i].double().cpu().numpy().reshape(-1)
+        assert np.max(np.abs(R - Rr)) <= 1e-5 * np.max(np.abs(Rr))
+        el = [0, m.n_elem - 1]
+        Bo = o.jac_blocks(Uq, el, ctxs[i].b, ctxs[i].nface)
+        Bn = Bs[i].double().cpu().numpy().transpose(0, 1, 3, 2)
+        for j, e in enumerate(el):
+            assert np.max(np.abs(Bn[e] - Bo[j])) <= 1e-5 * np.max(np.abs(Bo[j]))
+
+
+def test_batch_rejects_mixed_systems():
+    from paper_2105_08632_amd import fr
+    (m1, p1, tp1, ph1, U1), = _meshes("euler")[:1]
+    (m2, p2, tp2, ph2, U2), = _meshes("ns")[1:2]
+    with pytest.raises(fr.FrError):
+        fr.Batch([fr.Context(m1, ph1, "f32", tri_pts=tp1), fr.Context(m2, ph2, "f32", tri_pts=tp2)])
