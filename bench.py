@@ -122,7 +122,8 @@ def newton_bench(torch, fr, I, train_steps, log):
     ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
     m = I.quad_mesh(256, degree=3, jitter=0.05)
     out = {"workload": "2D NS p=3, 256x256 jittered periodic quads (4.19 M DOF), backward Euler, Newton to "
-                       "1e-8 relative, GMRES(30) forcing 1e-3, preconditioner set up at U^n",
+                       "1e-8 relative, GMRES(30) forcing 1e-3, preconditioner set up at U^n; restart cycles "
+                       "replayed from a captured hipGraph (lu_host_arnoldi: host-driven Arnoldi for comparison)",
            "mlp_training": info}
     runs = {"lu": [], "mlp": []}
     held = []
@@ -139,15 +140,17 @@ def newton_bench(torch, fr, I, train_steps, log):
         held.append(float(torch.cat([net.loss_grad(Xh[i:i + 4096].contiguous())[2]
                                      for i in range(0, Xh.shape[0], 4096)]).mean().item()))
         del Xh
-        for name, pc in (("lu", fr.Precond(ctx)), ("mlp", pcm)):
-            r = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False)
-            runs[name].append(r)
+        pcl = fr.Precond(ctx)
+        for name, pc, graph in (("lu", pcl, True), ("lu_host_arnoldi", pcl, False), ("mlp", pcm, True)):
+            r = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False, use_graph=graph)
+            runs.setdefault(name, []).append(r)
             log(f"newton cfl {cfl} seed {s} {name}: conv {r['converged']} newton {r['newton_iters']} "
                 f"gmres {r['gmres_iters']} s {r['ms'] / 1e3:.3f}")
         if s == 8:
             hard = {}
             for name, pc in (("lu", fr.Precond(ctx)), ("mlp", pcm)):
-                r = sol.newton_step(Ud, pc=pc, dt=_dt(m, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False)
+                r = sol.newton_step(Ud, pc=pc, dt=_dt(m, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False,
+                                    use_graph=True)
                 hard[name] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
                               "gmres_iters": r["gmres_iters"], "final_rel_residual": r["res"] / r["res0"],
                               "s": round(r["ms"] / 1e3, 3)}
@@ -162,6 +165,63 @@ def newton_bench(torch, fr, I, train_steps, log):
     out["mlp_heldout_resid_mean"] = round(float(np.mean(held)), 3)
     out["learned_over_lu_time"] = round(out["mlp"]["s_per_step_median"] / out["lu"]["s_per_step_median"], 3)
     return out
+
+
+def batch_bench(torch, fr, I, reps, log):
+    """64 independent periodic 2-D Euler meshes (FP32; triangles and quads,
+    degrees 1-4, 500-5000 elements each): residual + all Jacobian blocks,
+    per-mesh calls vs one persistent launch per phase, before and after the
+    autotuner."""
+    meshes = I.mixed_batch()
+    ph = I.euler_physics(2)
+    ctxs = [fr.Context(m, ph, "f32", tri_pts=tp) for (m, p, tp, U) in meshes]
+    Us = [torch.from_numpy(U).float().cuda().contiguous() for (m, p, tp, U) in meshes]
+    Rs = [c.empty_state() for c in ctxs]
+    Bs = [c.block_tensor("f32") for c in ctxs]
+    dof = sum(c.ndof for c in ctxs)
+    alg = 0
+    for c in ctxs:
+        alg += c.ne * ((1 + c.nface) * c.b * c.b * 4 + c.ns * c.nv * 4 * 2 +
+                       (2 * c.ns * 4 + c.ns + c.nf * 2 + c.nf + c.nf) * 4 + c.nface * 4)
+    batch = fr.Batch(ctxs)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def alone():
+        for c, u, r, bb in zip(ctxs, Us, Rs, Bs):
+            c.rhs(u, r)
+            c.jacobian_blocks(u, bb, "f32")
+
+    def batched():
+        batch.rhs(Us, Rs)
+        batch.jacobian_blocks(Us, Bs)
+
+    t_alone = timed(alone)
+    t_batch = timed(batched)
+    t0 = time.perf_counter()
+    table = batch.tune(Us, reps=2)
+    t_tune = time.perf_counter() - t0
+    t_tuned = timed(batched)
+    finite = all(bool(torch.isfinite(bb).all()) and bool(torch.isfinite(r).all()) for r, bb in zip(Rs, Bs))
+    log(f"batch: alone {t_alone:.2f} ms, batched {t_batch:.2f} ms, tuned {t_tuned:.2f} ms")
+    floor_ms = alg / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"workload": "64 periodic 2-D Euler meshes (isentropic vortex), FP32, triangles and quadrilaterals, "
+                        "p 1-4, 500-5000 elements each: R(U) + all Jacobian blocks",
+            "meshes": len(ctxs), "elements": int(sum(c.ne for c in ctxs)), "dof": int(dof),
+            "alg_bytes": int(alg), "hbm_floor_ms": round(floor_ms, 3),
+            "ms_per_mesh_calls": round(t_alone, 3), "ms_batched_default": round(t_batch, 3),
+            "ms_batched_tuned": round(t_tuned, 3), "tune_s": round(t_tune, 2),
+            "dof_per_s_tuned": dof / (t_tuned * 1e-3), "frac_of_hbm_floor": round(floor_ms / t_tuned, 4),
+            "tuning": table, "outputs_finite": finite}
 
 
 def cpu_baseline(m, ph, p, U, budget_s):
@@ -198,6 +258,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-GMRES part of the metric")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed-mesh batch measurement")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
@@ -265,9 +326,14 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-    if not args.no_newton:
+    if not args.no_batch or not args.no_newton:
         del B, R
         torch.cuda.empty_cache()
+    if not args.no_batch:
+        from paper_2105_08632_amd import inputs as I
+        out["batch"] = batch_bench(torch, fr, I, 5, lambda s: print(s, file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
+    if not args.no_newton:
         from paper_2105_08632_amd import inputs as I
         out["newton"] = newton_bench(torch, fr, I, args.mlp_steps, lambda s: print(s, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:

@@ -245,13 +245,22 @@ const char* fr_batch_last_error(const fr_batch* b);
 fr_status fr_batch_rhs(fr_batch* b, const void* const* U, void* const* R);
 /* blocks[i]: mesh i's FP32 blocks (layout as fr_jacobian_blocks). */
 fr_status fr_batch_jacobian_blocks(fr_batch* b, const void* const* U, void* const* blocks);
-/* Autotuner: times candidate persistent-grid sizes and, per (type, degree),
- * the tiles (residual) or elements (assembly) per work item on these
- * arrays (reps timed repetitions each) and keeps the fastest. */
+/* Autotuner: times, per phase, the launch strategy (one mixed launch, or
+ * one launch per (type, degree) group with that group's own register and
+ * LDS budget), the persistent-grid size and, per (type, degree), the tiles
+ * (residual) or elements (assembly) per work item, on these arrays (reps
+ * timed repetitions each), and keeps the fastest. */
 fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void* const* blocks, int reps);
-/* The current table: workgroups per launch and units per work item, indexed
- * by 8 * type + degree (32 entries each). */
-fr_status fr_batch_tuning(const fr_batch* b, int* grid_res, int* grid_jac, int* k_res, int* k_jac);
+/* The current table: modes[0] / modes[1] = residual / Jacobian launch
+ * strategy (0: one mixed launch per phase, 1: one launch per (type, degree)
+ * group), workgroups per launch (0: one per work item, scheduled by the
+ * hardware), and units per work item indexed by 8 * type + degree (32
+ * entries each). */
+fr_status fr_batch_tuning(const fr_batch* b, int* modes, int* grid_res, int* grid_jac, int* k_res, int* k_jac);
+/* Load a table (e.g. one saved from fr_batch_tuning); modes / k_* may be NULL
+ * to keep the current entries; units per work item below 1 read as 1. */
+fr_status fr_batch_set_tuning(fr_batch* b, const int* modes, int grid_res, int grid_jac, const int* k_res,
+                              const int* k_jac);
 
 /* Profiling.  When enabled, the dominant kernel of fr_jacobian_blocks
  * (which = 0: block assembly) and of fr_rhs / fr_jvp (which = 1: the flux /

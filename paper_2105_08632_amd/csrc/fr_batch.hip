@@ -75,7 +75,73 @@ template <int SYS> constexpr int jac_lds_all() {
   return m;
 }
 
-// PH: 0 traces, 1 gradients, 2 divergence (FP64 residual of FP32 states)
+// One work item of a residual phase (PH: 0 traces, 1 gradients, 2
+// divergence; FP64 residual of FP32 states) for one (type, degree).
+// The descriptor is copied into locals first: the bodies store through float
+// pointers, and operands read through a pointer into global memory would
+// have to be reloaded after every such store.
+template <int ET, int DEG, int SYS, int PH>
+__device__ __forceinline__ void res_item(char* lds, const BDesc* D, const BPtrs& P, const BItem& w) {
+  typedef Elem<ET, DEG> E;
+  const OpsD<double> op = D[w.desc].opd;
+  const GeoD<double> geo = D[w.desc].geod;
+  const PhysP ph = D[w.desc].ph;
+  const int ne = D[w.desc].ne;
+  double* UF = D[w.desc].UF64;
+  double* Q = D[w.desc].Q64;
+  double* QF = D[w.desc].QF64;
+  const float* U = P.U[w.desc];
+  float* Rout = P.R[w.desc];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int t = w.first; t < w.first + w.count; ++t) {
+    if constexpr (PH == 0)
+      trace_body<E, kNV, double, double, float>(t, tid, nth, lds, op, ne, U, (const float*)nullptr, UF, DevSync());
+    else if constexpr (PH == 1)
+      grad_body<E, kNV, double, double, float>(t, tid, nth, lds, op, geo, ph.beta, U, (const float*)nullptr,
+                                               (const double*)UF, Q, QF, DevSync());
+    else
+      div_body<E, kNV, SYS, double, double, float>(t, tid, nth, lds, op, geo, ph, U, (const float*)nullptr,
+                                                   (const double*)UF, (const double*)Q, (const double*)QF, Rout,
+                                                   (float*)nullptr, DevSync());
+    __syncthreads();
+  }
+}
+
+template <int ET, int DEG, int SYS, int PH>
+__device__ __forceinline__ void jac_item(char* lds, const BDesc* D, const BPtrs& P, const BItem& w) {
+  typedef Elem<ET, DEG> E;
+  const OpsD<float> op = D[w.desc].opr;
+  const GeoD<float> geo = D[w.desc].geor;
+  const PhysP ph = D[w.desc].ph;
+  const int ne = D[w.desc].ne, nblk = D[w.desc].nblk;
+  float* UF = D[w.desc].UFr;
+  float* Q = D[w.desc].Qr;
+  float* QF = D[w.desc].QFr;
+  const float* U = P.U[w.desc];
+  float* B = P.B[w.desc];
+  const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (PH == 2 && ET != ET_TRI) {
+    const Ops1D<float> o1 = D[w.desc].o1;
+    for (int t = w.first; t < w.first + w.count; ++t) {
+      jac_tp_body<E, kNV, SYS, float, float>(t, tid, nth, lds, op, o1, geo, ph, U, Q, UF, QF, B, nblk, DevSync());
+      __syncthreads();
+    }
+  } else {
+    for (int t = w.first; t < w.first + w.count; ++t) {
+      if constexpr (PH == 0)
+        trace_body<E, kNV, float, float, float>(t, tid, nth, lds, op, ne, U, (const float*)nullptr, UF, DevSync());
+      else if constexpr (PH == 1)
+        grad_body<E, kNV, float, float, float>(t, tid, nth, lds, op, geo, ph.beta, U, (const float*)nullptr,
+                                               (const float*)UF, Q, QF, DevSync());
+      else
+        jac_body<E, kNV, SYS, float, float>(t, tid, nth, lds, op, geo, ph, U, Q, UF, QF, B, nblk, DevSync());
+      __syncthreads();
+    }
+  }
+}
+
+// The mixed launch: one persistent grid over the whole work list, switching
+// on each item's (type, degree).
 template <int SYS, int PH>
 __global__ void __launch_bounds__(kBT) k_batch_res(const BDesc* D, BPtrs P, const BItem* items, int nitems) {
   __shared__ __align__(16) char lds[res_lds<SYS>()];
@@ -83,34 +149,13 @@ __global__ void __launch_bounds__(kBT) k_batch_res(const BDesc* D, BPtrs P, cons
     const BItem w = items[it];
     const BDesc& d = D[w.desc];
     switch (d.code) {
-#define RCASE(ET, DEG)                                                                                            \
-  case bcode(ET, DEG): {                                                                                          \
-    typedef Elem<ET, DEG> E;                                                                                      \
-    const float* U = P.U[w.desc];                                                                                 \
-    for (int t = w.first; t < w.first + w.count; ++t) {                                                           \
-      if constexpr (PH == 0)                                                                                      \
-        trace_body<E, kNV, double, double, float>(t, threadIdx.x, kBT, lds, d.opd, d.ne, U, (const float*)nullptr, \
-                                                  d.UF64, DevSync());                                             \
-      else if constexpr (PH == 1)                                                                                 \
-        grad_body<E, kNV, double, double, float>(t, threadIdx.x, kBT, lds, d.opd, d.geod, d.ph.beta, U,           \
-                                                 (const float*)nullptr, (const double*)d.UF64, d.Q64, d.QF64,     \
-                                                 DevSync());                                                      \
-      else                                                                                                        \
-        div_body<E, kNV, SYS, double, double, float>(t, threadIdx.x, kBT, lds, d.opd, d.geod, d.ph, U,            \
-                                                     (const float*)nullptr, (const double*)d.UF64,                \
-                                                     (const double*)d.Q64, (const double*)d.QF64, P.R[w.desc],    \
-                                                     (float*)nullptr, DevSync());                                 \
-      __syncthreads();                                                                                            \
-    }                                                                                                             \
-  } break;
+#define RCASE(ET, DEG) case bcode(ET, DEG): res_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
       FR_BATCH_CASES(RCASE)
 #undef RCASE
       default: break;
     }
   }
 }
-
-// PH: 0 traces, 1 gradients (FP32, the assembly's inputs), 2 block assembly
 template <int SYS, int PH>
 __global__ void __launch_bounds__(kBT) k_batch_jac(const BDesc* D, BPtrs P, const BItem* items, int nitems) {
   __shared__ __align__(16) char lds[jac_lds_all<SYS>()];
@@ -118,31 +163,44 @@ __global__ void __launch_bounds__(kBT) k_batch_jac(const BDesc* D, BPtrs P, cons
     const BItem w = items[it];
     const BDesc& d = D[w.desc];
     switch (d.code) {
-#define JKCASE(ET, DEG)                                                                                           \
-  case bcode(ET, DEG): {                                                                                          \
-    typedef Elem<ET, DEG> E;                                                                                      \
-    const float* U = P.U[w.desc];                                                                                 \
-    for (int t = w.first; t < w.first + w.count; ++t) {                                                           \
-      if constexpr (PH == 0)                                                                                      \
-        trace_body<E, kNV, float, float, float>(t, threadIdx.x, kBT, lds, d.opr, d.ne, U, (const float*)nullptr,  \
-                                                d.UFr, DevSync());                                                \
-      else if constexpr (PH == 1)                                                                                 \
-        grad_body<E, kNV, float, float, float>(t, threadIdx.x, kBT, lds, d.opr, d.geor, d.ph.beta, U,             \
-                                               (const float*)nullptr, (const float*)d.UFr, d.Qr, d.QFr,           \
-                                               DevSync());                                                        \
-      else if constexpr (ET == ET_TRI)                                                                            \
-        jac_body<E, kNV, SYS, float, float>(t, threadIdx.x, kBT, lds, d.opr, d.geor, d.ph, U, d.Qr, d.UFr,       \
-                                            d.QFr, P.B[w.desc], d.nblk, DevSync());                               \
-      else                                                                                                        \
-        jac_tp_body<E, kNV, SYS, float, float>(t, threadIdx.x, kBT, lds, d.opr, d.o1, d.geor, d.ph, U, d.Qr,     \
-                                               d.UFr, d.QFr, P.B[w.desc], d.nblk, DevSync());                     \
-      __syncthreads();                                                                                            \
-    }                                                                                                             \
-  } break;
-      FR_BATCH_CASES(JKCASE)
-#undef JKCASE
+#define JCASE2(ET, DEG) case bcode(ET, DEG): jac_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
+      FR_BATCH_CASES(JCASE2)
+#undef JCASE2
       default: break;
     }
+  }
+}
+
+// Grouped launches: one persistent grid per (type, degree) with that
+// group's own LDS and thread count.
+template <int ET, int DEG, int SYS, int PH> constexpr int gres_lds() {
+  typedef Elem<ET, DEG> E;
+  return PH == 0 ? trace_lds<E, kNV, double, double>()
+                 : (PH == 1 ? grad_lds<E, kNV, double, double>() : div_lds<E, kNV, SYS, double, double>());
+}
+template <int ET, int DEG, int SYS, int PH> constexpr int gjac_lds() {
+  typedef Elem<ET, DEG> E;
+  return PH == 0 ? trace_lds<E, kNV, float, float>()
+                 : (PH == 1 ? grad_lds<E, kNV, float, float>() : asm_lds_one<ET, DEG, SYS>());
+}
+template <int ET, int DEG, int SYS, int PH> constexpr int gjac_threads() {
+  return (PH == 2 && ET != ET_TRI) ? jac_tp_threads<Elem<ET, DEG>, kNV, SYS, float>() : kThreads;
+}
+template <int ET, int DEG, int SYS, int PH>
+__global__ void __launch_bounds__(kThreads) k_group_res(const BDesc* D, BPtrs P, const BItem* items, int nitems) {
+  __shared__ __align__(16) char lds[gres_lds<ET, DEG, SYS, PH>()];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    res_item<ET, DEG, SYS, PH>(lds, D, P, w);
+  }
+}
+template <int ET, int DEG, int SYS, int PH>
+__global__ void __launch_bounds__((gjac_threads<ET, DEG, SYS, PH>())) k_group_jac(const BDesc* D, BPtrs P,
+                                                                                 const BItem* items, int nitems) {
+  __shared__ __align__(16) char lds[gjac_lds<ET, DEG, SYS, PH>()];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BItem w = items[it];
+    jac_item<ET, DEG, SYS, PH>(lds, D, P, w);
   }
 }
 
@@ -154,11 +212,16 @@ struct fr_batch_s {
   hipStream_t stream = nullptr;
   BDesc* ddesc = nullptr;          // device
   BDesc* hdesc = nullptr;          // pinned
-  BItem* dres = nullptr;           // device work lists
-  BItem* djac = nullptr;
+  // device work lists (all items longest first, then the same items grouped
+  // by (type, degree)); seg_* give each group's range in the grouped half
+  BItem* dres = nullptr;           // residual tiles
+  BItem* djac = nullptr;           // assembly elements
   BItem* dtil = nullptr;           // tiles of the Jacobian prelude
   int nres = 0, njac = 0, ntil = 0;
   size_t cap_res = 0, cap_jac = 0, cap_til = 0;
+  int seg_off[3][32], seg_cnt[3][32];
+  std::vector<int> codes;          // (type, degree) codes present
+  int res_mode = 0, jac_mode = 0;  // 0: one mixed launch per phase, 1: one launch per group
   int k_res[32], k_jac[32];        // work-item granularity per (type, degree)
   int grid_res = 0, grid_jac = 0;  // persistent workgroups per launch
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -173,8 +236,10 @@ static fr_status bfail(fr_batch_s* b, fr_status s, const std::string& m) {
 
 static int sec_cost(const fr_ctx_s* c) { return c->ns * (c->ns + c->nf); }
 
-// work list: `count` units (tiles or elements) of `per` each, longest first
-static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BItem>& out) {
+// work list: units (tiles or elements) in items of k[code] units, longest
+// first; `seg` receives each group's range in the grouped copy (appended)
+static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BItem>& out, int* seg_off,
+                       int* seg_cnt) {
   out.clear();
   std::vector<std::pair<long, BItem>> v;
   for (size_t i = 0; i < b->ctx.size(); ++i) {
@@ -190,6 +255,14 @@ static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BIte
   }
   std::stable_sort(v.begin(), v.end(), [](const auto& a, const auto& c) { return a.first > c.first; });
   for (auto& x : v) out.push_back(x.second);
+  const size_t nall = out.size();
+  for (int code = 0; code < 32; ++code) { seg_off[code] = 0; seg_cnt[code] = 0; }
+  for (int code : b->codes) {
+    seg_off[code] = (int)out.size();
+    for (size_t j = 0; j < nall; ++j)
+      if (bcode(b->ctx[out[j].desc]->type, b->ctx[out[j].desc]->p) == code) out.push_back(out[j]);
+    seg_cnt[code] = (int)out.size() - seg_off[code];
+  }
 }
 
 static fr_status upload_items(fr_batch_s* b, const std::vector<BItem>& v, BItem** dst, size_t* cap, int* n) {
@@ -202,7 +275,7 @@ static fr_status upload_items(fr_batch_s* b, const std::vector<BItem>& v, BItem*
   }
   if (hipMemcpy(*dst, v.data(), v.size() * sizeof(BItem), hipMemcpyHostToDevice) != hipSuccess)
     return bfail(b, FR_E_DEVICE, "batch work list upload");
-  *n = (int)v.size();
+  *n = (int)v.size() / 2;          // the mixed half
   return FR_OK;
 }
 
@@ -211,31 +284,81 @@ static fr_status rebuild(fr_batch_s* b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, FR_E_DEVICE, "batch stream");
   std::vector<BItem> v;
   fr_status st;
-  make_items(b, true, b->k_res, v);
+  make_items(b, true, b->k_res, v, b->seg_off[0], b->seg_cnt[0]);
   if ((st = upload_items(b, v, &b->dres, &b->cap_res, &b->nres))) return st;
   int one[32];
   std::fill(one, one + 32, 1);
-  make_items(b, true, one, v);
+  make_items(b, true, one, v, b->seg_off[1], b->seg_cnt[1]);
   if ((st = upload_items(b, v, &b->dtil, &b->cap_til, &b->ntil))) return st;
-  make_items(b, false, b->k_jac, v);
+  make_items(b, false, b->k_jac, v, b->seg_off[2], b->seg_cnt[2]);
   return upload_items(b, v, &b->djac, &b->cap_jac, &b->njac);
 }
 
+template <int SYS, int PH>
+static void group_res(fr_batch_s* b, int code, const BItem* items, int n, int grid) {
+  switch (code) {
+#define GR(ET, DEG)                                                                                             \
+  case bcode(ET, DEG):                                                                                          \
+    hipLaunchKernelGGL((k_group_res<ET, DEG, SYS, PH>), dim3(grid), dim3(kThreads), 0, b->stream, b->ddesc,      \
+                       b->ptrs, items, n);                                                                      \
+    break;
+    FR_BATCH_CASES(GR)
+#undef GR
+    default: break;
+  }
+}
+template <int SYS, int PH>
+static void group_jac(fr_batch_s* b, int code, const BItem* items, int n, int grid) {
+  switch (code) {
+#define GJ(ET, DEG)                                                                                             \
+  case bcode(ET, DEG):                                                                                          \
+    hipLaunchKernelGGL((k_group_jac<ET, DEG, SYS, PH>), dim3(grid), dim3(gjac_threads<ET, DEG, SYS, PH>()), 0,   \
+                       b->stream, b->ddesc, b->ptrs, items, n);                                                 \
+    break;
+    FR_BATCH_CASES(GJ)
+#undef GJ
+    default: break;
+  }
+}
+// grid <= 0: one workgroup per item (hardware scheduling, no persistent loop)
+static int gsize(int grid, int n) { return grid <= 0 ? std::max(1, n) : std::max(1, std::min(grid, n)); }
+
 template <int SYS>
 static fr_status launch_res(fr_batch_s* b, bool visc) {
-  const dim3 g(std::max(1, std::min(b->grid_res, b->nres))), t(kBT);
-  hipLaunchKernelGGL((k_batch_res<SYS, 0>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
-  if (visc) hipLaunchKernelGGL((k_batch_res<SYS, 1>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
-  hipLaunchKernelGGL((k_batch_res<SYS, 2>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
+  if (b->res_mode == 0) {
+    const dim3 g(gsize(b->grid_res, b->nres)), t(kBT);
+    hipLaunchKernelGGL((k_batch_res<SYS, 0>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
+    if (visc) hipLaunchKernelGGL((k_batch_res<SYS, 1>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
+    hipLaunchKernelGGL((k_batch_res<SYS, 2>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
+  } else {
+    for (int code : b->codes) {
+      const BItem* it = b->dres + b->seg_off[0][code];
+      const int n = b->seg_cnt[0][code], g = gsize(b->grid_res, n);
+      group_res<SYS, 0>(b, code, it, n, g);
+      if (visc) group_res<SYS, 1>(b, code, it, n, g);
+      group_res<SYS, 2>(b, code, it, n, g);
+    }
+  }
   return hipGetLastError() == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch residual launch");
 }
 template <int SYS>
 static fr_status launch_jac(fr_batch_s* b, bool visc) {
-  const dim3 gt(std::max(1, std::min(b->grid_res, b->ntil))), t(kBT);
-  hipLaunchKernelGGL((k_batch_jac<SYS, 0>), gt, t, 0, b->stream, b->ddesc, b->ptrs, b->dtil, b->ntil);
-  if (visc) hipLaunchKernelGGL((k_batch_jac<SYS, 1>), gt, t, 0, b->stream, b->ddesc, b->ptrs, b->dtil, b->ntil);
-  const dim3 gj(std::max(1, std::min(b->grid_jac, b->njac)));
-  hipLaunchKernelGGL((k_batch_jac<SYS, 2>), gj, t, 0, b->stream, b->ddesc, b->ptrs, b->djac, b->njac);
+  if (b->jac_mode == 0) {
+    const dim3 gt(gsize(b->grid_res, b->ntil)), t(kBT);
+    hipLaunchKernelGGL((k_batch_jac<SYS, 0>), gt, t, 0, b->stream, b->ddesc, b->ptrs, b->dtil, b->ntil);
+    if (visc) hipLaunchKernelGGL((k_batch_jac<SYS, 1>), gt, t, 0, b->stream, b->ddesc, b->ptrs, b->dtil, b->ntil);
+    hipLaunchKernelGGL((k_batch_jac<SYS, 2>), dim3(gsize(b->grid_jac, b->njac)), t, 0, b->stream, b->ddesc, b->ptrs,
+                       b->djac, b->njac);
+  } else {
+    for (int code : b->codes) {
+      const BItem* tl = b->dtil + b->seg_off[1][code];
+      const int nt = b->seg_cnt[1][code], gt = gsize(b->grid_res, nt);
+      group_jac<SYS, 0>(b, code, tl, nt, gt);
+      if (visc) group_jac<SYS, 1>(b, code, tl, nt, gt);
+      const int na = b->seg_cnt[2][code];
+      group_jac<SYS, 2>(b, code, b->djac + b->seg_off[2][code], na, gsize(b->grid_jac, na));
+    }
+  }
   return hipGetLastError() == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch Jacobian launch");
 }
 
@@ -295,6 +418,9 @@ fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out) {
   }
   b->sys = ctxs[0]->system;
   b->stream = ctxs[0]->stream;
+  for (auto* c : b->ctx) b->codes.push_back(bcode(c->type, c->p));
+  std::sort(b->codes.begin(), b->codes.end());
+  b->codes.erase(std::unique(b->codes.begin(), b->codes.end()), b->codes.end());
   int dev = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -361,21 +487,26 @@ fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void*
   fr_status st = set_ptrs(b, U, R, blocks);
   if (st) return st;
   // residual: grid size, then the tiles per work item of each (type, degree)
-  auto tune_one = [&](int* grid, int* k, fr_status (*fn)(fr_batch_s*), const std::vector<int>& grids,
+  // per phase: launch strategy, then grid size, then units per work item of
+  // each (type, degree) (coordinate descent on measured times)
+  auto tune_one = [&](int* mode, int* grid, int* k, fr_status (*fn)(fr_batch_s*), const std::vector<int>& grids,
                       const std::vector<int>& ks) -> fr_status {
     double best = 1e30;
+    int bm = *mode;
+    for (int md : {0, 1}) {
+      *mode = md;
+      double t = time_ms(b, fn, reps);
+      if (t < best) { best = t; bm = md; }
+    }
+    *mode = bm;
     int bg = *grid;
     for (int gm : grids) {
-      *grid = gm * b->ncu;
+      *grid = gm * b->ncu;          // 0: uncapped
       double t = time_ms(b, fn, reps);
       if (t < best) { best = t; bg = *grid; }
     }
     *grid = bg;
-    std::vector<int> codes;
-    for (auto* c : b->ctx) codes.push_back(bcode(c->type, c->p));
-    std::sort(codes.begin(), codes.end());
-    codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
-    for (int code : codes) {
+    for (int code : b->codes) {
       int bk = k[code];
       for (int kk : ks) {
         k[code] = kk;
@@ -390,18 +521,36 @@ fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void*
     }
     return FR_OK;
   };
-  if ((st = tune_one(&b->grid_res, b->k_res, run_rhs, {1, 2, 4, 8}, {1, 2, 4, 8}))) return st;
-  if ((st = tune_one(&b->grid_jac, b->k_jac, run_jac, {1, 2, 4}, {1, 2, 4}))) return st;
+  if ((st = tune_one(&b->res_mode, &b->grid_res, b->k_res, run_rhs, {1, 2, 4, 8, 0}, {1, 2, 4, 8}))) return st;
+  if ((st = tune_one(&b->jac_mode, &b->grid_jac, b->k_jac, run_jac, {1, 2, 4, 8, 0}, {1, 2, 4}))) return st;
   return hipStreamSynchronize(b->stream) == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch tuning");
 }
 
-fr_status fr_batch_tuning(const fr_batch* b, int* grid_res, int* grid_jac, int* k_res, int* k_jac) {
+fr_status fr_batch_tuning(const fr_batch* b, int* modes, int* grid_res, int* grid_jac, int* k_res, int* k_jac) {
   if (!b) return FR_E_INVALID;
+  if (modes) { modes[0] = b->res_mode; modes[1] = b->jac_mode; }
   if (grid_res) *grid_res = b->grid_res;
   if (grid_jac) *grid_jac = b->grid_jac;
   if (k_res) std::copy(b->k_res, b->k_res + 32, k_res);
   if (k_jac) std::copy(b->k_jac, b->k_jac + 32, k_jac);
   return FR_OK;
+}
+
+fr_status fr_batch_set_tuning(fr_batch* b, const int* modes, int grid_res, int grid_jac, const int* k_res,
+                              const int* k_jac) {
+  if (!b || grid_res < 0 || grid_jac < 0) return FR_E_INVALID;
+  if (modes) {
+    if (modes[0] < 0 || modes[0] > 1 || modes[1] < 0 || modes[1] > 1) return bfail(b, FR_E_INVALID, "launch mode");
+    b->res_mode = modes[0];
+    b->jac_mode = modes[1];
+  }
+  b->grid_res = grid_res;
+  b->grid_jac = grid_jac;
+  for (int i = 0; i < 32; ++i) {
+    if (k_res) b->k_res[i] = std::max(1, k_res[i]);
+    if (k_jac) b->k_jac[i] = std::max(1, k_jac[i]);
+  }
+  return rebuild(b);
 }
 
 }  // extern "C"

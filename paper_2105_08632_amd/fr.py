@@ -430,15 +430,18 @@ def _batch_symbols(L):
     L.fr_batch_rhs.argtypes = [P, PP, PP]
     L.fr_batch_jacobian_blocks.argtypes = [P, PP, PP]
     L.fr_batch_tune.argtypes = [P, PP, PP, PP, C.c_int]
-    L.fr_batch_tuning.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.fr_batch_tuning.argtypes = [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                  C.POINTER(C.c_int)]
+    L.fr_batch_set_tuning.argtypes = [P, C.POINTER(C.c_int), C.c_int, C.c_int, C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int)]
     for n in ("fr_batch_create", "fr_batch_destroy", "fr_batch_rhs", "fr_batch_jacobian_blocks", "fr_batch_tune",
-              "fr_batch_tuning"):
+              "fr_batch_tuning", "fr_batch_set_tuning"):
         getattr(L, n).restype = C.c_int
 
 
 _extensions.append(_batch_symbols)
 EXPORTED += ["fr_batch_create", "fr_batch_destroy", "fr_batch_last_error", "fr_batch_rhs",
-             "fr_batch_jacobian_blocks", "fr_batch_tune", "fr_batch_tuning"]
+             "fr_batch_jacobian_blocks", "fr_batch_tune", "fr_batch_tuning", "fr_batch_set_tuning"]
 
 
 def _ptrs(ts):
@@ -483,13 +486,24 @@ class Batch:
 
     def tuning(self) -> dict:
         gr, gj = C.c_int(), C.c_int()
+        md = (C.c_int * 2)()
         kr, kj = (C.c_int * 32)(), (C.c_int * 32)()
-        self._check(lib().fr_batch_tuning(self.h, C.byref(gr), C.byref(gj), kr, kj))
+        self._check(lib().fr_batch_tuning(self.h, md, C.byref(gr), C.byref(gj), kr, kj))
         codes = sorted({8 * int(c.mesh.elem_type[0]) + int(c.mesh.degree[0]) for c in self.ctxs})
         name = {0: "quad", 1: "tri"}
-        return {"grid_res": gr.value, "grid_jac": gj.value,
+        mode = {0: "mixed", 1: "grouped"}
+        return {"res_launch": mode[md[0]], "jac_launch": mode[md[1]], "grid_res": gr.value, "grid_jac": gj.value,
                 "tiles_per_item": {f"{name[k // 8]}p{k % 8}": kr[k] for k in codes},
                 "elems_per_item": {f"{name[k // 8]}p{k % 8}": kj[k] for k in codes}}
+
+    def set_tuning(self, res_launch: str, jac_launch: str, grid_res: int, grid_jac: int, k_res: int = 1,
+                   k_jac: int = 1):
+        """Loads a table: launch strategies ("mixed" | "grouped"), workgroups
+        per launch, and one units-per-item value for every (type, degree)."""
+        md = (C.c_int * 2)(*[{"mixed": 0, "grouped": 1}[x] for x in (res_launch, jac_launch)])
+        kr = (C.c_int * 32)(*([k_res] * 32))
+        kj = (C.c_int * 32)(*([k_jac] * 32))
+        self._check(lib().fr_batch_set_tuning(self.h, md, grid_res, grid_jac, kr, kj))
 
     def close(self):
         if getattr(self, "h", None) is not None and _lib is not None:

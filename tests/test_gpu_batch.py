@@ -39,16 +39,22 @@ def test_batch_matches_meshes_alone(system):
     alone_B = [c.jacobian_blocks(u, out_prec="f32").clone() for c, u in zip(ctxs, Us)]
     torch.cuda.synchronize()
     b = fr.Batch(ctxs)
-    for rnd in range(2):
+    settings = [("mixed", "mixed", 1024, 512, 1, 1), ("grouped", "grouped", 64, 32, 3, 2),
+                ("mixed", "grouped", 7, 5, 2, 3)]
+    for rnd in range(len(settings) + 1):
         Rs = b.rhs(Us)
         Bs = b.jacobian_blocks(Us)
         torch.cuda.synchronize()
         for i in range(len(cases)):
             assert torch.equal(Rs[i], alone_R[i]), (rnd, i)
             assert torch.equal(Bs[i], alone_B[i]), (rnd, i)
-        if rnd == 0:
-            info = b.tune(Us, reps=1)
-            assert info["grid_res"] > 0 and info["grid_jac"] > 0
+        if rnd < len(settings):
+            b.set_tuning(*settings[rnd])
+    info = b.tune(Us, reps=1)
+    assert info["grid_res"] > 0 and info["grid_jac"] > 0
+    Rs, Bs = b.rhs(Us), b.jacobian_blocks(Us)
+    torch.cuda.synchronize()
+    assert all(torch.equal(Rs[i], alone_R[i]) and torch.equal(Bs[i], alone_B[i]) for i in range(len(cases)))
 
 
 def test_batch_mesh_against_oracle():
