@@ -107,6 +107,7 @@ static void release(fr_ctx_s* c) {
   if (c->ops_mem) (void)hipFree(c->ops_mem);
   if (c->geo_mem) (void)hipFree(c->geo_mem);
   if (c->work_mem) (void)hipFree(c->work_mem);
+  if (c->mf_mem) (void)hipFree(c->mf_mem);
   for (int w = 0; w < 2; ++w)
     for (int k = 0; k < fr_ctx_s::kEvPool; ++k)
       for (int j = 0; j < 2; ++j)
@@ -243,6 +244,23 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   c->UFd = w + off[3]; c->Qd = w + off[4]; c->QFd = w + off[5];
   if (f32) { c->UF64 = w + off[6]; c->Q64 = w + off[7]; c->QF64 = w + off[8]; }
   else { c->UF64 = c->UF; c->Q64 = c->Q; c->QF64 = c->QF; }
+  // matrix-core Jacobian: geometry-only sensitivities (computed here, once)
+  // and the per-state tables
+  const size_t mfs = c->ks.mf_bytes ? c->ks.mf_bytes(0) : 0, mft = c->ks.mf_bytes ? c->ks.mf_bytes(1) : 0;
+  if (mfs) {
+    const size_t a = ((size_t)c->ne * mfs + 255) & ~(size_t)255;
+    if (hipMalloc(&c->mf_mem, a + (size_t)c->ne * mft) != hipSuccess) {
+      release(c);
+      return fail(nullptr, FR_E_NOMEM, "device allocation failed (Jacobian workspaces)");
+    }
+    c->mf_sens = c->mf_mem;
+    c->mf_tab = (char*)c->mf_mem + a;
+    if (c->ks.mf_setup(c) != 0) {
+      std::string e = c->err;
+      release(c);
+      return fail(nullptr, FR_E_DEVICE, "Jacobian sensitivities: " + e);
+    }
+  }
   *out = c;
   return FR_OK;
 }

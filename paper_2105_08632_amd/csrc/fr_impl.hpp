@@ -4,6 +4,7 @@
 #include <type_traits>
 
 #include "fr_ctx.hpp"
+#include "fr_jac_mf.hpp"
 
 constexpr int kThreads = 256;
 constexpr int kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
@@ -43,6 +44,38 @@ __global__ void __launch_bounds__((jac_tp_threads<E, NV, SYS, R>())) k_jac_tp(Op
   __shared__ __align__(16) char lds[jac_tp_lds<E, NV, SYS, R>()];
   jac_tp_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, o1, geo, ph, U, Q, UF, QF, B, nblk,
                                  DevSync());
+}
+
+// Matrix-core Jacobian (tensor-product elements, FP32): sensitivities once
+// per mesh, tables per state, then one wavefront per (element, block, tile).
+template <class E, int NV, int SYS, class R>
+__global__ void __launch_bounds__(kThreads) k_jac_mf_sens(OpsD<R> op, Ops1D<R> o1, GeoD<R> geo, PhysP ph, R* out,
+                                                          int nsb) {
+  __shared__ __align__(16) char lds[jac_mf_sens_lds<E, NV, SYS, R>()];
+  jac_mf_sens_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, o1, geo, ph, out, nsb);
+}
+template <class E, int NV, int SYS, class R>
+__global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, const R* U, const R* Q, const R* UF,
+                                                         const R* QF, R* out) {
+  __shared__ __align__(16) char lds[jac_mf_tables_lds<E, NV, SYS, R>()];
+  jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out);
+}
+template <class E, int NV, int SYS, class R, class OT>
+__global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>())) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
+                                                                                const R* tab, const R* sens, int nsb,
+                                                                                int nblk, long ntasks, OT* B) {
+  typedef MfSizes<E, NV, SYS> Y;
+  constexpr int TILES = Y::MT * Y::NT, WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
+  __shared__ __align__(16) R stage[WPB * STG];
+  const int wave = threadIdx.x >> 6;
+  const long task = (long)blockIdx.x * WPB + wave;
+  const bool active = task < ntasks;        // every wave reaches the barrier inside the task
+  const long t = active ? task : 0;
+  const int tile = (int)(t % TILES);
+  const int k = (int)((t / TILES) % nblk);
+  const int n = (int)(t / ((long)TILES * nblk));
+  jac_mf_task<E, NV, SYS, R, OT>(n, k, tile, threadIdx.x & 63, o1, rdet, tab, sens, nsb, nblk, B, stage + wave * STG,
+                                 active);
 }
 
 template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);
@@ -99,6 +132,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   static constexpr bool kTensorPath = (ET != ET_TRI) && (jac_tp_lds<E, NV, SYS, R>() <= kMaxLds);
+  // matrix-core path: FP32 quadrilaterals (one accumulator tile per solution point)
+  static constexpr bool kMfmaPath = (ET == ET_QUAD) && std::is_same<R, float>::value;
+  typedef MfSizes<E, NV, SYS> MF;
 
   template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B, int nblk) {
     if constexpr (!kTensorPath && jac_lds<E, NV, SYS, R>() > kMaxLds) {
@@ -119,6 +155,21 @@ template <int ET, int P, int SYS, class R> struct Impl {
       hipLaunchKernelGGL((k_grad<E, NV, R, R, R>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta, U,
                          (const R*)nullptr, (const R*)UF, Q, QF);
       FR_LAUNCH_CHECK(c);
+    }
+    if constexpr (kMfmaPath) {
+      if (!c->mf_sens || !c->mf_tab) { c->err = "Jacobian workspace missing"; return -4; }
+      hipLaunchKernelGGL((k_jac_mf_tab<E, NV, SYS, R>), dim3(ne), dim3(kThreads), 0, c->stream, geo, c->ph, U,
+                         (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab);
+      FR_LAUNCH_CHECK(c);
+      const long ntasks = (long)ne * nblk * MF::MT * MF::NT;
+      constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
+      if (c->timing) fr_time_begin(c, 0);
+      hipLaunchKernelGGL((k_jac_mf_asm<E, NV, SYS, R, OT>), dim3((unsigned)((ntasks + per - 1) / per)), dim3(64 * per),
+                         0, c->stream, ctx_o1<R>(c), geo.rdet, (const R*)c->mf_tab, (const R*)c->mf_sens,
+                         1 + E::NFACE, nblk, ntasks, B);
+      FR_LAUNCH_CHECK(c);
+      if (c->timing) fr_time_end(c, 0);
+      return 0;
     }
     if (c->timing) fr_time_begin(c, 0);
     if constexpr (kTensorPath)
@@ -146,5 +197,19 @@ template <int ET, int P, int SYS, class R> struct Impl {
     return -2;
   }
 
-  static KernelSet set() { return KernelSet{&rhs, &jvp, &jac}; }
+  // bytes per element of the matrix-core path's sensitivity and table arrays (0: not used)
+  static size_t mf_bytes(int which) {
+    if constexpr (kMfmaPath) return which == 0 ? (size_t)(1 + E::NFACE) * MF::BLK * sizeof(R) : (size_t)MF::TAB * sizeof(R);
+    else return 0;
+  }
+  static int mf_setup(fr_ctx_s* c) {
+    if constexpr (kMfmaPath) {
+      hipLaunchKernelGGL((k_jac_mf_sens<E, NV, SYS, R>), dim3((unsigned)c->ne), dim3(kThreads), 0, c->stream,
+                         ctx_ops<R>(c), ctx_o1<R>(c), ctx_geo<R>(c), c->ph, (R*)c->mf_sens, 1 + E::NFACE);
+      FR_LAUNCH_CHECK(c);
+    }
+    return 0;
+  }
+
+  static KernelSet set() { return KernelSet{&rhs, &jvp, &jac, &mf_bytes, &mf_setup}; }
 };

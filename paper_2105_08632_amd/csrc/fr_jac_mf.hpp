@@ -1,0 +1,496 @@
+// Jacobian blocks of tensor-product elements on the matrix cores.
+//
+// For each variable pair (alpha, beta) the block is (FR method, eq.
+// "divergence_fr", differentiated as in eq. "jacobian_rhs")
+//   J = -rdet (.) ( sum_d Dc_d X_d + Cor Y ),
+//   X_d[tau] = sum_k T_d[tau][k] G_k[tau]   (k: Gam_0 .. Gam_{ND-1}, delta),
+//   Y[g]     = sum_j W[g][j] S_j[g]          (j: DL, DR, SL_d.., SR_d..),
+// where T, W are the pointwise Jacobian tables (rows m = alpha*NV + beta) and
+// G, S the sensitivities of the gradient and face states to U_k (columns
+// sigma).  For fixed tau (or g) the contraction over k (or j) is a
+// (pairs x k) . (k x sigma) product: one 16x16x4 MFMA per (tau, d) and two
+// per g.  The 1-D factors Dc1 (along the d-lines through tau) and h+- (along
+// g's normal line) then scatter X and Y into 16x16 accumulator tiles per
+// solution point rho, as scalar-constant FMAs (the indices are compile-time,
+// so the factors live in scalar registers).  One wavefront per (block,
+// pair tile, sigma tile) task.
+//
+// Three kernels: the sensitivities G, S depend on the geometry only and are
+// computed once per mesh (jac_mf_sens_body); the tables T, W of a state are
+// computed per element (jac_mf_tables_body); the assembly (jac_mf_task) is
+// one wavefront per task with no LDS: every MFMA fragment is one coalesced
+// 256-byte read (operand index fastest in memory) of those arrays, and the
+// outputs are written straight from the accumulators.
+#pragma once
+#include "fr_jac_tp.hpp"
+
+template <class E, int NV, int SYS> struct MfSizes {
+  static constexpr int ND = E::ND, NS = E::NS, NF = E::NF, NFACE = E::NFACE, NV2 = NV * NV;
+  static constexpr int KV = ND + 1;                 // Gam_0 .. Gam_{ND-1}, delta
+  static constexpr int JF = 2 + 2 * ND;             // DL, DR, SL_d.., SR_d..
+  static constexpr int JC = (JF + 3) / 4;           // K chunks of the face product
+  static constexpr int MT = (NV2 + 15) / 16, MP = 16 * MT;   // pair tiles
+  static constexpr int NT = (NS + 15) / 16, NP = 16 * NT;    // sigma tiles
+  static constexpr int TBT = NS * ND * KV * MP;
+  static constexpr int TFT = NF * JF * MP;
+  static constexpr int GSZ = NS * KV * NP;          // per block: G
+  static constexpr int SSZ = NF * JF * NP;          // per block: S
+  static constexpr int BLK = GSZ + SSZ;             // sensitivities of one block
+  static constexpr int TAB = TBT + TFT;             // tables of one element
+};
+
+template <class R> struct Mfma;
+template <> struct Mfma<float> {
+  typedef __attribute__((__vector_size__(4 * sizeof(float)))) float acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of D held in accumulator r by lanes 16 q .. 16 q + 15
+  static constexpr __device__ int row(int q, int r) { return 4 * q + r; }
+};
+template <> struct Mfma<double> {
+  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static constexpr __device__ int row(int q, int r) { return q + 4 * r; }
+};
+
+
+// assembly tasks per workgroup and the LDS staging of one task's tile
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() { return 16 * NV * (E::NS * NV + 1); }
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
+  return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
+}
+
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_sens_lds() {
+  typedef TPSizes<E, NV, SYS> Z;
+  typedef MfSizes<E, NV, SYS> Y;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP;
+  return lds_bytes<R>(NF * NS) + lds_bytes<R>(NS * NF) + lds_bytes<R>(NS * ND * ND) + lds_bytes<int>(NF) +
+         lds_bytes<R>(NFACE * NS * ND * ND) + 2 * lds_bytes<int>(NFACE) + lds_bytes<R>(NFACE * NFP * ND) +
+         lds_bytes<Ops1D<R>>(1) + lds_bytes<R>((1 + NFACE) * Y::GSZ);
+}
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_tables_lds() {
+  typedef TPSizes<E, NV, SYS> Z;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND;
+  return lds_bytes<R>(NS * NV) + lds_bytes<R>(NS * ND * NV) + 2 * lds_bytes<R>(NF * NV) +
+         2 * lds_bytes<R>(NF * ND * NV) + 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) +
+         lds_bytes<int>(NF) + jac_tp_scratch<E, NV, SYS, R>();
+}
+
+// Sensitivities of element n for all blocks (geometry only):
+// out[k][G | S] (MfSizes::BLK values per block, operand layout).
+template <class E, int NV, int SYS, class R>
+__device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const Ops1D<R>& o1,
+                                 const GeoD<R>& geo, const PhysP& ph, R* out, int nblk) {
+  typedef TPSizes<E, NV, SYS> Z;
+  typedef MfSizes<E, NV, SYS> Y;
+  typedef TPIdx<E> X;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP;
+  constexpr int N1 = E::DEG + 1;
+  constexpr int KV = Y::KV, JF = Y::JF, NP = Y::NP, BLK = Y::BLK;
+  const bool visc = SysTraits<SYS>::kVisc && (SYS != SYS_ADV || ph.mu != 0.0);
+  const R cb = R(0.5 + ph.beta);
+  auto sync = []() { __syncthreads(); };
+  Lds L{lds};
+  R* sM0 = L.take<R>(NF * NS);
+  R* sCor = L.take<R>(NS * NF);
+  R* sJi = L.take<R>(NS * ND * ND);
+  int* spg = L.take<int>(NF);
+  R* sJm = L.take<R>(NFACE * NS * ND * ND);
+  int* snb = L.take<int>(NFACE);
+  int* snf = L.take<int>(NFACE);
+  R* sW = L.take<R>(NFACE * NFP * ND);
+  Ops1D<R>* sO1 = L.take<Ops1D<R>>(1);
+  R* gamT = L.take<R>((1 + NFACE) * Y::GSZ);
+  const long nl = n;
+  R* gout = out + nl * nblk * BLK;
+  for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
+  for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
+  for (int i = tid; i < NF; i += nth) spg[i] = geo.nbfp[nl * NF + i];
+  for (int i = tid; i < NS * ND * ND; i += nth) sJi[i] = geo.Jinv[nl * NS * ND * ND + i];
+  for (int i = tid; i < NFACE; i += nth) { snb[i] = geo.nbr[nl * NFACE + i]; snf[i] = geo.nbface[nl * NFACE + i]; }
+  for (int i = tid; i < (int)(sizeof(Ops1D<R>) / sizeof(R)); i += nth)
+    reinterpret_cast<R*>(sO1)[i] = reinterpret_cast<const R*>(&o1)[i];
+  sync();
+  for (int i = tid; i < NFACE * NS * ND * ND; i += nth) {
+    int f = i / (NS * ND * ND), r = i % (NS * ND * ND);
+    sJm[i] = geo.Jinv[(long)snb[f] * NS * ND * ND + r];
+  }
+  sync();
+  // W_d'(g): the neighbour's face gradient at g's partner w.r.t. u_n (same
+  // face point only on tensor elements)
+  if (visc)
+    for (int i = tid; i < NFACE * NFP * ND; i += nth) {
+      int f = i / (NFP * ND), gi = (i / ND) % NFP, d2 = i % ND;
+      int g = f * NFP + gi;
+      int g2 = spg[g] - snb[f] * NF;
+      int f2 = g2 / NFP;
+      int ax = X::fax(f2);
+      R sg = R(X::fsg(f2));
+      R acc = R(0);
+      for (int w = 0; w < N1; ++w) {
+        int t = X::fline(g2, w);
+        acc += sM0[g2 * NS + t] * sCor[t * NF + g2] * sJm[((f * NS + t) * ND + ax) * ND + d2] * sg;
+      }
+      sW[i] = cb * acc;
+    }
+  sync();
+  const int kb = 0, nbk = nblk;
+    // G_e[tau][sigma] = d q~_e(tau) / d u_k(sigma); e = ND: delta (k = 0)
+    for (int i = tid; i < nbk * NS * KV * NP; i += nth) {
+      const int kk = i / (NS * KV * NP), t = (i / (KV * NP)) % NS, e = (i / NP) % KV, s = i % NP;
+      const int k = kb + kk;
+      R v = R(0);
+      if (s < NS) {
+        if (e == ND) {
+          v = (k == 0 && t == s) ? R(1) : R(0);
+        } else if (visc) {
+          if (k == 0) {
+            bool on = true;
+            for (int d = 0; d < ND; ++d)
+              if (d != e && X::co(t, d) != X::co(s, d)) on = false;
+            if (on) v = sO1->G1[X::co(t, e)][X::co(s, e)];
+          } else {
+            const int f = k - 1, m = snb[f];
+            if (X::fax(f) == e) {
+              // cb sum_{g on f} Cor[tau][g] nref_e(g) M0_m[P(g)][sigma]
+              for (int gi = 0; gi < NFP; ++gi) {
+                const int g = f * NFP + gi;
+                const R c = sCor[t * NF + g];
+                if (c != R(0)) v += c * R(X::fsg(f)) * sM0[(spg[g] - m * NF) * NS + s];
+              }
+              v *= cb;
+            }
+          }
+        }
+      }
+      gamT[kk * Y::GSZ + (t * KV + e) * NP + s] = v;
+      gout[kk * BLK + (t * KV + e) * NP + s] = v;
+    }
+    sync();
+    // S_j[g][sigma]: DL, DR (face values), SL_d', SR_d' (own / neighbour
+    // physical face gradients)
+    for (int i = tid; i < nbk * NF * NP; i += nth) {
+      const int kk = i / (NF * NP), g = (i / NP) % NF, s = i % NP;
+      const int k = kb + kk;
+      R* o = gout + kk * BLK + Y::GSZ + g * JF * NP + s;
+      const int fg = g / NFP;
+      R dl = R(0), dr = R(0);
+      if (s < NS) {
+        if (k == 0) dl = sM0[g * NS + s];
+        else if (fg == k - 1) dr = sM0[(spg[g] - snb[fg] * NF) * NS + s];
+      }
+      o[0] = dl;
+      o[NP] = dr;
+      for (int d2 = 0; d2 < ND; ++d2) {
+        R sl = R(0), sr = R(0);
+        if (visc && s < NS) {
+          for (int w = 0; w < N1; ++w) {
+            const int t = X::fline(g, w);
+            R acc = R(0);
+            for (int e = 0; e < ND; ++e)
+              acc += sJi[(t * ND + e) * ND + d2] * gamT[kk * Y::GSZ + (t * KV + e) * NP + s];
+            sl += sM0[g * NS + t] * acc;
+          }
+          if (k == 0) {
+            sr = sW[g * ND + d2] * sM0[g * NS + s];
+          } else if (fg == k - 1) {
+            const int g2 = spg[g] - snb[fg] * NF;
+            for (int w = 0; w < N1; ++w) {
+              const int t = X::fline(g2, w);
+              R acc = R(0);
+              for (int e = 0; e < ND; ++e) {
+                bool on = true;
+                for (int d = 0; d < ND; ++d)
+                  if (d != e && X::co(t, d) != X::co(s, d)) on = false;
+                if (on) acc += sJm[((fg * NS + t) * ND + e) * ND + d2] * sO1->G1[X::co(t, e)][X::co(s, e)];
+              }
+              sr += sM0[g2 * NS + t] * acc;
+            }
+          }
+        }
+        o[(2 + d2) * NP] = sl;
+        o[(2 + ND + d2) * NP] = sr;
+      }
+    }
+    sync();
+}
+
+// Pointwise Jacobian tables of element n at the state:
+// out[n][T | W] (MfSizes::TAB values, operand layout).
+template <class E, int NV, int SYS, class R>
+__device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const GeoD<R>& geo, const PhysP& ph,
+                                   const R* U, const R* Q, const R* UF, const R* QF, R* out) {
+  typedef TPSizes<E, NV, SYS> Z;
+  typedef MfSizes<E, NV, SYS> Y;
+  constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NV2 = Z::NV2;
+  constexpr int KV = Y::KV, JF = Y::JF, MP = Y::MP;
+  const bool visc = SysTraits<SYS>::kVisc && (SYS != SYS_ADV || ph.mu != 0.0);
+  const R cL = R(0.5 + ph.beta), cR = R(0.5 - ph.beta), eta = R(ph.eta);
+  auto sync = []() { __syncthreads(); };
+  Lds L{lds};
+  R* su = L.take<R>(NS * NV);
+  R* sq = L.take<R>(NS * ND * NV);
+  R* suL = L.take<R>(NF * NV);
+  R* suR = L.take<R>(NF * NV);
+  R* sqL = L.take<R>(NF * ND * NV);
+  R* sqR = L.take<R>(NF * ND * NV);
+  R* sJi = L.take<R>(NS * ND * ND);
+  R* sS = L.take<R>(NS * ND * ND);
+  R* snn = L.take<R>(NF * ND);
+  R* smg = L.take<R>(NF);
+  int* spg = L.take<int>(NF);
+  Lds L1{L.p};
+  R* bh = L1.take<R>(ND * ND * NS * NV2);
+  R* rL = L1.take<R>(NF * NV2);
+  R* rR = L1.take<R>(NF * NV2);
+  R* vL = L1.take<R>(NF * NV2);
+  R* vR = L1.take<R>(NF * NV2);
+  R* qLt = L1.take<R>(ND * NF * NV2);
+  R* qRt = L1.take<R>(ND * NF * NV2);
+  const long nl = n;
+  R* tbT = out + nl * Y::TAB;
+  R* tfT = tbT + Y::TBT;
+  for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
+  if (visc)
+    for (int i = tid; i < NS * ND * NV; i += nth) sq[i] = Q[nl * NS * ND * NV + i];
+  for (int i = tid; i < NF; i += nth) { spg[i] = geo.nbfp[nl * NF + i]; smg[i] = geo.magN[nl * NF + i]; }
+  for (int i = tid; i < NS * ND * ND; i += nth) { sJi[i] = geo.Jinv[nl * NS * ND * ND + i]; sS[i] = geo.S[nl * NS * ND * ND + i]; }
+  for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
+  sync();
+  for (int i = tid; i < NF * NV; i += nth) {
+    int g = i / NV, a = i % NV;
+    suL[i] = UF[(nl * NF + g) * NV + a];
+    suR[i] = UF[(long)spg[g] * NV + a];
+  }
+  if (visc)
+    for (int i = tid; i < NF * ND * NV; i += nth) {
+      int g = i / (ND * NV), r = i % (ND * NV);
+      sqL[i] = QF[(nl * NF + g) * ND * NV + r];
+      sqR[i] = QF[(long)spg[g] * ND * NV + r];
+    }
+  sync();
+  // ---------------------------------------------------------------- tables
+  // one seeded input per item (single-tangent duals keep register use low):
+  // solution points: (tau, pass, c), pass 0 seeds u_c, pass 1+d seeds q_{d,c};
+  // flux points: (g, pass, c), passes 0/1 seed u_L,c / u_R,c in the
+  // convective flux, 2/3 seed u_c in the viscous flux at L / R, then q_{d,c}
+  // at L, then at R.
+  {
+    typedef Dual<R> DT;
+    constexpr int NPS = SysTraits<SYS>::kVisc ? 1 + ND : 1;
+    constexpr int NPF = SysTraits<SYS>::kVisc ? 4 + 2 * ND : 2;
+    const int nsp = visc ? NPS : 1, nfp = visc ? NPF : 2;
+    for (int it = tid; it < (NS * nsp + NF * nfp) * NV; it += nth) {
+      const int c = it % NV, j0 = it / NV;
+      if (j0 < NS * nsp) {
+        int t = j0 / nsp, ps = j0 % nsp;
+        DT u[NV], f[ND][NV], q[ND][NV];
+        for (int a = 0; a < NV; ++a) u[a] = DT(su[t * NV + a], (ps == 0 && a == c) ? R(1) : R(0));
+        for (int d = 0; d < ND; ++d)
+          for (int a = 0; a < NV; ++a)
+            q[d][a] = DT(visc ? sq[(t * ND + d) * NV + a] : R(0), (ps == 1 + d && a == c) ? R(1) : R(0));
+        if (ps == 0) {
+          flux_inviscid<SYS, ND, NV, DT>(ph, u, f);
+          if (visc) {
+            DT fv[ND][NV];
+            flux_viscous<SYS, ND, NV, DT>(ph, u, q, fv);
+            for (int d = 0; d < ND; ++d)
+              for (int a = 0; a < NV; ++a) f[d][a] += fv[d][a];
+          }
+          for (int a = 0; a < NV; ++a)
+            for (int d = 0; d < ND; ++d) {
+              R acc = R(0);
+              for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d;
+              tbT[((t * ND + d) * KV + ND) * MP + a * NV + c] = acc;
+            }
+        } else {
+          flux_viscous<SYS, ND, NV, DT>(ph, u, q, f);
+          for (int k = 0; k < ND; ++k)
+            for (int a = 0; a < NV; ++a) bh[(((ps - 1) * ND + k) * NS + t) * NV2 + a * NV + c] = f[k][a].d;
+        }
+      } else {
+        int j = j0 - NS * nsp;
+        int g = j / nfp, ps = j % nfp;
+        R nn[ND];
+        for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
+        if (ps < 2) {
+          DT uL[NV], uR[NV], F[NV];
+          for (int a = 0; a < NV; ++a) {
+            uL[a] = DT(suL[g * NV + a], (ps == 0 && a == c) ? R(1) : R(0));
+            uR[a] = DT(suR[g * NV + a], (ps == 1 && a == c) ? R(1) : R(0));
+          }
+          common_inviscid<SYS, ND, NV, DT>(ph, uL, uR, nn, F);
+          R* o = ps == 0 ? rL : rR;
+          for (int a = 0; a < NV; ++a) o[g * NV2 + a * NV + c] = F[a].d;
+        } else {
+          int pp = ps - 2;
+          int side = (pp == 1 || pp >= 2 + ND) ? 1 : 0;
+          int qd = pp < 2 ? -1 : (pp - 2) % ND;
+          const R* us = side ? suR : suL;
+          const R* qs = side ? sqR : sqL;
+          DT u[NV], q[ND][NV], fv[ND][NV];
+          for (int a = 0; a < NV; ++a) u[a] = DT(us[g * NV + a], (qd < 0 && a == c) ? R(1) : R(0));
+          for (int d = 0; d < ND; ++d)
+            for (int a = 0; a < NV; ++a) q[d][a] = DT(qs[(g * ND + d) * NV + a], (qd == d && a == c) ? R(1) : R(0));
+          flux_viscous<SYS, ND, NV, DT>(ph, u, q, fv);
+          R wgt = side ? cR : cL;
+          for (int a = 0; a < NV; ++a) {
+            R acc = R(0);
+            for (int d = 0; d < ND; ++d) acc += nn[d] * fv[d][a].d;
+            acc *= wgt;
+            if (qd < 0) (side ? vR : vL)[g * NV2 + a * NV + c] = acc;
+            else (side ? qRt : qLt)[(qd * NF + g) * NV2 + a * NV + c] = acc;
+          }
+        }
+      }
+    }
+    sync();
+    if (!visc)
+      for (int i = tid; i < NV2 * NS * ND; i += nth) {
+        const int ab = i / (NS * ND), r = i % (NS * ND);
+        for (int e = 0; e < ND; ++e) tbT[(r * KV + e) * MP + ab] = R(0);
+      }
+    if (visc)
+      for (int i = tid; i < NV2 * NS * ND * ND; i += nth) {
+        int ab = i / (NS * ND * ND), t = (i / (ND * ND)) % NS, d = (i / ND) % ND, e = i % ND;
+        R acc = R(0);
+        for (int k = 0; k < ND; ++k) {
+          R s = sS[(t * ND + d) * ND + k];
+          for (int d2 = 0; d2 < ND; ++d2) acc += s * bh[((d2 * ND + k) * NS + t) * NV2 + ab] * sJi[(t * ND + e) * ND + d2];
+        }
+        tbT[((t * ND + d) * KV + e) * MP + ab] = acc;
+      }
+    for (int i = tid; i < NV2 * NF; i += nth) {
+      int ab = i / NF, g = i % NF;
+      int a = ab / NV, c = ab % NV;
+      R mg = smg[g];
+      R id = (a == c) ? eta : R(0);
+      R* o = tfT + g * JF * MP + ab;
+      o[0] = mg * (rL[g * NV2 + ab] + (visc ? vL[g * NV2 + ab] + id : R(0)));
+      o[MP] = mg * (rR[g * NV2 + ab] + (visc ? vR[g * NV2 + ab] - id : R(0)));
+      for (int d = 0; d < ND; ++d) {
+        o[(2 + d) * MP] = visc ? mg * qLt[(d * NF + g) * NV2 + ab] : R(0);
+        o[(2 + ND + d) * MP] = visc ? mg * qRt[(d * NF + g) * NV2 + ab] : R(0);
+      }
+    }
+    sync();
+  }
+
+}
+
+// One wavefront task: block kb + kk, pair tile mt, sigma tile nt.  MFMA
+// fragments: A[m][k] from lane (m = lane % 16, k = lane / 16), B[k][n] from
+// lane (k = lane / 16, n = lane % 16); D[i][lane % 16] in accumulator r with
+// i = Mfma<R>::row(lane / 16, r) (FP32: 4 (lane / 16) + r, FP64: lane / 16 + 4 r).
+template <class E, int NV, int SYS, class R, class OT>
+__device__ __forceinline__ void jac_mf_task(int n, int k, int tile, int lane, const Ops1D<R>& o1, const R* rdet,
+                                            const R* tab, const R* sens, int nsb, int nblk, OT* B, R* stage,
+                                            bool active) {
+  typedef MfSizes<E, NV, SYS> Y;
+  typedef TPIdx<E> X;
+  typedef Mfma<R> M;
+  typedef typename M::acc acc;
+  constexpr int NS = Y::NS, ND = Y::ND, NF = Y::NF, NFP = E::NFP, N1 = E::DEG + 1;
+  constexpr int KV = Y::KV, JF = Y::JF, JC = Y::JC, MP = Y::MP, NP = Y::NP, BB = NS * NV;
+  const int mt = tile / Y::NT, nt = tile % Y::NT;
+  const int li = lane & 15, kq = lane >> 4;
+  const long nl = n;
+  const R* tbT = tab + nl * Y::TAB;
+  const R* tfT = tbT + Y::TBT;
+  const R* G = sens + (nl * nsb + k) * Y::BLK;
+  const R* S = G + Y::GSZ;
+  const R* srd = rdet + nl * NS;
+  OT* Bn = B + nl * (long)nblk * BB * BB;
+  const int kb = k, kk = 0;
+  const acc zero = {};
+  acc V[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) V[r] = zero;
+  // Operands come straight from global memory: each phase issues the
+  // fragment loads of up to 16 points (or flux points) at once, one memory
+  // round trip per chunk, then computes; chunks bound the live registers.
+  constexpr int CH = 16;
+  // volume: X_d[tau] scattered along the d-line through tau
+#pragma unroll
+  for (int t0 = 0; t0 < NS; t0 += CH) {
+    R bv[CH], av[CH][ND];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int t = t0 + i;
+      bv[i] = (t < NS && kq < KV) ? G[(t * KV + kq) * NP + nt * 16 + li] : R(0);
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+        av[i][d] = (t < NS && kq < KV) ? tbT[((t * ND + d) * KV + kq) * MP + mt * 16 + li] : R(0);
+    }
+    fr_sched_fence();
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int t = t0 + i;
+      if (t < NS) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const acc x = M::mma(av[i][d], bv[i], zero);
+#pragma unroll
+          for (int w = 0; w < N1; ++w) V[X::line(t, d, w)] += o1.Dc1[w][X::co(t, d)] * x;
+        }
+      }
+    }
+    fr_sched_fence();
+  }
+  // faces: Y[g] scattered along g's normal line
+#pragma unroll
+  for (int g0 = 0; g0 < NF; g0 += CH) {
+    R fa[CH][JC], fb[CH][JC];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+#pragma unroll
+      for (int ch = 0; ch < JC; ++ch) {
+        const int g = g0 + i, j = ch * 4 + kq;
+        fa[i][ch] = (g < NF && j < JF) ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
+        fb[i][ch] = (g < NF && j < JF) ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+      }
+    fr_sched_fence();
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int g = g0 + i;
+      if (g < NF) {
+        acc y = zero;
+#pragma unroll
+        for (int ch = 0; ch < JC; ++ch) y = M::mma(fa[i][ch], fb[i][ch], y);
+        const bool pos = X::fsg(g / NFP) > 0;
+#pragma unroll
+        for (int w = 0; w < N1; ++w) V[X::fline(g, w)] += (pos ? o1.hp[w] : o1.hm[w]) * y;
+      }
+    }
+    fr_sched_fence();
+  }
+  // D rows are pairs m, columns sigma; block column c = sigma NV + beta,
+  // row rho NV + alpha.  With one pair tile (NV <= 4) a task owns whole
+  // columns nt*16*NV .. (nt*16 + 16)*NV - 1 of block k, one contiguous range:
+  // the tile goes through LDS (column stride BB + 1) and leaves as
+  // consecutive 256-byte stores.
+  static_assert(Y::MT == 1, "staged stores need one pair tile");
+  constexpr int SP = BB + 1;
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = M::row(kq, r);
+      if (m < NV * NV && nt * 16 + li < NS) {
+        const int a = m / NV, b = m % NV;
+        R* col = stage + (li * NV + b) * SP + a;
+#pragma unroll
+        for (int rho = 0; rho < NS; ++rho) col[rho * NV] = -(srd[rho] * V[rho][r]);
+      }
+    }
+  }
+  __syncthreads();
+  if (active) {
+    const int ncol = ((NS - nt * 16) < 16 ? (NS - nt * 16) : 16) * NV;
+    OT* dst = Bn + (long)(kb + kk) * BB * BB + (long)nt * 16 * NV * BB;
+    for (int i = lane; i < ncol * BB; i += 64) dst[i] = to_out<OT>(stage[(i / BB) * SP + i % BB]);
+  }
+}
+

@@ -51,7 +51,7 @@ def test_batch_matches_meshes_alone(system):
         if rnd < len(settings):
             b.set_tuning(*settings[rnd])
     info = b.tune(Us, reps=1)
-    assert info["grid_res"] > 0 and info["grid_jac"] > 0
+    assert info["grid_res"] >= 0 and info["grid_jac"] >= 0   # 0: one workgroup per item
     Rs, Bs = b.rhs(Us), b.jacobian_blocks(Us)
     torch.cuda.synchronize()
     assert all(torch.equal(Rs[i], alone_R[i]) and torch.equal(Bs[i], alone_B[i]) for i in range(len(cases)))

@@ -105,11 +105,15 @@ def test_quad_fp64(p, system):
     _assert(out, "f64", (p, system))
 
 
-@pytest.mark.parametrize("p", [1, 3])
-def test_quad_ns_fp32(p):
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("system", ["ns", "euler"])
+def test_quad_fp32(system, p):
+    """FP32 contexts: the matrix-core Jacobian path (every degree, both
+    systems), FP64-evaluated residual, FP32 JVP."""
     m = I.quad_mesh(6, degree=p, jitter=0.05, K=1)
-    out = check_case(m, I.ns_physics(2, 1000.0, 0.72), p, I.ns2d_state(m, p), "f32", [0, 13, 35])
-    _assert(out, "f32", p)
+    ph = I.ns_physics(2, 1000.0, 0.72) if system == "ns" else I.euler_physics(2)
+    out = check_case(m, ph, p, I.ns2d_state(m, p), "f32", [0, 13, 35])
+    _assert(out, "f32", (system, p))
 
 
 def test_ragged_tile_tail():
