@@ -158,12 +158,12 @@ template <int ET, int P, int SYS, class R> struct Impl {
     }
     if constexpr (kMfmaPath) {
       if (!c->mf_sens || !c->mf_tab) { c->err = "Jacobian workspace missing"; return -4; }
+      if (c->timing) fr_time_begin(c, 0);     // tables + assembly
       hipLaunchKernelGGL((k_jac_mf_tab<E, NV, SYS, R>), dim3(ne), dim3(kThreads), 0, c->stream, geo, c->ph, U,
                          (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab);
       FR_LAUNCH_CHECK(c);
       const long ntasks = (long)ne * nblk * MF::MT * MF::NT;
       constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
-      if (c->timing) fr_time_begin(c, 0);
       hipLaunchKernelGGL((k_jac_mf_asm<E, NV, SYS, R, OT>), dim3((unsigned)((ntasks + per - 1) / per)), dim3(64 * per),
                          0, c->stream, ctx_o1<R>(c), geo.rdet, (const R*)c->mf_tab, (const R*)c->mf_sens,
                          1 + E::NFACE, nblk, ntasks, B);

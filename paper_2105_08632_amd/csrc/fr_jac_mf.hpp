@@ -22,6 +22,8 @@
 // 256-byte read (operand index fastest in memory) of those arrays, and the
 // outputs are written straight from the accumulators.
 #pragma once
+#include <type_traits>
+
 #include "fr_jac_tp.hpp"
 
 template <class E, int NV, int SYS> struct MfSizes {
@@ -490,7 +492,16 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int tile, int lane, co
   if (active) {
     const int ncol = ((NS - nt * 16) < 16 ? (NS - nt * 16) : 16) * NV;
     OT* dst = Bn + (long)(kb + kk) * BB * BB + (long)nt * 16 * NV * BB;
-    for (int i = lane; i < ncol * BB; i += 64) dst[i] = to_out<OT>(stage[(i / BB) * SP + i % BB]);
+    if constexpr (std::is_same<OT, float>::value && BB % 4 == 0) {
+      // 16-byte stores: 1 KB per instruction (dst and the tile are 4-aligned)
+      for (int i = 4 * lane; i < ncol * BB; i += 256) {
+        const int cc = i / BB, rr = i % BB;
+        const R* sp = stage + cc * SP + rr;
+        *reinterpret_cast<float4*>(dst + i) = make_float4(sp[0], sp[1], sp[2], sp[3]);
+      }
+    } else {
+      for (int i = lane; i < ncol * BB; i += 64) dst[i] = to_out<OT>(stage[(i / BB) * SP + i % BB]);
+    }
   }
 }
 
