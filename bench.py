@@ -56,7 +56,7 @@ def kernel_source_hash():
 def measured_traffic(per_launch_alg):
     """HBM bytes per launch of the block-assembly kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_jac_tp_ns2d_p3_128_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_jac_mf_ns2d_p3_128_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
