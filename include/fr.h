@@ -113,7 +113,9 @@ const char* fr_last_error(const fr_ctx* ctx);
 fr_status fr_ctx_sync(fr_ctx* ctx);
 
 /* R = R(U): the FR-DG residual, eq. "divergence_fr" and the method of
- * lines.  U, R: [n_dof] device arrays in the context precision. */
+ * lines.  U, R: [n_dof] device arrays in the context precision; the
+ * arithmetic is FP64 in every context (the divergence of a flux with a large
+ * mean, e.g. the pressure at low Mach number, cancels). */
 fr_status fr_rhs(fr_ctx* ctx, const void* U, void* R);
 
 /* Jacobian blocks dR_n/dU_k, k in {n} and the face neighbours of n (eq.
@@ -123,7 +125,9 @@ fr_status fr_rhs(fr_ctx* ctx, const void* U, void* R);
 fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precision out_prec);
 
 /* Jv = dR/dU(U) v exactly (forward-mode tangent of every step, including the
- * viscous second layer).  R_out (may be NULL) receives R(U). */
+ * viscous second layer).  R_out (may be NULL) receives R(U).  Like fr_rhs it
+ * is evaluated in FP64 (dual numbers) whatever the context precision; U, v,
+ * Jv and R_out are in the context precision. */
 fr_status fr_jvp(fr_ctx* ctx, const void* U, const void* v, void* Jv, void* R_out);
 
 /* ---- Implicit steps (backward Euler) -------------------------------------

@@ -226,12 +226,14 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     c->opsf = ops_view<float>((char*)c->ops_mem, oo32);
     c->geof = geo_view<float>((char*)c->geo_mem, go32, (int)c->ne);
   }
-  // workspaces: traces / gradients for the residual, their dual versions for the JVP
+  // workspaces: traces / gradients for the Jacobian assembly (context
+  // precision), their FP64 dual versions for the JVP and FP64 ones for the
+  // residual (both evaluated in FP64 whatever the context precision)
   const size_t rs = (prec == FR_F64) ? 8 : 4;
   const size_t nuf = (size_t)c->ne * c->nf * nv, nq = (size_t)c->ne * c->ns * c->nd * nv, nqf = (size_t)c->ne * c->nf * c->nd * nv;
   const bool f32 = prec == FR_F32;
   size_t sizes[9] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
-                     2 * nuf * rs, visc ? 2 * nq * rs : 0, visc ? 2 * nqf * rs : 0,
+                     2 * nuf * 8, visc ? 2 * nq * 8 : 0, visc ? 2 * nqf * 8 : 0,
                      f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0};
   size_t off[9], tot = 0;
   for (int i = 0; i < 9; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
@@ -247,14 +249,17 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   // matrix-core Jacobian: geometry-only sensitivities (computed here, once)
   // and the per-state tables
   const size_t mfs = c->ks.mf_bytes ? c->ks.mf_bytes(0) : 0, mft = c->ks.mf_bytes ? c->ks.mf_bytes(1) : 0;
+  const size_t mfc = c->ks.mf_bytes ? c->ks.mf_bytes(2) : 0;
   if (mfs) {
     const size_t a = ((size_t)c->ne * mfs + 255) & ~(size_t)255;
-    if (hipMalloc(&c->mf_mem, a + (size_t)c->ne * mft) != hipSuccess) {
+    const size_t t = ((size_t)c->ne * mft + 255) & ~(size_t)255;
+    if (hipMalloc(&c->mf_mem, a + t + (size_t)c->ne * mfc) != hipSuccess) {
       release(c);
       return fail(nullptr, FR_E_NOMEM, "device allocation failed (Jacobian workspaces)");
     }
     c->mf_sens = c->mf_mem;
     c->mf_tab = (char*)c->mf_mem + a;
+    c->mf_scr = mfc ? (char*)c->mf_mem + a + t : nullptr;
     if (c->ks.mf_setup(c) != 0) {
       std::string e = c->err;
       release(c);

@@ -14,7 +14,7 @@ struct KernelSet {
   int (*rhs)(fr_ctx_s*, const void* U, void* R);
   int (*jvp)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
   int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec, int nblk);
-  size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: 1-block sensitivities, 1: tables)
+  size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: sensitivities, 1: tables, 2: scratch)
   int (*mf_setup)(fr_ctx_s*);          // computes the geometry-only sensitivities
 };
 
@@ -39,6 +39,7 @@ struct fr_ctx_s {
   void* UF64 = nullptr; void* Q64 = nullptr; void* QF64 = nullptr;  // FP64 residual
   void* UFd = nullptr; void* Qd = nullptr; void* QFd = nullptr;
   void* mf_mem = nullptr; void* mf_sens = nullptr; void* mf_tab = nullptr;   // matrix-core Jacobian
+  void* mf_scr = nullptr;                                                     // its table-build scratch (3-D)
   // optional timing of the dominant kernels with HIP events on the context stream
   static constexpr int kEvPool = 64;
   bool timing = false;

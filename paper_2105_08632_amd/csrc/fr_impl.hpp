@@ -56,26 +56,39 @@ __global__ void __launch_bounds__(kThreads) k_jac_mf_sens(OpsD<R> op, Ops1D<R> o
 }
 template <class E, int NV, int SYS, class R>
 __global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, const R* U, const R* Q, const R* UF,
-                                                         const R* QF, R* out) {
+                                                         const R* QF, R* out, R* gscratch) {
   __shared__ __align__(16) char lds[jac_mf_tables_lds<E, NV, SYS, R>()];
-  jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out);
+  jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out, gscratch);
 }
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>())) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
                                                                                 const R* tab, const R* sens, int nsb,
                                                                                 int nblk, long ntasks, OT* B) {
   typedef MfSizes<E, NV, SYS> Y;
-  constexpr int TILES = Y::MT * Y::NT, WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
+  constexpr int WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
   __shared__ __align__(16) R stage[WPB * STG];
   const int wave = threadIdx.x >> 6;
   const long task = (long)blockIdx.x * WPB + wave;
   const bool active = task < ntasks;        // every wave reaches the barrier inside the task
   const long t = active ? task : 0;
-  const int tile = (int)(t % TILES);
-  const int k = (int)((t / TILES) % nblk);
-  const int n = (int)(t / ((long)TILES * nblk));
-  jac_mf_task<E, NV, SYS, R, OT>(n, k, tile, threadIdx.x & 63, o1, rdet, tab, sens, nsb, nblk, B, stage + wave * STG,
-                                 active);
+  const int sub = (int)(t % Y::TASKS);
+  const int k = (int)((t / Y::TASKS) % nblk);
+  const int n = (int)(t / ((long)Y::TASKS * nblk));
+  const int slab = sub % Y::SL, nt = (sub / Y::SL) % Y::NT, mt = sub / (Y::SL * Y::NT);
+  R* stg = stage + wave * STG;
+  const int lane = threadIdx.x & 63;
+  // slab is uniform across the workgroup only per wave: every case reaches
+  // exactly one barrier, so a workgroup's waves may take different cases
+  switch (slab) {
+#define FR_SLAB_CASE(z)                                                                                          \
+  case z:                                                                                                        \
+    if constexpr (z < Y::SL)                                                                                     \
+      jac_mf_task<E, NV, SYS, R, OT, z>(n, k, mt, nt, lane, o1, rdet, tab, sens, nsb, nblk, B, stg, active);     \
+    break;
+    FR_SLAB_CASE(0) FR_SLAB_CASE(1) FR_SLAB_CASE(2) FR_SLAB_CASE(3) FR_SLAB_CASE(4)
+#undef FR_SLAB_CASE
+    default: break;
+  }
 }
 
 template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);
@@ -126,18 +139,22 @@ template <int ET, int P, int SYS, class R> struct Impl {
                                        (double*)c->QF64, (R*)Rout, (R*)nullptr);
   }
 
+  // The JVP too: one FP64 dual-number evaluation (the tangent of a
+  // low-Mach flux divergence cancels like the divergence itself).
   static int jvp(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
-    return residual<Dual<R>, R, R>(c, (const R*)U, (const R*)V, (Dual<R>*)c->UFd, (Dual<R>*)c->Qd,
-                                   (Dual<R>*)c->QFd, (R*)Rv, (R*)Jv);
+    return residual<Dual<double>, double, R>(c, (const R*)U, (const R*)V, (Dual<double>*)c->UFd,
+                                             (Dual<double>*)c->Qd, (Dual<double>*)c->QFd, (R*)Rv, (R*)Jv);
   }
 
   static constexpr bool kTensorPath = (ET != ET_TRI) && (jac_tp_lds<E, NV, SYS, R>() <= kMaxLds);
-  // matrix-core path: FP32 quadrilaterals (one accumulator tile per solution point)
-  static constexpr bool kMfmaPath = (ET == ET_QUAD) && std::is_same<R, float>::value;
+  // matrix-core path: FP32 quadrilaterals and hexahedra
+  static constexpr bool kMfmaPath = (ET != ET_TRI) && std::is_same<R, float>::value &&
+                                    jac_mf_sens_lds<E, NV, SYS, R>() <= kMaxLds &&
+                                    jac_mf_tables_lds<E, NV, SYS, R>() <= kMaxLds;
   typedef MfSizes<E, NV, SYS> MF;
 
   template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B, int nblk) {
-    if constexpr (!kTensorPath && jac_lds<E, NV, SYS, R>() > kMaxLds) {
+    if constexpr (!kMfmaPath && !kTensorPath && jac_lds<E, NV, SYS, R>() > kMaxLds) {
       c->err = "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
       return -2;
     } else {
@@ -160,9 +177,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
       if (!c->mf_sens || !c->mf_tab) { c->err = "Jacobian workspace missing"; return -4; }
       if (c->timing) fr_time_begin(c, 0);     // tables + assembly
       hipLaunchKernelGGL((k_jac_mf_tab<E, NV, SYS, R>), dim3(ne), dim3(kThreads), 0, c->stream, geo, c->ph, U,
-                         (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab);
+                         (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab, (R*)c->mf_scr);
       FR_LAUNCH_CHECK(c);
-      const long ntasks = (long)ne * nblk * MF::MT * MF::NT;
+      const long ntasks = (long)ne * nblk * MF::TASKS;
       constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
       hipLaunchKernelGGL((k_jac_mf_asm<E, NV, SYS, R, OT>), dim3((unsigned)((ntasks + per - 1) / per)), dim3(64 * per),
                          0, c->stream, ctx_o1<R>(c), geo.rdet, (const R*)c->mf_tab, (const R*)c->mf_sens,
@@ -170,7 +187,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
       FR_LAUNCH_CHECK(c);
       if (c->timing) fr_time_end(c, 0);
       return 0;
-    }
+    } else {
     if (c->timing) fr_time_begin(c, 0);
     if constexpr (kTensorPath)
       hipLaunchKernelGGL((k_jac_tp<E, NV, SYS, R, OT>), dim3(ne), dim3(jac_tp_threads<E, NV, SYS, R>()), 0, c->stream,
@@ -182,6 +199,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
     FR_LAUNCH_CHECK(c);
     if (c->timing) fr_time_end(c, 0);
     return 0;
+    }
     }
   }
 
@@ -198,8 +216,12 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   // bytes per element of the matrix-core path's sensitivity and table arrays (0: not used)
+  // which: 0 sensitivities, 1 tables, 2 table-build scratch
   static size_t mf_bytes(int which) {
-    if constexpr (kMfmaPath) return which == 0 ? (size_t)(1 + E::NFACE) * MF::BLK * sizeof(R) : (size_t)MF::TAB * sizeof(R);
+    if constexpr (kMfmaPath)
+      return which == 0 ? (size_t)(1 + E::NFACE) * MF::BLK * sizeof(R)
+                        : (which == 1 ? (size_t)MF::TAB * sizeof(R)
+                                      : (size_t)jac_mf_gscratch<E, NV, SYS, R>() * sizeof(R));
     else return 0;
   }
   static int mf_setup(fr_ctx_s* c) {

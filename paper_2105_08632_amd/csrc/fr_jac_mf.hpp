@@ -39,6 +39,25 @@ template <class E, int NV, int SYS> struct MfSizes {
   static constexpr int SSZ = NF * JF * NP;          // per block: S
   static constexpr int BLK = GSZ + SSZ;             // sensitivities of one block
   static constexpr int TAB = TBT + TFT;             // tables of one element
+  // Pair rows: a tile of 16 rows owns whole columns (every alpha of its
+  // betas).  NV <= 4: m = alpha NV + beta, one tile; NV = 5: three betas per
+  // tile, m = 16 (beta / 3) + 5 (beta % 3) + alpha.
+  static constexpr int BT = NV <= 4 ? NV : 3;       // betas per pair tile
+  static constexpr FR_HD int pidx(int a, int b) { return NV <= 4 ? a * NV + b : (b / 3) * 16 + (b % 3) * 5 + a; }
+  static constexpr FR_HD bool pair(int m, int& a, int& b) {
+    if (NV <= 4) { a = m / NV; b = m % NV; return m < NV2; }
+    const int t = m / 16, l = m % 16;
+    a = l % 5; b = 3 * t + l / 5;
+    return l < 15 && b < NV;
+  }
+  // solution-point slabs of a task: hexahedra split along the third
+  // coordinate (one accumulator tile per point of the slab)
+  static constexpr int N1 = E::DEG + 1;
+  static constexpr int SL = ND == 3 ? N1 : 1, SLS = NS / SL;
+  static constexpr int TASKS = MT * NT * SL;       // tasks per (element, block)
+  static constexpr int NR = SLS * NV;               // rows of a task's column segment
+  // table-build scratch in global memory where it does not fit beside the rest
+  static constexpr bool kGlobalScratch = ND == 3;
 };
 
 template <class R> struct Mfma;
@@ -60,7 +79,10 @@ template <> struct Mfma<double> {
 
 
 // assembly tasks per workgroup and the LDS staging of one task's tile
-template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() { return 16 * NV * (E::NS * NV + 1); }
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() {
+  typedef MfSizes<E, NV, SYS> Y;
+  return 16 * Y::BT * (Y::NR + 1);
+}
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
   return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
 }
@@ -71,14 +93,19 @@ template <class E, int NV, int SYS, class R> constexpr int jac_mf_sens_lds() {
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NFACE = Z::NFACE, NFP = Z::NFP;
   return lds_bytes<R>(NF * NS) + lds_bytes<R>(NS * NF) + lds_bytes<R>(NS * ND * ND) + lds_bytes<int>(NF) +
          lds_bytes<R>(NFACE * NS * ND * ND) + 2 * lds_bytes<int>(NFACE) + lds_bytes<R>(NFACE * NFP * ND) +
-         lds_bytes<Ops1D<R>>(1) + lds_bytes<R>((1 + NFACE) * Y::GSZ);
+         lds_bytes<Ops1D<R>>(1) + (ND == 3 ? 0 : lds_bytes<R>((1 + NFACE) * Y::GSZ));
 }
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_tables_lds() {
   typedef TPSizes<E, NV, SYS> Z;
+  typedef MfSizes<E, NV, SYS> Y;
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND;
   return lds_bytes<R>(NS * NV) + lds_bytes<R>(NS * ND * NV) + 2 * lds_bytes<R>(NF * NV) +
          2 * lds_bytes<R>(NF * ND * NV) + 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) +
-         lds_bytes<int>(NF) + jac_tp_scratch<E, NV, SYS, R>();
+         lds_bytes<int>(NF) + (Y::kGlobalScratch ? 0 : jac_tp_scratch<E, NV, SYS, R>());
+}
+// table-build scratch per element when it lives in global memory (floats of R)
+template <class E, int NV, int SYS, class R> constexpr long jac_mf_gscratch() {
+  return MfSizes<E, NV, SYS>::kGlobalScratch ? (long)jac_tp_scratch<E, NV, SYS, R>() / (long)sizeof(R) + 64 : 0;
 }
 
 // Sensitivities of element n for all blocks (geometry only):
@@ -105,9 +132,12 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
   int* snf = L.take<int>(NFACE);
   R* sW = L.take<R>(NFACE * NFP * ND);
   Ops1D<R>* sO1 = L.take<Ops1D<R>>(1);
-  R* gamT = L.take<R>((1 + NFACE) * Y::GSZ);
   const long nl = n;
   R* gout = out + nl * nblk * BLK;
+  // G of every block: in LDS where it fits, else read back from the output
+  // (same workgroup, after a barrier)
+  R* gamT = ND == 3 ? gout : L.take<R>((1 + NFACE) * Y::GSZ);
+  constexpr int GST = ND == 3 ? BLK : Y::GSZ;
   for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
   for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
   for (int i = tid; i < NF; i += nth) spg[i] = geo.nbfp[nl * NF + i];
@@ -168,7 +198,7 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
           }
         }
       }
-      gamT[kk * Y::GSZ + (t * KV + e) * NP + s] = v;
+      if (ND != 3) gamT[kk * Y::GSZ + (t * KV + e) * NP + s] = v;
       gout[kk * BLK + (t * KV + e) * NP + s] = v;
     }
     sync();
@@ -193,7 +223,7 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
             const int t = X::fline(g, w);
             R acc = R(0);
             for (int e = 0; e < ND; ++e)
-              acc += sJi[(t * ND + e) * ND + d2] * gamT[kk * Y::GSZ + (t * KV + e) * NP + s];
+              acc += sJi[(t * ND + e) * ND + d2] * gamT[kk * GST + (t * KV + e) * NP + s];
             sl += sM0[g * NS + t] * acc;
           }
           if (k == 0) {
@@ -224,7 +254,7 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
 // out[n][T | W] (MfSizes::TAB values, operand layout).
 template <class E, int NV, int SYS, class R>
 __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const GeoD<R>& geo, const PhysP& ph,
-                                   const R* U, const R* Q, const R* UF, const R* QF, R* out) {
+                                   const R* U, const R* Q, const R* UF, const R* QF, R* out, R* gscratch) {
   typedef TPSizes<E, NV, SYS> Z;
   typedef MfSizes<E, NV, SYS> Y;
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NV2 = Z::NV2;
@@ -244,7 +274,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
   R* snn = L.take<R>(NF * ND);
   R* smg = L.take<R>(NF);
   int* spg = L.take<int>(NF);
-  Lds L1{L.p};
+  Lds L1{Y::kGlobalScratch ? reinterpret_cast<char*>(gscratch + (long)n * jac_mf_gscratch<E, NV, SYS, R>()) : L.p};
   R* bh = L1.take<R>(ND * ND * NS * NV2);
   R* rL = L1.take<R>(NF * NV2);
   R* rR = L1.take<R>(NF * NV2);
@@ -306,7 +336,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
             for (int d = 0; d < ND; ++d) {
               R acc = R(0);
               for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d;
-              tbT[((t * ND + d) * KV + ND) * MP + a * NV + c] = acc;
+              tbT[((t * ND + d) * KV + ND) * MP + Y::pidx(a, c)] = acc;
             }
         } else {
           flux_viscous<SYS, ND, NV, DT>(ph, u, q, f);
@@ -353,7 +383,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
     if (!visc)
       for (int i = tid; i < NV2 * NS * ND; i += nth) {
         const int ab = i / (NS * ND), r = i % (NS * ND);
-        for (int e = 0; e < ND; ++e) tbT[(r * KV + e) * MP + ab] = R(0);
+        for (int e = 0; e < ND; ++e) tbT[(r * KV + e) * MP + Y::pidx(ab / NV, ab % NV)] = R(0);
       }
     if (visc)
       for (int i = tid; i < NV2 * NS * ND * ND; i += nth) {
@@ -363,14 +393,14 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
           R s = sS[(t * ND + d) * ND + k];
           for (int d2 = 0; d2 < ND; ++d2) acc += s * bh[((d2 * ND + k) * NS + t) * NV2 + ab] * sJi[(t * ND + e) * ND + d2];
         }
-        tbT[((t * ND + d) * KV + e) * MP + ab] = acc;
+        tbT[((t * ND + d) * KV + e) * MP + Y::pidx(ab / NV, ab % NV)] = acc;
       }
     for (int i = tid; i < NV2 * NF; i += nth) {
       int ab = i / NF, g = i % NF;
       int a = ab / NV, c = ab % NV;
       R mg = smg[g];
       R id = (a == c) ? eta : R(0);
-      R* o = tfT + g * JF * MP + ab;
+      R* o = tfT + g * JF * MP + Y::pidx(a, c);
       o[0] = mg * (rL[g * NV2 + ab] + (visc ? vL[g * NV2 + ab] + id : R(0)));
       o[MP] = mg * (rR[g * NV2 + ab] + (visc ? vR[g * NV2 + ab] - id : R(0)));
       for (int d = 0; d < ND; ++d) {
@@ -383,21 +413,35 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
 
 }
 
-// One wavefront task: block kb + kk, pair tile mt, sigma tile nt.  MFMA
-// fragments: A[m][k] from lane (m = lane % 16, k = lane / 16), B[k][n] from
-// lane (k = lane / 16, n = lane % 16); D[i][lane % 16] in accumulator r with
-// i = Mfma<R>::row(lane / 16, r) (FP32: 4 (lane / 16) + r, FP64: lane / 16 + 4 r).
-template <class E, int NV, int SYS, class R, class OT>
-__device__ __forceinline__ void jac_mf_task(int n, int k, int tile, int lane, const Ops1D<R>& o1, const R* rdet,
-                                            const R* tab, const R* sens, int nsb, int nblk, OT* B, R* stage,
-                                            bool active) {
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
+template <int B, int E, class F> __device__ __forceinline__ void mf_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    mf_for<B + 1, E>(f);
+  }
+}
+
+// Marks v as read and rewritten here (no instruction): updates of v are
+// computed before this point instead of being sunk towards their last use.
+template <class A> __device__ __forceinline__ void mf_pin(A& v) { asm volatile("" : "+v"(v)); }
+
+// One wavefront task: element n, block k, pair tile mt, sigma tile nt and
+// solution-point slab Z0 (points whose third coordinate is Z0; the whole
+// element for quadrilaterals).  MFMA fragments: A[m][k] from lane (m = lane %
+// 16, k = lane / 16), B[k][n] from lane (k = lane / 16, n = lane % 16);
+// D[i][lane % 16] in accumulator r with i = Mfma<R>::row(lane / 16, r)
+// (FP32: 4 (lane / 16) + r, FP64: lane / 16 + 4 r).
+template <class E, int NV, int SYS, class R, class OT, int Z0>
+__device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int lane, const Ops1D<R>& o1,
+                                            const R* rdet, const R* tab, const R* sens, int nsb, int nblk, OT* B,
+                                            R* stage, bool active) {
   typedef MfSizes<E, NV, SYS> Y;
   typedef TPIdx<E> X;
   typedef Mfma<R> M;
   typedef typename M::acc acc;
   constexpr int NS = Y::NS, ND = Y::ND, NF = Y::NF, NFP = E::NFP, N1 = E::DEG + 1;
   constexpr int KV = Y::KV, JF = Y::JF, JC = Y::JC, MP = Y::MP, NP = Y::NP, BB = NS * NV;
-  const int mt = tile / Y::NT, nt = tile % Y::NT;
+  constexpr int SL = Y::SL, SLS = Y::SLS, R0 = Z0 * SLS;   // the slab's points R0 .. R0 + SLS - 1
   const int li = lane & 15, kq = lane >> 4;
   const long nl = n;
   const R* tbT = tab + nl * Y::TAB;
@@ -405,103 +449,158 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int tile, int lane, co
   const R* G = sens + (nl * nsb + k) * Y::BLK;
   const R* S = G + Y::GSZ;
   const R* srd = rdet + nl * NS;
-  OT* Bn = B + nl * (long)nblk * BB * BB;
-  const int kb = k, kk = 0;
+  // the few 1-D coefficients the task uses, as scalars (indexing the
+  // by-value operator struct directly keeps a private copy of it alive)
+  R dc[N1][N1], hp[N1], hm[N1];
+  mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+    constexpr int w = decltype(W)::value;
+    hp[w] = o1.hp[w];
+    hm[w] = o1.hm[w];
+    mf_for<0, N1>([&](auto C) __attribute__((always_inline)) { dc[w][decltype(C)::value] = o1.Dc1[w][decltype(C)::value]; });
+  });
   const acc zero = {};
-  acc V[NS];
+  acc V[SLS];
 #pragma unroll
-  for (int r = 0; r < NS; ++r) V[r] = zero;
-  // Operands come straight from global memory: each phase issues the
-  // fragment loads of up to 16 points (or flux points) at once, one memory
-  // round trip per chunk, then computes; chunks bound the live registers.
+  for (int r = 0; r < SLS; ++r) V[r] = zero;
+  // which lines reach the slab (compile-time once the loops are unrolled):
+  // a line along the third axis meets it at one point, any other line lies
+  // in it or misses it
+  // Which contributions reach the slab, decided at compile time: a line
+  // along the third axis meets it at one point, any other line lies in it
+  // or misses it.  The loops run through mf_for, so every index into V and
+  // the operand arrays is a constant and they stay in registers.
+  constexpr auto in_slab = [](int r) constexpr { return SL == 1 || X::co(r, 2) == Z0; };
+  constexpr auto vol_used = [](int t, int d) constexpr { return SL == 1 || d == 2 || X::co(t, 2) == Z0; };
+  constexpr auto face_used = [](int g) constexpr {
+    bool u = SL == 1;
+    for (int w = 0; w < N1; ++w) u = u || (X::fline(g, w) / SLS == Z0);
+    return u;
+  };
+  // Operands come straight from global memory: each chunk of up to 16
+  // points (or flux points) issues its fragment loads at once (one memory
+  // round trip), then computes; chunks bound the live registers.
   constexpr int CH = 16;
   // volume: X_d[tau] scattered along the d-line through tau
-#pragma unroll
-  for (int t0 = 0; t0 < NS; t0 += CH) {
+  mf_for<0, (NS + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
+    constexpr int t0 = decltype(C)::value * CH;
     R bv[CH], av[CH][ND];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int t = t0 + i;
-      bv[i] = (t < NS && kq < KV) ? G[(t * KV + kq) * NP + nt * 16 + li] : R(0);
-#pragma unroll
-      for (int d = 0; d < ND; ++d)
-        av[i][d] = (t < NS && kq < KV) ? tbT[((t * ND + d) * KV + kq) * MP + mt * 16 + li] : R(0);
-    }
+    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+      constexpr int t = t0 + decltype(I)::value;
+      bv[decltype(I)::value] = (t < NS && kq < KV) ? G[(t * KV + kq) * NP + nt * 16 + li] : R(0);
+      mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
+        constexpr int d = decltype(D)::value;
+        if constexpr (t < NS && vol_used(t < NS ? t : 0, d))
+          av[decltype(I)::value][d] = kq < KV ? tbT[((t * ND + d) * KV + kq) * MP + mt * 16 + li] : R(0);
+      });
+    });
     fr_sched_fence();
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int t = t0 + i;
-      if (t < NS) {
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const acc x = M::mma(av[i][d], bv[i], zero);
-#pragma unroll
-          for (int w = 0; w < N1; ++w) V[X::line(t, d, w)] += o1.Dc1[w][X::co(t, d)] * x;
+    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+      constexpr int t = t0 + decltype(I)::value;
+      if constexpr (t < NS) {
+        mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
+          constexpr int d = decltype(D)::value;
+          if constexpr (vol_used(t, d)) {
+            const acc x = M::mma(av[decltype(I)::value][d], bv[decltype(I)::value], zero);
+            mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+              constexpr int w = decltype(W)::value, rho = X::line(t, d, w);
+              if constexpr (in_slab(rho)) V[rho - R0] += dc[w][X::co(t, d)] * x;
+            });
+          }
+        });
+        // finish each point's scatter before the next point's MFMAs; without
+        // the pins instruction selection sinks every update to the final
+        // store and keeps each product of the element live
+        {
+          mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
+            constexpr int d = decltype(D)::value;
+            if constexpr (vol_used(t, d))
+              mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+                constexpr int rho = X::line(t, d, decltype(W)::value);
+                if constexpr (in_slab(rho)) mf_pin(V[rho - R0]);
+              });
+          });
+          fr_sched_fence();
         }
       }
-    }
+    });
     fr_sched_fence();
-  }
+  });
   // faces: Y[g] scattered along g's normal line
-#pragma unroll
-  for (int g0 = 0; g0 < NF; g0 += CH) {
+  mf_for<0, (NF + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
+    constexpr int g0 = decltype(C)::value * CH;
     R fa[CH][JC], fb[CH][JC];
-#pragma unroll
-    for (int i = 0; i < CH; ++i)
-#pragma unroll
-      for (int ch = 0; ch < JC; ++ch) {
-        const int g = g0 + i, j = ch * 4 + kq;
-        fa[i][ch] = (g < NF && j < JF) ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
-        fb[i][ch] = (g < NF && j < JF) ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+      constexpr int g = g0 + decltype(I)::value;
+      if constexpr (g < NF && face_used(g < NF ? g : 0)) {
+        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+          constexpr int ch = decltype(CC)::value;
+          const int j = ch * 4 + kq;
+          const bool use = j < JF;
+          fa[decltype(I)::value][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
+          fb[decltype(I)::value][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+        });
       }
+    });
     fr_sched_fence();
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int g = g0 + i;
-      if (g < NF) {
+    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+      constexpr int g = g0 + decltype(I)::value;
+      if constexpr (g < NF && face_used(g < NF ? g : 0)) {
         acc y = zero;
-#pragma unroll
-        for (int ch = 0; ch < JC; ++ch) y = M::mma(fa[i][ch], fb[i][ch], y);
-        const bool pos = X::fsg(g / NFP) > 0;
-#pragma unroll
-        for (int w = 0; w < N1; ++w) V[X::fline(g, w)] += (pos ? o1.hp[w] : o1.hm[w]) * y;
+        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+          y = M::mma(fa[decltype(I)::value][decltype(CC)::value], fb[decltype(I)::value][decltype(CC)::value], y);
+        });
+        constexpr bool pos = X::fsg(g / NFP) > 0;
+        mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+          constexpr int w = decltype(W)::value, rho = X::fline(g, w);
+          if constexpr (in_slab(rho)) V[rho - R0] += (pos ? hp[w] : hm[w]) * y;
+        });
+        {
+          mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+            constexpr int rho = X::fline(g, decltype(W)::value);
+            if constexpr (in_slab(rho)) mf_pin(V[rho - R0]);
+          });
+          fr_sched_fence();
+        }
       }
-    }
+    });
     fr_sched_fence();
-  }
-  // D rows are pairs m, columns sigma; block column c = sigma NV + beta,
-  // row rho NV + alpha.  With one pair tile (NV <= 4) a task owns whole
-  // columns nt*16*NV .. (nt*16 + 16)*NV - 1 of block k, one contiguous range:
-  // the tile goes through LDS (column stride BB + 1) and leaves as
-  // consecutive 256-byte stores.
-  static_assert(Y::MT == 1, "staged stores need one pair tile");
-  constexpr int SP = BB + 1;
+  });
+  // D rows are pairs m, columns sigma.  The task owns the columns (sigma in
+  // tile nt, beta in pair tile mt) of block k and, in each, the contiguous
+  // row segment (rho in the slab, every alpha): the tile goes through LDS
+  // (segment stride NR + 1) and leaves as contiguous (16-byte) stores.
+  constexpr int NR = Y::NR, SP = NR + 1, BT = Y::BT;
+  const int b0 = mt * BT, nbt = (NV - b0) < BT ? (NV - b0) : BT;
   if (active) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = M::row(kq, r);
-      if (m < NV * NV && nt * 16 + li < NS) {
-        const int a = m / NV, b = m % NV;
-        R* col = stage + (li * NV + b) * SP + a;
+      int a, b;
+      const bool ok = Y::pair(mt * 16 + M::row(kq, r), a, b);
+      if (ok && nt * 16 + li < NS) {
+        R* col = stage + (li * nbt + (b - b0)) * SP + a;
 #pragma unroll
-        for (int rho = 0; rho < NS; ++rho) col[rho * NV] = -(srd[rho] * V[rho][r]);
+        for (int rl = 0; rl < SLS; ++rl) col[rl * NV] = -(srd[R0 + rl] * V[rl][r]);
       }
     }
   }
   __syncthreads();
   if (active) {
-    const int ncol = ((NS - nt * 16) < 16 ? (NS - nt * 16) : 16) * NV;
-    OT* dst = Bn + (long)(kb + kk) * BB * BB + (long)nt * 16 * NV * BB;
-    if constexpr (std::is_same<OT, float>::value && BB % 4 == 0) {
-      // 16-byte stores: 1 KB per instruction (dst and the tile are 4-aligned)
-      for (int i = 4 * lane; i < ncol * BB; i += 256) {
-        const int cc = i / BB, rr = i % BB;
-        const R* sp = stage + cc * SP + rr;
-        *reinterpret_cast<float4*>(dst + i) = make_float4(sp[0], sp[1], sp[2], sp[3]);
+    const int nsg = (NS - nt * 16) < 16 ? (NS - nt * 16) : 16;
+    const int ncol = nsg * nbt;
+    OT* Bk = B + (nl * nblk + k) * (long)BB * BB + (long)R0 * NV;
+    if constexpr (std::is_same<OT, float>::value && NR % 4 == 0 && BB % 4 == 0) {
+      for (int i = 4 * lane; i < ncol * NR; i += 256) {
+        const int cl = i / NR, rr = i % NR;
+        const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
+        const R* sp = stage + cl * SP + rr;
+        *reinterpret_cast<float4*>(Bk + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
       }
     } else {
-      for (int i = lane; i < ncol * BB; i += 64) dst[i] = to_out<OT>(stage[(i / BB) * SP + i % BB]);
+      for (int i = lane; i < ncol * NR; i += 64) {
+        const int cl = i / NR, rr = i % NR;
+        const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
+        Bk[(long)c * BB + rr] = to_out<OT>(stage[cl * SP + rr]);
+      }
     }
   }
 }
-

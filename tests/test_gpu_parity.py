@@ -132,6 +132,54 @@ def test_hex_ns_fp64(p):
     _assert(out, "f64", p)
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("system", ["adv", "euler", "ns"])
+def test_hex_fp32(system, p):
+    """FP32 hexahedra: the matrix-core Jacobian path (slabs of solution
+    points, split pair tiles for five variables), FP64-evaluated residual,
+    FP32 JVP."""
+    m = I.hex_mesh(4, degree=p, jitter=0.05, K=1)
+    if system == "adv":
+        ph, U = I.advection_physics((1.0, 0.5, -0.7)), I.advection_state(m, p, seed=4)
+    else:
+        ph = I.ns_physics(3, 50.0, 0.71) if system == "ns" else I.euler_physics(3)
+        U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    elems = [0, m.n_elem - 1] if (p < 3 or system == "adv") else [37]
+    out = check_case(m, ph, p, U, "f32", elems)
+    _assert(out, "f32", (system, p))
+
+
+def _sampled_blocks(ctx, Ud, elems, out_prec=None):
+    """Jacobian blocks of the whole mesh on the device, only the sampled
+    elements copied back (row-major, FP64)."""
+    B = ctx.jacobian_blocks(Ud) if out_prec is None else ctx.jacobian_blocks(Ud, out_prec=out_prec)
+    idx = torch.tensor(elems, device=B.device)
+    Bs = B.index_select(0, idx)
+    del B
+    return _blocks_rowmajor(Bs)
+
+
+def test_cfg2_full_size_fp32():
+    """3D NS, p=3, 24^3 jittered periodic hexes (13824 elements, seven
+    320x320 blocks each), FP32: R and the JVP over the whole mesh, Jacobian
+    blocks of the whole mesh checked on a seeded sample of elements."""
+    p = 3
+    m = I.hex_mesh(24, degree=p, jitter=0.05)
+    ph = I.ns_physics(3, 1600.0, 0.71)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    elems = [int(np.random.default_rng(0).integers(m.n_elem)), m.n_elem - 1]
+    out = check_case(m, ph, p, U, "f32", elems, blocks=False)
+    from paper_2105_08632_amd import fr
+    ctx = fr.Context(m, ph, "f32")
+    Ud = _dev(U, "f32")
+    Uq = Ud.double().cpu().numpy()
+    Bn = _sampled_blocks(ctx, Ud, elems)
+    torch.cuda.synchronize()
+    Bo = O.Oracle(m, ph, p).jac_blocks(Uq, elems, ctx.b, ctx.nface)
+    out["blocks"] = max(rel(Bn[i], Bo[i]) for i in range(len(elems)))
+    _assert(out, "f32")
+
+
 def test_cfg1_full_size_fp32():
     """2D NS, p=3, 128x128 jittered periodic quads, FP32: R and the JVP over
     the whole mesh, Jacobian blocks on a seeded sample of elements."""
@@ -156,6 +204,20 @@ def test_bf16_blocks():
     err = max(rel(B[e], Bo[i]) for i, e in enumerate([0, 20]))
     assert err <= 2e-2
     assert err > 1e-6     # really stored in bf16
+
+
+def test_hex_bf16_blocks():
+    """BF16 blocks of the 3D NS p=3 Jacobian (the cfg2 block size, 320)."""
+    p = 3
+    m = I.hex_mesh(4, degree=p, jitter=0.05, K=1)
+    ph = I.ns_physics(3, 50.0, 0.71)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    Ud = _dev(U, "f32")
+    ctx = _ctx(m, ph, "f32")
+    B = _sampled_blocks(ctx, Ud, [21], out_prec="bf16")
+    Bo = O.Oracle(m, ph, p).jac_blocks(Ud.double().cpu().numpy(), [21], ctx.b, ctx.nface)
+    err = rel(B[0], Bo[0])
+    assert 1e-6 < err <= 2e-2
 
 
 def test_errors_are_reported():
