@@ -27,9 +27,16 @@ def _sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
+# Element-kernel instantiations: MFMA accumulators in ordinary VGPRs (the
+# Jacobian assembly updates them with vector FMAs between MFMAs; the
+# accumulation-register form would copy every product out).
+ELEM_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    extra = ELEM_FLAGS if os.path.basename(src).startswith("inst_") else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

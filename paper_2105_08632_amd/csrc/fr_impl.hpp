@@ -68,7 +68,12 @@ __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>())) k_jac_mf_a
   constexpr int WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
   __shared__ __align__(16) R stage[WPB * STG];
   const int wave = threadIdx.x >> 6;
-  const long task = (long)blockIdx.x * WPB + wave;
+  // Workgroups are dealt to the 8 XCDs in turn; renumber them so that each
+  // XCD runs a contiguous range of tasks: the tasks of one (element, block)
+  // and the blocks of one element then share that XCD's L2.
+  const unsigned nwg = gridDim.x, q = nwg / 8u, rm = nwg % 8u, x = blockIdx.x % 8u, j = blockIdx.x / 8u;
+  const unsigned wg = x < rm ? x * (q + 1u) + j : rm * (q + 1u) + (x - rm) * q + j;
+  const long task = (long)wg * WPB + wave;
   const bool active = task < ntasks;        // every wave reaches the barrier inside the task
   const long t = active ? task : 0;
   const int sub = (int)(t % Y::TASKS);
@@ -77,18 +82,7 @@ __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>())) k_jac_mf_a
   const int slab = sub % Y::SL, nt = (sub / Y::SL) % Y::NT, mt = sub / (Y::SL * Y::NT);
   R* stg = stage + wave * STG;
   const int lane = threadIdx.x & 63;
-  // slab is uniform across the workgroup only per wave: every case reaches
-  // exactly one barrier, so a workgroup's waves may take different cases
-  switch (slab) {
-#define FR_SLAB_CASE(z)                                                                                          \
-  case z:                                                                                                        \
-    if constexpr (z < Y::SL)                                                                                     \
-      jac_mf_task<E, NV, SYS, R, OT, z>(n, k, mt, nt, lane, o1, rdet, tab, sens, nsb, nblk, B, stg, active);     \
-    break;
-    FR_SLAB_CASE(0) FR_SLAB_CASE(1) FR_SLAB_CASE(2) FR_SLAB_CASE(3) FR_SLAB_CASE(4)
-#undef FR_SLAB_CASE
-    default: break;
-  }
+  jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, nsb, nblk, B, stg, active);
 }
 
 template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);

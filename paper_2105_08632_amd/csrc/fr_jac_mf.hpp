@@ -56,6 +56,9 @@ template <class E, int NV, int SYS> struct MfSizes {
   static constexpr int SL = ND == 3 ? N1 : 1, SLS = NS / SL;
   static constexpr int TASKS = MT * NT * SL;       // tasks per (element, block)
   static constexpr int NR = SLS * NV;               // rows of a task's column segment
+  // staged in NH passes of NRH rows (two where the halves stay whole points
+  // and 16-byte multiples: half the LDS, more resident waves)
+  static constexpr int NH = (SLS % 2 == 0 && (SLS / 2 * NV) % 4 == 0 && NR >= 32) ? 2 : 1, NRH = NR / NH;
   // table-build scratch in global memory where it does not fit beside the rest
   static constexpr bool kGlobalScratch = ND == 3;
 };
@@ -81,7 +84,7 @@ template <> struct Mfma<double> {
 // assembly tasks per workgroup and the LDS staging of one task's tile
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() {
   typedef MfSizes<E, NV, SYS> Y;
-  return 16 * Y::BT * (Y::NR + 1);
+  return 16 * Y::BT * (Y::NRH + 1);
 }
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
   return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
@@ -426,13 +429,20 @@ template <int B, int E, class F> __device__ __forceinline__ void mf_for(F&& f) {
 template <class A> __device__ __forceinline__ void mf_pin(A& v) { asm volatile("" : "+v"(v)); }
 
 // One wavefront task: element n, block k, pair tile mt, sigma tile nt and
-// solution-point slab Z0 (points whose third coordinate is Z0; the whole
+// solution-point slab z0 (points whose third coordinate is z0; the whole
 // element for quadrilaterals).  MFMA fragments: A[m][k] from lane (m = lane %
 // 16, k = lane / 16), B[k][n] from lane (k = lane / 16, n = lane % 16);
 // D[i][lane % 16] in accumulator r with i = Mfma<R>::row(lane / 16, r)
 // (FP32: 4 (lane / 16) + r, FP64: lane / 16 + 4 r).
-template <class E, int NV, int SYS, class R, class OT, int Z0>
-__device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int lane, const Ops1D<R>& o1,
+//
+// The slab is a run-time (wave-uniform) value: one code path serves every
+// slab, so the unrolled task stays within the instruction cache.  Indices
+// into the accumulators are compile-time throughout: slab-relative for the
+// point sets that move with z0 (their operands are loaded at a uniform
+// run-time offset), and slab-independent for the third-axis lines, whose
+// slab-dependent weight goes into the A operand instead.
+template <class E, int NV, int SYS, class R, class OT>
+__device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0, int lane, const Ops1D<R>& o1,
                                             const R* rdet, const R* tab, const R* sens, int nsb, int nblk, OT* B,
                                             R* stage, bool active) {
   typedef MfSizes<E, NV, SYS> Y;
@@ -441,7 +451,8 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int la
   typedef typename M::acc acc;
   constexpr int NS = Y::NS, ND = Y::ND, NF = Y::NF, NFP = E::NFP, N1 = E::DEG + 1;
   constexpr int KV = Y::KV, JF = Y::JF, JC = Y::JC, MP = Y::MP, NP = Y::NP, BB = NS * NV;
-  constexpr int SL = Y::SL, SLS = Y::SLS, R0 = Z0 * SLS;   // the slab's points R0 .. R0 + SLS - 1
+  constexpr int SLS = Y::SLS;
+  const int R0 = z0 * SLS;                 // the slab's points R0 .. R0 + SLS - 1
   const int li = lane & 15, kq = lane >> 4;
   const long nl = n;
   const R* tbT = tab + nl * Y::TAB;
@@ -462,145 +473,224 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int la
   acc V[SLS];
 #pragma unroll
   for (int r = 0; r < SLS; ++r) V[r] = zero;
-  // which lines reach the slab (compile-time once the loops are unrolled):
-  // a line along the third axis meets it at one point, any other line lies
-  // in it or misses it
-  // Which contributions reach the slab, decided at compile time: a line
-  // along the third axis meets it at one point, any other line lies in it
-  // or misses it.  The loops run through mf_for, so every index into V and
-  // the operand arrays is a constant and they stay in registers.
-  constexpr auto in_slab = [](int r) constexpr { return SL == 1 || X::co(r, 2) == Z0; };
-  constexpr auto vol_used = [](int t, int d) constexpr { return SL == 1 || d == 2 || X::co(t, 2) == Z0; };
-  constexpr auto face_used = [](int g) constexpr {
-    bool u = SL == 1;
-    for (int w = 0; w < N1; ++w) u = u || (X::fline(g, w) / SLS == Z0);
-    return u;
-  };
+  // lane offsets of the A (pair) and B (sigma) fragments
+  const int ao = kq * MP + mt * 16 + li, bo = kq * NP + nt * 16 + li;
+  const bool kin = kq < KV;
   // Operands come straight from global memory: each chunk of up to 16
   // points (or flux points) issues its fragment loads at once (one memory
-  // round trip), then computes; chunks bound the live registers.
+  // round trip), then computes; chunks bound the live registers.  After each
+  // point the updated accumulators are pinned: without that, instruction
+  // selection sinks every update to the final store and keeps each product
+  // of the task live.
   constexpr int CH = 16;
-  // volume: X_d[tau] scattered along the d-line through tau
-  mf_for<0, (NS + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
+  constexpr int NDS = ND == 3 ? 2 : ND;    // directions whose lines lie in the slab
+  // volume, in-slab directions: X_d[tau] (tau in the slab) scattered along
+  // the d-line through tau
+  mf_for<0, (SLS + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
     constexpr int t0 = decltype(C)::value * CH;
-    R bv[CH], av[CH][ND];
+    R bv[CH], av[CH][NDS];
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int t = t0 + decltype(I)::value;
-      bv[decltype(I)::value] = (t < NS && kq < KV) ? G[(t * KV + kq) * NP + nt * 16 + li] : R(0);
-      mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
-        constexpr int d = decltype(D)::value;
-        if constexpr (t < NS && vol_used(t < NS ? t : 0, d))
-          av[decltype(I)::value][d] = kq < KV ? tbT[((t * ND + d) * KV + kq) * MP + mt * 16 + li] : R(0);
-      });
+      constexpr int i = decltype(I)::value, tl = t0 + i;
+      if constexpr (tl < SLS) {
+        const int t = R0 + tl;
+        bv[i] = kin ? G[t * KV * NP + bo] : R(0);
+        mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
+          constexpr int d = decltype(D)::value;
+          av[i][d] = kin ? tbT[(t * ND + d) * KV * MP + ao] : R(0);
+        });
+      }
     });
     fr_sched_fence();
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int t = t0 + decltype(I)::value;
-      if constexpr (t < NS) {
-        mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
+      constexpr int i = decltype(I)::value, tl = t0 + i;
+      if constexpr (tl < SLS) {
+        mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
           constexpr int d = decltype(D)::value;
-          if constexpr (vol_used(t, d)) {
-            const acc x = M::mma(av[decltype(I)::value][d], bv[decltype(I)::value], zero);
-            mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
-              constexpr int w = decltype(W)::value, rho = X::line(t, d, w);
-              if constexpr (in_slab(rho)) V[rho - R0] += dc[w][X::co(t, d)] * x;
-            });
-          }
-        });
-        // finish each point's scatter before the next point's MFMAs; without
-        // the pins instruction selection sinks every update to the final
-        // store and keeps each product of the element live
-        {
-          mf_for<0, ND>([&](auto D) __attribute__((always_inline)) {
-            constexpr int d = decltype(D)::value;
-            if constexpr (vol_used(t, d))
-              mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
-                constexpr int rho = X::line(t, d, decltype(W)::value);
-                if constexpr (in_slab(rho)) mf_pin(V[rho - R0]);
-              });
+          const acc x = M::mma(av[i][d], bv[i], zero);
+          mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
+            constexpr int w = decltype(W)::value, rho = X::line(tl, d, w);
+            V[rho] += dc[w][X::co(tl, d)] * x;
           });
-          fr_sched_fence();
-        }
+          mf_for<0, N1>([&](auto W) __attribute__((always_inline)) { mf_pin(V[X::line(tl, d, decltype(W)::value)]); });
+        });
+        fr_sched_fence();
       }
     });
     fr_sched_fence();
   });
-  // faces: Y[g] scattered along g's normal line
-  mf_for<0, (NF + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
+  if constexpr (ND == 3) {
+    // volume, third direction: every point tau = (x, y, c) reaches the slab
+    // at (x, y, z0) with weight Dc1[z0][c], folded into A so that the MFMA
+    // accumulates in place
+    R wz[N1];
+    mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+      constexpr int c = decltype(Cc)::value;
+      wz[c] = dc[0][c];
+      mf_for<1, N1>([&](auto Z) __attribute__((always_inline)) {
+        if (z0 == decltype(Z)::value) wz[c] = dc[decltype(Z)::value][c];
+      });
+    });
+    mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+      constexpr int c = decltype(Cc)::value;
+      static_assert(SLS <= CH, "one chunk per level of the third coordinate");
+      R bv[SLS], av[SLS];
+      mf_for<0, SLS>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i = decltype(I)::value, t = c * SLS + i;
+        bv[i] = kin ? G[t * KV * NP + bo] : R(0);
+        av[i] = kin ? tbT[(t * ND + 2) * KV * MP + ao] : R(0);
+      });
+      fr_sched_fence();
+      mf_for<0, SLS>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i = decltype(I)::value;
+        V[i] = M::mma(wz[c] * av[i], bv[i], V[i]);
+      });
+      fr_sched_fence();
+    });
+  }
+  // faces whose normal lines lie in the slab: Y[g] scattered along g's
+  // normal line (quadrilaterals: every face; hexahedra: the first- and
+  // second-axis faces, flux points (ta, z0) of each)
+  constexpr int FPS = ND == 3 ? N1 : NFP;          // in-slab flux points per such face
+  constexpr int NFS = ND == 3 ? 4 : E::NFACE;       // such faces
+  auto face_of = [](int j) constexpr {              // j-th such face
+    if (ND == 2) return j;
+    int f = 0, seen = 0;
+    for (int q = 0; q < E::NFACE; ++q)
+      if (X::fax(q) != 2) { if (seen == j) f = q; ++seen; }
+    return f;
+  };
+  constexpr int NG = NFS * FPS;
+  mf_for<0, (NG + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
     constexpr int g0 = decltype(C)::value * CH;
     R fa[CH][JC], fb[CH][JC];
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int g = g0 + decltype(I)::value;
-      if constexpr (g < NF && face_used(g < NF ? g : 0)) {
+      constexpr int i = decltype(I)::value, gi = g0 + i;
+      if constexpr (gi < NG) {
+        constexpr int f = face_of(gi / FPS), ta = gi % FPS;
+        const int g = f * NFP + ta + (ND == 3 ? N1 * z0 : 0);
         mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
           constexpr int ch = decltype(CC)::value;
           const int j = ch * 4 + kq;
           const bool use = j < JF;
-          fa[decltype(I)::value][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
-          fb[decltype(I)::value][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+          fa[i][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
+          fb[i][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
         });
       }
     });
     fr_sched_fence();
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int g = g0 + decltype(I)::value;
-      if constexpr (g < NF && face_used(g < NF ? g : 0)) {
+      constexpr int i = decltype(I)::value, gi = g0 + i;
+      if constexpr (gi < NG) {
+        constexpr int f = face_of(gi / FPS), ta = gi % FPS, ax = X::fax(f);
+        constexpr bool pos = X::fsg(f) > 0;
         acc y = zero;
         mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          y = M::mma(fa[decltype(I)::value][decltype(CC)::value], fb[decltype(I)::value][decltype(CC)::value], y);
+          y = M::mma(fa[i][decltype(CC)::value], fb[i][decltype(CC)::value], y);
         });
-        constexpr bool pos = X::fsg(g / NFP) > 0;
+        // slab-relative target: the normal line through (ta, z0) of face f
+        auto tgt = [](int w) constexpr {
+          return ND == 2 ? X::fline(f * NFP + ta, w) : (ax == 0 ? w + N1 * ta : ta + N1 * w);
+        };
         mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
-          constexpr int w = decltype(W)::value, rho = X::fline(g, w);
-          if constexpr (in_slab(rho)) V[rho - R0] += (pos ? hp[w] : hm[w]) * y;
+          constexpr int w = decltype(W)::value;
+          V[tgt(w)] += (pos ? hp[w] : hm[w]) * y;
         });
-        {
-          mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
-            constexpr int rho = X::fline(g, decltype(W)::value);
-            if constexpr (in_slab(rho)) mf_pin(V[rho - R0]);
-          });
-          fr_sched_fence();
-        }
+        mf_for<0, N1>([&](auto W) __attribute__((always_inline)) { mf_pin(V[tgt(decltype(W)::value)]); });
+        fr_sched_fence();
       }
     });
     fr_sched_fence();
   });
+  if constexpr (ND == 3) {
+    // third-axis faces: flux point t = (x, y) of either face reaches the
+    // slab at (x, y, z0) with weight h(z0), folded into A
+    R hzp = hp[0], hzm = hm[0];
+    mf_for<1, N1>([&](auto Z) __attribute__((always_inline)) {
+      if (z0 == decltype(Z)::value) { hzp = hp[decltype(Z)::value]; hzm = hm[decltype(Z)::value]; }
+    });
+    auto zface = [](int j) constexpr {
+      int f = 0, seen = 0;
+      for (int q = 0; q < E::NFACE; ++q)
+        if (X::fax(q) == 2) { if (seen == j) f = q; ++seen; }
+      return f;
+    };
+    mf_for<0, 2>([&](auto Fi) __attribute__((always_inline)) {
+      constexpr int f = zface(decltype(Fi)::value);
+      const R hz = X::fsg(f) > 0 ? hzp : hzm;
+      static_assert(NFP <= CH, "one chunk per face");
+      R fa[NFP][JC], fb[NFP][JC];
+      mf_for<0, NFP>([&](auto I) __attribute__((always_inline)) {
+        constexpr int t = decltype(I)::value, g = f * NFP + t;
+        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+          constexpr int ch = decltype(CC)::value;
+          const int j = ch * 4 + kq;
+          const bool use = j < JF;
+          fa[t][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
+          fb[t][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+        });
+      });
+      fr_sched_fence();
+      mf_for<0, NFP>([&](auto I) __attribute__((always_inline)) {
+        constexpr int t = decltype(I)::value;
+        static_assert(X::fline(f * NFP + t, 0) % SLS == t, "third-axis flux point t lies over slab point t");
+        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+          V[t] = M::mma(hz * fa[t][decltype(CC)::value], fb[t][decltype(CC)::value], V[t]);
+        });
+      });
+      fr_sched_fence();
+    });
+  }
   // D rows are pairs m, columns sigma.  The task owns the columns (sigma in
   // tile nt, beta in pair tile mt) of block k and, in each, the contiguous
   // row segment (rho in the slab, every alpha): the tile goes through LDS
-  // (segment stride NR + 1) and leaves as contiguous (16-byte) stores.
-  constexpr int NR = Y::NR, SP = NR + 1, BT = Y::BT;
+  // (NH passes of NRH rows, stride NRH + 1) and leaves as contiguous 16-byte
+  // (FP32) or 8-byte (BF16) stores.
+  constexpr int NH = Y::NH, NRH = Y::NRH, SP = NRH + 1, BT = Y::BT, PR = SLS / NH;
   const int b0 = mt * BT, nbt = (NV - b0) < BT ? (NV - b0) : BT;
-  if (active) {
+  const int nsg = (NS - nt * 16) < 16 ? (NS - nt * 16) : 16;
+  const int ncol = nsg * nbt;
+  OT* Bk = B + (nl * nblk + k) * (long)BB * BB + (long)R0 * NV;
+  mf_for<0, NH>([&](auto H) __attribute__((always_inline)) {
+    constexpr int h = decltype(H)::value;
+    if constexpr (h > 0) __syncthreads();      // the previous pass has left the stage
+    if (active) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int a, b;
-      const bool ok = Y::pair(mt * 16 + M::row(kq, r), a, b);
-      if (ok && nt * 16 + li < NS) {
-        R* col = stage + (li * nbt + (b - b0)) * SP + a;
-#pragma unroll
-        for (int rl = 0; rl < SLS; ++rl) col[rl * NV] = -(srd[R0 + rl] * V[rl][r]);
+      for (int r = 0; r < 4; ++r) {
+        int a, b;
+        const bool ok = Y::pair(mt * 16 + M::row(kq, r), a, b);
+        if (ok && nt * 16 + li < NS) {
+          R* col = stage + (li * nbt + (b - b0)) * SP + a;
+          mf_for<0, PR>([&](auto L) __attribute__((always_inline)) {
+            constexpr int rl = h * PR + decltype(L)::value;
+            col[decltype(L)::value * NV] = -(srd[R0 + rl] * V[rl][r]);
+          });
+        }
       }
     }
-  }
-  __syncthreads();
-  if (active) {
-    const int nsg = (NS - nt * 16) < 16 ? (NS - nt * 16) : 16;
-    const int ncol = nsg * nbt;
-    OT* Bk = B + (nl * nblk + k) * (long)BB * BB + (long)R0 * NV;
-    if constexpr (std::is_same<OT, float>::value && NR % 4 == 0 && BB % 4 == 0) {
-      for (int i = 4 * lane; i < ncol * NR; i += 256) {
-        const int cl = i / NR, rr = i % NR;
-        const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
-        const R* sp = stage + cl * SP + rr;
-        *reinterpret_cast<float4*>(Bk + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
-      }
-    } else {
-      for (int i = lane; i < ncol * NR; i += 64) {
-        const int cl = i / NR, rr = i % NR;
-        const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
-        Bk[(long)c * BB + rr] = to_out<OT>(stage[cl * SP + rr]);
+    __syncthreads();
+    if (active) {
+      OT* Bh = Bk + h * NRH;
+      if constexpr (NRH % 4 == 0 && BB % 4 == 0) {
+        for (int i = 4 * lane; i < ncol * NRH; i += 256) {
+          const int cl = i / NRH, rr = i % NRH;
+          const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
+          const R* sp = stage + cl * SP + rr;
+          if constexpr (std::is_same<OT, float>::value) {
+            *reinterpret_cast<float4*>(Bh + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
+          } else {
+            const OT q[4] = {to_out<OT>(sp[0]), to_out<OT>(sp[1]), to_out<OT>(sp[2]), to_out<OT>(sp[3])};
+            uint2 w;
+            __builtin_memcpy(&w, q, sizeof(w));
+            *reinterpret_cast<uint2*>(Bh + (long)c * BB + rr) = w;
+          }
+        }
+      } else {
+        for (int i = lane; i < ncol * NRH; i += 64) {
+          const int cl = i / NRH, rr = i % NRH;
+          const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
+          Bh[(long)c * BB + rr] = to_out<OT>(stage[cl * SP + rr]);
+        }
       }
     }
-  }
+  });
 }
