@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, 
   jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out, gscratch);
 }
 template <class E, int NV, int SYS, class R, class OT>
-__global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>())) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
+__global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>()))
+__attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R>()))) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
                                                                                 const R* tab, const R* sens, int nsb,
                                                                                 int nblk, long ntasks, OT* B) {
   typedef MfSizes<E, NV, SYS> Y;

@@ -33,10 +33,20 @@ template <class E, int NV, int SYS> struct MfSizes {
   static constexpr int JC = (JF + 3) / 4;           // K chunks of the face product
   static constexpr int MT = (NV2 + 15) / 16, MP = 16 * MT;   // pair tiles
   static constexpr int NT = (NS + 15) / 16, NP = 16 * NT;    // sigma tiles
-  static constexpr int TBT = NS * ND * KV * MP;
-  static constexpr int TFT = NF * JF * MP;
-  static constexpr int GSZ = NS * KV * NP;          // per block: G
-  static constexpr int SSZ = NF * JF * NP;          // per block: S
+  static constexpr int NS4 = (NS + 3) / 4 * 4, NF4 = (NF + 3) / 4 * 4;   // padded to groups of four
+  static constexpr int TBT = NS4 * ND * KV * MP;
+  static constexpr int TFT = NF4 * JF * MP;
+  static constexpr int GSZ = NS4 * KV * NP;         // per block: G
+  static constexpr int SSZ = NF4 * JF * NP;         // per block: S
+  // Operand layouts: the fragment element of four consecutive points (flux
+  // points) is contiguous, so a lane fetches four MFMA operands with one
+  // 16-byte load.  G[t][e][sigma], S[g][j][sigma], T[t][d][e][m], W[g][j][m]:
+  static constexpr FR_HD int gi(int t, int e, int sg) { return ((t >> 2) * KV + e) * NP * 4 + sg * 4 + (t & 3); }
+  static constexpr FR_HD int si(int g, int j, int sg) { return ((g >> 2) * JF + j) * NP * 4 + sg * 4 + (g & 3); }
+  static constexpr FR_HD int ti(int t, int d, int e, int m) {
+    return (((t >> 2) * ND + d) * KV + e) * MP * 4 + m * 4 + (t & 3);
+  }
+  static constexpr FR_HD int fi(int g, int j, int m) { return ((g >> 2) * JF + j) * MP * 4 + m * 4 + (g & 3); }
   static constexpr int BLK = GSZ + SSZ;             // sensitivities of one block
   static constexpr int TAB = TBT + TFT;             // tables of one element
   // Pair rows: a tile of 16 rows owns whole columns (every alpha of its
@@ -85,6 +95,12 @@ template <> struct Mfma<double> {
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() {
   typedef MfSizes<E, NV, SYS> Y;
   return 16 * Y::BT * (Y::NRH + 1);
+}
+// Resident waves per SIMD the register allocation aims for: hexahedra of
+// degree 3 sit just above the three-wave limit without the hint and reach
+// it without spilling; elsewhere the hint would only force spills.
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_min_waves() {
+  return (E::ND == 3 && E::DEG == 3) ? 3 : 1;
 }
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
   return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
@@ -202,7 +218,7 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
         }
       }
       if (ND != 3) gamT[kk * Y::GSZ + (t * KV + e) * NP + s] = v;
-      gout[kk * BLK + (t * KV + e) * NP + s] = v;
+      gout[kk * BLK + Y::gi(t, e, s)] = v;
     }
     sync();
     // S_j[g][sigma]: DL, DR (face values), SL_d', SR_d' (own / neighbour
@@ -210,15 +226,15 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
     for (int i = tid; i < nbk * NF * NP; i += nth) {
       const int kk = i / (NF * NP), g = (i / NP) % NF, s = i % NP;
       const int k = kb + kk;
-      R* o = gout + kk * BLK + Y::GSZ + g * JF * NP + s;
+      R* o = gout + kk * BLK + Y::GSZ;
       const int fg = g / NFP;
       R dl = R(0), dr = R(0);
       if (s < NS) {
         if (k == 0) dl = sM0[g * NS + s];
         else if (fg == k - 1) dr = sM0[(spg[g] - snb[fg] * NF) * NS + s];
       }
-      o[0] = dl;
-      o[NP] = dr;
+      o[Y::si(g, 0, s)] = dl;
+      o[Y::si(g, 1, s)] = dr;
       for (int d2 = 0; d2 < ND; ++d2) {
         R sl = R(0), sr = R(0);
         if (visc && s < NS) {
@@ -226,7 +242,8 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
             const int t = X::fline(g, w);
             R acc = R(0);
             for (int e = 0; e < ND; ++e)
-              acc += sJi[(t * ND + e) * ND + d2] * gamT[kk * GST + (t * KV + e) * NP + s];
+              acc += sJi[(t * ND + e) * ND + d2] *
+                     gamT[kk * GST + (ND == 3 ? Y::gi(t, e, s) : (t * KV + e) * NP + s)];
             sl += sM0[g * NS + t] * acc;
           }
           if (k == 0) {
@@ -246,8 +263,8 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
             }
           }
         }
-        o[(2 + d2) * NP] = sl;
-        o[(2 + ND + d2) * NP] = sr;
+        o[Y::si(g, 2 + d2, s)] = sl;
+        o[Y::si(g, 2 + ND + d2, s)] = sr;
       }
     }
     sync();
@@ -339,7 +356,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
             for (int d = 0; d < ND; ++d) {
               R acc = R(0);
               for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d;
-              tbT[((t * ND + d) * KV + ND) * MP + Y::pidx(a, c)] = acc;
+              tbT[Y::ti(t, d, ND, Y::pidx(a, c))] = acc;
             }
         } else {
           flux_viscous<SYS, ND, NV, DT>(ph, u, q, f);
@@ -386,7 +403,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
     if (!visc)
       for (int i = tid; i < NV2 * NS * ND; i += nth) {
         const int ab = i / (NS * ND), r = i % (NS * ND);
-        for (int e = 0; e < ND; ++e) tbT[(r * KV + e) * MP + Y::pidx(ab / NV, ab % NV)] = R(0);
+        for (int e = 0; e < ND; ++e) tbT[Y::ti(r / ND, r % ND, e, Y::pidx(ab / NV, ab % NV))] = R(0);
       }
     if (visc)
       for (int i = tid; i < NV2 * NS * ND * ND; i += nth) {
@@ -396,19 +413,19 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
           R s = sS[(t * ND + d) * ND + k];
           for (int d2 = 0; d2 < ND; ++d2) acc += s * bh[((d2 * ND + k) * NS + t) * NV2 + ab] * sJi[(t * ND + e) * ND + d2];
         }
-        tbT[((t * ND + d) * KV + e) * MP + Y::pidx(ab / NV, ab % NV)] = acc;
+        tbT[Y::ti(t, d, e, Y::pidx(ab / NV, ab % NV))] = acc;
       }
     for (int i = tid; i < NV2 * NF; i += nth) {
       int ab = i / NF, g = i % NF;
       int a = ab / NV, c = ab % NV;
       R mg = smg[g];
       R id = (a == c) ? eta : R(0);
-      R* o = tfT + g * JF * MP + Y::pidx(a, c);
-      o[0] = mg * (rL[g * NV2 + ab] + (visc ? vL[g * NV2 + ab] + id : R(0)));
-      o[MP] = mg * (rR[g * NV2 + ab] + (visc ? vR[g * NV2 + ab] - id : R(0)));
+      const int m = Y::pidx(a, c);
+      tfT[Y::fi(g, 0, m)] = mg * (rL[g * NV2 + ab] + (visc ? vL[g * NV2 + ab] + id : R(0)));
+      tfT[Y::fi(g, 1, m)] = mg * (rR[g * NV2 + ab] + (visc ? vR[g * NV2 + ab] - id : R(0)));
       for (int d = 0; d < ND; ++d) {
-        o[(2 + d) * MP] = visc ? mg * qLt[(d * NF + g) * NV2 + ab] : R(0);
-        o[(2 + ND + d) * MP] = visc ? mg * qRt[(d * NF + g) * NV2 + ab] : R(0);
+        tfT[Y::fi(g, 2 + d, m)] = visc ? mg * qLt[(d * NF + g) * NV2 + ab] : R(0);
+        tfT[Y::fi(g, 2 + ND + d, m)] = visc ? mg * qRt[(d * NF + g) * NV2 + ab] : R(0);
       }
     }
     sync();
@@ -422,6 +439,31 @@ template <int B, int E, class F> __device__ __forceinline__ void mf_for(F&& f) {
     f(std::integral_constant<int, B>{});
     mf_for<B + 1, E>(f);
   }
+}
+
+// Four consecutive operand values (16-byte aligned) in one load.
+template <class R> __device__ __forceinline__ void mf_ld4(const R* p, R& a, R& b, R& c, R& d) {
+  if constexpr (std::is_same<R, float>::value) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    a = v.x; b = v.y; c = v.z; d = v.w;
+  } else {
+    a = p[0]; b = p[1]; c = p[2]; d = p[3];
+  }
+}
+
+// Loads of a chunk of CNT points whose first point is congruent to B4 mod 4
+// (B4 < 0: unknown): a group of four that starts on a multiple of four and
+// lies inside the chunk is one 16-byte load (four(i) for its first point i),
+// every other point a scalar load (one(i)).
+template <int CNT, int B4, class L1, class L4> __device__ __forceinline__ void mf_chunk(L1&& one, L4&& four) {
+  mf_for<0, CNT>([&](auto I) __attribute__((always_inline)) {
+    constexpr int i = decltype(I)::value;
+    constexpr int ph = B4 < 0 ? -1 : (B4 + i) % 4;            // position in its group of four
+    constexpr bool start = ph == 0 && i + 3 < CNT;
+    constexpr bool inside = ph > 0 && i - ph >= 0 && i - ph + 3 < CNT;
+    if constexpr (start) four(I);
+    else if constexpr (!inside) one(I);
+  });
 }
 
 // Marks v as read and rewritten here (no instruction): updates of v are
@@ -474,7 +516,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
 #pragma unroll
   for (int r = 0; r < SLS; ++r) V[r] = zero;
   // lane offsets of the A (pair) and B (sigma) fragments
-  const int ao = kq * MP + mt * 16 + li, bo = kq * NP + nt * 16 + li;
+  const int mo = mt * 16 + li, so = nt * 16 + li;   // this lane's pair row and sigma column
   const bool kin = kq < KV;
   // Operands come straight from global memory: each chunk of up to 16
   // points (or flux points) issues its fragment loads at once (one memory
@@ -488,25 +530,36 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   // the d-line through tau
   mf_for<0, (SLS + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
     constexpr int t0 = decltype(C)::value * CH;
-    R bv[CH], av[CH][NDS];
-    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int i = decltype(I)::value, tl = t0 + i;
-      if constexpr (tl < SLS) {
-        const int t = R0 + tl;
-        bv[i] = kin ? G[t * KV * NP + bo] : R(0);
-        mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
-          constexpr int d = decltype(D)::value;
-          av[i][d] = kin ? tbT[(t * ND + d) * KV * MP + ao] : R(0);
+    R bv[CH], av[NDS][CH];
+    constexpr int CNT = (SLS - t0) < CH ? (SLS - t0) : CH;
+    mf_chunk<CNT, (ND == 2 || SLS % 4 == 0) ? 0 : -1>(
+        [&](auto I) __attribute__((always_inline)) {
+          constexpr int i = decltype(I)::value;
+          const int t = R0 + t0 + i;
+          bv[i] = kin ? G[Y::gi(t, kq, so)] : R(0);
+          mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
+            constexpr int d = decltype(D)::value;
+            av[d][i] = kin ? tbT[Y::ti(t, d, kq, mo)] : R(0);
+          });
+        },
+        [&](auto I) __attribute__((always_inline)) {
+          constexpr int i = decltype(I)::value;
+          const int t = R0 + t0 + i;
+          if (kin) mf_ld4(G + Y::gi(t, kq, so), bv[i], bv[i + 1], bv[i + 2], bv[i + 3]);
+          else bv[i] = bv[i + 1] = bv[i + 2] = bv[i + 3] = R(0);
+          mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
+            constexpr int d = decltype(D)::value;
+            if (kin) mf_ld4(tbT + Y::ti(t, d, kq, mo), av[d][i], av[d][i + 1], av[d][i + 2], av[d][i + 3]);
+            else av[d][i] = av[d][i + 1] = av[d][i + 2] = av[d][i + 3] = R(0);
+          });
         });
-      }
-    });
     fr_sched_fence();
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
       constexpr int i = decltype(I)::value, tl = t0 + i;
       if constexpr (tl < SLS) {
         mf_for<0, NDS>([&](auto D) __attribute__((always_inline)) {
           constexpr int d = decltype(D)::value;
-          const acc x = M::mma(av[i][d], bv[i], zero);
+          const acc x = M::mma(av[d][i], bv[i], zero);
           mf_for<0, N1>([&](auto W) __attribute__((always_inline)) {
             constexpr int w = decltype(W)::value, rho = X::line(tl, d, w);
             V[rho] += dc[w][X::co(tl, d)] * x;
@@ -534,11 +587,22 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
       constexpr int c = decltype(Cc)::value;
       static_assert(SLS <= CH, "one chunk per level of the third coordinate");
       R bv[SLS], av[SLS];
-      mf_for<0, SLS>([&](auto I) __attribute__((always_inline)) {
-        constexpr int i = decltype(I)::value, t = c * SLS + i;
-        bv[i] = kin ? G[t * KV * NP + bo] : R(0);
-        av[i] = kin ? tbT[(t * ND + 2) * KV * MP + ao] : R(0);
-      });
+      mf_chunk<SLS, (c * SLS) % 4>(
+          [&](auto I) __attribute__((always_inline)) {
+            constexpr int i = decltype(I)::value, t = c * SLS + i;
+            bv[i] = kin ? G[Y::gi(t, kq, so)] : R(0);
+            av[i] = kin ? tbT[Y::ti(t, 2, kq, mo)] : R(0);
+          },
+          [&](auto I) __attribute__((always_inline)) {
+            constexpr int i = decltype(I)::value, t = c * SLS + i;
+            if (kin) {
+              mf_ld4(G + Y::gi(t, kq, so), bv[i], bv[i + 1], bv[i + 2], bv[i + 3]);
+              mf_ld4(tbT + Y::ti(t, 2, kq, mo), av[i], av[i + 1], av[i + 2], av[i + 3]);
+            } else {
+              bv[i] = bv[i + 1] = bv[i + 2] = bv[i + 3] = R(0);
+              av[i] = av[i + 1] = av[i + 2] = av[i + 3] = R(0);
+            }
+          });
       fr_sched_fence();
       mf_for<0, SLS>([&](auto I) __attribute__((always_inline)) {
         constexpr int i = decltype(I)::value;
@@ -562,21 +626,42 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   constexpr int NG = NFS * FPS;
   mf_for<0, (NG + CH - 1) / CH>([&](auto C) __attribute__((always_inline)) {
     constexpr int g0 = decltype(C)::value * CH;
-    R fa[CH][JC], fb[CH][JC];
-    mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
-      constexpr int i = decltype(I)::value, gi = g0 + i;
-      if constexpr (gi < NG) {
-        constexpr int f = face_of(gi / FPS), ta = gi % FPS;
-        const int g = f * NFP + ta + (ND == 3 ? N1 * z0 : 0);
-        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          constexpr int ch = decltype(CC)::value;
-          const int j = ch * 4 + kq;
-          const bool use = j < JF;
-          fa[i][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
-          fb[i][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
+    R fa[JC][CH], fb[JC][CH];
+    constexpr int CNT = (NG - g0) < CH ? (NG - g0) : CH;
+    // consecutive in-slab flux points are consecutive in memory within a
+    // face: always for quadrilaterals, for hexahedra when N1 = 4 (aligned)
+    constexpr int B4 = (ND == 2) ? 0 : (FPS == 4 ? 0 : -1);
+    auto gof = [&](int gi) {
+      const int f = face_of(gi / FPS), ta = gi % FPS;
+      return f * NFP + ta + (ND == 3 ? N1 * z0 : 0);
+    };
+    mf_chunk<CNT, B4>(
+        [&](auto I) __attribute__((always_inline)) {
+          constexpr int i = decltype(I)::value;
+          const int g = gof(g0 + i);
+          mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+            constexpr int ch = decltype(CC)::value;
+            const int j = ch * 4 + kq;
+            const bool use = j < JF;
+            fa[ch][i] = use ? tfT[Y::fi(g, j, mo)] : R(0);
+            fb[ch][i] = use ? S[Y::si(g, j, so)] : R(0);
+          });
+        },
+        [&](auto I) __attribute__((always_inline)) {
+          constexpr int i = decltype(I)::value;
+          const int g = gof(g0 + i);
+          mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+            constexpr int ch = decltype(CC)::value;
+            const int j = ch * 4 + kq;
+            if (j < JF) {
+              mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][i], fa[ch][i + 1], fa[ch][i + 2], fa[ch][i + 3]);
+              mf_ld4(S + Y::si(g, j, so), fb[ch][i], fb[ch][i + 1], fb[ch][i + 2], fb[ch][i + 3]);
+            } else {
+              fa[ch][i] = fa[ch][i + 1] = fa[ch][i + 2] = fa[ch][i + 3] = R(0);
+              fb[ch][i] = fb[ch][i + 1] = fb[ch][i + 2] = fb[ch][i + 3] = R(0);
+            }
+          });
         });
-      }
-    });
     fr_sched_fence();
     mf_for<0, CH>([&](auto I) __attribute__((always_inline)) {
       constexpr int i = decltype(I)::value, gi = g0 + i;
@@ -585,7 +670,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
         constexpr bool pos = X::fsg(f) > 0;
         acc y = zero;
         mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          y = M::mma(fa[i][decltype(CC)::value], fb[i][decltype(CC)::value], y);
+          y = M::mma(fa[decltype(CC)::value][i], fb[decltype(CC)::value][i], y);
         });
         // slab-relative target: the normal line through (ta, z0) of face f
         auto tgt = [](int w) constexpr {
@@ -618,23 +703,38 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
       constexpr int f = zface(decltype(Fi)::value);
       const R hz = X::fsg(f) > 0 ? hzp : hzm;
       static_assert(NFP <= CH, "one chunk per face");
-      R fa[NFP][JC], fb[NFP][JC];
-      mf_for<0, NFP>([&](auto I) __attribute__((always_inline)) {
-        constexpr int t = decltype(I)::value, g = f * NFP + t;
-        mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          constexpr int ch = decltype(CC)::value;
-          const int j = ch * 4 + kq;
-          const bool use = j < JF;
-          fa[t][ch] = use ? tfT[(g * JF + j) * MP + mt * 16 + li] : R(0);
-          fb[t][ch] = use ? S[(g * JF + j) * NP + nt * 16 + li] : R(0);
-        });
-      });
+      R fa[JC][NFP], fb[JC][NFP];
+      mf_chunk<NFP, (f * NFP) % 4>(
+          [&](auto I) __attribute__((always_inline)) {
+            constexpr int t = decltype(I)::value, g = f * NFP + t;
+            mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+              constexpr int ch = decltype(CC)::value;
+              const int j = ch * 4 + kq;
+              const bool use = j < JF;
+              fa[ch][t] = use ? tfT[Y::fi(g, j, mo)] : R(0);
+              fb[ch][t] = use ? S[Y::si(g, j, so)] : R(0);
+            });
+          },
+          [&](auto I) __attribute__((always_inline)) {
+            constexpr int t = decltype(I)::value, g = f * NFP + t;
+            mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
+              constexpr int ch = decltype(CC)::value;
+              const int j = ch * 4 + kq;
+              if (j < JF) {
+                mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][t], fa[ch][t + 1], fa[ch][t + 2], fa[ch][t + 3]);
+                mf_ld4(S + Y::si(g, j, so), fb[ch][t], fb[ch][t + 1], fb[ch][t + 2], fb[ch][t + 3]);
+              } else {
+                fa[ch][t] = fa[ch][t + 1] = fa[ch][t + 2] = fa[ch][t + 3] = R(0);
+                fb[ch][t] = fb[ch][t + 1] = fb[ch][t + 2] = fb[ch][t + 3] = R(0);
+              }
+            });
+          });
       fr_sched_fence();
       mf_for<0, NFP>([&](auto I) __attribute__((always_inline)) {
         constexpr int t = decltype(I)::value;
         static_assert(X::fline(f * NFP + t, 0) % SLS == t, "third-axis flux point t lies over slab point t");
         mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          V[t] = M::mma(hz * fa[t][decltype(CC)::value], fb[t][decltype(CC)::value], V[t]);
+          V[t] = M::mma(hz * fa[decltype(CC)::value][t], fb[decltype(CC)::value][t], V[t]);
         });
       });
       fr_sched_fence();
