@@ -2,9 +2,11 @@
 // Newton-GMRES step.
 //
 // The preconditioner inverts the diagonal Jacobian blocks A_n = shift I +
-// scale dR_n/dU_n in FP64 (Gauss-Jordan elimination with partial pivoting,
-// one workgroup per element, the block resident in LDS) and applies the
-// explicit inverses as a batched matrix-vector product.  The Newton step
+// scale dR_n/dU_n in FP64: blocks up to 128 by Gauss-Jordan elimination with
+// partial pivoting (one workgroup per element, the block resident in LDS),
+// applied as explicit inverses in a batched matrix-vector product; larger
+// blocks by a blocked LU factorization in global memory, applied by
+// substitution.  The Newton step
 // solves U - U^n - dt R(U) = 0 with restarted, right-preconditioned GMRES
 // (classical Gram-Schmidt applied twice, Givens rotations on the host),
 // Jacobian-vector products from the exact tangent kernels, and the true
@@ -235,6 +237,245 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
   est[j] = fabs(g[j + 1]);
 }
 
+// ------------------------------------------------------------ large blocks
+// Blocks above 128 (hexahedra of degree 3: b = 320) do not fit one
+// workgroup's LDS.  They are factorized in place in global memory: blocked
+// right-looking LU with partial pivoting (panels of kLuNB columns factorized
+// in LDS; the panel's row exchanges applied to every other column; U12 by a
+// triangular solve; A22 -= L21 U12 from LDS-staged operands in 4 x 4
+// register tiles), one workgroup per element.  The preconditioner applies
+// the factors by forward and backward substitution.
+constexpr int kLuThreads = 512, kLuNB = 32, kLuMaxB = 320;
+
+// Wave-uniform lane l's value of v.
+__device__ __forceinline__ double fr_readlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// A = shift I + scale J (column-major, input type IT) factorized as P A = L U
+// (unit lower L and upper U stored over A in LU, column-major); perm[i] is
+// the row of A that P moves to row i.  bad[n] = 1 when a pivot is zero or not
+// finite.
+template <class IT>
+__global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
+                                                         double* LU, int* perm, int* bad, const int* list) {
+  constexpr int LD = kLuMaxB;                         // panel leading dimension (constant offsets)
+  __shared__ double P[kLuMaxB * kLuNB];               // panel rows k0.., column-major
+  __shared__ double Ut[(kLuMaxB - kLuNB) * kLuNB];    // U12, column c at c * kLuNB
+  __shared__ double red_v[kLuThreads / 64];
+  __shared__ int red_i[kLuThreads / 64];
+  __shared__ int s_piv[kLuMaxB];                      // row exchanged with row k at step k
+  __shared__ int s_perm[kLuMaxB];
+  __shared__ int s_bad;
+  const int n = list ? list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
+  const long bb = (long)b * b;
+  const IT* Jn = J + (long)n * jstride;
+  double* A = LU + (long)n * bb;
+  for (long i = tid; i < bb; i += kLuThreads) {
+    const int c = (int)(i / b), r = (int)(i % b);
+    A[i] = scale * (double)Jn[i] + (r == c ? shift : 0.0);
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < b; k0 += kLuNB) {
+    const int w = min(kLuNB, b - k0), m = b - k0;
+    for (int i = tid; i < m * w; i += kLuThreads) {
+      const int j = i / m, r = i % m;
+      P[j * LD + r] = A[(long)(k0 + j) * b + k0 + r];
+    }
+    __syncthreads();
+    for (int j = 0; j < w; ++j) {
+      // pivot: the largest |P[r][j]|, r >= j (lowest index on ties)
+      double best = -1.0;
+      int bi = j;
+      for (int r = j + tid; r < m; r += kLuThreads) {
+        const double v = fabs(P[j * LD + r]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) { red_v[tid >> 6] = best; red_i[tid >> 6] = bi; }
+      __syncthreads();
+      best = red_v[0];
+      int p = red_i[0];
+      for (int q = 1; q < kLuThreads / 64; ++q)
+        if (red_v[q] > best || (red_v[q] == best && red_i[q] < p)) { best = red_v[q]; p = red_i[q]; }
+      if (tid == 0) {
+        s_piv[k0 + j] = k0 + p;
+        const double pv = P[j * LD + p];
+        if (!(fabs(pv) > 0.0) || !isfinite(pv)) s_bad = 1;
+      }
+      if (p != j && tid < w) {
+        const double t = P[tid * LD + j];
+        P[tid * LD + j] = P[tid * LD + p];
+        P[tid * LD + p] = t;
+      }
+      __syncthreads();
+      const double pv = P[j * LD + j];
+      const double ip = (pv != 0.0 && isfinite(pv)) ? 1.0 / pv : 0.0;
+      for (int r = j + 1 + tid; r < m; r += kLuThreads) P[j * LD + r] *= ip;
+      __syncthreads();
+      const int mr = m - j - 1;
+      for (int i = tid; i < (w - j - 1) * mr; i += kLuThreads) {
+        const int c = j + 1 + i / mr, r = j + 1 + i % mr;
+        P[c * LD + r] -= P[j * LD + r] * P[c * LD + j];
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < m * w; i += kLuThreads) {
+      const int j = i / m, r = i % m;
+      A[(long)(k0 + j) * b + k0 + r] = P[j * LD + r];
+    }
+    // the panel's row exchanges, in order, on every other column
+    for (int c = tid; c < b - w; c += kLuThreads) {
+      double* Ac = A + (long)(c < k0 ? c : c + w) * b;
+      for (int j = 0; j < w; ++j) {
+        const int p = s_piv[k0 + j];
+        if (p != k0 + j) {
+          const double t = Ac[k0 + j];
+          Ac[k0 + j] = Ac[p];
+          Ac[p] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const int n2 = b - k0 - w;
+    if (n2 > 0) {
+      // U12 = L11^-1 A12, one column per thread (L11[r][q] = P[q LD + r]);
+      // n2 < kLuThreads, so no thread takes two columns (a loop here would
+      // let the compiler hoist all of L11 into registers)
+      static_assert(kLuMaxB - kLuNB <= kLuThreads, "one U12 column per thread");
+      if (tid < n2) {
+        const int c = tid;
+        double* Ac = A + (long)(k0 + w + c) * b + k0;
+        double x[kLuNB];
+#pragma unroll
+        for (int r = 0; r < kLuNB; ++r) x[r] = r < w ? Ac[r] : 0.0;
+        // column-oriented: x[r] -= L11[r][q] x[q] for r > q, one column of
+        // L11 at a time (the fence keeps its loads from piling up)
+#pragma unroll
+        for (int q = 0; q < kLuNB - 1; ++q) {
+          const double xq = x[q];
+          // the column's base is opaque to the optimizer and depends on x[q]:
+          // its loads wait for x[q] instead of all 496 being issued (and
+          // spilled) first
+          int qo = q * LD;
+          asm volatile("" : "+v"(qo) : "v"(xq));
+          const double* Pq = P + qo;
+#pragma unroll
+          for (int r = q + 1; r < kLuNB; ++r) x[r] -= Pq[r] * xq;
+        }
+#pragma unroll
+        for (int r = 0; r < kLuNB; ++r) x[r] = r < w ? x[r] : 0.0;
+#pragma unroll
+        for (int r = 0; r < kLuNB; ++r)
+          if (r < w) { Ac[r] = x[r]; Ut[c * kLuNB + r] = x[r]; }
+      }
+      __syncthreads();
+      // A22 -= L21 U12 in 4 x 4 register tiles (threads along rows)
+      const int nt2 = (n2 + 3) / 4;
+      for (int ti = tid; ti < nt2 * nt2; ti += kLuThreads) {
+        const int i0 = (ti % nt2) * 4, c0 = (ti / nt2) * 4;
+        double acc[4][4];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            acc[a][cc] = (i0 + a < n2 && c0 + cc < n2) ? A[(long)(k0 + w + c0 + cc) * b + k0 + w + i0 + a] : 0.0;
+        for (int q = 0; q < w; ++q) {
+          double l[4], u[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) l[a] = i0 + a < n2 ? P[q * LD + w + i0 + a] : 0.0;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) u[cc] = c0 + cc < n2 ? Ut[(c0 + cc) * kLuNB + q] : 0.0;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) acc[a][cc] -= l[a] * u[cc];
+        }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (i0 + a < n2 && c0 + cc < n2) A[(long)(k0 + w + c0 + cc) * b + k0 + w + i0 + a] = acc[a][cc];
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    // (P r)[i] = r[perm[i]]: the recorded exchanges applied to the identity
+    for (int i = 0; i < b; ++i) s_perm[i] = i;
+    for (int k = 0; k < b; ++k) {
+      const int p = s_piv[k], t = s_perm[k];
+      s_perm[k] = s_perm[p];
+      s_perm[p] = t;
+    }
+    bad[n] = s_bad;
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += kLuThreads) perm[(long)n * b + i] = s_perm[i];
+}
+
+// z_n = U_n^-1 L_n^-1 (P_n r_n): one wavefront per element, rows lane + 64 q
+// of the vector in registers, each substitution step's value broadcast from
+// the lane that owns it (columns of L and U are contiguous runs).
+template <class VT>
+__global__ void __launch_bounds__(256) k_block_lu_apply(long ne, int b, const double* LU, const int* perm, const VT* r,
+                                                        VT* z) {
+  constexpr int QM = (kLuMaxB + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= ne) return;
+  const double* A = LU + n * b * b;
+  const int* pn = perm + n * b;
+  const VT* rn = r + n * b;
+  double y[QM];
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const int row = lane + 64 * q;
+    y[q] = row < b ? (double)rn[pn[row]] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const int jend = min(64, b - 64 * q);
+    for (int jl = 0; jl < jend; ++jl) {
+      const int j = 64 * q + jl;
+      const double yj = fr_readlane(y[q], jl);
+      const double* Lc = A + (long)j * b;
+#pragma unroll
+      for (int q2 = q; q2 < QM; ++q2) {
+        const int row = lane + 64 * q2;
+        if (row > j && row < b) y[q2] -= Lc[row] * yj;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = QM - 1; q >= 0; --q) {
+    const int jend = min(64, b - 64 * q);
+    for (int jl = jend - 1; jl >= 0; --jl) {
+      const int j = 64 * q + jl;
+      const double* Uc = A + (long)j * b;
+      const double yj = fr_readlane(y[q], jl) / Uc[j];
+      if (lane == jl) y[q] = yj;
+#pragma unroll
+      for (int q2 = 0; q2 <= q; ++q2) {
+        const int row = lane + 64 * q2;
+        if (row < j) y[q2] -= Uc[row] * yj;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QM; ++q) {
+    const int row = lane + 64 * q;
+    if (row < b) z[n * b + row] = (VT)y[q];
+  }
+}
+
 // ------------------------------------------------------------ helpers
 static fr_status sfail(fr_ctx_s* c, fr_status s, const std::string& m) {
   c->err = m;
@@ -273,8 +514,16 @@ fr_status pc_invert(fr_precond_s* pc, double shift, double scale, const int* lis
     else
       hipLaunchKernelGGL((k_block_inverse<float, 128>), dim3(count), dim3(kInvThreads), 0, c->stream,
                          (const float*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
+  } else if (b <= kLuMaxB) {
+    if (!pc->perm) return sfail(c, FR_E_INVALID, "preconditioner without pivot storage");
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_block_lu<double>), dim3(count), dim3(kLuThreads), 0, c->stream, (const double*)J, bb, b,
+                         shift, scale, pc->inv, pc->perm, pc->bad, list);
+    else
+      hipLaunchKernelGGL((k_block_lu<float>), dim3(count), dim3(kLuThreads), 0, c->stream, (const float*)J, bb, b,
+                         shift, scale, pc->inv, pc->perm, pc->bad, list);
   } else {
-    return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi inverse supports blocks up to 128 x 128");
+    return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
   }
   HIPCHK(c, hipGetLastError());
   return FR_OK;
@@ -302,7 +551,14 @@ fr_status pc_lu_apply(fr_precond_s* pc, const void* r, void* z) {
   fr_ctx_s* c = pc->ctx;
   const long ne = c->ne;
   const int grid = (int)((ne + 3) / 4);
-  if (c->prec == 0)
+  if (c->b > 128) {
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_block_lu_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->perm,
+                         (const double*)r, (double*)z);
+    else
+      hipLaunchKernelGGL((k_block_lu_apply<float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->perm,
+                         (const float*)r, (float*)z);
+  } else if (c->prec == 0)
     hipLaunchKernelGGL((k_block_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv,
                        (const double*)r, (double*)z);
   else
@@ -584,18 +840,22 @@ fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
   if (!c || !out) return FR_E_INVALID;
   *out = nullptr;
   if (kind != FR_PC_BLOCK_JACOBI && kind != FR_PC_MLP) return sfail(c, FR_E_INVALID, "unknown preconditioner kind");
-  if (c->b > 128) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi inverse supports blocks up to 128 x 128");
+  if (c->b > kLuMaxB) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
+  if (kind == FR_PC_MLP && c->b > 128) return sfail(c, FR_E_UNSUPPORTED, "learned preconditioner blocks up to 128 x 128");
   fr_precond_s* pc = new fr_precond_s();
   pc->ctx = c; pc->kind = kind;
   const size_t bb = (size_t)c->b * c->b, ne = (size_t)c->ne;
   const size_t rs = c->prec == 0 ? 8 : 4;
+  const bool lu = c->b > 128;     // LU factors and row order instead of explicit inverses
   size_t off_inv = (ne * bb * rs + 255) & ~(size_t)255;
   size_t off_bad = off_inv + ((ne * bb * 8 + 255) & ~(size_t)255);
-  size_t tot = off_bad + ne * sizeof(int);
+  size_t off_perm = off_bad + ((ne * sizeof(int) + 255) & ~(size_t)255);
+  size_t tot = off_perm + (lu ? ne * (size_t)c->b * sizeof(int) : 0);
   if (hipMalloc(&pc->mem, tot) != hipSuccess) { delete pc; return sfail(c, FR_E_NOMEM, "preconditioner storage"); }
   pc->jbuf = pc->mem;
   pc->inv = (double*)((char*)pc->mem + off_inv);
   pc->bad = (int*)((char*)pc->mem + off_bad);
+  pc->perm = lu ? (int*)((char*)pc->mem + off_perm) : nullptr;
   if (hipHostMalloc((void**)&pc->bad_host, ne * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     (void)hipFree(pc->mem); delete pc; return sfail(c, FR_E_NOMEM, "pinned flags");
   }

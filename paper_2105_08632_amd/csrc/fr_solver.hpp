@@ -10,7 +10,8 @@ struct fr_precond_s {
   int kind = 0;              // fr_pc_kind
   void* mem = nullptr;
   void* jbuf = nullptr;      // diagonal blocks, context precision
-  double* inv = nullptr;     // [ne][b][b] column-major inverses (FP64)
+  double* inv = nullptr;     // [ne][b][b] column-major inverses (FP64); LU factors when b > 128
+  int* perm = nullptr;       // [ne][b] row order of the LU factors (b > 128)
   int* bad = nullptr;        // [ne] singular-pivot flags
   int* bad_host = nullptr;   // pinned copy
   bool ready = false;
