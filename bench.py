@@ -224,6 +224,66 @@ def batch_bench(torch, fr, I, reps, log):
             "tuning": table, "outputs_finite": finite}
 
 
+def hex3d_bench(torch, fr, I, reps, log):
+    """3-D Navier-Stokes FR-DG p=3 on 24^3 jittered periodic hexahedra
+    (Taylor-Green vortex, Re 1600): R(U), all seven 320 x 320 Jacobian
+    blocks per element in FP32 and BF16, and the FP64 block-Jacobi LU of the
+    diagonal blocks (setup from the state, then one application)."""
+    p, N = 3, 24
+    m = I.hex_mesh(N, degree=p, jitter=0.05)
+    ph = I.ns_physics(3, 1600.0, 0.71)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    ctx = fr.Context(m, ph, "f32")
+    Ud = torch.from_numpy(U).float().cuda().contiguous()
+    R = ctx.empty_state()
+
+    def timed(fn, n=reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {"workload": "3D Navier-Stokes FR-DG p=3, 24^3 jittered periodic hexes (Taylor-Green, Re 1600), FP32: "
+                       "R(U), 7 Jacobian blocks 320x320 per element, FP64 block-Jacobi LU",
+           "n_elem": ctx.ne, "dof": ctx.ndof, "block": ctx.b}
+    out["rhs_ms"] = round(timed(lambda: ctx.rhs(Ud, R)), 4)
+    for prec, sz in (("f32", 4), ("bf16", 2)):
+        B = ctx.block_tensor(prec)
+        ctx.set_kernel_timing(True)
+        ctx.kernel_time(0)
+        t = timed(lambda: ctx.jacobian_blocks(Ud, B, prec))
+        ctx.sync()
+        kms, kn = ctx.kernel_time(0)
+        ctx.set_kernel_timing(False)
+        ob = B.numel() * sz
+        out["jac_" + prec] = {"ms": round(t, 3), "kernel_ms": round(kms / max(kn, 1), 3), "out_GB": round(ob / 1e9, 2),
+                              "out_GB_per_s": round(ob / (t * 1e-3) / 1e9, 1)}
+        del B
+        torch.cuda.empty_cache()
+    out["dof_per_s_rhs_plus_jac_f32"] = ctx.ndof / ((out["rhs_ms"] + out["jac_f32"]["ms"]) * 1e-3)
+    rho = U[..., 0]
+    v = U[..., 1:4] / rho[..., None]
+    pr = 0.4 * (U[..., 4] - 0.5 * rho * np.sum(v * v, axis=-1))
+    dt = 5.0 / N / float(np.max(np.linalg.norm(v, axis=-1) + np.sqrt(1.4 * pr / rho)))
+    pc = fr.Precond(ctx)
+    t_setup = timed(lambda: pc.setup(Ud, 1.0, -dt), 2)
+    z = ctx.empty_state()
+    t_apply = timed(lambda: pc.apply(R, z))
+    flop = ctx.ne * (2.0 / 3.0) * ctx.b ** 3
+    out["block_lu"] = {"setup_ms": round(t_setup, 2), "apply_ms": round(t_apply, 3),
+                       "lu_gflop": round(flop / 1e9, 1), "note": "setup = diagonal blocks (FP32) + FP64 LU of each",
+                       "finite": bool(torch.isfinite(z).all())}
+    log(f"hex3d: rhs {out['rhs_ms']} ms, jac f32 {out['jac_f32']['ms']} ms, bf16 {out['jac_bf16']['ms']} ms, "
+        f"LU setup {out['block_lu']['setup_ms']} ms, apply {out['block_lu']['apply_ms']} ms")
+    pc.close()
+    return out
+
+
 def cpu_baseline(m, ph, p, U, budget_s):
     """The FP64 oracle (as is) on a bounded sample: the full-mesh residual,
     then the five Jacobian blocks of a seeded sample of elements."""
@@ -259,6 +319,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-GMRES part of the metric")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-mesh batch measurement")
+    ap.add_argument("--no-hex", action="store_true", help="skip the 3-D hexahedral measurement")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
@@ -327,12 +388,16 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-    if not args.no_batch or not args.no_newton:
+    if not args.no_batch or not args.no_newton or not args.no_hex:
         del B, R
         torch.cuda.empty_cache()
     if not args.no_batch:
         from paper_2105_08632_amd import inputs as I
         out["batch"] = batch_bench(torch, fr, I, 5, lambda s: print(s, file=sys.stderr, flush=True))
+        torch.cuda.empty_cache()
+    if not args.no_hex:
+        from paper_2105_08632_amd import inputs as I
+        out["hex3d"] = hex3d_bench(torch, fr, I, 3, lambda s: print(s, file=sys.stderr, flush=True))
         torch.cuda.empty_cache()
     if not args.no_newton:
         from paper_2105_08632_amd import inputs as I

@@ -251,13 +251,16 @@ fr_status fr_batch_rhs(fr_batch* b, const void* const* U, void* const* R);
 fr_status fr_batch_jacobian_blocks(fr_batch* b, const void* const* U, void* const* blocks);
 /* Autotuner: times, per phase, the launch strategy (one mixed launch, or
  * one launch per (type, degree) group with that group's own register and
- * LDS budget), the persistent-grid size and, per (type, degree), the tiles
- * (residual) or elements (assembly) per work item, on these arrays (reps
- * timed repetitions each), and keeps the fastest. */
+ * LDS budget, or for the Jacobian also: triangles per group, quadrilateral
+ * meshes one by one on the single-mesh matrix-core path), the
+ * persistent-grid size and, per (type, degree), the tiles (residual) or
+ * elements (assembly) per work item, on these arrays (reps timed
+ * repetitions each), and keeps the fastest. */
 fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void* const* blocks, int reps);
 /* The current table: modes[0] / modes[1] = residual / Jacobian launch
  * strategy (0: one mixed launch per phase, 1: one launch per (type, degree)
- * group), workgroups per launch (0: one per work item, scheduled by the
+ * group, 2 (Jacobian only): 1 for triangles, the matrix-core single-mesh
+ * path for quadrilaterals), workgroups per launch (0: one per work item, scheduled by the
  * hardware), and units per work item indexed by 8 * type + degree (32
  * entries each). */
 fr_status fr_batch_tuning(const fr_batch* b, int* modes, int* grid_res, int* grid_jac, int* k_res, int* k_jac);

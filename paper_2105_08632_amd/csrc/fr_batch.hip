@@ -6,10 +6,14 @@
 // gradients, divergence; or the Jacobian prelude and block assembly) is one
 // persistent launch: workgroups walk a work list of (mesh, first tile,
 // tile count) items, longest first, and switch on the mesh's (type, degree)
-// to the same kernel bodies the single-mesh path uses, so every mesh's result
-// is bitwise identical to the mesh run alone.  The grid size and the work-item
-// granularity per (type, degree) come from a table that fr_batch_tune fills by
-// timing candidates on the batch itself.
+// to the same kernel bodies the single-mesh path uses, so every mesh's
+// residual is bitwise identical to the mesh run alone.  Jacobian blocks of
+// quadrilateral meshes have a faster single-mesh path (matrix-core tables and
+// assembly): the default Jacobian strategy runs those meshes on it (bitwise
+// identical again), the fully persistent strategies assemble them with the
+// scalar bodies (FP32 parity).  The strategy, grid size and work-item
+// granularity per (type, degree) come from a table that fr_batch_tune fills
+// by timing candidates on the batch itself.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -221,7 +225,8 @@ struct fr_batch_s {
   size_t cap_res = 0, cap_jac = 0, cap_til = 0;
   int seg_off[3][32], seg_cnt[3][32];
   std::vector<int> codes;          // (type, degree) codes present
-  int res_mode = 0, jac_mode = 0;  // 0: one mixed launch per phase, 1: one launch per group
+  int res_mode = 0, jac_mode = 2;  // 0: one mixed launch per phase, 1: one launch per group,
+                                   // 2 (Jacobian): as 1, quadrilateral meshes on the matrix-core path
   int k_res[32], k_jac[32];        // work-item granularity per (type, degree)
   int grid_res = 0, grid_jac = 0;  // persistent workgroups per launch
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -351,6 +356,20 @@ static fr_status launch_jac(fr_batch_s* b, bool visc) {
                        b->djac, b->njac);
   } else {
     for (int code : b->codes) {
+      if (b->jac_mode == 2 && code / 8 == ET_QUAD) {
+        // the single-mesh matrix-core path (tables + MFMA assembly), mesh by
+        // mesh on the batch stream: the same kernels as the mesh run alone
+        for (size_t i = 0; i < b->ctx.size(); ++i) {
+          if (b->hdesc[i].code != code) continue;
+          fr_ctx_s* c = b->ctx[i];
+          hipStream_t own = c->stream;
+          c->stream = b->stream;
+          const int rc = c->ks.jac(c, b->ptrs.U[i], b->ptrs.B[i], 1, b->hdesc[i].nblk);
+          c->stream = own;
+          if (rc) return bfail(b, (fr_status)rc, "mesh " + std::to_string(i) + ": " + c->err);
+        }
+        continue;
+      }
       const BItem* tl = b->dtil + b->seg_off[1][code];
       const int nt = b->seg_cnt[1][code], gt = gsize(b->grid_res, nt);
       group_jac<SYS, 0>(b, code, tl, nt, gt);
@@ -489,11 +508,11 @@ fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void*
   // residual: grid size, then the tiles per work item of each (type, degree)
   // per phase: launch strategy, then grid size, then units per work item of
   // each (type, degree) (coordinate descent on measured times)
-  auto tune_one = [&](int* mode, int* grid, int* k, fr_status (*fn)(fr_batch_s*), const std::vector<int>& grids,
-                      const std::vector<int>& ks) -> fr_status {
+  auto tune_one = [&](int* mode, int nmodes, int* grid, int* k, fr_status (*fn)(fr_batch_s*),
+                      const std::vector<int>& grids, const std::vector<int>& ks) -> fr_status {
     double best = 1e30;
     int bm = *mode;
-    for (int md : {0, 1}) {
+    for (int md = 0; md < nmodes; ++md) {
       *mode = md;
       double t = time_ms(b, fn, reps);
       if (t < best) { best = t; bm = md; }
@@ -521,8 +540,8 @@ fr_status fr_batch_tune(fr_batch* b, const void* const* U, void* const* R, void*
     }
     return FR_OK;
   };
-  if ((st = tune_one(&b->res_mode, &b->grid_res, b->k_res, run_rhs, {1, 2, 4, 8, 0}, {1, 2, 4, 8}))) return st;
-  if ((st = tune_one(&b->jac_mode, &b->grid_jac, b->k_jac, run_jac, {1, 2, 4, 8, 0}, {1, 2, 4}))) return st;
+  if ((st = tune_one(&b->res_mode, 2, &b->grid_res, b->k_res, run_rhs, {1, 2, 4, 8, 0}, {1, 2, 4, 8}))) return st;
+  if ((st = tune_one(&b->jac_mode, 3, &b->grid_jac, b->k_jac, run_jac, {1, 2, 4, 8, 0}, {1, 2, 4}))) return st;
   return hipStreamSynchronize(b->stream) == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch tuning");
 }
 
@@ -540,7 +559,7 @@ fr_status fr_batch_set_tuning(fr_batch* b, const int* modes, int grid_res, int g
                               const int* k_jac) {
   if (!b || grid_res < 0 || grid_jac < 0) return FR_E_INVALID;
   if (modes) {
-    if (modes[0] < 0 || modes[0] > 1 || modes[1] < 0 || modes[1] > 1) return bfail(b, FR_E_INVALID, "launch mode");
+    if (modes[0] < 0 || modes[0] > 1 || modes[1] < 0 || modes[1] > 2) return bfail(b, FR_E_INVALID, "launch mode");
     b->res_mode = modes[0];
     b->jac_mode = modes[1];
   }

@@ -491,16 +491,17 @@ class Batch:
         self._check(lib().fr_batch_tuning(self.h, md, C.byref(gr), C.byref(gj), kr, kj))
         codes = sorted({8 * int(c.mesh.elem_type[0]) + int(c.mesh.degree[0]) for c in self.ctxs})
         name = {0: "quad", 1: "tri"}
-        mode = {0: "mixed", 1: "grouped"}
+        mode = {0: "mixed", 1: "grouped", 2: "grouped_mfma_quads"}
         return {"res_launch": mode[md[0]], "jac_launch": mode[md[1]], "grid_res": gr.value, "grid_jac": gj.value,
                 "tiles_per_item": {f"{name[k // 8]}p{k % 8}": kr[k] for k in codes},
                 "elems_per_item": {f"{name[k // 8]}p{k % 8}": kj[k] for k in codes}}
 
     def set_tuning(self, res_launch: str, jac_launch: str, grid_res: int, grid_jac: int, k_res: int = 1,
                    k_jac: int = 1):
-        """Loads a table: launch strategies ("mixed" | "grouped"), workgroups
-        per launch, and one units-per-item value for every (type, degree)."""
-        md = (C.c_int * 2)(*[{"mixed": 0, "grouped": 1}[x] for x in (res_launch, jac_launch)])
+        """Loads a table: launch strategies ("mixed" | "grouped", and for the
+        Jacobian also "grouped_mfma_quads"), workgroups per launch, and one
+        units-per-item value for every (type, degree)."""
+        md = (C.c_int * 2)(*[{"mixed": 0, "grouped": 1, "grouped_mfma_quads": 2}[x] for x in (res_launch, jac_launch)])
         kr = (C.c_int * 32)(*([k_res] * 32))
         kj = (C.c_int * 32)(*([k_jac] * 32))
         self._check(lib().fr_batch_set_tuning(self.h, md, grid_res, grid_jac, kr, kj))
