@@ -3,6 +3,7 @@
 
 #include <cstring>
 #include <mutex>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -251,19 +252,65 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   const size_t mfs = c->ks.mf_bytes ? c->ks.mf_bytes(0) : 0, mft = c->ks.mf_bytes ? c->ks.mf_bytes(1) : 0;
   const size_t mfc = c->ks.mf_bytes ? c->ks.mf_bytes(2) : 0;
   if (mfs) {
+    // The reference part of a block's sensitivities (the corrected-gradient
+    // rows and the face-value rows) involves no geometry: it depends on the
+    // block (self, or the face) and on which neighbour flux point each of
+    // the face's flux points pairs with.  Blocks with equal keys share one
+    // copy, which the assembly reads instead of the element's own.
+    const int nsb = 1 + c->nface, nf = c->nf, nfp = c->nf / c->nface;
+    std::map<std::vector<int>, int> ids;
+    std::vector<int> sig((size_t)c->ne * nsb);
+    std::vector<std::pair<int64_t, int>> reps;     // representative (element, block) of each key
+    std::vector<int> key;
+    for (int64_t n = 0; n < c->ne; ++n)
+      for (int k = 0; k < nsb; ++k) {
+        key.assign(1, k);
+        if (k > 0)
+          for (int j = 0; j < nfp; ++j) key.push_back(geo.nbfp[(size_t)n * nf + (k - 1) * nfp + j] % nf);
+        auto it = ids.find(key);
+        int id;
+        if (it == ids.end()) {
+          id = (int)reps.size();
+          ids.emplace(key, id);
+          reps.emplace_back(n, k);
+        } else {
+          id = it->second;
+        }
+        sig[(size_t)n * nsb + k] = id;
+      }
+    const size_t blk = mfs / nsb;                     // bytes of one block's sensitivities
     const size_t a = ((size_t)c->ne * mfs + 255) & ~(size_t)255;
     const size_t t = ((size_t)c->ne * mft + 255) & ~(size_t)255;
-    if (hipMalloc(&c->mf_mem, a + t + (size_t)c->ne * mfc) != hipSuccess) {
+    const size_t sc = ((size_t)c->ne * mfc + 255) & ~(size_t)255;
+    const size_t st = ((size_t)reps.size() * blk + 255) & ~(size_t)255;
+    if (hipMalloc(&c->mf_mem, a + t + sc + st + sig.size() * sizeof(int)) != hipSuccess) {
       release(c);
       return fail(nullptr, FR_E_NOMEM, "device allocation failed (Jacobian workspaces)");
     }
     c->mf_sens = c->mf_mem;
     c->mf_tab = (char*)c->mf_mem + a;
     c->mf_scr = mfc ? (char*)c->mf_mem + a + t : nullptr;
+    c->mf_sigtab = (char*)c->mf_mem + a + t + sc;
+    c->mf_sig = (int*)((char*)c->mf_mem + a + t + sc + st);
+    c->mf_nsig = (int)reps.size();
+    if (hipMemcpy(c->mf_sig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      release(c);
+      return fail(nullptr, FR_E_DEVICE, "upload of the sensitivity keys");
+    }
     if (c->ks.mf_setup(c) != 0) {
       std::string e = c->err;
       release(c);
       return fail(nullptr, FR_E_DEVICE, "Jacobian sensitivities: " + e);
+    }
+    for (size_t i = 0; i < reps.size(); ++i)
+      if (hipMemcpyAsync((char*)c->mf_sigtab + i * blk, (char*)c->mf_sens + ((size_t)reps[i].first * nsb + reps[i].second) * blk,
+                         blk, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+        release(c);
+        return fail(nullptr, FR_E_DEVICE, "copy of the shared sensitivities");
+      }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      release(c);
+      return fail(nullptr, FR_E_DEVICE, "Jacobian sensitivities");
     }
   }
   *out = c;

@@ -40,6 +40,9 @@ struct fr_ctx_s {
   void* UFd = nullptr; void* Qd = nullptr; void* QFd = nullptr;
   void* mf_mem = nullptr; void* mf_sens = nullptr; void* mf_tab = nullptr;   // matrix-core Jacobian
   void* mf_scr = nullptr;                                                     // its table-build scratch (3-D)
+  void* mf_sigtab = nullptr;   // shared reference sensitivities, one block per key
+  int* mf_sig = nullptr;       // [ne][1 + nface] key of each block's reference part
+  int mf_nsig = 0;
   // optional timing of the dominant kernels with HIP events on the context stream
   static constexpr int kEvPool = 64;
   bool timing = false;

@@ -63,8 +63,9 @@ __global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, 
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>()))
 __attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R>()))) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
-                                                                                const R* tab, const R* sens, int nsb,
-                                                                                int nblk, long ntasks, OT* B) {
+                                                                                const R* tab, const R* sens,
+                                                                                const R* sigtab, const int* sig,
+                                                                                int nsb, int nblk, long ntasks, OT* B) {
   typedef MfSizes<E, NV, SYS> Y;
   constexpr int WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
   __shared__ __align__(16) R stage[WPB * STG];
@@ -83,7 +84,8 @@ __attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R>()))) k_jac_mf
   const int slab = sub % Y::SL, nt = (sub / Y::SL) % Y::NT, mt = sub / (Y::SL * Y::NT);
   R* stg = stage + wave * STG;
   const int lane = threadIdx.x & 63;
-  jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, nsb, nblk, B, stg, active);
+  jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, sigtab, sig, nsb, nblk, B, stg,
+                                 active);
 }
 
 template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);
@@ -169,7 +171,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
       FR_LAUNCH_CHECK(c);
     }
     if constexpr (kMfmaPath) {
-      if (!c->mf_sens || !c->mf_tab) { c->err = "Jacobian workspace missing"; return -4; }
+      if (!c->mf_sens || !c->mf_tab || !c->mf_sigtab || !c->mf_sig) { c->err = "Jacobian workspace missing"; return -4; }
       if (c->timing) fr_time_begin(c, 0);     // tables + assembly
       hipLaunchKernelGGL((k_jac_mf_tab<E, NV, SYS, R>), dim3(ne), dim3(kThreads), 0, c->stream, geo, c->ph, U,
                          (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab, (R*)c->mf_scr);
@@ -178,7 +180,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
       constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
       hipLaunchKernelGGL((k_jac_mf_asm<E, NV, SYS, R, OT>), dim3((unsigned)((ntasks + per - 1) / per)), dim3(64 * per),
                          0, c->stream, ctx_o1<R>(c), geo.rdet, (const R*)c->mf_tab, (const R*)c->mf_sens,
-                         1 + E::NFACE, nblk, ntasks, B);
+                         (const R*)c->mf_sigtab, (const int*)c->mf_sig, 1 + E::NFACE, nblk, ntasks, B);
       FR_LAUNCH_CHECK(c);
       if (c->timing) fr_time_end(c, 0);
       return 0;

@@ -485,8 +485,8 @@ template <class A> __device__ __forceinline__ void mf_pin(A& v) { asm volatile("
 // slab-dependent weight goes into the A operand instead.
 template <class E, int NV, int SYS, class R, class OT>
 __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0, int lane, const Ops1D<R>& o1,
-                                            const R* rdet, const R* tab, const R* sens, int nsb, int nblk, OT* B,
-                                            R* stage, bool active) {
+                                            const R* rdet, const R* tab, const R* sens, const R* sigtab,
+                                            const int* sig, int nsb, int nblk, OT* B, R* stage, bool active) {
   typedef MfSizes<E, NV, SYS> Y;
   typedef TPIdx<E> X;
   typedef Mfma<R> M;
@@ -499,8 +499,11 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   const long nl = n;
   const R* tbT = tab + nl * Y::TAB;
   const R* tfT = tbT + Y::TBT;
-  const R* G = sens + (nl * nsb + k) * Y::BLK;
-  const R* S = G + Y::GSZ;
+  // the block's reference rows (G; face values DL, DR) from its shared
+  // copy, the geometric rows (face gradients SL, SR) from its own
+  const R* G = sigtab + (long)sig[nl * nsb + k] * Y::BLK;
+  const R* Sr = G + Y::GSZ;
+  const R* S = sens + (nl * nsb + k) * Y::BLK + Y::GSZ;
   const R* srd = rdet + nl * NS;
   // the few 1-D coefficients the task uses, as scalars (indexing the
   // by-value operator struct directly keeps a private copy of it alive)
@@ -644,7 +647,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
             const int j = ch * 4 + kq;
             const bool use = j < JF;
             fa[ch][i] = use ? tfT[Y::fi(g, j, mo)] : R(0);
-            fb[ch][i] = use ? S[Y::si(g, j, so)] : R(0);
+            fb[ch][i] = use ? (j < 2 ? Sr : S)[Y::si(g, j, so)] : R(0);
           });
         },
         [&](auto I) __attribute__((always_inline)) {
@@ -655,7 +658,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
             const int j = ch * 4 + kq;
             if (j < JF) {
               mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][i], fa[ch][i + 1], fa[ch][i + 2], fa[ch][i + 3]);
-              mf_ld4(S + Y::si(g, j, so), fb[ch][i], fb[ch][i + 1], fb[ch][i + 2], fb[ch][i + 3]);
+              mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), fb[ch][i], fb[ch][i + 1], fb[ch][i + 2], fb[ch][i + 3]);
             } else {
               fa[ch][i] = fa[ch][i + 1] = fa[ch][i + 2] = fa[ch][i + 3] = R(0);
               fb[ch][i] = fb[ch][i + 1] = fb[ch][i + 2] = fb[ch][i + 3] = R(0);
@@ -712,7 +715,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
               const int j = ch * 4 + kq;
               const bool use = j < JF;
               fa[ch][t] = use ? tfT[Y::fi(g, j, mo)] : R(0);
-              fb[ch][t] = use ? S[Y::si(g, j, so)] : R(0);
+              fb[ch][t] = use ? (j < 2 ? Sr : S)[Y::si(g, j, so)] : R(0);
             });
           },
           [&](auto I) __attribute__((always_inline)) {
@@ -722,7 +725,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
               const int j = ch * 4 + kq;
               if (j < JF) {
                 mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][t], fa[ch][t + 1], fa[ch][t + 2], fa[ch][t + 3]);
-                mf_ld4(S + Y::si(g, j, so), fb[ch][t], fb[ch][t + 1], fb[ch][t + 2], fb[ch][t + 3]);
+                mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), fb[ch][t], fb[ch][t + 1], fb[ch][t + 2], fb[ch][t + 3]);
               } else {
                 fa[ch][t] = fa[ch][t + 1] = fa[ch][t + 2] = fa[ch][t + 3] = R(0);
                 fb[ch][t] = fb[ch][t + 1] = fb[ch][t + 2] = fb[ch][t + 3] = R(0);

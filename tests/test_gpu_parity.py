@@ -132,6 +132,38 @@ def test_hex_ns_fp64(p):
     _assert(out, "f64", p)
 
 
+def _rotate_quads(m, seed):
+    """The same mesh with each element's local frame rotated by a seeded
+    random quarter turn (vertex order shifted; local face f joins vertices f
+    and f+1), neighbour face indices updated to match: the face-point
+    pairings then differ from element to element."""
+    import copy
+    r = copy.deepcopy(m)
+    sh = np.random.default_rng(seed).integers(0, 4, m.n_elem)
+    for e in range(m.n_elem):
+        k = int(sh[e])
+        r.xyz[e] = np.roll(m.xyz[e], -k, axis=0)
+        r.nbr[e] = np.roll(m.nbr[e], -k)
+        r.nbr_face[e] = np.roll(m.nbr_face[e], -k)
+    for e in range(m.n_elem):
+        for f in range(4):
+            nb = int(r.nbr[e, f])
+            r.nbr_face[e, f] = (int(r.nbr_face[e, f]) - int(sh[nb])) % 4
+    return r, sh
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_quad_fp32_rotated_frames(p):
+    """Matrix-core path on elements with rotated local frames: blocks whose
+    geometry-free sensitivities are shared must share the same pairing."""
+    m0 = I.quad_mesh(5, degree=p, jitter=0.05, K=1)
+    m, sh = _rotate_quads(m0, 3)
+    assert len(set(sh.tolist())) == 4
+    ph = I.ns_physics(2, 1000.0, 0.72)
+    out = check_case(m, ph, p, I.ns2d_state(m, p), "f32", [0, 7, 13, 24])
+    _assert(out, "f32", p)
+
+
 @pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("system", ["adv", "euler", "ns"])
 def test_hex_fp32(system, p):
