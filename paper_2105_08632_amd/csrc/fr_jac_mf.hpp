@@ -96,11 +96,15 @@ template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() {
   typedef MfSizes<E, NV, SYS> Y;
   return 16 * Y::BT * (Y::NRH + 1);
 }
-// Resident waves per SIMD the register allocation aims for: hexahedra of
-// degree 3 sit just above the three-wave limit without the hint and reach
-// it without spilling; elsewhere the hint would only force spills.
+// Resident waves per SIMD the register allocation aims for (degree 3: the
+// largest counts these tasks reach without spilling; elsewhere the hint
+// would only force spills).
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_min_waves() {
-  return (E::ND == 3 && E::DEG == 3) ? 3 : 1;
+  return E::DEG == 3 ? (E::ND == 3 ? 3 : 4) : 1;
+}
+// points (flux points) whose operands one load round trip fetches
+template <class E, int NV, int SYS, class R> constexpr int jac_mf_chunk() {
+  return (E::ND == 2 && E::DEG == 3) ? 8 : 16;   // quads p = 3: half the operand registers, a fourth wave
 }
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
   return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
@@ -527,7 +531,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   // point the updated accumulators are pinned: without that, instruction
   // selection sinks every update to the final store and keeps each product
   // of the task live.
-  constexpr int CH = 16;
+  constexpr int CH = jac_mf_chunk<E, NV, SYS, R>();
   constexpr int NDS = ND == 3 ? 2 : ND;    // directions whose lines lie in the slab
   // volume, in-slab directions: X_d[tau] (tau in the slab) scattered along
   // the d-line through tau
@@ -586,18 +590,20 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
         if (z0 == decltype(Z)::value) wz[c] = dc[decltype(Z)::value][c];
       });
     });
-    mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
-      constexpr int c = decltype(Cc)::value;
-      static_assert(SLS <= CH, "one chunk per level of the third coordinate");
-      R bv[SLS], av[SLS];
-      mf_chunk<SLS, (c * SLS) % 4>(
+    // chunks of CH points within each level c of the third coordinate
+    constexpr int QL = (SLS + CH - 1) / CH;
+    mf_for<0, N1 * QL>([&](auto CQ) __attribute__((always_inline)) {
+      constexpr int c = decltype(CQ)::value / QL, i0 = (decltype(CQ)::value % QL) * CH;
+      constexpr int CNT = (SLS - i0) < CH ? (SLS - i0) : CH;
+      R bv[CH], av[CH];
+      mf_chunk<CNT, (c * SLS + i0) % 4>(
           [&](auto I) __attribute__((always_inline)) {
-            constexpr int i = decltype(I)::value, t = c * SLS + i;
+            constexpr int i = decltype(I)::value, t = c * SLS + i0 + i;
             bv[i] = kin ? G[Y::gi(t, kq, so)] : R(0);
             av[i] = kin ? tbT[Y::ti(t, 2, kq, mo)] : R(0);
           },
           [&](auto I) __attribute__((always_inline)) {
-            constexpr int i = decltype(I)::value, t = c * SLS + i;
+            constexpr int i = decltype(I)::value, t = c * SLS + i0 + i;
             if (kin) {
               mf_ld4(G + Y::gi(t, kq, so), bv[i], bv[i + 1], bv[i + 2], bv[i + 3]);
               mf_ld4(tbT + Y::ti(t, 2, kq, mo), av[i], av[i + 1], av[i + 2], av[i + 3]);
@@ -607,9 +613,9 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
             }
           });
       fr_sched_fence();
-      mf_for<0, SLS>([&](auto I) __attribute__((always_inline)) {
+      mf_for<0, CNT>([&](auto I) __attribute__((always_inline)) {
         constexpr int i = decltype(I)::value;
-        V[i] = M::mma(wz[c] * av[i], bv[i], V[i]);
+        V[i0 + i] = M::mma(wz[c] * av[i], bv[i], V[i0 + i]);
       });
       fr_sched_fence();
     });
@@ -702,42 +708,44 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
         if (X::fax(q) == 2) { if (seen == j) f = q; ++seen; }
       return f;
     };
-    mf_for<0, 2>([&](auto Fi) __attribute__((always_inline)) {
-      constexpr int f = zface(decltype(Fi)::value);
+    // chunks of CH flux points within each of the two faces
+    constexpr int QF = (NFP + CH - 1) / CH;
+    mf_for<0, 2 * QF>([&](auto FQ) __attribute__((always_inline)) {
+      constexpr int f = zface(decltype(FQ)::value / QF), t0 = (decltype(FQ)::value % QF) * CH;
+      constexpr int CNT = (NFP - t0) < CH ? (NFP - t0) : CH;
       const R hz = X::fsg(f) > 0 ? hzp : hzm;
-      static_assert(NFP <= CH, "one chunk per face");
-      R fa[JC][NFP], fb[JC][NFP];
-      mf_chunk<NFP, (f * NFP) % 4>(
+      R fa[JC][CH], fb[JC][CH];
+      mf_chunk<CNT, (f * NFP + t0) % 4>(
           [&](auto I) __attribute__((always_inline)) {
-            constexpr int t = decltype(I)::value, g = f * NFP + t;
+            constexpr int i = decltype(I)::value, g = f * NFP + t0 + i;
             mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
               constexpr int ch = decltype(CC)::value;
               const int j = ch * 4 + kq;
               const bool use = j < JF;
-              fa[ch][t] = use ? tfT[Y::fi(g, j, mo)] : R(0);
-              fb[ch][t] = use ? (j < 2 ? Sr : S)[Y::si(g, j, so)] : R(0);
+              fa[ch][i] = use ? tfT[Y::fi(g, j, mo)] : R(0);
+              fb[ch][i] = use ? (j < 2 ? Sr : S)[Y::si(g, j, so)] : R(0);
             });
           },
           [&](auto I) __attribute__((always_inline)) {
-            constexpr int t = decltype(I)::value, g = f * NFP + t;
+            constexpr int i = decltype(I)::value, g = f * NFP + t0 + i;
             mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
               constexpr int ch = decltype(CC)::value;
               const int j = ch * 4 + kq;
               if (j < JF) {
-                mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][t], fa[ch][t + 1], fa[ch][t + 2], fa[ch][t + 3]);
-                mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), fb[ch][t], fb[ch][t + 1], fb[ch][t + 2], fb[ch][t + 3]);
+                mf_ld4(tfT + Y::fi(g, j, mo), fa[ch][i], fa[ch][i + 1], fa[ch][i + 2], fa[ch][i + 3]);
+                mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), fb[ch][i], fb[ch][i + 1], fb[ch][i + 2], fb[ch][i + 3]);
               } else {
-                fa[ch][t] = fa[ch][t + 1] = fa[ch][t + 2] = fa[ch][t + 3] = R(0);
-                fb[ch][t] = fb[ch][t + 1] = fb[ch][t + 2] = fb[ch][t + 3] = R(0);
+                fa[ch][i] = fa[ch][i + 1] = fa[ch][i + 2] = fa[ch][i + 3] = R(0);
+                fb[ch][i] = fb[ch][i + 1] = fb[ch][i + 2] = fb[ch][i + 3] = R(0);
               }
             });
           });
       fr_sched_fence();
-      mf_for<0, NFP>([&](auto I) __attribute__((always_inline)) {
-        constexpr int t = decltype(I)::value;
+      mf_for<0, CNT>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i = decltype(I)::value, t = t0 + i;
         static_assert(X::fline(f * NFP + t, 0) % SLS == t, "third-axis flux point t lies over slab point t");
         mf_for<0, JC>([&](auto CC) __attribute__((always_inline)) {
-          V[t] = M::mma(hz * fa[decltype(CC)::value][t], fb[decltype(CC)::value][t], V[t]);
+          V[t] = M::mma(hz * fa[decltype(CC)::value][i], fb[decltype(CC)::value][i], V[t]);
         });
       });
       fr_sched_fence();
