@@ -330,8 +330,8 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
   sync();
   // ---------------------------------------------------------------- tables
   // one seeded input per item (single-tangent duals keep register use low):
-  // solution points: (tau, pass, c), pass 0 seeds u_c, pass 1+d seeds q_{d,c};
-  // flux points: (g, pass, c), passes 0/1 seed u_L,c / u_R,c in the
+  // solution points: (pass, tau, c), pass 0 seeds u_c, pass 1+d seeds q_{d,c};
+  // flux points: (pass, g, c), passes 0/1 seed u_L,c / u_R,c in the
   // convective flux, 2/3 seed u_c in the viscous flux at L / R, then q_{d,c}
   // at L, then at R.
   {
@@ -339,10 +339,13 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
     constexpr int NPS = SysTraits<SYS>::kVisc ? 1 + ND : 1;
     constexpr int NPF = SysTraits<SYS>::kVisc ? 4 + 2 * ND : 2;
     const int nsp = visc ? NPS : 1, nfp = visc ? NPF : 2;
+    // items ordered pass-major (pass, point, variable): the pass decides the
+    // code path, so lanes of one wavefront take the same path (one pass per
+    // wavefront at N_s N_V = 64) instead of every path under masks
     for (int it = tid; it < (NS * nsp + NF * nfp) * NV; it += nth) {
       const int c = it % NV, j0 = it / NV;
       if (j0 < NS * nsp) {
-        int t = j0 / nsp, ps = j0 % nsp;
+        int t = j0 % NS, ps = j0 / NS;
         DT u[NV], f[ND][NV], q[ND][NV];
         for (int a = 0; a < NV; ++a) u[a] = DT(su[t * NV + a], (ps == 0 && a == c) ? R(1) : R(0));
         for (int d = 0; d < ND; ++d)
@@ -369,7 +372,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
         }
       } else {
         int j = j0 - NS * nsp;
-        int g = j / nfp, ps = j % nfp;
+        int g = j % NF, ps = j / NF;
         R nn[ND];
         for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
         if (ps < 2) {
