@@ -250,7 +250,6 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   // matrix-core Jacobian: geometry-only sensitivities (computed here, once)
   // and the per-state tables
   const size_t mfs = c->ks.mf_bytes ? c->ks.mf_bytes(0) : 0, mft = c->ks.mf_bytes ? c->ks.mf_bytes(1) : 0;
-  const size_t mfc = c->ks.mf_bytes ? c->ks.mf_bytes(2) : 0;
   if (mfs) {
     // The reference part of a block's sensitivities (the corrected-gradient
     // rows and the face-value rows) involves no geometry: it depends on the
@@ -281,17 +280,15 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     const size_t blk = mfs / nsb;                     // bytes of one block's sensitivities
     const size_t a = ((size_t)c->ne * mfs + 255) & ~(size_t)255;
     const size_t t = ((size_t)c->ne * mft + 255) & ~(size_t)255;
-    const size_t sc = ((size_t)c->ne * mfc + 255) & ~(size_t)255;
     const size_t st = ((size_t)reps.size() * blk + 255) & ~(size_t)255;
-    if (hipMalloc(&c->mf_mem, a + t + sc + st + sig.size() * sizeof(int)) != hipSuccess) {
+    if (hipMalloc(&c->mf_mem, a + t + st + sig.size() * sizeof(int)) != hipSuccess) {
       release(c);
       return fail(nullptr, FR_E_NOMEM, "device allocation failed (Jacobian workspaces)");
     }
     c->mf_sens = c->mf_mem;
     c->mf_tab = (char*)c->mf_mem + a;
-    c->mf_scr = mfc ? (char*)c->mf_mem + a + t : nullptr;
-    c->mf_sigtab = (char*)c->mf_mem + a + t + sc;
-    c->mf_sig = (int*)((char*)c->mf_mem + a + t + sc + st);
+    c->mf_sigtab = (char*)c->mf_mem + a + t;
+    c->mf_sig = (int*)((char*)c->mf_mem + a + t + st);
     c->mf_nsig = (int)reps.size();
     if (hipMemcpy(c->mf_sig, sig.data(), sig.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
       release(c);

@@ -14,7 +14,7 @@ struct KernelSet {
   int (*rhs)(fr_ctx_s*, const void* U, void* R);
   int (*jvp)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
   int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec, int nblk);
-  size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: sensitivities, 1: tables, 2: scratch)
+  size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: sensitivities, 1: tables)
   int (*mf_setup)(fr_ctx_s*);          // computes the geometry-only sensitivities
 };
 
@@ -39,7 +39,6 @@ struct fr_ctx_s {
   void* UF64 = nullptr; void* Q64 = nullptr; void* QF64 = nullptr;  // FP64 residual
   void* UFd = nullptr; void* Qd = nullptr; void* QFd = nullptr;
   void* mf_mem = nullptr; void* mf_sens = nullptr; void* mf_tab = nullptr;   // matrix-core Jacobian
-  void* mf_scr = nullptr;                                                     // its table-build scratch (3-D)
   void* mf_sigtab = nullptr;   // shared reference sensitivities, one block per key
   int* mf_sig = nullptr;       // [ne][1 + nface] key of each block's reference part
   int mf_nsig = 0;

@@ -56,9 +56,9 @@ __global__ void __launch_bounds__(kThreads) k_jac_mf_sens(OpsD<R> op, Ops1D<R> o
 }
 template <class E, int NV, int SYS, class R>
 __global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, const R* U, const R* Q, const R* UF,
-                                                         const R* QF, R* out, R* gscratch) {
+                                                         const R* QF, R* out) {
   __shared__ __align__(16) char lds[jac_mf_tables_lds<E, NV, SYS, R>()];
-  jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out, gscratch);
+  jac_mf_tables_body<E, NV, SYS, R>(blockIdx.x, threadIdx.x, blockDim.x, lds, geo, ph, U, Q, UF, QF, out);
 }
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>()))
@@ -174,7 +174,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
       if (!c->mf_sens || !c->mf_tab || !c->mf_sigtab || !c->mf_sig) { c->err = "Jacobian workspace missing"; return -4; }
       if (c->timing) fr_time_begin(c, 0);     // tables + assembly
       hipLaunchKernelGGL((k_jac_mf_tab<E, NV, SYS, R>), dim3(ne), dim3(kThreads), 0, c->stream, geo, c->ph, U,
-                         (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab, (R*)c->mf_scr);
+                         (const R*)Q, (const R*)UF, (const R*)QF, (R*)c->mf_tab);
       FR_LAUNCH_CHECK(c);
       const long ntasks = (long)ne * nblk * MF::TASKS;
       constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
@@ -213,12 +213,10 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   // bytes per element of the matrix-core path's sensitivity and table arrays (0: not used)
-  // which: 0 sensitivities, 1 tables, 2 table-build scratch
+  // which: 0 sensitivities, 1 tables
   static size_t mf_bytes(int which) {
     if constexpr (kMfmaPath)
-      return which == 0 ? (size_t)(1 + E::NFACE) * MF::BLK * sizeof(R)
-                        : (which == 1 ? (size_t)MF::TAB * sizeof(R)
-                                      : (size_t)jac_mf_gscratch<E, NV, SYS, R>() * sizeof(R));
+      return which == 0 ? (size_t)(1 + E::NFACE) * MF::BLK * sizeof(R) : (size_t)MF::TAB * sizeof(R);
     else return 0;
   }
   static int mf_setup(fr_ctx_s* c) {

@@ -69,8 +69,6 @@ template <class E, int NV, int SYS> struct MfSizes {
   // staged in NH passes of NRH rows (two where the halves stay whole points
   // and 16-byte multiples: half the LDS, more resident waves)
   static constexpr int NH = (SLS % 2 == 0 && (SLS / 2 * NV) % 4 == 0 && NR >= 32) ? 2 : 1, NRH = NR / NH;
-  // table-build scratch in global memory where it does not fit beside the rest
-  static constexpr bool kGlobalScratch = ND == 3;
 };
 
 template <class R> struct Mfma;
@@ -124,11 +122,7 @@ template <class E, int NV, int SYS, class R> constexpr int jac_mf_tables_lds() {
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND;
   return lds_bytes<R>(NS * NV) + lds_bytes<R>(NS * ND * NV) + 2 * lds_bytes<R>(NF * NV) +
          2 * lds_bytes<R>(NF * ND * NV) + 2 * lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) +
-         lds_bytes<int>(NF) + (Y::kGlobalScratch ? 0 : jac_tp_scratch<E, NV, SYS, R>());
-}
-// table-build scratch per element when it lives in global memory (floats of R)
-template <class E, int NV, int SYS, class R> constexpr long jac_mf_gscratch() {
-  return MfSizes<E, NV, SYS>::kGlobalScratch ? (long)jac_tp_scratch<E, NV, SYS, R>() / (long)sizeof(R) + 64 : 0;
+         lds_bytes<int>(NF);
 }
 
 // Sensitivities of element n for all blocks (geometry only):
@@ -278,7 +272,7 @@ __device__ void jac_mf_sens_body(int n, int tid, int nth, char* lds, const OpsD<
 // out[n][T | W] (MfSizes::TAB values, operand layout).
 template <class E, int NV, int SYS, class R>
 __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const GeoD<R>& geo, const PhysP& ph,
-                                   const R* U, const R* Q, const R* UF, const R* QF, R* out, R* gscratch) {
+                                   const R* U, const R* Q, const R* UF, const R* QF, R* out) {
   typedef TPSizes<E, NV, SYS> Z;
   typedef MfSizes<E, NV, SYS> Y;
   constexpr int NS = Z::NS, NF = Z::NF, ND = Z::ND, NV2 = Z::NV2;
@@ -298,14 +292,6 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
   R* snn = L.take<R>(NF * ND);
   R* smg = L.take<R>(NF);
   int* spg = L.take<int>(NF);
-  Lds L1{Y::kGlobalScratch ? reinterpret_cast<char*>(gscratch + (long)n * jac_mf_gscratch<E, NV, SYS, R>()) : L.p};
-  R* bh = L1.take<R>(ND * ND * NS * NV2);
-  R* rL = L1.take<R>(NF * NV2);
-  R* rR = L1.take<R>(NF * NV2);
-  R* vL = L1.take<R>(NF * NV2);
-  R* vR = L1.take<R>(NF * NV2);
-  R* qLt = L1.take<R>(ND * NF * NV2);
-  R* qRt = L1.take<R>(ND * NF * NV2);
   const long nl = n;
   R* tbT = out + nl * Y::TAB;
   R* tfT = tbT + Y::TBT;
@@ -329,29 +315,30 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
     }
   sync();
   // ---------------------------------------------------------------- tables
-  // one seeded input per item (single-tangent duals keep register use low):
-  // solution points: (pass, tau, c), pass 0 seeds u_c, pass 1+d seeds q_{d,c};
-  // flux points: (pass, g, c), passes 0/1 seed u_L,c / u_R,c in the
-  // convective flux, 2/3 seed u_c in the viscous flux at L / R, then q_{d,c}
-  // at L, then at R.
+  // Each item evaluates with single-tangent duals every seeded input that
+  // its table entries combine, and writes them directly (no intermediates):
+  //   solution point (tau, c), kind 0: u_c seeded: transformed inviscid +
+  //     viscous flux derivatives -> T[tau][d][delta];
+  //   kind 1 (viscous): q_{d2,c} seeded for each d2, contracted with S and
+  //     J^-1 -> T[tau][d][Gam_e];
+  //   flux point (g, c), kind 0 / 1: u_c seeded on side L / R: common
+  //     convective flux + that side's viscous flux -> W[g][DL] / W[g][DR];
+  //   kinds 2 .. 1 + 2 N_D (viscous): q_{d,c} seeded on side L, then R ->
+  //     W[g][SL_d] / W[g][SR_d].
+  // Items run kind-major (kind, point, c), so a wavefront takes one path.
   {
     typedef Dual<R> DT;
-    constexpr int NPS = SysTraits<SYS>::kVisc ? 1 + ND : 1;
-    constexpr int NPF = SysTraits<SYS>::kVisc ? 4 + 2 * ND : 2;
-    const int nsp = visc ? NPS : 1, nfp = visc ? NPF : 2;
-    // items ordered pass-major (pass, point, variable): the pass decides the
-    // code path, so lanes of one wavefront take the same path (one pass per
-    // wavefront at N_s N_V = 64) instead of every path under masks
-    for (int it = tid; it < (NS * nsp + NF * nfp) * NV; it += nth) {
-      const int c = it % NV, j0 = it / NV;
-      if (j0 < NS * nsp) {
-        int t = j0 % NS, ps = j0 / NS;
-        DT u[NV], f[ND][NV], q[ND][NV];
-        for (int a = 0; a < NV; ++a) u[a] = DT(su[t * NV + a], (ps == 0 && a == c) ? R(1) : R(0));
-        for (int d = 0; d < ND; ++d)
-          for (int a = 0; a < NV; ++a)
-            q[d][a] = DT(visc ? sq[(t * ND + d) * NV + a] : R(0), (ps == 1 + d && a == c) ? R(1) : R(0));
-        if (ps == 0) {
+    const int nsk = visc ? 2 : 1, nfk = visc ? 2 + 2 * ND : 2;
+    const int nsi = NS * NV * nsk, ntot = nsi + NF * NV * nfk;
+    for (int it = tid; it < ntot; it += nth) {
+      if (it < nsi) {
+        const int kind = it / (NS * NV), r = it % (NS * NV), t = r / NV, c = r % NV;
+        DT u[NV];
+        for (int a = 0; a < NV; ++a) u[a] = DT(su[t * NV + a], (kind == 0 && a == c) ? R(1) : R(0));
+        if (kind == 0) {
+          DT f[ND][NV], q[ND][NV];
+          for (int d = 0; d < ND; ++d)
+            for (int a = 0; a < NV; ++a) q[d][a] = DT(visc ? sq[(t * ND + d) * NV + a] : R(0), R(0));
           flux_inviscid<SYS, ND, NV, DT>(ph, u, f);
           if (visc) {
             DT fv[ND][NV];
@@ -366,75 +353,87 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
               tbT[Y::ti(t, d, ND, Y::pidx(a, c))] = acc;
             }
         } else {
-          flux_viscous<SYS, ND, NV, DT>(ph, u, q, f);
-          for (int k = 0; k < ND; ++k)
-            for (int a = 0; a < NV; ++a) bh[(((ps - 1) * ND + k) * NS + t) * NV2 + a * NV + c] = f[k][a].d;
+          R bq[ND][ND][NV];   // d f^k_a / d q_{d2,c}
+          for (int d2 = 0; d2 < ND; ++d2) {
+            DT q[ND][NV], f[ND][NV];
+            for (int d = 0; d < ND; ++d)
+              for (int a = 0; a < NV; ++a) q[d][a] = DT(sq[(t * ND + d) * NV + a], (d == d2 && a == c) ? R(1) : R(0));
+            flux_viscous<SYS, ND, NV, DT>(ph, u, q, f);
+            for (int k = 0; k < ND; ++k)
+              for (int a = 0; a < NV; ++a) bq[d2][k][a] = f[k][a].d;
+          }
+          for (int a = 0; a < NV; ++a)
+            for (int d = 0; d < ND; ++d)
+              for (int e = 0; e < ND; ++e) {
+                R acc = R(0);
+                for (int k = 0; k < ND; ++k) {
+                  R sk = sS[(t * ND + d) * ND + k];
+                  for (int d2 = 0; d2 < ND; ++d2) acc += sk * bq[d2][k][a] * sJi[(t * ND + e) * ND + d2];
+                }
+                tbT[Y::ti(t, d, e, Y::pidx(a, c))] = acc;
+              }
         }
       } else {
-        int j = j0 - NS * nsp;
-        int g = j % NF, ps = j / NF;
+        const int j = it - nsi, kind = j / (NF * NV), r = j % (NF * NV), g = r / NV, c = r % NV;
         R nn[ND];
         for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
-        if (ps < 2) {
+        const R mg = smg[g];
+        if (kind < 2) {
+          const int side = kind;
           DT uL[NV], uR[NV], F[NV];
           for (int a = 0; a < NV; ++a) {
-            uL[a] = DT(suL[g * NV + a], (ps == 0 && a == c) ? R(1) : R(0));
-            uR[a] = DT(suR[g * NV + a], (ps == 1 && a == c) ? R(1) : R(0));
+            uL[a] = DT(suL[g * NV + a], (side == 0 && a == c) ? R(1) : R(0));
+            uR[a] = DT(suR[g * NV + a], (side == 1 && a == c) ? R(1) : R(0));
           }
           common_inviscid<SYS, ND, NV, DT>(ph, uL, uR, nn, F);
-          R* o = ps == 0 ? rL : rR;
-          for (int a = 0; a < NV; ++a) o[g * NV2 + a * NV + c] = F[a].d;
+          R vs[NV];
+          for (int a = 0; a < NV; ++a) vs[a] = R(0);
+          if (visc) {
+            const R* us = side ? suR : suL;
+            const R* qs = side ? sqR : sqL;
+            DT u[NV], q[ND][NV], fv[ND][NV];
+            for (int a = 0; a < NV; ++a) u[a] = DT(us[g * NV + a], a == c ? R(1) : R(0));
+            for (int d = 0; d < ND; ++d)
+              for (int a = 0; a < NV; ++a) q[d][a] = DT(qs[(g * ND + d) * NV + a], R(0));
+            flux_viscous<SYS, ND, NV, DT>(ph, u, q, fv);
+            const R wgt = side ? cR : cL;
+            for (int a = 0; a < NV; ++a) {
+              R acc = R(0);
+              for (int d = 0; d < ND; ++d) acc += nn[d] * fv[d][a].d;
+              vs[a] = acc * wgt;
+            }
+          }
+          for (int a = 0; a < NV; ++a) {
+            const int m = Y::pidx(a, c);
+            const R id = (a == c) ? eta : R(0);
+            tfT[Y::fi(g, side, m)] = mg * (F[a].d + (visc ? (side == 0 ? vs[a] + id : vs[a] - id) : R(0)));
+            if (!visc)
+              for (int d = 0; d < ND; ++d) tfT[Y::fi(g, 2 + side * ND + d, m)] = R(0);
+          }
         } else {
-          int pp = ps - 2;
-          int side = (pp == 1 || pp >= 2 + ND) ? 1 : 0;
-          int qd = pp < 2 ? -1 : (pp - 2) % ND;
+          const int side = (kind - 2) / ND, qd = (kind - 2) % ND;
           const R* us = side ? suR : suL;
           const R* qs = side ? sqR : sqL;
           DT u[NV], q[ND][NV], fv[ND][NV];
-          for (int a = 0; a < NV; ++a) u[a] = DT(us[g * NV + a], (qd < 0 && a == c) ? R(1) : R(0));
+          for (int a = 0; a < NV; ++a) u[a] = DT(us[g * NV + a], R(0));
           for (int d = 0; d < ND; ++d)
             for (int a = 0; a < NV; ++a) q[d][a] = DT(qs[(g * ND + d) * NV + a], (qd == d && a == c) ? R(1) : R(0));
           flux_viscous<SYS, ND, NV, DT>(ph, u, q, fv);
-          R wgt = side ? cR : cL;
+          const R wgt = side ? cR : cL;
           for (int a = 0; a < NV; ++a) {
             R acc = R(0);
             for (int d = 0; d < ND; ++d) acc += nn[d] * fv[d][a].d;
             acc *= wgt;
-            if (qd < 0) (side ? vR : vL)[g * NV2 + a * NV + c] = acc;
-            else (side ? qRt : qLt)[(qd * NF + g) * NV2 + a * NV + c] = acc;
+            tfT[Y::fi(g, 2 + side * ND + qd, Y::pidx(a, c))] = mg * acc;
           }
         }
       }
     }
-    sync();
     if (!visc)
       for (int i = tid; i < NV2 * NS * ND; i += nth) {
         const int ab = i / (NS * ND), r = i % (NS * ND);
         for (int e = 0; e < ND; ++e) tbT[Y::ti(r / ND, r % ND, e, Y::pidx(ab / NV, ab % NV))] = R(0);
       }
-    if (visc)
-      for (int i = tid; i < NV2 * NS * ND * ND; i += nth) {
-        int ab = i / (NS * ND * ND), t = (i / (ND * ND)) % NS, d = (i / ND) % ND, e = i % ND;
-        R acc = R(0);
-        for (int k = 0; k < ND; ++k) {
-          R s = sS[(t * ND + d) * ND + k];
-          for (int d2 = 0; d2 < ND; ++d2) acc += s * bh[((d2 * ND + k) * NS + t) * NV2 + ab] * sJi[(t * ND + e) * ND + d2];
-        }
-        tbT[Y::ti(t, d, e, Y::pidx(ab / NV, ab % NV))] = acc;
-      }
-    for (int i = tid; i < NV2 * NF; i += nth) {
-      int ab = i / NF, g = i % NF;
-      int a = ab / NV, c = ab % NV;
-      R mg = smg[g];
-      R id = (a == c) ? eta : R(0);
-      const int m = Y::pidx(a, c);
-      tfT[Y::fi(g, 0, m)] = mg * (rL[g * NV2 + ab] + (visc ? vL[g * NV2 + ab] + id : R(0)));
-      tfT[Y::fi(g, 1, m)] = mg * (rR[g * NV2 + ab] + (visc ? vR[g * NV2 + ab] - id : R(0)));
-      for (int d = 0; d < ND; ++d) {
-        tfT[Y::fi(g, 2 + d, m)] = visc ? mg * qLt[(d * NF + g) * NV2 + ab] : R(0);
-        tfT[Y::fi(g, 2 + ND + d, m)] = visc ? mg * qRt[(d * NF + g) * NV2 + ab] : R(0);
-      }
-    }
     sync();
   }
 
