@@ -5,22 +5,23 @@
 //   J = -rdet (.) ( sum_d Dc_d X_d + Cor Y ),
 //   X_d[tau] = sum_k T_d[tau][k] G_k[tau]   (k: Gam_0 .. Gam_{ND-1}, delta),
 //   Y[g]     = sum_j W[g][j] S_j[g]          (j: DL, DR, SL_d.., SR_d..),
-// where T, W are the pointwise Jacobian tables (rows m = alpha*NV + beta) and
+// where T, W are the pointwise Jacobian tables (rows m: variable pairs) and
 // G, S the sensitivities of the gradient and face states to U_k (columns
 // sigma).  For fixed tau (or g) the contraction over k (or j) is a
-// (pairs x k) . (k x sigma) product: one 16x16x4 MFMA per (tau, d) and two
-// per g.  The 1-D factors Dc1 (along the d-lines through tau) and h+- (along
-// g's normal line) then scatter X and Y into 16x16 accumulator tiles per
-// solution point rho, as scalar-constant FMAs (the indices are compile-time,
-// so the factors live in scalar registers).  One wavefront per (block,
-// pair tile, sigma tile) task.
+// (pairs x k) . (k x sigma) product: one 16x16x4 MFMA per (tau, d) and one
+// per group of four j at g.  The 1-D factors Dc1 (along the d-lines through
+// tau) and h+- (along g's normal line) then scatter X and Y into 16x16
+// accumulator tiles per solution point rho, as FMAs with compile-time
+// indices (hexahedra: one slab of points per task; the factors of lines
+// crossing the slab go into the A operand instead).
 //
 // Three kernels: the sensitivities G, S depend on the geometry only and are
-// computed once per mesh (jac_mf_sens_body); the tables T, W of a state are
-// computed per element (jac_mf_tables_body); the assembly (jac_mf_task) is
-// one wavefront per task with no LDS: every MFMA fragment is one coalesced
-// 256-byte read (operand index fastest in memory) of those arrays, and the
-// outputs are written straight from the accumulators.
+// computed once per mesh (jac_mf_sens_body; their geometry-free rows are
+// shared between blocks with the same face-point pairing); the tables T, W
+// of a state are computed per element (jac_mf_tables_body); the assembly
+// (jac_mf_task) runs one wavefront per (element, block, pair tile, sigma
+// tile, slab) task, fetching four points' MFMA operands per 16-byte load
+// and staging the finished tile through LDS for contiguous stores.
 #pragma once
 #include <type_traits>
 
