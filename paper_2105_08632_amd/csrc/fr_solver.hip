@@ -243,9 +243,12 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
 // right-looking LU with partial pivoting (panels of kLuNB columns factorized
 // in LDS; the panel's row exchanges applied to every other column; U12 by a
 // triangular solve; A22 -= L21 U12 from LDS-staged operands in 4 x 4
-// register tiles), one workgroup per element.  The preconditioner applies
-// the factors by forward and backward substitution.
-constexpr int kLuThreads = 512, kLuNB = 32, kLuMaxB = 320;
+// register tiles), one workgroup per element, two resident per CU.  The
+// preconditioner applies the factors by forward and backward substitution.
+// 16-column panels keep the workgroup's LDS under half the CU's 160 KB: two
+// workgroups per CU hide each other's barrier waits (75 -> 53 ms for 13 824
+// blocks of 320, against 32-column panels at one workgroup per CU)
+constexpr int kLuThreads = 512, kLuNB = 16, kLuMaxB = 320;
 
 // Wave-uniform lane l's value of v.
 __device__ __forceinline__ double fr_readlane(double v, int l) {
@@ -267,8 +270,8 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
   __shared__ double red_v[kLuThreads / 64];
   __shared__ int red_i[kLuThreads / 64];
   __shared__ int s_piv[kLuMaxB];                      // row exchanged with row k at step k
-  __shared__ int s_perm[kLuMaxB];
   __shared__ int s_bad;
+  __shared__ int s_mv_dst[2 * kLuNB], s_mv_src[2 * kLuNB], s_nmv;   // a panel's row moves
   const int n = list ? list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const long bb = (long)b * b;
   const IT* Jn = J + (long)n * jstride;
@@ -331,19 +334,50 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
       const int j = i / m, r = i % m;
       A[(long)(k0 + j) * b + k0 + r] = P[j * LD + r];
     }
-    // the panel's row exchanges, in order, on every other column
-    for (int c = tid; c < b - w; c += kLuThreads) {
-      double* Ac = A + (long)(c < k0 ? c : c + w) * b;
-      for (int j = 0; j < w; ++j) {
-        const int p = s_piv[k0 + j];
-        if (p != k0 + j) {
-          const double t = Ac[k0 + j];
-          Ac[k0 + j] = Ac[p];
-          Ac[p] = t;
+    // the panel's row exchanges on every other column, composed into one
+    // row permutation: the list of (destination, source) moves (at most
+    // 2 kLuNB rows), then each column loads all its sources before storing
+    // (one memory round trip instead of a chain of dependent exchanges)
+    {
+      // the exchanges applied to the index of each row k0 .. b-1 (in the idle
+      // U12 buffer), then the moved rows compacted into the list
+      int* perm_k = reinterpret_cast<int*>(Ut);
+      for (int i = tid; i < m; i += kLuThreads) perm_k[i] = i;
+      if (tid == 0) s_nmv = 0;
+      __syncthreads();
+      if (tid == 0)
+        for (int j = 0; j < w; ++j) {
+          const int q = s_piv[k0 + j] - k0, t = perm_k[j];
+          perm_k[j] = perm_k[q];
+          perm_k[q] = t;
         }
-      }
+      __syncthreads();
+      for (int i = tid; i < m; i += kLuThreads)
+        if (perm_k[i] != i) {
+          const int slot = atomicAdd(&s_nmv, 1);     // at most 2 kLuNB rows move
+          s_mv_dst[slot] = k0 + i;
+          s_mv_src[slot] = k0 + perm_k[i];
+        }
     }
     __syncthreads();
+    {
+      // one column per thread; its sources are staged in the idle U12
+      // buffer (nm slots per column, as many columns per pass as fit), so
+      // every load is issued before any store.  The panel buffer still holds
+      // L11 and L21 for what follows.
+      static_assert(kLuMaxB - kLuNB <= kLuThreads, "one column per thread");
+      const int nm = s_nmv, c = tid;
+      const int cpp = nm > 0 ? (kLuMaxB - kLuNB) * kLuNB / nm : kLuThreads;   // columns per pass
+      for (int c0 = 0; c0 < b - w; c0 += cpp) {                          // uniform trip count
+        if (c >= c0 && c < c0 + cpp && c < b - w) {
+          double* Ac = A + (long)(c < k0 ? c : c + w) * b;
+          double* st = Ut + (c - c0) * nm;
+          for (int i = 0; i < nm; ++i) st[i] = Ac[s_mv_src[i]];
+          for (int i = 0; i < nm; ++i) Ac[s_mv_dst[i]] = st[i];
+        }
+        __syncthreads();
+      }
+    }
     const int n2 = b - k0 - w;
     if (n2 > 0) {
       // U12 = L11^-1 A12, one column per thread (L11[r][q] = P[q LD + r]);
@@ -407,6 +441,7 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
       __syncthreads();
     }
   }
+  int* s_perm = reinterpret_cast<int*>(Ut);           // U12 is no longer needed
   if (tid == 0) {
     // (P r)[i] = r[perm[i]]: the recorded exchanges applied to the identity
     for (int i = 0; i < b; ++i) s_perm[i] = i;
