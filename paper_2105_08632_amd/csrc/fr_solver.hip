@@ -257,13 +257,16 @@ __device__ __forceinline__ double fr_readlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// A = shift I + scale J (column-major, input type IT) factorized as P A = L U
-// (unit lower L and upper U stored over A in LU, column-major); perm[i] is
-// the row of A that P moves to row i.  bad[n] = 1 when a pivot is zero or not
-// finite.
+// A = shift I + scale J (column-major, input type IT) factorized with partial
+// pivoting: unit lower L and upper U stored over A in LU (column-major);
+// piv[k] is the row exchanged with row k at step k.  Each panel's L columns
+// keep the row order reached at that panel (later exchanges are not applied
+// to them), so A = P_1 L_1 P_2 L_2 ... U with P_p the exchanges of panel p
+// and L_p the unit lower factor of its columns.  bad[n] = 1 when a pivot is
+// zero or not finite.
 template <class IT>
 __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
-                                                         double* LU, int* perm, int* bad, const int* list) {
+                                                         double* LU, int* piv, int* bad, const int* list) {
   constexpr int LD = kLuMaxB;                         // panel leading dimension (constant offsets)
   __shared__ double P[kLuMaxB * kLuNB];               // panel rows k0.., column-major
   __shared__ double Ut[(kLuMaxB - kLuNB) * kLuNB];    // U12, column c at c * kLuNB
@@ -334,10 +337,13 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
       const int j = i / m, r = i % m;
       A[(long)(k0 + j) * b + k0 + r] = P[j * LD + r];
     }
-    // the panel's row exchanges on every other column, composed into one
-    // row permutation: the list of (destination, source) moves (at most
-    // 2 kLuNB rows), then each column loads all its sources before storing
-    // (one memory round trip instead of a chain of dependent exchanges)
+    // the panel's row exchanges on the trailing columns (the factored L
+    // columns to the left keep the row order of their own panel; the
+    // substitution applies each panel's exchanges before its columns),
+    // composed into one row permutation: the list of (destination, source)
+    // moves (at most 2 kLuNB rows), then each column loads all its sources
+    // before storing (one memory round trip instead of a chain of dependent
+    // exchanges)
     {
       // the exchanges applied to the index of each row k0 .. b-1 (in the idle
       // U12 buffer), then the moved rows compacted into the list
@@ -368,9 +374,10 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
       static_assert(kLuMaxB - kLuNB <= kLuThreads, "one column per thread");
       const int nm = s_nmv, c = tid;
       const int cpp = nm > 0 ? (kLuMaxB - kLuNB) * kLuNB / nm : kLuThreads;   // columns per pass
-      for (int c0 = 0; c0 < b - w; c0 += cpp) {                          // uniform trip count
-        if (c >= c0 && c < c0 + cpp && c < b - w) {
-          double* Ac = A + (long)(c < k0 ? c : c + w) * b;
+      const int nc = b - k0 - w;                                         // trailing columns
+      for (int c0 = 0; c0 < nc; c0 += cpp) {                             // uniform trip count
+        if (c >= c0 && c < c0 + cpp && c < nc) {
+          double* Ac = A + (long)(k0 + w + c) * b;
           double* st = Ut + (c - c0) * nm;
           for (int i = 0; i < nm; ++i) st[i] = Ac[s_mv_src[i]];
           for (int i = 0; i < nm; ++i) Ac[s_mv_dst[i]] = st[i];
@@ -441,45 +448,58 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
       __syncthreads();
     }
   }
-  int* s_perm = reinterpret_cast<int*>(Ut);           // U12 is no longer needed
-  if (tid == 0) {
-    // (P r)[i] = r[perm[i]]: the recorded exchanges applied to the identity
-    for (int i = 0; i < b; ++i) s_perm[i] = i;
-    for (int k = 0; k < b; ++k) {
-      const int p = s_piv[k], t = s_perm[k];
-      s_perm[k] = s_perm[p];
-      s_perm[p] = t;
-    }
-    bad[n] = s_bad;
-  }
-  __syncthreads();
-  for (int i = tid; i < b; i += kLuThreads) perm[(long)n * b + i] = s_perm[i];
+  if (tid == 0) bad[n] = s_bad;
+  for (int i = tid; i < b; i += kLuThreads) piv[(long)n * b + i] = s_piv[i];
 }
 
-// z_n = U_n^-1 L_n^-1 (P_n r_n): one wavefront per element, rows lane + 64 q
-// of the vector in registers, each substitution step's value broadcast from
-// the lane that owns it (columns of L and U are contiguous runs).
+// z_n = A_n^-1 r_n from the factors: one wavefront per element, rows
+// lane + 64 q of the vector in registers, each substitution step's value
+// broadcast from the lane that owns it (columns of L and U are contiguous
+// runs); each panel's row exchanges are applied to the vector just before
+// its columns eliminate (A = P_1 L_1 P_2 L_2 ... U).
 template <class VT>
-__global__ void __launch_bounds__(256) k_block_lu_apply(long ne, int b, const double* LU, const int* perm, const VT* r,
+__global__ void __launch_bounds__(256) k_block_lu_apply(long ne, int b, const double* LU, const int* piv, const VT* r,
                                                         VT* z) {
   constexpr int QM = (kLuMaxB + 63) / 64;
+  static_assert(64 % kLuNB == 0, "a panel lies in one 64-row block of the vector");
   const int lane = threadIdx.x & 63;
   const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= ne) return;
   const double* A = LU + n * b * b;
-  const int* pn = perm + n * b;
+  const int* pn = piv + n * b;
   const VT* rn = r + n * b;
   double y[QM];
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const int row = lane + 64 * q;
-    y[q] = row < b ? (double)rn[pn[row]] : 0.0;
+    y[q] = row < b ? (double)rn[row] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const int jend = min(64, b - 64 * q);
     for (int jl = 0; jl < jend; ++jl) {
       const int j = 64 * q + jl;
+      if (jl % kLuNB == 0) {
+        // this panel's exchanges, in order (rows j .. j + kLuNB - 1 with their
+        // pivot rows, which lie at or below them)
+        const int je = min(j + kLuNB, b);
+        for (int jj = j; jj < je; ++jj) {
+          const int p = pn[jj];
+          if (p != jj) {
+            const int lj = jj & 63, qp = p >> 6, lp = p & 63;
+            const double a = fr_readlane(y[q], lj);
+            double ysel = y[q];
+#pragma unroll
+            for (int qq = q + 1; qq < QM; ++qq)
+              if (qq == qp) ysel = y[qq];
+            const double bv = fr_readlane(ysel, lp);
+            if (lane == lj) y[q] = bv;
+#pragma unroll
+            for (int qq = q; qq < QM; ++qq)
+              if (qq == qp && lane == lp) y[qq] = a;
+          }
+        }
+      }
       const double yj = fr_readlane(y[q], jl);
       const double* Lc = A + (long)j * b;
 #pragma unroll
@@ -550,13 +570,13 @@ fr_status pc_invert(fr_precond_s* pc, double shift, double scale, const int* lis
       hipLaunchKernelGGL((k_block_inverse<float, 128>), dim3(count), dim3(kInvThreads), 0, c->stream,
                          (const float*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
   } else if (b <= kLuMaxB) {
-    if (!pc->perm) return sfail(c, FR_E_INVALID, "preconditioner without pivot storage");
+    if (!pc->piv) return sfail(c, FR_E_INVALID, "preconditioner without pivot storage");
     if (c->prec == 0)
       hipLaunchKernelGGL((k_block_lu<double>), dim3(count), dim3(kLuThreads), 0, c->stream, (const double*)J, bb, b,
-                         shift, scale, pc->inv, pc->perm, pc->bad, list);
+                         shift, scale, pc->inv, pc->piv, pc->bad, list);
     else
       hipLaunchKernelGGL((k_block_lu<float>), dim3(count), dim3(kLuThreads), 0, c->stream, (const float*)J, bb, b,
-                         shift, scale, pc->inv, pc->perm, pc->bad, list);
+                         shift, scale, pc->inv, pc->piv, pc->bad, list);
   } else {
     return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
   }
@@ -588,10 +608,10 @@ fr_status pc_lu_apply(fr_precond_s* pc, const void* r, void* z) {
   const int grid = (int)((ne + 3) / 4);
   if (c->b > 128) {
     if (c->prec == 0)
-      hipLaunchKernelGGL((k_block_lu_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->perm,
+      hipLaunchKernelGGL((k_block_lu_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->piv,
                          (const double*)r, (double*)z);
     else
-      hipLaunchKernelGGL((k_block_lu_apply<float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->perm,
+      hipLaunchKernelGGL((k_block_lu_apply<float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv, pc->piv,
                          (const float*)r, (float*)z);
   } else if (c->prec == 0)
     hipLaunchKernelGGL((k_block_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, pc->inv,
@@ -890,7 +910,7 @@ fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
   pc->jbuf = pc->mem;
   pc->inv = (double*)((char*)pc->mem + off_inv);
   pc->bad = (int*)((char*)pc->mem + off_bad);
-  pc->perm = lu ? (int*)((char*)pc->mem + off_perm) : nullptr;
+  pc->piv = lu ? (int*)((char*)pc->mem + off_perm) : nullptr;
   if (hipHostMalloc((void**)&pc->bad_host, ne * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     (void)hipFree(pc->mem); delete pc; return sfail(c, FR_E_NOMEM, "pinned flags");
   }

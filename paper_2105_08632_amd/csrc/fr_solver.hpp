@@ -11,7 +11,7 @@ struct fr_precond_s {
   void* mem = nullptr;
   void* jbuf = nullptr;      // diagonal blocks, context precision
   double* inv = nullptr;     // [ne][b][b] column-major inverses (FP64); LU factors when b > 128
-  int* perm = nullptr;       // [ne][b] row order of the LU factors (b > 128)
+  int* piv = nullptr;        // [ne][b] pivot rows of the LU factors (b > 128)
   int* bad = nullptr;        // [ne] singular-pivot flags
   int* bad_host = nullptr;   // pinned copy
   bool ready = false;
