@@ -79,3 +79,20 @@ def test_cfg2_full_size_block_lu():
     on sampled elements."""
     n = 24 ** 3
     assert _check(24, 3, [int(np.random.default_rng(1).integers(n)), n - 1], 5.0) == 320
+
+
+def test_large_block_singular_is_reported():
+    """An all-zero block (shift = scale = 0) on the b > 128 path is reported
+    as singular, naming the first element, and apply refuses to run."""
+    from paper_2105_08632_amd import fr
+    m = I.hex_mesh(4, degree=2, jitter=0.05, K=1)
+    ph = I.ns_physics(3, 50.0, 0.71)
+    U = I.tgv_state(m, 2, L=1.0 / (2 * np.pi))
+    ctx = fr.Context(m, ph, "f32")
+    Ud = torch.from_numpy(U).float().cuda().contiguous()
+    pc = fr.Precond(ctx)
+    with pytest.raises(fr.FrError) as ei:
+        pc.setup(Ud, 0.0, 0.0)
+    assert ei.value.status == -5 and "element 0" in str(ei.value)
+    with pytest.raises(fr.FrError):
+        pc.apply(Ud)
