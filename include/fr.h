@@ -138,11 +138,15 @@ typedef enum { FR_PC_BLOCK_JACOBI = 0, FR_PC_MLP = 1 } fr_pc_kind;
 
 /* Block preconditioner over the diagonal Jacobian blocks of the face stencil
  * (eq. "jacobian_rhs", k = n).  FR_PC_BLOCK_JACOBI: A_n = shift I + scale
- * dR_n/dU_n is inverted in FP64 by Gauss-Jordan elimination with partial
- * pivoting (blocks up to 128 x 128); FR_PC_MLP: the learned approximate
- * inverse (network attached with fr_precond_set_mlp), with block-Jacobi as
- * the per-element fallback.
- * Storage for the inverses is allocated here, not in setup/apply. */
+ * dR_n/dU_n in FP64 with partial pivoting: blocks up to 128 x 128 inverted
+ * by Gauss-Jordan elimination and applied as explicit inverses, blocks from
+ * 129 to 320 (hexahedra of degree 2 and 3) factorized by a blocked LU and
+ * applied by substitution; larger blocks return FR_E_UNSUPPORTED.
+ * FR_PC_MLP: the learned approximate inverse (network attached with
+ * fr_precond_set_mlp; blocks up to 128), with block-Jacobi as the
+ * per-element fallback.
+ * Storage for the inverses / factors (FP64, n_elem * b * b) is allocated
+ * here, not in setup/apply. */
 fr_status fr_precond_create(fr_ctx* ctx, fr_pc_kind kind, fr_precond** out);
 /* Assembles and inverts the diagonal blocks at state U (device, context
  * precision).  Backward Euler: shift = 1, scale = -dt.  Returns

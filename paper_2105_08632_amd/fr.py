@@ -229,7 +229,8 @@ EXPORTED += ["fr_precond_create", "fr_precond_setup", "fr_apply_precond", "fr_pr
 
 
 class Precond:
-    """Block preconditioner (block-Jacobi FP64 inverse, or the learned MLP)."""
+    """Block preconditioner (block-Jacobi in FP64: explicit inverses up to
+    b = 128, LU factors up to b = 320; or the learned MLP)."""
 
     def __init__(self, ctx: Context, kind: int = FR_PC_BLOCK_JACOBI):
         self.ctx = ctx
