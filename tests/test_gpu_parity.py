@@ -152,6 +152,61 @@ def _rotate_quads(m, seed):
     return r, sh
 
 
+def _rotate_hexes(m, seed):
+    """The same hex mesh with each element's local frame turned by a seeded
+    random proper rotation of the reference cube (one of 24): vertices and
+    face data permuted to match, neighbour face indices remapped.  Faces
+    0..5 are z-, y-, x+, y+, x-, z+; vertex v is corner offs[v]."""
+    import copy
+    import itertools
+    offs = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
+    corner = 2 * offs - 1
+    face_of = {(2, -1): 0, (1, -1): 1, (0, 1): 2, (1, 1): 3, (0, -1): 4, (2, 1): 5}
+    axis_sign = {f: k for k, f in face_of.items()}
+    rots = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((-1, 1), repeat=3):
+            R = np.zeros((3, 3), int)
+            for i in range(3):
+                R[i, perm[i]] = signs[i]
+            if round(np.linalg.det(R)) == 1:
+                rots.append(R)
+    assert len(rots) == 24
+    r = copy.deepcopy(m)
+    pick = np.random.default_rng(seed).integers(0, 24, m.n_elem)
+    tau = np.zeros((m.n_elem, 6), int)     # new face -> old face
+    for e in range(m.n_elem):
+        R = rots[pick[e]]
+        sig = [int(np.where((corner == R.T @ corner[v]).all(axis=1))[0][0]) for v in range(8)]
+        r.xyz[e] = m.xyz[e][sig]
+        for f in range(6):
+            a, sg = axis_sign[f]
+            old = R.T @ (sg * np.eye(3, dtype=int)[a])
+            ao = int(np.nonzero(old)[0][0])
+            tau[e, f] = face_of[(ao, int(old[ao]))]
+        r.nbr[e] = m.nbr[e][tau[e]]
+        r.nbr_face[e] = m.nbr_face[e][tau[e]]
+    for e in range(m.n_elem):
+        for f in range(6):
+            nb, fo = int(r.nbr[e, f]), int(r.nbr_face[e, f])
+            r.nbr_face[e, f] = int(np.nonzero(tau[nb] == fo)[0][0])
+    return r, pick
+
+
+@pytest.mark.parametrize("p,elems", [(2, [0, 21, 63]), (3, [42])])
+def test_hex_fp32_rotated_frames(p, elems):
+    """Matrix-core path on hexes with rotated local frames (up to 8 face
+    orientations): the shared geometry-free sensitivities must follow each
+    block's own face-point pairing."""
+    m0 = I.hex_mesh(4, degree=p, jitter=0.05, K=1)
+    m, pick = _rotate_hexes(m0, 5)
+    assert len(set(pick.tolist())) > 12
+    ph = I.ns_physics(3, 50.0, 0.71)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    out = check_case(m, ph, p, U, "f32", elems)
+    _assert(out, "f32", p)
+
+
 @pytest.mark.parametrize("p", [2, 3])
 def test_quad_fp32_rotated_frames(p):
     """Matrix-core path on elements with rotated local frames: blocks whose
