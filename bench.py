@@ -157,6 +157,27 @@ def newton_bench(torch, fr, I, train_steps, log):
                 log(f"newton cfl 100 {name}: conv {r['converged']} rel {r['res'] / r['res0']:.2e}")
             out["cfl100"] = hard
         del sol, pcm, ctx
+    # CFL 100 on 64x64, where GMRES(30) with a one-level block preconditioner
+    # still converges; plain and loose GMRES (3 of each cycle's 30 directions
+    # are earlier cycles' corrections)
+    m64 = I.quad_mesh(64, degree=3, jitter=0.05)
+    U = I.ns2d_state(m64, 3, seeds=(8, 108, 208))
+    ctx = fr.Context(m64, ph, "f64")
+    Ud = torch.from_numpy(U).cuda()
+    sol = fr.Solver(ctx, restart=30)
+    pcm = fr.Precond(ctx, fr.FR_PC_MLP)
+    pcm.set_mlp(net, 1e30)
+    pcl = fr.Precond(ctx)
+    small = {}
+    for name, pc, aug in (("lu", pcl, 0), ("lu_loose3", pcl, 3), ("mlp", pcm, 0), ("mlp_loose3", pcm, 3)):
+        r = sol.newton_step(Ud, pc=pc, dt=_dt(m64, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False,
+                            augment=aug)
+        small[name] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
+                       "gmres_iters": r["gmres_iters"], "final_rel_residual": r["res"] / r["res0"],
+                       "s": round(r["ms"] / 1e3, 3)}
+        log(f"newton cfl 100 64x64 {name}: conv {r['converged']} gmres {r['gmres_iters']} s {r['ms'] / 1e3:.3f}")
+    out["cfl100_64x64"] = small
+    del sol, pcm, pcl, ctx
     for name, rs in runs.items():
         out[name] = {"s_per_step_median": round(float(np.median([r["ms"] for r in rs])) / 1e3, 4),
                      "converged": [bool(r["converged"]) for r in rs],

@@ -213,6 +213,13 @@ typedef struct {
   int32_t pc_refresh;     /* 0: preconditioner set up once at U^n; 1: at every Newton iterate */
   int32_t use_graph;      /* 1: each GMRES restart cycle is a replayed hipGraph (device-resident
                              Arnoldi, one host read per cycle); 0: host-driven Arnoldi */
+  int32_t gmres_augment;  /* k in 0..3.  0: plain restarted GMRES.  k > 0: loose GMRES (Baker,
+                             Jessup & Manteuffel 2005), the last k of each cycle's restart
+                             directions are the corrections of the k previous cycles; the
+                             subspace stays restart wide.  Runs the host-driven Arnoldi (use_graph
+                             is ignored).  Out of range: FR_E_INVALID. */
+  int32_t gmres_stall;    /* a linear solve also stops when its true residual fell by less than
+                             1% over this many restart cycles; 0 means 4.  Negative: FR_E_INVALID. */
 } fr_newton_opts;
 typedef struct {
   int32_t newton_iters, gmres_iters, pc_setups, converged;

@@ -140,6 +140,7 @@ __global__ void k_axpby(long n, double a, const double* x, double b, const doubl
 }
 
 constexpr int kDotBlocks = 1024;
+constexpr int kAugMax = 3;          // stored corrections of loose GMRES
 constexpr int kDotThreads = 256;
 
 // partial[blk][j] = sum over the block's slice of V_j . w, j < k (V_j = V + j*ld)
@@ -630,6 +631,8 @@ struct fr_solver_s {
   long N = 0;
   void* mem = nullptr;
   double *V = nullptr, *Z = nullptr, *w = nullptr, *x = nullptr, *F = nullptr, *R = nullptr, *tmp = nullptr;
+  double* Aug = nullptr;   // kAugMax + 1 stored cycle corrections (loose GMRES)
+  int stall = 4;           // stagnation window in restart cycles
   double *partial = nullptr, *dots = nullptr, *hcol = nullptr;
   double* host = nullptr;   // pinned scalars
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -677,12 +680,22 @@ static fr_status precond(fr_solver_s* s, fr_precond_s* pc, const double* v, doub
 }
 
 // GMRES(m) on A x = rhs from x = 0; returns iterations, true residual norm.
+// With aug = k > 0 this is loose GMRES, LGMRES(m - k, k) (Baker, Jessup and
+// Manteuffel, SIAM J. Matrix Anal. Appl. 26, 2005): the last k directions of
+// every cycle are the corrections x_i - x_{i-1} of the k previous cycles,
+// newest first, in place of preconditioned Arnoldi vectors.  The flexible
+// form A Z = V H stays exact for any choice of Z's columns, so the cycle's
+// minimisation and update are unchanged; the subspace is still m wide.
 static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt, const double* rhs, double rtol,
-                       int maxit, double* x, int* iters, double* res_true, double* res0_out) {
+                       int maxit, int aug, double* x, int* iters, double* res_true, double* res0_out) {
   fr_ctx_s* c = s->ctx;
   const int m = s->m;
   const long N = s->N;
   std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hj(m + 1), hj2(m + 1), y(m);
+  aug = std::min(aug, m - 1);
+  std::vector<int> order;              // slots of the stored corrections, newest first
+  double aug_norm[kAugMax + 1] = {};
+  int ring = 0;
   hipLaunchKernelGGL(k_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 0.0, x);
   // r0 = rhs (x = 0)
   HIPCHK(c, hipMemcpyAsync(s->w, rhs, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -704,10 +717,16 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
     g[0] = beta;
     int j = 0;
     double est = beta;
+    const int mk = m - (int)order.size();   // directions from the preconditioned Arnoldi vectors
     for (; j < m && total < maxit; ++j, ++total) {
       double* vj = s->V + (long)j * N;
       double* zj = s->Z + (long)j * N;
-      if ((st = precond(s, pc, vj, zj))) return st;
+      if (j < mk) {
+        if ((st = precond(s, pc, vj, zj))) return st;
+      } else {
+        const int slot = order[j - mk];
+        if ((st = axpby(s, 1.0 / aug_norm[slot], s->Aug + (long)slot * N, 0.0, nullptr, zj))) return st;
+      }
       if ((st = apply_A(s, U, dt, zj, s->w, nullptr))) return st;
       // classical Gram-Schmidt, twice
       if ((st = dots(s, j + 1, s->V, s->w, hj.data()))) return st;
@@ -747,8 +766,27 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
       y[i] = acc / H[i * m + i];
     }
     HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), j * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, x);
-    HIPCHK(c, hipGetLastError());
+    if (aug > 0) {
+      // the cycle's correction d = Z y is kept for the next cycles (the ring
+      // has k + 1 slots, so the slot written is never one this cycle used)
+      double* d = s->Aug + (long)ring * N;
+      hipLaunchKernelGGL(k_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 0.0, d);
+      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, d);
+      HIPCHK(c, hipGetLastError());
+      if ((st = axpby(s, 1.0, x, 1.0, d, x))) return st;
+      double dn;
+      if ((st = dots(s, 1, d, d, &dn))) return st;
+      dn = std::sqrt(dn);
+      if (dn > 0.0 && std::isfinite(dn)) {
+        aug_norm[ring] = dn;
+        order.insert(order.begin(), ring);
+        if ((int)order.size() > aug) order.pop_back();
+        ring = (ring + 1) % (aug + 1);
+      }
+    } else {
+      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, x);
+      HIPCHK(c, hipGetLastError());
+    }
     // true residual r = rhs - A x
     if ((st = apply_A(s, U, dt, x, s->w, nullptr))) return st;
     if ((st = axpby(s, 1.0, rhs, -1.0, s->w, s->w))) return st;
@@ -756,10 +794,10 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
     beta = std::sqrt(nrm);
     *iters = total;
     *res_true = beta;
-    // stagnation: less than 1% reduction over the last four restart cycles
+    // stagnation: less than 1% reduction over the last s->stall restart cycles
     hist.push_back(beta);
     const size_t nh = hist.size();
-    const bool stalled = nh >= 5 && beta > 0.99 * hist[nh - 5];
+    const bool stalled = (int)nh > s->stall && beta > 0.99 * hist[nh - 1 - s->stall];
     if (beta <= rtol * b0 || total >= maxit || stalled) break;
   }
   return FR_OK;
@@ -883,7 +921,7 @@ static fr_status gmres_graph(fr_solver_s* s, fr_precond_s* pc, const double* U, 
     *res_true = beta;
     hist.push_back(beta);
     const size_t nh = hist.size();
-    const bool stalled = nh >= 5 && beta > 0.99 * hist[nh - 5];
+    const bool stalled = (int)nh > s->stall && beta > 0.99 * hist[nh - 1 - s->stall];
     if (beta <= rtol * b0 || work >= maxit || stalled || jj == 0) break;
   }
   return FR_OK;
@@ -951,12 +989,13 @@ fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
   fr_solver_s* s = new fr_solver_s();
   s->ctx = c; s->m = restart; s->N = c->ne * (long)c->b;
   const long N = s->N;
-  size_t doubles = (size_t)N * (2 * (restart + 1) + 5) + kDotBlocks * 32 + 64 + 64;
+  size_t doubles = (size_t)N * (2 * (restart + 1) + 5 + kAugMax + 1) + kDotBlocks * 32 + 64 + 64;
   if (hipMalloc(&s->mem, doubles * sizeof(double)) != hipSuccess) { delete s; return sfail(c, FR_E_NOMEM, "solver workspace"); }
   double* p = (double*)s->mem;
   s->V = p; p += N * (restart + 1);
   s->Z = p; p += N * (restart + 1);
   s->w = p; p += N; s->x = p; p += N; s->F = p; p += N; s->R = p; p += N; s->tmp = p; p += N;
+  s->Aug = p; p += N * (kAugMax + 1);
   s->partial = p; p += kDotBlocks * 32;
   s->dots = p; p += 64;
   s->hcol = p; p += 64;
@@ -1047,10 +1086,10 @@ static fr_status newton_body(fr_solver_s* s, fr_precond_s* pc, const void* Un_, 
     if ((rs = axpby(s, -1.0, s->F, 0.0, nullptr, s->F))) return rs;
     int gi = 0;
     double rt = 0.0, r0 = 0.0;
-    if (o->use_graph)
+    if (o->use_graph && o->gmres_augment == 0)
       rs = gmres_graph(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0, &st->cycles);
     else
-      rs = gmres(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, s->x, &gi, &rt, &r0);
+      rs = gmres(s, pc, U, o->dt, s->F, o->gmres_rtol, o->gmres_maxit, o->gmres_augment, s->x, &gi, &rt, &r0);
     if (rs) return rs;
     st->gmres_iters += gi;
     if (it < 32) st->gmres_hist[it] = gi;
@@ -1085,6 +1124,10 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
                          fr_newton_stats* st) {
   if (!s || !Un_ || !U_ || !o || !st) return FR_E_INVALID;
   fr_ctx_s* c = s->ctx;
+  if (o->gmres_augment < 0 || o->gmres_augment > kAugMax)
+    return sfail(c, FR_E_INVALID, "gmres_augment must be in 0..3");
+  if (o->gmres_stall < 0) return sfail(c, FR_E_INVALID, "gmres_stall must be >= 0");
+  s->stall = o->gmres_stall > 0 ? o->gmres_stall : 4;
   if (pc && pc->ctx != c) return sfail(c, FR_E_INVALID, "preconditioner belongs to another context");
   const hipStream_t orig = c->stream;
   HIPCHK(c, hipEventRecord(s->join0, orig));

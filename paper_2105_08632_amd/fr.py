@@ -199,7 +199,8 @@ FR_PC_BLOCK_JACOBI, FR_PC_MLP = 0, 1
 class _NewtonOpts(C.Structure):
     _fields_ = [("dt", C.c_double), ("newton_rtol", C.c_double), ("newton_maxit", C.c_int32),
                 ("gmres_rtol", C.c_double), ("gmres_maxit", C.c_int32), ("pc_refresh", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("gmres_augment", C.c_int32),
+                ("gmres_stall", C.c_int32)]
 
 
 class _NewtonStats(C.Structure):
@@ -269,9 +270,15 @@ class Solver:
 
     def newton_step(self, Un, U=None, pc: Precond | None = None, dt: float = 1e-3, newton_rtol: float = 1e-8,
                     newton_maxit: int = 20, gmres_rtol: float = 1e-3, gmres_maxit: int = 300,
-                    check: bool = True, pc_refresh: bool = False, use_graph: bool = False) -> dict:
+                    check: bool = True, pc_refresh: bool = False, use_graph: bool = False,
+                    augment: int = 0, stall_cycles: int = 0) -> dict:
+        """augment = k > 0 runs loose GMRES: each cycle's last k directions are
+        the corrections of the k previous cycles (host-driven Arnoldi).
+        stall_cycles: a linear solve stops when its true residual fell by less
+        than 1% over this many restart cycles (0: 4)."""
         U = self.ctx.empty_state() if U is None else self.ctx._vec(U)
-        o = _NewtonOpts(dt, newton_rtol, newton_maxit, gmres_rtol, gmres_maxit, int(pc_refresh), int(use_graph))
+        o = _NewtonOpts(dt, newton_rtol, newton_maxit, gmres_rtol, gmres_maxit, int(pc_refresh), int(use_graph),
+                        int(augment), int(stall_cycles))
         st = _NewtonStats()
         rc = lib().fr_newton_step(self.h, None if pc is None else pc.h, _ptr(self.ctx._vec(Un)), _ptr(U),
                                   C.byref(o), C.byref(st))

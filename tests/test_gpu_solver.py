@@ -132,3 +132,34 @@ def test_graph_replays_match_host_driven_gmres():
         du = (b["U"] - cur).abs().max().item()
         assert (a["U"] - b["U"]).abs().max().item() <= 1e-7 * du, step
         cur = b["U"].clone()
+
+
+def test_loose_gmres_matches_dense_newton():
+    """Loose GMRES (the last directions of each cycle are earlier cycles'
+    corrections): same root as the oracle's dense Newton, and the graph flag
+    falls back to the host-driven cycle."""
+    fr, m, ph, U, ctx, Ud = _setup(N=4, p=1)
+    dt = _dt(m, U, 20.0)
+    sol = fr.Solver(ctx, restart=10)
+    o = O.Oracle(m, ph, 1)
+    Ud_np = U.reshape(-1)
+    Uref, hist = ON.backward_euler_dense(o, Ud_np, dt, rtol=1e-12)
+    for use_pc, graph in ((True, False), (False, True)):
+        # Newton stops at |F| <= 1e-11 |F0|: with forcing 1e-4 a stop just below
+        # 1e-10 can leave the root error (about |A^-1| |F|) above the 1e-8 check
+        res = sol.newton_step(Ud, pc=fr.Precond(ctx) if use_pc else None, dt=dt, newton_rtol=1e-11,
+                              gmres_rtol=1e-4, gmres_maxit=400, augment=3, use_graph=graph)
+        assert res["converged"] == 1 and res["cycles"] == 0
+        Ug = res["U"].cpu().numpy().reshape(-1)
+        F = Ug - Ud_np - dt * o.rhs(Ug)
+        assert np.linalg.norm(F) <= 1e-9 * hist[0]
+        assert np.max(np.abs(Ug - Uref)) <= 1e-8 * np.max(np.abs(Uref - Ud_np))
+
+
+def test_newton_option_ranges_are_checked():
+    fr, m, ph, U, ctx, Ud = _setup(N=4, p=1)
+    sol = fr.Solver(ctx, restart=10)
+    for kw in ({"augment": 4}, {"augment": -1}, {"stall_cycles": -1}):
+        with pytest.raises(fr.FrError) as ei:
+            sol.newton_step(Ud, dt=1e-3, **kw)
+        assert ei.value.status == -1, kw
