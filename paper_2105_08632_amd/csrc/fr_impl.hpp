@@ -62,13 +62,14 @@ __global__ void __launch_bounds__(kThreads) k_jac_mf_tab(GeoD<R> geo, PhysP ph, 
 }
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>()))
-__attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R>()))) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
+__attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R, OT>()))) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
                                                                                 const R* tab, const R* sens,
                                                                                 const R* sigtab, const int* sig,
                                                                                 int nsb, int nblk, long ntasks, OT* B) {
   typedef MfSizes<E, NV, SYS> Y;
   constexpr int WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
   __shared__ __align__(16) R stage[WPB * STG];
+  __shared__ __align__(16) char xs[jac_mf_xs_bytes<E, NV, SYS, R, OT>()];
   const int wave = threadIdx.x >> 6;
   // Workgroups are dealt to the 8 XCDs in turn; renumber them so that each
   // XCD runs a contiguous range of tasks: the tasks of one (element, block)
@@ -84,7 +85,7 @@ __attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R>()))) k_jac_mf
   const int slab = sub % Y::SL, nt = (sub / Y::SL) % Y::NT, mt = sub / (Y::SL * Y::NT);
   R* stg = stage + wave * STG;
   const int lane = threadIdx.x & 63;
-  jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, sigtab, sig, nsb, nblk, B, stg,
+  jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, sigtab, sig, nsb, nblk, B, stg, xs,
                                  active);
 }
 

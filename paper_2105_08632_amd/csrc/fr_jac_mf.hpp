@@ -22,6 +22,9 @@
 // (jac_mf_task) runs one wavefront per (element, block, pair tile, sigma
 // tile, slab) task, fetching four points' MFMA operands per 16-byte load
 // and staging the finished tile through LDS for contiguous stores.
+// BF16 blocks of degree-3 elements take BF16 operands instead
+// (jac_mf_accum_bf16): each solution point's contributions of a family of
+// lines are one 16x16x32 product with the 1-D weights folded into A.
 #pragma once
 #include <type_traits>
 
@@ -98,7 +101,8 @@ template <class E, int NV, int SYS, class R> constexpr int jac_mf_stage() {
 // Resident waves per SIMD the register allocation aims for (degree 3: the
 // largest counts these tasks reach without spilling; elsewhere the hint
 // would only force spills).
-template <class E, int NV, int SYS, class R> constexpr int jac_mf_min_waves() {
+template <class E, int NV, int SYS, class R, class OT> constexpr int jac_mf_min_waves() {
+  if (std::is_same<OT, bf16_t>::value && E::DEG == 3) return 2;   // BF16 operands: two waves, no spills
   return E::DEG == 3 ? (E::ND == 3 ? 3 : 4) : 1;
 }
 // points (flux points) whose operands one load round trip fetches
@@ -109,6 +113,12 @@ template <class E, int NV, int SYS, class R> constexpr int jac_mf_wpb() {
   return (4 * jac_mf_stage<E, NV, SYS, R>() * (int)sizeof(R) <= 72 * 1024) ? 4 : 2;
 }
 
+// LDS of the third-axis operands a workgroup of hexahedral BF16 tasks shares
+template <class E, int NV, int SYS, class R, class OT> constexpr int jac_mf_xs_bytes() {
+  return (std::is_same<OT, bf16_t>::value && std::is_same<R, float>::value && E::DEG == 3 && E::ND == 3)
+             ? (4 * 4 * 4 * 16 * 4 + 2 * 2 * 4 * 4 * 16 * 4) * 4 + 4 * 4 * 4 * 16 * 16
+             : 16;
+}
 template <class E, int NV, int SYS, class R> constexpr int jac_mf_sens_lds() {
   typedef TPSizes<E, NV, SYS> Z;
   typedef MfSizes<E, NV, SYS> Y;
@@ -477,6 +487,229 @@ template <int CNT, int B4, class L1, class L4> __device__ __forceinline__ void m
 // computed before this point instead of being sunk towards their last use.
 template <class A> __device__ __forceinline__ void mf_pin(A& v) { asm volatile("" : "+v"(v)); }
 
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 mf_bf16x8;
+
+// BF16 blocks of degree-3 elements: BF16 operands on the 16x16x32 matrix
+// instruction, FP32 accumulation.  Its K = 32 holds every term one solution
+// point rho of the slab receives from a family of lines through it, with the
+// 1-D weight folded into the A operand, so nothing is scattered afterwards:
+//   1. the in-slab volume terms, sum_s Dc1[x][s] X_0[(s, y)] + Dc1[y][s] X_1[(x, s)];
+//   2. the in-slab faces, h+-(x) Y at both ends of rho's first-axis normal
+//      line and h+-(y) Y at both ends of its second-axis line;
+//   3. (hexahedra) the third-axis volume terms sum_c Dc1[z0][c] X_2[(x, y, c)]
+//      and both third-axis faces, h+-(z0) Y[(x, y)].
+// Lane group q = lane / 16 holds K entries 8 q .. 8 q + 7: the operand index
+// e = q of the 16x16x4 form (Gam_e / delta; face rows j = q and 4 + q) at
+// eight points, so the lanes load exactly the values of the FP32 form.
+template <class E, int NV, int SYS>
+__device__ __forceinline__ void jac_mf_accum_bf16(int z0, int kq, int mo, int so, const float (&dc)[4][4],
+                                                  const float (&hp)[4], const float (&hm)[4], const float* G,
+                                                  const float* tbT, const float* tfT, const float* Sr,
+                                                  const float* S, char* xs, typename Mfma<float>::acc* V) {
+  typedef MfSizes<E, NV, SYS> Y;
+  typedef TPIdx<E> X;
+  constexpr int ND = Y::ND, N1 = 4, SLS = Y::SLS, KV = Y::KV, JF = Y::JF, NFP = E::NFP;
+  static_assert(E::DEG == 3 && SLS == 16, "degree-3 elements, slabs of 16 points");
+  const int R0 = z0 * SLS;
+  const bool kin = kq < KV;
+  auto sface = [](int ax, bool pos) constexpr {   // in-slab face of axis ax, side pos
+    int f = 0;
+    for (int q = 0; q < E::NFACE; ++q)
+      if (X::fax(q) == ax && (X::fsg(q) > 0) == pos) f = q;
+    return f;
+  };
+  // flux point (face-local, slab-relative) of face f on rho's ax-line
+  auto ta_of = [](int f, int ax, int rho) constexpr {
+    int r = -1;
+    for (int ta = 0; ta < N1; ++ta)
+      if (X::fline(f * NFP + ta, X::co(rho, ax)) == rho) r = ta;
+    return r;
+  };
+  float gv[SLS], tv[2][SLS];                      // 1: G, T_0, T_1 of the slab points
+  float fa[2][2][2][N1], fb[2][2][2][N1];         // 2: W, S at the in-slab faces [axis][side][chunk][ta]
+  float tz[N1][4], gz[N1][4];                     // 3: T_2, G along the third axis [c][x]
+  float za[2][2][4], zb[2][2][4];                 // 3: W, S at the third-axis faces [side][chunk][x]
+  auto load1 = [&]() __attribute__((always_inline)) {
+    mf_for<0, SLS / 4>([&](auto Q) __attribute__((always_inline)) {
+      constexpr int i = 4 * decltype(Q)::value;
+      const int t = R0 + i;
+      if (kin) {
+        mf_ld4(G + Y::gi(t, kq, so), gv[i], gv[i + 1], gv[i + 2], gv[i + 3]);
+        mf_ld4(tbT + Y::ti(t, 0, kq, mo), tv[0][i], tv[0][i + 1], tv[0][i + 2], tv[0][i + 3]);
+        mf_ld4(tbT + Y::ti(t, 1, kq, mo), tv[1][i], tv[1][i + 1], tv[1][i + 2], tv[1][i + 3]);
+      } else {
+        gv[i] = gv[i + 1] = gv[i + 2] = gv[i + 3] = 0.f;
+        tv[0][i] = tv[0][i + 1] = tv[0][i + 2] = tv[0][i + 3] = 0.f;
+        tv[1][i] = tv[1][i + 1] = tv[1][i + 2] = tv[1][i + 3] = 0.f;
+      }
+    });
+  };
+  auto load2 = [&]() __attribute__((always_inline)) {
+    mf_for<0, 4>([&](auto AS) __attribute__((always_inline)) {
+      constexpr int ax = decltype(AS)::value / 2, sd = decltype(AS)::value % 2, f = sface(ax, sd == 1);
+      const int g = f * NFP + (ND == 3 ? N1 * z0 : 0);
+      mf_for<0, 2>([&](auto CC) __attribute__((always_inline)) {
+        constexpr int ch = decltype(CC)::value;
+        const int j = ch * 4 + kq;
+        if (j < JF) {
+          mf_ld4(tfT + Y::fi(g, j, mo), fa[ax][sd][ch][0], fa[ax][sd][ch][1], fa[ax][sd][ch][2], fa[ax][sd][ch][3]);
+          mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), fb[ax][sd][ch][0], fb[ax][sd][ch][1], fb[ax][sd][ch][2],
+                 fb[ax][sd][ch][3]);
+        } else {
+          fa[ax][sd][ch][0] = fa[ax][sd][ch][1] = fa[ax][sd][ch][2] = fa[ax][sd][ch][3] = 0.f;
+          fb[ax][sd][ch][0] = fb[ax][sd][ch][1] = fb[ax][sd][ch][2] = fb[ax][sd][ch][3] = 0.f;
+        }
+      });
+    });
+  };
+  // 1. volume, in-slab directions
+  auto comp1 = [&]() __attribute__((always_inline)) {
+    mf_for<0, SLS>([&](auto P) __attribute__((always_inline)) {
+      constexpr int rho = decltype(P)::value, cx = X::co(rho, 0), cy = X::co(rho, 1);
+      mf_bf16x8 a, b;
+      mf_for<0, N1>([&](auto Sx) __attribute__((always_inline)) {
+        constexpr int sx = decltype(Sx)::value, tx = X::line(rho, 0, sx), ty = X::line(rho, 1, sx);
+        a[sx] = (__bf16)(dc[cx][sx] * tv[0][tx]);
+        a[4 + sx] = (__bf16)(dc[cy][sx] * tv[1][ty]);
+        b[sx] = (__bf16)gv[tx];
+        b[4 + sx] = (__bf16)gv[ty];
+      });
+      V[rho] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, V[rho], 0, 0, 0);
+    });
+  };
+  // 2. faces whose normal lines lie in the slab: both ends of rho's lines
+  auto comp2 = [&]() __attribute__((always_inline)) {
+    mf_for<0, SLS>([&](auto P) __attribute__((always_inline)) {
+      constexpr int rho = decltype(P)::value;
+      mf_bf16x8 a, b;
+      mf_for<0, 8>([&](auto I) __attribute__((always_inline)) {
+        constexpr int i = decltype(I)::value, ax = i / 4, sd = (i / 2) % 2, ch = i % 2;
+        constexpr int f = sface(ax, sd == 1), ta = ta_of(f, ax, rho), w = X::co(rho, ax);
+        static_assert(ta >= 0, "every slab point lies on a normal line of each in-slab face");
+        a[i] = (__bf16)((sd == 1 ? hp[w] : hm[w]) * fa[ax][sd][ch][ta]);
+        b[i] = (__bf16)fb[ax][sd][ch][ta];
+      });
+      V[rho] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, V[rho], 0, 0, 0);
+    });
+  };
+  if constexpr (ND == 2) {
+    load1();
+    load2();
+    fr_sched_fence();
+    comp1();
+    fr_sched_fence();
+    comp2();
+    fr_sched_fence();
+  } else {
+    // 3. third axis, volume and faces, one row of the slab (four points) at
+    // a time
+    float wz[N1], hzm = hm[0], hzp = hp[0];
+    mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+      constexpr int c = decltype(Cc)::value;
+      wz[c] = dc[0][c];
+      mf_for<1, N1>([&](auto Z) __attribute__((always_inline)) {
+        if (z0 == decltype(Z)::value) wz[c] = dc[decltype(Z)::value][c];
+      });
+    });
+    mf_for<1, N1>([&](auto Z) __attribute__((always_inline)) {
+      if (z0 == decltype(Z)::value) { hzp = hp[decltype(Z)::value]; hzm = hm[decltype(Z)::value]; }
+    });
+    constexpr int fzm = 0, fzp = 5;
+    static_assert(X::fax(fzm) == 2 && X::fsg(fzm) < 0 && X::fax(fzp) == 2 && X::fsg(fzp) > 0, "third-axis faces");
+    mf_for<0, SLS>([&](auto Tq) __attribute__((always_inline)) {
+      constexpr int t = decltype(Tq)::value;
+      static_assert(X::fline(fzm * NFP + t, 0) % SLS == t && X::fline(fzp * NFP + t, 0) % SLS == t,
+                    "third-axis flux point t lies over slab point t");
+    });
+    // The four waves of a workgroup are the four slabs of one (element,
+    // block, pair tile, sigma tile) and read the same third-axis operands:
+    // each loads one row of them into LDS; A operands stay FP32 (their
+    // weights depend on the slab), B operands are stored as packed BF16.
+    static_assert(jac_mf_wpb<E, NV, SYS, float>() == Y::SL, "one workgroup = the slabs of one task column");
+    float* xT = reinterpret_cast<float*>(xs);                 // [c][y][e][m][x]
+    float* xW = xT + N1 * N1 * 4 * 16 * 4;                    // [side][chunk][y][e][m][x]
+    mf_bf16x8* xB = reinterpret_cast<mf_bf16x8*>(xW + 2 * 2 * N1 * 4 * 16 * 4);   // [y][x][e][sigma]
+    const int li = so & 15;
+    load1();
+    load2();
+    fr_sched_fence();
+    comp1();
+    fr_sched_fence();
+    {
+      const int r0 = N1 * z0;                                  // this wave's row: slab points r0 .. r0 + 3
+      float tz[N1][4], gz[N1][4], za[2][2][4], zb[2][2][4];
+      mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(Cc)::value;
+        const int t = c * SLS + r0;
+        mf_ld4(G + Y::gi(t, kq, so), gz[c][0], gz[c][1], gz[c][2], gz[c][3]);
+        mf_ld4(tbT + Y::ti(t, 2, kq, mo), tz[c][0], tz[c][1], tz[c][2], tz[c][3]);
+      });
+      mf_for<0, 4>([&](auto FC) __attribute__((always_inline)) {
+        constexpr int sd = decltype(FC)::value / 2, ch = decltype(FC)::value % 2;
+        const int g = (sd ? fzp : fzm) * NFP + r0;
+        const int j = ch * 4 + kq;   // JF = 8: every j is a face row
+        mf_ld4(tfT + Y::fi(g, j, mo), za[sd][ch][0], za[sd][ch][1], za[sd][ch][2], za[sd][ch][3]);
+        mf_ld4((j < 2 ? Sr : S) + Y::si(g, j, so), zb[sd][ch][0], zb[sd][ch][1], zb[sd][ch][2], zb[sd][ch][3]);
+      });
+      fr_sched_fence();
+      comp2();
+      fr_sched_fence();
+      mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(Cc)::value;
+        *reinterpret_cast<float4*>(xT + (((c * N1 + z0) * 4 + kq) * 16 + li) * 4) =
+            make_float4(tz[c][0], tz[c][1], tz[c][2], tz[c][3]);
+      });
+      mf_for<0, 4>([&](auto FC) __attribute__((always_inline)) {
+        constexpr int sd = decltype(FC)::value / 2, ch = decltype(FC)::value % 2;
+        *reinterpret_cast<float4*>(xW + ((((sd * 2 + ch) * N1 + z0) * 4 + kq) * 16 + li) * 4) =
+            make_float4(za[sd][ch][0], za[sd][ch][1], za[sd][ch][2], za[sd][ch][3]);
+      });
+      mf_for<0, 4>([&](auto Xc) __attribute__((always_inline)) {
+        constexpr int x = decltype(Xc)::value;
+        mf_bf16x8 b;
+        mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+          b[decltype(Cc)::value] = (__bf16)gz[decltype(Cc)::value][x];
+        });
+        mf_for<0, 4>([&](auto FC) __attribute__((always_inline)) {
+          constexpr int sd = decltype(FC)::value / 2, ch = decltype(FC)::value % 2;
+          b[4 + 2 * sd + ch] = (__bf16)zb[sd][ch][x];
+        });
+        xB[((z0 * 4 + x) * 4 + kq) * 16 + li] = b;
+      });
+    }
+    __syncthreads();
+    mf_for<0, N1>([&](auto Yr) __attribute__((always_inline)) {
+      constexpr int y = decltype(Yr)::value, r0 = N1 * y;
+      float tz[N1][4], za[2][2][4];
+      mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+        constexpr int c = decltype(Cc)::value;
+        const float4 v = *reinterpret_cast<const float4*>(xT + (((c * N1 + y) * 4 + kq) * 16 + li) * 4);
+        tz[c][0] = v.x; tz[c][1] = v.y; tz[c][2] = v.z; tz[c][3] = v.w;
+      });
+      mf_for<0, 4>([&](auto FC) __attribute__((always_inline)) {
+        constexpr int sd = decltype(FC)::value / 2, ch = decltype(FC)::value % 2;
+        const float4 v = *reinterpret_cast<const float4*>(xW + ((((sd * 2 + ch) * N1 + y) * 4 + kq) * 16 + li) * 4);
+        za[sd][ch][0] = v.x; za[sd][ch][1] = v.y; za[sd][ch][2] = v.z; za[sd][ch][3] = v.w;
+      });
+      mf_for<0, 4>([&](auto Xc) __attribute__((always_inline)) {
+        constexpr int x = decltype(Xc)::value;
+        const mf_bf16x8 b = xB[((y * 4 + x) * 4 + kq) * 16 + li];
+        mf_bf16x8 a;
+        mf_for<0, N1>([&](auto Cc) __attribute__((always_inline)) {
+          constexpr int c = decltype(Cc)::value;
+          a[c] = (__bf16)(wz[c] * tz[c][x]);
+        });
+        mf_for<0, 4>([&](auto FC) __attribute__((always_inline)) {
+          constexpr int sd = decltype(FC)::value / 2, ch = decltype(FC)::value % 2;
+          a[4 + 2 * sd + ch] = (__bf16)((sd ? hzp : hzm) * za[sd][ch][x]);
+        });
+        V[r0 + x] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, V[r0 + x], 0, 0, 0);
+      });
+      fr_sched_fence();
+    });
+  }
+}
+
 // One wavefront task: element n, block k, pair tile mt, sigma tile nt and
 // solution-point slab z0 (points whose third coordinate is z0; the whole
 // element for quadrilaterals).  MFMA fragments: A[m][k] from lane (m = lane %
@@ -493,7 +726,8 @@ template <class A> __device__ __forceinline__ void mf_pin(A& v) { asm volatile("
 template <class E, int NV, int SYS, class R, class OT>
 __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0, int lane, const Ops1D<R>& o1,
                                             const R* rdet, const R* tab, const R* sens, const R* sigtab,
-                                            const int* sig, int nsb, int nblk, OT* B, R* stage, bool active) {
+                                            const int* sig, int nsb, int nblk, OT* B, R* stage, char* xs,
+                                            bool active) {
   typedef MfSizes<E, NV, SYS> Y;
   typedef TPIdx<E> X;
   typedef Mfma<R> M;
@@ -528,6 +762,10 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   // lane offsets of the A (pair) and B (sigma) fragments
   const int mo = mt * 16 + li, so = nt * 16 + li;   // this lane's pair row and sigma column
   const bool kin = kq < KV;
+  constexpr bool kBf16Mfma = std::is_same<OT, bf16_t>::value && std::is_same<R, float>::value && E::DEG == 3;
+  if constexpr (kBf16Mfma) {
+    jac_mf_accum_bf16<E, NV, SYS>(z0, kq, mo, so, dc, hp, hm, G, tbT, tfT, Sr, S, xs, V);
+  } else {
   // Operands come straight from global memory: each chunk of up to 16
   // points (or flux points) issues its fragment loads at once (one memory
   // round trip), then computes; chunks bound the live registers.  After each
@@ -754,6 +992,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
       fr_sched_fence();
     });
   }
+  }   // FP32 operands
   // D rows are pairs m, columns sigma.  The task owns the columns (sigma in
   // tile nt, beta in pair tile mt) of block k and, in each, the contiguous
   // row segment (rho in the slab, every alpha): the tile goes through LDS

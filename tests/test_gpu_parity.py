@@ -267,6 +267,24 @@ def test_cfg2_full_size_fp32():
     _assert(out, "f32")
 
 
+def test_cfg2_full_size_bf16():
+    """The same 24^3 hex mesh with BF16 blocks (BF16 operands on the matrix
+    cores, FP32 accumulation), checked on a seeded sample of elements."""
+    p = 3
+    m = I.hex_mesh(24, degree=p, jitter=0.05)
+    ph = I.ns_physics(3, 1600.0, 0.71)
+    U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    elems = [int(np.random.default_rng(1).integers(m.n_elem)), 0]
+    from paper_2105_08632_amd import fr
+    ctx = fr.Context(m, ph, "f32")
+    Ud = _dev(U, "f32")
+    Bn = _sampled_blocks(ctx, Ud, elems, out_prec="bf16")
+    torch.cuda.synchronize()
+    Bo = O.Oracle(m, ph, p).jac_blocks(Ud.double().cpu().numpy(), elems, ctx.b, ctx.nface)
+    err = max(rel(Bn[i], Bo[i]) for i in range(len(elems)))
+    assert 1e-6 < err <= TOL["bf16"]
+
+
 def test_cfg1_full_size_fp32():
     """2D NS, p=3, 128x128 jittered periodic quads, FP32: R and the JVP over
     the whole mesh, Jacobian blocks on a seeded sample of elements."""
