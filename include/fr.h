@@ -120,7 +120,9 @@ fr_status fr_rhs(fr_ctx* ctx, const void* U, void* R);
 
 /* Jacobian blocks dR_n/dU_k, k in {n} and the face neighbours of n (eq.
  * "jacobian_rhs").  out_prec: FR_F64 (F64 contexts) or FR_F32 / FR_BF16
- * (F32 contexts; computed in FP32, stored rounded to nearest even).
+ * (F32 contexts).  FR_BF16 values are stored rounded to nearest even; for
+ * quadrilaterals and hexahedra of degree 3 they are also computed from
+ * BF16-rounded operands (matrix cores, FP32 accumulation), elsewhere in FP32.
  * blocks: n_elem * blocks_per_elem * b * b values, layout above. */
 fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precision out_prec);
 
