@@ -626,6 +626,7 @@ __device__ __forceinline__ void jac_mf_accum_bf16(int z0, int kq, int mo, int so
     // each loads one row of them into LDS; A operands stay FP32 (their
     // weights depend on the slab), B operands are stored as packed BF16.
     static_assert(jac_mf_wpb<E, NV, SYS, float>() == Y::SL, "one workgroup = the slabs of one task column");
+    static_assert(KV == 4 && JF == 8, "hexahedra: every lane group holds an operand index and face rows");
     float* xT = reinterpret_cast<float*>(xs);                 // [c][y][e][m][x]
     float* xW = xT + N1 * N1 * 4 * 16 * 4;                    // [side][chunk][y][e][m][x]
     mf_bf16x8* xB = reinterpret_cast<mf_bf16x8*>(xW + 2 * 2 * N1 * 4 * 16 * 4);   // [y][x][e][sigma]
