@@ -99,3 +99,51 @@ def test_batch_rejects_mixed_systems():
     (m2, p2, tp2, ph2, U2), = _meshes("ns")[1:2]
     with pytest.raises(fr.FrError):
         fr.Batch([fr.Context(m1, ph1, "f32", tri_pts=tp1), fr.Context(m2, ph2, "f32", tri_pts=tp2)])
+
+
+def test_cfg3_full_size_batch():
+    """The 64-mesh mixed Euler workload (about 175k elements: triangles and
+    quadrilaterals of degrees 1-4) as one batch, default and autotuned: every
+    mesh's residual equals the mesh alone bit for bit, and so do its
+    Jacobian blocks wherever the batch runs the mesh's own kernels; the first
+    triangle and quadrilateral meshes are also checked against the FP64
+    oracle on sampled elements (FP32 bar 1e-5)."""
+    from paper_2105_08632_amd import fr
+    meshes = I.mixed_batch()
+    ph = I.euler_physics(2)
+    ctxs = [fr.Context(m, ph, "f32", tri_pts=tp) for (m, p, tp, U) in meshes]
+    Us = [torch.from_numpy(U).float().cuda().contiguous() for (m, p, tp, U) in meshes]
+    assert sum(c.ne for c in ctxs) > 100000 and {tp is None for (m, p, tp, U) in meshes} == {True, False}
+    b = fr.Batch(ctxs)
+
+    def check(tag):
+        Rs = b.rhs(Us)
+        Bs = b.jacobian_blocks(Us)
+        torch.cuda.synchronize()
+        jl = b.tuning()["jac_launch"]
+        for i, (c, u) in enumerate(zip(ctxs, Us)):
+            assert torch.equal(Rs[i], c.rhs(u)), (tag, i)
+            Ba = c.jacobian_blocks(u)
+            if meshes[i][2] is not None or jl == "grouped_mfma_quads":
+                assert torch.equal(Bs[i], Ba), (tag, i, jl)
+            else:
+                assert float((Bs[i] - Ba).abs().max() / Ba.abs().max()) <= 1e-5, (tag, i, jl)
+            del Ba
+        return Rs, Bs
+
+    Rs, Bs = check("default")
+    for want_tri in (True, False):
+        i = next(k for k, mm in enumerate(meshes) if (mm[2] is not None) == want_tri)
+        m, p, tp, U = meshes[i]
+        Uq = Us[i].double().cpu().numpy()
+        o = O.Oracle(m, ph, p, tp)
+        Rr = o.rhs(Uq)
+        assert np.max(np.abs(Rs[i].double().cpu().numpy().reshape(-1) - Rr)) <= 1e-5 * np.max(np.abs(Rr))
+        el = [0, m.n_elem - 1]
+        Bo = o.jac_blocks(Uq, el, ctxs[i].b, ctxs[i].nface)
+        Bn = Bs[i][el].double().cpu().numpy().transpose(0, 1, 3, 2)
+        for j in range(len(el)):
+            assert np.max(np.abs(Bn[j] - Bo[j])) <= 1e-5 * np.max(np.abs(Bo[j])), (i, el[j])
+    del Rs, Bs
+    b.tune(Us, reps=1)
+    check("tuned")
