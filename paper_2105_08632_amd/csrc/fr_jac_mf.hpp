@@ -527,8 +527,6 @@ __device__ __forceinline__ void jac_mf_accum_bf16(int z0, int kq, int mo, int so
   };
   float gv[SLS], tv[2][SLS];                      // 1: G, T_0, T_1 of the slab points
   float fa[2][2][2][N1], fb[2][2][2][N1];         // 2: W, S at the in-slab faces [axis][side][chunk][ta]
-  float tz[N1][4], gz[N1][4];                     // 3: T_2, G along the third axis [c][x]
-  float za[2][2][4], zb[2][2][4];                 // 3: W, S at the third-axis faces [side][chunk][x]
   auto load1 = [&]() __attribute__((always_inline)) {
     mf_for<0, SLS / 4>([&](auto Q) __attribute__((always_inline)) {
       constexpr int i = 4 * decltype(Q)::value;
