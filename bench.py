@@ -7,7 +7,7 @@ Rusanov + BR1 fluxes, smooth random state (rho = 1 + 0.1 s, Mach 0.2).  One
 step = R(U) plus the five 64x64 Jacobian blocks of every element (FP32 block
 storage), inputs resident in HBM.  Prints one JSON line.
 
-Options: --gpus N (only 1: this build drives one GPU), --steps K, --warmup W.
+Options: --gpus N (only 1: the benchmark drives one GPU), --steps K, --warmup W.
 """
 from __future__ import annotations
 
@@ -347,8 +347,7 @@ def main():
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py drives exactly one GPU: this build has no multi-GPU path "
-              "(the element-partitioned design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py drives exactly one GPU: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
