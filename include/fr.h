@@ -87,8 +87,9 @@ typedef struct {
   double gamma;               /* ratio of specific heats */
   double mu;                  /* dynamic viscosity (advection: diffusivity) */
   double prandtl;
-  double ldg_beta;            /* common-solution / viscous-flux weight; 0 = BR1 */
-  double ldg_penalty;         /* LDG penalty eta; 0 for BR1 */
+  double ldg_beta;            /* common-solution / viscous-flux weight (eq. "common_var_for_grad");
+                                 must be 0 (BR1), else fr_ctx_create returns FR_E_UNSUPPORTED */
+  double ldg_penalty;         /* LDG penalty eta; must be 0 (BR1), else FR_E_UNSUPPORTED */
 } fr_physics;
 
 typedef struct {

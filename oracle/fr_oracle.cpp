@@ -786,6 +786,11 @@ int oracle_create(int nd, int64_t ne, const int8_t* etype, int p, const double* 
                   const int64_t* nbr, const int8_t* nbrf, int maxf, int system, int nv,
                   const double* c, double gamma, double mu, double prandtl, double beta, double eta,
                   const double* tri_pts, void** out) {
+  // BR1 only: beta = 0 and no penalty (the von Neumann analysis with
+  // diffusion identifies BR1 with beta = 0).  A single scalar beta taken
+  // from each element's own side would make the common solution and the
+  // viscous common flux two-valued across a face.
+  if (beta != 0.0 || eta != 0.0) return -11;
   Oracle* O = new Oracle();
   O->nd = nd; O->ne = ne; O->maxv = maxv; O->maxf = maxf;
   O->ph.system = system; O->ph.nv = nv;

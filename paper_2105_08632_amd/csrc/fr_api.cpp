@@ -157,6 +157,8 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   if (ph->nvars != nv) return fail(nullptr, FR_E_INVALID, "nvars does not match the system");
   if (ph->system != FR_ADVECTION && !(ph->gamma > 1.0)) return fail(nullptr, FR_E_INVALID, "gamma must exceed 1");
   if (ph->system == FR_NAVIER_STOKES && !(ph->prandtl > 0.0)) return fail(nullptr, FR_E_INVALID, "prandtl must be positive");
+  if (ph->ldg_beta != 0.0 || ph->ldg_penalty != 0.0)
+    return fail(nullptr, FR_E_UNSUPPORTED, "only the BR1 scheme is provided: ldg_beta and ldg_penalty must be 0");
 
   frh::RefOps ref;
   std::string err;

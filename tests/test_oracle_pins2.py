@@ -1,0 +1,194 @@
+"""Further pins of the oracle, each chosen so that a plausible slip in one
+specific part of it fails here:
+
+* the Rusanov wave-speed estimate phi of the convective common flux (SDRT
+  section, common inviscid flux): it must be the largest |eigenvalue| of the
+  normal flux Jacobian n.df/du over both states, found here numerically
+  (finite differences of the oracle's physical flux, numpy eigenvalues);
+* the Stokes bulk term of the Newtonian stress (eq.
+  "fluxOperatorNavierStokes"): a compressible manufactured field with
+  div v != 0 whose exact residual -div f(u, grad u) is derived with sympy;
+* the plain LU solve against numpy.linalg.solve on systems that need row
+  exchanges;
+* triangles: consistency of the advection residual at the expected order;
+* BR1 only (beta = 0, eta = 0, section on the von Neumann analysis with
+  diffusion): any other value is refused.
+"""
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import oracle as O
+from paper_2105_08632_amd import inputs as I
+
+
+# ------------------------------------------------------------ Rusanov phi
+def _normal_flux_jacobian(ph, nd, u, n, h=1e-6):
+    nv = len(u)
+    A = np.zeros((nv, nv))
+    for j in range(nv):
+        e = np.zeros(nv)
+        e[j] = h * max(1.0, abs(u[j]))
+        fp = n @ O.flux(ph, nd, u + e)
+        fm = n @ O.flux(ph, nd, u - e)
+        A[:, j] = (fp - fm) / (2 * e[j])
+    return A
+
+
+def _phi_from_common_flux(ph, nd, uL, uR, n):
+    z = np.zeros((nd, len(uL)))
+    F = O.common_flux(ph, nd, uL, uR, z, z, n)
+    central = 0.5 * n @ (O.flux(ph, nd, uL) + O.flux(ph, nd, uR))
+    return 2.0 * (F - central) / (uL - uR)
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_rusanov_speed_is_largest_flux_jacobian_eigenvalue(nd):
+    """phi/2 (u_L - u_R) is the dissipative part of the common flux; phi is
+    the same for every variable and equals max over the two states of the
+    spectral radius of n.df/du (eigenvalues v.n - c, v.n, v.n + c, computed
+    here as plain eigenvalues, not from that formula)."""
+    ph = I.euler_physics(nd)
+    rng = np.random.default_rng(11)
+    cases = []
+    for _ in range(6):
+        mk = lambda: I.conservative(np.array(0.5 + rng.random()), rng.standard_normal(nd),
+                                    np.array(0.5 + 3 * rng.random()), ph.gamma)
+        cases.append((mk(), mk()))
+    n = np.zeros(nd)
+    n[0] = 1.0
+    # the faster side on the right, then on the left (the max must pick it)
+    slow = I.conservative(np.array(1.0), 0.1 * np.ones(nd), np.array(1.0), ph.gamma)
+    fast = I.conservative(np.array(0.4), np.r_[3.0, np.zeros(nd - 1)], np.array(4.0), ph.gamma)
+    cases += [(slow, fast), (fast, slow)]
+    for uL, uR in cases:
+        nn = rng.standard_normal(nd)
+        nn /= np.linalg.norm(nn)
+        for nvec in (n, nn):
+            phi = _phi_from_common_flux(ph, nd, uL, uR, nvec)
+            assert np.max(np.abs(phi - phi[0])) < 1e-9 * abs(phi[0])
+            rad = [np.max(np.abs(np.linalg.eigvals(_normal_flux_jacobian(ph, nd, u, nvec)))) for u in (uL, uR)]
+            assert abs(phi[0] - max(rad)) < 1e-6 * max(rad), (phi[0], rad)
+    # the pinned case really has the larger speed on one side only
+    rs = [np.max(np.abs(np.linalg.eigvals(_normal_flux_jacobian(ph, nd, u, n)))) for u in (slow, fast)]
+    assert rs[1] > 2 * rs[0]
+
+
+# ------------------------------------------------ compressible viscous term
+def _ns_exact_residual(mu, Pr, gam, bulk):
+    """Sympy: R = -div f(u, grad u) of the 2-D Navier-Stokes flux for the
+    manufactured primitive field below, with the Newtonian stress
+    tau = mu (grad v + grad v^T + bulk (div v) I) and the Fourier heat flux
+    mu gam / (Pr (gam - 1)) grad(p / rho)."""
+    x, y = sp.symbols("x y", real=True)
+    tp = 2 * sp.pi
+    rho = 1 + sp.Rational(1, 5) * sp.sin(tp * (x + y))
+    vx = sp.Rational(3, 10) * sp.sin(tp * x) + sp.Rational(1, 10) * sp.cos(tp * y)
+    vy = sp.Rational(1, 5) * sp.cos(tp * y) - sp.Rational(1, 10) * sp.sin(tp * x)
+    p = 5 + sp.Rational(3, 10) * sp.sin(tp * (x - y))
+    v = [vx, vy]
+    X = [x, y]
+    E = p / (gam - 1) + rho * (vx ** 2 + vy ** 2) / 2
+    divv = sp.diff(vx, x) + sp.diff(vy, y)
+    tau = [[mu * (sp.diff(v[i], X[d]) + sp.diff(v[d], X[i]) + (bulk * divv if i == d else 0))
+            for d in range(2)] for i in range(2)]
+    kap = mu * gam / (Pr * (gam - 1))
+    Th = p / rho
+    F = []
+    for d in range(2):
+        F.append([rho * v[d],
+                  rho * v[d] * v[0] + (p if d == 0 else 0) - tau[0][d],
+                  rho * v[d] * v[1] + (p if d == 1 else 0) - tau[1][d],
+                  (E + p) * v[d] - (tau[0][d] * v[0] + tau[1][d] * v[1]) - kap * sp.diff(Th, X[d])])
+    R = [-(sp.diff(F[0][a], x) + sp.diff(F[1][a], y)) for a in range(4)]
+    prim = [sp.lambdify((x, y), e, "numpy") for e in (rho, vx, vy, p)]
+    res = [sp.lambdify((x, y), e, "numpy") for e in R]
+    return prim, res
+
+
+def test_ns_compressible_stress_bulk_term():
+    """div v != 0: the residual tends to the exact -div f with the Stokes
+    bulk coefficient -2/3.  The test also evaluates the exact residual with
+    -1/3 and requires the discrete error to be far below their difference,
+    so a wrong bulk coefficient cannot pass."""
+    mu, Pr, gam = 0.05, 0.72, 1.4
+    prim, exact = _ns_exact_residual(mu, Pr, gam, sp.Rational(-2, 3))
+    _, wrong = _ns_exact_residual(mu, Pr, gam, sp.Rational(-1, 3))
+    ph = I.ns_physics(2, 1.0 / mu, Pr, gamma=gam)
+    p = 4
+    errs, gaps = [], []
+    for N in (8, 16):
+        m = I.quad_mesh(N, degree=p, jitter=0.05, K=1)
+        o = O.Oracle(m, ph, p)
+        xs = I.sol_points_phys(m, p)
+        X, Y = xs[..., 0], xs[..., 1]
+        rho, vx, vy, pr = (f(X, Y) * np.ones_like(X) for f in prim)
+        U = I.conservative(rho, np.stack([vx, vy], axis=-1), pr, gam)
+        R = o.rhs(U).reshape(U.shape)
+        ex = np.stack([f(X, Y) * np.ones_like(X) for f in exact], axis=-1)
+        wr = np.stack([f(X, Y) * np.ones_like(X) for f in wrong], axis=-1)
+        errs.append(np.max(np.abs(R - ex)))
+        gaps.append(np.max(np.abs(wr - ex)))
+    assert errs[1] < 0.05 * gaps[1], (errs, gaps)
+    assert np.log2(errs[0] / errs[1]) > p - 1.3, errs
+
+
+# ------------------------------------------------------------- LU solve
+def test_lu_solve_matches_numpy_with_pivoting():
+    rng = np.random.default_rng(3)
+    for n in (1, 2, 5, 17, 64):
+        for kind in range(3):
+            A = rng.standard_normal((n, n))
+            if kind == 1:      # zero diagonal: every column needs an exchange
+                np.fill_diagonal(A, 0.0)
+                A += np.eye(n)[rng.permutation(n)] * 3.0
+                np.fill_diagonal(A, 0.0)
+            if kind == 2:      # a permuted triangular matrix with tiny leading pivots
+                A = np.triu(A) + 4 * np.eye(n)
+                A = A[rng.permutation(n)]
+                A[0, 0] = 1e-14
+            if n == 1:
+                A = np.array([[2.5]])
+            b = rng.standard_normal(n)
+            x = O.lu_solve(A, b)
+            ref = np.linalg.solve(A, b)
+            cond = np.linalg.cond(A)
+            assert np.max(np.abs(x - ref)) <= 1e-13 * cond * (1 + np.max(np.abs(ref))), (n, kind)
+            assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b) * max(1.0, np.linalg.norm(A))
+
+
+def test_lu_solve_singular():
+    A = np.array([[1.0, 2.0], [2.0, 4.0]])
+    with pytest.raises(np.linalg.LinAlgError):
+        O.lu_solve(A, np.ones(2))
+
+
+# ------------------------------------------------- triangle consistency
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_triangle_advection_consistency_rate(p):
+    """u = sin(2 pi (x + 2 y)) on split-cell triangle meshes: R(u) tends to
+    -c.grad u at the solution points at order >= p - 0.3 (the same bound as
+    on quadrilaterals)."""
+    c = np.array([1.0, 0.5])
+    tp = I.tri_points(p)
+    errs = []
+    Ns = (8, 16) if p > 1 else (16, 32)
+    for N in Ns:
+        m = I.tri_mesh(N, degree=p, seed=3)
+        o = O.Oracle(m, I.advection_physics(tuple(c)), p, tri_pts=tp)
+        x = I.sol_points_phys(m, p, tp)
+        arg = 2 * np.pi * (x[..., 0] + 2 * x[..., 1])
+        exact = -(c[0] * 2 * np.pi + c[1] * 4 * np.pi) * np.cos(arg)
+        R = o.rhs(np.sin(arg)[..., None]).reshape(arg.shape)
+        errs.append(np.max(np.abs(R - exact)))
+    assert np.log2(errs[0] / errs[1]) > p - 0.3, errs
+
+
+# ---------------------------------------------------------------- BR1
+@pytest.mark.parametrize("beta,eta", [(0.5, 0.0), (-0.5, 0.0), (0.0, 0.1)])
+def test_oracle_refuses_non_br1(beta, eta):
+    m = I.quad_mesh(4, degree=2)
+    ph = I.ns_physics(2, 100.0, 0.72)
+    ph.beta, ph.eta = beta, eta
+    with pytest.raises(RuntimeError):
+        O.Oracle(m, ph, 2)
