@@ -55,7 +55,8 @@ typedef enum {
   FR_E_NOMEM = -3,         /* device allocation failed (creation only) */
   FR_E_DEVICE = -4,        /* HIP launch or runtime error */
   FR_E_SINGULAR = -5,      /* a diagonal block has a zero pivot */
-  FR_E_NOT_CONVERGED = -6  /* Newton/GMRES did not reach its tolerance */
+  FR_E_NOT_CONVERGED = -6, /* Newton/GMRES did not reach its tolerance */
+  FR_E_NONFINITE = -7      /* a NaN or infinity was stored to R, Jv or the Jacobian blocks */
 } fr_status;
 
 typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2 } fr_elem_type;
@@ -110,7 +111,13 @@ fr_status fr_ctx_create(const fr_mesh_desc* mesh, const fr_physics* phys, fr_pre
 fr_status fr_ctx_destroy(fr_ctx* ctx);
 fr_status fr_ctx_info(const fr_ctx* ctx, fr_info* info);
 const char* fr_last_error(const fr_ctx* ctx);
-/* Waits for the context stream and reports any asynchronous HIP error. */
+/* Waits for the context stream and reports any asynchronous HIP error.
+ * The residual, JVP and Jacobian kernels record every non-finite value they
+ * store in a device status word of the context; fr_ctx_sync returns
+ * FR_E_NONFINITE if any was stored since the previous fr_ctx_sync (the
+ * message names the outputs and the smallest element index) and clears the
+ * word.  The hot calls return before their kernels finish, so they cannot
+ * report it themselves. */
 fr_status fr_ctx_sync(fr_ctx* ctx);
 
 /* R = R(U): the FR-DG residual, eq. "divergence_fr" and the method of
@@ -242,7 +249,10 @@ fr_status fr_solver_destroy(fr_solver* s);
  * GMRES(restart) on (I - dt dR/dU) dU = -F with exact Jacobian-vector
  * products; the preconditioner (or NULL) is set up at Un, and again at
  * every Newton iterate when opts->pc_refresh is set.  Returns
- * FR_E_NOT_CONVERGED if newton_maxit iterations do not reach newton_rtol. */
+ * FR_E_NOT_CONVERGED if newton_maxit iterations do not reach newton_rtol,
+ * FR_E_NONFINITE if the residual of an iterate, or of every line-search
+ * trial, is not finite (U then holds the last finite iterate).  The step
+ * clears the context's non-finite status word before it returns. */
 fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un, void* U, const fr_newton_opts* opts,
                          fr_newton_stats* stats);
 

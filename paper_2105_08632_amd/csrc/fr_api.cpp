@@ -89,7 +89,7 @@ static void pack_geo(const frh::Geometry& g, std::vector<char>& blob, std::vecto
 }
 
 template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>& o, int ne) {
-  GeoD<R> v;
+  GeoD<R> v{};
   v.ne = ne;
   v.S = (const R*)(base + o[0]); v.Jinv = (const R*)(base + o[1]); v.rdet = (const R*)(base + o[2]);
   v.nrm = (const R*)(base + o[3]); v.magN = (const R*)(base + o[4]);
@@ -134,6 +134,11 @@ void fr_time_begin(fr_ctx_s* c, int w) {
 void fr_time_end(fr_ctx_s* c, int w) {
   (void)hipEventRecord(c->ev[w][c->ev_n[w]][1], c->stream);
   ++c->ev_n[w];
+}
+
+int fr_status_reset(fr_ctx_s* c) {
+  static const int clear[2] = {0, 0x7fffffff};
+  return hipMemcpy(c->status, clear, sizeof(clear), hipMemcpyHostToDevice) == hipSuccess ? 0 : -4;
 }
 
 // ------------------------------------------------------------ ABI
@@ -235,11 +240,12 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   const size_t rs = (prec == FR_F64) ? 8 : 4;
   const size_t nuf = (size_t)c->ne * c->nf * nv, nq = (size_t)c->ne * c->ns * c->nd * nv, nqf = (size_t)c->ne * c->nf * c->nd * nv;
   const bool f32 = prec == FR_F32;
-  size_t sizes[9] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
-                     2 * nuf * 8, visc ? 2 * nq * 8 : 0, visc ? 2 * nqf * 8 : 0,
-                     f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0};
-  size_t off[9], tot = 0;
-  for (int i = 0; i < 9; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
+  size_t sizes[10] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
+                      2 * nuf * 8, visc ? 2 * nq * 8 : 0, visc ? 2 * nqf * 8 : 0,
+                      f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0,
+                      2 * sizeof(int)};
+  size_t off[10], tot = 0;
+  for (int i = 0; i < 10; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
   if (hipMalloc(&c->work_mem, tot) != hipSuccess) {
     release(c);
     return fail(nullptr, FR_E_NOMEM, "device allocation failed (workspaces)");
@@ -249,6 +255,14 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   c->UFd = w + off[3]; c->Qd = w + off[4]; c->QFd = w + off[5];
   if (f32) { c->UF64 = w + off[6]; c->Q64 = w + off[7]; c->QF64 = w + off[8]; }
   else { c->UF64 = c->UF; c->Q64 = c->Q; c->QF64 = c->QF; }
+  c->status = (int*)(w + off[9]);
+  c->geod.status = c->status;
+  c->geof.status = c->status;
+  (void)hipGetDevice(&c->dev);
+  if (fr_status_reset(c) != 0) {
+    release(c);
+    return fail(nullptr, FR_E_DEVICE, "status word initialisation failed");
+  }
   // matrix-core Jacobian: geometry-only sensitivities (computed here, once)
   // and the per-state tables
   const size_t mfs = c->ks.mf_bytes ? c->ks.mf_bytes(0) : 0, mft = c->ks.mf_bytes ? c->ks.mf_bytes(1) : 0;
@@ -338,6 +352,18 @@ fr_status fr_ctx_sync(fr_ctx* c) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return fail(c, FR_E_DEVICE, std::string("device: ") + hipGetErrorString(e));
+  int st[2] = {0, 0};
+  if (hipMemcpy(st, c->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(c, FR_E_DEVICE, "reading the status word");
+  if (st[0]) {
+    std::string what;
+    if (st[0] & FR_NF_RHS) what += " R";
+    if (st[0] & FR_NF_JVP) what += " Jv";
+    if (st[0] & FR_NF_BLOCKS) what += " Jacobian-blocks";
+    if (fr_status_reset(c) != 0) return fail(c, FR_E_DEVICE, "clearing the status word");
+    return fail(c, FR_E_NONFINITE,
+                "non-finite value stored to" + what + "; first element " + std::to_string(st[1]));
+  }
   return FR_OK;
 }
 

@@ -31,6 +31,8 @@ struct fr_ctx_s {
   void* ops_mem = nullptr;
   void* geo_mem = nullptr;
   void* work_mem = nullptr;
+  int* status = nullptr;       // device [2]: kinds of non-finite outputs (FR_NF_*), smallest element
+  int dev = 0;                 // device the context was created on
   OpsD<float> opsf{}; OpsD<double> opsd{};
   Ops1D<float> o1f{}; Ops1D<double> o1d{};
   GeoD<float> geof{}; GeoD<double> geod{};
@@ -55,6 +57,9 @@ struct fr_ctx_s {
 // 1 = residual divergence pass).  Pools are drained when full.
 void fr_time_begin(fr_ctx_s* c, int which);
 void fr_time_end(fr_ctx_s* c, int which);
+
+// Clears the non-finite report (synchronous; not for capture).
+int fr_status_reset(fr_ctx_s* c);
 
 // Registry lookup implemented by the per-instantiation translation units.
 bool fr_find_kernels(int type, int p, int system, int prec, KernelSet* out);

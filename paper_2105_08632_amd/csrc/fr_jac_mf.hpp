@@ -84,13 +84,6 @@ template <> struct Mfma<float> {
   // row of D held in accumulator r by lanes 16 q .. 16 q + 15
   static constexpr __device__ int row(int q, int r) { return 4 * q + r; }
 };
-template <> struct Mfma<double> {
-  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double acc;
-  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static constexpr __device__ int row(int q, int r) { return q + 4 * r; }
-};
 
 
 // assembly tasks per workgroup and the LDS staging of one task's tile
@@ -726,7 +719,7 @@ template <class E, int NV, int SYS, class R, class OT>
 __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0, int lane, const Ops1D<R>& o1,
                                             const R* rdet, const R* tab, const R* sens, const R* sigtab,
                                             const int* sig, int nsb, int nblk, OT* B, R* stage, char* xs,
-                                            bool active) {
+                                            bool active, int* status) {
   typedef MfSizes<E, NV, SYS> Y;
   typedef TPIdx<E> X;
   typedef Mfma<R> M;
@@ -1002,6 +995,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   const int nsg = (NS - nt * 16) < 16 ? (NS - nt * 16) : 16;
   const int ncol = nsg * nbt;
   OT* Bk = B + (nl * nblk + k) * (long)BB * BB + (long)R0 * NV;
+  bool bad = false;      // a non-finite value among this lane's stores
   mf_for<0, NH>([&](auto H) __attribute__((always_inline)) {
     constexpr int h = decltype(H)::value;
     if constexpr (h > 0) __syncthreads();      // the previous pass has left the stage
@@ -1027,6 +1021,7 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
           const int cl = i / NRH, rr = i % NRH;
           const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
           const R* sp = stage + cl * SP + rr;
+          bad |= !(fr_finite(sp[0]) && fr_finite(sp[1]) && fr_finite(sp[2]) && fr_finite(sp[3]));
           if constexpr (std::is_same<OT, float>::value) {
             *reinterpret_cast<float4*>(Bh + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
           } else {
@@ -1041,8 +1036,10 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
           const int cl = i / NRH, rr = i % NRH;
           const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
           Bh[(long)c * BB + rr] = to_out<OT>(stage[cl * SP + rr]);
+          bad |= !fr_finite(stage[cl * SP + rr]);
         }
       }
     }
   });
+  if (bad) fr_flag_nonfinite(status, FR_NF_BLOCKS, nl);
 }

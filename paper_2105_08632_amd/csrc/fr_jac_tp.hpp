@@ -132,7 +132,7 @@ template <class E, int NV, int SYS, class R> constexpr int jac_tp_lds() {
 // One assembly task (see jac_tp_body): kept out of line so its register
 // live range ends with the task.
 template <class E, int NV, int SYS, class R, class OT>
-FR_HD __forceinline__ void jac_tp_task(int item, int kb, const Ops1D<R>& o1, const R* srd, const R* tb,
+FR_HD __forceinline__ bool jac_tp_task(int item, int kb, const Ops1D<R>& o1, const R* srd, const R* tb,
                                        const R* tf, const R* gam, const R* slr, OT* Bn) {
   typedef TPSizes<E, NV, SYS> Z;
   typedef TPIdx<E> X;
@@ -199,6 +199,7 @@ FR_HD __forceinline__ void jac_tp_task(int item, int kb, const Ops1D<R>& o1, con
     }
     fr_sched_fence();
   }
+  bool bad = false;
   if (live) {
 #pragma unroll
     for (int bb = 0; bb < NBT; ++bb) {
@@ -206,10 +207,15 @@ FR_HD __forceinline__ void jac_tp_task(int item, int kb, const Ops1D<R>& o1, con
       if (beta < NV) {
         OT* col = Bn + (long)k * BB * BB + (long)(s * NV + beta) * BB;
 #pragma unroll
-        for (int r = 0; r < NS; ++r) col[r * NV + a] = to_out<OT>(-(srd[r] * out[bb][r]));
+        for (int r = 0; r < NS; ++r) {
+          const R jv = -(srd[r] * out[bb][r]);
+          col[r * NV + a] = to_out<OT>(jv);
+          bad |= !fr_finite(jv);
+        }
       }
     }
   }
+  return bad;
 }
 
 template <class E, int NV, int SYS, class R, class OT, class Sync>
@@ -516,8 +522,10 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
   constexpr int NBT = jac_tp_nbt<E, NV>();
   constexpr int NBG = (NV + NBT - 1) / NBT;
   const int nitems = nbk * CHUNKS * NBG * 64;
+  bool bad = false;
   for (int item = tid; item < nitems; item += nth)
-    jac_tp_task<E, NV, SYS, R, OT>(item, kb, o1, srd, tb, tf, gam, slr, Bn);
+    bad |= jac_tp_task<E, NV, SYS, R, OT>(item, kb, o1, srd, tb, tf, gam, slr, Bn);
+  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, nl);
   sync();
   }
 }

@@ -67,7 +67,23 @@ template <class R> struct GeoD {
   const int* nbr;   // [ne][NFACE]       face neighbours
   const int* nbface;  // [ne][NFACE]     the neighbour's local index of the shared face
   const int* back;    // [ne][NFACE][NFP] this element's point paired with each point of that neighbour face
+  int* status;        // [2] non-finite output report (device): [0] kinds, [1] smallest element
 };
+
+// Kinds of output a non-finite value was stored to.
+enum { FR_NF_RHS = 1, FR_NF_JVP = 2, FR_NF_BLOCKS = 4 };
+template <class R> FR_HD bool fr_finite(R x) { return __builtin_isfinite(x); }
+// Records that element `elem` stored a non-finite value of kind `what`.
+FR_HD void fr_flag_nonfinite(int* st, int what, long elem) {
+  if (!st) return;
+#if defined(__HIP_DEVICE_COMPILE__)
+  atomicOr(&st[0], what);
+  atomicMin(&st[1], (int)elem);
+#else
+  st[0] |= what;
+  if ((int)elem < st[1]) st[1] = (int)elem;
+#endif
+}
 
 struct DevSync {
   __device__ __forceinline__ void operator()() const { __syncthreads(); }
@@ -299,9 +315,15 @@ FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, co
     for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * sJ[(e * NF + crc[r * WC + w]) * NV + a];
     T res = -(geo.rdet[n * NS + r] * acc);
     long o = (n * NS + r) * NV + a;
-    if (Rout) Rout[o] = IO(val(res));
+    if (Rout) {
+      Rout[o] = IO(val(res));
+      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, n);
+    }
     if constexpr (!std::is_same<T, R>::value) {
-      if (Rtan) Rtan[o] = IO(res.d);
+      if (Rtan) {
+        Rtan[o] = IO(res.d);
+        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, n);
+      }
     }
   }
 }
@@ -717,7 +739,9 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
           for (int w = 0; w < WL; ++w)
             acc += dcv[(d * NS + r) * WL + w] * X[((a * ND + d) * NS + dcc[(d * NS + r) * WL + w]) * NS + s];
         for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * Y[(a * NF + crc[r * WC + w]) * NS + s];
-        Bk[(long)(s * NV + beta) * BB + r * NV + a] = to_out<OT>(-(srd[r] * acc));
+        const R jv = -(srd[r] * acc);
+        Bk[(long)(s * NV + beta) * BB + r * NV + a] = to_out<OT>(jv);
+        if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, n);
       }
       sync();
     }

@@ -1071,6 +1071,7 @@ static fr_status newton_body(fr_solver_s* s, fr_precond_s* pc, const void* Un_, 
     double fn;
     if ((rs = dots(s, 1, s->F, s->F, &fn))) return rs;
     fn = std::sqrt(fn);
+    if (!std::isfinite(fn)) return sfail(c, FR_E_NONFINITE, "Newton: the residual of the iterate is not finite");
     if (it == 0) f0 = fn;
     if (it < 32) st->res_hist[it] = fn;
     st->res0 = f0;
@@ -1096,6 +1097,7 @@ static fr_status newton_body(fr_solver_s* s, fr_precond_s* pc, const void* Un_, 
     st->last_linear_rel = r0 > 0 ? rt / r0 : 0.0;
     // backtracking on |F|: U + lambda dU, lambda = 1, 1/2, ... (at most 5 halvings)
     double lam = 1.0;
+    bool found = false;
     for (int ls = 0; ls < 6; ++ls) {
       if ((rs = axpby(s, 1.0, U, lam, s->x, s->tmp))) return rs;
       rc = c->ks.rhs(c, s->tmp, s->R);
@@ -1105,9 +1107,11 @@ static fr_status newton_body(fr_solver_s* s, fr_precond_s* pc, const void* Un_, 
       double ft;
       if ((rs = dots(s, 1, s->w, s->w, &ft))) return rs;
       ft = std::sqrt(ft);
-      if (std::isfinite(ft) && (ft < fn || ls == 5)) break;
+      if (std::isfinite(ft) && (ft < fn || ls == 5)) { found = true; break; }
       lam *= 0.5;
     }
+    // no finite trial: the iterate is left as it is
+    if (!found) return sfail(c, FR_E_NONFINITE, "Newton: no line-search trial has a finite residual");
     if ((rs = axpby(s, 1.0, U, lam, s->x, U))) return rs;
   }
   HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -1140,6 +1144,10 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
     (void)hipGraphExecDestroy(s->cycle);
     s->cycle = nullptr;
   }
+  // rejected line-search trials may have recorded non-finite residuals:
+  // the step reports its own outcome, so the word is cleared
+  (void)hipStreamSynchronize(s->cs);
+  if (fr_status_reset(c) != 0 && r == FR_OK) r = sfail(c, FR_E_DEVICE, "clearing the status word");
   c->stream = orig;
   (void)hipEventRecord(s->join1, s->cs);
   (void)hipStreamWaitEvent(orig, s->join1, 0);

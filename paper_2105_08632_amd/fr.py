@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libfr.so")
 FR_F64, FR_F32, FR_BF16 = 0, 1, 2
 _PREC = {"f64": FR_F64, "f32": FR_F32, "bf16": FR_BF16}
 _STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_UNSUPPORTED", -3: "FR_E_NOMEM", -4: "FR_E_DEVICE",
-           -5: "FR_E_SINGULAR", -6: "FR_E_NOT_CONVERGED"}
+           -5: "FR_E_SINGULAR", -6: "FR_E_NOT_CONVERGED", -7: "FR_E_NONFINITE"}
 
 EXPORTED = ["fr_ctx_create", "fr_ctx_destroy", "fr_ctx_info", "fr_last_error", "fr_ctx_sync", "fr_rhs",
             "fr_jacobian_blocks", "fr_jvp", "fr_set_kernel_timing", "fr_kernel_time"]

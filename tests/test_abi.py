@@ -45,3 +45,23 @@ def test_create_rejects_bad_mesh_without_gpu_work():
     rc = L.fr_ctx_create(ctypes.byref(m), ctypes.byref(ph), 0, None, ctypes.byref(h))
     assert rc == -1
     assert b"ndim" in L.fr_last_error(None)
+
+
+def test_create_refuses_non_br1_without_gpu_work():
+    """ldg_beta / ldg_penalty other than 0 are refused on the host (BR1 only)."""
+    if not os.path.exists(fr.LIB_PATH):
+        pytest.skip("libfr.so not built")
+    import numpy as np
+    from paper_2105_08632_amd import inputs as I
+    L = fr.lib()
+    m = I.quad_mesh(4, degree=2)
+    keep = [np.ascontiguousarray(m.elem_type, dtype=np.int8), np.ascontiguousarray(m.xyz),
+            np.ascontiguousarray(m.nbr, dtype=np.int64), np.ascontiguousarray(m.nbr_face, dtype=np.int8)]
+    md = fr._Mesh(2, m.n_elem, 2, keep[0].ctypes.data, keep[1].ctypes.data, m.max_vert,
+                  keep[2].ctypes.data, keep[3].ctypes.data, m.max_face, None)
+    for beta, eta in ((0.5, 0.0), (0.0, 0.1)):
+        ph = fr._Phys(2, 4, (ctypes.c_double * 3)(0, 0, 0), 1.4, 0.01, 0.72, beta, eta)
+        h = ctypes.c_void_p()
+        rc = L.fr_ctx_create(ctypes.byref(md), ctypes.byref(ph), 0, None, ctypes.byref(h))
+        assert rc == -2
+        assert b"BR1" in L.fr_last_error(None)
