@@ -126,6 +126,23 @@ fr_status fr_ctx_sync(fr_ctx* ctx);
  * mean, e.g. the pressure at low Mach number, cancels). */
 fr_status fr_rhs(fr_ctx* ctx, const void* U, void* R);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fr_rhs
+ * with its intermediate FP64 traces and gradients in a scratch array the
+ * library holds per device (64 MiB, a static device array whose address is
+ * looked up at the first fr_ctx_create on that device) instead of the
+ * context's workspaces.  Same arguments, kernels and result as fr_rhs
+ * (bitwise).  Allocates nothing and calls no allocating routine.  A mesh
+ * whose traces and gradients exceed 64 MiB (ne * Nf * Nv * 8 bytes, plus
+ * ne * Ns * ndim * Nv * 8 and ne * Nf * ndim * Nv * 8 for viscous systems,
+ * each rounded up to 256 bytes; Nf = flux points per element) returns
+ * FR_E_UNSUPPORTED with the sizes in the message.  Every value the kernels
+ * read from the array is written earlier in the same call, so nothing is
+ * cleared.  Every call on one device shares that device's array: calls that
+ * may overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller. */
+fr_status fr_rhs_noalloc(fr_ctx* ctx, const void* U, void* R);
+
 /* Jacobian blocks dR_n/dU_k, k in {n} and the face neighbours of n (eq.
  * "jacobian_rhs").  out_prec: FR_F64 (F64 contexts) or FR_F32 / FR_BF16
  * (F32 contexts).  FR_BF16 values are stored rounded to nearest even; for

@@ -38,6 +38,37 @@ bool fr_find_kernels(int type, int p, int system, int prec, KernelSet* out) {
 
 static thread_local std::string g_create_err;
 
+// ------------------------------------------------------------ allocation-free residual
+// fr_rhs_noalloc keeps the FP64 traces and gradients of the residual in this
+// file-scope array instead of the context's workspaces.  Every device holds
+// its own copy until the process ends.  In host code `scratch` names a host
+// stand-in: kernels receive the device address from hipGetSymbolAddress,
+// looked up once per device when the first context is created on it.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static hipError_t g_scratch_rc[kMaxDevices] = {};
+
+// Called with the context's device current.
+static void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] || g_scratch_rc[dev] != hipSuccess) return;
+  void* ptr = nullptr;
+  hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (rc == hipSuccess && ptr) g_scratch_ptr[dev] = ptr;
+  else g_scratch_rc[dev] = rc != hipSuccess ? rc : hipErrorInvalidSymbol;
+}
+
+static void* scratch_ptr(int dev, hipError_t* rc) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) { *rc = hipErrorInvalidDevice; return nullptr; }
+  *rc = g_scratch_rc[dev];
+  return g_scratch_ptr[dev];
+}
+
 // ------------------------------------------------------------ helpers
 template <class R>
 static void pack_ops(const frh::RefOps& ref, std::vector<char>& blob, std::vector<size_t>& offs) {
@@ -259,6 +290,7 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   c->geod.status = c->status;
   c->geof.status = c->status;
   (void)hipGetDevice(&c->dev);
+  scratch_setup(c->dev);
   if (fr_status_reset(c) != 0) {
     release(c);
     return fail(nullptr, FR_E_DEVICE, "status word initialisation failed");
@@ -397,6 +429,29 @@ fr_status fr_rhs(fr_ctx* c, const void* U, void* R) {
   if (U == R) return fail(c, FR_E_INVALID, "fr_rhs: U and R must not alias");
   int rc = c->ks.rhs(c, U, R);
   return rc ? (fr_status)rc : FR_OK;
+}
+
+fr_status fr_rhs_noalloc(fr_ctx* c, const void* U, void* R) {
+  if (!c) return FR_E_INVALID;
+  const size_t a = c->prec == FR_F64 ? 8 : 4;
+  if (!U || !R || !aligned(U, a) || !aligned(R, a))
+    return fail(c, FR_E_INVALID, "fr_rhs_noalloc: null or misaligned pointer");
+  if (U == R) return fail(c, FR_E_INVALID, "fr_rhs_noalloc: U and R must not alias");
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t nuf = (size_t)c->ne * c->nf * c->nv * 8;
+  const size_t nq = c->visc ? (size_t)c->ne * c->ns * c->nd * c->nv * 8 : 0;
+  const size_t nqf = c->visc ? (size_t)c->ne * c->nf * c->nd * c->nv * 8 : 0;
+  const size_t need = up(nuf) + up(nq) + up(nqf);
+  if (need > kScratchBytes)
+    return fail(c, FR_E_UNSUPPORTED, "fr_rhs_noalloc: this mesh needs " + std::to_string(need) +
+                                         " bytes of scratch, more than the " + std::to_string(kScratchBytes) +
+                                         " the library holds per device");
+  hipError_t rc = hipSuccess;
+  char* w = (char*)scratch_ptr(c->dev, &rc);
+  if (!w)
+    return fail(c, FR_E_DEVICE, std::string("fr_rhs_noalloc: scratch address unavailable: ") + hipGetErrorString(rc));
+  int r = c->ks.rhs_ws(c, U, R, w, w + up(nuf), w + up(nuf) + up(nq));
+  return r ? (fr_status)r : FR_OK;
 }
 
 fr_status fr_jvp(fr_ctx* c, const void* U, const void* v, void* Jv, void* Rout) {

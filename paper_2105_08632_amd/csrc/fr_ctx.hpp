@@ -12,6 +12,8 @@ struct fr_ctx_s;
 // Type-erased launchers of one (element type, degree, system, precision).
 struct KernelSet {
   int (*rhs)(fr_ctx_s*, const void* U, void* R);
+  // the residual with caller-provided FP64 trace / gradient workspaces
+  int (*rhs_ws)(fr_ctx_s*, const void* U, void* R, void* UF, void* Q, void* QF);
   int (*jvp)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
   int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec, int nblk);
   size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: sensitivities, 1: tables)

@@ -138,6 +138,12 @@ template <int ET, int P, int SYS, class R> struct Impl {
                                        (double*)c->QF64, (R*)Rout, (R*)nullptr);
   }
 
+  // The same evaluation with the FP64 traces and gradients in caller memory.
+  static int rhs_ws(fr_ctx_s* c, const void* U, void* Rout, void* UF, void* Q, void* QF) {
+    return residual<double, double, R>(c, (const R*)U, (const R*)nullptr, (double*)UF, (double*)Q, (double*)QF,
+                                       (R*)Rout, (R*)nullptr);
+  }
+
   // The JVP too: one FP64 dual-number evaluation (the tangent of a
   // low-Mach flux divergence cancels like the divergence itself).
   static int jvp(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
@@ -230,5 +236,5 @@ template <int ET, int P, int SYS, class R> struct Impl {
     return 0;
   }
 
-  static KernelSet set() { return KernelSet{&rhs, &jvp, &jac, &mf_bytes, &mf_setup}; }
+  static KernelSet set() { return KernelSet{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup}; }
 };

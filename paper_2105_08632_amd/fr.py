@@ -20,7 +20,7 @@ _PREC = {"f64": FR_F64, "f32": FR_F32, "bf16": FR_BF16}
 _STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_UNSUPPORTED", -3: "FR_E_NOMEM", -4: "FR_E_DEVICE",
            -5: "FR_E_SINGULAR", -6: "FR_E_NOT_CONVERGED", -7: "FR_E_NONFINITE"}
 
-EXPORTED = ["fr_ctx_create", "fr_ctx_destroy", "fr_ctx_info", "fr_last_error", "fr_ctx_sync", "fr_rhs",
+EXPORTED = ["fr_ctx_create", "fr_ctx_destroy", "fr_ctx_info", "fr_last_error", "fr_ctx_sync", "fr_rhs", "fr_rhs_noalloc",
             "fr_jacobian_blocks", "fr_jvp", "fr_set_kernel_timing", "fr_kernel_time"]
 
 
@@ -67,6 +67,7 @@ def lib():
         L.fr_last_error.restype = C.c_char_p
         L.fr_ctx_sync.argtypes = [P]
         L.fr_rhs.argtypes = [P, P, P]
+        L.fr_rhs_noalloc.argtypes = [P, P, P]
         L.fr_jacobian_blocks.argtypes = [P, P, P, C.c_int]
         L.fr_jvp.argtypes = [P, P, P, P, P]
         L.fr_set_kernel_timing.argtypes = [P, C.c_int]
@@ -155,6 +156,12 @@ class Context:
         U = self._vec(U)
         out = self.empty_state() if out is None else self._vec(out)
         _check(lib().fr_rhs(self.h, _ptr(U), _ptr(out)), self.h)
+        return out
+
+    def rhs_noalloc(self, U, out):
+        """fr_rhs_noalloc: the residual with its intermediates in the library's per-device scratch."""
+        U, out = self._vec(U), self._vec(out)
+        _check(lib().fr_rhs_noalloc(self.h, _ptr(U), _ptr(out)), self.h)
         return out
 
     def jvp(self, U, v, out=None, R_out=None):
