@@ -1,11 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark of the FR-DG residual + Jacobian-block assembly on one MI355X.
 
-Workload: 2-D compressible Navier-Stokes (gamma 1.4, Re 1000, Pr 0.72), FR-DG
-degree 3 on a 128x128 periodic quad mesh with 5% sinusoidal vertex jitter,
-Rusanov + BR1 fluxes, smooth random state (rho = 1 + 0.1 s, Mach 0.2).  One
-step = R(U) plus the five 64x64 Jacobian blocks of every element (FP32 block
-storage), inputs resident in HBM.  Prints one JSON line.
+Headline workload: 3-D compressible Navier-Stokes (gamma 1.4, Re 1600,
+Pr 0.71), FR-DG degree 3 on a 24^3 periodic hexahedral mesh with 5% vertex
+jitter, Rusanov + BR1 fluxes, Taylor-Green state at Mach 0.1 with random
+phases.  One step = R(U) plus the seven 320x320 Jacobian blocks of every
+element (FP32 block storage, 39.6 GB), inputs resident in HBM.  Beside it:
+the same step with BF16 blocks, the FP64 block-Jacobi LU of the diagonal
+blocks, the 2-D NS p=3 step on 128^2 quads, the mixed-mesh batch, the
+Newton-GMRES step with block-Jacobi LU and the learned preconditioner, and
+the FP64 oracle timed on the host with each output's error against it.
+Prints one JSON line.
 
 Options: --gpus N (only 1: the benchmark drives one GPU), --steps K, --warmup W.
 """
@@ -53,10 +58,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_alg):
-    """HBM bytes per launch of the block-assembly kernel from the committed
+def measured_traffic(name):
+    """HBM bytes per launch of the block-assembly kernels from a committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_jac_mf_ns2d_p3_128_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -245,102 +250,170 @@ def batch_bench(torch, fr, I, reps, log):
             "tuning": table, "outputs_finite": finite}
 
 
-def hex3d_bench(torch, fr, I, reps, log):
-    """3-D Navier-Stokes FR-DG p=3 on 24^3 jittered periodic hexahedra
-    (Taylor-Green vortex, Re 1600): R(U), all seven 320 x 320 Jacobian
-    blocks per element in FP32 and BF16, and the FP64 block-Jacobi LU of the
-    diagonal blocks (setup from the state, then one application)."""
+def _omp():
+    """The OpenMP runtime the oracle is linked against (thread count control)."""
+    import ctypes
+    try:
+        g = ctypes.CDLL("libgomp.so.1")
+        g.omp_get_max_threads.restype = ctypes.c_int
+        return g
+    except OSError:
+        return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def cpu_baseline(m, ph, p, U32, R_gpu, Jv_gpu, v, blocks, budget_s, log):
+    """The FP64 oracle (as is) on a bounded sample of the headline workload:
+    the full-mesh residual, then all Jacobian blocks of a seeded sample of
+    elements (complex-step columns), timed on every host core and on one
+    thread; the same oracle results give each GPU output's error.
+
+    U32: the state as the GPU saw it (FP32, widened to FP64), so input
+    rounding is not charged to the kernels.  blocks: {prec: (elements,
+    GPU blocks [n, slot, c, r] as float64)} for the sampled elements."""
+    from oracle import oracle as O
+    o = O.Oracle(m, ph, p)
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nface = m.max_face
+    b = R_gpu.shape[1] * R_gpu.shape[2]
+    t0 = time.perf_counter()
+    R_ref = o.rhs(U32)
+    t_rhs = time.perf_counter() - t0
+    errors = {"R": _rel(R_gpu.reshape(-1), R_ref)}
+    Jv_ref = o.jvp(U32, v)
+    errors["Jv"] = _rel(Jv_gpu.reshape(-1), Jv_ref)
+    elems = next(iter(blocks.values()))[0]
+    t0 = time.perf_counter()
+    ref = o.jac_blocks(U32, elems, b, nface)
+    t_blk = time.perf_counter() - t0
+    for prec, (el, B) in blocks.items():
+        assert np.array_equal(el, elems)
+        Bg = B.transpose(0, 1, 3, 2)                 # [n, slot, r, c] like the oracle's
+        errors["blocks_" + prec] = max(_rel(Bg[i], ref[i]) for i in range(len(el)))
+    n = len(elems)
+    t = t_blk + t_rhs * n / m.n_elem
+    out = {"value": n * b / t, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+           "sample": f"full-mesh R ({t_rhs:.2f} s, scaled to the sample) + all {1 + nface} Jacobian blocks of "
+                     f"{n} seeded elements of {m.n_elem} ({t_blk:.1f} s); FP64, complex-step columns",
+           "cpu_model": cpu_model()}
+    if omp is not None:
+        omp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        o.jac_blocks(U32, elems[:1], b, nface)
+        t1 = time.perf_counter() - t0
+        omp.omp_set_num_threads(cores)
+        out["one_thread"] = {"value": b / (t1 + t_rhs * cores / m.n_elem), "unit": "DOF/s", "cores": 1,
+                             "sample": f"all blocks of 1 element ({t1:.1f} s) + its share of the residual "
+                                       f"(all-core R time x cores / elements, {t_rhs * cores / m.n_elem * 1e3:.2f} ms)"}
+    log(f"cpu baseline: {out['value']:.1f} DOF/s on {cores} threads; errors {errors}")
+    return out, errors
+
+
+def budget_sample(ne, budget_s, per_elem_s, cores, rng):
+    """Seeded element sample sized to about budget_s of oracle time."""
+    n = int(max(cores, min(ne, budget_s * cores / per_elem_s)))
+    return np.sort(rng.choice(ne, n, replace=False))
+
+
+def cfg2_workload():
+    from paper_2105_08632_amd import inputs as I
     p, N = 3, 24
     m = I.hex_mesh(N, degree=p, jitter=0.05)
     ph = I.ns_physics(3, 1600.0, 0.71)
     U = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
+    return m, ph, p, U
+
+
+def _timed_steps(torch, ctx, step, steps, warmup):
+    """warmup untimed steps, then steps timed with the host clock and HIP
+    events (the context stream is torch's current stream); the dominant
+    kernels (tables + assembly) are bracketed by the library's own events."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ctx.set_kernel_timing(True)
+    ctx.kernel_time(0)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()
+    jac_ms, jac_n = ctx.kernel_time(0)
+    ctx.set_kernel_timing(False)
+    return wall, ev0.elapsed_time(ev1), jac_ms / max(jac_n, 1)
+
+
+def _roofline(ctx, kernel_ms, bytes_out, traffic_file, kernel_name, ms_per_step):
+    per_launch = jac_bytes_per_element(ctx.ns, ctx.nv, ctx.info.ndim, ctx.nf, ctx.nface, bytes_out) * ctx.ne
+    achieved = per_launch / (kernel_ms * 1e-3) / 1e9
+    # one step: the Jacobian's bytes plus the residual written once (U and
+    # the geometry are read once by a fused step)
+    step_bytes = per_launch + ctx.ndof * 4
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(traffic_file),
+            "kernel": kernel_name, "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": per_launch,
+            "step_alg_bytes": step_bytes,
+            "step_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def cfg1_bench(torch, fr, steps, warmup, log):
+    """2-D NS p=3 on 128x128 quads: R(U) + the five 64x64 FP32 blocks per element."""
+    m, ph, p, U = workload()
+    Ud = torch.from_numpy(U).to(torch.float32).cuda().contiguous()
     ctx = fr.Context(m, ph, "f32")
-    Ud = torch.from_numpy(U).float().cuda().contiguous()
     R = ctx.empty_state()
+    B = ctx.block_tensor("f32")
 
-    def timed(fn, n=reps):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(n):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / n
+    def step():
+        ctx.rhs(Ud, R)
+        ctx.jacobian_blocks(Ud, B, "f32")
 
-    out = {"workload": "3D Navier-Stokes FR-DG p=3, 24^3 jittered periodic hexes (Taylor-Green, Re 1600), FP32: "
-                       "R(U), 7 Jacobian blocks 320x320 per element, FP64 block-Jacobi LU",
-           "n_elem": ctx.ne, "dof": ctx.ndof, "block": ctx.b}
-    out["rhs_ms"] = round(timed(lambda: ctx.rhs(Ud, R)), 4)
-    for prec, sz in (("f32", 4), ("bf16", 2)):
-        B = ctx.block_tensor(prec)
-        ctx.set_kernel_timing(True)
-        ctx.kernel_time(0)
-        t = timed(lambda: ctx.jacobian_blocks(Ud, B, prec))
-        ctx.sync()
-        kms, kn = ctx.kernel_time(0)
-        ctx.set_kernel_timing(False)
-        ob = B.numel() * sz
-        out["jac_" + prec] = {"ms": round(t, 3), "kernel_ms": round(kms / max(kn, 1), 3), "out_GB": round(ob / 1e9, 2),
-                              "out_GB_per_s": round(ob / (t * 1e-3) / 1e9, 1)}
-        del B
-        torch.cuda.empty_cache()
-    out["dof_per_s_rhs_plus_jac_f32"] = ctx.ndof / ((out["rhs_ms"] + out["jac_f32"]["ms"]) * 1e-3)
-    rho = U[..., 0]
-    v = U[..., 1:4] / rho[..., None]
-    pr = 0.4 * (U[..., 4] - 0.5 * rho * np.sum(v * v, axis=-1))
-    dt = 5.0 / N / float(np.max(np.linalg.norm(v, axis=-1) + np.sqrt(1.4 * pr / rho)))
-    pc = fr.Precond(ctx)
-    t_setup = timed(lambda: pc.setup(Ud, 1.0, -dt), 2)
-    z = ctx.empty_state()
-    t_apply = timed(lambda: pc.apply(R, z))
-    flop = ctx.ne * (2.0 / 3.0) * ctx.b ** 3
-    out["block_lu"] = {"setup_ms": round(t_setup, 2), "apply_ms": round(t_apply, 3),
-                       "lu_gflop": round(flop / 1e9, 1), "note": "setup = diagonal blocks (FP32) + FP64 LU of each",
-                       "finite": bool(torch.isfinite(z).all())}
-    log(f"hex3d: rhs {out['rhs_ms']} ms, jac f32 {out['jac_f32']['ms']} ms, bf16 {out['jac_bf16']['ms']} ms, "
-        f"LU setup {out['block_lu']['setup_ms']} ms, apply {out['block_lu']['apply_ms']} ms")
-    pc.close()
+    wall, gpu_ms, kms = _timed_steps(torch, ctx, step, steps, warmup)
+    ms = 1e3 * wall / steps
+    out = {"workload": "2D Navier-Stokes FR-DG p=3, 128x128 jittered periodic quads, R(U) + 5 Jacobian blocks "
+                       "64x64 per element (FP32 blocks, FP64 residual)",
+           "n_elem": ctx.ne, "dof": ctx.ndof, "ms_per_step": round(ms, 4), "dof_per_s": ctx.ndof / (ms * 1e-3),
+           "roofline": _roofline(ctx, kms, 4, "k_jac_mf_ns2d_p3_128_traffic.json",
+                                 "k_jac_mf_tab + k_jac_mf_asm (quads p=3)", ms)}
+    log(f"cfg1: {ms:.4f} ms per step, Jacobian kernels {kms:.4f} ms")
     return out
-
-
-def cpu_baseline(m, ph, p, U, budget_s):
-    """The FP64 oracle (as is) on a bounded sample: the full-mesh residual,
-    then the five Jacobian blocks of a seeded sample of elements."""
-    from oracle import oracle as O
-    o = O.Oracle(m, ph, p)
-    t0 = time.perf_counter()
-    o.rhs(U)
-    t_rhs = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    b = 16 * 4
-    cal = rng.choice(m.n_elem, 16, replace=False)
-    t0 = time.perf_counter()
-    o.jac_blocks(U, cal, b, 4)
-    t_cal = (time.perf_counter() - t0) / len(cal)
-    n = int(max(16, min(m.n_elem, budget_s / max(t_cal, 1e-6))))
-    sample = rng.choice(m.n_elem, n, replace=False)
-    t0 = time.perf_counter()
-    o.jac_blocks(U, sample, b, 4)
-    t_blk = time.perf_counter() - t0
-    t = t_blk + t_rhs * n / m.n_elem
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n * b / t, "unit": "DOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"full-mesh R ({t_rhs:.2f} s, scaled to the sample) + 5 Jacobian blocks of {n} of "
-                      f"{m.n_elem} elements ({t_blk:.1f} s); FP64, complex-step columns"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-newton", action="store_true", help="skip the Newton-GMRES part of the metric")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-mesh batch measurement")
-    ap.add_argument("--no-hex", action="store_true", help="skip the 3-D hexahedral measurement")
+    ap.add_argument("--no-cfg1", action="store_true", help="skip the 2-D quadrilateral measurement")
+    ap.add_argument("--no-lu", action="store_true", help="skip the block-Jacobi LU of the 3-D blocks")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 block assembly")
+    ap.add_argument("--only", choices=["cfg2", "cfg1"], default=None,
+                    help="time only this workload's step (profiling runs)")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
@@ -349,11 +422,21 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py drives exactly one GPU: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    log = lambda s: print(s, file=sys.stderr, flush=True)  # noqa: E731
 
     import torch
     from paper_2105_08632_amd import fr
+    from paper_2105_08632_amd import inputs as I
 
-    m, ph, p, U = workload()
+    if args.only == "cfg1":
+        out = cfg1_bench(torch, fr, args.steps, args.warmup, log)
+        if args.copy_probe > 0:
+            _copy_probe(torch, args.copy_probe)
+        print(json.dumps(out), flush=True)
+        return
+
+    # ---- headline: 3-D NS p=3 on 24^3 hexahedra, R(U) + seven 320x320 FP32 blocks per element
+    m, ph, p, U = cfg2_workload()
     dev = torch.device("cuda:0")
     Ud = torch.from_numpy(U).to(torch.float32).to(dev).contiguous()
     ctx = fr.Context(m, ph, "f32")
@@ -365,66 +448,120 @@ def main():
         ctx.rhs(Ud, R)
         ctx.jacobian_blocks(Ud, B, "f32")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.sync()
-    ctx.set_kernel_timing(True)
-    ctx.kernel_time(0)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.sync()
-    jac_ms, jac_n = ctx.kernel_time(0)
-    gpu_ms = ev0.elapsed_time(ev1)
+    wall, gpu_ms, kms = _timed_steps(torch, ctx, step, args.steps, args.warmup)
     ms_per_step = 1e3 * wall / args.steps
-
-    per_launch = jac_bytes_per_element(ctx.ns, ctx.nv, 2, ctx.nf, ctx.nface) * ctx.ne
-    avg_jac_s = jac_ms / max(jac_n, 1) / 1e3
-    achieved = per_launch / avg_jac_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(per_launch),
-            "kernel": "k_jac_mf_tab + k_jac_mf_asm (Jacobian tables + matrix-core block assembly)",
-            "kernel_ms": round(avg_jac_s * 1e3, 4),
-            "alg_bytes_per_launch": per_launch}
+    roof = _roofline(ctx, kms, 4, "k_jac_mf_ns3d_hex_p3_24_traffic.json",
+                     "k_jac_mf_tab + k_jac_mf_asm (Jacobian tables + matrix-core block assembly, hexes p=3)",
+                     ms_per_step)
+    log(f"cfg2 f32: {ms_per_step:.3f} ms per step, Jacobian kernels {kms:.3f} ms")
     out = {"metric": METRIC, "value": dof * args.steps / wall, "unit": "DOF/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "2D Navier-Stokes FR-DG p=3, 128x128 jittered periodic quads, "
-                                  "R(U) + 5 Jacobian blocks 64x64 per element (FP32 blocks, FP64 residual)",
+           "config": {"workload": "3D Navier-Stokes FR-DG p=3, 24^3 jittered periodic hexahedra (Taylor-Green, "
+                                  "Re 1600, Ma 0.1), R(U) + 7 Jacobian blocks 320x320 per element (FP32 blocks, "
+                                  "FP64 residual arithmetic)",
                       "n_elem": ctx.ne, "dof": dof, "gpu_ms_per_step": round(gpu_ms / args.steps, 4)},
            "roofline": roof}
     if args.copy_probe > 0:
-        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-    if not args.no_batch or not args.no_newton or not args.no_hex:
-        del B, R
+        _copy_probe(torch, args.copy_probe)
+    if args.only == "cfg2":
+        print(json.dumps(out), flush=True)
+        return
+
+    # outputs kept for the oracle comparison (the CPU leg): R, a JVP, and the
+    # blocks of a seeded element sample
+    rng = np.random.default_rng(0)
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else (os.cpu_count() or 1)
+    sample = budget_sample(ctx.ne, args.cpu_seconds, 8.0, cores, rng)
+    v = I.random_direction(U.shape, 1)
+    vd = torch.from_numpy(v).to(torch.float32).cuda().contiguous()
+    Jv = ctx.jvp(Ud, vd)
+    sel = torch.from_numpy(sample).cuda()
+    kept = {"R": R.double().cpu().numpy(), "Jv": Jv.double().cpu().numpy(),
+            "blocks": {"f32": (sample, B[sel].double().cpu().numpy())}}
+    ctx.sync()
+    del B
+    torch.cuda.empty_cache()
+    if not args.no_bf16:
+        B16 = ctx.block_tensor("bf16")
+
+        def step16():
+            ctx.rhs(Ud, R)
+            ctx.jacobian_blocks(Ud, B16, "bf16")
+
+        w16, g16, k16 = _timed_steps(torch, ctx, step16, args.steps, args.warmup)
+        ms16 = 1e3 * w16 / args.steps
+        out["bf16"] = {"ms_per_step": round(ms16, 4), "dof_per_s": dof / (ms16 * 1e-3),
+                       "roofline": _roofline(ctx, k16, 2, "k_jac_mf_ns3d_hex_p3_24_bf16_traffic.json",
+                                             "k_jac_mf_tab + k_jac_mf_asm, BF16 operands and blocks", ms16)}
+        log(f"cfg2 bf16: {ms16:.3f} ms per step, Jacobian kernels {k16:.3f} ms")
+        kept["blocks"]["bf16"] = (sample, B16[sel].double().cpu().numpy())
+        del B16
+        torch.cuda.empty_cache()
+    if not args.no_lu:
+        out["block_lu"] = block_lu_bench(torch, fr, ctx, U, Ud, R, log)
+    del ctx, R
+    torch.cuda.empty_cache()
+    if not args.no_cfg1:
+        out["cfg1"] = cfg1_bench(torch, fr, args.steps, args.warmup, log)
         torch.cuda.empty_cache()
     if not args.no_batch:
-        from paper_2105_08632_amd import inputs as I
-        out["batch"] = batch_bench(torch, fr, I, 5, lambda s: print(s, file=sys.stderr, flush=True))
-        torch.cuda.empty_cache()
-    if not args.no_hex:
-        from paper_2105_08632_amd import inputs as I
-        out["hex3d"] = hex3d_bench(torch, fr, I, 3, lambda s: print(s, file=sys.stderr, flush=True))
+        out["batch"] = batch_bench(torch, fr, I, 5, log)
         torch.cuda.empty_cache()
     if not args.no_newton:
-        from paper_2105_08632_amd import inputs as I
-        out["newton"] = newton_bench(torch, fr, I, args.mlp_steps, lambda s: print(s, file=sys.stderr, flush=True))
+        out["newton"] = newton_bench(torch, fr, I, args.mlp_steps, log)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(m, ph, p, U, args.cpu_seconds)
+        U32 = U.astype(np.float32).astype(np.float64)
+        v32 = v.astype(np.float32).astype(np.float64)
+        out["cpu_baseline"], out["errors_vs_oracle"] = cpu_baseline(
+            m, ph, p, U32, kept["R"], kept["Jv"], v32, kept["blocks"], args.cpu_seconds, log)
+        out["errors_vs_oracle"]["metric"] = ("normwise relative: max |x - x_oracle| / max |x_oracle| per output "
+                                             "(blocks: per sampled element, largest), oracle at the GPU's FP32 "
+                                             "inputs; bars FP32 1e-5, BF16 2e-2")
     print(json.dumps(out), flush=True)
+
+
+def _copy_probe(torch, mib):
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def block_lu_bench(torch, fr, ctx, U, Ud, R, log):
+    """FP64 block-Jacobi of the 3-D blocks: the diagonal blocks of
+    I - dt dR/dU (FP32 assembly) and the LU of each 320x320 block in FP64
+    (setup), then one application."""
+    N = round(ctx.ne ** (1.0 / 3.0))
+    rho = U[..., 0]
+    v = U[..., 1:4] / rho[..., None]
+    pr = 0.4 * (U[..., 4] - 0.5 * rho * np.sum(v * v, axis=-1))
+    dt = 5.0 / N / float(np.max(np.linalg.norm(v, axis=-1) + np.sqrt(1.4 * pr / rho)))
+    pc = fr.Precond(ctx)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    t_setup = timed(lambda: pc.setup(Ud, 1.0, -dt), 2)
+    z = ctx.empty_state()
+    t_apply = timed(lambda: pc.apply(R, z), 5)
+    flop = ctx.ne * (2.0 / 3.0) * ctx.b ** 3
+    out = {"setup_ms": round(t_setup, 2), "apply_ms": round(t_apply, 3), "lu_gflop": round(flop / 1e9, 1),
+           "note": "setup = diagonal blocks (FP32) + FP64 LU of each", "finite": bool(torch.isfinite(z).all())}
+    log(f"cfg2 block LU: setup {out['setup_ms']} ms, apply {out['apply_ms']} ms")
+    pc.close()
+    return out
 
 
 if __name__ == "__main__":
