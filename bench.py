@@ -119,18 +119,44 @@ def train_mlp(torch, fr, I, steps, log):
     return net, info
 
 
+def _pc_times(torch, pc, Ud, dt, r, z, reps=3):
+    """Setup and apply times of a preconditioner (HIP events, ms)."""
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+    return timed(lambda: pc.setup(Ud, 1.0, -dt), reps), timed(lambda: pc.apply(r, z), 10)
+
+
 def newton_bench(torch, fr, I, train_steps, log):
     """Seconds per backward-Euler Newton step (to |F| <= 1e-8 |F0|, GMRES(30),
-    forcing 1e-3) on 256x256 NS p=3: FP64 block-Jacobi LU vs the learned
-    preconditioner, each set up at U^n (setup time included)."""
+    forcing 1e-3) on 256x256 NS p=3: FP64 block-Jacobi (Gauss-Jordan
+    inverses) against the learned preconditioner (network, then Newton-Schulz
+    refinement, FP64 block-Jacobi fallback where ||I - A^ M||_F > theta), the
+    network alone, and the same refinement started without the network; each
+    set up at U^n (setup time included)."""
     net, info = train_mlp(torch, fr, I, train_steps, log)
     ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
     m = I.quad_mesh(256, degree=3, jitter=0.05)
+    theta = 0.05
     out = {"workload": "2D NS p=3, 256x256 jittered periodic quads (4.19 M DOF), backward Euler, Newton to "
-                       "1e-8 relative, GMRES(30) forcing 1e-3, preconditioner set up at U^n; restart cycles "
-                       "replayed from a captured hipGraph (lu_host_arnoldi: host-driven Arnoldi for comparison)",
-           "mlp_training": info}
-    runs = {"lu": [], "mlp": []}
+                       "1e-8 relative, GMRES(30) forcing 1e-3, preconditioner set up at U^n, host-driven "
+                       "Arnoldi (lu_graph: restart cycles replayed from a captured hipGraph)",
+           "mlp_training": info, "theta": theta,
+           "variants": {"lu": "FP64 block-Jacobi, Gauss-Jordan inverses (the comparator)",
+                        "learned": "network + Newton-Schulz refinement to ||I - A^M||_F <= 1e-2 (FP32, at most "
+                                   "16 steps), FP32 inverse, FP64 LU fallback above theta",
+                        "mlp_only": "network output (BF16) as is, FP64 LU fallback above theta = 1",
+                        "ns_no_network": "the same refinement from the scaled transpose (no network, at most 64 "
+                                         "steps)"}}
+    runs = {}
+    per = {}
     held = []
     cfl = 5.0
     for s in (8, 9, 10):
@@ -139,42 +165,64 @@ def newton_bench(torch, fr, I, train_steps, log):
         Ud = torch.from_numpy(U).cuda()
         dt = _dt(m, U, cfl)
         sol = fr.Solver(ctx, restart=30)
-        pcm = fr.Precond(ctx, fr.FR_PC_MLP)
-        pcm.set_mlp(net, 1e30)
-        Xh, _ = pcm.mlp_inputs(Ud, 1.0, -dt)
-        held.append(float(torch.cat([net.loss_grad(Xh[i:i + 4096].contiguous())[2]
-                                     for i in range(0, Xh.shape[0], 4096)]).mean().item()))
-        del Xh
         pcl = fr.Precond(ctx)
-        for name, pc, graph in (("lu", pcl, True), ("lu_host_arnoldi", pcl, False), ("mlp", pcm, True)):
+        pcs = {"lu": (pcl, False), "lu_graph": (pcl, True)}
+        for name, refine, start, th in (("learned", 16, "network", theta), ("mlp_only", 0, "network", 1.0),
+                                        ("ns_no_network", 64, "transpose", theta)):
+            pc = fr.Precond(ctx, fr.FR_PC_MLP)
+            pc.set_mlp(net if start == "network" else None, th)
+            pc.set_refine(refine, 1e-2, start)
+            pcs[name] = (pc, False)
+        if s == 8:
+            Xh, _ = pcs["learned"][0].mlp_inputs(Ud, 1.0, -dt)
+            held.append(float(torch.cat([net.loss_grad(Xh[i:i + 4096].contiguous())[2]
+                                         for i in range(0, Xh.shape[0], 4096)]).mean().item()))
+            del Xh
+            r = torch.randn_like(Ud)
+            z = torch.empty_like(Ud)
+            for name, (pc, _) in pcs.items():
+                if name == "lu_graph":
+                    continue
+                t_setup, t_apply = _pc_times(torch, pc, Ud, dt, r, z)
+                per[name] = {"setup_ms": round(t_setup, 3), "apply_ms": round(t_apply, 4)}
+                if name != "lu":
+                    per[name].update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in pc.stats().items()})
+            log(f"preconditioners: {per}")
+        for name, (pc, graph) in pcs.items():
             r = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False, use_graph=graph)
+            r["n_fallback"] = pc.stats()["n_fallback"] if name not in ("lu", "lu_graph") else 0
             runs.setdefault(name, []).append(r)
             log(f"newton cfl {cfl} seed {s} {name}: conv {r['converged']} newton {r['newton_iters']} "
-                f"gmres {r['gmres_iters']} s {r['ms'] / 1e3:.3f}")
+                f"gmres {r['gmres_iters']} s {r['ms'] / 1e3:.3f} fallback {r['n_fallback']}")
         if s == 8:
-            hard = {}
-            for name, pc in (("lu", fr.Precond(ctx)), ("mlp", pcm)):
-                r = sol.newton_step(Ud, pc=pc, dt=_dt(m, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False,
-                                    use_graph=True)
-                hard[name] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
-                              "gmres_iters": r["gmres_iters"], "final_rel_residual": r["res"] / r["res0"],
-                              "s": round(r["ms"] / 1e3, 3)}
-                log(f"newton cfl 100 {name}: conv {r['converged']} rel {r['res'] / r['res0']:.2e}")
-            out["cfl100"] = hard
-        del sol, pcm, ctx
+            # largest CFL at which the LU-preconditioned step converges on 256^2
+            study = {}
+            for c in (10.0, 20.0, 50.0, 100.0):
+                for name in ("lu", "learned"):
+                    pc, _ = pcs[name]
+                    r = sol.newton_step(Ud, pc=pc, dt=_dt(m, U, c), gmres_maxit=3000, newton_maxit=12,
+                                        check=False)
+                    study.setdefault(str(c), {})[name] = {
+                        "converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
+                        "gmres_iters": r["gmres_iters"], "final_rel_residual": r["res"] / r["res0"],
+                        "s": round(r["ms"] / 1e3, 3)}
+                    log(f"newton cfl {c} {name}: conv {r['converged']} gmres {r['gmres_iters']} "
+                        f"rel {r['res'] / r['res0']:.2e} s {r['ms'] / 1e3:.3f}")
+            out["cfl_study_256"] = study
+        del sol, pcs, pcl, ctx
     # CFL 100 on 64x64, where GMRES(30) with a one-level block preconditioner
-    # still converges; plain and loose GMRES (3 of each cycle's 30 directions
-    # are earlier cycles' corrections)
+    # still converges
     m64 = I.quad_mesh(64, degree=3, jitter=0.05)
     U = I.ns2d_state(m64, 3, seeds=(8, 108, 208))
     ctx = fr.Context(m64, ph, "f64")
     Ud = torch.from_numpy(U).cuda()
     sol = fr.Solver(ctx, restart=30)
-    pcm = fr.Precond(ctx, fr.FR_PC_MLP)
-    pcm.set_mlp(net, 1e30)
     pcl = fr.Precond(ctx)
+    pcm = fr.Precond(ctx, fr.FR_PC_MLP)
+    pcm.set_mlp(net, theta)
+    pcm.set_refine(16, 1e-2, "network")
     small = {}
-    for name, pc, aug in (("lu", pcl, 0), ("lu_loose3", pcl, 3), ("mlp", pcm, 0), ("mlp_loose3", pcm, 3)):
+    for name, pc, aug in (("lu", pcl, 0), ("lu_loose3", pcl, 3), ("learned", pcm, 0), ("learned_loose3", pcm, 3)):
         r = sol.newton_step(Ud, pc=pc, dt=_dt(m64, U, 100.0), gmres_maxit=3000, newton_maxit=12, check=False,
                             augment=aug)
         small[name] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
@@ -184,12 +232,20 @@ def newton_bench(torch, fr, I, train_steps, log):
     out["cfl100_64x64"] = small
     del sol, pcm, pcl, ctx
     for name, rs in runs.items():
-        out[name] = {"s_per_step_median": round(float(np.median([r["ms"] for r in rs])) / 1e3, 4),
+        ms = float(np.median([r["ms"] for r in rs]))
+        it = float(np.median([r["gmres_iters"] for r in rs]))
+        out[name] = {"s_per_step_median": round(ms / 1e3, 4),
                      "converged": [bool(r["converged"]) for r in rs],
-                     "newton_iters": [r["newton_iters"] for r in rs], "gmres_iters": [r["gmres_iters"] for r in rs]}
+                     "newton_iters": [r["newton_iters"] for r in rs], "gmres_iters": [r["gmres_iters"] for r in rs],
+                     "n_fallback": [r["n_fallback"] for r in rs]}
+        if name in per:
+            out[name].update(per[name])
+            out[name]["ms_per_gmres_iter"] = round((ms - per[name]["setup_ms"]) / max(it, 1.0), 4)
     out["cfl"] = cfl
     out["mlp_heldout_resid_mean"] = round(float(np.mean(held)), 3)
-    out["learned_over_lu_time"] = round(out["mlp"]["s_per_step_median"] / out["lu"]["s_per_step_median"], 3)
+    lu_best = min(out["lu"]["s_per_step_median"], out["lu_graph"]["s_per_step_median"])
+    out["learned_over_lu_time"] = round(out["learned"]["s_per_step_median"] / lu_best, 3)
+    out["mlp_only_over_lu_time"] = round(out["mlp_only"]["s_per_step_median"] / lu_best, 3)
     return out
 
 

@@ -170,7 +170,7 @@ typedef enum { FR_PC_BLOCK_JACOBI = 0, FR_PC_MLP = 1 } fr_pc_kind;
  * 129 to 320 (hexahedra of degree 2 and 3) factorized by a blocked LU and
  * applied by substitution; larger blocks return FR_E_UNSUPPORTED.
  * FR_PC_MLP: the learned approximate inverse (network attached with
- * fr_precond_set_mlp; blocks up to 128), with block-Jacobi as the
+ * fr_precond_set_mlp; blocks up to 64), with block-Jacobi as the
  * per-element fallback.
  * Storage for the inverses / factors (FP64, n_elem * b * b) is allocated
  * here, not in setup/apply. */
@@ -220,10 +220,30 @@ fr_status fr_mlp_loss_grad(fr_mlp* m, const void* X, int64_t nb, float* loss, fl
 /* One Adam step at learning rate lr on the batch; loss (device float or NULL)
  * receives the batch loss before the step. */
 fr_status fr_mlp_train_step(fr_mlp* m, const void* X, int64_t nb, float lr, float* loss);
-/* Attach a network to an FR_PC_MLP preconditioner.  In fr_precond_setup every
- * element with ||I - A^_n M_n||_F > theta (or non-finite) falls back to the
- * FP64 block-Jacobi inverse. */
+/* Attach a network to an FR_PC_MLP preconditioner (m may be NULL: no
+ * network, for the refinement's scaled-transpose start).  In
+ * fr_precond_setup every element with ||I - A^_n M_n||_F > theta (or
+ * non-finite) falls back to the FP64 block-Jacobi inverse.  The residual is
+ * evaluated in FP32 against A^_n rounded from the assembled block (not the
+ * network's BF16 input), after any refinement. */
 fr_status fr_precond_set_mlp(fr_precond* pc, fr_mlp* m, double theta);
+/* Newton-Schulz refinement of the approximate inverse in fr_precond_setup,
+ * before the safeguard: E = I - A^_n M_n, M_n <- M_n + M_n E (the residual
+ * squares each step), FP32 on the matrix cores, until ||E||_F <= tol, or
+ * max_iters steps, or divergence (||E||_F > 1e6).  start = 0 refines the
+ * network's output; start = 1 refines the scaled transpose
+ * A^_n^T / (|A^_n|_1 |A^_n|_inf), which converges for every nonsingular
+ * block: the same preconditioner without the network, for comparison.
+ * max_iters = 0 (the default) applies the network's BF16 output as is;
+ * otherwise the refined inverse is stored and applied in FP32.  max_iters in
+ * 0..64, tol >= 0, start 0 or 1, else FR_E_INVALID. */
+fr_status fr_precond_set_refine(fr_precond* pc, int max_iters, double tol, int start);
+/* Statistics of the last fr_precond_setup of an FR_PC_MLP preconditioner
+ * (zeros for block-Jacobi): elements that fell back to block-Jacobi, mean
+ * refinement steps, mean and largest ||I - A^_n M_n||_F.  Any pointer may be
+ * NULL. */
+fr_status fr_precond_stats(const fr_precond* pc, int64_t* n_fallback, double* mean_refine_iters, double* mean_resid,
+                           double* max_resid);
 /* Training samples: assembles A_n = shift I + scale dR_n/dU_n at U and
  * writes X (BF16, n_elem x b^2) and s (FP32, n_elem). */
 fr_status fr_precond_mlp_inputs(fr_precond* pc, const void* U, double shift, double scale, void* X, float* s);

@@ -301,34 +301,138 @@ __global__ void __launch_bounds__(256) k_mlp_inputs(long ne, int b, const IT* J,
 
 // z_n = M_n r_n / s_n (network), or Ainv_n r_n where the safeguard rejected
 // the network (use_lu[n] != 0).  One wavefront per element, lanes over rows.
-template <class VT>
-__global__ void __launch_bounds__(256) k_mlp_apply(long ne, int b, const bfu* M, const float* s, const int* use_lu,
+template <class VT, class MT>
+__global__ void __launch_bounds__(256) k_mlp_apply(long ne, int b, const MT* M, const float* s, const int* use_lu,
                                                    const double* Ainv, const VT* r, VT* z) {
   const int lane = threadIdx.x & 63;
   const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= ne) return;
   const long bb = (long)b * b;
-  const VT* rn = r + n * b;
-  double a0 = 0.0, a1 = 0.0;
-  const int r0 = lane, r1 = lane + 64;
-  if (use_lu[n]) {
-    const double* A = Ainv + n * bb;
-    for (int c = 0; c < b; ++c) {
-      const double rc = (double)rn[c];
-      if (r0 < b) a0 += A[(long)c * b + r0] * rc;
-      if (r1 < b) a1 += A[(long)c * b + r1] * rc;
+  if (use_lu[n]) block_matvec<double, VT>(b, Ainv + n * bb, r + n * b, 1.0, z + n * b, lane);
+  else block_matvec<MT, VT>(b, M + n * bb, r + n * b, 1.0 / (double)s[n], z + n * b, lane);
+}
+
+// ------------------------------------------------------------------ refinement
+// Newton-Schulz refinement of an approximate inverse M of A^ = (shift I +
+// scale J_n) / s_n, one workgroup of four wavefronts per element (b <= 64,
+// padded to 64 with identity rows and columns):
+//   E = I - A^ M,   M <- M + M E      (the new residual is E^2)
+// until ||E||_F <= tol, max_it steps, or divergence (||E||_F > 1e6 or not
+// finite).  A^ is rounded to FP32 from the assembled block (not from the
+// network's BF16 input), so res[n] is the residual the safeguard needs.
+// start 0: M from the network output (BF16); start 1: the scaled transpose
+// A^T / (|A^|_1 |A^|_inf), for which rho(I - A^ M) < 1 for any nonsingular
+// block (the refinement without the network).  Products on
+// v_mfma_f32_16x16x4f32: wave w owns rows 16w..16w+15 of each product.
+constexpr int kNS = 64, kNSS = 68;   // padded order; LDS row stride (16-byte aligned rows)
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float ns_acc;
+
+// C rows 16w..16w+15, columns 0..63: C[r][c] = sum_k A[r][k] B[k][c], A and B
+// row-major with stride kNSS.  Matrix instruction kk takes k = 16 g + kk in
+// the slot of lane group g (the order of a sum over k is free as long as A
+// and B agree), so each lane reads its sixteen A values as four 16-byte runs.
+__device__ __forceinline__ void ns_gemm(const float* A, const float* B, int w, int lane, ns_acc (&acc)[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = ns_acc{0.f, 0.f, 0.f, 0.f};
+  const int i = lane & 15, g = lane >> 4;
+  const float4* ar = (const float4*)(A + (16 * w + i) * kNSS + 16 * g);
+  float av[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = ar[q];
+    av[4 * q] = v.x; av[4 * q + 1] = v.y; av[4 * q + 2] = v.z; av[4 * q + 3] = v.w;
+  }
+  const float* bcol = B + 16 * g * kNSS + i;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk], bcol[kk * kNSS + 16 * t], acc[t], 0, 0, 0);
+}
+
+template <class IT>
+__global__ void __launch_bounds__(256) k_ns_refine(long ne, int b, const IT* J, double shift, double scale,
+                                                   const float* s, const bfu* M0, int start, int max_it, float tol,
+                                                   float* Mout, float* res, int* iters) {
+  __shared__ __attribute__((aligned(16))) float Ar[kNS * kNSS];   // A^ row-major
+  __shared__ __attribute__((aligned(16))) float Mr[kNS * kNSS];   // M row-major
+  __shared__ __attribute__((aligned(16))) float Er[kNS * kNSS];   // E row-major
+  __shared__ float red[8];
+  const long n = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const long bb = (long)b * b;
+  const double is = 1.0 / (double)s[n];
+  for (int i = tid; i < kNS * kNS; i += 256) {
+    const int c = i >> 6, r = i & 63;
+    float a = (r == c) ? 1.f : 0.f;
+    if (r < b && c < b) a = (float)((scale * (double)J[n * bb + (long)c * b + r] + (r == c ? shift : 0.0)) * is);
+    Ar[r * kNSS + c] = a;
+  }
+  __syncthreads();
+  if (start == 1) {
+    // alpha = 1 / (largest column sum * largest row sum) of |A^|
+    float cs = 0.f;
+    if (tid < 64) {
+      for (int r = 0; r < kNS; ++r) cs += fabsf(Ar[r * kNSS + tid]);
+    } else if (tid < 128) {
+      for (int c = 0; c < kNS; ++c) cs += fabsf(Ar[(tid - 64) * kNSS + c]);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) cs = fmaxf(cs, __shfl_xor(cs, m, 64));
+    if (lane == 0) red[w] = cs;
+    __syncthreads();
+    const float alpha = 1.f / (red[0] * red[1]);
+    for (int i = tid; i < kNS * kNS; i += 256) {
+      const int c = i >> 6, r = i & 63;
+      Mr[r * kNSS + c] = alpha * Ar[c * kNSS + r];        // M[r][c] = alpha A^[c][r]
     }
   } else {
-    const bfu* Mn = M + n * bb;
-    const double is = 1.0 / (double)s[n];
-    for (int c = 0; c < b; ++c) {
-      const double rc = (double)rn[c] * is;
-      if (r0 < b) a0 += (double)bf2f(Mn[(long)c * b + r0]) * rc;
-      if (r1 < b) a1 += (double)bf2f(Mn[(long)c * b + r1]) * rc;
+    for (int i = tid; i < kNS * kNS; i += 256) {
+      const int c = i >> 6, r = i & 63;
+      float v = (r == c) ? 1.f : 0.f;
+      if (r < b && c < b) v = bf2f(M0[n * bb + (long)c * b + r]);
+      Mr[r * kNSS + c] = v;
     }
   }
-  if (r0 < b) z[n * b + r0] = (VT)a0;
-  if (r1 < b) z[n * b + r1] = (VT)a1;
+  __syncthreads();
+  // output fragment of this lane: rows rq..rq+3, column 16 t + col of tile t
+  const int col = lane & 15, rq = 16 * w + 4 * (lane >> 4);
+  int it = 0;
+  float nrm = 0.f;
+  for (;;) {
+    ns_acc acc[4];
+    ns_gemm(Ar, Mr, w, lane, acc);                         // T = A^ M
+    float ss = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rq + v, c = 16 * t + col;
+        const float e = ((r == c) ? 1.f : 0.f) - acc[t][v];
+        Er[r * kNSS + c] = e;
+        ss += e * e;
+      }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m, 64);
+    if (lane == 0) red[4 + w] = ss;
+    __syncthreads();
+    nrm = sqrtf(red[4] + red[5] + red[6] + red[7]);
+    if (!(nrm > tol) || it >= max_it || !(nrm <= 1e6f)) break;   // uniform over the workgroup
+    ns_gemm(Mr, Er, w, lane, acc);                         // P = M E
+    __syncthreads();                                       // every wave has read M
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Mr[(rq + v) * kNSS + 16 * t + col] += acc[t][v];
+    __syncthreads();
+    ++it;
+  }
+  float* out = Mout + n * bb;
+  for (int i = tid; i < b * b; i += 256) {
+    const int c = i / b, r = i % b;
+    out[i] = Mr[r * kNSS + c];
+  }
+  if (tid == 0) { res[n] = nrm; iters[n] = it; }
 }
 
 // ------------------------------------------------------------------ host object
@@ -459,9 +563,17 @@ struct PcMlp {
   float* res = nullptr;   // [ne] ||A^ M - I||_F
   int* use_lu = nullptr;  // [ne]
   int* list = nullptr;    // [ne] elements that fall back to LU
+  float* M32 = nullptr;   // [ne][b*b] refined inverses (FP32)
+  int* iters = nullptr;   // [ne] refinement steps taken
   float* res_host = nullptr;
   int* flag_host = nullptr;
+  int* iters_host = nullptr;
   long n_fallback = 0;
+  // Newton-Schulz refinement: steps, tolerance, start (0 network, 1 scaled transpose)
+  int refine = 0;
+  float refine_tol = 0.f;
+  int start = 0;
+  double mean_iters = 0.0, mean_res = 0.0, max_res = 0.0;
 };
 
 static fr_status sfail_pc(fr_precond_s* pc, fr_status s, const std::string& m) {
@@ -478,14 +590,21 @@ fr_status pc_mlp_create(fr_precond_s* pc) {
   size_t o3 = o2 + ((ne * 4 + 255) & ~(size_t)255);
   size_t o4 = o3 + ((ne * 4 + 255) & ~(size_t)255);
   size_t o5 = o4 + ((ne * 4 + 255) & ~(size_t)255);
-  size_t tot = o5 + ne * 4;
+  size_t o6 = o5 + ((ne * 4 + 255) & ~(size_t)255);
+  size_t o7 = o6 + ((ne * bb * 4 + 255) & ~(size_t)255);
+  size_t tot = o7 + ne * 4;
   if (hipMalloc(&p->mem, tot) != hipSuccess) { delete p; c->err = "learned-preconditioner storage"; return FR_E_NOMEM; }
   char* base = (char*)p->mem;
   p->X = (bfu*)base; p->M = (bfu*)(base + o1); p->s = (float*)(base + o2); p->res = (float*)(base + o3);
-  p->use_lu = (int*)(base + o4); p->list = (int*)(base + o5);
+  p->use_lu = (int*)(base + o4); p->list = (int*)(base + o5); p->M32 = (float*)(base + o6);
+  p->iters = (int*)(base + o7);
   if (hipHostMalloc((void**)&p->res_host, ne * 4, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&p->flag_host, ne * 4, hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(p->mem); delete p; c->err = "pinned buffers"; return FR_E_NOMEM;
+      hipHostMalloc((void**)&p->flag_host, ne * 4, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->iters_host, ne * 4, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(p->mem);
+    if (p->res_host) (void)hipHostFree(p->res_host);
+    if (p->flag_host) (void)hipHostFree(p->flag_host);
+    delete p; c->err = "pinned buffers"; return FR_E_NOMEM;
   }
   pc->mlp = p;
   return FR_OK;
@@ -497,6 +616,7 @@ void pc_mlp_destroy(fr_precond_s* pc) {
   (void)hipFree(p->mem);
   (void)hipHostFree(p->res_host);
   (void)hipHostFree(p->flag_host);
+  (void)hipHostFree(p->iters_host);
   delete p;
   pc->mlp = nullptr;
 }
@@ -515,36 +635,59 @@ static fr_status pc_mlp_normalise(fr_precond_s* pc, const void* U, double shift,
   return FR_OK;
 }
 
+static bool b_too_large(const fr_ctx_s* c) { return c->b > kNS; }
+
 fr_status pc_mlp_setup(fr_precond_s* pc, const void* U, double shift, double scale) {
   fr_ctx_s* c = pc->ctx;
   PcMlp* p = (PcMlp*)pc->mlp;
-  if (!p->net) { c->err = "learned preconditioner has no network (fr_precond_set_mlp)"; return FR_E_INVALID; }
+  const bool use_net = p->start == 0;
+  if (use_net && !p->net) {
+    c->err = "learned preconditioner has no network (fr_precond_set_mlp)"; return FR_E_INVALID;
+  }
+  if (b_too_large(c)) { c->err = "learned preconditioner: blocks up to 64 x 64"; return FR_E_UNSUPPORTED; }
   fr_mlp_s* mm = p->net;
   const long ne = c->ne;
   const int b = c->b;
   fr_status st = pc_mlp_normalise(pc, U, shift, scale, p->X, p->s);
   if (st) return st;
   // network outputs in chunks of the network's batch capacity
-  for (long n0 = 0; n0 < ne; n0 += mm->max_batch) {
-    long nb = std::min<long>(mm->max_batch, ne - n0);
-    if ((st = mlp_forward(mm, c->stream, p->X + n0 * mm->nin, nb, p->M + n0 * mm->nin))) {
-      c->err = mm->err; return st;
+  if (use_net)
+    for (long n0 = 0; n0 < ne; n0 += mm->max_batch) {
+      long nb = std::min<long>(mm->max_batch, ne - n0);
+      if ((st = mlp_forward(mm, c->stream, p->X + n0 * mm->nin, nb, p->M + n0 * mm->nin))) {
+        c->err = mm->err; return st;
+      }
     }
-  }
-  // safeguard: ||I - A^ M||_F per element
-  hipLaunchKernelGGL(k_mlp_resid, dim3(ne), dim3(256), 0, c->stream, b, p->X, p->M, 0.f, p->res, (bfu*)nullptr);
-  if (hipGetLastError() != hipSuccess) { c->err = "k_mlp_resid launch"; return FR_E_DEVICE; }
+  // refinement (none: 0 steps) and the safeguard residual ||I - A^ M||_F
+  // against the assembled block in FP32
+  if (c->prec == 0)
+    hipLaunchKernelGGL(k_ns_refine<double>, dim3(ne), dim3(256), 0, c->stream, ne, b, (const double*)pc->jbuf, shift,
+                       scale, (const float*)p->s, (const bfu*)p->M, p->start, p->refine, p->refine_tol, p->M32,
+                       p->res, p->iters);
+  else
+    hipLaunchKernelGGL(k_ns_refine<float>, dim3(ne), dim3(256), 0, c->stream, ne, b, (const float*)pc->jbuf, shift,
+                       scale, (const float*)p->s, (const bfu*)p->M, p->start, p->refine, p->refine_tol, p->M32,
+                       p->res, p->iters);
+  if (hipGetLastError() != hipSuccess) { c->err = "k_ns_refine launch"; return FR_E_DEVICE; }
   if (hipMemcpyAsync(p->res_host, p->res, ne * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipMemcpyAsync(p->iters_host, p->iters, ne * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     c->err = "safeguard residual copy"; return FR_E_DEVICE;
   }
   std::vector<int> lst;
+  double sum_it = 0.0, sum_res = 0.0, max_res = 0.0;
   for (long n = 0; n < ne; ++n) {
     const float r = p->res_host[n];
     const int fb = !(r <= (float)p->theta);          // also catches NaN
     p->flag_host[n] = fb;
     if (fb) lst.push_back((int)n);
+    sum_it += p->iters_host[n];
+    sum_res += std::isfinite(r) ? r : 1e30;
+    max_res = std::max(max_res, std::isfinite(r) ? (double)r : 1e30);
   }
+  p->mean_iters = sum_it / (double)ne;
+  p->mean_res = sum_res / (double)ne;
+  p->max_res = max_res;
   p->n_fallback = (long)lst.size();
   if (hipMemcpyAsync(p->use_lu, p->flag_host, ne * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
     c->err = "fallback flags copy"; return FR_E_DEVICE;
@@ -572,12 +715,22 @@ fr_status pc_mlp_apply(fr_precond_s* pc, const void* r, void* z) {
   PcMlp* p = (PcMlp*)pc->mlp;
   const long ne = c->ne;
   const int grid = (int)((ne + 3) / 4);
-  if (c->prec == 0)
-    hipLaunchKernelGGL((k_mlp_apply<double>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, p->M, p->s, p->use_lu,
-                       pc->inv, (const double*)r, (double*)z);
-  else
-    hipLaunchKernelGGL((k_mlp_apply<float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b, p->M, p->s, p->use_lu,
-                       pc->inv, (const float*)r, (float*)z);
+  // the network's BF16 output when it is used as is, else the refined FP32 inverse
+  if (p->refine == 0 && p->start == 0) {
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_mlp_apply<double, bfu>), dim3(grid), dim3(256), 0, c->stream, ne, c->b,
+                         (const bfu*)p->M, p->s, p->use_lu, pc->inv, (const double*)r, (double*)z);
+    else
+      hipLaunchKernelGGL((k_mlp_apply<float, bfu>), dim3(grid), dim3(256), 0, c->stream, ne, c->b,
+                         (const bfu*)p->M, p->s, p->use_lu, pc->inv, (const float*)r, (float*)z);
+  } else {
+    if (c->prec == 0)
+      hipLaunchKernelGGL((k_mlp_apply<double, float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b,
+                         (const float*)p->M32, p->s, p->use_lu, pc->inv, (const double*)r, (double*)z);
+    else
+      hipLaunchKernelGGL((k_mlp_apply<float, float>), dim3(grid), dim3(256), 0, c->stream, ne, c->b,
+                         (const float*)p->M32, p->s, p->use_lu, pc->inv, (const float*)r, (float*)z);
+  }
   if (hipGetLastError() != hipSuccess) { c->err = "k_mlp_apply launch"; return FR_E_DEVICE; }
   return FR_OK;
 }
@@ -694,9 +847,9 @@ fr_status fr_mlp_train_step(fr_mlp* m, const void* X, int64_t nb, float lr, floa
 }
 
 fr_status fr_precond_set_mlp(fr_precond* pc, fr_mlp* m, double theta) {
-  if (!pc || !m) return FR_E_INVALID;
+  if (!pc) return FR_E_INVALID;
   if (pc->kind != FR_PC_MLP) return sfail_pc(pc, FR_E_INVALID, "fr_precond_set_mlp needs an FR_PC_MLP preconditioner");
-  if (m->b != pc->ctx->b) return sfail_pc(pc, FR_E_INVALID, "network block size differs from the context's");
+  if (m && m->b != pc->ctx->b) return sfail_pc(pc, FR_E_INVALID, "network block size differs from the context's");
   PcMlp* p = (PcMlp*)pc->mlp;
   p->net = m;
   p->theta = theta;
@@ -707,6 +860,30 @@ fr_status fr_precond_set_mlp(fr_precond* pc, fr_mlp* m, double theta) {
 fr_status fr_precond_mlp_inputs(fr_precond* pc, const void* U, double shift, double scale, void* X, float* s) {
   if (!pc || !U || !X || !s) return FR_E_INVALID;
   return pc_mlp_normalise(pc, U, shift, scale, (bfu*)X, s);
+}
+
+fr_status fr_precond_set_refine(fr_precond* pc, int max_iters, double tol, int start) {
+  if (!pc) return FR_E_INVALID;
+  if (pc->kind != FR_PC_MLP) return sfail_pc(pc, FR_E_INVALID, "fr_precond_set_refine needs an FR_PC_MLP preconditioner");
+  if (max_iters < 0 || max_iters > 64 || !(tol >= 0.0) || (start != 0 && start != 1))
+    return sfail_pc(pc, FR_E_INVALID, "fr_precond_set_refine: max_iters in 0..64, tol >= 0, start 0 or 1");
+  PcMlp* p = (PcMlp*)pc->mlp;
+  p->refine = max_iters;
+  p->refine_tol = (float)tol;
+  p->start = start;
+  pc->ready = false;
+  return FR_OK;
+}
+
+fr_status fr_precond_stats(const fr_precond* pc, int64_t* n_fallback, double* mean_refine_iters, double* mean_resid,
+                           double* max_resid) {
+  if (!pc) return FR_E_INVALID;
+  const PcMlp* p = (pc->kind == FR_PC_MLP) ? (const PcMlp*)pc->mlp : nullptr;
+  if (n_fallback) *n_fallback = p ? p->n_fallback : 0;
+  if (mean_refine_iters) *mean_refine_iters = p ? p->mean_iters : 0.0;
+  if (mean_resid) *mean_resid = p ? p->mean_res : 0.0;
+  if (max_resid) *max_resid = p ? p->max_res : 0.0;
+  return FR_OK;
 }
 
 fr_status fr_precond_info(const fr_precond* pc, int64_t* n_fallback) {

@@ -112,6 +112,83 @@ __global__ void __launch_bounds__(kInvThreads) k_block_inverse(const IT* J, long
   if (tid == 0) bad[n] = s_bad;
 }
 
+// Blocks up to 64 x 64: one wavefront per element, row r of A_n held in the
+// registers of lane r.  Gauss-Jordan exchange steps without row
+// interchanges: step k takes as pivot the unused row p_k with the largest
+// |A[r][k]| (ties: the lowest row), scales it by 1/pivot and eliminates
+// column k from every other row; the final tableau T then holds the inverse
+// with permuted rows and columns, inv[k][p_j] = T[p_k][j].  After each step
+// every row moves one register down (the new column k goes to the last
+// register), so the pivot column always sits in register 0 and every
+// register index is a compile-time constant; after b steps register i holds
+// column (i + b) mod 64.  The normalised pivot row reaches the other lanes
+// through LDS.  Rows b..63 are identity rows that are never pivots.
+template <class IT>
+__global__ void __launch_bounds__(256) k_block_inverse_w64(const IT* J, long jstride, int b, double shift,
+                                                          double scale, double* Ainv, int* bad, const int* list,
+                                                          long count) {
+  __shared__ double prow_s[4][64];
+  __shared__ int perm_s[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long item = (long)blockIdx.x * 4 + w;
+  if (item >= count) return;                  // per-wave work, no workgroup barriers
+  const long n = list ? (long)list[item] : item;
+  const IT* Jn = J + n * jstride;
+  double* prow = prow_s[w];
+  double a[64];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) {
+    double v = (lane == c) ? 1.0 : 0.0;
+    if (lane < b && c < b) v = scale * (double)Jn[(long)c * b + lane] + (lane == c ? shift : 0.0);
+    a[c] = v;
+  }
+  bool used = lane >= b;
+  int kstep = 0, sbad = 0;
+  for (int k = 0; k < b; ++k) {
+    const double a0 = a[0];
+    const double av = fabs(a0);
+    double v = used ? -2.0 : (av == av ? av : -1.0);   // NaN rows rank below zero rows
+    int idx = lane;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const double ov = __shfl_xor(v, m, 64);
+      const int oi = __shfl_xor(idx, m, 64);
+      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(idx);
+    const double pv = __shfl(a0, p, 64);
+    const bool ok = (v > 0.0) && isfinite(pv);
+    sbad |= !ok;
+    const double ip = ok ? 1.0 / pv : 0.0;
+    const bool is_p = lane == p;
+    if (is_p) {
+#pragma unroll
+      for (int i = 0; i < 63; ++i) prow[i] = a[i + 1] * ip;
+      used = true;
+      kstep = k;
+    }
+    if (lane == 0) perm_s[w][k] = p;
+    __builtin_amdgcn_wave_barrier();
+    // pivot row: T'[p][.] = T[p][.] / pivot, T'[p][k] = 1 / pivot;
+    // other rows: T'[r][.] = T[r][.] - T[r][k] T'[p][.], T'[r][k] = -T[r][k] / pivot
+    const double f = is_p ? -1.0 : a0;
+    const double keep = is_p ? 0.0 : 1.0;
+#pragma unroll
+    for (int i = 0; i < 63; ++i) a[i] = fma(-f, prow[i], a[i + 1] * keep);
+    a[63] = is_p ? ip : -a0 * ip;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if (lane < b) {
+    double* out = Ainv + n * (long)b * b;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const int j = (i + b) & 63;
+      if (j < b) out[(long)perm_s[w][j] * b + kstep] = a[i];
+    }
+  }
+  if (lane == 0) bad[n] = sbad;
+}
+
 // z_n = Ainv_n r_n, one wavefront per element, lanes over rows, columns
 // streamed (column-major inverse: each column is a contiguous run).
 template <class VT>
@@ -119,17 +196,7 @@ __global__ void __launch_bounds__(256) k_block_apply(long ne, int b, const doubl
   const int lane = threadIdx.x & 63;
   const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (n >= ne) return;
-  const double* M = Ainv + n * b * b;
-  const VT* rn = r + n * b;
-  double acc0 = 0.0, acc1 = 0.0;
-  const int r0 = lane, r1 = lane + 64;
-  for (int c = 0; c < b; ++c) {
-    double rc = (double)rn[c];
-    if (r0 < b) acc0 += M[(long)c * b + r0] * rc;
-    if (r1 < b) acc1 += M[(long)c * b + r1] * rc;
-  }
-  if (r0 < b) z[n * b + r0] = (VT)acc0;
-  if (r1 < b) z[n * b + r1] = (VT)acc1;
+  block_matvec<double, VT>(b, Ainv + n * b * b, r + n * b, 1.0, z + n * b, lane);
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -557,12 +624,13 @@ fr_status pc_invert(fr_precond_s* pc, double shift, double scale, const int* lis
   if (count <= 0) return FR_OK;
   const void* J = pc->jbuf;
   if (b <= 64) {
+    const unsigned grid = (unsigned)((count + 3) / 4);
     if (c->prec == 0)
-      hipLaunchKernelGGL((k_block_inverse<double, 64>), dim3(count), dim3(kInvThreads), 0, c->stream,
-                         (const double*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
+      hipLaunchKernelGGL((k_block_inverse_w64<double>), dim3(grid), dim3(256), 0, c->stream, (const double*)J, bb, b,
+                         shift, scale, pc->inv, pc->bad, list, count);
     else
-      hipLaunchKernelGGL((k_block_inverse<float, 64>), dim3(count), dim3(kInvThreads), 0, c->stream,
-                         (const float*)J, bb, b, shift, scale, pc->inv, pc->bad, list);
+      hipLaunchKernelGGL((k_block_inverse_w64<float>), dim3(grid), dim3(256), 0, c->stream, (const float*)J, bb, b,
+                         shift, scale, pc->inv, pc->bad, list, count);
   } else if (b <= 128) {
     if (c->prec == 0)
       hipLaunchKernelGGL((k_block_inverse<double, 128>), dim3(count), dim3(kInvThreads), 0, c->stream,
@@ -934,7 +1002,7 @@ fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
   *out = nullptr;
   if (kind != FR_PC_BLOCK_JACOBI && kind != FR_PC_MLP) return sfail(c, FR_E_INVALID, "unknown preconditioner kind");
   if (c->b > kLuMaxB) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
-  if (kind == FR_PC_MLP && c->b > 128) return sfail(c, FR_E_UNSUPPORTED, "learned preconditioner blocks up to 128 x 128");
+  if (kind == FR_PC_MLP && c->b > 64) return sfail(c, FR_E_UNSUPPORTED, "learned preconditioner blocks up to 64 x 64");
   fr_precond_s* pc = new fr_precond_s();
   pc->ctx = c; pc->kind = kind;
   const size_t bb = (size_t)c->b * c->b, ne = (size_t)c->ne;

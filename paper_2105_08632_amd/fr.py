@@ -327,16 +327,19 @@ def _mlp_symbols(L):
     L.fr_precond_set_mlp.argtypes = [P, P, C.c_double]
     L.fr_precond_mlp_inputs.argtypes = [P, P, C.c_double, C.c_double, P, P]
     L.fr_precond_info.argtypes = [P, C.POINTER(C.c_int64)]
+    L.fr_precond_set_refine.argtypes = [P, C.c_int, C.c_double, C.c_int]
+    L.fr_precond_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]
     for n in ("fr_mlp_create", "fr_mlp_destroy", "fr_mlp_info", "fr_mlp_set_params", "fr_mlp_get_params",
               "fr_mlp_forward", "fr_mlp_loss_grad", "fr_mlp_train_step", "fr_precond_set_mlp",
-              "fr_precond_mlp_inputs", "fr_precond_info"):
+              "fr_precond_mlp_inputs", "fr_precond_info", "fr_precond_set_refine", "fr_precond_stats"):
         getattr(L, n).restype = C.c_int
 
 
 _extensions.append(_mlp_symbols)
 EXPORTED += ["fr_mlp_create", "fr_mlp_destroy", "fr_mlp_last_error", "fr_mlp_info", "fr_mlp_set_params",
              "fr_mlp_get_params", "fr_mlp_forward", "fr_mlp_loss_grad", "fr_mlp_train_step", "fr_precond_set_mlp",
-             "fr_precond_mlp_inputs", "fr_precond_info"]
+             "fr_precond_mlp_inputs", "fr_precond_info", "fr_precond_set_refine", "fr_precond_stats"]
 
 
 def _mcheck(rc: int, h):
@@ -409,9 +412,21 @@ class Mlp:
             pass
 
 
-def _precond_set_mlp(self, mlp: Mlp, theta: float):
-    _check(lib().fr_precond_set_mlp(self.h, mlp.h, theta), self.ctx.h)
+def _precond_set_mlp(self, mlp: Mlp | None, theta: float):
+    _check(lib().fr_precond_set_mlp(self.h, None if mlp is None else mlp.h, theta), self.ctx.h)
     self.mlp = mlp
+
+
+def _precond_set_refine(self, max_iters: int, tol: float = 1e-2, start: str = "network"):
+    """Newton-Schulz refinement after the network (start="network") or from
+    the scaled transpose (start="transpose": the same without the network)."""
+    _check(lib().fr_precond_set_refine(self.h, max_iters, tol, {"network": 0, "transpose": 1}[start]), self.ctx.h)
+
+
+def _precond_stats(self) -> dict:
+    nf, it, mr, xr = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+    _check(lib().fr_precond_stats(self.h, C.byref(nf), C.byref(it), C.byref(mr), C.byref(xr)), self.ctx.h)
+    return {"n_fallback": nf.value, "mean_refine_iters": it.value, "mean_resid": mr.value, "max_resid": xr.value}
 
 
 def _precond_mlp_inputs(self, U, shift: float, scale: float, X=None, s=None):
@@ -430,6 +445,8 @@ def _precond_n_fallback(self) -> int:
 
 
 Precond.set_mlp = _precond_set_mlp
+Precond.set_refine = _precond_set_refine
+Precond.stats = _precond_stats
 Precond.mlp_inputs = _precond_mlp_inputs
 Precond.n_fallback = property(_precond_n_fallback)
 

@@ -144,3 +144,57 @@ def test_trained_network_preconditions_newton_gmres():
     pc.set_mlp(net, 0.0)
     c = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=500)
     assert pc.n_fallback == m.n_elem and c["converged"] == 1
+    # Newton-Schulz refinement: from the network's output it needs fewer steps
+    # than from the scaled transpose (the same method without the network),
+    # and the refined preconditioner does as well as FP64 block-Jacobi LU
+    pc.set_mlp(net, 0.05)
+    steps = {}
+    for start in ("network", "transpose"):
+        pc.set_refine(64, 1e-2, start)
+        pc.setup(Ud, 1.0, -dt)
+        st = pc.stats()
+        print("refine", start, st, flush=True)
+        assert st["n_fallback"] <= (0 if start == "transpose" else 0.1 * m.n_elem), st
+        steps[start] = st["mean_refine_iters"]
+    assert steps["network"] < steps["transpose"], steps
+    pc.set_refine(16, 1e-2, "network")
+    d = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=500)
+    e = sol.newton_step(Ud, pc=fr.Precond(ctx), dt=dt, gmres_maxit=500)
+    assert d["converged"] == 1 and d["res"] <= 1e-8 * d["res0"]
+    assert d["gmres_iters"] <= 1.25 * e["gmres_iters"] + 2, (d["gmres_iters"], e["gmres_iters"])
+
+
+@pytest.mark.parametrize("start,p", [("transpose", 3), ("transpose", 2), ("network", 3)])
+def test_refined_inverse_residual_bounds_the_solve(start, p):
+    """A z - r = -(I - A^ M) r exactly for z = M r / s, so the reported
+    residual bounds the preconditioner's error against the oracle's blocks;
+    from an untrained network the refinement diverges and the safeguard
+    hands those elements to FP64 LU, which must then agree with the
+    oracle's LU solve."""
+    from paper_2105_08632_amd import fr
+    fr_, m, ph, U, ctx = _ctx(N=5, p=p)
+    dt = _dt(m, U, 5.0)
+    Ud = torch.from_numpy(U).cuda()
+    pc = fr.Precond(ctx, fr.FR_PC_MLP)
+    net = fr.Mlp(ctx.b, 256, seed=5, max_batch=64) if start == "network" else None
+    pc.set_mlp(net, 1e-3)
+    pc.set_refine(40, 2e-4, start)
+    print("refine case", start, p, flush=True)
+    pc.setup(Ud, 1.0, -dt)
+    st = pc.stats()
+    r = I.random_direction(U.shape, 4)
+    z = pc.apply(torch.from_numpy(r).cuda()).cpu().numpy().reshape(m.n_elem, -1)
+    r = r.reshape(m.n_elem, -1)
+    o = O.Oracle(m, ph, p)
+    b = ctx.b
+    if start == "transpose":
+        assert st["n_fallback"] == 0 and st["max_resid"] <= 1e-3, st
+        assert st["mean_refine_iters"] >= 1
+    for n in (0, 7, m.n_elem - 1):
+        A = np.eye(b) - dt * o.jac_block(U, n, n, b, b)
+        if start == "transpose":
+            bound = 1.01 * st["max_resid"] * np.linalg.norm(r[n]) + 1e-12 * np.linalg.norm(r[n])
+            assert np.linalg.norm(A @ z[n] - r[n]) <= bound
+        else:
+            zr = O.lu_solve(A, r[n])
+            assert np.max(np.abs(z[n] - zr)) <= 1e-10 * np.max(np.abs(zr))

@@ -30,21 +30,27 @@ def _dt(m, U, cfl):
     return cfl * (1.0 / round(np.sqrt(m.n_elem))) / smax
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 2e-5)])
-def test_block_jacobi_inverse_matches_lu_solve(prec, tol):
-    fr, m, ph, U, ctx, Ud = _setup(prec=prec)
+@pytest.mark.parametrize("prec,tol,p,shift", [("f64", 1e-11, 2, 1.0), ("f32", 2e-5, 2, 1.0), ("f64", 1e-11, 3, 1.0),
+                                              ("f64", 1e-11, 1, 1.0), ("f64", 1e-10, 2, 0.0),
+                                              ("f64", 1e-10, 4, 1.0)])
+def test_block_jacobi_inverse_matches_lu_solve(prec, tol, p, shift):
+    """b = 36, 64, 16 (register Gauss-Jordan, padded to 64 rows), b = 100
+    (LDS Gauss-Jordan); shift 0 inverts the Jacobian block itself, which
+    needs row exchanges."""
+    fr, m, ph, U, ctx, Ud = _setup(prec=prec, p=p)
     dt = _dt(m, U, 100.0)
     pc = fr.Precond(ctx)
-    pc.setup(Ud, 1.0, -dt)
+    print("block inverse case", prec, p, shift, flush=True)
+    pc.setup(Ud, shift, -dt)
     r = I.random_direction(U.shape, 4)
     rd = torch.from_numpy(r).to(Ud.dtype).cuda()
     z = pc.apply(rd).double().cpu().numpy().reshape(m.n_elem, -1)
-    o = O.Oracle(m, ph, 2)
+    o = O.Oracle(m, ph, p)
     Uq = Ud.double().cpu().numpy()
     b = ctx.b
     rq = rd.double().cpu().numpy().reshape(m.n_elem, -1)
     for n in (0, 11, m.n_elem - 1):
-        A = np.eye(b) - dt * o.jac_block(Uq, n, n, b, b)
+        A = shift * np.eye(b) - dt * o.jac_block(Uq, n, n, b, b)
         zr = O.lu_solve(A, rq[n])
         assert np.max(np.abs(z[n] - zr)) <= tol * np.max(np.abs(zr))
         # residual of the GPU solution against the oracle's block
