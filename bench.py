@@ -249,6 +249,46 @@ def newton_bench(torch, fr, I, train_steps, log):
     return out
 
 
+def fourier_bench(torch, fr, I, log):
+    """Von Neumann analysis on the GPU from the library's own Jacobian blocks:
+    FR-DG linear advection (theta0 = pi/6, theta1 = pi/4), eigenvalues of the
+    Fourier symbol along the ray kappa h in (0, 4 pi] and the RK3 / RK4 / RK54
+    CFL limits, against the paper's printed values."""
+    rk = {"rk3": [1.0, 1.0, 1 / 2, 1 / 6], "rk4": [1.0, 1.0, 1 / 2, 1 / 6, 1 / 24],
+          "rk54": [1.0, 1.0, 1 / 2, 1 / 6, 1 / 24, 1 / 200]}
+    printed = {"quad": {"rk3": 0.096, "rk4": 0.106, "rk54": 0.162}, "hex": {"rk3": 0.075, "rk4": 0.084, "rk54": 0.127}}
+    out = {}
+    t0, t1 = np.pi / 6, np.pi / 4
+    for name, nk in (("quad", 1500), ("hex", 400)):
+        p = 3
+        if name == "quad":
+            c = np.array([np.cos(t0), np.sin(t0)])
+            m, prec = I.quad_mesh(4, degree=p), "f64"
+        else:
+            c = np.array([np.cos(t0) * np.cos(t1), np.sin(t0), np.cos(t0) * np.sin(t1)])
+            m, prec = I.hex_mesh(3, degree=p), "f32"
+        ctx = fr.Context(m, I.advection_physics(c), prec)
+        U = torch.zeros(ctx.ndof, dtype=torch.float64 if prec == "f64" else torch.float32, device="cuda")
+        h = 1.0 / round(m.n_elem ** (1 / m.ndim))
+        kap = torch.from_numpy((np.linspace(1e-3, 4 * np.pi, nk) / h)[:, None] * c[None, :]).cuda()
+        tol = 1e-12 if prec == "f64" else 1e-6
+
+        def run():
+            B = ctx.jacobian_blocks(U)
+            E = ctx.fourier_eigs(B, 0, kap, scale=h)
+            return {s: ctx.cfl_max(E, rk[s], tau_max=2.0, tol=tol) for s in rk}
+
+        run()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        got = run()
+        ms = (time.perf_counter() - ts) * 1e3
+        out[name + "_p3"] = {"wavenumbers": nk, "block": ctx.b, "blocks_precision": prec, "ms": round(ms, 2),
+                             "cfl": {s: round(v, 4) for s, v in got.items()}, "printed": printed[name]}
+        log(f"fourier {name} p3: {ms:.1f} ms {got}")
+    return out
+
+
 def batch_bench(torch, fr, I, reps, log):
     """64 independent periodic 2-D Euler meshes (FP32; triangles and quads,
     degrees 1-4, 500-5000 elements each): residual + all Jacobian blocks,
@@ -566,6 +606,7 @@ def main():
     if not args.no_batch:
         out["batch"] = batch_bench(torch, fr, I, 5, log)
         torch.cuda.empty_cache()
+    out["fourier"] = fourier_bench(torch, fr, I, log)
     if not args.no_newton:
         out["newton"] = newton_bench(torch, fr, I, args.mlp_steps, log)
     if not args.no_cpu_baseline:

@@ -157,6 +157,37 @@ fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precis
  * Jv and R_out are in the context precision. */
 fr_status fr_jvp(fr_ctx* ctx, const void* U, const void* v, void* Jv, void* R_out);
 
+/* ---- Fourier (von Neumann) analysis --------------------------------------
+ * Linear stability of the semi-discretisation on a uniform periodic mesh
+ * (section 3, temporal linear stability: eq. "semi_discrete_pattern" and the
+ * Runge-Kutta amplification polynomials of eq. "rk_exponential").  There the
+ * Jacobian is block-circulant and a Bloch wave of wavenumber kappa sees
+ * G(kappa) = scale * sum_k B_k exp(i kappa . d_k) over the face stencil of
+ * one element, B_k its blocks as fr_jacobian_blocks returns them and d_k the
+ * offset of block k's element (twice the face-centroid offset: exact on a
+ * uniform mesh of parallelograms or parallelepipeds). */
+
+/* Eigenvalues of G(kappa) for nk wavenumbers.  blocks: device, the context's
+ * block array (context precision, layout of fr_jacobian_blocks; only element
+ * elem's blocks are read); kappa: device [nk][ndim]; eigs: device
+ * [nk][b] complex values as (re, im) pairs (order unspecified).  scale
+ * multiplies G (e.g. h / |c| for the CFL number of the paper).  b <= 64,
+ * quadrilaterals and hexahedra (FR_E_UNSUPPORTED otherwise).  Eigenvalues
+ * come from Householder reduction to Hessenberg form and the shifted QR
+ * algorithm in FP64, one wavefront per wavenumber; a wavenumber whose QR
+ * iteration does not converge gets NaN eigenvalues.  Asynchronous. */
+fr_status fr_fourier_eigs(fr_ctx* ctx, const void* blocks, int64_t elem, const double* kappa, int64_t nk, double scale,
+                          double* eigs);
+/* The largest tau in [0, tau_max] with |P(tau lambda)| <= 1 + tol for all n
+ * eigenvalues (device complex pairs), P(z) = sum_j coef[j] z^j (coef: host,
+ * degree 1..8), by bisection: the CFL limit of an explicit Runge-Kutta scheme
+ * whose amplification polynomial is P.  tol absorbs the rounding of the
+ * blocks (eigenvalues of an exact, stable semi-discretisation have Re <= 0;
+ * FP32 blocks move them by about 1e-7 |lambda|).  cfl: device double (NaN if
+ * an eigenvalue is not finite).  Asynchronous. */
+fr_status fr_cfl_max(fr_ctx* ctx, const double* eigs, int64_t n, const double* coef, int degree, double tau_max,
+                     double tol, double* cfl);
+
 /* ---- Implicit steps (backward Euler) -------------------------------------
  * The paper integrates explicitly; these calls use the same residual and
  * Jacobian for an implicit step U - U^n - dt R(U) = 0. */

@@ -211,6 +211,22 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   c->nd = m->ndim; c->type = type; c->p = m->degree; c->system = ph->system; c->nv = nv; c->prec = prec;
   c->ne = m->n_elem; c->ns = ref.ns; c->nf = ref.nf; c->nface = ref.nface; c->nfp = ref.nfp; c->b = ref.ns * nv;
   c->visc = visc;
+  // face-centroid offsets (vertex averages), used by the Fourier analysis
+  c->face_off.assign((size_t)c->ne * ref.nface * m->ndim, 0.0);
+  for (int64_t e = 0; e < c->ne; ++e) {
+    const double* X = m->elem_xyz + (size_t)e * m->max_vert * m->ndim;
+    for (int d = 0; d < m->ndim; ++d) {
+      double ctr = 0.0;
+      for (int v = 0; v < ref.nvert; ++v) ctr += X[v * m->ndim + d];
+      ctr /= ref.nvert;
+      for (int f = 0; f < ref.nface; ++f) {
+        double fc = 0.0;
+        for (int v : ref.face_verts[f]) fc += X[v * m->ndim + d];
+        fc /= (double)ref.face_verts[f].size();
+        c->face_off[((size_t)e * ref.nface + f) * m->ndim + d] = fc - ctr;
+      }
+    }
+  }
   for (int i = 0; i < 3; ++i) c->ph.c[i] = ph->adv_vel[i];
   c->ph.gamma = ph->gamma; c->ph.mu = ph->mu; c->ph.prandtl = ph->prandtl;
   c->ph.beta = ph->ldg_beta; c->ph.eta = ph->ldg_penalty;

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "fr_jac_tp.hpp"
 
@@ -34,6 +35,7 @@ struct fr_ctx_s {
   void* geo_mem = nullptr;
   void* work_mem = nullptr;
   int* status = nullptr;       // device [2]: kinds of non-finite outputs (FR_NF_*), smallest element
+  std::vector<double> face_off;  // host [ne][nface][nd]: face centroid - element centroid
   int dev = 0;                 // device the context was created on
   OpsD<float> opsf{}; OpsD<double> opsd{};
   Ops1D<float> o1f{}; Ops1D<double> o1d{};

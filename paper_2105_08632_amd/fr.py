@@ -199,6 +199,46 @@ class Context:
         return ms.value, n.value
 
 
+# ---------------------------------------------------------------- Fourier analysis
+def _fourier_symbols(L):
+    P = C.c_void_p
+    L.fr_fourier_eigs.argtypes = [P, P, C.c_int64, P, C.c_int64, C.c_double, P]
+    L.fr_cfl_max.argtypes = [P, P, C.c_int64, P, C.c_int, C.c_double, C.c_double, P]
+    L.fr_fourier_eigs.restype = C.c_int
+    L.fr_cfl_max.restype = C.c_int
+
+
+_extensions.append(_fourier_symbols)
+EXPORTED += ["fr_fourier_eigs", "fr_cfl_max"]
+
+
+def _fourier_eigs(self, blocks, elem: int, kappa, scale: float = 1.0, out=None):
+    """Eigenvalues of G(kappa) = scale sum_k B_k exp(i kappa . d_k) for each
+    row of kappa ([nk, ndim] float64 CUDA tensor): complex tensor [nk, b]."""
+    import torch
+    kappa = kappa.to(torch.float64).contiguous()
+    assert kappa.is_cuda and kappa.dim() == 2 and kappa.shape[1] == self.info.ndim
+    nk = kappa.shape[0]
+    out = torch.empty(nk, self.b, 2, dtype=torch.float64, device="cuda") if out is None else out
+    _check(lib().fr_fourier_eigs(self.h, _ptr(blocks), elem, _ptr(kappa), nk, scale, _ptr(out)), self.h)
+    return out
+
+
+def _cfl_max(self, eigs, coef, tau_max: float = 4.0, tol: float = 1e-12) -> float:
+    """Largest tau with |P(tau lambda)| <= 1 + tol for all eigenvalues (eigs:
+    [.., 2] float64 CUDA tensor of (re, im) pairs), P(z) = sum_j coef[j] z^j."""
+    import torch
+    eigs = eigs.contiguous()
+    c = np.ascontiguousarray(np.asarray(coef, dtype=np.float64))
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    _check(lib().fr_cfl_max(self.h, _ptr(eigs), eigs.numel() // 2, c.ctypes.data, len(c) - 1, tau_max, tol,
+                            _ptr(out)), self.h)
+    return float(out.item())
+
+
+Context.fourier_eigs = _fourier_eigs
+Context.cfl_max = _cfl_max
+
 # ---------------------------------------------------------------- implicit step
 FR_PC_BLOCK_JACOBI, FR_PC_MLP = 0, 1
 
