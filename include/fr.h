@@ -188,6 +188,18 @@ fr_status fr_fourier_eigs(fr_ctx* ctx, const void* blocks, int64_t elem, const d
 fr_status fr_cfl_max(fr_ctx* ctx, const double* eigs, int64_t n, const double* coef, int degree, double tau_max,
                      double tol, double* cfl);
 
+/* ---- Explicit time integration ------------------------------------------
+ * nsteps steps of dU/dt = R(U) with time step dt by the five-stage,
+ * fourth-order, two-register Runge-Kutta scheme of Carpenter and Kennedy
+ * (the RK54 of the paper's linear advection-diffusion experiments; its
+ * amplification polynomial is the RK54 polynomial of eq. "rk_exponential").
+ * U: device state (context precision), advanced in place.  work: device
+ * array of 2 n_dof values in the context precision (the residual and the
+ * second register; its contents need no initialisation), not overlapping U.
+ * Each stage is one residual evaluation (FP64 arithmetic) and one update
+ * kernel; asynchronous on the context stream, allocates nothing. */
+fr_status fr_rk54(fr_ctx* ctx, void* U, void* work, double dt, int64_t nsteps);
+
 /* ---- Implicit steps (backward Euler) -------------------------------------
  * The paper integrates explicitly; these calls use the same residual and
  * Jacobian for an implicit step U - U^n - dt R(U) = 0. */

@@ -236,6 +236,26 @@ def _cfl_max(self, eigs, coef, tau_max: float = 4.0, tol: float = 1e-12) -> floa
     return float(out.item())
 
 
+def _rk54_symbols(L):
+    L.fr_rk54.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
+    L.fr_rk54.restype = C.c_int
+
+
+_extensions.append(_rk54_symbols)
+EXPORTED += ["fr_rk54"]
+
+
+def _rk54(self, U, dt: float, nsteps: int, work=None):
+    """Advances U in place by nsteps RK54 steps; work: 2 n_dof scratch values."""
+    import torch
+    U = self._vec(U)
+    work = torch.empty(2 * self.ndof, dtype=self.dtype, device="cuda") if work is None else work
+    assert work.dtype == self.dtype and work.numel() >= 2 * self.ndof and work.is_contiguous()
+    _check(lib().fr_rk54(self.h, _ptr(U), _ptr(work), dt, nsteps), self.h)
+    return U
+
+
+Context.rk54 = _rk54
 Context.fourier_eigs = _fourier_eigs
 Context.cfl_max = _cfl_max
 
