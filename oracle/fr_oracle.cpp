@@ -32,6 +32,17 @@
 // non-analytic operations (|.|, max, sign) branch on the real part, which is
 // the derivative of the active branch (ties go to the left state).
 //
+// Schemes (tensor elements): FR-DG (the Radau corrections above), FR-SDRT
+// (FR whose correction functions are the Raviart-Thomas flux basis functions
+// of the external flux points: along the normal line, the Lagrange
+// polynomial of degree p+1 on the SD flux points {-1, zeros of P_p, +1} that
+// is 1 at the face; section "Connections between the SDRT and FR formalisms")
+// and SDRT itself (section "SDRT method"): u and the gradient interpolated to
+// the internal flux points, the transformed normal flux evaluated there, the
+// common flux at the external ones, and the divergence of the flux nodal
+// basis at the solution points (eq. "divergence_sdrt"); the gradient from
+// the internal values and the common solution with the same basis.
+//
 // Triangles: the solution point set is supplied by the caller (the paper's
 // Williams-Shunn tables are not reproduced in the text); the nodal basis is
 // built from the orthonormal Dubiner (PKD) modal basis through the
@@ -107,6 +118,23 @@ static double radau_right_d(int p, double t) {
   return 0.5 * (dP1 + dP0);
 }
 
+// SD flux points on a line: -1, the p zeros of P_p, +1 (ascending).
+static std::vector<double> sd_points(int p) {
+  std::vector<double> z, w;
+  gauss_legendre(p, z, w);
+  std::vector<double> out;
+  out.push_back(-1.0);
+  for (double v : z) out.push_back(v);
+  out.push_back(1.0);
+  return out;
+}
+// Derivative of the right SD correction: the Lagrange polynomial on the SD
+// flux points that is 1 at +1.
+static double sd_right_d(int p, double t) {
+  std::vector<double> z = sd_points(p);
+  return lagrange_d(z, p + 1, t);
+}
+
 // ------------------------------------------------------ triangle basis (PKD)
 // Orthonormal Dubiner (PKD) basis on the reference triangle (v0=(-1,-1),
 // v1=(1,-1), v2=(-1,1)): psi_ij = c_ij ((1-s)/2)^i P_i(a) P_j^{(2i+1,0)}(s)
@@ -153,6 +181,13 @@ struct RefElem {
   std::vector<double> Cor;    // [ns][nf] div g_f at x_rho
   std::vector<double> wq;     // [ns] quadrature weights at solution points (mass lumping for conservation checks)
   std::vector<std::vector<int>> face_verts;
+  int scheme = 0;             // 0 FR-DG, 1 FR-SDRT, 2 SDRT
+  // SDRT internal flux points (tensor elements)
+  int nint = 0;
+  std::vector<double> ip;     // [nint][nd] reference position
+  std::vector<int> idir;      // [nint] axis d of the degree of freedom (normal e_d)
+  std::vector<double> Mint;   // [nint][ns] solution basis at the point
+  std::vector<double> Dint;   // [ns][nint] divergence of the point's flux basis function at x_rho
 };
 
 static void shape_fn(int type, const double* xi, double* N, double* dN /*[nvert][nd]*/) {
@@ -201,8 +236,8 @@ static bool invert(std::vector<double> A, int n, std::vector<double>& inv) {
   return true;
 }
 
-static void build_tensor(RefElem& R, int type, int p) {
-  R.type = type; R.p = p;
+static void build_tensor(RefElem& R, int type, int p, int scheme) {
+  R.type = type; R.p = p; R.scheme = scheme;
   R.nd = (type == QUAD) ? 2 : 3;
   const int n1 = p + 1, nd = R.nd;
   std::vector<double> x, w; gauss_legendre(n1, x, w);
@@ -275,7 +310,9 @@ static void build_tensor(RefElem& R, int type, int p) {
     int f = R.fface[g], ax = faces[f].first, sg = faces[f].second;
     for (int r = 0; r < R.ns; ++r) {
       double t = R.sp[r * nd + ax];
-      double dg = (sg > 0) ? radau_right_d(p, t) : radau_right_d(p, -t);  // s * d/dt g_L(t) = (-1)(-g_R'(-t))
+      // s * d/dt g_L(t) = (-1)(-g_R'(-t)) for g_L(t) = g_R(-t)
+      double dg = (scheme == 0) ? ((sg > 0) ? radau_right_d(p, t) : radau_right_d(p, -t))
+                                : ((sg > 0) ? sd_right_d(p, t) : sd_right_d(p, -t));
       double tv = 1.0;
       int ir[3] = {r % n1, (r / n1) % n1, r / (n1 * n1)};
       for (int d = 0; d < nd; ++d)
@@ -283,6 +320,40 @@ static void build_tensor(RefElem& R, int type, int p) {
       R.Cor[r * R.nf + g] = dg * tv;
     }
   }
+  if (scheme != 2) return;
+  // SDRT internal flux points: on each line along axis d, the p interior SD
+  // points z_1..z_p of that axis at the solution-point positions of the
+  // other axes; degree of freedom e_d, flux basis function
+  // e_d psi_j(xi_d) prod_{e != d} l_{i_e}(xi_e) with psi_j the Lagrange
+  // polynomial on the SD points.
+  std::vector<double> z = sd_points(p);
+  const int nl = R.ns / n1;                        // lines per axis
+  R.nint = nd * nl * p;
+  R.ip.assign(R.nint * nd, 0.0); R.idir.assign(R.nint, 0);
+  R.Mint.assign(R.nint * R.ns, 0.0); R.Dint.assign(R.ns * R.nint, 0.0);
+  int k = 0;
+  for (int d = 0; d < nd; ++d)
+    for (int l = 0; l < nl; ++l)
+      for (int j = 1; j <= p; ++j, ++k) {
+        // tangential solution-point indices of line l (the other axes in order)
+        int tan[3] = {0, 0, 0}, rem = l;
+        for (int e = 0; e < nd; ++e)
+          if (e != d) { tan[e] = rem % n1; rem /= n1; }
+        R.idir[k] = d;
+        for (int e = 0; e < nd; ++e) R.ip[k * nd + e] = (e == d) ? z[j] : x[tan[e]];
+        for (int s2 = 0; s2 < R.ns; ++s2) {
+          int is[3] = {s2 % n1, (s2 / n1) % n1, s2 / (n1 * n1)};
+          double v = 1.0;
+          for (int e = 0; e < nd; ++e) v *= lagrange(x, is[e], R.ip[k * nd + e]);
+          R.Mint[k * R.ns + s2] = v;
+        }
+        for (int r = 0; r < R.ns; ++r) {
+          double v = lagrange_d(z, j, R.sp[r * nd + d]);
+          for (int e = 0; e < nd; ++e)
+            if (e != d) v *= lagrange(x, tan[e], R.sp[r * nd + e]);
+          R.Dint[r * R.nint + k] = v;
+        }
+      }
 }
 
 static void build_tri(RefElem& R, int p, const double* pts /*[ns][2]*/) {
@@ -386,6 +457,8 @@ struct Oracle {
   std::vector<double> detJ, Smat, Jinv;   // at solution points: [ns], [ns][nd][nd], [ns][nd][nd]
   std::vector<double> nrm, magN, fxyz;    // at flux points: [nf][nd], [nf], [nf][nd]
   std::vector<int> pair;                  // [elem][nf] neighbour flux point index
+  std::vector<int64_t> goff_i;            // SDRT: first internal flux point of each element
+  std::vector<double> Sint;               // SDRT: detJ J^{-1} at internal flux points [nint][nd][nd]
   int64_t ndof = 0;
   const RefElem& R(int64_t e) const { return ref[etype[e]]; }
 };
@@ -562,6 +635,25 @@ template <class T> static void elem_grad(const Oracle& O, const State<T>& S, int
       C[g * nv + a] = (0.5 - O.ph.beta) * uf[g * nv + a] + (0.5 + O.ph.beta) * uR;
     }
   }
+  if (R.scheme == 2) {
+    // SDRT: q~(x_rho) = sum_int u_int n_int div psi_int(x_rho) + sum_ext C n_ext div psi_ext(x_rho)
+    std::vector<T> ui(R.nint * nv);
+    for (int k = 0; k < R.nint; ++k)
+      for (int a = 0; a < nv; ++a) {
+        T v = T(0.0);
+        for (int s = 0; s < ns; ++s) v += R.Mint[k * ns + s] * u[s * nv + a];
+        ui[k * nv + a] = v;
+      }
+    for (int r = 0; r < ns; ++r)
+      for (int d = 0; d < nd; ++d)
+        for (int a = 0; a < nv; ++a) {
+          T v = T(0.0);
+          for (int k = 0; k < R.nint; ++k)
+            if (R.idir[k] == d) v += R.Dint[r * R.nint + k] * ui[k * nv + a];
+          for (int g = 0; g < nf; ++g) v += R.Cor[r * nf + g] * R.nref[g * nd + d] * C[g * nv + a];
+          qt[(r * nd + d) * nv + a] = v;
+        }
+  } else {
   for (int r = 0; r < ns; ++r)
     for (int d = 0; d < nd; ++d)
       for (int a = 0; a < nv; ++a) {
@@ -571,6 +663,7 @@ template <class T> static void elem_grad(const Oracle& O, const State<T>& S, int
           v += R.Cor[r * nf + g] * R.nref[g * nd + d] * (C[g * nv + a] - uf[g * nv + a]);
         qt[(r * nd + d) * nv + a] = v;
       }
+  }
   const double* Ji = &O.Jinv[O.goff_s[e] * nd * nd];
   for (int r = 0; r < ns; ++r)
     for (int d2 = 0; d2 < nd; ++d2)
@@ -603,6 +696,34 @@ static void elem_residual(const Oracle& O, const State<T>& S, int64_t n, const T
         Ft[(s * nd + d) * nv + a] = v;
       }
   }
+  if (R.scheme == 2) {
+    // SDRT volume part: transformed normal flux at the internal flux points,
+    // F~n = (detJ J^{-1} f(u_int, q_int)) . e_d, times div psi_int
+    for (int r = 0; r < ns * nv; ++r) div[r] = T(0.0);
+    for (int k = 0; k < R.nint; ++k) {
+      T ui[5], qi[3 * 5], f[3 * 5];
+      for (int a = 0; a < nv; ++a) {
+        T v = T(0.0);
+        for (int s = 0; s < ns; ++s) v += R.Mint[k * ns + s] * u[s * nv + a];
+        ui[a] = v;
+      }
+      if (visc)
+        for (int d = 0; d < nd; ++d)
+          for (int a = 0; a < nv; ++a) {
+            T v = T(0.0);
+            for (int s = 0; s < ns; ++s) v += R.Mint[k * ns + s] * qn[(s * nd + d) * nv + a];
+            qi[d * nv + a] = v;
+          }
+      flux_phys<T>(O.ph, nd, ui, visc ? qi : nullptr, f);
+      const double* Si = &O.Sint[(O.goff_i[n] + k) * nd * nd];
+      const int d = R.idir[k];
+      for (int a = 0; a < nv; ++a) {
+        T fn = T(0.0);
+        for (int kk = 0; kk < nd; ++kk) fn += Si[d * nd + kk] * f[kk * nv + a];
+        for (int r = 0; r < ns; ++r) div[r * nv + a] += R.Dint[r * R.nint + k] * fn;
+      }
+    }
+  } else {
   // volume part: sum_d D_d F~_d
   for (int r = 0; r < ns; ++r)
     for (int a = 0; a < nv; ++a) {
@@ -611,6 +732,7 @@ static void elem_residual(const Oracle& O, const State<T>& S, int64_t n, const T
         for (int s = 0; s < ns; ++s) v += R.Dm[(d * ns + r) * ns + s] * Ft[(s * nd + d) * nv + a];
       div[r * nv + a] = v;
     }
+  }
   // flux points: interpolated discontinuous normal flux and common flux
   for (int g = 0; g < nf; ++g) {
     int f = R.fface[g];
@@ -644,7 +766,9 @@ static void elem_residual(const Oracle& O, const State<T>& S, int64_t n, const T
     common_flux<T>(O.ph, nd, uL, uR, qL, qR, nn, Fc);
     double mg = O.magN[O.goff_f[n] + g];
     for (int a = 0; a < nv; ++a) {
-      T jump = mg * Fc[a] - Fn[a];
+      // SDRT: the common flux times the external basis divergence; FR: the
+      // correction of the interpolated normal flux to the common flux
+      T jump = (R.scheme == 2) ? mg * Fc[a] : mg * Fc[a] - Fn[a];
       for (int r = 0; r < ns; ++r) div[r * nv + a] += R.Cor[r * nf + g] * jump;
     }
   }
@@ -740,6 +864,19 @@ static int setup(Oracle& O, std::vector<std::string>& err) {
       for (int i = 0; i < nd; ++i) { O.nrm[k * nd + i] = N[i] / mg; O.fxyz[k * nd + i] = x[i]; }
     }
   }
+  // SDRT: metric terms at the internal flux points
+  O.goff_i.assign(O.ne + 1, 0);
+  for (int64_t e = 0; e < O.ne; ++e) O.goff_i[e + 1] = O.goff_i[e] + O.R(e).nint;
+  O.Sint.assign(O.goff_i[O.ne] * nd * nd, 0.0);
+  for (int64_t e = 0; e < O.ne; ++e) {
+    const RefElem& R = O.R(e);
+    double x[3], J[9], S[9];
+    for (int k = 0; k < R.nint; ++k) {
+      map_eval(O, e, &R.ip[k * nd], x, J);
+      adjugate(nd, J, S);
+      for (int i = 0; i < nd * nd; ++i) O.Sint[(O.goff_i[e] + k) * nd * nd + i] = S[i];
+    }
+  }
   // Pair flux points across faces by physical position relative to the
   // face centroid (translation invariant, so periodic wraps pair too).
   for (int64_t e = 0; e < O.ne; ++e) {
@@ -785,7 +922,7 @@ extern "C" {
 int oracle_create(int nd, int64_t ne, const int8_t* etype, int p, const double* xyz, int maxv,
                   const int64_t* nbr, const int8_t* nbrf, int maxf, int system, int nv,
                   const double* c, double gamma, double mu, double prandtl, double beta, double eta,
-                  const double* tri_pts, void** out) {
+                  int scheme, const double* tri_pts, void** out) {
   // BR1 only: beta = 0 and no penalty (the von Neumann analysis with
   // diffusion identifies BR1 with beta = 0).  A single scalar beta taken
   // from each element's own side would make the common solution and the
@@ -802,8 +939,9 @@ int oracle_create(int nd, int64_t ne, const int8_t* etype, int p, const double* 
   O->nbrf.assign(nbrf, nbrf + ne * maxf);
   bool has[3] = {false, false, false};
   for (int64_t e = 0; e < ne; ++e) has[etype[e]] = true;
-  if (has[QUAD]) build_tensor(O->ref[QUAD], QUAD, p);
-  if (has[HEX]) build_tensor(O->ref[HEX], HEX, p);
+  if (scheme < 0 || scheme > 2 || (scheme != 0 && has[TRI])) { delete O; return -12; }
+  if (has[QUAD]) build_tensor(O->ref[QUAD], QUAD, p, scheme);
+  if (has[HEX]) build_tensor(O->ref[HEX], HEX, p, scheme);
   if (has[TRI]) {
     if (!tri_pts) { delete O; return -10; }
     build_tri(O->ref[TRI], p, tri_pts);

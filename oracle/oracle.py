@@ -39,7 +39,7 @@ def lib():
             d = C.c_double
             i64 = C.c_int64
             L.oracle_create.argtypes = [C.c_int, i64, P, C.c_int, P, C.c_int, P, P, C.c_int,
-                                        C.c_int, C.c_int, P, d, d, d, d, d, P, C.POINTER(C.c_void_p)]
+                                        C.c_int, C.c_int, P, d, d, d, d, d, C.c_int, P, C.POINTER(C.c_void_p)]
             L.oracle_create.restype = C.c_int
             L.oracle_destroy.argtypes = [P]
             L.oracle_ndof.argtypes = [P]
@@ -83,7 +83,8 @@ class Oracle:
         h = C.c_void_p()
         rc = L.oracle_create(mesh.ndim, mesh.n_elem, _p(et), p, _p(xyz), mesh.max_vert, _p(nbr), _p(nbf),
                              mesh.max_face, phys.system, phys.nvars, _p(c), phys.gamma, phys.mu,
-                             phys.prandtl, phys.beta, phys.eta, None if tp is None else _p(tp), C.byref(h))
+                             phys.prandtl, phys.beta, phys.eta, int(getattr(phys, "scheme", 0)),
+                             None if tp is None else _p(tp), C.byref(h))
         if rc != 0:
             raise RuntimeError(f"oracle_create failed ({rc})")
         self.h = h

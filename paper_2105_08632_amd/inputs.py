@@ -351,7 +351,8 @@ ADVECTION, EULER, NAVIER_STOKES = 0, 1, 2
 class Physics:
     """Field variables and flux parameters (paper section 2 and the test
     cases of section 5).  mu is the dynamic viscosity; beta and eta are the
-    LDG parameters (beta = eta = 0 is the BR1 scheme)."""
+    LDG parameters (beta = eta = 0 is the BR1 scheme); scheme selects the
+    spatial discretisation."""
     system: int
     nvars: int
     adv_vel: tuple = (0.0, 0.0, 0.0)
@@ -360,6 +361,7 @@ class Physics:
     prandtl: float = 0.72
     beta: float = 0.0
     eta: float = 0.0
+    scheme: int = 0        # 0 FR-DG, 1 FR-SDRT, 2 SDRT (tensor elements)
 
 
 def advection_physics(vel=(1.0, 0.5), mu: float = 0.0) -> Physics:

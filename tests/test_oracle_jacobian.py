@@ -35,7 +35,7 @@ def _amp(z, scheme):
     return poly + z ** 5 / 200
 
 
-def cfl_max(etype, p, theta0, theta1, nk):
+def cfl_max(etype, p, theta0, theta1, nk, scheme=0):
     """CFL_MAX along the ray kappa = k c_hat, k h in (0, 4 pi]."""
     if etype == I.QUAD:
         c = (np.cos(theta0), np.sin(theta0))
@@ -45,7 +45,8 @@ def cfl_max(etype, p, theta0, theta1, nk):
         m = I.hex_mesh(3, degree=p)
     N = round(m.n_elem ** (1 / m.ndim))
     h = 1.0 / N
-    o = O.Oracle(m, I.advection_physics(c), p)
+    import dataclasses
+    o = O.Oracle(m, dataclasses.replace(I.advection_physics(c), scheme=scheme), p)
     b = I.n_sol_points(etype, p)
     U = np.zeros(m.n_elem * b)
     ctr = m.xyz.mean(axis=1)
