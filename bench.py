@@ -252,35 +252,42 @@ def newton_bench(torch, fr, I, train_steps, log):
 def rk54_pm_bench(torch, fr, I, log, N=40, steps=4):
     """The paper's own performance metric on its own case: wall time per
     degree of freedom per Runge-Kutta stage, PM = T / (N_iter N_s N_V n_elem
-    N_RK), for the Taylor-Green vortex on N^3 hexahedra, FR-DG degree 3,
+    N_RK), for the Taylor-Green vortex on N^3 hexahedra, degree 3,
     Navier-Stokes, RK54 at a constant time step (one R(U) evaluation and one
-    stage update per stage).  FP64 state and arithmetic."""
+    stage update per stage), for FR-DG, FR-SDRT and SDRT.  FP64 state and
+    arithmetic."""
+    import dataclasses
     p = 3
     m = I.hex_mesh(N, degree=p)
-    ph = I.ns_physics(3, 1600.0, 0.71)
     U0 = I.tgv_state(m, p, L=1.0 / (2 * np.pi))
-    ctx = fr.Context(m, ph, "f64")
-    U = torch.from_numpy(U0).cuda().contiguous().view(-1)
-    work = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
     rho = U0[..., 0]
     v = U0[..., 1:4] / rho[..., None]
     pr = 0.4 * (U0[..., 4] - 0.5 * rho * np.sum(v * v, axis=-1))
     dt = 0.1 / N / float(np.max(np.linalg.norm(v, axis=-1) + np.sqrt(1.4 * pr / rho)))
-    ctx.rk54(U, dt, 1)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    ctx.rk54(U, dt, steps, work)
-    e1.record()
-    torch.cuda.synchronize()
-    ctx.sync()
-    ms = e0.elapsed_time(e1)
-    pm = ms * 1e6 / (steps * ctx.ndof * 5)
-    out = {"workload": f"Taylor-Green vortex, 3-D Navier-Stokes FR-DG p=3 on {N}^3 hexahedra, RK54, FP64",
-           "dof": ctx.ndof, "steps": steps, "ms_per_step": round(ms / steps, 3), "pm_ns_per_dof_stage": round(pm, 4),
-           "paper_pm_ns": 0.67, "paper_hardware": "one NVIDIA V100 (PyFR), precision not stated",
-           "finite": bool(torch.isfinite(U).all())}
-    log(f"rk54 pm: {pm:.4f} ns per DOF per stage ({ms / steps:.2f} ms per step)")
+    paper = {"fr_dg": 0.67, "fr_sdrt": 0.67, "sdrt": 0.85}
+    out = {"workload": f"Taylor-Green vortex, 3-D Navier-Stokes degree 3 on {N}^3 hexahedra, RK54, FP64",
+           "steps": steps, "paper_hardware": "one NVIDIA V100 (PyFR), precision not stated"}
+    for name, scheme in (("fr_dg", 0), ("fr_sdrt", 1), ("sdrt", 2)):
+        ph = dataclasses.replace(I.ns_physics(3, 1600.0, 0.71), scheme=scheme)
+        ctx = fr.Context(m, ph, "f64")
+        U = torch.from_numpy(U0).cuda().contiguous().view(-1)
+        work = torch.empty(2 * ctx.ndof, dtype=torch.float64, device="cuda")
+        ctx.rk54(U, dt, 1, work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.rk54(U, dt, steps, work)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms = e0.elapsed_time(e1)
+        pm = ms * 1e6 / (steps * ctx.ndof * 5)
+        out["dof"] = ctx.ndof
+        out[name] = {"ms_per_step": round(ms / steps, 3), "pm_ns_per_dof_stage": round(pm, 4),
+                     "paper_pm_ns": paper[name], "finite": bool(torch.isfinite(U).all())}
+        log(f"rk54 pm {name}: {pm:.4f} ns per DOF per stage ({ms / steps:.2f} ms per step)")
+        del ctx, U, work
+        torch.cuda.empty_cache()
     return out
 
 

@@ -62,6 +62,15 @@ typedef enum {
 typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2 } fr_elem_type;
 typedef enum { FR_ADVECTION = 0, FR_EULER = 1, FR_NAVIER_STOKES = 2 } fr_system;
 typedef enum { FR_F64 = 0, FR_F32 = 1, FR_BF16 = 2 } fr_precision;
+/* Spatial discretisation (quadrilaterals and hexahedra; triangles FR-DG only):
+ * FR-DG (correction functions that recover nodal DG), FR-SDRT (FR with the
+ * Raviart-Thomas flux basis of the external flux points as correction
+ * functions: on each line, the Lagrange polynomial of degree p+1 on the SD
+ * flux points {-1, Gauss-Legendre points of order p, +1}; section
+ * "Connections between the SDRT and FR formalisms") and SDRT (section "SDRT
+ * method": the flux evaluated at interior flux points, eq.
+ * "divergence_sdrt"). */
+typedef enum { FR_SCHEME_FR_DG = 0, FR_SCHEME_FR_SDRT = 1, FR_SCHEME_SDRT = 2 } fr_scheme;
 
 /* Mesh: the paper's tessellation of the domain into conforming elements
  * (section 2) with its face-neighbour stencil (section 3).  All elements of
@@ -91,6 +100,9 @@ typedef struct {
   double ldg_beta;            /* common-solution / viscous-flux weight (eq. "common_var_for_grad");
                                  must be 0 (BR1), else fr_ctx_create returns FR_E_UNSUPPORTED */
   double ldg_penalty;         /* LDG penalty eta; must be 0 (BR1), else FR_E_UNSUPPORTED */
+  int32_t scheme;             /* fr_scheme.  SDRT contexts provide fr_rhs, fr_jvp and the time steppers,
+                                 not Jacobian blocks, block preconditioners or fr_rhs_noalloc
+                                 (FR_E_UNSUPPORTED) */
 } fr_physics;
 
 typedef struct {

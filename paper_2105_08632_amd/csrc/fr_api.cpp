@@ -86,6 +86,7 @@ static void pack_ops(const frh::RefOps& ref, std::vector<char>& blob, std::vecto
   putR(ref.M0); putR(ref.D); putR(ref.Cor); putR(ref.nref); putI(ref.fface);
   putI(ref.m0c); putR(ref.m0v); putI(ref.dcc); putR(ref.dcv); putI(ref.gc); putR(ref.gv);
   putI(ref.crc); putR(ref.crv); putI(ref.ddc); putR(ref.ddv);
+  putR(ref.sdI); putR(ref.sdD); putI(ref.sdend);
 }
 
 template <class R> static OpsD<R> ops_view(char* base, const std::vector<size_t>& o) {
@@ -97,6 +98,7 @@ template <class R> static OpsD<R> ops_view(char* base, const std::vector<size_t>
   v.gc = (const int*)(base + o[9]); v.gv = (const R*)(base + o[10]);
   v.crc = (const int*)(base + o[11]); v.crv = (const R*)(base + o[12]);
   v.ddc = (const int*)(base + o[13]); v.ddv = (const R*)(base + o[14]);
+  v.sdI = (const R*)(base + o[15]); v.sdD = (const R*)(base + o[16]); v.sdend = (const int*)(base + o[17]);
   return v;
 }
 
@@ -117,6 +119,7 @@ static void pack_geo(const frh::Geometry& g, std::vector<char>& blob, std::vecto
   put(g.nbr.data(), g.nbr.size() * sizeof(int));
   put(g.nbface.data(), g.nbface.size() * sizeof(int));
   put(g.back.data(), g.back.size() * sizeof(int));
+  putR(g.Sint);
 }
 
 template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>& o, int ne) {
@@ -126,6 +129,7 @@ template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>
   v.nrm = (const R*)(base + o[3]); v.magN = (const R*)(base + o[4]);
   v.nbfp = (const int*)(base + o[5]); v.nbr = (const int*)(base + o[6]);
   v.nbface = (const int*)(base + o[7]); v.back = (const int*)(base + o[8]);
+  v.Sint = (const R*)(base + o[9]);
   return v;
 }
 
@@ -195,14 +199,21 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   if (ph->system == FR_NAVIER_STOKES && !(ph->prandtl > 0.0)) return fail(nullptr, FR_E_INVALID, "prandtl must be positive");
   if (ph->ldg_beta != 0.0 || ph->ldg_penalty != 0.0)
     return fail(nullptr, FR_E_UNSUPPORTED, "only the BR1 scheme is provided: ldg_beta and ldg_penalty must be 0");
+  if (ph->scheme < FR_SCHEME_FR_DG || ph->scheme > FR_SCHEME_SDRT)
+    return fail(nullptr, FR_E_INVALID, "unknown scheme");
+  if (ph->scheme != FR_SCHEME_FR_DG && type == FR_TRI)
+    return fail(nullptr, FR_E_UNSUPPORTED, "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra");
 
   frh::RefOps ref;
   std::string err;
-  if (!frh::build_ref(type, m->degree, ph->ldg_beta, m->tri_sol_pts, ref, err)) return fail(nullptr, FR_E_INVALID, err);
+  if (!frh::build_ref(type, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, ref, err))
+    return fail(nullptr, FR_E_INVALID, err);
   if (m->max_vert < ref.nvert || m->max_face < ref.nface) return fail(nullptr, FR_E_INVALID, "max_vert/max_face too small");
   frh::Geometry geo;
   if (!frh::build_geometry(ref, m->ndim, m->n_elem, m->elem_xyz, m->max_vert, m->nbr, m->nbr_face, m->max_face, geo, err))
     return fail(nullptr, FR_E_INVALID, err);
+  if (ph->scheme == FR_SCHEME_SDRT)
+    frh::build_sd_metric(ref, m->ndim, m->n_elem, m->elem_xyz, m->max_vert, geo.Sint);
   const bool visc = (ph->system == FR_NAVIER_STOKES) || (ph->system == FR_ADVECTION && ph->mu != 0.0);
   if (visc && !frh::check_stencil(m->n_elem, ref.nface, geo.nbr.data(), err)) return fail(nullptr, FR_E_UNSUPPORTED, err);
   if (m->n_elem * ref.nf > ((int64_t)1 << 31) - 1) return fail(nullptr, FR_E_UNSUPPORTED, "mesh too large for 32-bit face indices");
@@ -234,6 +245,20 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   if (!fr_find_kernels(type, m->degree, ph->system, prec, &c->ks)) {
     release(c);
     return fail(nullptr, FR_E_UNSUPPORTED, "no kernels for this element type / degree / system / precision");
+  }
+  c->scheme = ph->scheme;
+  if (c->scheme == FR_SCHEME_SDRT) {
+    // the SDRT residual and tangent replace the FR ones; no Jacobian blocks
+    if (!c->ks.rhs_sd || !c->ks.jvp_sd) {
+      release(c);
+      return fail(nullptr, FR_E_UNSUPPORTED, "no SDRT kernels for this element type");
+    }
+    c->ks.rhs = c->ks.rhs_sd;
+    c->ks.jvp = c->ks.jvp_sd;
+    c->ks.rhs_ws = nullptr;
+    c->ks.jac = nullptr;
+    c->ks.mf_bytes = nullptr;
+    c->ks.mf_setup = nullptr;
   }
   std::vector<char> ob, gb;
   std::vector<size_t> oo, go;
@@ -453,6 +478,7 @@ fr_status fr_rhs_noalloc(fr_ctx* c, const void* U, void* R) {
   if (!U || !R || !aligned(U, a) || !aligned(R, a))
     return fail(c, FR_E_INVALID, "fr_rhs_noalloc: null or misaligned pointer");
   if (U == R) return fail(c, FR_E_INVALID, "fr_rhs_noalloc: U and R must not alias");
+  if (!c->ks.rhs_ws) return fail(c, FR_E_UNSUPPORTED, "fr_rhs_noalloc: not provided for SDRT contexts");
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t nuf = (size_t)c->ne * c->nf * c->nv * 8;
   const size_t nq = c->visc ? (size_t)c->ne * c->ns * c->nd * c->nv * 8 : 0;
@@ -488,6 +514,9 @@ fr_status fr_jacobian_blocks(fr_ctx* c, const void* U, void* blocks, fr_precisio
   if (!U || !blocks || !aligned(U, a) || !aligned(blocks, ob))
     return fail(c, FR_E_INVALID, "fr_jacobian_blocks: null or misaligned pointer");
   if (out_prec < FR_F64 || out_prec > FR_BF16) return fail(c, FR_E_INVALID, "fr_jacobian_blocks: bad precision");
+  if (!c->ks.jac)
+    return fail(c, FR_E_UNSUPPORTED, "fr_jacobian_blocks: not provided for SDRT contexts (for linear fluxes on "
+                                     "affine elements FR-SDRT gives the same operator)");
   int rc = c->ks.jac(c, U, blocks, (int)out_prec, 1 + c->nface);
   return rc ? (fr_status)rc : FR_OK;
 }

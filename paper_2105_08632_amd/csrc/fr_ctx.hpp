@@ -19,10 +19,14 @@ struct KernelSet {
   int (*jac)(fr_ctx_s*, const void* U, void* B, int out_prec, int nblk);
   size_t (*mf_bytes)(int which);       // matrix-core Jacobian workspaces per element (0: sensitivities, 1: tables)
   int (*mf_setup)(fr_ctx_s*);          // computes the geometry-only sensitivities
+  // SDRT residual and its tangent (tensor elements; null for triangles)
+  int (*rhs_sd)(fr_ctx_s*, const void* U, void* R);
+  int (*jvp_sd)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
 };
 
 struct fr_ctx_s {
   int nd = 0, type = 0, p = 0, system = 0, nv = 0, prec = 0;
+  int scheme = 0;              // 0 FR-DG, 1 FR-SDRT, 2 SDRT
   int64_t ne = 0;
   int ns = 0, nf = 0, nface = 0, nfp = 0, b = 0;
   bool visc = false;

@@ -9,6 +9,10 @@
 //     Gauss-Legendre solution points the divergence of the correction
 //     function of an end point is l_i(+-1)/w_i (the DG-recovering choice of
 //     the paper's FR section), tensorised along the normal line.
+//   * FR-SDRT / SDRT (tensor elements): the correction of an end point is the
+//     derivative of the flux-point Lagrange polynomial that is 1 there, on the
+//     SD flux points {-1, Gauss-Legendre points of order p, +1} (the
+//     Raviart-Thomas basis of the external flux points), in barycentric form;
 //   * triangles: orthonormal Dubiner basis from a Gauss-Jacobi quadrature mass
 //     matrix, nodal basis by the inverse Vandermonde, lifting M^{-1} E.
 #include "fr_host.hpp"
@@ -91,6 +95,16 @@ struct Bary {
     for (size_t j = 0; j < n; ++j) den += bw[j] / (t - x[j]);
     for (size_t j = 0; j < n; ++j) l[j] = bw[j] / (t - x[j]) / den;
   }
+  // all basis derivatives at t (t not a node)
+  void deriv(double t, std::vector<double>& d) const {
+    const size_t n = x.size();
+    std::vector<double> l;
+    eval(t, l);
+    double s = 0.0;
+    for (size_t k = 0; k < n; ++k) s += 1.0 / (t - x[k]);
+    d.assign(n, 0.0);
+    for (size_t j = 0; j < n; ++j) d[j] = l[j] * (s - 1.0 / (t - x[j]));
+  }
   // D_ij = l_j'(x_i)
   std::vector<double> diff() const {
     const size_t n = x.size();
@@ -135,7 +149,7 @@ static void finish_ops(RefOps& R, double beta) {
       }
 }
 
-static void build_tensor(RefOps& R, int type, int p) {
+static void build_tensor(RefOps& R, int type, int p, int scheme) {
   const int n1 = p + 1;
   const int nd = (type == QUAD) ? 2 : 3;
   R.type = type; R.p = p; R.nd = nd;
@@ -152,6 +166,31 @@ static void build_tensor(RefOps& R, int type, int p) {
   B.eval(1.0, lp); B.eval(-1.0, lm);
   std::vector<double> hp(n1), hm(n1);
   for (int i = 0; i < n1; ++i) { hp[i] = lp[i] / w[i]; hm[i] = lm[i] / w[i]; }
+  R.scheme = scheme;
+  if (scheme != 0) {
+    // SD flux points: -1, the p Gauss-Legendre points of order p, +1
+    std::vector<double> zi, wi;
+    gl_golub_welsch(p, zi, wi);
+    std::vector<double> z(1, -1.0);
+    z.insert(z.end(), zi.begin(), zi.end());
+    z.push_back(1.0);
+    Bary Bz(z);
+    R.sdz = z;
+    R.sdD.assign(n1 * (p + 2), 0.0);
+    std::vector<double> d;
+    for (int i = 0; i < n1; ++i) {
+      Bz.deriv(x[i], d);
+      for (int j = 0; j < p + 2; ++j) R.sdD[i * (p + 2) + j] = d[j];
+      hp[i] = d[p + 1];      // div of the +1 end's basis function
+      hm[i] = -d[0];         // outward normal -1 at the other end
+    }
+    R.sdI.assign(p * n1, 0.0);
+    std::vector<double> l;
+    for (int j = 0; j < p; ++j) {
+      B.eval(z[j + 1], l);
+      for (int i = 0; i < n1; ++i) R.sdI[j * n1 + i] = l[i];
+    }
+  }
   R.D1 = D1; R.hp = hp; R.hm = hm; R.lp = lp; R.lm = lm;
 
   auto sidx = [&](int r, int d) { return d == 0 ? r % n1 : (d == 1 ? (r / n1) % n1 : r / (n1 * n1)); };
@@ -189,6 +228,26 @@ static void build_tensor(RefOps& R, int type, int p) {
       }
       for (int d = 0; d < nd; ++d) R.fp[g * nd + d] = (d == ax) ? sg : x[fidx[g * 3 + d]];
     }
+  }
+  if (scheme != 0) {
+    // external flux points at the ends of each line (tangential indices of
+    // the other axes in increasing axis order, as the line numbering)
+    const int nl = R.ns / n1;
+    R.sdend.assign(nd * nl * 2, -1);
+    for (int d = 0; d < nd; ++d)
+      for (int l = 0; l < nl; ++l) {
+        int tan[3] = {-1, -1, -1}, rem = l;
+        for (int e = 0; e < nd; ++e)
+          if (e != d) { tan[e] = rem % n1; rem /= n1; }
+        for (int g = 0; g < R.nf; ++g) {
+          const int f = R.fface[g];
+          if (faces[f].ax != d) continue;
+          bool on = true;
+          for (int e = 0; e < nd; ++e)
+            if (e != d && fidx[g * 3 + e] != tan[e]) on = false;
+          if (on) R.sdend[(d * nl + l) * 2 + (faces[f].sg > 0 ? 1 : 0)] = g;
+        }
+      }
   }
   R.M0.assign(R.nf * R.ns, 0.0);
   R.Cor.assign(R.ns * R.nf, 0.0);
@@ -356,9 +415,11 @@ static bool build_tri(RefOps& R, int p, const double* pts, std::string& err) {
   return true;
 }
 
-bool build_ref(int type, int p, double beta, const double* tri_pts, RefOps& R, std::string& err) {
+bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, RefOps& R, std::string& err) {
   if (p < 1 || p > 4) { err = "degree must be in 1..4"; return false; }
-  if (type == QUAD || type == HEX) build_tensor(R, type, p);
+  if (scheme < 0 || scheme > 2) { err = "unknown scheme"; return false; }
+  if (scheme != 0 && type == TRI) { err = "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra"; return false; }
+  if (type == QUAD || type == HEX) build_tensor(R, type, p, scheme);
   else if (type == TRI) {
     if (!tri_pts) { err = "triangles need tri_sol_pts"; return false; }
     if (!build_tri(R, p, tri_pts, err)) return false;
@@ -421,6 +482,31 @@ static double adj(int nd, const double* J, double* S) {
   S[3] = J[5] * J[6] - J[3] * J[8]; S[4] = J[0] * J[8] - J[2] * J[6]; S[5] = J[2] * J[3] - J[0] * J[5];
   S[6] = J[3] * J[7] - J[4] * J[6]; S[7] = J[1] * J[6] - J[0] * J[7]; S[8] = J[0] * J[4] - J[1] * J[3];
   return J[0] * S[0] + J[1] * S[3] + J[2] * S[6];
+}
+
+void build_sd_metric(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, std::vector<double>& Sint) {
+  const int p = R.p, n1 = p + 1, nl = R.ns / n1;
+  Sint.assign((size_t)ne * nd * nl * p * nd, 0.0);
+  std::vector<double> X((size_t)R.nvert * nd);
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int v = 0; v < R.nvert; ++v)
+      for (int i = 0; i < nd; ++i) X[v * nd + i] = xyz[((size_t)e * max_vert + v) * nd + i];
+    for (int d = 0; d < nd; ++d)
+      for (int l = 0; l < nl; ++l) {
+        int tan[3] = {0, 0, 0}, rem = l;
+        for (int a = 0; a < nd; ++a)
+          if (a != d) { tan[a] = rem % n1; rem /= n1; }
+        for (int j = 0; j < p; ++j) {
+          double xi[3], x[3], J[9], S[9];
+          // 1-D node i is the first coordinate of solution point i
+          for (int a = 0; a < nd; ++a) xi[a] = (a == d) ? R.sdz[j + 1] : R.sp[tan[a] * nd + 0];
+          mapping(R, nd, X.data(), xi, x, J);
+          adj(nd, J, S);
+          for (int k = 0; k < nd; ++k)
+            Sint[((((size_t)e * nd + d) * nl + l) * p + j) * nd + k] = S[d * nd + k];
+        }
+      }
+  }
 }
 
 bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,

@@ -25,11 +25,24 @@ struct RefOps {
   // h+-_i = l_i(+-1)/w_i and end values l_i(+-1)
   std::vector<double> D1, hp, hm, lp, lm;
   std::vector<std::vector<int>> face_verts;
+  // scheme: 0 FR-DG, 1 FR-SDRT, 2 SDRT (tensor elements)
+  int scheme = 0;
+  // SDRT lines: interior SD flux points z_1..z_p of a line, sdI[j][i] =
+  // l_i(z_{j+1}) (solution points to interior flux points), sdD[i][j] =
+  // psi_j'(x_i) (derivative of the flux-point Lagrange basis psi_0..psi_{p+1}
+  // at the solution points), sdend[(d * nl + l) * 2 + side] = the external
+  // flux point at the -1 (side 0) / +1 (side 1) end of line l along axis d
+  std::vector<double> sdz, sdI, sdD;
+  std::vector<int> sdend;
 };
 
 // Builds the FR-DG reference operators.  beta enters G (self gradient).
 // tri_pts: [ns][2] solution points for triangles (may be null otherwise).
-bool build_ref(int type, int p, double beta, const double* tri_pts, RefOps& out, std::string& err);
+bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, RefOps& out, std::string& err);
+
+// SDRT: row d of detJ J^{-1} at the interior flux points of every line along
+// axis d, [ne][nd][nl][p][nd] (nl = lines per axis).
+void build_sd_metric(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, std::vector<double>& Sint);
 
 struct Geometry {
   int nd = 0, ns = 0, nf = 0, nface = 0;
@@ -37,6 +50,7 @@ struct Geometry {
   std::vector<double> S, Jinv, rdet, nrm, magN;   // per element, element-major
   std::vector<int> nbfp, nbr;
   std::vector<int> nbface, back;      // [ne][nface], [ne][nface][nfp]
+  std::vector<double> Sint;           // SDRT: see build_sd_metric (empty otherwise)
 };
 
 // Metric terms at solution / flux points and the flux-point pairing across

@@ -30,6 +30,14 @@ __global__ void __launch_bounds__(kThreads) k_div(OpsD<R> op, GeoD<R> geo, PhysP
                                  Rtan, DevSync());
 }
 
+template <class E, int NV, int SYS, class T, class R, class IO>
+__global__ void __launch_bounds__(kThreads) k_sd_div(OpsD<R> op, GeoD<R> geo, PhysP ph, const IO* U, const IO* V,
+                                                     const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan) {
+  __shared__ __align__(16) char lds[sd_div_lds<E, NV, SYS, T, R>()];
+  sd_div_body<E, NV, SYS, T, R, IO>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, V, UF, Q, QF, Rout,
+                                    Rtan, DevSync());
+}
+
 template <class E, int NV, int SYS, class R, class OT>
 __global__ void __launch_bounds__(kThreads) k_jac(OpsD<R> op, GeoD<R> geo, PhysP ph, const R* U, const R* Q,
                                                   const R* UF, const R* QF, OT* B, int nblk) {
@@ -108,6 +116,43 @@ template <int ET, int P, int SYS, class R> struct Impl {
 
   // T: scalar of the evaluation (real or dual), RC: its base precision
   // (operators and geometry), IO: precision of U, V and the outputs.
+  // SDRT (tensor elements): the FR trace and gradient passes (the gradient
+  // with the SD correction is the SDRT gradient), then the SDRT divergence.
+  template <class T, class RC, class IO>
+  static int residual_sd(fr_ctx_s* c, const IO* U, const IO* V, T* UF, T* Q, T* QF, IO* Rout, IO* Rtan) {
+    if constexpr (ET == ET_TRI) {
+      c->err = "SDRT is provided for quadrilaterals and hexahedra";
+      return -2;
+    } else {
+      OpsD<RC> op = ctx_ops<RC>(c);
+      GeoD<RC> geo = ctx_geo<RC>(c);
+      const int ne = (int)c->ne;
+      const int TE = rhs_tile<E>();
+      const int nt = (ne + TE - 1) / TE;
+      hipLaunchKernelGGL((k_trace<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
+      FR_LAUNCH_CHECK(c);
+      if (c->visc) {
+        hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta,
+                           U, V, (const T*)UF, Q, QF);
+        FR_LAUNCH_CHECK(c);
+      }
+      if (c->timing) fr_time_begin(c, 1);
+      hipLaunchKernelGGL((k_sd_div<E, NV, SYS, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph,
+                         U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan);
+      FR_LAUNCH_CHECK(c);
+      if (c->timing) fr_time_end(c, 1);
+      return 0;
+    }
+  }
+  static int rhs_sd(fr_ctx_s* c, const void* U, void* Rout) {
+    return residual_sd<double, double, R>(c, (const R*)U, (const R*)nullptr, (double*)c->UF64, (double*)c->Q64,
+                                          (double*)c->QF64, (R*)Rout, (R*)nullptr);
+  }
+  static int jvp_sd(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
+    return residual_sd<Dual<double>, double, R>(c, (const R*)U, (const R*)V, (Dual<double>*)c->UFd,
+                                                (Dual<double>*)c->Qd, (Dual<double>*)c->QFd, (R*)Rv, (R*)Jv);
+  }
+
   template <class T, class RC, class IO>
   static int residual(fr_ctx_s* c, const IO* U, const IO* V, T* UF, T* Q, T* QF, IO* Rout, IO* Rtan) {
     OpsD<RC> op = ctx_ops<RC>(c);
@@ -236,5 +281,8 @@ template <int ET, int P, int SYS, class R> struct Impl {
     return 0;
   }
 
-  static KernelSet set() { return KernelSet{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup}; }
+  static KernelSet set() {
+    return KernelSet{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup, ET == ET_TRI ? nullptr : &rhs_sd,
+                     ET == ET_TRI ? nullptr : &jvp_sd};
+  }
 };

@@ -53,6 +53,10 @@ template <class R> struct OpsD {
   const int* gc;  const R* gv;     // [ND][NS][WL]  G_d  = D_d - (1/2+beta) Cor diag(nref_d) M0
   const int* ddc; const R* ddv;    // [ND][NS][WL]  D_d
   const int* crc; const R* crv;    // [NS][WC]      Cor rows
+  // SDRT (tensor elements): sdI [p][p+1] solution points -> interior SD flux
+  // points of a line, sdD [p+1][p+2] flux-point Lagrange derivatives at the
+  // solution points, sdend [ND][NL][2] external flux point at each line end
+  const R* sdI; const R* sdD; const int* sdend;
 };
 
 // Per-element geometry of one group, element-major.
@@ -68,6 +72,7 @@ template <class R> struct GeoD {
   const int* nbface;  // [ne][NFACE]     the neighbour's local index of the shared face
   const int* back;    // [ne][NFACE][NFP] this element's point paired with each point of that neighbour face
   int* status;        // [2] non-finite output report (device): [0] kinds, [1] smallest element
+  const R* Sint;      // SDRT: [ne][ND][NL][p][ND] row d of detJ J^{-1} at the interior flux points of d-lines
 };
 
 // Kinds of output a non-finite value was stored to.
@@ -315,6 +320,152 @@ FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, co
     for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * sJ[(e * NF + crc[r * WC + w]) * NV + a];
     T res = -(geo.rdet[n * NS + r] * acc);
     long o = (n * NS + r) * NV + a;
+    if (Rout) {
+      Rout[o] = IO(val(res));
+      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, n);
+    }
+    if constexpr (!std::is_same<T, R>::value) {
+      if (Rtan) {
+        Rtan[o] = IO(res.d);
+        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, n);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// SDRT divergence (tensor elements, section "SDRT method"): on every line
+// along axis d the flux is represented by the Lagrange basis psi_0..psi_{p+1}
+// of the SD flux points {-1, z_1..z_p, +1}.  At the interior points the
+// transformed normal flux (detJ J^{-1} f(u, q)) . e_d is evaluated from u and
+// q interpolated along the line; at the two ends the |N|-scaled common flux
+// (outward) stands in, with sign -1 at the -1 end.  The divergence at the
+// solution points is the sum over axes of psi_j' along the point's line
+// (eq. "divergence_sdrt"); R = -div / detJ.  The gradient pass is the FR one
+// with the SD correction, which equals the SDRT gradient (u is of degree p).
+template <class E> struct SdSizes {
+  static constexpr int N1 = E::DEG + 1, P = E::DEG, NL = E::NS / (E::DEG + 1), NI = E::ND * NL * P;
+};
+template <class E, int NV, int SYS, class T, class R> constexpr int sd_div_lds() {
+  typedef SdSizes<E> Q;
+  constexpr int TE = rhs_tile<E>();
+  return lds_bytes<R>(Q::P * Q::N1) + lds_bytes<R>(Q::N1 * (Q::P + 2)) + lds_bytes<int>(E::ND * Q::NL * 2) +
+         lds_bytes<T>(TE * Q::NI * NV) + lds_bytes<T>(TE * E::NF * NV);
+}
+// index of the solution point at position m of line l along axis d (the
+// other axes' indices taken from l in increasing axis order)
+template <class E> FR_HD int sd_point(int d, int l, int m) {
+  constexpr int N1 = E::DEG + 1;
+  int idx[3] = {0, 0, 0}, rem = l;
+  for (int a = 0; a < E::ND; ++a)
+    if (a != d) { idx[a] = rem % N1; rem /= N1; }
+  idx[d] = m;
+  return idx[0] + N1 * (idx[1] + N1 * idx[2]);
+}
+template <class E> FR_HD void sd_line_of(int r, int d, int& l, int& m) {
+  constexpr int N1 = E::DEG + 1;
+  int idx[3] = {r % N1, (r / N1) % N1, r / (N1 * N1)};
+  m = idx[d];
+  l = 0;
+  int mul = 1;
+  for (int a = 0; a < E::ND; ++a)
+    if (a != d) { l += idx[a] * mul; mul *= N1; }
+}
+template <class E, int NV, int SYS, class T, class R, class IO, class Sync>
+FR_HD void sd_div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
+                       const IO* U, const IO* V, const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, Sync sync) {
+  typedef SdSizes<E> Z;
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, N1 = Z::N1, P = Z::P, NL = Z::NL, NI = Z::NI;
+  constexpr int TE = rhs_tile<E>();
+  constexpr bool VISC = SysTraits<SYS>::kVisc;
+  Lds L{lds};
+  R* sI = L.take<R>(P * N1);
+  R* sD = L.take<R>(N1 * (P + 2));
+  int* send = L.take<int>(ND * NL * 2);
+  T* sFi = L.take<T>(TE * NI * NV);
+  T* sJ = L.take<T>(TE * NF * NV);
+  const int e0 = tile * TE;
+  const int nte = (geo.ne - e0) < TE ? (geo.ne - e0) : TE;
+  const bool visc = VISC && (SYS != SYS_ADV || ph.mu != 0.0);
+  for (int i = tid; i < P * N1; i += nth) sI[i] = op.sdI[i];
+  for (int i = tid; i < N1 * (P + 2); i += nth) sD[i] = op.sdD[i];
+  for (int i = tid; i < ND * NL * 2; i += nth) send[i] = op.sdend[i];
+  sync();
+  // transformed normal flux at the interior flux points
+  for (int i = tid; i < nte * NI; i += nth) {
+    const int e = i / NI, k = i % NI, d = k / (NL * P), l = (k / P) % NL, j = k % P;
+    const long n = e0 + e;
+    T u[NV], f[ND][NV];
+    for (int a = 0; a < NV; ++a) u[a] = T(R(0));
+    for (int m = 0; m < N1; ++m) {
+      const long o = (n * NS + sd_point<E>(d, l, m)) * NV;
+      for (int a = 0; a < NV; ++a) u[a] += sI[j * N1 + m] * make_in<T, R, IO>(U, V, o + a);
+    }
+    flux_inviscid<SYS, ND, NV, T>(ph, u, f);
+    if (visc) {
+      T q[ND][NV], fv[ND][NV];
+      for (int dd = 0; dd < ND; ++dd)
+        for (int a = 0; a < NV; ++a) q[dd][a] = T(R(0));
+      for (int m = 0; m < N1; ++m) {
+        const long o = (n * NS + sd_point<E>(d, l, m)) * ND * NV;
+        for (int dd = 0; dd < ND; ++dd)
+          for (int a = 0; a < NV; ++a) q[dd][a] += sI[j * N1 + m] * Q[o + dd * NV + a];
+      }
+      flux_viscous<SYS, ND, NV, T>(ph, u, q, fv);
+      for (int dd = 0; dd < ND; ++dd)
+        for (int a = 0; a < NV; ++a) f[dd][a] += fv[dd][a];
+    }
+    const R* Sr = geo.Sint + (((n * ND + d) * NL + l) * P + j) * ND;
+    for (int a = 0; a < NV; ++a) {
+      T acc = T(R(0));
+      for (int kk = 0; kk < ND; ++kk) acc += Sr[kk] * f[kk][a];
+      sFi[(e * NI + k) * NV + a] = acc;
+    }
+  }
+  // |N| times the common flux at the external flux points
+  const R cL = R(0.5 + ph.beta), cR = R(0.5 - ph.beta), eta = R(ph.eta);
+  for (int i = tid; i < nte * NF; i += nth) {
+    const int e = i / NF, g = i % NF;
+    const long n = e0 + e;
+    const long pg = geo.nbfp[n * NF + g];
+    T uL[NV], uR[NV], F[NV];
+    for (int a = 0; a < NV; ++a) { uL[a] = UF[(n * NF + g) * NV + a]; uR[a] = UF[pg * NV + a]; }
+    R nn[ND];
+    for (int d = 0; d < ND; ++d) nn[d] = geo.nrm[(n * NF + g) * ND + d];
+    common_inviscid<SYS, ND, NV, T>(ph, uL, uR, nn, F);
+    if (visc) {
+      T qL[ND][NV], qR[ND][NV], fL[ND][NV], fR[ND][NV];
+      for (int d = 0; d < ND; ++d)
+        for (int a = 0; a < NV; ++a) {
+          qL[d][a] = QF[((n * NF + g) * ND + d) * NV + a];
+          qR[d][a] = QF[(pg * ND + d) * NV + a];
+        }
+      flux_viscous<SYS, ND, NV, T>(ph, uL, qL, fL);
+      flux_viscous<SYS, ND, NV, T>(ph, uR, qR, fR);
+      for (int a = 0; a < NV; ++a) {
+        T acc = eta * (uL[a] - uR[a]);
+        for (int d = 0; d < ND; ++d) acc += nn[d] * (cL * fL[d][a] + cR * fR[d][a]);
+        F[a] += acc;
+      }
+    }
+    const R mg = geo.magN[n * NF + g];
+    for (int a = 0; a < NV; ++a) sJ[(e * NF + g) * NV + a] = mg * F[a];
+  }
+  sync();
+  for (int i = tid; i < nte * NS * NV; i += nth) {
+    const int e = i / (NS * NV), r = (i / NV) % NS, a = i % NV;
+    const long n = e0 + e;
+    T acc = T(R(0));
+    for (int d = 0; d < ND; ++d) {
+      int l, m;
+      sd_line_of<E>(r, d, l, m);
+      const R* Dm = sD + m * (P + 2);
+      acc += Dm[P + 1] * sJ[(e * NF + send[(d * NL + l) * 2 + 1]) * NV + a];
+      acc -= Dm[0] * sJ[(e * NF + send[(d * NL + l) * 2 + 0]) * NV + a];
+      for (int j = 0; j < P; ++j) acc += Dm[j + 1] * sFi[(e * NI + (d * NL + l) * P + j) * NV + a];
+    }
+    T res = -(geo.rdet[n * NS + r] * acc);
+    const long o = (n * NS + r) * NV + a;
     if (Rout) {
       Rout[o] = IO(val(res));
       if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, n);

@@ -1001,6 +1001,7 @@ fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
   if (!c || !out) return FR_E_INVALID;
   *out = nullptr;
   if (kind != FR_PC_BLOCK_JACOBI && kind != FR_PC_MLP) return sfail(c, FR_E_INVALID, "unknown preconditioner kind");
+  if (!c->ks.jac) return sfail(c, FR_E_UNSUPPORTED, "block preconditioners need Jacobian blocks (not for SDRT contexts)");
   if (c->b > kLuMaxB) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
   if (kind == FR_PC_MLP && c->b > 64) return sfail(c, FR_E_UNSUPPORTED, "learned preconditioner blocks up to 64 x 64");
   fr_precond_s* pc = new fr_precond_s();

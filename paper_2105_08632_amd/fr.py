@@ -40,7 +40,7 @@ class _Mesh(C.Structure):
 class _Phys(C.Structure):
     _fields_ = [("system", C.c_int32), ("nvars", C.c_int32), ("adv_vel", C.c_double * 3),
                 ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
-                ("ldg_beta", C.c_double), ("ldg_penalty", C.c_double)]
+                ("ldg_beta", C.c_double), ("ldg_penalty", C.c_double), ("scheme", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -117,7 +117,7 @@ class Context:
                   self._keep[2].ctypes.data, self._keep[3].ctypes.data, mesh.max_face,
                   None if tp is None else tp.ctypes.data)
         ph = _Phys(phys.system, phys.nvars, (C.c_double * 3)(*[float(x) for x in phys.adv_vel]),
-                   phys.gamma, phys.mu, phys.prandtl, phys.beta, phys.eta)
+                   phys.gamma, phys.mu, phys.prandtl, phys.beta, phys.eta, int(getattr(phys, "scheme", 0)))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
