@@ -53,20 +53,25 @@ def jac_bytes_per_element(ns, nv, nd, nf, nface, bytes_out=4):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fr_kernels.hpp", "fr_jac_tp.hpp", "fr_jac_mf.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp"):
+    for f in ("fr_kernels.hpp", "fr_jac_tp.hpp", "fr_jac_mf.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp",
+              "fr_solver.hip"):
         h.update(open(os.path.join(ROOT, "paper_2105_08632_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
-    """HBM bytes per launch of the block-assembly kernels from a committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+def measured_traffic(name, kernel=None):
+    """HBM bytes per launch (of all the summary's kernels, or of one) from a
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
+    if kernel:
+        k = d["per_kernel"][kernel]
+        return k["hbm_read_bytes"] + k["hbm_write_bytes"]
     return d.get("hbm_bytes_per_launch")
 
 
@@ -550,8 +555,9 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true", help="skip the 2-D quadrilateral measurement")
     ap.add_argument("--no-lu", action="store_true", help="skip the block-Jacobi LU of the 3-D blocks")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 block assembly")
-    ap.add_argument("--only", choices=["cfg2", "cfg1"], default=None,
-                    help="time only this workload's step (profiling runs)")
+    ap.add_argument("--only", choices=["cfg2", "cfg2_bf16", "cfg1", "lu"], default=None,
+                    help="time only this workload's step: the 3-D step with FP32 or BF16 blocks, the 2-D "
+                         "step, or the block-Jacobi LU of the 3-D blocks (profiling runs)")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
@@ -581,6 +587,29 @@ def main():
     R = ctx.empty_state()
     B = ctx.block_tensor("f32")
     dof = ctx.ndof
+
+    if args.only == "lu":
+        out = block_lu_bench(torch, fr, ctx, U, Ud, R, log)
+        if args.copy_probe > 0:
+            _copy_probe(torch, args.copy_probe)
+        print(json.dumps(out), flush=True)
+        return
+    if args.only == "cfg2_bf16":
+        del B
+        torch.cuda.empty_cache()
+        B16 = ctx.block_tensor("bf16")
+
+        def step16():
+            ctx.rhs(Ud, R)
+            ctx.jacobian_blocks(Ud, B16, "bf16")
+
+        w16, g16, k16 = _timed_steps(torch, ctx, step16, args.steps, args.warmup)
+        ms16 = 1e3 * w16 / args.steps
+        out = {"ms_per_step": round(ms16, 4), "kernel_ms": round(k16, 4)}
+        if args.copy_probe > 0:
+            _copy_probe(torch, args.copy_probe)
+        print(json.dumps(out), flush=True)
+        return
 
     def step():
         ctx.rhs(Ud, R)
@@ -694,12 +723,26 @@ def block_lu_bench(torch, fr, ctx, U, Ud, R, log):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
+    pc.setup(Ud, 1.0, -dt)
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    ctx.kernel_time(0)
     t_setup = timed(lambda: pc.setup(Ud, 1.0, -dt), 2)
+    ctx.sync()
+    jac_ms, jac_n = ctx.kernel_time(0)            # the diagonal-block assembly inside each setup
+    ctx.set_kernel_timing(False)
     z = ctx.empty_state()
     t_apply = timed(lambda: pc.apply(R, z), 5)
     flop = ctx.ne * (2.0 / 3.0) * ctx.b ** 3
+    lu_ms = t_setup - jac_ms / max(jac_n, 1)       # one timed assembly launch per setup
+    tflops = flop / (lu_ms * 1e-3) / 1e12
     out = {"setup_ms": round(t_setup, 2), "apply_ms": round(t_apply, 3), "lu_gflop": round(flop / 1e9, 1),
-           "note": "setup = diagonal blocks (FP32) + FP64 LU of each", "finite": bool(torch.isfinite(z).all())}
+           "lu_ms": round(lu_ms, 2),
+           "roofline": {"bound": "fp64", "achieved": round(tflops, 2), "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": round(tflops / 78.6, 4), "kernel": "k_block_lu",
+                        "traffic": measured_traffic("k_block_lu_hex_p3_24_traffic.json", "k_block_lu")},
+           "note": "setup = diagonal blocks (FP32) + FP64 LU of each; lu_ms = setup minus the timed assembly",
+           "finite": bool(torch.isfinite(z).all())}
     log(f"cfg2 block LU: setup {out['setup_ms']} ms, apply {out['apply_ms']} ms")
     pc.close()
     return out
