@@ -51,10 +51,12 @@ def jac_bytes_per_element(ns, nv, nd, nf, nface, bytes_out=4):
     return out + state + geom
 
 
-def kernel_source_hash():
+JAC_SOURCES = ("fr_kernels.hpp", "fr_jac_tp.hpp", "fr_jac_mf.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp")
+
+
+def kernel_source_hash(files=JAC_SOURCES):
     h = hashlib.sha256()
-    for f in ("fr_kernels.hpp", "fr_jac_tp.hpp", "fr_jac_mf.hpp", "physics.hpp", "dual.hpp", "fr_impl.hpp",
-              "fr_solver.hip"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2105_08632_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -67,7 +69,7 @@ def measured_traffic(name, kernel=None):
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(tuple(d.get("sources", JAC_SOURCES))):
         return None
     if kernel:
         k = d["per_kernel"][kernel]
