@@ -124,12 +124,17 @@ fr_status fr_ctx_destroy(fr_ctx* ctx);
 fr_status fr_ctx_info(const fr_ctx* ctx, fr_info* info);
 const char* fr_last_error(const fr_ctx* ctx);
 /* Waits for the context stream and reports any asynchronous HIP error.
- * The residual, JVP and Jacobian kernels record every non-finite value they
- * store in a device status word of the context; fr_ctx_sync returns
- * FR_E_NONFINITE if any was stored since the previous fr_ctx_sync (the
- * message names the outputs and the smallest element index) and clears the
- * word.  The hot calls return before their kernels finish, so they cannot
- * report it themselves. */
+ * The residual and JVP kernels record every non-finite value they store in a
+ * device status word of the context, and so does the Jacobian assembly: the
+ * matrix-core path (FP32 contexts, quadrilaterals and hexahedra) records the
+ * non-finite entries of the per-state flux-derivative tables its blocks are
+ * sums of products of (with finite geometric factors, so a non-finite block
+ * entry comes from one; an overflow of a product of finite values is not
+ * caught), the other paths every non-finite block value.  fr_ctx_sync
+ * returns FR_E_NONFINITE if any was recorded since the previous fr_ctx_sync
+ * (the message names the outputs and the smallest element index) and clears
+ * the word.  The hot calls return before their kernels finish, so they
+ * cannot report it themselves. */
 fr_status fr_ctx_sync(fr_ctx* ctx);
 
 /* R = R(U): the FR-DG residual, eq. "divergence_fr" and the method of

@@ -73,8 +73,7 @@ __global__ void __launch_bounds__((64 * jac_mf_wpb<E, NV, SYS, R>()))
 __attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R, OT>()))) k_jac_mf_asm(Ops1D<R> o1, const R* rdet,
                                                                                 const R* tab, const R* sens,
                                                                                 const R* sigtab, const int* sig,
-                                                                                int nsb, int nblk, long ntasks, OT* B,
-                                                                                int* status) {
+                                                                                int nsb, int nblk, long ntasks, OT* B) {
   typedef MfSizes<E, NV, SYS> Y;
   constexpr int WPB = jac_mf_wpb<E, NV, SYS, R>(), STG = jac_mf_stage<E, NV, SYS, R>();
   __shared__ __align__(16) R stage[WPB * STG];
@@ -95,7 +94,7 @@ __attribute__((amdgpu_waves_per_eu(jac_mf_min_waves<E, NV, SYS, R, OT>()))) k_ja
   R* stg = stage + wave * STG;
   const int lane = threadIdx.x & 63;
   jac_mf_task<E, NV, SYS, R, OT>(n, k, mt, nt, slab, lane, o1, rdet, tab, sens, sigtab, sig, nsb, nblk, B, stg, xs,
-                                 active, status);
+                                 active);
 }
 
 template <class R> Ops1D<R>& ctx_o1(fr_ctx_s* c);
@@ -233,7 +232,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
       constexpr int per = jac_mf_wpb<E, NV, SYS, R>();
       hipLaunchKernelGGL((k_jac_mf_asm<E, NV, SYS, R, OT>), dim3((unsigned)((ntasks + per - 1) / per)), dim3(64 * per),
                          0, c->stream, ctx_o1<R>(c), geo.rdet, (const R*)c->mf_tab, (const R*)c->mf_sens,
-                         (const R*)c->mf_sigtab, (const int*)c->mf_sig, 1 + E::NFACE, nblk, ntasks, B, geo.status);
+                         (const R*)c->mf_sigtab, (const int*)c->mf_sig, 1 + E::NFACE, nblk, ntasks, B);
       FR_LAUNCH_CHECK(c);
       if (c->timing) fr_time_end(c, 0);
       return 0;

@@ -299,6 +299,11 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
   const long nl = n;
   R* tbT = out + nl * Y::TAB;
   R* tfT = tbT + Y::TBT;
+  // The blocks are sums of products of these tables with the finite
+  // geometric sensitivities, so a non-finite block entry can only come from
+  // a non-finite table entry: they are recorded here, once per element,
+  // rather than at every block store.
+  bool bad = false;
   for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
   if (visc)
     for (int i = tid; i < NS * ND * NV; i += nth) sq[i] = Q[nl * NS * ND * NV + i];
@@ -355,6 +360,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
               R acc = R(0);
               for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d;
               tbT[Y::ti(t, d, ND, Y::pidx(a, c))] = acc;
+              bad |= !fr_finite(acc);
             }
         } else {
           R bq[ND][ND][NV];   // d f^k_a / d q_{d2,c}
@@ -375,6 +381,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
                   for (int d2 = 0; d2 < ND; ++d2) acc += sk * bq[d2][k][a] * sJi[(t * ND + e) * ND + d2];
                 }
                 tbT[Y::ti(t, d, e, Y::pidx(a, c))] = acc;
+                bad |= !fr_finite(acc);
               }
         }
       } else {
@@ -410,7 +417,9 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
           for (int a = 0; a < NV; ++a) {
             const int m = Y::pidx(a, c);
             const R id = (a == c) ? eta : R(0);
-            tfT[Y::fi(g, side, m)] = mg * (F[a].d + (visc ? (side == 0 ? vs[a] + id : vs[a] - id) : R(0)));
+            const R w = mg * (F[a].d + (visc ? (side == 0 ? vs[a] + id : vs[a] - id) : R(0)));
+            tfT[Y::fi(g, side, m)] = w;
+            bad |= !fr_finite(w);
             if (!visc)
               for (int d = 0; d < ND; ++d) tfT[Y::fi(g, 2 + side * ND + d, m)] = R(0);
           }
@@ -429,6 +438,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
             for (int d = 0; d < ND; ++d) acc += nn[d] * fv[d][a].d;
             acc *= wgt;
             tfT[Y::fi(g, 2 + side * ND + qd, Y::pidx(a, c))] = mg * acc;
+            bad |= !fr_finite(mg * acc);
           }
         }
       }
@@ -440,7 +450,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
       }
     sync();
   }
-
+  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, nl);
 }
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
@@ -719,7 +729,7 @@ template <class E, int NV, int SYS, class R, class OT>
 __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0, int lane, const Ops1D<R>& o1,
                                             const R* rdet, const R* tab, const R* sens, const R* sigtab,
                                             const int* sig, int nsb, int nblk, OT* B, R* stage, char* xs,
-                                            bool active, int* status) {
+                                            bool active) {
   typedef MfSizes<E, NV, SYS> Y;
   typedef TPIdx<E> X;
   typedef Mfma<R> M;
@@ -995,7 +1005,6 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
   const int nsg = (NS - nt * 16) < 16 ? (NS - nt * 16) : 16;
   const int ncol = nsg * nbt;
   OT* Bk = B + (nl * nblk + k) * (long)BB * BB + (long)R0 * NV;
-  bool bad = false;      // a non-finite value among this lane's stores
   mf_for<0, NH>([&](auto H) __attribute__((always_inline)) {
     constexpr int h = decltype(H)::value;
     if constexpr (h > 0) __syncthreads();      // the previous pass has left the stage
@@ -1021,7 +1030,6 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
           const int cl = i / NRH, rr = i % NRH;
           const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
           const R* sp = stage + cl * SP + rr;
-          bad |= !(fr_finite(sp[0]) && fr_finite(sp[1]) && fr_finite(sp[2]) && fr_finite(sp[3]));
           if constexpr (std::is_same<OT, float>::value) {
             *reinterpret_cast<float4*>(Bh + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
           } else {
@@ -1036,10 +1044,8 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
           const int cl = i / NRH, rr = i % NRH;
           const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
           Bh[(long)c * BB + rr] = to_out<OT>(stage[cl * SP + rr]);
-          bad |= !fr_finite(stage[cl * SP + rr]);
         }
       }
     }
   });
-  if (bad) fr_flag_nonfinite(status, FR_NF_BLOCKS, nl);
 }
