@@ -21,7 +21,9 @@
  *    index rho = i + (p+1) j (+ (p+1)^2 k), xi_i ascending (appendix A);
  *    triangles use the caller's points (tri_sol_pts).
  *  - State vectors are element-major U[n][rho][alpha] (alpha = conserved
- *    variable), in the context precision.  DOF index = (n*Ns + rho)*Nv + alpha.
+ *    variable), in the context precision.  DOF index = (n*Ns + rho)*Nv + alpha
+ *    (mixed meshes: element n's entries follow those of elements 0..n-1,
+ *    each with its own Ns).
  *  - Jacobian blocks: for element n, 1 + n_faces blocks of b x b, b = Ns*Nv:
  *    slot 0 = dR_n/dU_n, slot 1+f = dR_n/dU_{nbr(n,f)}.  Each block is stored
  *    column-major: blocks[((n*(1+nface) + slot)*b + c)*b + r] with
@@ -29,6 +31,9 @@
  *    For viscous systems the exact derivative includes every path through the
  *    neighbours' corrected gradients; blocks of the second face layer (which
  *    a viscous residual also depends on) are not returned.  fr_jvp is exact.
+ *    Mixed meshes: element n's blocks start at fr_block_offsets()[n]: its
+ *    self block (b_n x b_n), then one block per local face f (b_n x b_m, m
+ *    the neighbour across f, b_m = Ns(m)*Nv), packed, each column-major.
  *  - Pointers named U, R, v, Jv, blocks, r, z are DEVICE pointers owned by
  *    the caller, aligned to the element size.  Mesh arrays are HOST pointers,
  *    copied during fr_ctx_create.
@@ -74,7 +79,15 @@ typedef enum { FR_SCHEME_FR_DG = 0, FR_SCHEME_FR_SDRT = 1, FR_SCHEME_SDRT = 2 } 
 
 /* Mesh: the paper's tessellation of the domain into conforming elements
  * (section 2) with its face-neighbour stencil (section 3).  All elements of
- * a context share one polynomial degree and one element type. */
+ * a context share one polynomial degree.  A 2-D mesh may mix triangles and
+ * quadrilaterals (conforming: a triangle edge and a quadrilateral edge that
+ * meet carry the same p+1 Gauss-Legendre flux points; the paper's hybrid
+ * meshes and its quadrilateral-to-two-triangles subdivision, section 2); its
+ * elements must be listed grouped by type, all elements of one type first,
+ * else FR_E_INVALID.  Mixed meshes provide fr_rhs, fr_rhs_noalloc, fr_jvp,
+ * fr_rk54 and (inviscid systems) fr_jacobian_blocks in FR-DG; the block
+ * preconditioners, Newton-GMRES, the Fourier analysis and batches take
+ * single-type contexts (FR_E_UNSUPPORTED). */
 typedef struct {
   int32_t ndim;               /* 2 or 3 */
   int64_t n_elem;
@@ -105,6 +118,8 @@ typedef struct {
                                  (FR_E_UNSUPPORTED) */
 } fr_physics;
 
+/* Mixed meshes: n_sol, n_flux, n_face and block_dim are the largest over the
+ * element types, n_dof the sum over the elements. */
 typedef struct {
   int32_t ndim, n_sol, n_flux, n_face, nvars, block_dim;
   int64_t n_elem, n_dof;
@@ -165,8 +180,19 @@ fr_status fr_rhs_noalloc(fr_ctx* ctx, const void* U, void* R);
  * (F32 contexts).  FR_BF16 values are stored rounded to nearest even; for
  * quadrilaterals and hexahedra of degree 3 they are also computed from
  * BF16-rounded operands (matrix cores, FP32 accumulation), elsewhere in FP32.
- * blocks: n_elem * blocks_per_elem * b * b values, layout above. */
+ * blocks: n_elem * blocks_per_elem * b * b values, layout above (mixed
+ * meshes: fr_block_offsets()[n_elem] values; inviscid systems only, viscous
+ * ones return FR_E_UNSUPPORTED).  On mixed meshes the blocks of an element
+ * and its face blocks come from the same chain rule as on single-type meshes,
+ * the face blocks through the neighbour's own interpolation to its flux
+ * points (eq. "interpolate_sol_to_flux"), FP32/FP64 arithmetic. */
 fr_status fr_jacobian_blocks(fr_ctx* ctx, const void* U, void* blocks, fr_precision out_prec);
+
+/* First entry of each element's Jacobian blocks in the array of
+ * fr_jacobian_blocks: off[n] for n = 0..n_elem (off[n_elem] = the array's
+ * length in values).  off: host, n_elem + 1 entries.  Single-type meshes:
+ * off[n] = n * blocks_per_elem * b * b. */
+fr_status fr_block_offsets(const fr_ctx* ctx, int64_t* off);
 
 /* Jv = dR/dU(U) v exactly (forward-mode tangent of every step, including the
  * viscous second layer).  R_out (may be NULL) receives R(U).  Like fr_rhs it

@@ -1,6 +1,7 @@
 // C ABI of libfr.so (declared in include/fr.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <map>
@@ -133,6 +134,10 @@ template <class R> static GeoD<R> geo_view(char* base, const std::vector<size_t>
   return v;
 }
 
+template <class R> static const OpsD<R>& ctx_ops_c(const fr_ctx_s* c);
+template <> const OpsD<double>& ctx_ops_c<double>(const fr_ctx_s* c) { return c->opsd; }
+template <> const OpsD<float>& ctx_ops_c<float>(const fr_ctx_s* c) { return c->opsf; }
+
 static fr_status fail(fr_ctx_s* c, fr_status s, const std::string& m) {
   if (c) c->err = m; else g_create_err = m;
   return s;
@@ -140,6 +145,12 @@ static fr_status fail(fr_ctx_s* c, fr_status s, const std::string& m) {
 
 static void release(fr_ctx_s* c) {
   if (!c) return;
+  for (fr_ctx_s* s : c->grp) release(s);
+  if (c->mix_mem) (void)hipFree(c->mix_mem);
+  if (c->mixd_host) {
+    if (c->prec == FR_F64) delete (MixD<double>*)c->mixd_host;
+    else delete (MixD<float>*)c->mixd_host;
+  }
   if (c->ops_mem) (void)hipFree(c->ops_mem);
   if (c->geo_mem) (void)hipFree(c->geo_mem);
   if (c->work_mem) (void)hipFree(c->work_mem);
@@ -176,6 +187,282 @@ int fr_status_reset(fr_ctx_s* c) {
   return hipMemcpy(c->status, clear, sizeof(clear), hipMemcpyHostToDevice) == hipSuccess ? 0 : -4;
 }
 
+// Uploads one context's (or element group's) FP64 operators and geometry,
+// and FP32 copies for FP32 contexts; fills the views and the 1-D factors of
+// tensor elements.  On failure the caller releases the context.
+static fr_status upload_ops_geo(fr_ctx_s* c, const frh::RefOps& ref, const frh::Geometry& geo, fr_precision prec,
+                                double beta) {
+  std::vector<char> ob, gb;
+  std::vector<size_t> oo, go;
+  // FP64 operators and geometry always (residual); FP32 copies for FP32 contexts
+  pack_ops<double>(ref, ob, oo); pack_geo<double>(geo, gb, go);
+  std::vector<size_t> oo32, go32;
+  if (prec == FR_F32) {
+    std::vector<char> o2, g2;
+    pack_ops<float>(ref, o2, oo32); pack_geo<float>(geo, g2, go32);
+    size_t obase = (ob.size() + 255) & ~(size_t)255, gbase = (gb.size() + 255) & ~(size_t)255;
+    ob.resize(obase + o2.size()); std::memcpy(ob.data() + obase, o2.data(), o2.size());
+    gb.resize(gbase + g2.size()); std::memcpy(gb.data() + gbase, g2.data(), g2.size());
+    for (auto& v : oo32) v += obase;
+    for (auto& v : go32) v += gbase;
+  }
+
+  if (hipMalloc(&c->ops_mem, ob.size()) != hipSuccess || hipMalloc(&c->geo_mem, gb.size()) != hipSuccess) {
+    return fail(nullptr, FR_E_NOMEM, "device allocation failed (operators/geometry)");
+  }
+  if (hipMemcpy(c->ops_mem, ob.data(), ob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->geo_mem, gb.data(), gb.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    return fail(nullptr, FR_E_DEVICE, "upload failed");
+  }
+  if (ref.type != FR_TRI) {
+    for (int i = 0; i <= ref.p; ++i) {
+      for (int j = 0; j <= ref.p; ++j) {
+        double d = ref.D1[i * (ref.p + 1) + j];
+        double cm = ref.hp[i] * ref.lp[j] - ref.hm[i] * ref.lm[j];
+        c->o1d.Dc1[i][j] = d - cm;
+        c->o1d.G1[i][j] = d - (0.5 + beta) * cm;
+        c->o1f.Dc1[i][j] = (float)(d - cm);
+        c->o1f.G1[i][j] = (float)(d - (0.5 + beta) * cm);
+      }
+      c->o1d.hp[i] = ref.hp[i]; c->o1d.hm[i] = ref.hm[i]; c->o1d.lp[i] = ref.lp[i]; c->o1d.lm[i] = ref.lm[i];
+      c->o1f.hp[i] = (float)ref.hp[i]; c->o1f.hm[i] = (float)ref.hm[i];
+      c->o1f.lp[i] = (float)ref.lp[i]; c->o1f.lm[i] = (float)ref.lm[i];
+    }
+  }
+  c->opsd = ops_view<double>((char*)c->ops_mem, oo);
+  c->geod = geo_view<double>((char*)c->geo_mem, go, (int)c->ne);
+  if (prec == FR_F32) {
+    c->opsf = ops_view<float>((char*)c->ops_mem, oo32);
+    c->geof = geo_view<float>((char*)c->geo_mem, go32, (int)c->ne);
+  }
+  return FR_OK;
+}
+
+// Workspaces: traces / gradients for the Jacobian assembly (context
+// precision), their FP64 dual versions for the JVP and FP64 ones for the
+// residual (both evaluated in FP64 whatever the context precision), sized by
+// the mesh's flux and solution points; and the status word.  On failure the
+// caller releases the context.
+static fr_status alloc_work(fr_ctx_s* c) {
+  const size_t nv = (size_t)c->nv, rs = (c->prec == FR_F64) ? 8 : 4;
+  const bool visc = c->visc, f32 = c->prec == FR_F32;
+  const size_t nuf = (size_t)c->nf_tot * nv, nq = (size_t)c->ns_tot * c->nd * nv, nqf = (size_t)c->nf_tot * c->nd * nv;
+  size_t sizes[10] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
+                      2 * nuf * 8, visc ? 2 * nq * 8 : 0, visc ? 2 * nqf * 8 : 0,
+                      f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0,
+                      2 * sizeof(int)};
+  size_t off[10], tot = 0;
+  for (int i = 0; i < 10; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
+  if (hipMalloc(&c->work_mem, tot) != hipSuccess) return fail(nullptr, FR_E_NOMEM, "device allocation failed (workspaces)");
+  char* w = (char*)c->work_mem;
+  c->UF = w + off[0]; c->Q = w + off[1]; c->QF = w + off[2];
+  c->UFd = w + off[3]; c->Qd = w + off[4]; c->QFd = w + off[5];
+  if (f32) { c->UF64 = w + off[6]; c->Q64 = w + off[7]; c->QF64 = w + off[8]; }
+  else { c->UF64 = c->UF; c->Q64 = c->Q; c->QF64 = c->QF; }
+  c->status = (int*)(w + off[9]);
+  c->geod.status = c->status;
+  c->geof.status = c->status;
+  (void)hipGetDevice(&c->dev);
+  scratch_setup(c->dev);
+  if (fr_status_reset(c) != 0) return fail(nullptr, FR_E_DEVICE, "status word initialisation failed");
+  return FR_OK;
+}
+
+// ------------------------------------------------------------ mixed meshes
+// A 2-D mesh of triangles and quadrilaterals (of one degree) listed grouped
+// by type is one context with a sub-context per group.  The groups share the
+// context's trace and gradient workspaces, in a flux-point numbering that
+// runs over the groups in order; each group's kernels see their slice, and
+// reach the traces of a neighbour in the other group through partner indices
+// relative to the slice (build_geometry_groups).  Each residual pass runs over
+// every group before the next pass starts.
+
+// Residual (dual = 0) or residual and tangent (dual = 1) of a mixed mesh on
+// the given FP64 workspaces.
+static int mixed_eval(fr_ctx_s* c, int dual, const void* U, const void* V, void* Rout, void* Rtan, void* UF, void* Q,
+                      void* QF) {
+  const size_t io = c->prec == FR_F64 ? 8 : 4, ts = dual ? 16 : 8;
+  const size_t nv = (size_t)c->nv, nd = (size_t)c->nd;
+  for (int pass = 0; pass < 3; ++pass)
+    for (size_t g = 0; g < c->grp.size(); ++g) {
+      fr_ctx_s* s = c->grp[g];
+      const size_t du = (size_t)c->grp_dof0[g] * io;
+      const size_t fo = (size_t)c->grp_fp0[g] * nv * ts, so = (size_t)c->grp_sp0[g] * nd * nv * ts;
+      int rc = s->ks.phase(s, pass, dual, (const char*)U + du, V ? (const char*)V + du : nullptr, (char*)UF + fo,
+                           Q ? (char*)Q + so : nullptr, QF ? (char*)QF + fo * nd : nullptr,
+                           Rout ? (char*)Rout + du : nullptr, Rtan ? (char*)Rtan + du : nullptr);
+      if (rc) { c->err = s->err; return rc; }
+    }
+  return 0;
+}
+static int mixed_rhs(fr_ctx_s* c, const void* U, void* R) {
+  return mixed_eval(c, 0, U, nullptr, R, nullptr, c->UF64, c->Q64, c->QF64);
+}
+static int mixed_rhs_ws(fr_ctx_s* c, const void* U, void* R, void* UF, void* Q, void* QF) {
+  return mixed_eval(c, 0, U, nullptr, R, nullptr, UF, Q, QF);
+}
+static int mixed_jvp(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
+  return mixed_eval(c, 1, U, V, Rv, Jv, c->UFd, c->Qd, c->QFd);
+}
+// Blocks of every element: traces of all groups, then self blocks, then
+// face blocks (those read the traces of the neighbours in either group).
+static int mixed_jac(fr_ctx_s* c, const void* U, void* B, int out_prec, int nblk) {
+  (void)nblk;
+  if (c->visc) { c->err = "Jacobian blocks of mixed meshes: inviscid systems only"; return FR_E_UNSUPPORTED; }
+  const size_t io = c->prec == FR_F64 ? 8 : 4;
+  for (int stage = 0; stage < 3; ++stage)
+    for (size_t g = 0; g < c->grp.size(); ++g) {
+      fr_ctx_s* s = c->grp[g];
+      if (!s->ks.jac_mixed) { c->err = "no mixed-mesh Jacobian kernels for this element type"; return FR_E_UNSUPPORTED; }
+      int rc = s->ks.jac_mixed(s, stage, (const char*)U + (size_t)c->grp_dof0[g] * io, B, out_prec, s->mixd);
+      if (rc) { c->err = s->err; return rc; }
+    }
+  return 0;
+}
+
+template <class R> static void set_mixd(fr_ctx_s* s, const fr_ctx_s* other, const int* nbpt, const int* nbt,
+                                        const long* fboff) {
+  MixD<R>* h = new MixD<R>();
+  h->nbpt = nbpt; h->nbt = nbt; h->fboff = fboff; h->M0o = ctx_ops_c<R>(other).M0;
+  s->mixd_host = h;
+  s->mixd = h;
+}
+
+static fr_status create_mixed(const fr_mesh_desc* m, const fr_physics* ph, fr_precision prec, void* stream, int nv,
+                              bool visc, fr_ctx** out) {
+  const int64_t ne = m->n_elem;
+  if (m->ndim != 2) return fail(nullptr, FR_E_UNSUPPORTED, "mixed meshes: 2-D triangles and quadrilaterals only");
+  if (ph->scheme != FR_SCHEME_FR_DG) return fail(nullptr, FR_E_UNSUPPORTED, "mixed meshes: FR-DG only");
+  std::vector<int64_t> gs = {0};
+  for (int64_t e = 1; e < ne; ++e)
+    if (m->elem_type[e] != m->elem_type[e - 1]) gs.push_back(e);
+  gs.push_back(ne);
+  const int ngrp = (int)gs.size() - 1;
+  for (int g = 0; g < ngrp; ++g) {
+    const int t = m->elem_type[gs[g]];
+    if (t != FR_TRI && t != FR_QUAD) return fail(nullptr, FR_E_UNSUPPORTED, "mixed meshes: 2-D triangles and quadrilaterals only");
+  }
+  if (ngrp != 2) return fail(nullptr, FR_E_INVALID, "mixed meshes must list their elements grouped by type");
+  frh::RefOps refs[3];
+  std::string err;
+  for (int g = 0; g < ngrp; ++g) {
+    const int t = m->elem_type[gs[g]];
+    if (!frh::build_ref(t, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, refs[t], err))
+      return fail(nullptr, FR_E_INVALID, err);
+    if (m->max_vert < refs[t].nvert || m->max_face < refs[t].nface)
+      return fail(nullptr, FR_E_INVALID, "max_vert/max_face too small");
+  }
+  const frh::RefOps* rp[3] = {&refs[0], &refs[1], &refs[2]};
+  frh::Geometry geo[2];
+  frh::MixInfo mix[2];
+  if (!frh::build_geometry_groups(rp, 2, ne, m->elem_type, m->elem_xyz, m->max_vert, m->nbr, m->nbr_face, m->max_face,
+                                  ngrp, gs.data(), geo, mix, err))
+    return fail(nullptr, FR_E_INVALID, err);
+
+  fr_ctx_s* c = new fr_ctx_s();
+  c->mixed = true;
+  c->nd = 2; c->type = -1; c->p = m->degree; c->system = ph->system; c->nv = nv; c->prec = prec; c->ne = ne;
+  c->visc = visc;
+  for (int i = 0; i < 3; ++i) c->ph.c[i] = ph->adv_vel[i];
+  c->ph.gamma = ph->gamma; c->ph.mu = ph->mu; c->ph.prandtl = ph->prandtl;
+  c->ph.beta = ph->ldg_beta; c->ph.eta = ph->ldg_penalty;
+  c->stream = (hipStream_t)stream;
+  c->scheme = ph->scheme;
+  // block sizes and Jacobian-block offsets: per element its self block, then
+  // one block per local face (b_n x b_m, m the neighbour), packed
+  std::vector<int> bsz((size_t)ne);
+  for (int64_t e = 0; e < ne; ++e) bsz[e] = refs[m->elem_type[e]].ns * nv;
+  c->blk_off.assign((size_t)ne + 1, 0);
+  for (int64_t e = 0; e < ne; ++e) {
+    const frh::RefOps& R = refs[m->elem_type[e]];
+    int64_t n = (int64_t)bsz[e] * bsz[e];
+    for (int f = 0; f < R.nface; ++f) n += (int64_t)bsz[e] * bsz[m->nbr[e * m->max_face + f]];
+    c->blk_off[e + 1] = c->blk_off[e] + n;
+  }
+  int64_t dof = 0, fp = 0, sp = 0;
+  for (int g = 0; g < ngrp; ++g) {
+    const frh::RefOps& R = refs[m->elem_type[gs[g]]];
+    const int64_t ng = gs[g + 1] - gs[g];
+    c->grp_e0.push_back(gs[g]); c->grp_dof0.push_back(dof); c->grp_fp0.push_back(fp); c->grp_sp0.push_back(sp);
+    dof += ng * R.ns * nv; fp += ng * R.nf; sp += ng * R.ns;
+    c->ns = std::max(c->ns, R.ns); c->nf = std::max(c->nf, R.nf); c->nface = std::max(c->nface, R.nface);
+    c->nfp = R.nfp; c->b = std::max(c->b, R.ns * nv);
+  }
+  c->ndof = dof; c->nf_tot = fp; c->ns_tot = sp;
+  c->ks = KernelSet{};
+  c->ks.rhs = &mixed_rhs; c->ks.rhs_ws = &mixed_rhs_ws; c->ks.jvp = &mixed_jvp; c->ks.jac = &mixed_jac;
+  if (fr_status ws = alloc_work(c)) { release(c); return ws; }
+  for (int g = 0; g < ngrp; ++g) {
+    const int t = m->elem_type[gs[g]];
+    const frh::RefOps& R = refs[t];
+    const int64_t ng = gs[g + 1] - gs[g];
+    fr_ctx_s* s = new fr_ctx_s();
+    c->grp.push_back(s);
+    s->sub = true;
+    s->nd = 2; s->type = t; s->p = m->degree; s->system = ph->system; s->nv = nv; s->prec = prec; s->scheme = c->scheme;
+    s->ne = ng; s->ns = R.ns; s->nf = R.nf; s->nface = R.nface; s->nfp = R.nfp; s->b = R.ns * nv; s->visc = visc;
+    s->ph = c->ph; s->stream = c->stream; s->dev = c->dev; s->status = c->status;
+    s->ndof = ng * s->b; s->nf_tot = ng * R.nf; s->ns_tot = ng * R.ns;
+    if (!fr_find_kernels(t, m->degree, ph->system, prec, &s->ks)) {
+      release(c);
+      return fail(nullptr, FR_E_UNSUPPORTED, "no kernels for this element type / degree / system / precision");
+    }
+    if (fr_status us = upload_ops_geo(s, R, geo[g], prec, ph->ldg_beta)) { release(c); return us; }
+    // the group's slices of the shared workspaces
+    const size_t rs = (prec == FR_F64) ? 8 : 4, nvs = (size_t)nv, nds = 2;
+    const size_t fo = (size_t)c->grp_fp0[g] * nvs, so = (size_t)c->grp_sp0[g] * nds * nvs;
+    s->UF = (char*)c->UF + fo * rs;
+    s->Q = c->Q ? (char*)c->Q + so * rs : nullptr;
+    s->QF = c->QF ? (char*)c->QF + fo * nds * rs : nullptr;
+    s->UF64 = (char*)c->UF64 + fo * 8;
+    s->Q64 = c->Q64 ? (char*)c->Q64 + so * 8 : nullptr;
+    s->QF64 = c->QF64 ? (char*)c->QF64 + fo * nds * 8 : nullptr;
+    s->UFd = (char*)c->UFd + fo * 16;
+    s->Qd = c->Qd ? (char*)c->Qd + so * 16 : nullptr;
+    s->QFd = c->QFd ? (char*)c->QFd + fo * nds * 16 : nullptr;
+    // cross-type data and block offsets on the device
+    std::vector<long> boff((size_t)ng), fboff((size_t)ng * R.nface);
+    for (int64_t el = 0; el < ng; ++el) {
+      const int64_t e = gs[g] + el;
+      boff[el] = (long)c->blk_off[e];
+      long o = (long)c->blk_off[e] + (long)bsz[e] * bsz[e];
+      for (int f = 0; f < R.nface; ++f) {
+        fboff[el * R.nface + f] = o;
+        o += (long)bsz[e] * bsz[m->nbr[e * m->max_face + f]];
+      }
+    }
+    const size_t b0 = 0, b1 = (b0 + boff.size() * sizeof(long) + 255) & ~(size_t)255;
+    const size_t b2 = (b1 + fboff.size() * sizeof(long) + 255) & ~(size_t)255;
+    const size_t b3 = (b2 + mix[g].nbpt.size() * sizeof(int) + 255) & ~(size_t)255;
+    const size_t bt = b3 + mix[g].nbt.size() * sizeof(int);
+    if (hipMalloc(&s->mix_mem, bt) != hipSuccess) { release(c); return fail(nullptr, FR_E_NOMEM, "device allocation failed (mixed mesh)"); }
+    char* mm = (char*)s->mix_mem;
+    if (hipMemcpy(mm + b0, boff.data(), boff.size() * sizeof(long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mm + b1, fboff.data(), fboff.size() * sizeof(long), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mm + b2, mix[g].nbpt.data(), mix[g].nbpt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mm + b3, mix[g].nbt.data(), mix[g].nbt.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      release(c);
+      return fail(nullptr, FR_E_DEVICE, "upload failed (mixed mesh)");
+    }
+    s->geod.boff = (const long*)(mm + b0); s->geof.boff = (const long*)(mm + b0);
+    s->geod.e0 = (long)gs[g]; s->geof.e0 = (long)gs[g];
+    s->geod.status = c->status; s->geof.status = c->status;
+  }
+  for (int g = 0; g < ngrp; ++g) {
+    fr_ctx_s* s = c->grp[g];
+    char* mm = (char*)s->mix_mem;
+    const size_t ng = (size_t)s->ne;
+    const size_t b1 = (ng * sizeof(long) + 255) & ~(size_t)255;
+    const size_t b2 = (b1 + ng * s->nface * sizeof(long) + 255) & ~(size_t)255;
+    const size_t b3 = (b2 + ng * s->nf * sizeof(int) + 255) & ~(size_t)255;
+    const fr_ctx_s* o = c->grp[1 - g];
+    if (prec == FR_F64) set_mixd<double>(s, o, (const int*)(mm + b2), (const int*)(mm + b3), (const long*)(mm + b1));
+    else set_mixd<float>(s, o, (const int*)(mm + b2), (const int*)(mm + b3), (const long*)(mm + b1));
+  }
+  *out = c;
+  return FR_OK;
+}
+
 // ------------------------------------------------------------ ABI
 extern "C" {
 
@@ -188,10 +475,13 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   if (m->degree < 1 || m->degree > 4) return fail(nullptr, FR_E_UNSUPPORTED, "degree must be in 1..4");
   if (prec != FR_F64 && prec != FR_F32) return fail(nullptr, FR_E_UNSUPPORTED, "state precision must be FR_F64 or FR_F32");
   const int type = m->elem_type[0];
+  bool one_type = true;
+  for (int64_t e = 0; e < m->n_elem; ++e) {
+    if (m->elem_type[e] < 0 || m->elem_type[e] > 2) return fail(nullptr, FR_E_INVALID, "unknown element type");
+    if (m->elem_type[e] != type) one_type = false;
+  }
   for (int64_t e = 0; e < m->n_elem; ++e)
-    if (m->elem_type[e] != type) return fail(nullptr, FR_E_UNSUPPORTED, "one element type per context");
-  if (type < 0 || type > 2) return fail(nullptr, FR_E_INVALID, "unknown element type");
-  if ((type == FR_HEX) != (m->ndim == 3)) return fail(nullptr, FR_E_INVALID, "element type does not match ndim");
+    if ((m->elem_type[e] == FR_HEX) != (m->ndim == 3)) return fail(nullptr, FR_E_INVALID, "element type does not match ndim");
   if (ph->system < 0 || ph->system > 2) return fail(nullptr, FR_E_INVALID, "unknown system");
   const int nv = (ph->system == FR_ADVECTION) ? 1 : m->ndim + 2;
   if (ph->nvars != nv) return fail(nullptr, FR_E_INVALID, "nvars does not match the system");
@@ -203,6 +493,9 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     return fail(nullptr, FR_E_INVALID, "unknown scheme");
   if (ph->scheme != FR_SCHEME_FR_DG && type == FR_TRI)
     return fail(nullptr, FR_E_UNSUPPORTED, "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra");
+  if (!one_type)
+    return create_mixed(m, ph, prec, stream, nv,
+                        (ph->system == FR_NAVIER_STOKES) || (ph->system == FR_ADVECTION && ph->mu != 0.0), out);
 
   frh::RefOps ref;
   std::string err;
@@ -260,81 +553,16 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     c->ks.mf_bytes = nullptr;
     c->ks.mf_setup = nullptr;
   }
-  std::vector<char> ob, gb;
-  std::vector<size_t> oo, go;
-  // FP64 operators and geometry always (residual); FP32 copies for FP32 contexts
-  pack_ops<double>(ref, ob, oo); pack_geo<double>(geo, gb, go);
-  std::vector<size_t> oo32, go32;
-  if (prec == FR_F32) {
-    std::vector<char> o2, g2;
-    pack_ops<float>(ref, o2, oo32); pack_geo<float>(geo, g2, go32);
-    size_t obase = (ob.size() + 255) & ~(size_t)255, gbase = (gb.size() + 255) & ~(size_t)255;
-    ob.resize(obase + o2.size()); std::memcpy(ob.data() + obase, o2.data(), o2.size());
-    gb.resize(gbase + g2.size()); std::memcpy(gb.data() + gbase, g2.data(), g2.size());
-    for (auto& v : oo32) v += obase;
-    for (auto& v : go32) v += gbase;
-  }
-
-  if (hipMalloc(&c->ops_mem, ob.size()) != hipSuccess || hipMalloc(&c->geo_mem, gb.size()) != hipSuccess) {
+  if (fr_status us = upload_ops_geo(c, ref, geo, prec, ph->ldg_beta)) {
     release(c);
-    return fail(nullptr, FR_E_NOMEM, "device allocation failed (operators/geometry)");
+    return us;
   }
-  if (hipMemcpy(c->ops_mem, ob.data(), ob.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->geo_mem, gb.data(), gb.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  c->nf_tot = c->ne * c->nf;
+  c->ns_tot = c->ne * c->ns;
+  c->ndof = c->ne * (int64_t)c->b;
+  if (fr_status ws = alloc_work(c)) {
     release(c);
-    return fail(nullptr, FR_E_DEVICE, "upload failed");
-  }
-  if (type != FR_TRI) {
-    const double beta = ph->ldg_beta;
-    for (int i = 0; i <= m->degree; ++i) {
-      for (int j = 0; j <= m->degree; ++j) {
-        double d = ref.D1[i * (m->degree + 1) + j];
-        double cm = ref.hp[i] * ref.lp[j] - ref.hm[i] * ref.lm[j];
-        c->o1d.Dc1[i][j] = d - cm;
-        c->o1d.G1[i][j] = d - (0.5 + beta) * cm;
-        c->o1f.Dc1[i][j] = (float)(d - cm);
-        c->o1f.G1[i][j] = (float)(d - (0.5 + beta) * cm);
-      }
-      c->o1d.hp[i] = ref.hp[i]; c->o1d.hm[i] = ref.hm[i]; c->o1d.lp[i] = ref.lp[i]; c->o1d.lm[i] = ref.lm[i];
-      c->o1f.hp[i] = (float)ref.hp[i]; c->o1f.hm[i] = (float)ref.hm[i];
-      c->o1f.lp[i] = (float)ref.lp[i]; c->o1f.lm[i] = (float)ref.lm[i];
-    }
-  }
-  c->opsd = ops_view<double>((char*)c->ops_mem, oo);
-  c->geod = geo_view<double>((char*)c->geo_mem, go, (int)c->ne);
-  if (prec == FR_F32) {
-    c->opsf = ops_view<float>((char*)c->ops_mem, oo32);
-    c->geof = geo_view<float>((char*)c->geo_mem, go32, (int)c->ne);
-  }
-  // workspaces: traces / gradients for the Jacobian assembly (context
-  // precision), their FP64 dual versions for the JVP and FP64 ones for the
-  // residual (both evaluated in FP64 whatever the context precision)
-  const size_t rs = (prec == FR_F64) ? 8 : 4;
-  const size_t nuf = (size_t)c->ne * c->nf * nv, nq = (size_t)c->ne * c->ns * c->nd * nv, nqf = (size_t)c->ne * c->nf * c->nd * nv;
-  const bool f32 = prec == FR_F32;
-  size_t sizes[10] = {nuf * rs, visc ? nq * rs : 0, visc ? nqf * rs : 0,
-                      2 * nuf * 8, visc ? 2 * nq * 8 : 0, visc ? 2 * nqf * 8 : 0,
-                      f32 ? nuf * 8 : 0, (f32 && visc) ? nq * 8 : 0, (f32 && visc) ? nqf * 8 : 0,
-                      2 * sizeof(int)};
-  size_t off[10], tot = 0;
-  for (int i = 0; i < 10; ++i) { off[i] = tot; tot += (sizes[i] + 255) & ~(size_t)255; }
-  if (hipMalloc(&c->work_mem, tot) != hipSuccess) {
-    release(c);
-    return fail(nullptr, FR_E_NOMEM, "device allocation failed (workspaces)");
-  }
-  char* w = (char*)c->work_mem;
-  c->UF = w + off[0]; c->Q = w + off[1]; c->QF = w + off[2];
-  c->UFd = w + off[3]; c->Qd = w + off[4]; c->QFd = w + off[5];
-  if (f32) { c->UF64 = w + off[6]; c->Q64 = w + off[7]; c->QF64 = w + off[8]; }
-  else { c->UF64 = c->UF; c->Q64 = c->Q; c->QF64 = c->QF; }
-  c->status = (int*)(w + off[9]);
-  c->geod.status = c->status;
-  c->geof.status = c->status;
-  (void)hipGetDevice(&c->dev);
-  scratch_setup(c->dev);
-  if (fr_status_reset(c) != 0) {
-    release(c);
-    return fail(nullptr, FR_E_DEVICE, "status word initialisation failed");
+    return ws;
   }
   // matrix-core Jacobian: geometry-only sensitivities (computed here, once)
   // and the per-state tables
@@ -413,7 +641,7 @@ fr_status fr_ctx_destroy(fr_ctx* c) {
 fr_status fr_ctx_info(const fr_ctx* c, fr_info* info) {
   if (!c || !info) return FR_E_INVALID;
   info->ndim = c->nd; info->n_sol = c->ns; info->n_flux = c->nf; info->n_face = c->nface; info->nvars = c->nv;
-  info->block_dim = c->b; info->n_elem = c->ne; info->n_dof = c->ne * (int64_t)c->b;
+  info->block_dim = c->b; info->n_elem = c->ne; info->n_dof = c->ndof;
   info->blocks_per_elem = 1 + c->nface; info->precision = c->prec;
   return FR_OK;
 }
@@ -480,9 +708,9 @@ fr_status fr_rhs_noalloc(fr_ctx* c, const void* U, void* R) {
   if (U == R) return fail(c, FR_E_INVALID, "fr_rhs_noalloc: U and R must not alias");
   if (!c->ks.rhs_ws) return fail(c, FR_E_UNSUPPORTED, "fr_rhs_noalloc: not provided for SDRT contexts");
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t nuf = (size_t)c->ne * c->nf * c->nv * 8;
-  const size_t nq = c->visc ? (size_t)c->ne * c->ns * c->nd * c->nv * 8 : 0;
-  const size_t nqf = c->visc ? (size_t)c->ne * c->nf * c->nd * c->nv * 8 : 0;
+  const size_t nuf = (size_t)c->nf_tot * c->nv * 8;
+  const size_t nq = c->visc ? (size_t)c->ns_tot * c->nd * c->nv * 8 : 0;
+  const size_t nqf = c->visc ? (size_t)c->nf_tot * c->nd * c->nv * 8 : 0;
   const size_t need = up(nuf) + up(nq) + up(nqf);
   if (need > kScratchBytes)
     return fail(c, FR_E_UNSUPPORTED, "fr_rhs_noalloc: this mesh needs " + std::to_string(need) +
@@ -505,6 +733,17 @@ fr_status fr_jvp(fr_ctx* c, const void* U, const void* v, void* Jv, void* Rout) 
     return fail(c, FR_E_INVALID, "fr_jvp: outputs must not alias inputs");
   int rc = c->ks.jvp(c, U, v, Jv, Rout);
   return rc ? (fr_status)rc : FR_OK;
+}
+
+fr_status fr_block_offsets(const fr_ctx* c, int64_t* off) {
+  if (!c || !off) return FR_E_INVALID;
+  if (c->mixed) {
+    std::memcpy(off, c->blk_off.data(), c->blk_off.size() * sizeof(int64_t));
+  } else {
+    const int64_t per = (int64_t)(1 + c->nface) * c->b * c->b;
+    for (int64_t n = 0; n <= c->ne; ++n) off[n] = n * per;
+  }
+  return FR_OK;
 }
 
 fr_status fr_jacobian_blocks(fr_ctx* c, const void* U, void* blocks, fr_precision out_prec) {

@@ -425,6 +425,7 @@ fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out) {
     const char* why = nullptr;
     if (c->prec != 1) why = "batched meshes must be FP32 contexts";
     else if (c->scheme == 2) why = "batched meshes must be FR (FR-DG or FR-SDRT) contexts";
+    else if (c->mixed) why = "batched meshes must be single-type contexts";
     else if (c->nd != 2 || (c->type != ET_QUAD && c->type != ET_TRI)) why = "batched meshes must be 2-D triangles or quadrilaterals";
     else if (c->system != SYS_EULER && c->system != SYS_NS) why = "batched meshes must be Euler or Navier-Stokes";
     else if (i > 0 && c->system != ctxs[0]->system) why = "batched meshes must share one system";

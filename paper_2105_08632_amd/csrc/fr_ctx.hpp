@@ -22,6 +22,15 @@ struct KernelSet {
   // SDRT residual and its tangent (tensor elements; null for triangles)
   int (*rhs_sd)(fr_ctx_s*, const void* U, void* R);
   int (*jvp_sd)(fr_ctx_s*, const void* U, const void* V, void* Jv, void* Rv);
+  // one pass of the FR-DG residual (0 traces, 1 BR1 gradients, 2 divergence)
+  // in FP64 on the given workspaces; dual = 1 carries the tangent direction V
+  // (outputs: Rout = R, may be null; Rtan = Jv)
+  int (*phase)(fr_ctx_s*, int which, int dual, const void* U, const void* V, void* UF, void* Q, void* QF, void* Rout,
+               void* Rtan);
+  // element group of a mixed mesh, inviscid systems: stage 0 traces (context
+  // precision, into the group's UF), 1 self blocks, 2 face blocks; mix: a
+  // host MixD of the context precision (2-D types only, null otherwise)
+  int (*jac_mixed)(fr_ctx_s*, int stage, const void* U, void* B, int out_prec, const void* mix);
 };
 
 struct fr_ctx_s {
@@ -40,6 +49,17 @@ struct fr_ctx_s {
   void* work_mem = nullptr;
   int* status = nullptr;       // device [2]: kinds of non-finite outputs (FR_NF_*), smallest element
   std::vector<double> face_off;  // host [ne][nface][nd]: face centroid - element centroid
+  int64_t ndof = 0;            // state entries (sum of ns * nv over the elements)
+  int64_t nf_tot = 0, ns_tot = 0;   // flux and solution points of the whole mesh
+  // mixed meshes: one sub-context per element-type group (elements grouped
+  // by type), sharing this context's workspaces and status word
+  bool mixed = false, sub = false;
+  std::vector<fr_ctx_s*> grp;
+  std::vector<int64_t> grp_e0, grp_dof0, grp_fp0, grp_sp0;   // first element / state entry / flux / solution point
+  std::vector<int64_t> blk_off;     // [ne + 1] first Jacobian-block entry of each element
+  void* mix_mem = nullptr;          // group: MixInfo arrays and block offsets (device)
+  const void* mixd = nullptr;       // group: host MixD<context precision> for jac_mixed
+  void* mixd_host = nullptr;        // its storage
   int dev = 0;                 // device the context was created on
   OpsD<float> opsf{}; OpsD<double> opsd{};
   Ops1D<float> o1f{}; Ops1D<double> o1d{};

@@ -262,8 +262,8 @@ fr_status fr_fourier_eigs(fr_ctx* c, const void* blocks, int64_t elem, const dou
     c->err = "fr_fourier_eigs: null pointer or element / count out of range";
     return FR_E_INVALID;
   }
-  if (c->type == FR_TRI) {
-    c->err = "fr_fourier_eigs: triangle meshes are not translation-invariant element by element";
+  if (c->type == FR_TRI || c->mixed) {
+    c->err = "fr_fourier_eigs: meshes with triangles are not translation-invariant element by element";
     return FR_E_UNSUPPORTED;
   }
   if (c->b > kFB) {

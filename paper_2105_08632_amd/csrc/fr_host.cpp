@@ -509,63 +509,96 @@ void build_sd_metric(const RefOps& R, int nd, int64_t ne, const double* xyz, int
   }
 }
 
-bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
-                    const int8_t* nbr_face, int max_face, Geometry& G, std::string& err) {
-  const int ns = R.ns, nf = R.nf;
-  G.nd = nd; G.ns = ns; G.nf = nf; G.nface = R.nface; G.ne = ne;
-  G.S.assign((size_t)ne * ns * nd * nd, 0.0);
-  G.Jinv.assign((size_t)ne * ns * nd * nd, 0.0);
-  G.rdet.assign((size_t)ne * ns, 0.0);
-  G.nrm.assign((size_t)ne * nf * nd, 0.0);
-  G.magN.assign((size_t)ne * nf, 0.0);
-  G.nbfp.assign((size_t)ne * nf, -1);
-  G.nbr.assign((size_t)ne * R.nface, -1);
-  std::vector<double> fx((size_t)ne * nf * nd);
+bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const int8_t* etype, const double* xyz,
+                           int max_vert, const int64_t* nbr, const int8_t* nbr_face, int max_face, int ngrp,
+                           const int64_t* gstart, Geometry* G, MixInfo* mix, std::string& err) {
   char buf[256];
-  for (int64_t e = 0; e < ne; ++e) {
-    const double* X = xyz + (size_t)e * max_vert * nd;
-    double x[3], J[9], S[9];
-    for (int r = 0; r < ns; ++r) {
-      mapping(R, nd, X, &R.sp[r * nd], x, J);
-      double dj = adj(nd, J, S);
-      if (!(dj > 0.0)) {
-        std::snprintf(buf, sizeof buf, "element %lld: non-positive Jacobian determinant", (long long)e);
-        err = buf; return false;
-      }
-      size_t k = (size_t)e * ns + r;
-      G.rdet[k] = 1.0 / dj;
-      for (int i = 0; i < nd * nd; ++i) { G.S[k * nd * nd + i] = S[i]; G.Jinv[k * nd * nd + i] = S[i] / dj; }
+  // group of each element, and the first global flux point of each group
+  std::vector<int> grp((size_t)ne, -1);
+  std::vector<int64_t> fbase((size_t)ngrp + 1, 0);
+  for (int g = 0; g < ngrp; ++g) {
+    const RefOps& R = *refs[etype[gstart[g]]];
+    for (int64_t e = gstart[g]; e < gstart[g + 1]; ++e) {
+      if (etype[e] != etype[gstart[g]]) { err = "element types are not grouped"; return false; }
+      grp[e] = g;
     }
-    for (int g = 0; g < nf; ++g) {
-      mapping(R, nd, X, &R.fp[g * nd], x, J);
-      adj(nd, J, S);
-      double N[3] = {0, 0, 0}, mg = 0.0;
-      for (int i = 0; i < nd; ++i) {
-        for (int d = 0; d < nd; ++d) N[i] += S[d * nd + i] * R.nref[g * nd + d];
-        mg += N[i] * N[i];
+    fbase[g + 1] = fbase[g] + (gstart[g + 1] - gstart[g]) * R.nf;
+  }
+  if (fbase[ngrp] > ((int64_t)1 << 31) - 1) { err = "mesh too large for 32-bit face indices"; return false; }
+  auto ref_of = [&](int64_t e) -> const RefOps& { return *refs[etype[e]]; };
+  auto gfp = [&](int64_t e, int j) -> int64_t {   // global flux point index
+    const int g = grp[e];
+    return fbase[g] + (e - gstart[g]) * ref_of(e).nf + j;
+  };
+  // physical flux-point positions, global numbering
+  std::vector<double> fx((size_t)fbase[ngrp] * nd);
+  for (int g = 0; g < ngrp; ++g) {
+    const RefOps& R = *refs[etype[gstart[g]]];
+    const int64_t ng = gstart[g + 1] - gstart[g];
+    const int ns = R.ns, nf = R.nf;
+    Geometry& Gg = G[g];
+    Gg = Geometry();
+    Gg.nd = nd; Gg.ns = ns; Gg.nf = nf; Gg.nface = R.nface; Gg.ne = ng;
+    Gg.S.assign((size_t)ng * ns * nd * nd, 0.0);
+    Gg.Jinv.assign((size_t)ng * ns * nd * nd, 0.0);
+    Gg.rdet.assign((size_t)ng * ns, 0.0);
+    Gg.nrm.assign((size_t)ng * nf * nd, 0.0);
+    Gg.magN.assign((size_t)ng * nf, 0.0);
+    Gg.nbfp.assign((size_t)ng * nf, -1);
+    Gg.nbr.assign((size_t)ng * R.nface, -1);
+    for (int64_t el = 0; el < ng; ++el) {
+      const int64_t e = gstart[g] + el;
+      const double* X = xyz + (size_t)e * max_vert * nd;
+      double x[3], J[9], S[9];
+      for (int r = 0; r < ns; ++r) {
+        mapping(R, nd, X, &R.sp[r * nd], x, J);
+        double dj = adj(nd, J, S);
+        if (!(dj > 0.0)) {
+          std::snprintf(buf, sizeof buf, "element %lld: non-positive Jacobian determinant", (long long)e);
+          err = buf; return false;
+        }
+        size_t k = (size_t)el * ns + r;
+        Gg.rdet[k] = 1.0 / dj;
+        for (int i = 0; i < nd * nd; ++i) { Gg.S[k * nd * nd + i] = S[i]; Gg.Jinv[k * nd * nd + i] = S[i] / dj; }
       }
-      mg = std::sqrt(mg);
-      size_t k = (size_t)e * nf + g;
-      G.magN[k] = mg;
-      for (int i = 0; i < nd; ++i) { G.nrm[k * nd + i] = N[i] / mg; fx[k * nd + i] = x[i]; }
-    }
-    for (int f = 0; f < R.nface; ++f) {
-      int64_t m = nbr[e * max_face + f];
-      if (m < 0 || m >= ne) {
-        std::snprintf(buf, sizeof buf, "element %lld face %d: neighbour out of range", (long long)e, f);
-        err = buf; return false;
+      for (int j = 0; j < nf; ++j) {
+        mapping(R, nd, X, &R.fp[j * nd], x, J);
+        adj(nd, J, S);
+        double N[3] = {0, 0, 0}, mg = 0.0;
+        for (int i = 0; i < nd; ++i) {
+          for (int d = 0; d < nd; ++d) N[i] += S[d * nd + i] * R.nref[j * nd + d];
+          mg += N[i] * N[i];
+        }
+        mg = std::sqrt(mg);
+        size_t k = (size_t)el * nf + j;
+        Gg.magN[k] = mg;
+        for (int i = 0; i < nd; ++i) { Gg.nrm[k * nd + i] = N[i] / mg; fx[(size_t)gfp(e, j) * nd + i] = x[i]; }
       }
-      G.nbr[e * R.nface + f] = (int)m;
+      for (int f = 0; f < R.nface; ++f) {
+        int64_t m = nbr[e * max_face + f];
+        if (m < 0 || m >= ne) {
+          std::snprintf(buf, sizeof buf, "element %lld face %d: neighbour out of range", (long long)e, f);
+          err = buf; return false;
+        }
+        // group-local index when the neighbour shares the group, else the
+        // element itself (the kernels that read it run on single-type meshes)
+        Gg.nbr[el * R.nface + f] = grp[m] == g ? (int)(m - gstart[g]) : (int)el;
+      }
     }
   }
+  // flux-point pairing across faces by position relative to the face centroid
+  std::vector<int64_t> pair((size_t)fbase[ngrp], -1);
   for (int64_t e = 0; e < ne; ++e) {
+    const RefOps& R = ref_of(e);
     for (int f = 0; f < R.nface; ++f) {
       int64_t m = nbr[e * max_face + f];
+      const RefOps& Rm = ref_of(m);
       int f2 = nbr_face[e * max_face + f];
-      if (f2 < 0 || f2 >= R.nface) { err = "neighbour face index out of range"; return false; }
+      if (f2 < 0 || f2 >= Rm.nface) { err = "neighbour face index out of range"; return false; }
+      if (Rm.nfp != R.nfp) { err = "faces of different point counts meet"; return false; }
       double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0}, sz = 0.0;
       const std::vector<int>& v1 = R.face_verts[f];
-      const std::vector<int>& v2 = R.face_verts[f2];
+      const std::vector<int>& v2 = Rm.face_verts[f2];
       for (int v : v1)
         for (int i = 0; i < nd; ++i) c1[i] += xyz[((size_t)e * max_vert + v) * nd + i] / v1.size();
       for (int v : v2)
@@ -576,45 +609,89 @@ bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int 
       }
       sz = std::sqrt(sz);
       for (int a = 0; a < R.nfp; ++a) {
-        int g = f * R.nfp + a;
-        int best = -1; double bd = 1e300;
-        for (int b = 0; b < R.nfp; ++b) {
-          int g2 = f2 * R.nfp + b;
+        const int64_t ga = gfp(e, f * R.nfp + a);
+        int64_t best = -1; double bd = 1e300;
+        for (int b = 0; b < Rm.nfp; ++b) {
+          const int64_t gb = gfp(m, f2 * Rm.nfp + b);
           double d2 = 0.0;
           for (int i = 0; i < nd; ++i) {
-            double t = (fx[((size_t)e * nf + g) * nd + i] - c1[i]) - (fx[((size_t)m * nf + g2) * nd + i] - c2[i]);
+            double t = (fx[(size_t)ga * nd + i] - c1[i]) - (fx[(size_t)gb * nd + i] - c2[i]);
             d2 += t * t;
           }
-          if (d2 < bd) { bd = d2; best = g2; }
+          if (d2 < bd) { bd = d2; best = gb; }
         }
         if (std::sqrt(bd) > 1e-8 * sz) {
           std::snprintf(buf, sizeof buf, "element %lld face %d: neighbour face points do not coincide", (long long)e, f);
           err = buf; return false;
         }
-        G.nbfp[(size_t)e * nf + g] = (int)(m * nf + best);
+        pair[(size_t)ga] = best;
       }
     }
   }
   // the pairing must be an involution
-  for (int64_t e = 0; e < ne; ++e)
-    for (int g = 0; g < nf; ++g) {
-      int pg = G.nbfp[(size_t)e * nf + g];
-      if (G.nbfp[(size_t)pg] != (int)(e * nf + g)) { err = "face-point pairing is not symmetric"; return false; }
-    }
+  for (int64_t i = 0; i < fbase[ngrp]; ++i)
+    if (pair[(size_t)i] < 0 || pair[(size_t)pair[(size_t)i]] != i) { err = "face-point pairing is not symmetric"; return false; }
+  // per group: partner indices relative to the group's first flux point
+  // (negative or past the group for partners in other groups)
+  for (int g = 0; g < ngrp; ++g) {
+    const RefOps& R = *refs[etype[gstart[g]]];
+    const int64_t ng = gstart[g + 1] - gstart[g];
+    for (int64_t i = 0; i < ng * R.nf; ++i) G[g].nbfp[(size_t)i] = (int)(pair[(size_t)(fbase[g] + i)] - fbase[g]);
+  }
   // per face: the neighbour's local face index and, for each point of that
-  // neighbour face, the partner point in this element
-  G.nbface.assign((size_t)ne * R.nface, 0);
-  G.back.assign((size_t)ne * R.nface * R.nfp, 0);
-  for (int64_t e = 0; e < ne; ++e)
-    for (int f = 0; f < R.nface; ++f) {
-      int pg = G.nbfp[(size_t)e * nf + f * R.nfp];
-      int64_t m = pg / nf;
-      int f2 = R.fface[pg - m * nf];
-      G.nbface[e * R.nface + f] = f2;
-      for (int j = 0; j < R.nfp; ++j)
-        G.back[((size_t)e * R.nface + f) * R.nfp + j] = (int)(G.nbfp[(size_t)m * nf + f2 * R.nfp + j] - e * nf);
+  // neighbour face, the partner point in this element (single groups: used by
+  // the viscous Jacobian paths)
+  for (int g = 0; g < ngrp; ++g) {
+    const RefOps& R = *refs[etype[gstart[g]]];
+    const int64_t ng = gstart[g + 1] - gstart[g];
+    const int nf = R.nf;
+    G[g].nbface.assign((size_t)ng * R.nface, 0);
+    G[g].back.assign((size_t)ng * R.nface * R.nfp, 0);
+    if (ngrp == 1)
+      for (int64_t e = 0; e < ng; ++e)
+        for (int f = 0; f < R.nface; ++f) {
+          int pg = G[g].nbfp[(size_t)e * nf + f * R.nfp];
+          int64_t m = pg / nf;
+          int f2 = R.fface[pg - m * nf];
+          G[g].nbface[e * R.nface + f] = f2;
+          for (int j = 0; j < R.nfp; ++j)
+            G[g].back[((size_t)e * R.nface + f) * R.nfp + j] = (int)(G[g].nbfp[(size_t)m * nf + f2 * R.nfp + j] - e * nf);
+        }
+  }
+  if (mix) {
+    for (int g = 0; g < ngrp; ++g) {
+      const int gt = etype[gstart[g]];
+      const RefOps& R = *refs[gt];
+      const int64_t ng = gstart[g + 1] - gstart[g];
+      MixInfo& M = mix[g];
+      M.nbpt.assign((size_t)ng * R.nf, 0);
+      M.nbt.assign((size_t)ng * R.nface, 0);
+      M.nbg.assign((size_t)ng * R.nface, 0);
+      for (int64_t el = 0; el < ng; ++el) {
+        const int64_t e = gstart[g] + el;
+        for (int f = 0; f < R.nface; ++f) {
+          const int64_t m = nbr[e * max_face + f];
+          M.nbg[el * R.nface + f] = m;
+          M.nbt[el * R.nface + f] = etype[m] != gt ? 1 : 0;
+          for (int a = 0; a < R.nfp; ++a) {
+            const int j = f * R.nfp + a;
+            const int64_t pg = pair[(size_t)gfp(e, j)];
+            M.nbpt[(size_t)el * R.nf + j] = (int)(pg - gfp(m, 0));
+          }
+        }
+      }
     }
+  }
   return true;
+}
+
+bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
+                    const int8_t* nbr_face, int max_face, Geometry& G, std::string& err) {
+  const RefOps* refs[3] = {&R, &R, &R};
+  std::vector<int8_t> et((size_t)ne, (int8_t)R.type);
+  const int64_t gs[2] = {0, ne};
+  return build_geometry_groups(refs, nd, ne, et.data(), xyz, max_vert, nbr, nbr_face, max_face, 1, gs, &G, nullptr,
+                               err);
 }
 
 bool check_stencil(int64_t ne, int nface, const int* nbr, std::string& err) {

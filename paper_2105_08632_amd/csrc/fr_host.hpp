@@ -58,6 +58,24 @@ struct Geometry {
 bool build_geometry(const RefOps& ref, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
                     const int8_t* nbr_face, int max_face, Geometry& g, std::string& err);
 
+// Cross-type face data of one element group of a mixed mesh.
+struct MixInfo {
+  std::vector<int> nbpt;              // [ne_g][nf]: the paired point's local index in the neighbour
+  std::vector<int> nbt;               // [ne_g][nface]: 1 when the neighbour is of the other type
+  std::vector<int64_t> nbg;           // [ne_g][nface]: the neighbour's mesh index
+};
+
+// The same over ngrp contiguous groups of one element type each (elements
+// gstart[g] .. gstart[g+1]-1; refs indexed by element type).  Each group's
+// arrays are group-local; nbfp holds the partner's index in a flux-point
+// numbering that runs over the groups in order, minus the group's first
+// point (so a kernel given the group's slice of a shared trace array reads
+// partners in other groups at negative or past-the-end offsets).  mix (may
+// be null) receives the cross-type data per group.
+bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const int8_t* etype, const double* xyz,
+                           int max_vert, const int64_t* nbr, const int8_t* nbr_face, int max_face, int ngrp,
+                           const int64_t* gstart, Geometry* g, MixInfo* mix, std::string& err);
+
 // Checks the truncated viscous Jacobian's assumptions: distinct face
 // neighbours and a second face layer that does not fold back onto the first.
 bool check_stencil(int64_t ne, int nface, const int* nbr, std::string& err);

@@ -54,6 +54,21 @@ __global__ void __launch_bounds__((jac_tp_threads<E, NV, SYS, R>())) k_jac_tp(Op
                                  DevSync());
 }
 
+template <class E, int NV, int SYS, class R, class OT>
+__global__ void __launch_bounds__(kThreads) k_jac_self_inv(OpsD<R> op, GeoD<R> geo, PhysP ph, const R* U, const R* UF,
+                                                           OT* B) {
+  __shared__ __align__(16) char lds[jac_self_inv_lds<E, NV, R>()];
+  jac_self_inv_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, UF, B, DevSync());
+}
+
+template <class E, class EO, int NV, int SYS, class R, class OT>
+__global__ void __launch_bounds__(kThreads) k_jac_nb_mixed(OpsD<R> op, GeoD<R> geo, MixD<R> mx, PhysP ph, const R* UF,
+                                                           OT* B) {
+  __shared__ __align__(16) char lds[jac_nb_mixed_lds<E, EO, NV, R>()];
+  jac_nb_mixed_body<E, EO, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, mx, ph, UF, B,
+                                           DevSync());
+}
+
 // Matrix-core Jacobian (tensor-product elements, FP32): sensitivities once
 // per mesh, tables per state, then one wavefront per (element, block, tile).
 template <class E, int NV, int SYS, class R>
@@ -195,6 +210,78 @@ template <int ET, int P, int SYS, class R> struct Impl {
                                              (Dual<double>*)c->Qd, (Dual<double>*)c->QFd, (R*)Rv, (R*)Jv);
   }
 
+  // One residual pass of an element group (mixed meshes run each pass over
+  // every group before the next: the passes read the neighbours' traces).
+  template <class T, class IO>
+  static int phase_t(fr_ctx_s* c, int which, const IO* U, const IO* V, T* UF, T* Q, T* QF, IO* Rout, IO* Rtan) {
+    OpsD<double> op = ctx_ops<double>(c);
+    GeoD<double> geo = ctx_geo<double>(c);
+    const int ne = (int)c->ne;
+    if (ne == 0) return 0;
+    const int TE = rhs_tile<E>();
+    const int nt = (ne + TE - 1) / TE;
+    if (which == 0) {
+      hipLaunchKernelGGL((k_trace<E, NV, T, double, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
+    } else if (which == 1) {
+      if (!c->visc) return 0;
+      hipLaunchKernelGGL((k_grad<E, NV, T, double, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta,
+                         U, V, (const T*)UF, Q, QF);
+    } else {
+      hipLaunchKernelGGL((k_div<E, NV, SYS, T, double, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph,
+                         U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan);
+    }
+    FR_LAUNCH_CHECK(c);
+    return 0;
+  }
+  static int phase(fr_ctx_s* c, int which, int dual, const void* U, const void* V, void* UF, void* Q, void* QF,
+                   void* Rout, void* Rtan) {
+    if (dual)
+      return phase_t<Dual<double>, R>(c, which, (const R*)U, (const R*)V, (Dual<double>*)UF, (Dual<double>*)Q,
+                                      (Dual<double>*)QF, (R*)Rout, (R*)Rtan);
+    return phase_t<double, R>(c, which, (const R*)U, (const R*)nullptr, (double*)UF, (double*)Q, (double*)QF,
+                              (R*)Rout, (R*)nullptr);
+  }
+
+  // Jacobian blocks of an element group of a mixed 2-D mesh (inviscid).
+  static constexpr bool kMixedJac = ET != ET_HEX && SYS != SYS_NS;
+  template <class OT> static int jac_mixed_t(fr_ctx_s* c, int stage, const R* U, OT* B, const MixD<R>* mx) {
+    if constexpr (!kMixedJac) {
+      c->err = "Jacobian blocks of mixed meshes: 2-D inviscid systems only";
+      return -2;
+    } else {
+      typedef Elem<(ET == ET_TRI ? ET_QUAD : ET_TRI), P> EO;
+      if (c->visc) { c->err = "Jacobian blocks of mixed meshes: inviscid systems only"; return -2; }
+      const int ne = (int)c->ne;
+      if (ne == 0) return 0;
+      OpsD<R> op = ctx_ops<R>(c);
+      GeoD<R> geo = ctx_geo<R>(c);
+      if (stage == 0) {
+        const int TE = rhs_tile<E>();
+        hipLaunchKernelGGL((k_trace<E, NV, R, R, R>), dim3((ne + TE - 1) / TE), dim3(kThreads), 0, c->stream, op, ne,
+                           U, (const R*)nullptr, (R*)c->UF);
+      } else if (stage == 1) {
+        hipLaunchKernelGGL((k_jac_self_inv<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo,
+                           c->ph, U, (const R*)c->UF, B);
+      } else {
+        hipLaunchKernelGGL((k_jac_nb_mixed<E, EO, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo,
+                           *mx, c->ph, (const R*)c->UF, B);
+      }
+      FR_LAUNCH_CHECK(c);
+      return 0;
+    }
+  }
+  static int jac_mixed(fr_ctx_s* c, int stage, const void* U, void* B, int out_prec, const void* mix) {
+    const MixD<R>* mx = (const MixD<R>*)mix;
+    if constexpr (std::is_same<R, double>::value) {
+      if (out_prec == 0) return jac_mixed_t<double>(c, stage, (const R*)U, (double*)B, mx);
+    } else {
+      if (out_prec == 1) return jac_mixed_t<float>(c, stage, (const R*)U, (float*)B, mx);
+      if (out_prec == 2) return jac_mixed_t<bf16_t>(c, stage, (const R*)U, (bf16_t*)B, mx);
+    }
+    c->err = "unsupported block precision for this context precision";
+    return -2;
+  }
+
   static constexpr bool kTensorPath = (ET != ET_TRI) && (jac_tp_lds<E, NV, SYS, R>() <= kMaxLds);
   // matrix-core path: FP32 quadrilaterals and hexahedra
   static constexpr bool kMfmaPath = (ET != ET_TRI) && std::is_same<R, float>::value &&
@@ -282,6 +369,6 @@ template <int ET, int P, int SYS, class R> struct Impl {
 
   static KernelSet set() {
     return KernelSet{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup, ET == ET_TRI ? nullptr : &rhs_sd,
-                     ET == ET_TRI ? nullptr : &jvp_sd};
+                     ET == ET_TRI ? nullptr : &jvp_sd, &phase, ET == ET_HEX ? nullptr : &jac_mixed};
   }
 };

@@ -450,7 +450,7 @@ __device__ void jac_mf_tables_body(int n, int tid, int nth, char* lds, const Geo
       }
     sync();
   }
-  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, nl);
+  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + nl);
 }
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).

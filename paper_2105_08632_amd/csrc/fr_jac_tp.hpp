@@ -525,7 +525,7 @@ FR_HD void jac_tp_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, co
   bool bad = false;
   for (int item = tid; item < nitems; item += nth)
     bad |= jac_tp_task<E, NV, SYS, R, OT>(item, kb, o1, srd, tb, tf, gam, slr, Bn);
-  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, nl);
+  if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + nl);
   sync();
   }
 }

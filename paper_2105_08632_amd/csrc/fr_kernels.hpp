@@ -73,6 +73,8 @@ template <class R> struct GeoD {
   const int* back;    // [ne][NFACE][NFP] this element's point paired with each point of that neighbour face
   int* status;        // [2] non-finite output report (device): [0] kinds, [1] smallest element
   const R* Sint;      // SDRT: [ne][ND][NL][p][ND] row d of detJ J^{-1} at the interior flux points of d-lines
+  const long* boff;   // mixed meshes: [ne] first block entry of each element (null: element stride nblk b^2)
+  long e0;            // mesh index of the group's first element (reports of non-finite values)
 };
 
 // Kinds of output a non-finite value was stored to.
@@ -322,12 +324,12 @@ FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, co
     long o = (n * NS + r) * NV + a;
     if (Rout) {
       Rout[o] = IO(val(res));
-      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, n);
+      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, geo.e0 + n);
     }
     if constexpr (!std::is_same<T, R>::value) {
       if (Rtan) {
         Rtan[o] = IO(res.d);
-        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, n);
+        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, geo.e0 + n);
       }
     }
   }
@@ -468,12 +470,12 @@ FR_HD void sd_div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op,
     const long o = (n * NS + r) * NV + a;
     if (Rout) {
       Rout[o] = IO(val(res));
-      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, n);
+      if (!fr_finite(val(res))) fr_flag_nonfinite(geo.status, FR_NF_RHS, geo.e0 + n);
     }
     if constexpr (!std::is_same<T, R>::value) {
       if (Rtan) {
         Rtan[o] = IO(res.d);
-        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, n);
+        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, geo.e0 + n);
       }
     }
   }
@@ -648,16 +650,20 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
       sqL[i] = QF[(nl * NF + g) * ND * NV + r];
       sqR[i] = QF[(long)spg[g] * ND * NV + r];
     }
-  for (int i = tid; i < NFACE; i += nth) snf[i] = sff[spg[i * NFP] - snb[i] * NF];
-  for (int i = tid; i < NFACE * NS * ND * ND; i += nth) {
-    int f = i / (NS * ND * ND), r = i % (NS * ND * ND);
-    sJm[i] = geo.Jinv[(long)snb[f] * NS * ND * ND + r];
+  // the neighbours' faces, metric and pairing enter the viscous blocks only
+  if (visc) {
+    for (int i = tid; i < NFACE; i += nth) snf[i] = sff[spg[i * NFP] - snb[i] * NF];
+    for (int i = tid; i < NFACE * NS * ND * ND; i += nth) {
+      int f = i / (NS * ND * ND), r = i % (NS * ND * ND);
+      sJm[i] = geo.Jinv[(long)snb[f] * NS * ND * ND + r];
+    }
   }
   sync();
-  for (int i = tid; i < NFACE * NFP; i += nth) {
-    int f = i / NFP, gj = i % NFP;
-    sback[i] = geo.nbfp[(long)snb[f] * NF + snf[f] * NFP + gj] - n * NF;
-  }
+  if (visc)
+    for (int i = tid; i < NFACE * NFP; i += nth) {
+      int f = i / NFP, gj = i % NFP;
+      sback[i] = geo.nbfp[(long)snb[f] * NF + snf[f] * NFP + gj] - n * NF;
+    }
   // W_d'[f][g][g'] for the neighbour gradient's dependence on u_n (self block):
   // sum_tau' M0[g2][tau'] Cor[tau'][g'] sum_e Jinv_m[tau'][e][d'] nref[g'][e],
   // g on face f, g2 its partner in m, g' on the shared face f2 of m.
@@ -892,9 +898,187 @@ FR_HD void jac_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const
         for (int w = 0; w < WC; ++w) acc += crv[r * WC + w] * Y[(a * NF + crc[r * WC + w]) * NS + s];
         const R jv = -(srd[r] * acc);
         Bk[(long)(s * NV + beta) * BB + r * NV + a] = to_out<OT>(jv);
-        if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, n);
+        if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + n);
       }
       sync();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- mixed meshes
+// Face-neighbour blocks of an inviscid system on a conforming mesh that mixes
+// element types: element n (type E) and its neighbour m across face f (type
+// E or EO) meet only through the common flux at the face's points, so
+//   dR_n(rho, alpha) / dU_m(sigma, beta) =
+//     -(1/detJ_rho) sum_{g on f} Cor[rho][g] |N_g| dF_alpha/du_R,beta (g) M0_m[g'][sigma]
+// with g' the point of m paired with g (eq. "divergence_fr"; the neighbour's
+// trace u_R(g) = M0_m u_m, eq. "interpolate_sol_to_flux").  The block is
+// b_n x b_m (rows rho*NV+alpha, columns sigma*NV+beta, column-major) at
+// fboff[n][f].
+template <class R> struct MixD {
+  const int* nbpt;    // [ne][NF]: the paired point's local index in the neighbour
+  const int* nbt;     // [ne][NFACE]: 1 when the neighbour is of the other type
+  const long* fboff;  // [ne][NFACE]: first entry of each face block
+  const R* M0o;       // [NFo][NSo]: the other type's solution-to-flux-point interpolation
+};
+
+// Self blocks of an inviscid system, written at geo.boff[n]:
+//   dR_n(rho, alpha) / dU_n(sigma, beta) = -(1/detJ_rho) [ sum_d Dc_d[rho][sigma] A_d(sigma)
+//       + sum_g Cor[rho][g] |N_g| dF/du_L (g) M0[g][sigma] ]_{alpha beta}
+// with A_d = sum_k S_dk df_k/du (eq. "transformed_quantities") and Dc_d =
+// D_d - Cor diag(nref_d) M0 (the flux's own trace leaves through the
+// correction, eq. "divergence_fr").
+template <class E, int NV, class R> constexpr int jac_self_inv_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, NV2 = NV * NV;
+  return lds_bytes<R>(ND * NS * NV2) + lds_bytes<R>(NF * NV2) + lds_bytes<R>(NF * NS) + lds_bytes<int>(ND * NS * WL) +
+         lds_bytes<R>(ND * NS * WL) + lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NS) +
+         lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS * NV) + 2 * lds_bytes<R>(NF * NV) + lds_bytes<R>(NF * ND) +
+         lds_bytes<R>(NF);
+}
+
+template <class E, int NV, int SYS, class R, class OT, class Sync>
+FR_HD void jac_self_inv_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo,
+                             const PhysP& ph, const R* U, const R* UF, OT* B, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, NV2 = NV * NV, BB = NS * NV;
+  typedef MDual<R, NV> MD;
+  Lds L{lds};
+  R* ta = L.take<R>(ND * NS * NV2);     // A_d(sigma)[alpha][beta]
+  R* tL = L.take<R>(NF * NV2);          // |N_g| dF/du_L (g)
+  R* sM0 = L.take<R>(NF * NS);
+  int* dcc = L.take<int>(ND * NS * WL);
+  R* dcv = L.take<R>(ND * NS * WL);
+  int* crc = L.take<int>(NS * WC);
+  R* crv = L.take<R>(NS * WC);
+  R* srd = L.take<R>(NS);
+  R* sS = L.take<R>(NS * ND * ND);
+  R* su = L.take<R>(NS * NV);
+  R* suL = L.take<R>(NF * NV);
+  R* suR = L.take<R>(NF * NV);
+  R* snn = L.take<R>(NF * ND);
+  R* smg = L.take<R>(NF);
+  const long nl = n;
+  for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
+  for (int i = tid; i < ND * NS * WL; i += nth) { dcc[i] = op.dcc[i]; dcv[i] = op.dcv[i]; }
+  for (int i = tid; i < NS * WC; i += nth) { crc[i] = op.crc[i]; crv[i] = op.crv[i]; }
+  for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
+  for (int i = tid; i < NS * ND * ND; i += nth) sS[i] = geo.S[nl * NS * ND * ND + i];
+  for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
+  for (int i = tid; i < NF * NV; i += nth) {
+    const int g = i / NV, a = i % NV;
+    suL[i] = UF[(nl * NF + g) * NV + a];
+    suR[i] = UF[(long)geo.nbfp[nl * NF + g] * NV + a];
+  }
+  for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
+  for (int i = tid; i < NF; i += nth) smg[i] = geo.magN[nl * NF + i];
+  sync();
+  for (int it = tid; it < NS + NF; it += nth) {
+    if (it < NS) {
+      const int t = it;
+      MD u[NV], f[ND][NV];
+      for (int a = 0; a < NV; ++a) { u[a] = MD(su[t * NV + a]); u[a].d[a] = R(1); }
+      flux_inviscid<SYS, ND, NV, MD>(ph, u, f);
+      for (int d = 0; d < ND; ++d)
+        for (int a = 0; a < NV; ++a)
+          for (int c = 0; c < NV; ++c) {
+            R acc = R(0);
+            for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d[c];
+            ta[(d * NS + t) * NV2 + a * NV + c] = acc;
+          }
+    } else {
+      const int g = it - NS;
+      R nn[ND];
+      for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
+      MD uL[NV], uR[NV], F[NV];
+      for (int a = 0; a < NV; ++a) {
+        uL[a] = MD(suL[g * NV + a]);
+        uR[a] = MD(suR[g * NV + a]);
+        uL[a].d[a] = R(1);
+      }
+      common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
+      for (int a = 0; a < NV; ++a)
+        for (int c = 0; c < NV; ++c) tL[g * NV2 + a * NV + c] = smg[g] * F[a].d[c];
+    }
+  }
+  sync();
+  OT* Bn = B + geo.boff[nl];
+  for (int i = tid; i < BB * BB; i += nth) {
+    const int col = i / BB, row = i % BB;
+    const int s = col / NV, beta = col % NV, r = row / NV, a = row % NV;
+    const int ab = a * NV + beta;
+    R acc = R(0);
+    for (int d = 0; d < ND; ++d)
+      for (int w = 0; w < WL; ++w)
+        if (dcc[(d * NS + r) * WL + w] == s) acc += dcv[(d * NS + r) * WL + w] * ta[(d * NS + s) * NV2 + ab];
+    for (int w = 0; w < WC; ++w) {
+      const int g = crc[r * WC + w];
+      acc += crv[r * WC + w] * tL[g * NV2 + ab] * sM0[g * NS + s];
+    }
+    const R jv = -(srd[r] * acc);
+    Bn[i] = to_out<OT>(jv);
+    if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + n);
+  }
+}
+
+template <class E, class EO, int NV, class R> constexpr int jac_nb_mixed_lds() {
+  return lds_bytes<R>(E::NS * E::NF) + lds_bytes<R>(E::NF * E::NS) + lds_bytes<R>(EO::NF * EO::NS) +
+         lds_bytes<R>(E::NS) + lds_bytes<R>(E::NF * NV * NV) + lds_bytes<int>(E::NF) + lds_bytes<int>(E::NFACE);
+}
+
+template <class E, class EO, int NV, int SYS, class R, class OT, class Sync>
+FR_HD void jac_nb_mixed_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo,
+                             const MixD<R>& mx, const PhysP& ph, const R* UF, OT* B, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, NFP = E::NFP, NV2 = NV * NV;
+  constexpr int NSO = EO::NS, NFO = EO::NF;
+  constexpr int BB = NS * NV;
+  typedef MDual<R, NV> MD;
+  Lds L{lds};
+  R* sCor = L.take<R>(NS * NF);
+  R* sM0 = L.take<R>(NF * NS);
+  R* sM0o = L.take<R>(NFO * NSO);
+  R* srd = L.take<R>(NS);
+  R* tR = L.take<R>(NF * NV2);       // |N_g| dF/du_R at each flux point
+  int* spt = L.take<int>(NF);
+  int* snt = L.take<int>(NFACE);
+  const long nl = n;
+  for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
+  for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
+  for (int i = tid; i < NFO * NSO; i += nth) sM0o[i] = mx.M0o[i];
+  for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
+  for (int i = tid; i < NF; i += nth) spt[i] = mx.nbpt[nl * NF + i];
+  for (int i = tid; i < NFACE; i += nth) snt[i] = mx.nbt[nl * NFACE + i];
+  for (int g = tid; g < NF; g += nth) {
+    const long pg = geo.nbfp[nl * NF + g];
+    R nn[ND];
+    for (int d = 0; d < ND; ++d) nn[d] = geo.nrm[(nl * NF + g) * ND + d];
+    MD uL[NV], uR[NV], F[NV];
+    for (int a = 0; a < NV; ++a) {
+      uL[a] = MD(UF[(nl * NF + g) * NV + a]);
+      uR[a] = MD(UF[pg * NV + a]);
+      uR[a].d[a] = R(1);
+    }
+    common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
+    const R mg = geo.magN[nl * NF + g];
+    for (int a = 0; a < NV; ++a)
+      for (int c = 0; c < NV; ++c) tR[g * NV2 + a * NV + c] = mg * F[a].d[c];
+  }
+  sync();
+  for (int f = 0; f < NFACE; ++f) {
+    const bool other = snt[f] != 0;
+    const int nsm = other ? NSO : NS;
+    const R* M0m = other ? sM0o : sM0;
+    const int bm = nsm * NV;
+    OT* Bk = B + mx.fboff[nl * NFACE + f];
+    for (int i = tid; i < BB * bm; i += nth) {
+      const int col = i / BB, row = i % BB;
+      const int s = col / NV, beta = col % NV, r = row / NV, a = row % NV;
+      R acc = R(0);
+      for (int gi = 0; gi < NFP; ++gi) {
+        const int g = f * NFP + gi;
+        acc += sCor[r * NF + g] * tR[g * NV2 + a * NV + beta] * M0m[spt[g] * nsm + s];
+      }
+      const R jv = -(srd[r] * acc);
+      Bk[i] = to_out<OT>(jv);
+      if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + n);
     }
   }
 }

@@ -45,7 +45,7 @@ fr_status fr_rk54(fr_ctx* c, void* U, void* work, double dt, int64_t nsteps) {
     c->err = "fr_rk54: null or misaligned pointer, negative step count or NaN time step";
     return FR_E_INVALID;
   }
-  const long n = (long)c->ne * c->b;
+  const long n = (long)c->ndof;
   char* R = (char*)work;
   char* dU = R + (size_t)n * a;
   if ((char*)U >= R && (char*)U < R + 2 * (size_t)n * a) {

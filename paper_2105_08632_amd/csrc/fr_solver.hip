@@ -1002,6 +1002,7 @@ fr_status fr_precond_create(fr_ctx* c, fr_pc_kind kind, fr_precond** out) {
   *out = nullptr;
   if (kind != FR_PC_BLOCK_JACOBI && kind != FR_PC_MLP) return sfail(c, FR_E_INVALID, "unknown preconditioner kind");
   if (!c->ks.jac) return sfail(c, FR_E_UNSUPPORTED, "block preconditioners need Jacobian blocks (not for SDRT contexts)");
+  if (c->mixed) return sfail(c, FR_E_UNSUPPORTED, "block preconditioners need one block size (not for mixed meshes)");
   if (c->b > kLuMaxB) return sfail(c, FR_E_UNSUPPORTED, "block-Jacobi preconditioner supports blocks up to 320 x 320");
   if (kind == FR_PC_MLP && c->b > 64) return sfail(c, FR_E_UNSUPPORTED, "learned preconditioner blocks up to 64 x 64");
   fr_precond_s* pc = new fr_precond_s();
@@ -1055,6 +1056,7 @@ fr_status fr_precond_destroy(fr_precond* pc) {
 fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
   if (!c || !out || restart < 1 || restart > 31) return FR_E_INVALID;
   if (c->prec != 0) return sfail(c, FR_E_UNSUPPORTED, "Newton-GMRES runs on FP64 contexts");
+  if (c->mixed) return sfail(c, FR_E_UNSUPPORTED, "Newton-GMRES runs on single-type meshes");
   fr_solver_s* s = new fr_solver_s();
   s->ctx = c; s->m = restart; s->N = c->ne * (long)c->b;
   const long N = s->N;

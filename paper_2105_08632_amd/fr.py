@@ -21,7 +21,7 @@ _STATUS = {0: "FR_OK", -1: "FR_E_INVALID", -2: "FR_E_UNSUPPORTED", -3: "FR_E_NOM
            -5: "FR_E_SINGULAR", -6: "FR_E_NOT_CONVERGED", -7: "FR_E_NONFINITE"}
 
 EXPORTED = ["fr_ctx_create", "fr_ctx_destroy", "fr_ctx_info", "fr_last_error", "fr_ctx_sync", "fr_rhs", "fr_rhs_noalloc",
-            "fr_jacobian_blocks", "fr_jvp", "fr_set_kernel_timing", "fr_kernel_time"]
+            "fr_jacobian_blocks", "fr_block_offsets", "fr_jvp", "fr_set_kernel_timing", "fr_kernel_time"]
 
 
 class FrError(RuntimeError):
@@ -69,6 +69,7 @@ def lib():
         L.fr_rhs.argtypes = [P, P, P]
         L.fr_rhs_noalloc.argtypes = [P, P, P]
         L.fr_jacobian_blocks.argtypes = [P, P, P, C.c_int]
+        L.fr_block_offsets.argtypes = [P, P]
         L.fr_jvp.argtypes = [P, P, P, P, P]
         L.fr_set_kernel_timing.argtypes = [P, C.c_int]
         L.fr_kernel_time.argtypes = [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -131,6 +132,10 @@ class Context:
         self.info = info
         self.ns, self.nf, self.nface = info.n_sol, info.n_flux, info.n_face
         self.nv, self.b, self.ne, self.ndof = info.nvars, info.block_dim, info.n_elem, info.n_dof
+        self.mixed = bool(np.any(self._keep[0] != self._keep[0][0]))
+        off = np.zeros(self.ne + 1, dtype=np.int64)
+        _check(L.fr_block_offsets(h, off.ctypes.data), h)
+        self.block_offsets = off
 
     def close(self):
         if getattr(self, "h", None) is not None and _lib is not None:
@@ -150,6 +155,8 @@ class Context:
 
     def empty_state(self):
         import torch
+        if self.mixed:      # element n's entries follow those of elements 0..n-1
+            return torch.empty(self.ndof, dtype=self.dtype, device="cuda")
         return torch.empty(self.ne, self.ns, self.nv, dtype=self.dtype, device="cuda")
 
     def rhs(self, U, out=None):
@@ -174,7 +181,30 @@ class Context:
     def block_tensor(self, out_prec: str):
         import torch
         dt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[out_prec]
+        if self.mixed:      # packed blocks, element n's from block_offsets[n]
+            return torch.empty(int(self.block_offsets[-1]), dtype=dt, device="cuda")
         return torch.empty(self.ne, 1 + self.nface, self.b, self.b, dtype=dt, device="cuda")
+
+    def block(self, blocks, n: int, slot: int):
+        """Block `slot` of element n (0: self, 1+f: the neighbour across face
+        f) of a fr_jacobian_blocks array, as a [b_m, b_n] view (column-major
+        block: index [c][r])."""
+        if not self.mixed:
+            return blocks[n, slot]
+        p = int(self.mesh.degree[0])
+        ns = {0: (p + 1) ** 2, 1: (p + 1) * (p + 2) // 2}
+        et = self._keep[0]
+        bn = ns[int(et[n])] * self.nv
+        o = int(self.block_offsets[n])
+        if slot == 0:
+            return blocks[o:o + bn * bn].view(bn, bn)
+        o += bn * bn
+        for f in range(slot):
+            m = int(self.mesh.nbr[n, f])
+            bm = ns[int(et[m])] * self.nv
+            if f == slot - 1:
+                return blocks[o:o + bn * bm].view(bm, bn)
+            o += bn * bm
 
     def jacobian_blocks(self, U, out=None, out_prec: str | None = None):
         """Blocks [n, slot, c, r] (each block column-major: index [c][r])."""

@@ -166,6 +166,61 @@ def tri_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0), degree: int = 1,
     return Mesh(2, np.full(n, TRI, np.int8), np.full(n, degree, np.int8), xyz, nbr, nbr_face, h)
 
 
+def mixed_mesh(N: int, frac: float = 0.5, L: float = 1.0, origin=(0.0, 0.0), degree: int = 1,
+               jitter: float = 0.0, K: int | None = None, seed: int = 0) -> Mesh:
+    """N x N periodic cells on [origin, origin+L]^2; each cell is split into
+    two triangles along a random diagonal with probability `frac` (the
+    quadrilateral-to-two-triangles subdivision of the paper's hybrid meshes)
+    and stays a quadrilateral otherwise, all drawn from `seed`.  Vertices are
+    jittered as in quad_mesh.  Elements are listed grouped by type: every
+    triangle (cell order), then every quadrilateral.  max_vert = max_face =
+    4; a triangle's fourth vertex repeats its first and its fourth face has
+    no neighbour (-1)."""
+    if N < 3:
+        raise ValueError("mixed_mesh needs N >= 3 (distinct periodic edges)")
+    h = L / N
+    if K is None:
+        K = max(N // 4, 1)
+    rng = np.random.default_rng(seed)
+    split = rng.uniform(size=N * N) < frac
+    diag = rng.integers(0, 2, size=N * N)
+    tris, quads = [], []
+    for j in range(N):
+        for i in range(N):
+            c = i + N * j
+            A, B, C, D = (i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)
+            if split[c]:
+                tris.extend(((A, B, C), (A, C, D)) if diag[c] == 0 else ((A, B, D), (B, C, D)))
+            else:
+                quads.append((A, B, C, D))
+    verts = tris + quads
+    n = len(verts)
+    et = np.array([TRI] * len(tris) + [QUAD] * len(quads), dtype=np.int8)
+    xyz = np.zeros((n, 4, 2))
+    for e, vs in enumerate(verts):
+        for v in range(4):
+            vi, vj = vs[v % len(vs)]
+            xs, ys = vi / N, vj / N
+            jx, jy = _jitter2(xs, ys, 1.0 / N, jitter, K)
+            xyz[e, v, 0] = origin[0] + L * (xs + jx)
+            xyz[e, v, 1] = origin[1] + L * (ys + jy)
+    edges = {}
+    for e, vs in enumerate(verts):
+        for f in range(len(vs)):
+            a, b = vs[f], vs[(f + 1) % len(vs)]
+            key = frozenset(((a[0] % N, a[1] % N), (b[0] % N, b[1] % N)))
+            edges.setdefault(key, []).append((e, f))
+    nbr = np.full((n, 4), -1, dtype=np.int64)
+    nbr_face = np.full((n, 4), -1, dtype=np.int8)
+    for lst in edges.values():
+        if len(lst) != 2:
+            raise RuntimeError("mixed_mesh: non-conforming edge")
+        (e1, f1), (e2, f2) = lst
+        nbr[e1, f1], nbr_face[e1, f1] = e2, f2
+        nbr[e2, f2], nbr_face[e2, f2] = e1, f1
+    return Mesh(2, et, np.full(n, degree, np.int8), xyz, nbr, nbr_face, h)
+
+
 def hex_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0, 0.0), degree: int = 1,
              jitter: float = 0.0, K: int | None = None) -> Mesh:
     """N^3 periodic hexes on [origin, origin+L]^3 (optionally jittered with
@@ -218,10 +273,17 @@ def sol_points_phys(mesh: Mesh, p: int, tri_pts: np.ndarray | None = None
                     ) -> np.ndarray:
     """Physical coordinates [n, Ns, ndim] of the solution points of a
     single-type mesh (tensor Gauss-Legendre points through the bilinear or
-    trilinear vertex map; triangles use the affine map of tri_pts)."""
+    trilinear vertex map; triangles use the affine map of tri_pts).  For a
+    mesh that mixes types: [sum of Ns over the elements, ndim], element by
+    element in mesh order."""
     et = int(mesh.elem_type[0])
     if not np.all(mesh.elem_type == et):
-        raise ValueError("sol_points_phys expects a single element type")
+        parts = []
+        for e in range(mesh.n_elem):
+            sub = dataclasses.replace(mesh, elem_type=mesh.elem_type[e:e + 1],
+                                      xyz=mesh.xyz[e:e + 1, :(3 if mesh.elem_type[e] == TRI else 4)])
+            parts.append(sol_points_phys(sub, p, tri_pts)[0])
+        return np.concatenate(parts, axis=0)
     if et == TRI:
         r = tri_pts[:, 0]
         s = tri_pts[:, 1]
@@ -262,7 +324,7 @@ def advection_state(mesh: Mesh, p: int, seed: int = 1, tri_pts: np.ndarray | Non
     integer wave vectors in [-3,3]^2, random phases) at the solution points."""
     rng = np.random.default_rng(seed)
     x = sol_points_phys(mesh, p, tri_pts)
-    u = np.zeros(x.shape[:2])
+    u = np.zeros(x.shape[:-1])
     for _ in range(3):
         a = rng.uniform(0.5, 1.5)
         while True:
@@ -271,7 +333,7 @@ def advection_state(mesh: Mesh, p: int, seed: int = 1, tri_pts: np.ndarray | Non
                 break
         phi = rng.uniform(0, 2 * np.pi)
         u += a * np.sin(2 * np.pi * (x @ m) + phi)
-    return np.ascontiguousarray(u[:, :, None])
+    return np.ascontiguousarray(u[..., None])
 
 
 def conservative(rho, vel, p, gamma):

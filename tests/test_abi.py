@@ -65,3 +65,29 @@ def test_create_refuses_non_br1_without_gpu_work():
         rc = L.fr_ctx_create(ctypes.byref(md), ctypes.byref(ph), 0, None, ctypes.byref(h))
         assert rc == -2
         assert b"BR1" in L.fr_last_error(None)
+
+
+def test_create_refuses_ungrouped_mixed_mesh_without_gpu_work():
+    """A mesh that mixes triangles and quadrilaterals must list them grouped
+    by type; an interleaved order is refused on the host."""
+    if not os.path.exists(fr.LIB_PATH):
+        pytest.skip("libfr.so not built")
+    import numpy as np
+    from paper_2105_08632_amd import inputs as I
+    L = fr.lib()
+    m = I.mixed_mesh(4, 0.5, degree=1, seed=1)
+    perm = np.argsort(np.arange(m.n_elem) % 2, kind="stable")       # interleave the two groups
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m.n_elem)
+    et = np.ascontiguousarray(m.elem_type[perm])
+    assert np.any(np.diff(et.astype(int)) > 0) and np.any(np.diff(et.astype(int)) < 0)
+    nbr = np.where(m.nbr[perm] >= 0, inv[np.maximum(m.nbr[perm], 0)], -1).astype(np.int64)
+    keep = [et, np.ascontiguousarray(m.xyz[perm]), np.ascontiguousarray(nbr),
+            np.ascontiguousarray(m.nbr_face[perm], dtype=np.int8), np.ascontiguousarray(I.tri_points(1))]
+    md = fr._Mesh(2, m.n_elem, 1, keep[0].ctypes.data, keep[1].ctypes.data, m.max_vert,
+                  keep[2].ctypes.data, keep[3].ctypes.data, m.max_face, keep[4].ctypes.data)
+    ph = fr._Phys(1, 4, (ctypes.c_double * 3)(0, 0, 0), 1.4, 0.0, 0.72, 0.0, 0.0, 0)
+    h = ctypes.c_void_p()
+    rc = L.fr_ctx_create(ctypes.byref(md), ctypes.byref(ph), 0, None, ctypes.byref(h))
+    assert rc == -1
+    assert b"grouped by type" in L.fr_last_error(None)
