@@ -2,7 +2,10 @@
 // phase (mixed element types and degrees).
 //
 // A batch groups FP32 contexts of one system (2-D Euler or Navier-Stokes) on
-// triangles and quadrilaterals of degree 1..4.  Each phase (traces, BR1
+// triangles and quadrilaterals of degree 1..4; a context whose mesh mixes
+// triangles and quadrilaterals (Euler batches) enters as its two element
+// groups, which share the mesh's trace workspace, so every phase covers every
+// group before the next phase starts.  Each phase (traces, BR1
 // gradients, divergence; or the Jacobian prelude and block assembly) is one
 // persistent launch: workgroups walk a work list of (mesh, first tile,
 // tile count) items, longest first, and switch on the mesh's (type, degree)
@@ -28,6 +31,7 @@ namespace {
 constexpr int kBT = 256;   // threads of the persistent workgroups
 constexpr int kNV = 4;     // 2-D Euler / Navier-Stokes
 constexpr FR_HD int bcode(int et, int p) { return et * 8 + p; }
+constexpr int kMixCode = 16;   // added to the code of an element group of a mixed mesh
 
 #define FR_BATCH_CASES(X) \
   X(ET_TRI, 1) X(ET_TRI, 2) X(ET_TRI, 3) X(ET_TRI, 4) X(ET_QUAD, 1) X(ET_QUAD, 2) X(ET_QUAD, 3) X(ET_QUAD, 4)
@@ -36,8 +40,11 @@ struct BDesc {
   OpsD<double> opd; GeoD<double> geod;        // FP64 residual
   OpsD<float> opr; GeoD<float> geor;          // FP32 Jacobian
   Ops1D<float> o1;
+  MixD<float> md;                             // element group of a mixed mesh: cross-type data
   PhysP ph;
   int ne, code, visc, nblk;
+  int mesh, mix;                              // mesh of the group; 1 for a group of a mixed mesh
+  long uoff;                                  // first state entry of the group in its mesh
   double *UF64, *Q64, *QF64;
   float *UFr, *Qr, *QFr;
 };
@@ -48,6 +55,7 @@ struct BPtrs { const float* U[kMaxMeshes]; float* R[kMaxMeshes]; float* B[kMaxMe
 
 template <int ET, int P> constexpr int tile_of() { return rhs_tile<Elem<ET, P>>(); }
 static int tile_rt(int code) {
+  code %= kMixCode;
 #define TCASE(ET, P) if (code == bcode(ET, P)) return tile_of<ET, P>();
   FR_BATCH_CASES(TCASE)
 #undef TCASE
@@ -65,8 +73,11 @@ template <int SYS> constexpr int res_lds() {
 #undef LCASE
   return m;
 }
+template <int ET, int P> using OtherElem = Elem<(ET == ET_TRI ? ET_QUAD : ET_TRI), P>;
 template <int ET, int P, int SYS> constexpr int asm_lds_one() {
-  return ET == ET_TRI ? jac_lds<Elem<ET, P>, kNV, SYS, float>() : jac_tp_lds<Elem<ET, P>, kNV, SYS, float>();
+  return cmax(cmax(ET == ET_TRI ? jac_lds<Elem<ET, P>, kNV, SYS, float>() : jac_tp_lds<Elem<ET, P>, kNV, SYS, float>(),
+                   jac_self_inv_lds<Elem<ET, P>, kNV, float>()),
+              jac_nb_mixed_lds<Elem<ET, P>, OtherElem<ET, P>, kNV, float>());
 }
 template <int SYS> constexpr int jac_lds_all() {
   int m = 0;
@@ -94,8 +105,10 @@ __device__ __forceinline__ void res_item(char* lds, const BDesc* D, const BPtrs&
   double* UF = D[w.desc].UF64;
   double* Q = D[w.desc].Q64;
   double* QF = D[w.desc].QF64;
-  const float* U = P.U[w.desc];
-  float* Rout = P.R[w.desc];
+  const long uoff = D[w.desc].uoff;
+  const int mesh = D[w.desc].mesh;
+  const float* U = P.U[mesh] + uoff;
+  float* Rout = P.R[mesh] ? P.R[mesh] + uoff : nullptr;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int t = w.first; t < w.first + w.count; ++t) {
     if constexpr (PH == 0)
@@ -121,9 +134,26 @@ __device__ __forceinline__ void jac_item(char* lds, const BDesc* D, const BPtrs&
   float* UF = D[w.desc].UFr;
   float* Q = D[w.desc].Qr;
   float* QF = D[w.desc].QFr;
-  const float* U = P.U[w.desc];
-  float* B = P.B[w.desc];
+  const int mesh = D[w.desc].mesh;
+  const float* U = P.U[mesh] + D[w.desc].uoff;
+  float* B = P.B[mesh];
   const int tid = threadIdx.x, nth = blockDim.x;
+  if constexpr (PH == 2 && SYS == SYS_EULER) {
+    if (D[w.desc].mix) {
+      // a group of a mixed mesh (inviscid): self blocks, then the face
+      // blocks through the neighbour's own interpolation; blocks at absolute
+      // offsets in the mesh's array
+      const MixD<float> md = D[w.desc].md;
+      for (int t = w.first; t < w.first + w.count; ++t) {
+        jac_self_inv_body<E, kNV, SYS, float, float>(t, tid, nth, lds, op, geo, ph, U, UF, B, DevSync());
+        __syncthreads();
+        jac_nb_mixed_body<E, OtherElem<ET, DEG>, kNV, SYS, float, float>(t, tid, nth, lds, op, geo, md, ph, UF, B,
+                                                                         DevSync());
+        __syncthreads();
+      }
+      return;
+    }
+  }
   if constexpr (PH == 2 && ET != ET_TRI) {
     const Ops1D<float> o1 = D[w.desc].o1;
     for (int t = w.first; t < w.first + w.count; ++t) {
@@ -153,7 +183,9 @@ __global__ void __launch_bounds__(kBT) k_batch_res(const BDesc* D, BPtrs P, cons
     const BItem w = items[it];
     const BDesc& d = D[w.desc];
     switch (d.code) {
-#define RCASE(ET, DEG) case bcode(ET, DEG): res_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
+#define RCASE(ET, DEG) \
+  case bcode(ET, DEG): \
+  case bcode(ET, DEG) + kMixCode: res_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
       FR_BATCH_CASES(RCASE)
 #undef RCASE
       default: break;
@@ -167,7 +199,9 @@ __global__ void __launch_bounds__(kBT) k_batch_jac(const BDesc* D, BPtrs P, cons
     const BItem w = items[it];
     const BDesc& d = D[w.desc];
     switch (d.code) {
-#define JCASE2(ET, DEG) case bcode(ET, DEG): jac_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
+#define JCASE2(ET, DEG) \
+  case bcode(ET, DEG): \
+  case bcode(ET, DEG) + kMixCode: jac_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
       FR_BATCH_CASES(JCASE2)
 #undef JCASE2
       default: break;
@@ -211,7 +245,8 @@ __global__ void __launch_bounds__((gjac_threads<ET, DEG, SYS, PH>())) k_group_ja
 }  // namespace
 
 struct fr_batch_s {
-  std::vector<fr_ctx_s*> ctx;
+  std::vector<fr_ctx_s*> mesh;     // the contexts as given, one per mesh
+  std::vector<fr_ctx_s*> ctx;      // one per descriptor: a single-type mesh, or a group of a mixed mesh
   int sys = 0, ncu = 1;
   hipStream_t stream = nullptr;
   BDesc* ddesc = nullptr;          // device
@@ -234,12 +269,15 @@ struct fr_batch_s {
   std::string err;
 };
 
+static int desc_code(const fr_batch_s* b, size_t i) { return b->hdesc[i].code; }
+
 static fr_status bfail(fr_batch_s* b, fr_status s, const std::string& m) {
   if (b) b->err = m;
   return s;
 }
 
 static int sec_cost(const fr_ctx_s* c) { return c->ns * (c->ns + c->nf); }
+static int desc_code(const fr_batch_s* b, size_t i);
 
 // work list: units (tiles or elements) in items of k[code] units, longest
 // first; `seg` receives each group's range in the grouped copy (appended)
@@ -249,7 +287,7 @@ static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BIte
   std::vector<std::pair<long, BItem>> v;
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     const fr_ctx_s* c = b->ctx[i];
-    const int code = bcode(c->type, c->p);
+    const int code = desc_code(b, i);
     const int te = tiles ? tile_rt(code) : 1;
     const int units = (int)((c->ne + te - 1) / te);
     const int per = std::max(1, k[code]);
@@ -265,7 +303,7 @@ static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BIte
   for (int code : b->codes) {
     seg_off[code] = (int)out.size();
     for (size_t j = 0; j < nall; ++j)
-      if (bcode(b->ctx[out[j].desc]->type, b->ctx[out[j].desc]->p) == code) out.push_back(out[j]);
+      if (desc_code(b, (size_t)out[j].desc) == code) out.push_back(out[j]);
     seg_cnt[code] = (int)out.size() - seg_off[code];
   }
 }
@@ -304,6 +342,7 @@ static void group_res(fr_batch_s* b, int code, const BItem* items, int n, int gr
   switch (code) {
 #define GR(ET, DEG)                                                                                             \
   case bcode(ET, DEG):                                                                                          \
+  case bcode(ET, DEG) + kMixCode:                                                                               \
     hipLaunchKernelGGL((k_group_res<ET, DEG, SYS, PH>), dim3(grid), dim3(kThreads), 0, b->stream, b->ddesc,      \
                        b->ptrs, items, n);                                                                      \
     break;
@@ -317,6 +356,7 @@ static void group_jac(fr_batch_s* b, int code, const BItem* items, int n, int gr
   switch (code) {
 #define GJ(ET, DEG)                                                                                             \
   case bcode(ET, DEG):                                                                                          \
+  case bcode(ET, DEG) + kMixCode:                                                                               \
     hipLaunchKernelGGL((k_group_jac<ET, DEG, SYS, PH>), dim3(grid), dim3(gjac_threads<ET, DEG, SYS, PH>()), 0,   \
                        b->stream, b->ddesc, b->ptrs, items, n);                                                 \
     break;
@@ -336,13 +376,15 @@ static fr_status launch_res(fr_batch_s* b, bool visc) {
     if (visc) hipLaunchKernelGGL((k_batch_res<SYS, 1>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
     hipLaunchKernelGGL((k_batch_res<SYS, 2>), g, t, 0, b->stream, b->ddesc, b->ptrs, b->dres, b->nres);
   } else {
-    for (int code : b->codes) {
-      const BItem* it = b->dres + b->seg_off[0][code];
-      const int n = b->seg_cnt[0][code], g = gsize(b->grid_res, n);
-      group_res<SYS, 0>(b, code, it, n, g);
-      if (visc) group_res<SYS, 1>(b, code, it, n, g);
-      group_res<SYS, 2>(b, code, it, n, g);
-    }
+    // phase by phase: a group of a mixed mesh reads the other group's traces
+    for (int ph = 0; ph < 3; ++ph)
+      for (int code : b->codes) {
+        const BItem* it = b->dres + b->seg_off[0][code];
+        const int n = b->seg_cnt[0][code], g = gsize(b->grid_res, n);
+        if (ph == 0) group_res<SYS, 0>(b, code, it, n, g);
+        else if (ph == 1) { if (visc) group_res<SYS, 1>(b, code, it, n, g); }
+        else group_res<SYS, 2>(b, code, it, n, g);
+      }
   }
   return hipGetLastError() == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch residual launch");
 }
@@ -355,35 +397,44 @@ static fr_status launch_jac(fr_batch_s* b, bool visc) {
     hipLaunchKernelGGL((k_batch_jac<SYS, 2>), dim3(gsize(b->grid_jac, b->njac)), t, 0, b->stream, b->ddesc, b->ptrs,
                        b->djac, b->njac);
   } else {
+    // the single-mesh matrix-core path (tables + MFMA assembly) for
+    // single-type quadrilateral meshes in mode 2, mesh by mesh on the batch
+    // stream: the same kernels as the mesh run alone
+    auto mf = [&](int code) { return b->jac_mode == 2 && code / 8 == ET_QUAD; };
     for (int code : b->codes) {
-      if (b->jac_mode == 2 && code / 8 == ET_QUAD) {
-        // the single-mesh matrix-core path (tables + MFMA assembly), mesh by
-        // mesh on the batch stream: the same kernels as the mesh run alone
-        for (size_t i = 0; i < b->ctx.size(); ++i) {
-          if (b->hdesc[i].code != code) continue;
-          fr_ctx_s* c = b->ctx[i];
-          hipStream_t own = c->stream;
-          c->stream = b->stream;
-          const int rc = c->ks.jac(c, b->ptrs.U[i], b->ptrs.B[i], 1, b->hdesc[i].nblk);
-          c->stream = own;
-          if (rc) return bfail(b, (fr_status)rc, "mesh " + std::to_string(i) + ": " + c->err);
-        }
-        continue;
+      if (!mf(code)) continue;
+      for (size_t i = 0; i < b->ctx.size(); ++i) {
+        if (b->hdesc[i].code != code) continue;
+        fr_ctx_s* c = b->ctx[i];
+        const int ms = b->hdesc[i].mesh;
+        hipStream_t own = c->stream;
+        c->stream = b->stream;
+        const int rc = c->ks.jac(c, b->ptrs.U[ms], b->ptrs.B[ms], 1, b->hdesc[i].nblk);
+        c->stream = own;
+        if (rc) return bfail(b, (fr_status)rc, "mesh " + std::to_string(ms) + ": " + c->err);
       }
-      const BItem* tl = b->dtil + b->seg_off[1][code];
-      const int nt = b->seg_cnt[1][code], gt = gsize(b->grid_res, nt);
-      group_jac<SYS, 0>(b, code, tl, nt, gt);
-      if (visc) group_jac<SYS, 1>(b, code, tl, nt, gt);
-      const int na = b->seg_cnt[2][code];
-      group_jac<SYS, 2>(b, code, b->djac + b->seg_off[2][code], na, gsize(b->grid_jac, na));
     }
+    // the others phase by phase (a group of a mixed mesh reads the other
+    // group's traces)
+    for (int ph = 0; ph < 3; ++ph)
+      for (int code : b->codes) {
+        if (mf(code)) continue;
+        const BItem* tl = b->dtil + b->seg_off[1][code];
+        const int nt = b->seg_cnt[1][code], gt = gsize(b->grid_res, nt);
+        if (ph == 0) group_jac<SYS, 0>(b, code, tl, nt, gt);
+        else if (ph == 1) { if (visc) group_jac<SYS, 1>(b, code, tl, nt, gt); }
+        else {
+          const int na = b->seg_cnt[2][code];
+          group_jac<SYS, 2>(b, code, b->djac + b->seg_off[2][code], na, gsize(b->grid_jac, na));
+        }
+      }
   }
   return hipGetLastError() == hipSuccess ? FR_OK : bfail(b, FR_E_DEVICE, "batch Jacobian launch");
 }
 
 static fr_status set_ptrs(fr_batch_s* b, const void* const* U, void* const* R, void* const* B) {
   BPtrs p{};
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
+  for (size_t i = 0; i < b->mesh.size(); ++i) {
     if (!U[i] || (R && !R[i]) || (B && !B[i]))
       return bfail(b, FR_E_INVALID, "null pointer for mesh " + std::to_string(i));
     p.U[i] = (const float*)U[i];
@@ -425,8 +476,9 @@ fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out) {
     const char* why = nullptr;
     if (c->prec != 1) why = "batched meshes must be FP32 contexts";
     else if (c->scheme == 2) why = "batched meshes must be FR (FR-DG or FR-SDRT) contexts";
-    else if (c->mixed) why = "batched meshes must be single-type contexts";
-    else if (c->nd != 2 || (c->type != ET_QUAD && c->type != ET_TRI)) why = "batched meshes must be 2-D triangles or quadrilaterals";
+    else if (c->mixed && c->system != SYS_EULER) why = "batched mixed meshes must be Euler (inviscid blocks)";
+    else if (c->nd != 2 || (!c->mixed && c->type != ET_QUAD && c->type != ET_TRI))
+      why = "batched meshes must be 2-D triangles or quadrilaterals";
     else if (c->system != SYS_EULER && c->system != SYS_NS) why = "batched meshes must be Euler or Navier-Stokes";
     else if (i > 0 && c->system != ctxs[0]->system) why = "batched meshes must share one system";
     else if (c->p < 1 || c->p > 4) why = "batched meshes must have degree 1..4";
@@ -435,11 +487,26 @@ fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out) {
       delete b;
       return FR_E_UNSUPPORTED;
     }
-    b->ctx.push_back(c);
+    b->mesh.push_back(c);
+  }
+  std::vector<int> dmesh, dmix;
+  std::vector<long> duoff;
+  std::vector<const void*> dmd;
+  for (size_t i = 0; i < b->mesh.size(); ++i) {
+    fr_ctx_s* c = b->mesh[i];
+    if (!c->mixed) {
+      b->ctx.push_back(c); dmesh.push_back((int)i); dmix.push_back(0); duoff.push_back(0); dmd.push_back(nullptr);
+      continue;
+    }
+    for (size_t g = 0; g < c->grp.size(); ++g) {
+      b->ctx.push_back(c->grp[g]); dmesh.push_back((int)i); dmix.push_back(1);
+      duoff.push_back((long)c->grp_dof0[g]); dmd.push_back(c->grp[g]->mixd);
+    }
   }
   b->sys = ctxs[0]->system;
   b->stream = ctxs[0]->stream;
-  for (auto* c : b->ctx) b->codes.push_back(bcode(c->type, c->p));
+  for (size_t i = 0; i < b->ctx.size(); ++i)
+    b->codes.push_back(bcode(b->ctx[i]->type, b->ctx[i]->p) + (dmix[i] ? kMixCode : 0));
   std::sort(b->codes.begin(), b->codes.end());
   b->codes.erase(std::unique(b->codes.begin(), b->codes.end()), b->codes.end());
   int dev = 0;
@@ -464,6 +531,8 @@ fr_status fr_batch_create(fr_ctx* const* ctxs, int n_ctx, fr_batch** out) {
     d.ne = (int)c->ne; d.code = bcode(c->type, c->p); d.visc = c->visc ? 1 : 0; d.nblk = 1 + c->nface;
     d.UF64 = (double*)c->UF64; d.Q64 = (double*)c->Q64; d.QF64 = (double*)c->QF64;
     d.UFr = (float*)c->UF; d.Qr = (float*)c->Q; d.QFr = (float*)c->QF;
+    d.mesh = dmesh[i]; d.mix = dmix[i]; d.uoff = duoff[i];
+    if (dmix[i]) { d.md = *(const MixD<float>*)dmd[i]; d.code += kMixCode; }
   }
   if (hipMemcpy(b->ddesc, b->hdesc, nd * sizeof(BDesc), hipMemcpyHostToDevice) != hipSuccess) {
     fr_batch_destroy(b);

@@ -611,8 +611,9 @@ class Batch:
         md = (C.c_int * 2)()
         kr, kj = (C.c_int * 32)(), (C.c_int * 32)()
         self._check(lib().fr_batch_tuning(self.h, md, C.byref(gr), C.byref(gj), kr, kj))
-        codes = sorted({8 * int(c.mesh.elem_type[0]) + int(c.mesh.degree[0]) for c in self.ctxs})
-        name = {0: "quad", 1: "tri"}
+        codes = sorted({8 * int(t) + int(c.mesh.degree[0]) + (16 if c.mixed else 0)
+                        for c in self.ctxs for t in set(c.mesh.elem_type.tolist())})
+        name = {0: "quad", 1: "tri", 2: "mixed-quad", 3: "mixed-tri"}
         mode = {0: "mixed", 1: "grouped", 2: "grouped_mfma_quads"}
         return {"res_launch": mode[md[0]], "jac_launch": mode[md[1]], "grid_res": gr.value, "grid_jac": gj.value,
                 "tiles_per_item": {f"{name[k // 8]}p{k % 8}": kr[k] for k in codes},

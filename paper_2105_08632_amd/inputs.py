@@ -278,12 +278,17 @@ def sol_points_phys(mesh: Mesh, p: int, tri_pts: np.ndarray | None = None
     element in mesh order."""
     et = int(mesh.elem_type[0])
     if not np.all(mesh.elem_type == et):
-        parts = []
-        for e in range(mesh.n_elem):
-            sub = dataclasses.replace(mesh, elem_type=mesh.elem_type[e:e + 1],
-                                      xyz=mesh.xyz[e:e + 1, :(3 if mesh.elem_type[e] == TRI else 4)])
-            parts.append(sol_points_phys(sub, p, tri_pts)[0])
-        return np.concatenate(parts, axis=0)
+        ns = np.array([n_sol_points(int(t), p) for t in mesh.elem_type])
+        start = np.concatenate([[0], np.cumsum(ns)])
+        out = np.zeros((int(start[-1]), mesh.ndim))
+        for t in set(mesh.elem_type.tolist()):
+            sel = np.nonzero(mesh.elem_type == t)[0]
+            sub = dataclasses.replace(mesh, elem_type=mesh.elem_type[sel],
+                                      xyz=mesh.xyz[sel][:, :(3 if t == TRI else mesh.max_vert)])
+            x = sol_points_phys(sub, p, tri_pts)                     # [n_t, Ns_t, ndim]
+            rows = start[sel][:, None] + np.arange(x.shape[1])[None, :]
+            out[rows.reshape(-1)] = x.reshape(-1, mesh.ndim)
+        return out
     if et == TRI:
         r = tri_pts[:, 0]
         s = tri_pts[:, 1]
@@ -445,25 +450,24 @@ def ns_physics(ndim: int, reynolds: float, prandtl: float, gamma: float = 1.4,
 def mixed_batch(seed: int = 7, count: int = 64, n_min: int = 500, n_max: int = 5000, gamma: float = 1.4):
     """A batch of independent periodic 2-D Euler meshes shaped like the mixed
     workload: element-count targets ~ U{n_min..n_max}, degree ~ U{1..4}, a
-    split fraction s ~ U(0.3, 0.7).  Each mesh is one element type: with
-    probability s its n x n cells are split into triangles, else they stay
-    quadrilaterals (n = round(sqrt(target / (1 + s)))); vertices jittered by
-    5%; state = the isentropic vortex of the paper's Euler test.  Returns
-    [(mesh, p, tri_pts or None, U)]."""
+    split fraction s ~ U(0.3, 0.7).  Each mesh mixes the two types: its n x n
+    cells are split into two triangles with probability s and stay
+    quadrilaterals otherwise (mixed_mesh; n = round(sqrt(target / (1 + s)))),
+    vertices jittered by 5%.  State: a smooth random subsonic field (Mach
+    0.3; the isentropic vortex's core is narrower than the elements of the
+    smaller meshes).  Returns [(mesh, p, tri_pts, U)], U flat (mixed-mesh
+    layout)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
         target = int(rng.integers(n_min, n_max + 1))
         p = int(rng.integers(1, 5))
         s = float(rng.uniform(0.3, 0.7))
-        tri = bool(rng.uniform() < s)
         n = max(3, int(round(np.sqrt(target / (1.0 + s)))))
         msd = int(rng.integers(0, 2**31 - 1))
-        if tri:
-            m = tri_mesh(n, degree=p, jitter=0.05, seed=msd)
-            tp = tri_points(p)
-        else:
-            m = quad_mesh(n, degree=p, jitter=0.05)
-            tp = None
-        out.append((m, p, tp, isentropic_vortex_state(m, p, gamma=gamma, tri_pts=tp)))
+        m = mixed_mesh(n, s, degree=p, jitter=0.05, seed=msd)
+        tp = tri_points(p)
+        sd = tuple(int(x) for x in rng.integers(0, 2**31 - 1, size=3))
+        U = ns2d_state(m, p, seeds=sd, mach=0.3, gamma=gamma, tri_pts=tp)
+        out.append((m, p, tp, np.ascontiguousarray(U.reshape(-1))))
     return out
