@@ -304,13 +304,13 @@ static int mixed_rhs_ws(fr_ctx_s* c, const void* U, void* R, void* UF, void* Q, 
 static int mixed_jvp(fr_ctx_s* c, const void* U, const void* V, void* Jv, void* Rv) {
   return mixed_eval(c, 1, U, V, Rv, Jv, c->UFd, c->Qd, c->QFd);
 }
-// Blocks of every element: traces of all groups, then self blocks, then
-// face blocks (those read the traces of the neighbours in either group).
+// Blocks of every element: traces of all groups, then the blocks (the face
+// blocks read the traces of the neighbours in either group).
 static int mixed_jac(fr_ctx_s* c, const void* U, void* B, int out_prec, int nblk) {
   (void)nblk;
   if (c->visc) { c->err = "Jacobian blocks of mixed meshes: inviscid systems only"; return FR_E_UNSUPPORTED; }
   const size_t io = c->prec == FR_F64 ? 8 : 4;
-  for (int stage = 0; stage < 3; ++stage)
+  for (int stage = 0; stage < 2; ++stage)
     for (size_t g = 0; g < c->grp.size(); ++g) {
       fr_ctx_s* s = c->grp[g];
       if (!s->ks.jac_mixed) { c->err = "no mixed-mesh Jacobian kernels for this element type"; return FR_E_UNSUPPORTED; }

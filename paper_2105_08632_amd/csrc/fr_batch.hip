@@ -75,9 +75,8 @@ template <int SYS> constexpr int res_lds() {
 }
 template <int ET, int P> using OtherElem = Elem<(ET == ET_TRI ? ET_QUAD : ET_TRI), P>;
 template <int ET, int P, int SYS> constexpr int asm_lds_one() {
-  return cmax(cmax(ET == ET_TRI ? jac_lds<Elem<ET, P>, kNV, SYS, float>() : jac_tp_lds<Elem<ET, P>, kNV, SYS, float>(),
-                   jac_self_inv_lds<Elem<ET, P>, kNV, float>()),
-              jac_nb_mixed_lds<Elem<ET, P>, OtherElem<ET, P>, kNV, float>());
+  return cmax(ET == ET_TRI ? jac_lds<Elem<ET, P>, kNV, SYS, float>() : jac_tp_lds<Elem<ET, P>, kNV, SYS, float>(),
+              jac_mixed_inv_lds<Elem<ET, P>, OtherElem<ET, P>, kNV, float>());
 }
 template <int SYS> constexpr int jac_lds_all() {
   int m = 0;
@@ -124,7 +123,8 @@ __device__ __forceinline__ void res_item(char* lds, const BDesc* D, const BPtrs&
   }
 }
 
-template <int ET, int DEG, int SYS, int PH>
+// MIX: 1 the item is a group of a mixed mesh, 0 it is not, -1 decided per item.
+template <int ET, int DEG, int SYS, int PH, int MIX>
 __device__ __forceinline__ void jac_item(char* lds, const BDesc* D, const BPtrs& P, const BItem& w) {
   typedef Elem<ET, DEG> E;
   const OpsD<float> op = D[w.desc].opr;
@@ -138,23 +138,21 @@ __device__ __forceinline__ void jac_item(char* lds, const BDesc* D, const BPtrs&
   const float* U = P.U[mesh] + D[w.desc].uoff;
   float* B = P.B[mesh];
   const int tid = threadIdx.x, nth = blockDim.x;
-  if constexpr (PH == 2 && SYS == SYS_EULER) {
-    if (D[w.desc].mix) {
+  if constexpr (PH == 2 && SYS == SYS_EULER && MIX != 0) {
+    if (MIX == 1 || D[w.desc].mix) {
       // a group of a mixed mesh (inviscid): self blocks, then the face
       // blocks through the neighbour's own interpolation; blocks at absolute
       // offsets in the mesh's array
       const MixD<float> md = D[w.desc].md;
-      for (int t = w.first; t < w.first + w.count; ++t) {
-        jac_self_inv_body<E, kNV, SYS, float, float>(t, tid, nth, lds, op, geo, ph, U, UF, B, DevSync());
-        __syncthreads();
-        jac_nb_mixed_body<E, OtherElem<ET, DEG>, kNV, SYS, float, float>(t, tid, nth, lds, op, geo, md, ph, UF, B,
-                                                                         DevSync());
-        __syncthreads();
-      }
+      jac_mixed_inv_body<E, OtherElem<ET, DEG>, kNV, SYS, float, float>(w.first, w.first + w.count, tid, nth, lds,
+                                                                        op, geo, md, ph, U, UF, B, DevSync());
+      __syncthreads();
       return;
     }
   }
-  if constexpr (PH == 2 && ET != ET_TRI) {
+  if constexpr (PH == 2 && MIX == 1) {
+    return;
+  } else if constexpr (PH == 2 && ET != ET_TRI) {
     const Ops1D<float> o1 = D[w.desc].o1;
     for (int t = w.first; t < w.first + w.count; ++t) {
       jac_tp_body<E, kNV, SYS, float, float>(t, tid, nth, lds, op, o1, geo, ph, U, Q, UF, QF, B, nblk, DevSync());
@@ -201,7 +199,7 @@ __global__ void __launch_bounds__(kBT) k_batch_jac(const BDesc* D, BPtrs P, cons
     switch (d.code) {
 #define JCASE2(ET, DEG) \
   case bcode(ET, DEG): \
-  case bcode(ET, DEG) + kMixCode: jac_item<ET, DEG, SYS, PH>(lds, D, P, w); break;
+  case bcode(ET, DEG) + kMixCode: jac_item<ET, DEG, SYS, PH, -1>(lds, D, P, w); break;
       FR_BATCH_CASES(JCASE2)
 #undef JCASE2
       default: break;
@@ -216,13 +214,17 @@ template <int ET, int DEG, int SYS, int PH> constexpr int gres_lds() {
   return PH == 0 ? trace_lds<E, kNV, double, double>()
                  : (PH == 1 ? grad_lds<E, kNV, double, double>() : div_lds<E, kNV, SYS, double, double>());
 }
-template <int ET, int DEG, int SYS, int PH> constexpr int gjac_lds() {
+// MIX: the groups of mixed meshes, whose assembly takes the mixed-mesh body
+// only (its own LDS and thread count).
+template <int ET, int DEG, int SYS, int PH, int MIX> constexpr int gjac_lds() {
   typedef Elem<ET, DEG> E;
   return PH == 0 ? trace_lds<E, kNV, float, float>()
-                 : (PH == 1 ? grad_lds<E, kNV, float, float>() : asm_lds_one<ET, DEG, SYS>());
+                 : (PH == 1 ? grad_lds<E, kNV, float, float>()
+                            : (MIX ? jac_mixed_inv_lds<E, OtherElem<ET, DEG>, kNV, float>()
+                                   : asm_lds_one<ET, DEG, SYS>()));
 }
-template <int ET, int DEG, int SYS, int PH> constexpr int gjac_threads() {
-  return (PH == 2 && ET != ET_TRI) ? jac_tp_threads<Elem<ET, DEG>, kNV, SYS, float>() : kThreads;
+template <int ET, int DEG, int SYS, int PH, int MIX> constexpr int gjac_threads() {
+  return (PH == 2 && ET != ET_TRI && !MIX) ? jac_tp_threads<Elem<ET, DEG>, kNV, SYS, float>() : kThreads;
 }
 template <int ET, int DEG, int SYS, int PH>
 __global__ void __launch_bounds__(kThreads) k_group_res(const BDesc* D, BPtrs P, const BItem* items, int nitems) {
@@ -232,13 +234,14 @@ __global__ void __launch_bounds__(kThreads) k_group_res(const BDesc* D, BPtrs P,
     res_item<ET, DEG, SYS, PH>(lds, D, P, w);
   }
 }
-template <int ET, int DEG, int SYS, int PH>
-__global__ void __launch_bounds__((gjac_threads<ET, DEG, SYS, PH>())) k_group_jac(const BDesc* D, BPtrs P,
-                                                                                 const BItem* items, int nitems) {
-  __shared__ __align__(16) char lds[gjac_lds<ET, DEG, SYS, PH>()];
+template <int ET, int DEG, int SYS, int PH, int MIX>
+__global__ void __launch_bounds__((gjac_threads<ET, DEG, SYS, PH, MIX>())) k_group_jac(const BDesc* D, BPtrs P,
+                                                                                      const BItem* items,
+                                                                                      int nitems) {
+  __shared__ __align__(16) char lds[gjac_lds<ET, DEG, SYS, PH, MIX>()];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const BItem w = items[it];
-    jac_item<ET, DEG, SYS, PH>(lds, D, P, w);
+    jac_item<ET, DEG, SYS, PH, MIX>(lds, D, P, w);
   }
 }
 
@@ -356,9 +359,13 @@ static void group_jac(fr_batch_s* b, int code, const BItem* items, int n, int gr
   switch (code) {
 #define GJ(ET, DEG)                                                                                             \
   case bcode(ET, DEG):                                                                                          \
+    hipLaunchKernelGGL((k_group_jac<ET, DEG, SYS, PH, 0>), dim3(grid), dim3(gjac_threads<ET, DEG, SYS, PH, 0>()), \
+                       0, b->stream, b->ddesc, b->ptrs, items, n);                                              \
+    break;                                                                                                      \
   case bcode(ET, DEG) + kMixCode:                                                                               \
-    hipLaunchKernelGGL((k_group_jac<ET, DEG, SYS, PH>), dim3(grid), dim3(gjac_threads<ET, DEG, SYS, PH>()), 0,   \
-                       b->stream, b->ddesc, b->ptrs, items, n);                                                 \
+    if constexpr (SYS == SYS_EULER)                                                                             \
+      hipLaunchKernelGGL((k_group_jac<ET, DEG, SYS, PH, 1>), dim3(grid),                                        \
+                         dim3(gjac_threads<ET, DEG, SYS, PH, 1>()), 0, b->stream, b->ddesc, b->ptrs, items, n); \
     break;
     FR_BATCH_CASES(GJ)
 #undef GJ

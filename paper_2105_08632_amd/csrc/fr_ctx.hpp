@@ -28,8 +28,8 @@ struct KernelSet {
   int (*phase)(fr_ctx_s*, int which, int dual, const void* U, const void* V, void* UF, void* Q, void* QF, void* Rout,
                void* Rtan);
   // element group of a mixed mesh, inviscid systems: stage 0 traces (context
-  // precision, into the group's UF), 1 self blocks, 2 face blocks; mix: a
-  // host MixD of the context precision (2-D types only, null otherwise)
+  // precision, into the group's UF), 1 every block; mix: a host MixD of the
+  // context precision (2-D types only, null otherwise)
   int (*jac_mixed)(fr_ctx_s*, int stage, const void* U, void* B, int out_prec, const void* mix);
 };
 

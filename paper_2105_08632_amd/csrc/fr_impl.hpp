@@ -54,19 +54,15 @@ __global__ void __launch_bounds__((jac_tp_threads<E, NV, SYS, R>())) k_jac_tp(Op
                                  DevSync());
 }
 
-template <class E, int NV, int SYS, class R, class OT>
-__global__ void __launch_bounds__(kThreads) k_jac_self_inv(OpsD<R> op, GeoD<R> geo, PhysP ph, const R* U, const R* UF,
-                                                           OT* B) {
-  __shared__ __align__(16) char lds[jac_self_inv_lds<E, NV, R>()];
-  jac_self_inv_body<E, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, UF, B, DevSync());
-}
-
+// Mixed meshes: each workgroup assembles every block of a contiguous range of
+// `per` elements of the group.
 template <class E, class EO, int NV, int SYS, class R, class OT>
-__global__ void __launch_bounds__(kThreads) k_jac_nb_mixed(OpsD<R> op, GeoD<R> geo, MixD<R> mx, PhysP ph, const R* UF,
-                                                           OT* B) {
-  __shared__ __align__(16) char lds[jac_nb_mixed_lds<E, EO, NV, R>()];
-  jac_nb_mixed_body<E, EO, NV, SYS, R, OT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, mx, ph, UF, B,
-                                           DevSync());
+__global__ void __launch_bounds__(kThreads) k_jac_mixed_inv(OpsD<R> op, GeoD<R> geo, MixD<R> mx, PhysP ph,
+                                                            const R* U, const R* UF, OT* B, int ne, int per) {
+  __shared__ __align__(16) char lds[jac_mixed_inv_lds<E, EO, NV, R>()];
+  const int n0 = blockIdx.x * per, n1 = min(ne, n0 + per);
+  jac_mixed_inv_body<E, EO, NV, SYS, R, OT>(n0, n1, threadIdx.x, blockDim.x, lds, op, geo, mx, ph, U, UF, B,
+                                            DevSync());
 }
 
 // Matrix-core Jacobian (tensor-product elements, FP32): sensitivities once
@@ -260,11 +256,10 @@ template <int ET, int P, int SYS, class R> struct Impl {
         hipLaunchKernelGGL((k_trace<E, NV, R, R, R>), dim3((ne + TE - 1) / TE), dim3(kThreads), 0, c->stream, op, ne,
                            U, (const R*)nullptr, (R*)c->UF);
       } else if (stage == 1) {
-        hipLaunchKernelGGL((k_jac_self_inv<E, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo,
-                           c->ph, U, (const R*)c->UF, B);
-      } else {
-        hipLaunchKernelGGL((k_jac_nb_mixed<E, EO, NV, SYS, R, OT>), dim3(ne), dim3(kThreads), 0, c->stream, op, geo,
-                           *mx, c->ph, (const R*)c->UF, B);
+        // a few elements per workgroup: the operators are staged once for them
+        const int per = ne >= 4096 ? 4 : (ne >= 1024 ? 2 : 1);
+        hipLaunchKernelGGL((k_jac_mixed_inv<E, EO, NV, SYS, R, OT>), dim3((ne + per - 1) / per), dim3(kThreads), 0,
+                           c->stream, op, geo, *mx, c->ph, U, (const R*)c->UF, B, ne, per);
       }
       FR_LAUNCH_CHECK(c);
       return 0;

@@ -922,33 +922,52 @@ template <class R> struct MixD {
   const R* M0o;       // [NFo][NSo]: the other type's solution-to-flux-point interpolation
 };
 
-// Self blocks of an inviscid system, written at geo.boff[n]:
-//   dR_n(rho, alpha) / dU_n(sigma, beta) = -(1/detJ_rho) [ sum_d Dc_d[rho][sigma] A_d(sigma)
-//       + sum_g Cor[rho][g] |N_g| dF/du_L (g) M0[g][sigma] ]_{alpha beta}
-// with A_d = sum_k S_dk df_k/du (eq. "transformed_quantities") and Dc_d =
-// D_d - Cor diag(nref_d) M0 (the flux's own trace leaves through the
-// correction, eq. "divergence_fr").
-template <class E, int NV, class R> constexpr int jac_self_inv_lds() {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, NV2 = NV * NV;
-  return lds_bytes<R>(ND * NS * NV2) + lds_bytes<R>(NF * NV2) + lds_bytes<R>(NF * NS) + lds_bytes<int>(ND * NS * WL) +
-         lds_bytes<R>(ND * NS * WL) + lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NS) +
-         lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS * NV) + 2 * lds_bytes<R>(NF * NV) + lds_bytes<R>(NF * ND) +
-         lds_bytes<R>(NF);
+// Stores the NV rows r*NV .. r*NV+NV-1 of one block column (contiguous).
+template <int NV, class OT, class R> FR_HD void store_rows(OT* dst, const R* v) {
+  if constexpr (NV == 4 && std::is_same<OT, float>::value && std::is_same<R, float>::value) {
+    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    for (int a = 0; a < NV; ++a) dst[a] = to_out<OT>(v[a]);
+  }
 }
 
-template <class E, int NV, int SYS, class R, class OT, class Sync>
-FR_HD void jac_self_inv_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo,
-                             const PhysP& ph, const R* U, const R* UF, OT* B, Sync sync) {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, NV2 = NV * NV, BB = NS * NV;
+// All blocks of elements n0 .. n1-1 of one group of a mixed mesh, inviscid
+// system.  Self block (at geo.boff[n]):
+//   dR_n(rho, alpha) / dU_n(sigma, beta) = -(1/detJ_rho) [ sum_d Dc_d[rho][sigma] A_d(sigma)
+//       + sum_g Cor[rho][g] M0[g][sigma] |N_g| dF/du_L (g) ]_{alpha beta}
+// with A_d = sum_k S_dk df_k/du (eq. "transformed_quantities") and Dc_d =
+// D_d - Cor diag(nref_d) M0 (the flux's own trace leaves through the
+// correction, eq. "divergence_fr"); face blocks as described at MixD, with
+// |N_g| dF/du_R.  The operators are staged once per call; per element, one
+// thread per (rho, sigma) pair forms the NV x NV sub-block, so each operator
+// coefficient is read once for NV^2 outputs, and zero coefficients (the
+// sparse rows of tensor elements) are skipped.
+template <class E, class EO, int NV, class R> constexpr int jac_mixed_inv_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, WC = E::WC, NV2 = NV * NV;
+  return lds_bytes<R>(NF * NS) + lds_bytes<R>(NS * NF) + lds_bytes<R>(ND * NS * NS) + lds_bytes<int>(NS * WC) +
+         lds_bytes<R>(NS * WC) +
+         lds_bytes<R>(EO::NF * EO::NS) + lds_bytes<R>(ND * NS * NV2) + 2 * lds_bytes<R>(NF * NV2) +
+         lds_bytes<R>(NS) + lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS * NV) + 2 * lds_bytes<R>(NF * NV) +
+         lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF) + lds_bytes<int>(NFACE) +
+         lds_bytes<long>(NFACE + 1);
+}
+
+template <class E, class EO, int NV, int SYS, class R, class OT, class Sync>
+FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo,
+                              const MixD<R>& mx, const PhysP& ph, const R* U, const R* UF, OT* B, Sync sync) {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, NFP = E::NFP, WL = E::WL, WC = E::WC;
+  constexpr int NV2 = NV * NV, NSO = EO::NS, NFO = EO::NF, BB = NS * NV;
   typedef MDual<R, NV> MD;
   Lds L{lds};
+  R* sM0 = L.take<R>(NF * NS);
+  R* sCor = L.take<R>(NS * NF);
+  R* sDc = L.take<R>(ND * NS * NS);     // Dc_d, dense
+  int* scrc = L.take<int>(NS * WC);     // compressed rows of the correction
+  R* scrv = L.take<R>(NS * WC);
+  R* sM0o = L.take<R>(NFO * NSO);
   R* ta = L.take<R>(ND * NS * NV2);     // A_d(sigma)[alpha][beta]
   R* tL = L.take<R>(NF * NV2);          // |N_g| dF/du_L (g)
-  R* sM0 = L.take<R>(NF * NS);
-  int* dcc = L.take<int>(ND * NS * WL);
-  R* dcv = L.take<R>(ND * NS * WL);
-  int* crc = L.take<int>(NS * WC);
-  R* crv = L.take<R>(NS * WC);
+  R* tR = L.take<R>(NF * NV2);          // |N_g| dF/du_R (g)
   R* srd = L.take<R>(NS);
   R* sS = L.take<R>(NS * ND * ND);
   R* su = L.take<R>(NS * NV);
@@ -956,129 +975,119 @@ FR_HD void jac_self_inv_body(int n, int tid, int nth, char* lds, const OpsD<R>& 
   R* suR = L.take<R>(NF * NV);
   R* snn = L.take<R>(NF * ND);
   R* smg = L.take<R>(NF);
-  const long nl = n;
-  for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
-  for (int i = tid; i < ND * NS * WL; i += nth) { dcc[i] = op.dcc[i]; dcv[i] = op.dcv[i]; }
-  for (int i = tid; i < NS * WC; i += nth) { crc[i] = op.crc[i]; crv[i] = op.crv[i]; }
-  for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
-  for (int i = tid; i < NS * ND * ND; i += nth) sS[i] = geo.S[nl * NS * ND * ND + i];
-  for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
-  for (int i = tid; i < NF * NV; i += nth) {
-    const int g = i / NV, a = i % NV;
-    suL[i] = UF[(nl * NF + g) * NV + a];
-    suR[i] = UF[(long)geo.nbfp[nl * NF + g] * NV + a];
-  }
-  for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
-  for (int i = tid; i < NF; i += nth) smg[i] = geo.magN[nl * NF + i];
-  sync();
-  for (int it = tid; it < NS + NF; it += nth) {
-    if (it < NS) {
-      const int t = it;
-      MD u[NV], f[ND][NV];
-      for (int a = 0; a < NV; ++a) { u[a] = MD(su[t * NV + a]); u[a].d[a] = R(1); }
-      flux_inviscid<SYS, ND, NV, MD>(ph, u, f);
-      for (int d = 0; d < ND; ++d)
-        for (int a = 0; a < NV; ++a)
-          for (int c = 0; c < NV; ++c) {
-            R acc = R(0);
-            for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d[c];
-            ta[(d * NS + t) * NV2 + a * NV + c] = acc;
-          }
-    } else {
-      const int g = it - NS;
-      R nn[ND];
-      for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
-      MD uL[NV], uR[NV], F[NV];
-      for (int a = 0; a < NV; ++a) {
-        uL[a] = MD(suL[g * NV + a]);
-        uR[a] = MD(suR[g * NV + a]);
-        uL[a].d[a] = R(1);
-      }
-      common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
-      for (int a = 0; a < NV; ++a)
-        for (int c = 0; c < NV; ++c) tL[g * NV2 + a * NV + c] = smg[g] * F[a].d[c];
-    }
-  }
-  sync();
-  OT* Bn = B + geo.boff[nl];
-  for (int i = tid; i < BB * BB; i += nth) {
-    const int col = i / BB, row = i % BB;
-    const int s = col / NV, beta = col % NV, r = row / NV, a = row % NV;
-    const int ab = a * NV + beta;
-    R acc = R(0);
-    for (int d = 0; d < ND; ++d)
-      for (int w = 0; w < WL; ++w)
-        if (dcc[(d * NS + r) * WL + w] == s) acc += dcv[(d * NS + r) * WL + w] * ta[(d * NS + s) * NV2 + ab];
-    for (int w = 0; w < WC; ++w) {
-      const int g = crc[r * WC + w];
-      acc += crv[r * WC + w] * tL[g * NV2 + ab] * sM0[g * NS + s];
-    }
-    const R jv = -(srd[r] * acc);
-    Bn[i] = to_out<OT>(jv);
-    if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + n);
-  }
-}
-
-template <class E, class EO, int NV, class R> constexpr int jac_nb_mixed_lds() {
-  return lds_bytes<R>(E::NS * E::NF) + lds_bytes<R>(E::NF * E::NS) + lds_bytes<R>(EO::NF * EO::NS) +
-         lds_bytes<R>(E::NS) + lds_bytes<R>(E::NF * NV * NV) + lds_bytes<int>(E::NF) + lds_bytes<int>(E::NFACE);
-}
-
-template <class E, class EO, int NV, int SYS, class R, class OT, class Sync>
-FR_HD void jac_nb_mixed_body(int n, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo,
-                             const MixD<R>& mx, const PhysP& ph, const R* UF, OT* B, Sync sync) {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, NFP = E::NFP, NV2 = NV * NV;
-  constexpr int NSO = EO::NS, NFO = EO::NF;
-  constexpr int BB = NS * NV;
-  typedef MDual<R, NV> MD;
-  Lds L{lds};
-  R* sCor = L.take<R>(NS * NF);
-  R* sM0 = L.take<R>(NF * NS);
-  R* sM0o = L.take<R>(NFO * NSO);
-  R* srd = L.take<R>(NS);
-  R* tR = L.take<R>(NF * NV2);       // |N_g| dF/du_R at each flux point
   int* spt = L.take<int>(NF);
   int* snt = L.take<int>(NFACE);
-  const long nl = n;
-  for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
+  long* sbo = L.take<long>(NFACE + 1);  // self block, then each face block
   for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
+  for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
   for (int i = tid; i < NFO * NSO; i += nth) sM0o[i] = mx.M0o[i];
-  for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
-  for (int i = tid; i < NF; i += nth) spt[i] = mx.nbpt[nl * NF + i];
-  for (int i = tid; i < NFACE; i += nth) snt[i] = mx.nbt[nl * NFACE + i];
-  for (int g = tid; g < NF; g += nth) {
-    const long pg = geo.nbfp[nl * NF + g];
-    R nn[ND];
-    for (int d = 0; d < ND; ++d) nn[d] = geo.nrm[(nl * NF + g) * ND + d];
-    MD uL[NV], uR[NV], F[NV];
-    for (int a = 0; a < NV; ++a) {
-      uL[a] = MD(UF[(nl * NF + g) * NV + a]);
-      uR[a] = MD(UF[pg * NV + a]);
-      uR[a].d[a] = R(1);
-    }
-    common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
-    const R mg = geo.magN[nl * NF + g];
-    for (int a = 0; a < NV; ++a)
-      for (int c = 0; c < NV; ++c) tR[g * NV2 + a * NV + c] = mg * F[a].d[c];
-  }
+  for (int i = tid; i < NS * WC; i += nth) { scrc[i] = op.crc[i]; scrv[i] = op.crv[i]; }
+  for (int i = tid; i < ND * NS * NS; i += nth) sDc[i] = R(0);
   sync();
-  for (int f = 0; f < NFACE; ++f) {
-    const bool other = snt[f] != 0;
-    const int nsm = other ? NSO : NS;
-    const R* M0m = other ? sM0o : sM0;
-    const int bm = nsm * NV;
-    OT* Bk = B + mx.fboff[nl * NFACE + f];
-    for (int i = tid; i < BB * bm; i += nth) {
-      const int col = i / BB, row = i % BB;
-      const int s = col / NV, beta = col % NV, r = row / NV, a = row % NV;
-      R acc = R(0);
-      for (int gi = 0; gi < NFP; ++gi) {
-        const int g = f * NFP + gi;
-        acc += sCor[r * NF + g] * tR[g * NV2 + a * NV + beta] * M0m[spt[g] * nsm + s];
-      }
-      const R jv = -(srd[r] * acc);
-      Bk[i] = to_out<OT>(jv);
-      if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + n);
+  // dense Dc_d from its compressed rows (one thread per row: no collisions)
+  for (int i = tid; i < ND * NS; i += nth)
+    for (int w = 0; w < WL; ++w) sDc[i * NS + op.dcc[i * WL + w]] += op.dcv[i * WL + w];
+  for (long nl = n0; nl < n1; ++nl) {
+    for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
+    for (int i = tid; i < NS * ND * ND; i += nth) sS[i] = geo.S[nl * NS * ND * ND + i];
+    for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
+    for (int i = tid; i < NF * NV; i += nth) {
+      const int g = i / NV, a = i % NV;
+      suL[i] = UF[(nl * NF + g) * NV + a];
+      suR[i] = UF[(long)geo.nbfp[nl * NF + g] * NV + a];
     }
+    for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
+    for (int i = tid; i < NF; i += nth) { smg[i] = geo.magN[nl * NF + i]; spt[i] = mx.nbpt[nl * NF + i]; }
+    for (int i = tid; i < NFACE; i += nth) snt[i] = mx.nbt[nl * NFACE + i];
+    for (int i = tid; i <= NFACE; i += nth) sbo[i] = i == 0 ? geo.boff[nl] : mx.fboff[nl * NFACE + i - 1];
+    sync();
+    // pointwise flux derivatives: A_d at the solution points, the common
+    // flux's derivatives with respect to either side at the flux points
+#pragma unroll 1
+    for (int it = tid; it < NS + 2 * NF; it += nth) {
+      if (it < NS) {
+        const int t = it;
+        MD u[NV], f[ND][NV];
+        for (int a = 0; a < NV; ++a) { u[a] = MD(su[t * NV + a]); u[a].d[a] = R(1); }
+        flux_inviscid<SYS, ND, NV, MD>(ph, u, f);
+        for (int d = 0; d < ND; ++d)
+          for (int a = 0; a < NV; ++a)
+            for (int c = 0; c < NV; ++c) {
+              R acc = R(0);
+              for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d[c];
+              ta[(d * NS + t) * NV2 + a * NV + c] = acc;
+            }
+      } else {
+        const int g = (it - NS) >> 1, side = (it - NS) & 1;
+        R nn[ND];
+        for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
+        MD uL[NV], uR[NV], F[NV];
+        for (int a = 0; a < NV; ++a) {
+          uL[a] = MD(suL[g * NV + a]);
+          uR[a] = MD(suR[g * NV + a]);
+          (side ? uR : uL)[a].d[a] = R(1);
+        }
+        common_inviscid<SYS, ND, NV, MD>(ph, uL, uR, nn, F);
+        R* o = side ? tR : tL;
+        for (int a = 0; a < NV; ++a)
+          for (int c = 0; c < NV; ++c) o[g * NV2 + a * NV + c] = smg[g] * F[a].d[c];
+      }
+    }
+    sync();
+    bool bad = false;
+    // self block
+#pragma unroll 1
+    for (int i = tid; i < NS * NS; i += nth) {
+      const int r = i % NS, s = i / NS;
+      R acc[NV2];
+      for (int k = 0; k < NV2; ++k) acc[k] = R(0);
+      for (int d = 0; d < ND; ++d) {
+        const R c = sDc[(d * NS + r) * NS + s];
+        if (c != R(0))
+          for (int k = 0; k < NV2; ++k) acc[k] += c * ta[(d * NS + s) * NV2 + k];
+      }
+#pragma unroll 1
+      for (int w = 0; w < WC; ++w) {     // the non-zeros of row rho of the correction
+        const int g = scrc[r * WC + w];
+        const R c = scrv[r * WC + w] * sM0[g * NS + s];
+        if (c != R(0))
+          for (int k = 0; k < NV2; ++k) acc[k] += c * tL[g * NV2 + k];
+      }
+      const R sc = -srd[r];
+      OT* Bn = B + sbo[0];
+      for (int be = 0; be < NV; ++be) {
+        R v[NV];
+        for (int a = 0; a < NV; ++a) { v[a] = sc * acc[a * NV + be]; bad |= !fr_finite(v[a]); }
+        store_rows<NV>(Bn + (long)(s * NV + be) * BB + r * NV, v);
+      }
+    }
+    // face blocks, b_n x b_m
+#pragma unroll 1
+    for (int f = 0; f < NFACE; ++f) {
+      const bool other = snt[f] != 0;
+      const int nsm = other ? NSO : NS;
+      const R* M0m = other ? sM0o : sM0;
+      OT* Bk = B + sbo[1 + f];
+#pragma unroll 1
+      for (int i = tid; i < NS * nsm; i += nth) {
+        const int r = i % NS, s = i / NS;
+        R acc[NV2];
+        for (int k = 0; k < NV2; ++k) acc[k] = R(0);
+        for (int gi = 0; gi < NFP; ++gi) {
+          const int g = f * NFP + gi;
+          const R c = sCor[r * NF + g] * M0m[spt[g] * nsm + s];
+          if (c != R(0))
+            for (int k = 0; k < NV2; ++k) acc[k] += c * tR[g * NV2 + k];
+        }
+        const R sc = -srd[r];
+        for (int be = 0; be < NV; ++be) {
+          R v[NV];
+          for (int a = 0; a < NV; ++a) { v[a] = sc * acc[a * NV + be]; bad |= !fr_finite(v[a]); }
+          store_rows<NV>(Bk + (long)(s * NV + be) * BB + r * NV, v);
+        }
+      }
+    }
+    if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + nl);
+    sync();      // the next element's data overwrite the tables
   }
 }
