@@ -61,6 +61,16 @@ static int tile_rt(int code) {
 #undef TCASE
   return 1;
 }
+// elements per unit of the assembly work list: mixed-mesh groups are
+// assembled in tiles
+static int asm_unit_rt(int code) {
+  if (code < kMixCode) return 1;
+  code -= kMixCode;
+#define ACASE(ET, P) if (code == bcode(ET, P)) return mixed_tile<Elem<ET, P>>();
+  FR_BATCH_CASES(ACASE)
+#undef ACASE
+  return 1;
+}
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 template <int SYS> constexpr int res_lds() {
@@ -143,9 +153,12 @@ __device__ __forceinline__ void jac_item(char* lds, const BDesc* D, const BPtrs&
       // a group of a mixed mesh (inviscid): self blocks, then the face
       // blocks through the neighbour's own interpolation; blocks at absolute
       // offsets in the mesh's array
+      // items count tiles of mixed_tile<E>() elements
+      constexpr int TE = mixed_tile<E>();
       const MixD<float> md = D[w.desc].md;
-      jac_mixed_inv_body<E, OtherElem<ET, DEG>, kNV, SYS, float, float>(w.first, w.first + w.count, tid, nth, lds,
-                                                                        op, geo, md, ph, U, UF, B, DevSync());
+      const int n0 = w.first * TE, n1 = min(ne, (w.first + w.count) * TE);
+      jac_mixed_inv_body<E, OtherElem<ET, DEG>, kNV, SYS, float, float>(n0, n1, tid, nth, lds, op, geo, md, ph, U,
+                                                                        UF, B, DevSync());
       __syncthreads();
       return;
     }
@@ -291,7 +304,7 @@ static void make_items(fr_batch_s* b, bool tiles, const int* k, std::vector<BIte
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     const fr_ctx_s* c = b->ctx[i];
     const int code = desc_code(b, i);
-    const int te = tiles ? tile_rt(code) : 1;
+    const int te = tiles ? tile_rt(code) : asm_unit_rt(code);
     const int units = (int)((c->ne + te - 1) / te);
     const int per = std::max(1, k[code]);
     for (int u = 0; u < units; u += per) {

@@ -256,8 +256,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
         hipLaunchKernelGGL((k_trace<E, NV, R, R, R>), dim3((ne + TE - 1) / TE), dim3(kThreads), 0, c->stream, op, ne,
                            U, (const R*)nullptr, (R*)c->UF);
       } else if (stage == 1) {
-        // a few elements per workgroup: the operators are staged once for them
-        const int per = ne >= 4096 ? 4 : (ne >= 1024 ? 2 : 1);
+        // a few tiles per workgroup: the operators are staged once for them
+        constexpr int TE = mixed_tile<E>();
+        const int per = TE * (ne >= 4096 * TE ? 4 : (ne >= 1024 * TE ? 2 : 1));
         hipLaunchKernelGGL((k_jac_mixed_inv<E, EO, NV, SYS, R, OT>), dim3((ne + per - 1) / per), dim3(kThreads), 0,
                            c->stream, op, geo, *mx, c->ph, U, (const R*)c->UF, B, ne, per);
       }

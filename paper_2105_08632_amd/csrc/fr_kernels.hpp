@@ -938,18 +938,23 @@ template <int NV, class OT, class R> FR_HD void store_rows(OT* dst, const R* v) 
 // with A_d = sum_k S_dk df_k/du (eq. "transformed_quantities") and Dc_d =
 // D_d - Cor diag(nref_d) M0 (the flux's own trace leaves through the
 // correction, eq. "divergence_fr"); face blocks as described at MixD, with
-// |N_g| dF/du_R.  The operators are staged once per call; per element, one
-// thread per (rho, sigma) pair forms the NV x NV sub-block, so each operator
-// coefficient is read once for NV^2 outputs, and zero coefficients (the
-// sparse rows of tensor elements) are skipped.
+// |N_g| dF/du_R.  The operators are staged once per call and the elements
+// taken in tiles of mixed_tile<E>() (so that low degrees still occupy the
+// workgroup); one thread per (element, rho, sigma) forms an NV x NV
+// sub-block, so each operator coefficient is read once for NV^2 outputs, and
+// zero coefficients (the sparse rows of tensor elements) are skipped.
+template <class E> constexpr int mixed_tile() {
+  return E::NS * E::NS >= 128 ? 1 : (E::NS * E::NS >= 64 ? 2 : (E::NS * E::NS >= 32 ? 4 : (E::NS * E::NS >= 16 ? 8 : 16)));
+}
 template <class E, class EO, int NV, class R> constexpr int jac_mixed_inv_lds() {
   constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, WC = E::WC, NV2 = NV * NV;
+  constexpr int TE = mixed_tile<E>();
   return lds_bytes<R>(NF * NS) + lds_bytes<R>(NS * NF) + lds_bytes<R>(ND * NS * NS) + lds_bytes<int>(NS * WC) +
-         lds_bytes<R>(NS * WC) +
-         lds_bytes<R>(EO::NF * EO::NS) + lds_bytes<R>(ND * NS * NV2) + 2 * lds_bytes<R>(NF * NV2) +
-         lds_bytes<R>(NS) + lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS * NV) + 2 * lds_bytes<R>(NF * NV) +
-         lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF) + lds_bytes<int>(NFACE) +
-         lds_bytes<long>(NFACE + 1);
+         lds_bytes<R>(NS * WC) + lds_bytes<R>(EO::NF * EO::NS) +
+         TE * (lds_bytes<R>(ND * NS * NV2) + 2 * lds_bytes<R>(NF * NV2) + lds_bytes<R>(NS) +
+               lds_bytes<R>(NS * ND * ND) + lds_bytes<R>(NS * NV) + 2 * lds_bytes<R>(NF * NV) +
+               lds_bytes<R>(NF * ND) + lds_bytes<R>(NF) + lds_bytes<int>(NF) + lds_bytes<int>(NFACE) +
+               lds_bytes<long>(NFACE + 1));
 }
 
 template <class E, class EO, int NV, int SYS, class R, class OT, class Sync>
@@ -957,6 +962,7 @@ FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const
                               const MixD<R>& mx, const PhysP& ph, const R* U, const R* UF, OT* B, Sync sync) {
   constexpr int NS = E::NS, NF = E::NF, ND = E::ND, NFACE = E::NFACE, NFP = E::NFP, WL = E::WL, WC = E::WC;
   constexpr int NV2 = NV * NV, NSO = EO::NS, NFO = EO::NF, BB = NS * NV;
+  constexpr int TE = mixed_tile<E>(), NSM = NS > NSO ? NS : NSO;
   typedef MDual<R, NV> MD;
   Lds L{lds};
   R* sM0 = L.take<R>(NF * NS);
@@ -965,19 +971,20 @@ FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const
   int* scrc = L.take<int>(NS * WC);     // compressed rows of the correction
   R* scrv = L.take<R>(NS * WC);
   R* sM0o = L.take<R>(NFO * NSO);
-  R* ta = L.take<R>(ND * NS * NV2);     // A_d(sigma)[alpha][beta]
-  R* tL = L.take<R>(NF * NV2);          // |N_g| dF/du_L (g)
-  R* tR = L.take<R>(NF * NV2);          // |N_g| dF/du_R (g)
-  R* srd = L.take<R>(NS);
-  R* sS = L.take<R>(NS * ND * ND);
-  R* su = L.take<R>(NS * NV);
-  R* suL = L.take<R>(NF * NV);
-  R* suR = L.take<R>(NF * NV);
-  R* snn = L.take<R>(NF * ND);
-  R* smg = L.take<R>(NF);
-  int* spt = L.take<int>(NF);
-  int* snt = L.take<int>(NFACE);
-  long* sbo = L.take<long>(NFACE + 1);  // self block, then each face block
+  // per element of the tile
+  R* ta = L.take<R>(TE * ND * NS * NV2);   // A_d(sigma)[alpha][beta]
+  R* tL = L.take<R>(TE * NF * NV2);        // |N_g| dF/du_L (g)
+  R* tR = L.take<R>(TE * NF * NV2);        // |N_g| dF/du_R (g)
+  R* srd = L.take<R>(TE * NS);
+  R* sS = L.take<R>(TE * NS * ND * ND);
+  R* su = L.take<R>(TE * NS * NV);
+  R* suL = L.take<R>(TE * NF * NV);
+  R* suR = L.take<R>(TE * NF * NV);
+  R* snn = L.take<R>(TE * NF * ND);
+  R* smg = L.take<R>(TE * NF);
+  int* spt = L.take<int>(TE * NF);
+  int* snt = L.take<int>(TE * NFACE);
+  long* sbo = L.take<long>(TE * (NFACE + 1));  // self block, then each face block
   for (int i = tid; i < NF * NS; i += nth) sM0[i] = op.M0[i];
   for (int i = tid; i < NS * NF; i += nth) sCor[i] = op.Cor[i];
   for (int i = tid; i < NFO * NSO; i += nth) sM0o[i] = mx.M0o[i];
@@ -987,26 +994,32 @@ FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const
   // dense Dc_d from its compressed rows (one thread per row: no collisions)
   for (int i = tid; i < ND * NS; i += nth)
     for (int w = 0; w < WL; ++w) sDc[i * NS + op.dcc[i * WL + w]] += op.dcv[i * WL + w];
-  for (long nl = n0; nl < n1; ++nl) {
-    for (int i = tid; i < NS; i += nth) srd[i] = geo.rdet[nl * NS + i];
-    for (int i = tid; i < NS * ND * ND; i += nth) sS[i] = geo.S[nl * NS * ND * ND + i];
-    for (int i = tid; i < NS * NV; i += nth) su[i] = U[nl * NS * NV + i];
-    for (int i = tid; i < NF * NV; i += nth) {
-      const int g = i / NV, a = i % NV;
-      suL[i] = UF[(nl * NF + g) * NV + a];
-      suR[i] = UF[(long)geo.nbfp[nl * NF + g] * NV + a];
+  for (long t0 = n0; t0 < n1; t0 += TE) {
+    const int nte = (int)((n1 - t0) < TE ? (n1 - t0) : TE);
+    for (int i = tid; i < nte * NS; i += nth) srd[i] = geo.rdet[t0 * NS + i];
+    for (int i = tid; i < nte * NS * ND * ND; i += nth) sS[i] = geo.S[t0 * NS * ND * ND + i];
+    for (int i = tid; i < nte * NS * NV; i += nth) su[i] = U[t0 * NS * NV + i];
+    for (int i = tid; i < nte * NF * NV; i += nth) {
+      const long fg = t0 * NF + i / NV;                 // the tile's flux points are contiguous
+      const int a = i % NV;
+      suL[i] = UF[fg * NV + a];
+      suR[i] = UF[(long)geo.nbfp[fg] * NV + a];
     }
-    for (int i = tid; i < NF * ND; i += nth) snn[i] = geo.nrm[nl * NF * ND + i];
-    for (int i = tid; i < NF; i += nth) { smg[i] = geo.magN[nl * NF + i]; spt[i] = mx.nbpt[nl * NF + i]; }
-    for (int i = tid; i < NFACE; i += nth) snt[i] = mx.nbt[nl * NFACE + i];
-    for (int i = tid; i <= NFACE; i += nth) sbo[i] = i == 0 ? geo.boff[nl] : mx.fboff[nl * NFACE + i - 1];
+    for (int i = tid; i < nte * NF * ND; i += nth) snn[i] = geo.nrm[t0 * NF * ND + i];
+    for (int i = tid; i < nte * NF; i += nth) { smg[i] = geo.magN[t0 * NF + i]; spt[i] = mx.nbpt[t0 * NF + i]; }
+    for (int i = tid; i < nte * NFACE; i += nth) snt[i] = mx.nbt[t0 * NFACE + i];
+    for (int i = tid; i < nte * (NFACE + 1); i += nth) {
+      const int e = i / (NFACE + 1), k = i % (NFACE + 1);
+      sbo[i] = k == 0 ? geo.boff[t0 + e] : mx.fboff[(t0 + e) * NFACE + k - 1];
+    }
     sync();
     // pointwise flux derivatives: A_d at the solution points, the common
     // flux's derivatives with respect to either side at the flux points
 #pragma unroll 1
-    for (int it = tid; it < NS + 2 * NF; it += nth) {
-      if (it < NS) {
-        const int t = it;
+    for (int it = tid; it < nte * (NS + 2 * NF); it += nth) {
+      const int e = it / (NS + 2 * NF), j = it % (NS + 2 * NF);
+      if (j < NS) {
+        const int t = e * NS + j;
         MD u[NV], f[ND][NV];
         for (int a = 0; a < NV; ++a) { u[a] = MD(su[t * NV + a]); u[a].d[a] = R(1); }
         flux_inviscid<SYS, ND, NV, MD>(ph, u, f);
@@ -1015,10 +1028,10 @@ FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const
             for (int c = 0; c < NV; ++c) {
               R acc = R(0);
               for (int k = 0; k < ND; ++k) acc += sS[(t * ND + d) * ND + k] * f[k][a].d[c];
-              ta[(d * NS + t) * NV2 + a * NV + c] = acc;
+              ta[((e * ND + d) * NS + j) * NV2 + a * NV + c] = acc;
             }
       } else {
-        const int g = (it - NS) >> 1, side = (it - NS) & 1;
+        const int g = e * NF + ((j - NS) >> 1), side = (j - NS) & 1;
         R nn[ND];
         for (int d = 0; d < ND; ++d) nn[d] = snn[g * ND + d];
         MD uL[NV], uR[NV], F[NV];
@@ -1034,60 +1047,65 @@ FR_HD void jac_mixed_inv_body(int n0, int n1, int tid, int nth, char* lds, const
       }
     }
     sync();
-    bool bad = false;
-    // self block
+    // self blocks
 #pragma unroll 1
-    for (int i = tid; i < NS * NS; i += nth) {
-      const int r = i % NS, s = i / NS;
+    for (int i = tid; i < nte * NS * NS; i += nth) {
+      const int e = i / (NS * NS), r = i % NS, s = (i / NS) % NS;
       R acc[NV2];
       for (int k = 0; k < NV2; ++k) acc[k] = R(0);
       for (int d = 0; d < ND; ++d) {
         const R c = sDc[(d * NS + r) * NS + s];
         if (c != R(0))
-          for (int k = 0; k < NV2; ++k) acc[k] += c * ta[(d * NS + s) * NV2 + k];
+          for (int k = 0; k < NV2; ++k) acc[k] += c * ta[((e * ND + d) * NS + s) * NV2 + k];
       }
 #pragma unroll 1
       for (int w = 0; w < WC; ++w) {     // the non-zeros of row rho of the correction
         const int g = scrc[r * WC + w];
         const R c = scrv[r * WC + w] * sM0[g * NS + s];
         if (c != R(0))
-          for (int k = 0; k < NV2; ++k) acc[k] += c * tL[g * NV2 + k];
+          for (int k = 0; k < NV2; ++k) acc[k] += c * tL[(e * NF + g) * NV2 + k];
       }
-      const R sc = -srd[r];
-      OT* Bn = B + sbo[0];
+      const R sc = -srd[e * NS + r];
+      OT* Bn = B + sbo[e * (NFACE + 1)];
       for (int be = 0; be < NV; ++be) {
         R v[NV];
-        for (int a = 0; a < NV; ++a) { v[a] = sc * acc[a * NV + be]; bad |= !fr_finite(v[a]); }
+        for (int a = 0; a < NV; ++a) {
+          v[a] = sc * acc[a * NV + be];
+          if (!fr_finite(v[a])) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + t0 + e);
+        }
         store_rows<NV>(Bn + (long)(s * NV + be) * BB + r * NV, v);
       }
     }
     // face blocks, b_n x b_m
 #pragma unroll 1
     for (int f = 0; f < NFACE; ++f) {
-      const bool other = snt[f] != 0;
-      const int nsm = other ? NSO : NS;
-      const R* M0m = other ? sM0o : sM0;
-      OT* Bk = B + sbo[1 + f];
 #pragma unroll 1
-      for (int i = tid; i < NS * nsm; i += nth) {
-        const int r = i % NS, s = i / NS;
+      for (int i = tid; i < nte * NS * NSM; i += nth) {
+        const int e = i / (NS * NSM), r = i % NS, s = (i / NS) % NSM;
+        const bool other = snt[e * NFACE + f] != 0;
+        const int nsm = other ? NSO : NS;
+        if (s >= nsm) continue;
+        const R* M0m = other ? sM0o : sM0;
         R acc[NV2];
         for (int k = 0; k < NV2; ++k) acc[k] = R(0);
         for (int gi = 0; gi < NFP; ++gi) {
           const int g = f * NFP + gi;
-          const R c = sCor[r * NF + g] * M0m[spt[g] * nsm + s];
+          const R c = sCor[r * NF + g] * M0m[spt[e * NF + g] * nsm + s];
           if (c != R(0))
-            for (int k = 0; k < NV2; ++k) acc[k] += c * tR[g * NV2 + k];
+            for (int k = 0; k < NV2; ++k) acc[k] += c * tR[(e * NF + g) * NV2 + k];
         }
-        const R sc = -srd[r];
+        const R sc = -srd[e * NS + r];
+        OT* Bk = B + sbo[e * (NFACE + 1) + 1 + f];
         for (int be = 0; be < NV; ++be) {
           R v[NV];
-          for (int a = 0; a < NV; ++a) { v[a] = sc * acc[a * NV + be]; bad |= !fr_finite(v[a]); }
+          for (int a = 0; a < NV; ++a) {
+            v[a] = sc * acc[a * NV + be];
+            if (!fr_finite(v[a])) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + t0 + e);
+          }
           store_rows<NV>(Bk + (long)(s * NV + be) * BB + r * NV, v);
         }
       }
     }
-    if (bad) fr_flag_nonfinite(geo.status, FR_NF_BLOCKS, geo.e0 + nl);
-    sync();      // the next element's data overwrite the tables
+    sync();      // the next tile's data overwrite the tables
   }
 }
