@@ -247,13 +247,127 @@ __global__ void k_reduce_partials(int k, int nblk, const double* partial, double
   }
 }
 
-// w -= sum_j h[j] V_j
-__global__ void k_multi_axpy(long n, int k, const double* h, const double* V, long ld, double* w) {
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    double acc = w[i];
-    for (int j = 0; j < k; ++j) acc -= h[j] * V[(long)j * ld + i];
-    w[i] = acc;
+// ---- Arnoldi orthogonalisation: classical Gram-Schmidt with one
+// re-orthogonalisation, in three sweeps over the basis V_0 .. V_{K-1}:
+//   0: partial sums of V^T w
+//   1: h1 = the sum of sweep 0's partials; w <- w - V h1, then partial sums of
+//      V^T w (each entry projected right after its update, so the basis is
+//      read once for both)
+//   2: h2 likewise; w <- w - V h2, partial sums of w.w
+// Each workgroup of a sweep adds the previous sweep's per-workgroup partials
+// itself, in a fixed order (stream order guarantees they are complete), so
+// the results are deterministic, need no separate reduction launch and stay
+// on the device (graph-capturable).  Workgroup 0 stores h1 / h2.
+constexpr int kOrthBlocks = 512, kOrthThreads = 512, kMaxK = 32;
+
+// out[q] = sum over workgroups b < nblk of p[b][q], q < nq; every thread of
+// the workgroup gets the sums (through red, [waves][kMaxK] plus [kMaxK]).
+__device__ __forceinline__ void orth_sum_partials(const double* p, int nblk, int nq, double (*red)[kMaxK],
+                                                  double* sums) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kOrthThreads) v += p[(long)b * kMaxK + q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave][q] = v;
   }
+  __syncthreads();
+  if (threadIdx.x < nq) {
+    double v = 0.0;
+    for (int wv = 0; wv < kOrthThreads / 64; ++wv) v += red[wv][threadIdx.x];
+    sums[threadIdx.x] = v;
+  }
+  __syncthreads();
+}
+
+// K = the basis size, a template argument: the K loads of an entry are issued
+// back to back without guards.
+template <int MODE, int K>
+__global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, long ld, double* w, const double* pin,
+                                                       double* pout, double* hout) {
+  static_assert(K >= 1 && K <= kMaxK, "basis size");
+  __shared__ double red[kOrthThreads / 64][kMaxK];
+  __shared__ double hs[kMaxK];
+  constexpr int NA = MODE == 2 ? 1 : K;
+  double acc[NA], hq[K];
+  if constexpr (MODE >= 1) {
+    orth_sum_partials(pin, gridDim.x, K, red, hs);
+    if (blockIdx.x == 0 && threadIdx.x < K) hout[threadIdx.x] = hs[threadIdx.x];
+  }
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    if constexpr (MODE >= 1) hq[q] = hs[q];
+    else hq[q] = 0.0;
+  }
+  for (long i = (long)blockIdx.x * kOrthThreads + threadIdx.x; i < n; i += (long)gridDim.x * kOrthThreads) {
+    double vv[K];
+    const double* Vi = V + i;
+#pragma unroll
+    for (int q = 0; q < K; ++q) vv[q] = Vi[(long)q * ld];
+    double wi = w[i];
+    if constexpr (MODE >= 1) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) wi -= hq[q] * vv[q];
+      w[i] = wi;
+    }
+    if constexpr (MODE <= 1) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] += vv[q] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  __syncthreads();                    // red is reused
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    double v = acc[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NA) {
+    double v = 0.0;
+    for (int wv = 0; wv < kOrthThreads / 64; ++wv) v += red[wv][threadIdx.x];
+    pout[(long)blockIdx.x * kMaxK + threadIdx.x] = v;
+  }
+}
+
+template <int MODE, int K>
+static void launch_orth_k(hipStream_t st, int k, long n, const double* V, long ld, double* w, const double* pin,
+                          double* pout, double* hout) {
+  if constexpr (K <= kMaxK) {
+    if (k == K)
+      hipLaunchKernelGGL((k_orth<MODE, K>), dim3(kOrthBlocks), dim3(kOrthThreads), 0, st, n, V, ld, w, pin, pout, hout);
+    else
+      launch_orth_k<MODE, K + 1>(st, k, n, V, ld, w, pin, pout, hout);
+  }
+}
+template <int MODE>
+static void launch_orth(hipStream_t st, int k, long n, const double* V, long ld, double* w, const double* pin,
+                        double* pout, double* hout) {
+  launch_orth_k<MODE, 1>(st, k, n, V, ld, w, pin, pout, hout);
+}
+
+// The end of an Arnoldi step: |w| from the last sweep's partials; workgroup 0
+// writes the Hessenberg column H[i][j] = h1[i] + h2[i] (i <= j), H[j+1][j] =
+// |w| and dn = w.w; v_{j+1} = w / |w| (0 on breakdown).
+__global__ void __launch_bounds__(kOrthThreads) k_orth_finish(long n, int j, int m, const double* p2, int nblk,
+                                                              const double* h1, const double* h2, const double* w,
+                                                              double* v, double* H, double* dn) {
+  __shared__ double red[kOrthThreads / 64][kMaxK];
+  __shared__ double nn[1];
+  orth_sum_partials(p2, nblk, 1, red, nn);
+  const double hn = sqrt(fmax(nn[0], 0.0));
+  if (blockIdx.x == 0) {
+    if (threadIdx.x <= j) H[threadIdx.x * m + j] = h1[threadIdx.x] + h2[threadIdx.x];
+    if (threadIdx.x == 0) { H[(j + 1) * m + j] = hn; *dn = nn[0]; }
+  }
+  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (long i = (long)blockIdx.x * kOrthThreads + threadIdx.x; i < n; i += (long)gridDim.x * kOrthThreads)
+    v[i] = w[i] * inv;
 }
 
 __global__ void k_fill(long n, double v, double* x) {
@@ -271,20 +385,6 @@ __global__ void k_multi_axpy_add(long n, int k, const double* y, const double* Z
 
 // ---- device-resident Arnoldi step pieces (graph-capturable: every scalar
 // stays on the device)
-// H[i][j] = a[i] + b[i], i <= j (the two classical Gram-Schmidt passes)
-__global__ void k_arnoldi_col(int j, int m, const double* a, const double* b, double* H) {
-  const int i = threadIdx.x;
-  if (i <= j) H[i * m + j] = a[i] + b[i];
-}
-
-// hn = sqrt(*dn); H[j+1][j] = hn; v = w / hn (0 on breakdown)
-__global__ void k_norm_scale(long n, int j, int m, const double* dn, const double* w, double* v, double* H) {
-  const double hn = sqrt(fmax(*dn, 0.0));
-  if (blockIdx.x == 0 && threadIdx.x == 0) H[(j + 1) * m + j] = hn;
-  const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) v[i] = w[i] * inv;
-}
-
 // Givens rotations on Hessenberg column j (one thread): previous rotations,
 // then the new one; g is the rotated right-hand side, est[j] = |g[j+1]|.
 __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* est) {
@@ -710,7 +810,9 @@ struct fr_solver_s {
   double* hstate = nullptr;      // pinned copy of the state block
   hipStream_t cs = nullptr;      // the solver's own (capturable) stream
   hipEvent_t join0 = nullptr, join1 = nullptr;
-  hipGraphExec_t cycle = nullptr;
+  double* opart = nullptr;       // per-workgroup partial sums of the three Gram-Schmidt sweeps
+  static constexpr int kChunk = 5, kMaxChunks = (31 + kChunk - 1) / kChunk;
+  hipGraphExec_t chunk[kMaxChunks] = {};   // captured Arnoldi steps [c kChunk, (c+1) kChunk)
   const void* key_U = nullptr; const void* key_pc = nullptr; double key_dt = 0.0;
 };
 
@@ -747,7 +849,67 @@ static fr_status precond(fr_solver_s* s, fr_precond_s* pc, const double* v, doub
   return fr_apply_precond(pc, v, z);
 }
 
+// One Arnoldi step j with every scalar on the device: z_j = M^-1 v_j (or,
+// with zsrc, z_j = zscale zsrc), w = A z_j, two classical Gram-Schmidt
+// passes, the Hessenberg column, v_{j+1} = w / |w| and the Givens rotation
+// of column j (est[j] = the residual estimate).  Graph-capturable.
+static fr_status arnoldi_step(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt, int j, const double* zsrc,
+                              double zscale) {
+  fr_ctx_s* c = s->ctx;
+  const int m = s->m;
+  const long N = s->N;
+  const int grid = grid_for(N, 256);
+  double* vj = s->V + (long)j * N;
+  double* zj = s->Z + (long)j * N;
+  fr_status st = FR_OK;
+  if (zsrc) hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(256), 0, c->stream, N, zscale, zsrc, 0.0, nullptr, zj);
+  else if (pc) st = fr_apply_precond(pc, vj, zj);
+  else hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(256), 0, c->stream, N, 1.0, vj, 0.0, nullptr, zj);
+  if (st == FR_OK) st = apply_A(s, U, dt, zj, s->w, nullptr);
+  if (st) return st;
+  double* p0 = s->opart;
+  double* p1 = p0 + kOrthBlocks * kMaxK;
+  double* p2 = p1 + kOrthBlocks * kMaxK;
+  launch_orth<0>(c->stream, j + 1, N, s->V, N, s->w, nullptr, p0, nullptr);
+  launch_orth<1>(c->stream, j + 1, N, s->V, N, s->w, p0, p1, s->dh1);
+  launch_orth<2>(c->stream, j + 1, N, s->V, N, s->w, p1, p2, s->dh2);
+  hipLaunchKernelGGL(k_orth_finish, dim3(kOrthBlocks), dim3(kOrthThreads), 0, c->stream, N, j, m, (const double*)p2,
+                     kOrthBlocks, (const double*)s->dh1, (const double*)s->dh2, (const double*)s->w,
+                     s->V + (long)(j + 1) * N, s->dH, s->dn);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, j, m, s->dH, s->dcs, s->dsn, s->dg, s->dest);
+  HIPCHK(c, hipGetLastError());
+  return FR_OK;
+}
+
+// Reads the Hessenberg state after jj steps (H, g, est) and solves the
+// triangular system; returns the number of steps that enter the update (the
+// first whose estimate meets the tolerance, or the breakdown).
+static fr_status cycle_solution(fr_solver_s* s, int jj, double tol, std::vector<double>& y, int* used) {
+  fr_ctx_s* c = s->ctx;
+  const int m = s->m;
+  const size_t nstate = (size_t)(m + 1) * m + (m + 1) + m;    // H, g, est
+  HIPCHK(c, hipMemcpyAsync(s->hstate, s->dH, nstate * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double* H = s->hstate;
+  const double* g = H + (size_t)(m + 1) * m;
+  const double* est = g + (m + 1);
+  int n = jj;
+  for (int j = 0; j < jj; ++j) {
+    if (H[j * m + j] == 0.0) { n = j; break; }          // breakdown: the Krylov space is exhausted
+    if (est[j] <= tol) { n = j + 1; break; }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int k = i + 1; k < n; ++k) acc -= H[i * m + k] * y[k];
+    y[i] = acc / H[i * m + i];
+  }
+  *used = n;
+  return FR_OK;
+}
+
 // GMRES(m) on A x = rhs from x = 0; returns iterations, true residual norm.
+// The Arnoldi steps run on the device (arnoldi_step); the host reads the
+// residual estimate after each step to stop at the tolerance.
 // With aug = k > 0 this is loose GMRES, LGMRES(m - k, k) (Baker, Jessup and
 // Manteuffel, SIAM J. Matrix Anal. Appl. 26, 2005): the last k directions of
 // every cycle are the corrections x_i - x_{i-1} of the k previous cycles,
@@ -759,7 +921,7 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
   fr_ctx_s* c = s->ctx;
   const int m = s->m;
   const long N = s->N;
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), hj(m + 1), hj2(m + 1), y(m);
+  std::vector<double> g0(m + 1, 0.0), y(m);
   aug = std::min(aug, m - 1);
   std::vector<int> order;              // slots of the stored corrections, newest first
   double aug_norm[kAugMax + 1] = {};
@@ -781,65 +943,35 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
   while (true) {
     // v_0 = r / beta
     if ((st = axpby(s, 1.0 / beta, s->w, 0.0, nullptr, s->V))) return st;
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    g0[0] = beta;
+    HIPCHK(c, hipMemcpyAsync(s->dg, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
     int j = 0;
-    double est = beta;
     const int mk = m - (int)order.size();   // directions from the preconditioned Arnoldi vectors
     for (; j < m && total < maxit; ++j, ++total) {
-      double* vj = s->V + (long)j * N;
-      double* zj = s->Z + (long)j * N;
-      if (j < mk) {
-        if ((st = precond(s, pc, vj, zj))) return st;
-      } else {
+      const double* zsrc = nullptr;
+      double zscale = 1.0;
+      if (j >= mk) {
         const int slot = order[j - mk];
-        if ((st = axpby(s, 1.0 / aug_norm[slot], s->Aug + (long)slot * N, 0.0, nullptr, zj))) return st;
+        zsrc = s->Aug + (long)slot * N;
+        zscale = 1.0 / aug_norm[slot];
       }
-      if ((st = apply_A(s, U, dt, zj, s->w, nullptr))) return st;
-      // classical Gram-Schmidt, twice
-      if ((st = dots(s, j + 1, s->V, s->w, hj.data()))) return st;
-      HIPCHK(c, hipMemcpyAsync(s->hcol, hj.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
-      hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j + 1, s->hcol, s->V, N, s->w);
-      if ((st = dots(s, j + 1, s->V, s->w, hj2.data()))) return st;
-      HIPCHK(c, hipMemcpyAsync(s->hcol, hj2.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
-      hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j + 1, s->hcol, s->V, N, s->w);
-      HIPCHK(c, hipGetLastError());
-      for (int i = 0; i <= j; ++i) H[i * m + j] = hj[i] + hj2[i];
-      double hn;
-      if ((st = dots(s, 1, s->w, s->w, &hn))) return st;
-      hn = std::sqrt(hn);
-      H[(j + 1) * m + j] = hn;
-      if (hn > 0.0 && (st = axpby(s, 1.0 / hn, s->w, 0.0, nullptr, s->V + (long)(j + 1) * N))) return st;
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        double a = H[i * m + j], bb = H[(i + 1) * m + j];
-        H[i * m + j] = cs[i] * a + sn[i] * bb;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
-      }
-      double a = H[j * m + j], bb = H[(j + 1) * m + j];
-      double r = std::hypot(a, bb);
-      cs[j] = r > 0 ? a / r : 1.0;
-      sn[j] = r > 0 ? bb / r : 0.0;
-      H[j * m + j] = r;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      est = std::fabs(g[j + 1]);
-      if (est <= rtol * b0 || hn == 0.0) { ++j; ++total; break; }
+      if ((st = arnoldi_step(s, pc, U, dt, j, zsrc, zscale))) return st;
+      HIPCHK(c, hipMemcpyAsync(s->host, s->dest + j, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(s->host + 1, s->dn, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (s->host[0] <= rtol * b0 || !(s->host[1] > 0.0)) { ++j; ++total; break; }
     }
-    // y = H^{-1} g, x += Z y
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int k = i + 1; k < j; ++k) acc -= H[i * m + k] * y[k];
-      y[i] = acc / H[i * m + i];
-    }
-    HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), j * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int used = 0;
+    if ((st = cycle_solution(s, j, rtol * b0, y, &used))) return st;
+    if (used > 0) HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), used * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (aug > 0) {
       // the cycle's correction d = Z y is kept for the next cycles (the ring
       // has k + 1 slots, so the slot written is never one this cycle used)
       double* d = s->Aug + (long)ring * N;
       hipLaunchKernelGGL(k_fill, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, 0.0, d);
-      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, d);
+      if (used > 0)
+        hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, used, s->hcol, s->Z,
+                           N, d);
       HIPCHK(c, hipGetLastError());
       if ((st = axpby(s, 1.0, x, 1.0, d, x))) return st;
       double dn;
@@ -851,8 +983,8 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
         if ((int)order.size() > aug) order.pop_back();
         ring = (ring + 1) % (aug + 1);
       }
-    } else {
-      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, j, s->hcol, s->Z, N, x);
+    } else if (used > 0) {
+      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, used, s->hcol, s->Z, N, x);
       HIPCHK(c, hipGetLastError());
     }
     // true residual r = rhs - A x
@@ -866,68 +998,44 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
     hist.push_back(beta);
     const size_t nh = hist.size();
     const bool stalled = (int)nh > s->stall && beta > 0.99 * hist[nh - 1 - s->stall];
-    if (beta <= rtol * b0 || total >= maxit || stalled) break;
+    if (beta <= rtol * b0 || total >= maxit || stalled || used == 0) break;
   }
   return FR_OK;
 }
 
-// ---- GMRES with a captured restart cycle
-// One cycle = m Arnoldi steps with every scalar on the device (precondition,
-// Jacobian-vector product, two classical Gram-Schmidt passes, normalisation,
-// Givens rotation): recorded once into a hipGraph per (iterate buffer,
-// preconditioner, dt) and replayed for each restart; the host reads the
-// small Hessenberg state once per cycle.  The cycle always runs m steps; the
-// solution update uses the steps up to the first one whose residual
-// estimate meets the tolerance.
-static fr_status record_cycle(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
-  fr_ctx_s* c = s->ctx;
-  const int m = s->m;
-  const long N = s->N;
-  const int grid = grid_for(N, 256);
-  fr_status st = FR_OK;
-  for (int j = 0; j < m && st == FR_OK; ++j) {
-    double* vj = s->V + (long)j * N;
-    double* zj = s->Z + (long)j * N;
-    if (pc) st = fr_apply_precond(pc, vj, zj);
-    else hipLaunchKernelGGL(k_axpby, dim3(grid), dim3(256), 0, c->stream, N, 1.0, vj, 0.0, nullptr, zj);
-    if (st == FR_OK) st = apply_A(s, U, dt, zj, s->w, nullptr);
-    if (st) break;
-    for (int pass = 0; pass < 2; ++pass) {
-      double* h = pass == 0 ? s->dh1 : s->dh2;
-      hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks), dim3(kDotThreads), 0, c->stream, N, j + 1, s->V, N, s->w,
-                         s->partial);
-      hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->stream, j + 1, kDotBlocks, s->partial, h);
-      hipLaunchKernelGGL(k_multi_axpy, dim3(grid), dim3(256), 0, c->stream, N, j + 1, h, s->V, N, s->w);
-    }
-    hipLaunchKernelGGL(k_arnoldi_col, dim3(1), dim3(32), 0, c->stream, j, m, s->dh1, s->dh2, s->dH);
-    hipLaunchKernelGGL(k_multi_dot, dim3(kDotBlocks), dim3(kDotThreads), 0, c->stream, N, 1, s->w, N, s->w, s->partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, c->stream, 1, kDotBlocks, s->partial, s->dn);
-    hipLaunchKernelGGL(k_norm_scale, dim3(grid), dim3(256), 0, c->stream, N, j, m, s->dn, s->w,
-                       s->V + (long)(j + 1) * N, s->dH);
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, j, m, s->dH, s->dcs, s->dsn, s->dg, s->dest);
-    if (hipGetLastError() != hipSuccess) st = sfail(c, FR_E_DEVICE, "launch while recording the GMRES cycle");
-  }
-  return st;
+// ---- GMRES with captured Arnoldi steps
+// The steps of a restart cycle are captured in chunks of kChunk (one hipGraph
+// per chunk, recorded once per (iterate buffer, preconditioner, dt)) and
+// replayed; the host reads the residual estimates once per chunk, so a solve
+// runs at most kChunk - 1 steps past its tolerance.
+static void drop_chunks(fr_solver_s* s) {
+  for (auto& g : s->chunk)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
 }
 
-static fr_status ensure_cycle(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
+static fr_status ensure_chunks(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
   fr_ctx_s* c = s->ctx;
-  if (s->cycle && s->key_U == U && s->key_pc == pc && s->key_dt == dt) return FR_OK;
-  if (s->cycle) { (void)hipGraphExecDestroy(s->cycle); s->cycle = nullptr; }
+  if (s->chunk[0] && s->key_U == U && s->key_pc == pc && s->key_dt == dt) return FR_OK;
+  drop_chunks(s);
   const bool timing = c->timing;
   c->timing = false;
-  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  fr_status st = record_cycle(s, pc, U, dt);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(c->stream, &g);
-  c->timing = timing;
-  if (st == FR_OK && e != hipSuccess) st = sfail(c, FR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-  if (st == FR_OK && hipGraphInstantiate(&s->cycle, g, nullptr, nullptr, 0) != hipSuccess) {
-    s->cycle = nullptr;
-    st = sfail(c, FR_E_DEVICE, "hipGraphInstantiate of the GMRES cycle");
+  fr_status st = FR_OK;
+  const int nch = (s->m + fr_solver_s::kChunk - 1) / fr_solver_s::kChunk;
+  for (int ch = 0; ch < nch && st == FR_OK; ++ch) {
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int j1 = std::min(s->m, (ch + 1) * fr_solver_s::kChunk);
+    for (int j = ch * fr_solver_s::kChunk; j < j1 && st == FR_OK; ++j) st = arnoldi_step(s, pc, U, dt, j, nullptr, 1.0);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st == FR_OK && e != hipSuccess) st = sfail(c, FR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    if (st == FR_OK && hipGraphInstantiate(&s->chunk[ch], g, nullptr, nullptr, 0) != hipSuccess) {
+      s->chunk[ch] = nullptr;
+      st = sfail(c, FR_E_DEVICE, "hipGraphInstantiate of the Arnoldi steps");
+    }
+    if (g) (void)hipGraphDestroy(g);
   }
-  if (g) (void)hipGraphDestroy(g);
-  if (st) return st;
+  c->timing = timing;
+  if (st) { drop_chunks(s); return st; }
   s->key_U = U; s->key_pc = pc; s->key_dt = dt;
   return FR_OK;
 }
@@ -948,37 +1056,36 @@ static fr_status gmres_graph(fr_solver_s* s, fr_precond_s* pc, const double* U, 
   *iters = 0;
   *res_true = 0.0;
   if (b0 == 0.0) return FR_OK;
-  if ((st = ensure_cycle(s, pc, U, dt))) return st;
+  if ((st = ensure_chunks(s, pc, U, dt))) return st;
   double beta = b0;
   int total = 0, work = 0;
   std::vector<double> hist{b0}, g0(m + 1, 0.0), y(m);
-  const size_t nstate = (size_t)(m + 1) * m + (m + 1) + m;    // H, g, est
+  const int K = fr_solver_s::kChunk;
   while (true) {
     if ((st = axpby(s, 1.0 / beta, s->w, 0.0, nullptr, s->V))) return st;
     g0[0] = beta;
     HIPCHK(c, hipMemcpyAsync(s->dg, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipGraphLaunch(s->cycle, c->stream));
     *cycles += 1;
-    work += m;
-    HIPCHK(c, hipMemcpyAsync(s->hstate, s->dH, nstate * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    const double* H = s->hstate;
-    const double* g = H + (size_t)(m + 1) * m;
-    const double* est = g + (m + 1);
-    int jj = m;
-    for (int j = 0; j < m; ++j) {
-      if (H[j * m + j] == 0.0) { jj = j; break; }          // breakdown: the Krylov space is exhausted
-      if (est[j] <= rtol * b0) { jj = j + 1; break; }
+    int jj = 0;
+    for (int ch = 0; jj < m; ++ch) {
+      HIPCHK(c, hipGraphLaunch(s->chunk[ch], c->stream));
+      const int j1 = std::min(m, (ch + 1) * K);
+      work += j1 - jj;
+      // estimates and the rotated diagonal of the chunk's steps
+      HIPCHK(c, hipMemcpyAsync(s->host, s->dest + jj, (j1 - jj) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      bool stop = false;
+      for (int j = jj; j < j1; ++j)
+        if (s->host[j - jj] <= rtol * b0) { stop = true; break; }
+      jj = j1;
+      if (stop || work >= maxit) break;
     }
-    for (int i = jj - 1; i >= 0; --i) {
-      double acc = g[i];
-      for (int k = i + 1; k < jj; ++k) acc -= H[i * m + k] * y[k];
-      y[i] = acc / H[i * m + i];
-    }
-    total += jj;
-    if (jj > 0) {
-      HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), jj * sizeof(double), hipMemcpyHostToDevice, c->stream));
-      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, jj, s->hcol, s->Z, N, x);
+    int used = 0;
+    if ((st = cycle_solution(s, jj, rtol * b0, y, &used))) return st;
+    total += used;
+    if (used > 0) {
+      HIPCHK(c, hipMemcpyAsync(s->hcol, y.data(), used * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      hipLaunchKernelGGL(k_multi_axpy_add, dim3(grid_for(N, 256)), dim3(256), 0, c->stream, N, used, s->hcol, s->Z, N, x);
       HIPCHK(c, hipGetLastError());
     }
     if ((st = apply_A(s, U, dt, x, s->w, nullptr))) return st;
@@ -990,7 +1097,7 @@ static fr_status gmres_graph(fr_solver_s* s, fr_precond_s* pc, const double* U, 
     hist.push_back(beta);
     const size_t nh = hist.size();
     const bool stalled = (int)nh > s->stall && beta > 0.99 * hist[nh - 1 - s->stall];
-    if (beta <= rtol * b0 || work >= maxit || stalled || jj == 0) break;
+    if (beta <= rtol * b0 || work >= maxit || stalled || used == 0) break;
   }
   return FR_OK;
 }
@@ -1086,6 +1193,10 @@ fr_status fr_solver_create(fr_ctx* c, int restart, fr_solver** out) {
     fr_solver_destroy(s);
     return sfail(c, FR_E_NOMEM, "solver cycle state");
   }
+  if (hipMalloc(&s->opart, 3 * kOrthBlocks * kMaxK * sizeof(double)) != hipSuccess) {
+    fr_solver_destroy(s);
+    return sfail(c, FR_E_NOMEM, "solver partial sums");
+  }
   s->dg = s->dH + (size_t)(m + 1) * m;
   s->dest = s->dg + (m + 1);
   s->dcs = s->dest + m;
@@ -1101,8 +1212,9 @@ fr_status fr_solver_destroy(fr_solver* s) {
   if (!s) return FR_E_INVALID;
   (void)hipStreamSynchronize(s->ctx->stream);
   if (s->cs) (void)hipStreamSynchronize(s->cs);
-  if (s->cycle) (void)hipGraphExecDestroy(s->cycle);
+  drop_chunks(s);
   (void)hipFree(s->mem);
+  if (s->opart) (void)hipFree(s->opart);
   (void)hipFree(s->dH);
   (void)hipHostFree(s->host);
   (void)hipHostFree(s->hstate);
@@ -1209,11 +1321,10 @@ fr_status fr_newton_step(fr_solver* s, fr_precond* pc, const void* Un_, void* U_
   HIPCHK(c, hipStreamWaitEvent(s->cs, s->join0, 0));
   c->stream = s->cs;
   fr_status r = newton_body(s, pc, Un_, U_, o, st);
-  // the captured cycle refers to this call's buffers and preconditioner
-  if (s->cycle) {
+  // the captured steps refer to this call's buffers and preconditioner
+  if (s->chunk[0]) {
     (void)hipStreamSynchronize(s->cs);
-    (void)hipGraphExecDestroy(s->cycle);
-    s->cycle = nullptr;
+    drop_chunks(s);
   }
   // rejected line-search trials may have recorded non-finite residuals:
   // the step reports its own outcome, so the word is cleared
