@@ -813,6 +813,7 @@ struct fr_solver_s {
   double* opart = nullptr;       // per-workgroup partial sums of the three Gram-Schmidt sweeps
   static constexpr int kChunk = 5, kMaxChunks = (31 + kChunk - 1) / kChunk;
   hipGraphExec_t chunk[kMaxChunks] = {};   // captured Arnoldi steps [c kChunk, (c+1) kChunk)
+  hipGraphExec_t single[31] = {};          // captured Arnoldi step j
   const void* key_U = nullptr; const void* key_pc = nullptr; double key_dt = 0.0;
 };
 
@@ -1004,13 +1005,35 @@ static fr_status gmres(fr_solver_s* s, fr_precond_s* pc, const double* U, double
 }
 
 // ---- GMRES with captured Arnoldi steps
-// The steps of a restart cycle are captured in chunks of kChunk (one hipGraph
-// per chunk, recorded once per (iterate buffer, preconditioner, dt)) and
-// replayed; the host reads the residual estimates once per chunk, so a solve
-// runs at most kChunk - 1 steps past its tolerance.
+// The steps of a restart cycle are captured once per (iterate buffer,
+// preconditioner, dt) twice over: in chunks of kChunk steps and one step per
+// graph.  The host replays a chunk while the residual estimate, extrapolated
+// at the last chunk's rate of decrease, stays above the tolerance for all of
+// it, and single steps near the tolerance; it reads the estimates after each
+// replay, so few steps run past the tolerance and a host round trip is paid
+// once per chunk far from it.
 static void drop_chunks(fr_solver_s* s) {
   for (auto& g : s->chunk)
     if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  for (auto& g : s->single)
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+static fr_status capture_steps(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt, int j0, int j1,
+                               hipGraphExec_t* out) {
+  fr_ctx_s* c = s->ctx;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  fr_status st = FR_OK;
+  for (int j = j0; j < j1 && st == FR_OK; ++j) st = arnoldi_step(s, pc, U, dt, j, nullptr, 1.0);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (st == FR_OK && e != hipSuccess) st = sfail(c, FR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (st == FR_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) {
+    *out = nullptr;
+    st = sfail(c, FR_E_DEVICE, "hipGraphInstantiate of the Arnoldi steps");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  return st;
 }
 
 static fr_status ensure_chunks(fr_solver_s* s, fr_precond_s* pc, const double* U, double dt) {
@@ -1020,20 +1043,10 @@ static fr_status ensure_chunks(fr_solver_s* s, fr_precond_s* pc, const double* U
   const bool timing = c->timing;
   c->timing = false;
   fr_status st = FR_OK;
-  const int nch = (s->m + fr_solver_s::kChunk - 1) / fr_solver_s::kChunk;
-  for (int ch = 0; ch < nch && st == FR_OK; ++ch) {
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    const int j1 = std::min(s->m, (ch + 1) * fr_solver_s::kChunk);
-    for (int j = ch * fr_solver_s::kChunk; j < j1 && st == FR_OK; ++j) st = arnoldi_step(s, pc, U, dt, j, nullptr, 1.0);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(c->stream, &g);
-    if (st == FR_OK && e != hipSuccess) st = sfail(c, FR_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    if (st == FR_OK && hipGraphInstantiate(&s->chunk[ch], g, nullptr, nullptr, 0) != hipSuccess) {
-      s->chunk[ch] = nullptr;
-      st = sfail(c, FR_E_DEVICE, "hipGraphInstantiate of the Arnoldi steps");
-    }
-    if (g) (void)hipGraphDestroy(g);
-  }
+  const int K = fr_solver_s::kChunk;
+  for (int ch = 0; (ch + 1) * K <= s->m && st == FR_OK; ++ch)
+    st = capture_steps(s, pc, U, dt, ch * K, (ch + 1) * K, &s->chunk[ch]);
+  for (int j = 0; j < s->m && st == FR_OK; ++j) st = capture_steps(s, pc, U, dt, j, j + 1, &s->single[j]);
   c->timing = timing;
   if (st) { drop_chunks(s); return st; }
   s->key_U = U; s->key_pc = pc; s->key_dt = dt;
@@ -1067,17 +1080,23 @@ static fr_status gmres_graph(fr_solver_s* s, fr_precond_s* pc, const double* U, 
     HIPCHK(c, hipMemcpyAsync(s->dg, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
     *cycles += 1;
     int jj = 0;
-    for (int ch = 0; jj < m; ++ch) {
-      HIPCHK(c, hipGraphLaunch(s->chunk[ch], c->stream));
-      const int j1 = std::min(m, (ch + 1) * K);
-      work += j1 - jj;
-      // estimates and the rotated diagonal of the chunk's steps
-      HIPCHK(c, hipMemcpyAsync(s->host, s->dest + jj, (j1 - jj) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double est = beta, rate = 0.0;     // rate: per-step decrease of the estimate (0: unknown)
+    while (jj < m) {
+      // a chunk while the extrapolated estimate stays above the tolerance
+      const bool chunk = jj % K == 0 && s->chunk[jj / K] &&
+                         (rate <= 0.0 || est * std::pow(rate, (double)K) > rtol * b0);
+      const int n = chunk ? K : 1;
+      HIPCHK(c, hipGraphLaunch(chunk ? s->chunk[jj / K] : s->single[jj], c->stream));
+      work += n;
+      HIPCHK(c, hipMemcpyAsync(s->host, s->dest + jj, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
       bool stop = false;
-      for (int j = jj; j < j1; ++j)
-        if (s->host[j - jj] <= rtol * b0) { stop = true; break; }
-      jj = j1;
+      for (int q = 0; q < n; ++q)
+        if (s->host[q] <= rtol * b0) { stop = true; break; }
+      const double e1 = s->host[n - 1];
+      if (est > 0.0 && e1 > 0.0 && e1 < est) rate = std::pow(e1 / est, 1.0 / n);
+      est = e1;
+      jj += n;
       if (stop || work >= maxit) break;
     }
     int used = 0;
