@@ -48,7 +48,19 @@
 // built from the orthonormal Dubiner (PKD) modal basis through the
 // Vandermonde matrix, edge flux points are Gauss-Legendre, and the FR-DG
 // correction is the nodal-DG lifting M^{-1} E.
+//
+// Tetrahedra and prisms (FR-DG only): the solution points of tetrahedra are
+// supplied by the caller (the paper's Shunn-Ham tables are not reproduced
+// either); prisms take the triangle points times Gauss-Legendre points along
+// the prism axis.  Triangular faces carry the caller's triangle point set,
+// quadrilateral faces Gauss-Legendre points.  The nodal basis comes from the
+// collapsed-coordinate PKD basis (tetrahedra) or the triangle PKD basis times
+// Legendre polynomials (prisms) through the Vandermonde matrix; the mass
+// matrix and the face integrals E_jf = int_face l_j phi_f dS (phi_f the
+// face's nodal basis on its flux points) use collapsed Gauss-Legendre rules
+// exact for the integrands, and the correction is again M^{-1} E.
 
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -63,7 +75,7 @@ static inline double re(const cd& z) { return z.real(); }
 template <class T> static inline T tabs(const T& x) { return re(x) >= 0 ? x : -x; }
 template <class T> static inline T tmax(const T& a, const T& b) { return re(a) >= re(b) ? a : b; }
 
-enum { QUAD = 0, TRI = 1, HEX = 2 };
+enum { QUAD = 0, TRI = 1, HEX = 2, TET = 3, PRI = 4 };
 enum { ADVECTION = 0, EULER = 1, NAVIER_STOKES = 2 };
 
 // ---------------------------------------------------------------- 1-D data
@@ -207,6 +219,24 @@ static void shape_fn(int type, const double* xi, double* N, double* dN /*[nvert]
       dN[v * 3 + 0] = V[v][0] * b * c / 8;
       dN[v * 3 + 1] = a * V[v][1] * c / 8;
       dN[v * 3 + 2] = a * b * V[v][2] / 8;
+    }
+  } else if (type == TET) {  // affine, v0=(-1,-1,-1) v1=(1,-1,-1) v2=(-1,1,-1) v3=(-1,-1,1)
+    N[0] = -(1 + xi[0] + xi[1] + xi[2]) / 2; N[1] = (1 + xi[0]) / 2; N[2] = (1 + xi[1]) / 2; N[3] = (1 + xi[2]) / 2;
+    const double d[4][3] = {{-0.5, -0.5, -0.5}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 0.5}};
+    for (int v = 0; v < 4; ++v)
+      for (int k = 0; k < 3; ++k) dN[v * 3 + k] = d[v][k];
+  } else if (type == PRI) {  // triangle (r, s) x [-1, 1] (t); v0..v2 at t = -1, v3..v5 at t = +1
+    const double L[3] = {-(xi[0] + xi[1]) / 2, (1 + xi[0]) / 2, (1 + xi[1]) / 2};
+    const double dL[3][2] = {{-0.5, -0.5}, {0.5, 0.0}, {0.0, 0.5}};
+    for (int h = 0; h < 2; ++h) {
+      const double z = h == 0 ? (1 - xi[2]) / 2 : (1 + xi[2]) / 2, dz = h == 0 ? -0.5 : 0.5;
+      for (int a = 0; a < 3; ++a) {
+        const int v = 3 * h + a;
+        N[v] = L[a] * z;
+        dN[v * 3 + 0] = dL[a][0] * z;
+        dN[v * 3 + 1] = dL[a][1] * z;
+        dN[v * 3 + 2] = L[a] * dz;
+      }
     }
   } else {  // TRI affine
     N[0] = -(xi[0] + xi[1]) / 2; N[1] = (1 + xi[0]) / 2; N[2] = (1 + xi[1]) / 2;
@@ -435,6 +465,293 @@ static void build_tri(RefElem& R, int p, const double* pts /*[ns][2]*/) {
     for (int j = 0; j < ns; ++j) R.wq[r] += Mmass[r * ns + j];
 }
 
+// ---------------------------------------------- tetrahedra and prisms (FR-DG)
+// PKD basis on the reference tetrahedron (v0=(-1,-1,-1), v1=(1,-1,-1),
+// v2=(-1,1,-1), v3=(-1,-1,1)), collapsed coordinates a = 2(1+r)/(-s-t) - 1,
+// b = 2(1+s)/(1-t) - 1, c = t:
+//   psi_ijk = P_i(a) ((1-b)/2)^i P_j^{(2i+1,0)}(b) ((1-c)/2)^{i+j} P_k^{(2i+2j+2,0)}(c),
+// written as a polynomial: tau^i P_i(x / tau) with tau = (-s-t)/2, x = 1 + r +
+// (s+t)/2, and sigma^j P_j^{(2i+1,0)}(y / sigma) with sigma = (1-t)/2, y =
+// (1+2s+t)/2, each by its scaled recurrence (no singular points).  Not
+// normalised: the mass matrix is integrated.
+template <class T> static T scaled_jacobi(int n, double al, const T& y, const T& sg) {
+  T p0 = T(1.0);
+  if (n == 0) return p0;
+  T p1 = T(0.5 * (al + 2.0)) * y + T(0.5 * al) * sg;
+  for (int k = 2; k <= n; ++k) {
+    double a1 = 2.0 * k * (k + al) * (2.0 * k + al - 2.0);
+    double a2 = (2.0 * k + al - 1.0) * (al * al);
+    double a3 = (2.0 * k + al - 2.0) * (2.0 * k + al - 1.0) * (2.0 * k + al);
+    double a4 = 2.0 * (k + al - 1.0) * (k - 1.0) * (2.0 * k + al);
+    T p2 = ((T(a2) * sg + T(a3) * y) * p1 - T(a4) * sg * sg * p0) / T(a1);
+    p0 = p1; p1 = p2;
+  }
+  return p1;
+}
+template <class T> static T pkd_tet(int i, int j, int k, const T& r, const T& s, const T& t) {
+  const T tau = (-s - t) * T(0.5), x = T(1.0) + r + (s + t) * T(0.5);
+  T q0 = T(1.0), q1 = x, qi = (i == 0) ? q0 : q1;
+  for (int m = 2; m <= i; ++m) {
+    T q2 = (T(2.0 * m - 1.0) * x * q1 - T(m - 1.0) * tau * tau * q0) / T((double)m);
+    q0 = q1; q1 = q2; qi = q2;
+  }
+  const T sg = (T(1.0) - t) * T(0.5), y = (T(1.0) + T(2.0) * s + t) * T(0.5);
+  const T pj = scaled_jacobi(j, 2.0 * i + 1.0, y, sg);
+  const T pk = scaled_jacobi(k, 2.0 * i + 2.0 * j + 2.0, t, T(1.0));
+  return qi * pj * pk;
+}
+// Legendre P_n(t) (complex-capable).
+template <class T> static T leg(int n, const T& t) {
+  T p0 = T(1.0), p1 = t;
+  if (n == 0) return p0;
+  for (int k = 2; k <= n; ++k) {
+    T p2 = (T(2.0 * k - 1.0) * t * p1 - T(k - 1.0) * p0) / T((double)k);
+    p0 = p1; p1 = p2;
+  }
+  return p1;
+}
+
+// Collapsed Gauss-Legendre rule on the reference triangle (area 2), exact for
+// degree 2n - 2: (a, b) in [-1,1]^2, r = (1+a)(1-b)/2 - 1, s = b, dA =
+// (1-b)/2 da db.
+static void tri_rule(int n, std::vector<double>& q, std::vector<double>& w) {
+  std::vector<double> x, wx; gauss_legendre(n, x, wx);
+  q.clear(); w.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      q.push_back((1 + x[i]) * (1 - x[j]) / 2 - 1);
+      q.push_back(x[j]);
+      w.push_back(wx[i] * wx[j] * (1 - x[j]) / 2);
+    }
+}
+// Collapsed rule on the reference tetrahedron (volume 4/3): t = c, s = (1+b)(1-c)/2 - 1,
+// r = (1+a)(1-b)(1-c)/4 - 1, dV = (1-b)(1-c)^2/8 da db dc.
+static void tet_rule(int n, std::vector<double>& q, std::vector<double>& w) {
+  std::vector<double> x, wx; gauss_legendre(n, x, wx);
+  q.clear(); w.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double a = x[i], b = x[j], c = x[k];
+        q.push_back((1 + a) * (1 - b) * (1 - c) / 4 - 1);
+        q.push_back((1 + b) * (1 - c) / 2 - 1);
+        q.push_back(c);
+        w.push_back(wx[i] * wx[j] * wx[k] * (1 - b) * (1 - c) * (1 - c) / 8);
+      }
+}
+
+// One face of a 3-D reference element: its flux points, unit outward
+// normal, and a quadrature rule with the face's nodal basis at its points.
+struct FaceData {
+  std::vector<double> fp;      // [nfp][3]
+  double n[3];
+  std::vector<double> qx, qw;  // quadrature points [nq][3], weights (reference surface measure)
+  std::vector<double> phi;     // [nq][nfp] face nodal basis at the quadrature points
+};
+
+// Triangular face with vertices A, B, C: the caller's triangle points mapped
+// through the barycentric coordinates of the 2-D reference triangle.
+static FaceData tri_face(const double* A, const double* B, const double* C, const double* n, int p,
+                         const double* tri_pts) {
+  FaceData F;
+  const int nt = (p + 1) * (p + 2) / 2;
+  auto map = [&](double a, double b, double* X) {
+    const double l0 = -(a + b) / 2, l1 = (1 + a) / 2, l2 = (1 + b) / 2;
+    for (int k = 0; k < 3; ++k) X[k] = l0 * A[k] + l1 * B[k] + l2 * C[k];
+  };
+  for (int i = 0; i < nt; ++i) {
+    double X[3]; map(tri_pts[2 * i], tri_pts[2 * i + 1], X);
+    F.fp.insert(F.fp.end(), X, X + 3);
+  }
+  for (int k = 0; k < 3; ++k) F.n[k] = n[k];
+  // area of the face / area of the 2-D reference triangle
+  double e1[3], e2[3], cr[3];
+  for (int k = 0; k < 3; ++k) { e1[k] = B[k] - A[k]; e2[k] = C[k] - A[k]; }
+  cr[0] = e1[1] * e2[2] - e1[2] * e2[1]; cr[1] = e1[2] * e2[0] - e1[0] * e2[2]; cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double scale = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) / 2.0;
+  // face nodal basis: 2-D PKD Vandermonde on the triangle points
+  std::vector<std::pair<int, int>> modes;
+  for (int i = 0; i <= p; ++i)
+    for (int j = 0; i + j <= p; ++j) modes.push_back({i, j});
+  std::vector<double> V(nt * nt), Vinv;
+  for (int r = 0; r < nt; ++r)
+    for (int m = 0; m < nt; ++m) V[r * nt + m] = dubiner<double>(modes[m].first, modes[m].second, tri_pts[2 * r], tri_pts[2 * r + 1]);
+  invert(V, nt, Vinv);
+  std::vector<double> q, w; tri_rule(p + 2, q, w);
+  const int nq = (int)w.size();
+  F.phi.assign(nq * nt, 0.0);
+  for (int a = 0; a < nq; ++a) {
+    double X[3]; map(q[2 * a], q[2 * a + 1], X);
+    F.qx.insert(F.qx.end(), X, X + 3);
+    F.qw.push_back(w[a] * scale);
+    for (int g = 0; g < nt; ++g) {
+      double v = 0.0;
+      for (int m = 0; m < nt; ++m) v += Vinv[m * nt + g] * dubiner<double>(modes[m].first, modes[m].second, q[2 * a], q[2 * a + 1]);
+      F.phi[a * nt + g] = v;
+    }
+  }
+  return F;
+}
+// Quadrilateral face with vertices A, B, C, D (a planar parallelogram):
+// Gauss-Legendre points, point (i, j) at A + (1+x_i)/2 (B - A) + (1+x_j)/2 (D - A);
+// the rule is the same points (exact for the products of two face
+// polynomials of degree p in each direction).
+static FaceData quad_face(const double* A, const double* B, const double* D, const double* n, int p) {
+  FaceData F;
+  const int n1 = p + 1;
+  std::vector<double> x, w; gauss_legendre(n1, x, w);
+  double e1[3], e2[3], cr[3];
+  for (int k = 0; k < 3; ++k) { e1[k] = B[k] - A[k]; e2[k] = D[k] - A[k]; }
+  cr[0] = e1[1] * e2[2] - e1[2] * e2[1]; cr[1] = e1[2] * e2[0] - e1[0] * e2[2]; cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double scale = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) / 4.0;
+  for (int j = 0; j < n1; ++j)
+    for (int i = 0; i < n1; ++i) {
+      double X[3];
+      for (int k = 0; k < 3; ++k) X[k] = A[k] + 0.5 * (1 + x[i]) * e1[k] + 0.5 * (1 + x[j]) * e2[k];
+      F.fp.insert(F.fp.end(), X, X + 3);
+      F.qx.insert(F.qx.end(), X, X + 3);
+      F.qw.push_back(w[i] * w[j] * scale);
+    }
+  const int nf = n1 * n1;
+  F.phi.assign(nf * nf, 0.0);
+  for (int a = 0; a < nf; ++a) F.phi[a * nf + a] = 1.0;
+  for (int k = 0; k < 3; ++k) F.n[k] = n[k];
+  return F;
+}
+
+// Operators of a 3-D element from its modal basis (value through T = double,
+// derivatives by complex step), solution points, volume rule and faces.
+template <class Basis>
+static void build_3d(RefElem& R, int nm, Basis basis, const std::vector<double>& sp, const std::vector<double>& vq,
+                     const std::vector<double>& vw, const std::vector<FaceData>& faces) {
+  const int ns = (int)sp.size() / 3;
+  R.nd = 3; R.ns = ns; R.sp = sp;
+  std::vector<double> V(ns * nm), Vinv;
+  for (int r = 0; r < ns; ++r)
+    for (int m = 0; m < nm; ++m) V[r * nm + m] = basis(m, cd(sp[3 * r]), cd(sp[3 * r + 1]), cd(sp[3 * r + 2])).real();
+  invert(V, ns, Vinv);
+  auto lval = [&](int j, double r, double s, double t) {
+    double v = 0.0;
+    for (int m = 0; m < nm; ++m) v += Vinv[m * ns + j] * basis(m, cd(r), cd(s), cd(t)).real();
+    return v;
+  };
+  auto lgrad = [&](int j, const double* X, int d) {
+    const double hh = 1e-30;
+    double v = 0.0;
+    for (int m = 0; m < nm; ++m) {
+      cd a(X[0], d == 0 ? hh : 0.0), b(X[1], d == 1 ? hh : 0.0), c(X[2], d == 2 ? hh : 0.0);
+      v += Vinv[m * ns + j] * basis(m, a, b, c).imag() / hh;
+    }
+    return v;
+  };
+  R.nface = (int)faces.size();
+  R.face_off.assign(1, 0);
+  R.fp.clear(); R.nref.clear(); R.fface.clear();
+  for (int f = 0; f < R.nface; ++f) {
+    const int nfp = (int)faces[f].fp.size() / 3;
+    R.face_off.push_back(R.face_off.back() + nfp);
+    R.fp.insert(R.fp.end(), faces[f].fp.begin(), faces[f].fp.end());
+    for (int g = 0; g < nfp; ++g) {
+      R.nref.insert(R.nref.end(), faces[f].n, faces[f].n + 3);
+      R.fface.push_back(f);
+    }
+  }
+  R.nf = R.face_off.back();
+  R.M0.assign(R.nf * ns, 0.0);
+  for (int g = 0; g < R.nf; ++g)
+    for (int j = 0; j < ns; ++j) R.M0[g * ns + j] = lval(j, R.fp[3 * g], R.fp[3 * g + 1], R.fp[3 * g + 2]);
+  R.Dm.assign(3 * ns * ns, 0.0);
+  for (int d = 0; d < 3; ++d)
+    for (int r = 0; r < ns; ++r)
+      for (int j = 0; j < ns; ++j) R.Dm[(d * ns + r) * ns + j] = lgrad(j, &sp[3 * r], d);
+  // mass matrix by the volume rule
+  const int nq = (int)vw.size();
+  std::vector<double> L(nq * ns);
+  for (int a = 0; a < nq; ++a)
+    for (int j = 0; j < ns; ++j) L[a * ns + j] = lval(j, vq[3 * a], vq[3 * a + 1], vq[3 * a + 2]);
+  std::vector<double> Mm(ns * ns, 0.0), Minv;
+  for (int a = 0; a < nq; ++a)
+    for (int i = 0; i < ns; ++i)
+      for (int j = 0; j < ns; ++j) Mm[i * ns + j] += vw[a] * L[a * ns + i] * L[a * ns + j];
+  invert(Mm, ns, Minv);
+  // E[j][g] = int_face l_j phi_g dS, then the lifting M^{-1} E
+  std::vector<double> E(ns * R.nf, 0.0);
+  for (int f = 0; f < R.nface; ++f) {
+    const FaceData& F = faces[f];
+    const int nfp = R.face_off[f + 1] - R.face_off[f], nqf = (int)F.qw.size();
+    for (int a = 0; a < nqf; ++a)
+      for (int j = 0; j < ns; ++j) {
+        const double lj = lval(j, F.qx[3 * a], F.qx[3 * a + 1], F.qx[3 * a + 2]);
+        for (int g = 0; g < nfp; ++g) E[j * R.nf + R.face_off[f] + g] += F.qw[a] * lj * F.phi[a * nfp + g];
+      }
+  }
+  R.Cor.assign(ns * R.nf, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int g = 0; g < R.nf; ++g) {
+      double v = 0.0;
+      for (int j = 0; j < ns; ++j) v += Minv[r * ns + j] * E[j * R.nf + g];
+      R.Cor[r * R.nf + g] = v;
+    }
+  R.wq.assign(ns, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int j = 0; j < ns; ++j) R.wq[r] += Mm[r * ns + j];
+}
+
+static void build_tet(RefElem& R, int p, const double* tet_pts, const double* tri_pts) {
+  R.type = TET; R.p = p; R.nvert = 4;
+  const double v[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+  R.face_verts = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {0, 2, 3}};
+  const double q3 = 1.0 / std::sqrt(3.0);
+  const double nrm[4][3] = {{0, 0, -1}, {0, -1, 0}, {q3, q3, q3}, {-1, 0, 0}};
+  std::vector<FaceData> faces;
+  for (int f = 0; f < 4; ++f)
+    faces.push_back(tri_face(v[R.face_verts[f][0]], v[R.face_verts[f][1]], v[R.face_verts[f][2]], nrm[f], p, tri_pts));
+  std::vector<std::array<int, 3>> modes;
+  for (int i = 0; i <= p; ++i)
+    for (int j = 0; i + j <= p; ++j)
+      for (int k = 0; i + j + k <= p; ++k) modes.push_back({i, j, k});
+  const int ns = (int)modes.size();
+  std::vector<double> sp(tet_pts, tet_pts + 3 * ns), q, w;
+  tet_rule(p + 2, q, w);
+  build_3d(R, ns, [&](int m, const cd& r, const cd& s, const cd& t) { return pkd_tet<cd>(modes[m][0], modes[m][1], modes[m][2], r, s, t); },
+           sp, q, w, faces);
+}
+
+static void build_prism(RefElem& R, int p, const double* tri_pts) {
+  R.type = PRI; R.p = p; R.nvert = 6;
+  const double v[6][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}};
+  // faces: bottom, top (triangles), then the sides s = -1, r + s = 0, r = -1
+  R.face_verts = {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+  const double h = 1.0 / std::sqrt(2.0);
+  const double nrm[5][3] = {{0, 0, -1}, {0, 0, 1}, {0, -1, 0}, {h, h, 0}, {-1, 0, 0}};
+  std::vector<FaceData> faces;
+  faces.push_back(tri_face(v[0], v[1], v[2], nrm[0], p, tri_pts));
+  faces.push_back(tri_face(v[3], v[4], v[5], nrm[1], p, tri_pts));
+  faces.push_back(quad_face(v[0], v[1], v[3], nrm[2], p));
+  faces.push_back(quad_face(v[1], v[2], v[4], nrm[3], p));
+  faces.push_back(quad_face(v[2], v[0], v[5], nrm[4], p));
+  const int nt = (p + 1) * (p + 2) / 2, n1 = p + 1;
+  std::vector<std::array<int, 3>> modes;
+  for (int k = 0; k <= p; ++k)
+    for (int i = 0; i <= p; ++i)
+      for (int j = 0; i + j <= p; ++j) modes.push_back({i, j, k});
+  std::vector<double> x, wx; gauss_legendre(n1, x, wx);
+  std::vector<double> sp;                     // triangle point i at axis point k: index i + nt k
+  for (int k = 0; k < n1; ++k)
+    for (int i = 0; i < nt; ++i) { sp.push_back(tri_pts[2 * i]); sp.push_back(tri_pts[2 * i + 1]); sp.push_back(x[k]); }
+  std::vector<double> tq, tw, q, w;
+  tri_rule(p + 2, tq, tw);
+  std::vector<double> lx, lw; gauss_legendre(p + 2, lx, lw);
+  for (size_t a = 0; a < tw.size(); ++a)
+    for (size_t b = 0; b < lw.size(); ++b) {
+      q.push_back(tq[2 * a]); q.push_back(tq[2 * a + 1]); q.push_back(lx[b]);
+      w.push_back(tw[a] * lw[b]);
+    }
+  build_3d(R, (int)modes.size(), [&](int m, const cd& r, const cd& s, const cd& t) {
+    return dubiner<cd>(modes[m][0], modes[m][1], r, s) * leg<cd>(modes[m][2], t);
+  }, sp, q, w, faces);
+}
+
 // ------------------------------------------------------------- the problem
 struct Phys {
   int system, nv;
@@ -446,7 +763,7 @@ struct Oracle {
   int64_t ne = 0;
   int maxv = 0, maxf = 0;
   Phys ph{};
-  RefElem ref[3];
+  RefElem ref[5];
   std::vector<int8_t> etype;
   std::vector<double> xyz;
   std::vector<int64_t> nbr;
@@ -922,7 +1239,7 @@ extern "C" {
 int oracle_create(int nd, int64_t ne, const int8_t* etype, int p, const double* xyz, int maxv,
                   const int64_t* nbr, const int8_t* nbrf, int maxf, int system, int nv,
                   const double* c, double gamma, double mu, double prandtl, double beta, double eta,
-                  int scheme, const double* tri_pts, void** out) {
+                  int scheme, const double* tri_pts, const double* tet_pts, void** out) {
   // BR1 only: beta = 0 and no penalty (the von Neumann analysis with
   // diffusion identifies BR1 with beta = 0).  A single scalar beta taken
   // from each element's own side would make the common solution and the
@@ -937,14 +1254,25 @@ int oracle_create(int nd, int64_t ne, const int8_t* etype, int p, const double* 
   O->xyz.assign(xyz, xyz + ne * maxv * nd);
   O->nbr.assign(nbr, nbr + ne * maxf);
   O->nbrf.assign(nbrf, nbrf + ne * maxf);
-  bool has[3] = {false, false, false};
-  for (int64_t e = 0; e < ne; ++e) has[etype[e]] = true;
-  if (scheme < 0 || scheme > 2 || (scheme != 0 && has[TRI])) { delete O; return -12; }
+  bool has[5] = {false, false, false, false, false};
+  for (int64_t e = 0; e < ne; ++e) {
+    if (etype[e] < 0 || etype[e] > 4) { delete O; return -13; }
+    has[etype[e]] = true;
+  }
+  if (scheme < 0 || scheme > 2 || (scheme != 0 && (has[TRI] || has[TET] || has[PRI]))) { delete O; return -12; }
   if (has[QUAD]) build_tensor(O->ref[QUAD], QUAD, p, scheme);
   if (has[HEX]) build_tensor(O->ref[HEX], HEX, p, scheme);
   if (has[TRI]) {
     if (!tri_pts) { delete O; return -10; }
     build_tri(O->ref[TRI], p, tri_pts);
+  }
+  if (has[TET]) {
+    if (!tri_pts || !tet_pts) { delete O; return -10; }
+    build_tet(O->ref[TET], p, tet_pts, tri_pts);
+  }
+  if (has[PRI]) {
+    if (!tri_pts) { delete O; return -10; }
+    build_prism(O->ref[PRI], p, tri_pts);
   }
   std::vector<std::string> err;
   int rc = setup(*O, err);

@@ -39,7 +39,7 @@ def lib():
             d = C.c_double
             i64 = C.c_int64
             L.oracle_create.argtypes = [C.c_int, i64, P, C.c_int, P, C.c_int, P, P, C.c_int,
-                                        C.c_int, C.c_int, P, d, d, d, d, d, C.c_int, P, C.POINTER(C.c_void_p)]
+                                        C.c_int, C.c_int, P, d, d, d, d, d, C.c_int, P, P, C.POINTER(C.c_void_p)]
             L.oracle_create.restype = C.c_int
             L.oracle_destroy.argtypes = [P]
             L.oracle_ndof.argtypes = [P]
@@ -69,7 +69,7 @@ def _p(a: np.ndarray):
 class Oracle:
     """FP64 reference for one mesh + physics (single polynomial degree)."""
 
-    def __init__(self, mesh, phys, p: int, tri_pts: np.ndarray | None = None):
+    def __init__(self, mesh, phys, p: int, tri_pts: np.ndarray | None = None, tet_pts: np.ndarray | None = None):
         L = lib()
         self.mesh, self.phys, self.p = mesh, phys, p
         self._keep = []
@@ -79,12 +79,13 @@ class Oracle:
         nbf = np.ascontiguousarray(mesh.nbr_face, dtype=np.int8)
         c = np.ascontiguousarray(np.asarray(phys.adv_vel, dtype=np.float64).reshape(3))
         tp = None if tri_pts is None else np.ascontiguousarray(tri_pts, dtype=np.float64)
-        self._keep += [et, xyz, nbr, nbf, c, tp]
+        qp = None if tet_pts is None else np.ascontiguousarray(tet_pts, dtype=np.float64)
+        self._keep += [et, xyz, nbr, nbf, c, tp, qp]
         h = C.c_void_p()
         rc = L.oracle_create(mesh.ndim, mesh.n_elem, _p(et), p, _p(xyz), mesh.max_vert, _p(nbr), _p(nbf),
                              mesh.max_face, phys.system, phys.nvars, _p(c), phys.gamma, phys.mu,
                              phys.prandtl, phys.beta, phys.eta, int(getattr(phys, "scheme", 0)),
-                             None if tp is None else _p(tp), C.byref(h))
+                             None if tp is None else _p(tp), None if qp is None else _p(qp), C.byref(h))
         if rc != 0:
             raise RuntimeError(f"oracle_create failed ({rc})")
         self.h = h

@@ -15,6 +15,12 @@ Conventions shared by every consumer (they are part of the C ABI contract):
   4: xi=-1, 5: zeta=+1.
 * Reference triangle with vertices v0=(-1,-1), v1=(1,-1), v2=(-1,1); faces
   0: v0->v1 (eta=-1), 1: v1->v2 (hypotenuse), 2: v2->v0 (xi=-1).
+* Reference tetrahedron v0=(-1,-1,-1), v1=(1,-1,-1), v2=(-1,1,-1),
+  v3=(-1,-1,1); faces 0: (v0,v1,v2), 1: (v0,v1,v3), 2: (v1,v2,v3),
+  3: (v0,v2,v3).
+* Reference prism: the triangle (r, s) times t in [-1,1]; v0..v2 the
+  triangle at t=-1, v3..v5 at t=+1; faces 0: bottom (v0,v1,v2), 1: top
+  (v3,v4,v5), 2: (v0,v1,v4,v3), 3: (v1,v2,v5,v4), 4: (v2,v0,v3,v5).
 * Solution points of tensor elements are the Gauss-Legendre points with
   index rho = i + (p+1)*j (+ (p+1)^2*k), xi_i ascending (the paper's FR and
   SDRT setups put solution points at Gauss-Legendre points, appendix A).
@@ -31,7 +37,7 @@ import math
 
 import numpy as np
 
-QUAD, TRI, HEX = 0, 1, 2
+QUAD, TRI, HEX, TET, PRI = 0, 1, 2, 3, 4
 
 _QUAD_VERTS = np.array([[-1, -1], [1, -1], [1, 1], [-1, 1]], dtype=np.float64)
 _HEX_VERTS = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
@@ -121,18 +127,20 @@ def tri_points(p: int, shrink: float = 0.8) -> np.ndarray:
 
 
 def tri_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0), degree: int = 1,
-             jitter: float = 0.0, K: int | None = None, seed: int = 0) -> Mesh:
+             jitter: float = 0.0, K: int | None = None, seed: int = 0, diag: int | None = None) -> Mesh:
     """N x N periodic cells on [origin, origin+L]^2, each split into two
-    triangles along a diagonal drawn per cell from `seed`; vertices jittered
-    as in quad_mesh (straight edges, affine triangles).  Triangle vertices are
-    counter-clockwise; local face f joins vertices f and f+1 (mod 3)."""
+    triangles along a diagonal drawn per cell from `seed` (or, with diag = 0
+    or 1, the (0,0)-(1,1) or the (1,0)-(0,1) diagonal in every cell);
+    vertices jittered as in quad_mesh (straight edges, affine triangles).
+    Triangle vertices are counter-clockwise; local face f joins vertices f
+    and f+1 (mod 3)."""
     if N < 3:
         raise ValueError("tri_mesh needs N >= 3 (distinct periodic edges)")
     h = L / N
     if K is None:
         K = max(N // 4, 1)
     rng = np.random.default_rng(seed)
-    diag = rng.integers(0, 2, size=N * N)
+    diag = rng.integers(0, 2, size=N * N) if diag is None else np.full(N * N, int(diag))
     n = 2 * N * N
     xyz = np.zeros((n, 3, 2))
     verts = []          # lattice (i, j) of each element's vertices
@@ -266,7 +274,124 @@ def n_sol_points(etype: int, p: int) -> int:
         return (p + 1) ** 3
     if etype == TRI:
         return (p + 1) * (p + 2) // 2
+    if etype == TET:
+        return (p + 1) * (p + 2) * (p + 3) // 6
+    if etype == PRI:
+        return (p + 1) ** 2 * (p + 2) // 2
     raise ValueError(etype)
+
+
+def tet_points(p: int, shrink: float = 0.8) -> np.ndarray:
+    """Solution points [Ns, 3] on the reference tetrahedron: the equispaced
+    degree-p lattice contracted toward the centroid by `shrink` (symmetric
+    under the tetrahedron's symmetries, unisolvent, interior).  The paper
+    names Shunn-Ham points without tabulating them; FR-DG depends on the set
+    only through the nonlinear flux."""
+    v = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    pts = []
+    for i in range(p + 1):
+        for j in range(p + 1 - i):
+            for k in range(p + 1 - i - j):
+                l = p - i - j - k
+                pts.append((l * v[0] + i * v[1] + j * v[2] + k * v[3]) / p)
+    pts = np.array(pts)
+    c = v.mean(axis=0)
+    return c + shrink * (pts - c)
+
+
+def _hex_lattice(N, L, origin, jitter, K):
+    """Vertex position of lattice point (i, j, k) (unwrapped, jittered)."""
+    if K is None:
+        K = max(N // 4, 1)
+    h = 1.0 / N
+
+    def X(i, j, k):
+        xs, ys, zs = i / N, j / N, k / N
+        if jitter:
+            d = jitter * h * np.array([np.sin(2 * np.pi * K * (xs + ys + zs)), np.sin(2 * np.pi * K * (xs - ys)),
+                                       np.sin(2 * np.pi * K * (ys - zs))])
+        else:
+            d = np.zeros(3)
+        return np.array(origin) + L * (np.array([xs, ys, zs]) + d)
+    return X
+
+
+def _connect(verts, faces_of, N):
+    """Face neighbours of elements given as lattice-vertex tuples (periodic)."""
+    n = len(verts)
+    maxf = max(len(faces_of(e)) for e in range(n))
+    nbr = np.full((n, maxf), -1, dtype=np.int64)
+    nbr_face = np.full((n, maxf), -1, dtype=np.int8)
+    faces = {}
+    for e in range(n):
+        for f, fv in enumerate(faces_of(e)):
+            key = frozenset(tuple(c % N for c in verts[e][v]) for v in fv)
+            faces.setdefault(key, []).append((e, f))
+    for lst in faces.values():
+        if len(lst) != 2:
+            raise RuntimeError("non-conforming face")
+        (e1, f1), (e2, f2) = lst
+        nbr[e1, f1], nbr_face[e1, f1] = e2, f2
+        nbr[e2, f2], nbr_face[e2, f2] = e1, f1
+    return nbr, nbr_face
+
+
+TET_FACES = ((0, 1, 2), (0, 1, 3), (1, 2, 3), (0, 2, 3))
+PRI_FACES = ((0, 1, 2), (3, 4, 5), (0, 1, 4, 3), (1, 2, 5, 4), (2, 0, 3, 5))
+
+
+def tet_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0, 0.0), degree: int = 1, jitter: float = 0.0,
+             K: int | None = None, diag: int = 0) -> Mesh:
+    """N^3 periodic cells, each split into six tetrahedra around one of its
+    four main diagonals (diag: 0 from (0,0,0), 1 from (1,0,0), 2 from
+    (0,1,0), 3 from (0,0,1)) -- the paper's subdivision of a hexahedron into
+    six tetrahedra; the same split in every cell keeps the mesh conforming.
+    Vertices jittered by jitter*h (straight edges, affine elements)."""
+    if N < 3:
+        raise ValueError("tet_mesh needs N >= 3 (distinct periodic faces)")
+    X = _hex_lattice(N, L, origin, jitter, K)
+    flip = ((0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1))[diag]
+    corner = tuple(tuple(abs(f - v) for f, v in zip(flip, cv))
+                   for cv in ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)))
+    kuhn = ((0, 1, 2, 6), (0, 1, 5, 6), (0, 3, 2, 6), (0, 3, 7, 6), (0, 4, 5, 6), (0, 4, 7, 6))
+    verts, xyz = [], []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                for t in kuhn:
+                    vs = [tuple(np.add((i, j, k), corner[c])) for c in t]
+                    P = np.array([X(*v) for v in vs])
+                    if np.linalg.det(np.stack([P[1] - P[0], P[2] - P[0], P[3] - P[0]])) < 0:
+                        vs[1], vs[2] = vs[2], vs[1]
+                        P[[1, 2]] = P[[2, 1]]
+                    verts.append(vs)
+                    xyz.append(P)
+    nbr, nbr_face = _connect(verts, lambda e: TET_FACES, N)
+    n = len(verts)
+    return Mesh(3, np.full(n, TET, np.int8), np.full(n, degree, np.int8), np.array(xyz), nbr, nbr_face, L / N)
+
+
+def prism_mesh(N: int, L: float = 1.0, origin=(0.0, 0.0, 0.0), degree: int = 1, jitter: float = 0.0,
+               K: int | None = None, diag: int = 0) -> Mesh:
+    """N^3 periodic cells, each split into two triangular prisms (axis z) by
+    the diagonal plane through its (0,0)-(1,1) vertical edges (diag 0) or its
+    (1,0)-(0,1) ones (diag 1) (the paper's subdivision into two prisms)."""
+    if N < 3:
+        raise ValueError("prism_mesh needs N >= 3 (distinct periodic faces)")
+    X = _hex_lattice(N, L, origin, jitter, K)
+    corner = ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1))
+    split = ((0, 1, 2, 4, 5, 6), (0, 2, 3, 4, 6, 7)) if diag == 0 else ((0, 1, 3, 4, 5, 7), (1, 2, 3, 5, 6, 7))
+    verts, xyz = [], []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                for t in split:
+                    vs = [tuple(np.add((i, j, k), corner[c])) for c in t]
+                    verts.append(vs)
+                    xyz.append(np.array([X(*v) for v in vs]))
+    nbr, nbr_face = _connect(verts, lambda e: PRI_FACES, N)
+    n = len(verts)
+    return Mesh(3, np.full(n, PRI, np.int8), np.full(n, degree, np.int8), np.array(xyz), nbr, nbr_face, L / N)
 
 
 def sol_points_phys(mesh: Mesh, p: int, tri_pts: np.ndarray | None = None
@@ -294,6 +419,19 @@ def sol_points_phys(mesh: Mesh, p: int, tri_pts: np.ndarray | None = None
         s = tri_pts[:, 1]
         N = np.stack([-(r + s) / 2, (1 + r) / 2, (1 + s) / 2], axis=1)
         return np.einsum("pv,nvd->npd", N, mesh.xyz[:, :3, :])
+    if et == TET:
+        q = tet_points(p) if tri_pts is None or tri_pts.shape[-1] != 3 else tri_pts
+        r, s, t = q[:, 0], q[:, 1], q[:, 2]
+        N = np.stack([-(1 + r + s + t) / 2, (1 + r) / 2, (1 + s) / 2, (1 + t) / 2], axis=1)
+        return np.einsum("pv,nvd->npd", N, mesh.xyz[:, :4, :])
+    if et == PRI:
+        tp = tri_points(p) if tri_pts is None or tri_pts.shape[-1] != 2 else tri_pts
+        g, _ = np.polynomial.legendre.leggauss(p + 1)
+        pts = np.array([(tp[i, 0], tp[i, 1], g[k]) for k in range(p + 1) for i in range(len(tp))])
+        r, s, t = pts[:, 0], pts[:, 1], pts[:, 2]
+        Lt = np.stack([-(r + s) / 2, (1 + r) / 2, (1 + s) / 2], axis=1)
+        N = np.concatenate([Lt * ((1 - t) / 2)[:, None], Lt * ((1 + t) / 2)[:, None]], axis=1)
+        return np.einsum("pv,nvd->npd", N, mesh.xyz[:, :6, :])
     g, _ = np.polynomial.legendre.leggauss(p + 1)
     if et == QUAD:
         xi = np.array([(g[i], g[j]) for j in range(p + 1) for i in range(p + 1)])
