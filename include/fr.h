@@ -17,9 +17,19 @@
  *      hex  [-1,1]^3: v0..v3 as the quad at zeta=-1, v4..v7 at zeta=+1;
  *                     faces 0:zeta=-1 1:eta=-1 2:xi=+1 3:eta=+1 4:xi=-1 5:zeta=+1
  *      tri: v0=(-1,-1) v1=(1,-1) v2=(-1,1); faces 0:v0v1 1:v1v2 2:v2v0
+ *      tet: v0=(-1,-1,-1) v1=(1,-1,-1) v2=(-1,1,-1) v3=(-1,-1,1);
+ *           faces 0:v0v1v2 1:v0v1v3 2:v1v2v3 3:v0v2v3
+ *      pri: the triangle times [-1,1]: v0..v2 at zeta=-1, v3..v5 at zeta=+1;
+ *           faces 0:v0v1v2 1:v3v4v5 2:v0v1v4v3 3:v1v2v5v4 4:v2v0v3v5
+ *    (tetrahedra and prisms: FR-DG, R and the JVP for every system; Jacobian
+ *    blocks for tetrahedra where one element's assembly fits a workgroup's
+ *    LDS, none for prisms)
  *  - Solution points of quads/hexes are the tensor Gauss-Legendre points,
  *    index rho = i + (p+1) j (+ (p+1)^2 k), xi_i ascending (appendix A);
- *    triangles use the caller's points (tri_sol_pts).
+ *    triangles and tetrahedra use the caller's points (tri_sol_pts,
+ *    tet_sol_pts); prisms the triangle points times Gauss-Legendre points
+ *    along the axis, rho = i + n_tri k.  Flux points: Gauss-Legendre on
+ *    edges and quadrilateral faces, tri_sol_pts on triangular faces.
  *  - State vectors are element-major U[n][rho][alpha] (alpha = conserved
  *    variable), in the context precision.  DOF index = (n*Ns + rho)*Nv + alpha
  *    (mixed meshes: element n's entries follow those of elements 0..n-1,
@@ -64,7 +74,7 @@ typedef enum {
   FR_E_NONFINITE = -7      /* a NaN or infinity was stored to R, Jv or the Jacobian blocks */
 } fr_status;
 
-typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2 } fr_elem_type;
+typedef enum { FR_QUAD = 0, FR_TRI = 1, FR_HEX = 2, FR_TET = 3, FR_PRI = 4 } fr_elem_type;
 typedef enum { FR_ADVECTION = 0, FR_EULER = 1, FR_NAVIER_STOKES = 2 } fr_system;
 typedef enum { FR_F64 = 0, FR_F32 = 1, FR_BF16 = 2 } fr_precision;
 /* Spatial discretisation (quadrilaterals and hexahedra; triangles FR-DG only):
@@ -98,7 +108,10 @@ typedef struct {
   const int64_t* nbr;         /* [n_elem][max_face] element across each local face (periodic: always set) */
   const int8_t* nbr_face;     /* [n_elem][max_face] local face index of that face in the neighbour */
   int32_t max_face;
-  const double* tri_sol_pts;  /* triangles: [Ns][2] reference solution points; else NULL */
+  const double* tri_sol_pts;  /* triangles: [Ns][2] reference solution points; the same set is the
+                                 flux-point set of the triangular faces of tetrahedra and prisms and
+                                 the cross-section of the prisms' solution points; else NULL */
+  const double* tet_sol_pts;  /* tetrahedra: [Ns][3] reference solution points; else NULL */
 } fr_mesh_desc;
 
 /* Field variables and fluxes (section 2; eq. "flux_advection",

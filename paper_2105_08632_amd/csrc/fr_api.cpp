@@ -17,8 +17,10 @@
 FR_DECL(quad, 1) FR_DECL(quad, 2) FR_DECL(quad, 3) FR_DECL(quad, 4)
 FR_DECL(hex, 1) FR_DECL(hex, 2) FR_DECL(hex, 3) FR_DECL(hex, 4)
 FR_DECL(tri, 1) FR_DECL(tri, 2) FR_DECL(tri, 3) FR_DECL(tri, 4)
+FR_DECL(tet, 1) FR_DECL(tet, 2) FR_DECL(tet, 3) FR_DECL(tet, 4)
+FR_DECL(pri, 1) FR_DECL(pri, 2) FR_DECL(pri, 3) FR_DECL(pri, 4)
 
-static KernelSet g_table[3][5][6];
+static KernelSet g_table[5][5][6];
 static std::once_flag g_once;
 
 static void fill_table() {
@@ -28,11 +30,15 @@ static void fill_table() {
   fr_reg_hex_3(g_table[ET_HEX][3]); fr_reg_hex_4(g_table[ET_HEX][4]);
   fr_reg_tri_1(g_table[ET_TRI][1]); fr_reg_tri_2(g_table[ET_TRI][2]);
   fr_reg_tri_3(g_table[ET_TRI][3]); fr_reg_tri_4(g_table[ET_TRI][4]);
+  fr_reg_tet_1(g_table[ET_TET][1]); fr_reg_tet_2(g_table[ET_TET][2]);
+  fr_reg_tet_3(g_table[ET_TET][3]); fr_reg_tet_4(g_table[ET_TET][4]);
+  fr_reg_pri_1(g_table[ET_PRI][1]); fr_reg_pri_2(g_table[ET_PRI][2]);
+  fr_reg_pri_3(g_table[ET_PRI][3]); fr_reg_pri_4(g_table[ET_PRI][4]);
 }
 
 bool fr_find_kernels(int type, int p, int system, int prec, KernelSet* out) {
   std::call_once(g_once, fill_table);
-  if (type < 0 || type > 2 || p < 1 || p > 4 || system < 0 || system > 2 || prec < 0 || prec > 1) return false;
+  if (type < 0 || type > 4 || p < 1 || p > 4 || system < 0 || system > 2 || prec < 0 || prec > 1) return false;
   *out = g_table[type][p][system * 2 + prec];
   return out->rhs != nullptr;
 }
@@ -214,7 +220,7 @@ static fr_status upload_ops_geo(fr_ctx_s* c, const frh::RefOps& ref, const frh::
       hipMemcpy(c->geo_mem, gb.data(), gb.size(), hipMemcpyHostToDevice) != hipSuccess) {
     return fail(nullptr, FR_E_DEVICE, "upload failed");
   }
-  if (ref.type != FR_TRI) {
+  if (ref.type == FR_QUAD || ref.type == FR_HEX) {
     for (int i = 0; i <= ref.p; ++i) {
       for (int j = 0; j <= ref.p; ++j) {
         double d = ref.D1[i * (ref.p + 1) + j];
@@ -347,7 +353,7 @@ static fr_status create_mixed(const fr_mesh_desc* m, const fr_physics* ph, fr_pr
   std::string err;
   for (int g = 0; g < ngrp; ++g) {
     const int t = m->elem_type[gs[g]];
-    if (!frh::build_ref(t, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, refs[t], err))
+    if (!frh::build_ref(t, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, m->tet_sol_pts, refs[t], err))
       return fail(nullptr, FR_E_INVALID, err);
     if (m->max_vert < refs[t].nvert || m->max_face < refs[t].nface)
       return fail(nullptr, FR_E_INVALID, "max_vert/max_face too small");
@@ -477,11 +483,12 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
   const int type = m->elem_type[0];
   bool one_type = true;
   for (int64_t e = 0; e < m->n_elem; ++e) {
-    if (m->elem_type[e] < 0 || m->elem_type[e] > 2) return fail(nullptr, FR_E_INVALID, "unknown element type");
+    if (m->elem_type[e] < 0 || m->elem_type[e] > 4) return fail(nullptr, FR_E_INVALID, "unknown element type");
     if (m->elem_type[e] != type) one_type = false;
   }
   for (int64_t e = 0; e < m->n_elem; ++e)
-    if ((m->elem_type[e] == FR_HEX) != (m->ndim == 3)) return fail(nullptr, FR_E_INVALID, "element type does not match ndim");
+    if ((m->elem_type[e] == FR_QUAD || m->elem_type[e] == FR_TRI) != (m->ndim == 2))
+      return fail(nullptr, FR_E_INVALID, "element type does not match ndim");
   if (ph->system < 0 || ph->system > 2) return fail(nullptr, FR_E_INVALID, "unknown system");
   const int nv = (ph->system == FR_ADVECTION) ? 1 : m->ndim + 2;
   if (ph->nvars != nv) return fail(nullptr, FR_E_INVALID, "nvars does not match the system");
@@ -491,7 +498,7 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     return fail(nullptr, FR_E_UNSUPPORTED, "only the BR1 scheme is provided: ldg_beta and ldg_penalty must be 0");
   if (ph->scheme < FR_SCHEME_FR_DG || ph->scheme > FR_SCHEME_SDRT)
     return fail(nullptr, FR_E_INVALID, "unknown scheme");
-  if (ph->scheme != FR_SCHEME_FR_DG && type == FR_TRI)
+  if (ph->scheme != FR_SCHEME_FR_DG && type != FR_QUAD && type != FR_HEX)
     return fail(nullptr, FR_E_UNSUPPORTED, "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra");
   if (!one_type)
     return create_mixed(m, ph, prec, stream, nv,
@@ -499,7 +506,7 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
 
   frh::RefOps ref;
   std::string err;
-  if (!frh::build_ref(type, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, ref, err))
+  if (!frh::build_ref(type, m->degree, ph->ldg_beta, ph->scheme, m->tri_sol_pts, m->tet_sol_pts, ref, err))
     return fail(nullptr, FR_E_INVALID, err);
   if (m->max_vert < ref.nvert || m->max_face < ref.nface) return fail(nullptr, FR_E_INVALID, "max_vert/max_face too small");
   frh::Geometry geo;

@@ -14,10 +14,16 @@
 //     SD flux points {-1, Gauss-Legendre points of order p, +1} (the
 //     Raviart-Thomas basis of the external flux points), in barycentric form;
 //   * triangles: orthonormal Dubiner basis from a Gauss-Jacobi quadrature mass
-//     matrix, nodal basis by the inverse Vandermonde, lifting M^{-1} E.
+//     matrix, nodal basis by the inverse Vandermonde, lifting M^{-1} E;
+//   * tetrahedra and prisms (FR-DG): products of Legendre polynomials of
+//     total degree <= p (tetrahedra; the triangle part of prisms, times a
+//     Legendre polynomial along the axis) as the modal basis, nodal basis by
+//     the inverse Vandermonde, mass matrix and face integrals E by collapsed
+//     Gauss-Legendre rules, lifting M^{-1} E.
 #include "fr_host.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 
@@ -415,15 +421,345 @@ static bool build_tri(RefOps& R, int p, const double* pts, std::string& err) {
   return true;
 }
 
-bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, RefOps& R, std::string& err) {
+// ---------------------------------------------------- tetrahedra and prisms
+// Legendre P_n and its derivative at x.
+static void legendre_pd(int n, double x, double& P, double& dP) {
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+  if (n == 0) { P = 1.0; dP = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    const double d2 = d0 + (2.0 * k - 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  P = p1; dP = d1;
+}
+
+// A 3-D face: flux points, unit outward normal, a quadrature rule (reference
+// surface measure) and the face's nodal basis at the rule's points.
+struct Face3 {
+  std::vector<double> fp, qx, qw, phi;
+  double n[3];
+};
+
+// Triangle nodal basis on the caller's points: 2-D Legendre products of total
+// degree <= p through the inverse Vandermonde.
+struct TriNodal {
+  int nt = 0;
+  std::vector<std::pair<int, int>> modes;
+  std::vector<double> Vinv;
+  bool init(int p, const double* pts) {
+    nt = (p + 1) * (p + 2) / 2;
+    for (int a = 0; a <= p; ++a)
+      for (int b = 0; a + b <= p; ++b) modes.push_back({a, b});
+    std::vector<double> V(nt * nt);
+    for (int r = 0; r < nt; ++r)
+      for (int m = 0; m < nt; ++m) V[r * nt + m] = mode(m, pts[2 * r], pts[2 * r + 1]);
+    return invert_dense(V, nt, Vinv);
+  }
+  double mode(int m, double a, double b) const {
+    double Pa, dPa, Pb, dPb;
+    legendre_pd(modes[m].first, a, Pa, dPa);
+    legendre_pd(modes[m].second, b, Pb, dPb);
+    return Pa * Pb;
+  }
+  void eval(double a, double b, std::vector<double>& l) const {
+    l.assign(nt, 0.0);
+    for (int m = 0; m < nt; ++m) {
+      const double v = mode(m, a, b);
+      for (int q = 0; q < nt; ++q) l[q] += Vinv[m * nt + q] * v;
+    }
+  }
+};
+
+static void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1]; c[1] = a[2] * b[0] - a[0] * b[2]; c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Triangular face with vertices A, B, C; points and rule mapped through the
+// barycentric coordinates of the 2-D reference triangle.
+static Face3 face_tri(const double* A, const double* B, const double* C, const double* n, int p, const double* pts,
+                      const TriNodal& tn) {
+  Face3 F;
+  for (int k = 0; k < 3; ++k) F.n[k] = n[k];
+  auto map = [&](double a, double b, double* X) {
+    const double l0 = -0.5 * (a + b), l1 = 0.5 * (1 + a), l2 = 0.5 * (1 + b);
+    for (int k = 0; k < 3; ++k) X[k] = l0 * A[k] + l1 * B[k] + l2 * C[k];
+  };
+  for (int i = 0; i < tn.nt; ++i) {
+    double X[3]; map(pts[2 * i], pts[2 * i + 1], X);
+    F.fp.insert(F.fp.end(), X, X + 3);
+  }
+  double e1[3], e2[3], cr[3];
+  for (int k = 0; k < 3; ++k) { e1[k] = B[k] - A[k]; e2[k] = C[k] - A[k]; }
+  cross3(e1, e2, cr);
+  const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+  std::vector<double> g, w, l;
+  gl_golub_welsch(p + 2, g, w);
+  for (int i = 0; i < p + 2; ++i)
+    for (int j = 0; j < p + 2; ++j) {
+      const double a = 0.5 * (1 + g[i]) * (1 - g[j]) - 1, b = g[j];
+      double X[3]; map(a, b, X);
+      F.qx.insert(F.qx.end(), X, X + 3);
+      F.qw.push_back(w[i] * w[j] * 0.5 * (1 - g[j]) * area / 2.0);   // the 2-D reference triangle has area 2
+      tn.eval(a, b, l);
+      F.phi.insert(F.phi.end(), l.begin(), l.end());
+    }
+  return F;
+}
+
+// Parallelogram face A + u (B - A) + v (D - A), u, v in [0, 1]: Gauss-Legendre
+// points (the rule of its own nodal basis).
+static Face3 face_quad(const double* A, const double* B, const double* D, const double* n, int p) {
+  Face3 F;
+  for (int k = 0; k < 3; ++k) F.n[k] = n[k];
+  const int n1 = p + 1;
+  std::vector<double> g, w;
+  gl_golub_welsch(n1, g, w);
+  double e1[3], e2[3], cr[3];
+  for (int k = 0; k < 3; ++k) { e1[k] = B[k] - A[k]; e2[k] = D[k] - A[k]; }
+  cross3(e1, e2, cr);
+  const double area = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+  for (int j = 0; j < n1; ++j)
+    for (int i = 0; i < n1; ++i) {
+      double X[3];
+      for (int k = 0; k < 3; ++k) X[k] = A[k] + 0.5 * (1 + g[i]) * e1[k] + 0.5 * (1 + g[j]) * e2[k];
+      F.fp.insert(F.fp.end(), X, X + 3);
+      F.qx.insert(F.qx.end(), X, X + 3);
+      F.qw.push_back(w[i] * w[j] * area / 4.0);
+    }
+  const int nq = n1 * n1;
+  F.phi.assign(nq * nq, 0.0);
+  for (int a = 0; a < nq; ++a) F.phi[a * nq + a] = 1.0;
+  return F;
+}
+
+// Operators of a 3-D element from a modal basis (values and gradients),
+// solution points, a volume rule and its faces.  The modal basis is first
+// made orthonormal on the element (Cholesky factor of its Gram matrix under
+// the volume rule), which keeps the Vandermonde matrix well conditioned.
+template <class Modal0>
+static bool build_3d(RefOps& R, int nm, const Modal0& modal0, const std::vector<double>& sp,
+                     const std::vector<double>& vq, const std::vector<double>& vw, const std::vector<Face3>& faces,
+                     std::string& err) {
+  const int ns = (int)sp.size() / 3;
+  R.nd = 3; R.ns = ns; R.sp = sp;
+  if (nm != ns) { err = "solution point count does not match the polynomial space"; return false; }
+  // Gram matrix and its Cholesky factor G = L L^T; psi = L^{-1} phi
+  std::vector<double> Gm(nm * nm, 0.0), Lc(nm * nm, 0.0), Li(nm * nm, 0.0), phv(nm);
+  for (size_t a = 0; a < vw.size(); ++a) {
+    double g[3];
+    for (int m = 0; m < nm; ++m) phv[m] = modal0(m, &vq[3 * a], g);
+    for (int i = 0; i < nm; ++i)
+      for (int j = 0; j < nm; ++j) Gm[i * nm + j] += vw[a] * phv[i] * phv[j];
+  }
+  for (int j = 0; j < nm; ++j) {
+    double d = Gm[j * nm + j];
+    for (int k = 0; k < j; ++k) d -= Lc[j * nm + k] * Lc[j * nm + k];
+    if (!(d > 0.0)) { err = "modal basis is not independent on the element"; return false; }
+    Lc[j * nm + j] = std::sqrt(d);
+    for (int i = j + 1; i < nm; ++i) {
+      double v = Gm[i * nm + j];
+      for (int k = 0; k < j; ++k) v -= Lc[i * nm + k] * Lc[j * nm + k];
+      Lc[i * nm + j] = v / Lc[j * nm + j];
+    }
+  }
+  for (int c = 0; c < nm; ++c)          // L^{-1} by forward substitution, column by column
+    for (int i = 0; i < nm; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= Lc[i * nm + k] * Li[k * nm + c];
+      Li[i * nm + c] = v / Lc[i * nm + i];
+    }
+  auto modal = [&](int m, const double* X, double* g) {
+    double v = 0.0, gk[3];
+    g[0] = g[1] = g[2] = 0.0;
+    for (int k = 0; k <= m; ++k) {
+      const double c = Li[m * nm + k];
+      if (c == 0.0) continue;
+      v += c * modal0(k, X, gk);
+      for (int d = 0; d < 3; ++d) g[d] += c * gk[d];
+    }
+    return v;
+  };
+  std::vector<double> V(ns * ns), Vg(3 * ns * ns), Vinv;
+  for (int r = 0; r < ns; ++r)
+    for (int m = 0; m < ns; ++m) {
+      double g[3];
+      V[r * ns + m] = modal(m, &sp[3 * r], g);
+      for (int d = 0; d < 3; ++d) Vg[(d * ns + r) * ns + m] = g[d];
+    }
+  if (!invert_dense(V, ns, Vinv)) { err = "solution points are not unisolvent"; return false; }
+  auto nodal = [&](const double* X, std::vector<double>& l) {
+    l.assign(ns, 0.0);
+    double g[3];
+    for (int m = 0; m < ns; ++m) {
+      const double v = modal(m, X, g);
+      for (int q = 0; q < ns; ++q) l[q] += Vinv[m * ns + q] * v;
+    }
+  };
+  R.D.assign(3 * ns * ns, 0.0);
+  for (int d = 0; d < 3; ++d)
+    for (int r = 0; r < ns; ++r)
+      for (int s = 0; s < ns; ++s) {
+        double acc = 0.0;
+        for (int m = 0; m < ns; ++m) acc += Vg[(d * ns + r) * ns + m] * Vinv[m * ns + s];
+        R.D[(d * ns + r) * ns + s] = acc;
+      }
+  R.nface = (int)faces.size();
+  R.face_off.assign(1, 0);
+  R.fp.clear(); R.nref.clear(); R.fface.clear();
+  R.nfp = 0;
+  for (int f = 0; f < R.nface; ++f) {
+    const int nfp = (int)faces[f].fp.size() / 3;
+    R.nfp = std::max(R.nfp, nfp);
+    R.face_off.push_back(R.face_off.back() + nfp);
+    R.fp.insert(R.fp.end(), faces[f].fp.begin(), faces[f].fp.end());
+    for (int g = 0; g < nfp; ++g) {
+      R.nref.insert(R.nref.end(), faces[f].n, faces[f].n + 3);
+      R.fface.push_back(f);
+    }
+  }
+  R.nf = R.face_off.back();
+  std::vector<double> l;
+  R.M0.assign(R.nf * ns, 0.0);
+  for (int g = 0; g < R.nf; ++g) {
+    nodal(&R.fp[3 * g], l);
+    for (int s = 0; s < ns; ++s) R.M0[g * ns + s] = l[s];
+  }
+  std::vector<double> Mm(ns * ns, 0.0), Minv;
+  for (size_t a = 0; a < vw.size(); ++a) {
+    nodal(&vq[3 * a], l);
+    for (int i = 0; i < ns; ++i)
+      for (int j = 0; j < ns; ++j) Mm[i * ns + j] += vw[a] * l[i] * l[j];
+  }
+  if (!invert_dense(Mm, ns, Minv)) { err = "singular mass matrix"; return false; }
+  std::vector<double> E(ns * R.nf, 0.0);
+  for (int f = 0; f < R.nface; ++f) {
+    const Face3& F = faces[f];
+    const int nfp = R.face_off[f + 1] - R.face_off[f];
+    for (size_t a = 0; a < F.qw.size(); ++a) {
+      nodal(&F.qx[3 * a], l);
+      for (int j = 0; j < ns; ++j)
+        for (int g = 0; g < nfp; ++g) E[j * R.nf + R.face_off[f] + g] += F.qw[a] * l[j] * F.phi[a * nfp + g];
+    }
+  }
+  R.Cor.assign(ns * R.nf, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int g = 0; g < R.nf; ++g) {
+      double acc = 0.0;
+      for (int j = 0; j < ns; ++j) acc += Minv[r * ns + j] * E[j * R.nf + g];
+      R.Cor[r * R.nf + g] = acc;
+    }
+  R.wsol.assign(ns, 0.0);
+  for (int r = 0; r < ns; ++r)
+    for (int j = 0; j < ns; ++j) R.wsol[r] += Mm[r * ns + j];
+  R.wl = ns; R.wc = R.nf;
+  return true;
+}
+
+static bool build_tet(RefOps& R, int p, const double* tet_pts, const double* tri_pts, std::string& err) {
+  R.type = TET; R.p = p; R.nvert = 4;
+  const double v[4][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+  R.face_verts = {{0, 1, 2}, {0, 1, 3}, {1, 2, 3}, {0, 2, 3}};
+  const double q3 = 1.0 / std::sqrt(3.0);
+  const double nrm[4][3] = {{0, 0, -1}, {0, -1, 0}, {q3, q3, q3}, {-1, 0, 0}};
+  TriNodal tn;
+  if (!tn.init(p, tri_pts)) { err = "face points are not unisolvent"; return false; }
+  std::vector<Face3> faces;
+  for (int f = 0; f < 4; ++f)
+    faces.push_back(face_tri(v[R.face_verts[f][0]], v[R.face_verts[f][1]], v[R.face_verts[f][2]], nrm[f], p, tri_pts, tn));
+  std::vector<std::array<int, 3>> modes;
+  for (int a = 0; a <= p; ++a)
+    for (int b = 0; a + b <= p; ++b)
+      for (int c = 0; a + b + c <= p; ++c) modes.push_back({a, b, c});
+  const int ns = (int)modes.size();
+  auto modal = [&](int m, const double* X, double* g) {
+    double P[3], dP[3];
+    for (int d = 0; d < 3; ++d) legendre_pd(modes[m][d], X[d], P[d], dP[d]);
+    g[0] = dP[0] * P[1] * P[2]; g[1] = P[0] * dP[1] * P[2]; g[2] = P[0] * P[1] * dP[2];
+    return P[0] * P[1] * P[2];
+  };
+  // collapsed Gauss-Legendre rule on the tetrahedron (volume 4/3)
+  std::vector<double> gq, gw, vq, vw;
+  gl_golub_welsch(p + 3, gq, gw);
+  for (int i = 0; i < p + 3; ++i)
+    for (int j = 0; j < p + 3; ++j)
+      for (int k = 0; k < p + 3; ++k) {
+        const double a = gq[i], b = gq[j], c = gq[k];
+        vq.push_back(0.25 * (1 + a) * (1 - b) * (1 - c) - 1);
+        vq.push_back(0.5 * (1 + b) * (1 - c) - 1);
+        vq.push_back(c);
+        vw.push_back(gw[i] * gw[j] * gw[k] * (1 - b) * (1 - c) * (1 - c) / 8.0);
+      }
+  std::vector<double> sp(tet_pts, tet_pts + 3 * ns);
+  return build_3d(R, ns, modal, sp, vq, vw, faces, err);
+}
+
+static bool build_pri(RefOps& R, int p, const double* tri_pts, std::string& err) {
+  R.type = PRI; R.p = p; R.nvert = 6;
+  const double v[6][3] = {{-1, -1, -1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, 1}};
+  R.face_verts = {{0, 1, 2}, {3, 4, 5}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+  const double h = M_SQRT1_2;
+  const double nrm[5][3] = {{0, 0, -1}, {0, 0, 1}, {0, -1, 0}, {h, h, 0}, {-1, 0, 0}};
+  TriNodal tn;
+  if (!tn.init(p, tri_pts)) { err = "triangle points are not unisolvent"; return false; }
+  std::vector<Face3> faces;
+  faces.push_back(face_tri(v[0], v[1], v[2], nrm[0], p, tri_pts, tn));
+  faces.push_back(face_tri(v[3], v[4], v[5], nrm[1], p, tri_pts, tn));
+  faces.push_back(face_quad(v[0], v[1], v[3], nrm[2], p));
+  faces.push_back(face_quad(v[1], v[2], v[4], nrm[3], p));
+  faces.push_back(face_quad(v[2], v[0], v[5], nrm[4], p));
+  const int nt = (p + 1) * (p + 2) / 2, n1 = p + 1;
+  std::vector<std::array<int, 3>> modes;
+  for (int c = 0; c <= p; ++c)
+    for (int a = 0; a <= p; ++a)
+      for (int b = 0; a + b <= p; ++b) modes.push_back({a, b, c});
+  auto modal = [&](int m, const double* X, double* g) {
+    double P[3], dP[3];
+    for (int d = 0; d < 3; ++d) legendre_pd(modes[m][d], X[d], P[d], dP[d]);
+    g[0] = dP[0] * P[1] * P[2]; g[1] = P[0] * dP[1] * P[2]; g[2] = P[0] * P[1] * dP[2];
+    return P[0] * P[1] * P[2];
+  };
+  std::vector<double> gx, gwx;
+  gl_golub_welsch(n1, gx, gwx);
+  std::vector<double> sp;                    // triangle point i at axis point k: index i + nt k
+  for (int k = 0; k < n1; ++k)
+    for (int i = 0; i < nt; ++i) { sp.push_back(tri_pts[2 * i]); sp.push_back(tri_pts[2 * i + 1]); sp.push_back(gx[k]); }
+  std::vector<double> gq, gw, vq, vw;
+  gl_golub_welsch(p + 2, gq, gw);
+  for (int i = 0; i < p + 2; ++i)
+    for (int j = 0; j < p + 2; ++j)
+      for (int k = 0; k < p + 2; ++k) {
+        vq.push_back(0.5 * (1 + gq[i]) * (1 - gq[j]) - 1);
+        vq.push_back(gq[j]);
+        vq.push_back(gq[k]);
+        vw.push_back(gw[i] * gw[j] * gw[k] * 0.5 * (1 - gq[j]));
+      }
+  return build_3d(R, (int)modes.size(), modal, sp, vq, vw, faces, err);
+}
+
+bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, const double* tet_pts, RefOps& R,
+               std::string& err) {
   if (p < 1 || p > 4) { err = "degree must be in 1..4"; return false; }
   if (scheme < 0 || scheme > 2) { err = "unknown scheme"; return false; }
-  if (scheme != 0 && type == TRI) { err = "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra"; return false; }
+  if (scheme != 0 && type != QUAD && type != HEX) {
+    err = "FR-SDRT and SDRT are provided for quadrilaterals and hexahedra";
+    return false;
+  }
   if (type == QUAD || type == HEX) build_tensor(R, type, p, scheme);
   else if (type == TRI) {
     if (!tri_pts) { err = "triangles need tri_sol_pts"; return false; }
     if (!build_tri(R, p, tri_pts, err)) return false;
+  } else if (type == TET) {
+    if (!tri_pts || !tet_pts) { err = "tetrahedra need tri_sol_pts (faces) and tet_sol_pts"; return false; }
+    if (!build_tet(R, p, tet_pts, tri_pts, err)) return false;
+  } else if (type == PRI) {
+    if (!tri_pts) { err = "prisms need tri_sol_pts"; return false; }
+    if (!build_pri(R, p, tri_pts, err)) return false;
   } else { err = "unknown element type"; return false; }
+  if (R.face_off.empty()) {
+    R.face_off.assign(R.nface + 1, 0);
+    for (int f = 0; f <= R.nface; ++f) R.face_off[f] = f * R.nfp;
+  }
   finish_ops(R, beta);
   bool ok = compress(R.M0, R.nf, R.ns, R.wl, R.m0c, R.m0v) &&
             compress(R.Dc, R.nd * R.ns, R.ns, R.wl, R.dcc, R.dcv) &&
@@ -452,6 +788,21 @@ static void shape(int type, const double* xi, double* N, double* dN) {
       dN[v * 3] = 0.125 * V[v][0] * b * c;
       dN[v * 3 + 1] = 0.125 * a * V[v][1] * c;
       dN[v * 3 + 2] = 0.125 * a * b * V[v][2];
+    }
+  } else if (type == TET) {
+    N[0] = -0.5 * (1 + xi[0] + xi[1] + xi[2]); N[1] = 0.5 * (1 + xi[0]); N[2] = 0.5 * (1 + xi[1]);
+    N[3] = 0.5 * (1 + xi[2]);
+    for (int k = 0; k < 12; ++k) dN[k] = 0.0;
+    dN[0] = dN[1] = dN[2] = -0.5;
+    dN[3] = 0.5; dN[7] = 0.5; dN[11] = 0.5;
+  } else if (type == PRI) {
+    const double L[3] = {-0.5 * (xi[0] + xi[1]), 0.5 * (1 + xi[0]), 0.5 * (1 + xi[1])};
+    const double Lr[3] = {-0.5, 0.5, 0.0}, Ls[3] = {-0.5, 0.0, 0.5};
+    for (int a = 0; a < 3; ++a) {
+      const double zb = 0.5 * (1 - xi[2]), zt = 0.5 * (1 + xi[2]);
+      N[a] = L[a] * zb; N[a + 3] = L[a] * zt;
+      dN[a * 3] = Lr[a] * zb; dN[a * 3 + 1] = Ls[a] * zb; dN[a * 3 + 2] = -0.5 * L[a];
+      dN[(a + 3) * 3] = Lr[a] * zt; dN[(a + 3) * 3 + 1] = Ls[a] * zt; dN[(a + 3) * 3 + 2] = 0.5 * L[a];
     }
   } else {
     N[0] = -0.5 * (xi[0] + xi[1]); N[1] = 0.5 * (1 + xi[0]); N[2] = 0.5 * (1 + xi[1]);
@@ -595,7 +946,8 @@ bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const 
       const RefOps& Rm = ref_of(m);
       int f2 = nbr_face[e * max_face + f];
       if (f2 < 0 || f2 >= Rm.nface) { err = "neighbour face index out of range"; return false; }
-      if (Rm.nfp != R.nfp) { err = "faces of different point counts meet"; return false; }
+      const int na = R.face_off[f + 1] - R.face_off[f], nb = Rm.face_off[f2 + 1] - Rm.face_off[f2];
+      if (na != nb) { err = "faces of different point counts meet"; return false; }
       double c1[3] = {0, 0, 0}, c2[3] = {0, 0, 0}, sz = 0.0;
       const std::vector<int>& v1 = R.face_verts[f];
       const std::vector<int>& v2 = Rm.face_verts[f2];
@@ -608,11 +960,11 @@ bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const 
         sz += d * d;
       }
       sz = std::sqrt(sz);
-      for (int a = 0; a < R.nfp; ++a) {
-        const int64_t ga = gfp(e, f * R.nfp + a);
+      for (int a = 0; a < na; ++a) {
+        const int64_t ga = gfp(e, R.face_off[f] + a);
         int64_t best = -1; double bd = 1e300;
-        for (int b = 0; b < Rm.nfp; ++b) {
-          const int64_t gb = gfp(m, f2 * Rm.nfp + b);
+        for (int b = 0; b < nb; ++b) {
+          const int64_t gb = gfp(m, Rm.face_off[f2] + b);
           double d2 = 0.0;
           for (int i = 0; i < nd; ++i) {
             double t = (fx[(size_t)ga * nd + i] - c1[i]) - (fx[(size_t)gb * nd + i] - c2[i]);
@@ -647,7 +999,7 @@ bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const 
     const int nf = R.nf;
     G[g].nbface.assign((size_t)ng * R.nface, 0);
     G[g].back.assign((size_t)ng * R.nface * R.nfp, 0);
-    if (ngrp == 1)
+    if (ngrp == 1 && R.nf == R.nface * R.nfp)
       for (int64_t e = 0; e < ng; ++e)
         for (int f = 0; f < R.nface; ++f) {
           int pg = G[g].nbfp[(size_t)e * nf + f * R.nfp];
@@ -673,8 +1025,8 @@ bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const 
           const int64_t m = nbr[e * max_face + f];
           M.nbg[el * R.nface + f] = m;
           M.nbt[el * R.nface + f] = etype[m] != gt ? 1 : 0;
-          for (int a = 0; a < R.nfp; ++a) {
-            const int j = f * R.nfp + a;
+          for (int a = 0; a < R.face_off[f + 1] - R.face_off[f]; ++a) {
+            const int j = R.face_off[f] + a;
             const int64_t pg = pair[(size_t)gfp(e, j)];
             M.nbpt[(size_t)el * R.nf + j] = (int)(pg - gfp(m, 0));
           }
@@ -687,7 +1039,7 @@ bool build_geometry_groups(const RefOps* const* refs, int nd, int64_t ne, const 
 
 bool build_geometry(const RefOps& R, int nd, int64_t ne, const double* xyz, int max_vert, const int64_t* nbr,
                     const int8_t* nbr_face, int max_face, Geometry& G, std::string& err) {
-  const RefOps* refs[3] = {&R, &R, &R};
+  const RefOps* refs[5] = {&R, &R, &R, &R, &R};
   std::vector<int8_t> et((size_t)ne, (int8_t)R.type);
   const int64_t gs[2] = {0, ne};
   return build_geometry_groups(refs, nd, ne, et.data(), xyz, max_vert, nbr, nbr_face, max_face, 1, gs, &G, nullptr,

@@ -8,7 +8,7 @@
 
 namespace frh {
 
-enum { QUAD = 0, TRI = 1, HEX = 2 };
+enum { QUAD = 0, TRI = 1, HEX = 2, TET = 3, PRI = 4 };
 
 struct RefOps {
   int type = -1, p = 0, nd = 0, ns = 0, nf = 0, nface = 0, nfp = 0, nvert = 0;
@@ -16,6 +16,7 @@ struct RefOps {
   std::vector<double> sp, fp;         // reference solution / flux points
   std::vector<double> nref;           // [nf][nd]
   std::vector<int> fface;             // [nf]
+  std::vector<int> face_off;          // [nface + 1] first flux point of each face
   std::vector<double> M0, D, Cor;     // [nf][ns], [nd][ns][ns], [ns][nf]
   std::vector<double> Dc, G;          // [nd][ns][ns]
   std::vector<int> m0c, dcc, gc, crc, ddc; // compressed rows
@@ -37,8 +38,12 @@ struct RefOps {
 };
 
 // Builds the FR-DG reference operators.  beta enters G (self gradient).
-// tri_pts: [ns][2] solution points for triangles (may be null otherwise).
-bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, RefOps& out, std::string& err);
+// tri_pts: [ns][2] triangle points (triangles' solution points, the
+// triangular faces of tetrahedra and prisms, the prisms' cross-section);
+// tet_pts: [ns][3] solution points of tetrahedra.  Either may be null where
+// unused.
+bool build_ref(int type, int p, double beta, int scheme, const double* tri_pts, const double* tet_pts, RefOps& out,
+               std::string& err);
 
 // SDRT: row d of detJ J^{-1} at the interior flux points of every line along
 // axis d, [ne][nd][nl][p][nd] (nl = lines per axis).

@@ -130,7 +130,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
   // with the SD correction is the SDRT gradient), then the SDRT divergence.
   template <class T, class RC, class IO>
   static int residual_sd(fr_ctx_s* c, const IO* U, const IO* V, T* UF, T* Q, T* QF, IO* Rout, IO* Rtan) {
-    if constexpr (ET == ET_TRI) {
+    if constexpr (!et_tensor(ET)) {
       c->err = "SDRT is provided for quadrilaterals and hexahedra";
       return -2;
     } else {
@@ -239,7 +239,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   // Jacobian blocks of an element group of a mixed 2-D mesh (inviscid).
-  static constexpr bool kMixedJac = ET != ET_HEX && SYS != SYS_NS;
+  static constexpr bool kMixedJac = (ET == ET_QUAD || ET == ET_TRI) && SYS != SYS_NS;
   template <class OT> static int jac_mixed_t(fr_ctx_s* c, int stage, const R* U, OT* B, const MixD<R>* mx) {
     if constexpr (!kMixedJac) {
       c->err = "Jacobian blocks of mixed meshes: 2-D inviscid systems only";
@@ -278,16 +278,29 @@ template <int ET, int P, int SYS, class R> struct Impl {
     return -2;
   }
 
-  static constexpr bool kTensorPath = (ET != ET_TRI) && (jac_tp_lds<E, NV, SYS, R>() <= kMaxLds);
+  static constexpr bool tensor_fits() {
+    if constexpr (et_tensor(ET)) return jac_tp_lds<E, NV, SYS, R>() <= kMaxLds;
+    else return false;
+  }
+  static constexpr bool mfma_fits() {
+    if constexpr (et_tensor(ET) && std::is_same<R, float>::value)
+      return jac_mf_sens_lds<E, NV, SYS, R>() <= kMaxLds && jac_mf_tables_lds<E, NV, SYS, R>() <= kMaxLds;
+    else return false;
+  }
+  static constexpr bool kTensorPath = tensor_fits();
   // matrix-core path: FP32 quadrilaterals and hexahedra
-  static constexpr bool kMfmaPath = (ET != ET_TRI) && std::is_same<R, float>::value &&
-                                    jac_mf_sens_lds<E, NV, SYS, R>() <= kMaxLds &&
-                                    jac_mf_tables_lds<E, NV, SYS, R>() <= kMaxLds;
+  static constexpr bool kMfmaPath = mfma_fits();
+  // the generic assembly needs faces of equal size (not prisms)
+  static constexpr bool generic_fits() {
+    if constexpr (ET == ET_PRI) return false;
+    else return jac_lds<E, NV, SYS, R>() <= kMaxLds;
+  }
   typedef MfSizes<E, NV, SYS> MF;
 
   template <class OT> static int jac_t(fr_ctx_s* c, const R* U, OT* B, int nblk) {
-    if constexpr (!kMfmaPath && !kTensorPath && jac_lds<E, NV, SYS, R>() > kMaxLds) {
-      c->err = "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
+    if constexpr (!kMfmaPath && !kTensorPath && !generic_fits()) {
+      c->err = ET == ET_PRI ? "Jacobian blocks are not provided for prisms"
+                            : "Jacobian blocks of this element type / degree / precision do not fit one workgroup";
       return -2;
     } else {
     OpsD<R> op = ctx_ops<R>(c);
@@ -364,7 +377,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
   }
 
   static KernelSet set() {
-    return KernelSet{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup, ET == ET_TRI ? nullptr : &rhs_sd,
-                     ET == ET_TRI ? nullptr : &jvp_sd, &phase, ET == ET_HEX ? nullptr : &jac_mixed};
+    KernelSet k{&rhs, &rhs_ws, &jvp, &jac, &mf_bytes, &mf_setup, nullptr, nullptr, &phase, nullptr};
+    if constexpr (et_tensor(ET)) { k.rhs_sd = &rhs_sd; k.jvp_sd = &jvp_sd; }
+    if constexpr (ET == ET_QUAD || ET == ET_TRI) k.jac_mixed = &jac_mixed;
+    return k;
   }
 };

@@ -17,7 +17,9 @@
 #include "dual.hpp"
 #include "physics.hpp"
 
-enum { ET_QUAD = 0, ET_TRI = 1, ET_HEX = 2 };
+enum { ET_QUAD = 0, ET_TRI = 1, ET_HEX = 2, ET_TET = 3, ET_PRI = 4 };
+// Tensor-product element types (line operators, matrix-core Jacobian, SDRT).
+constexpr bool et_tensor(int et) { return et == ET_QUAD || et == ET_HEX; }
 
 template <int ET, int P> struct Elem;
 template <int P> struct Elem<ET_QUAD, P> {
@@ -31,6 +33,22 @@ template <int P> struct Elem<ET_HEX, P> {
                        NFP = (P + 1) * (P + 1), NF = 6 * (P + 1) * (P + 1), NVERT = 8;
   static constexpr int WL = P + 1;
   static constexpr int WC = 6;
+};
+// Tetrahedra: four triangular faces of (p+1)(p+2)/2 points; dense operator rows.
+template <int P> struct Elem<ET_TET, P> {
+  static constexpr int ET = ET_TET, DEG = P, ND = 3, NS = (P + 1) * (P + 2) * (P + 3) / 6, NFACE = 4,
+                       NFP = (P + 1) * (P + 2) / 2, NF = 4 * NFP, NVERT = 4;
+  static constexpr int WL = NS;
+  static constexpr int WC = NF;
+};
+// Prisms: two triangular faces of (p+1)(p+2)/2 points and three
+// quadrilateral faces of (p+1)^2 (faces of unequal size: NFP is the largest;
+// the residual kernels only use NF); dense operator rows.
+template <int P> struct Elem<ET_PRI, P> {
+  static constexpr int ET = ET_PRI, DEG = P, ND = 3, NS = (P + 1) * (P + 1) * (P + 2) / 2, NFACE = 5,
+                       NFP = (P + 1) * (P + 1), NF = (P + 1) * (P + 2) + 3 * (P + 1) * (P + 1), NVERT = 6;
+  static constexpr int WL = NS;
+  static constexpr int WC = NF;
 };
 template <int P> struct Elem<ET_TRI, P> {
   static constexpr int ET = ET_TRI, DEG = P, ND = 2, NS = (P + 1) * (P + 2) / 2, NFACE = 3, NFP = P + 1,
@@ -121,7 +139,9 @@ template <class T, class R, class IO> FR_HD T make_in(const IO* U, const IO* V, 
 }
 
 template <class E> constexpr int rhs_tile() {
-  return E::NS >= 64 ? 2 : (E::NS >= 25 ? 4 : (E::NS >= 9 ? 8 : 16));
+  // tetrahedra and prisms keep dense operator rows in LDS: fewer elements per tile
+  if constexpr (E::ET == ET_TET || E::ET == ET_PRI) return E::NS >= 30 ? 1 : (E::NS >= 10 ? 2 : 4);
+  else return E::NS >= 64 ? 2 : (E::NS >= 25 ? 4 : (E::NS >= 9 ? 8 : 16));
 }
 
 // --------------------------------------------------------------------------

@@ -34,7 +34,7 @@ class _Mesh(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("n_elem", C.c_int64), ("degree", C.c_int32),
                 ("elem_type", C.c_void_p), ("elem_xyz", C.c_void_p), ("max_vert", C.c_int32),
                 ("nbr", C.c_void_p), ("nbr_face", C.c_void_p), ("max_face", C.c_int32),
-                ("tri_sol_pts", C.c_void_p)]
+                ("tri_sol_pts", C.c_void_p), ("tet_sol_pts", C.c_void_p)]
 
 
 class _Phys(C.Structure):
@@ -101,7 +101,7 @@ def _ptr(t) -> int:
 class Context:
     """One mesh + physics + precision on one HIP stream."""
 
-    def __init__(self, mesh, phys, precision: str = "f64", stream=None, tri_pts=None):
+    def __init__(self, mesh, phys, precision: str = "f64", stream=None, tri_pts=None, tet_pts=None):
         import torch
         L = lib()
         self.mesh, self.phys = mesh, phys
@@ -112,11 +112,12 @@ class Context:
                       np.ascontiguousarray(mesh.nbr, dtype=np.int64),
                       np.ascontiguousarray(mesh.nbr_face, dtype=np.int8)]
         tp = None if tri_pts is None else np.ascontiguousarray(tri_pts, dtype=np.float64)
-        self._keep.append(tp)
+        qp = None if tet_pts is None else np.ascontiguousarray(tet_pts, dtype=np.float64)
+        self._keep += [tp, qp]
         m = _Mesh(mesh.ndim, mesh.n_elem, int(mesh.degree[0]),
                   self._keep[0].ctypes.data, self._keep[1].ctypes.data, mesh.max_vert,
                   self._keep[2].ctypes.data, self._keep[3].ctypes.data, mesh.max_face,
-                  None if tp is None else tp.ctypes.data)
+                  None if tp is None else tp.ctypes.data, None if qp is None else qp.ctypes.data)
         ph = _Phys(phys.system, phys.nvars, (C.c_double * 3)(*[float(x) for x in phys.adv_vel]),
                    phys.gamma, phys.mu, phys.prandtl, phys.beta, phys.eta, int(getattr(phys, "scheme", 0)))
         if stream is None:

@@ -91,3 +91,23 @@ def test_create_refuses_ungrouped_mixed_mesh_without_gpu_work():
     rc = L.fr_ctx_create(ctypes.byref(md), ctypes.byref(ph), 0, None, ctypes.byref(h))
     assert rc == -1
     assert b"grouped by type" in L.fr_last_error(None)
+
+
+def test_create_tetrahedra_need_their_points_without_gpu_work():
+    """Tetrahedra without tet_sol_pts are refused on the host."""
+    if not os.path.exists(fr.LIB_PATH):
+        pytest.skip("libfr.so not built")
+    import numpy as np
+    from paper_2105_08632_amd import inputs as I
+    L = fr.lib()
+    m = I.tet_mesh(3, degree=2)
+    keep = [np.ascontiguousarray(m.elem_type, dtype=np.int8), np.ascontiguousarray(m.xyz),
+            np.ascontiguousarray(m.nbr, dtype=np.int64), np.ascontiguousarray(m.nbr_face, dtype=np.int8),
+            np.ascontiguousarray(I.tri_points(2))]
+    md = fr._Mesh(3, m.n_elem, 2, keep[0].ctypes.data, keep[1].ctypes.data, m.max_vert,
+                  keep[2].ctypes.data, keep[3].ctypes.data, m.max_face, keep[4].ctypes.data, None)
+    ph = fr._Phys(1, 5, (ctypes.c_double * 3)(0, 0, 0), 1.4, 0.0, 0.72, 0.0, 0.0, 0)
+    h = ctypes.c_void_p()
+    rc = L.fr_ctx_create(ctypes.byref(md), ctypes.byref(ph), 0, None, ctypes.byref(h))
+    assert rc == -1
+    assert b"tet_sol_pts" in L.fr_last_error(None)
