@@ -256,6 +256,32 @@ def newton_bench(torch, fr, I, train_steps, log):
     return out
 
 
+def newton_step_profile(torch, fr, I, log):
+    """One backward-Euler Newton step on 256x256 NS p=3 at CFL 5 with FP64
+    block-Jacobi, host-driven and then graph-replayed (after one untimed step
+    of each), for kernel traces of the GMRES loop."""
+    ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
+    m = I.quad_mesh(256, degree=3, jitter=0.05)
+    U = I.ns2d_state(m, 3, seeds=(8, 108, 208))
+    ctx = fr.Context(m, ph, "f64")
+    Ud = torch.from_numpy(U).cuda()
+    dt = _dt(m, U, 5.0)
+    sol = fr.Solver(ctx, restart=30)
+    pc = fr.Precond(ctx)
+    out = {"workload": "2D NS p=3, 256x256 jittered periodic quads, backward Euler at CFL 5, Newton to 1e-8 "
+                       "relative, GMRES(30), FP64 block-Jacobi"}
+    for mode in ("host", "graph"):
+        for rep in range(2):
+            r = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False,
+                                use_graph=(mode == "graph"))
+            log(f"newton {mode} rep {rep}: conv {r['converged']} newton {r['newton_iters']} "
+                f"gmres {r['gmres_iters']} ms {r['ms']:.1f}")
+        out[mode] = {"converged": bool(r["converged"]), "newton_iters": r["newton_iters"],
+                     "gmres_iters": r["gmres_iters"], "ms": round(r["ms"], 2),
+                     "ms_per_gmres_iter": round(r["ms"] / max(1, r["gmres_iters"]), 4)}
+    return out
+
+
 def rk54_pm_bench(torch, fr, I, log, N=40, steps=4):
     """The paper's own performance metric on its own case: wall time per
     degree of freedom per Runge-Kutta stage, PM = T / (N_iter N_s N_V n_elem
@@ -565,9 +591,10 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true", help="skip the 2-D quadrilateral measurement")
     ap.add_argument("--no-lu", action="store_true", help="skip the block-Jacobi LU of the 3-D blocks")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 block assembly")
-    ap.add_argument("--only", choices=["cfg2", "cfg2_bf16", "cfg1", "lu"], default=None,
+    ap.add_argument("--only", choices=["cfg2", "cfg2_bf16", "cfg1", "lu", "newton"], default=None,
                     help="time only this workload's step: the 3-D step with FP32 or BF16 blocks, the 2-D "
-                         "step, or the block-Jacobi LU of the 3-D blocks (profiling runs)")
+                         "step, the block-Jacobi LU of the 3-D blocks, or one LU-preconditioned Newton step "
+                         "on 256x256 (host-driven, then graph-replayed; profiling runs)")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
@@ -582,6 +609,9 @@ def main():
     from paper_2105_08632_amd import fr
     from paper_2105_08632_amd import inputs as I
 
+    if args.only == "newton":
+        print(json.dumps(newton_step_profile(torch, fr, I, log)), flush=True)
+        return
     if args.only == "cfg1":
         out = cfg1_bench(torch, fr, args.steps, args.warmup, log)
         if args.copy_probe > 0:
