@@ -407,16 +407,31 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
 
 // ------------------------------------------------------------ large blocks
 // Blocks above 128 (hexahedra of degree 3: b = 320) do not fit one
-// workgroup's LDS.  They are factorized in place in global memory: blocked
-// right-looking LU with partial pivoting (panels of kLuNB columns factorized
-// in LDS; the panel's row exchanges applied to every other column; U12 by a
-// triangular solve; A22 -= L21 U12 from LDS-staged operands in 4 x 4
-// register tiles), one workgroup per element, two resident per CU.  The
-// preconditioner applies the factors by forward and backward substitution.
-// 16-column panels keep the workgroup's LDS under half the CU's 160 KB: two
-// workgroups per CU hide each other's barrier waits (75 -> 53 ms for 13 824
-// blocks of 320, against 32-column panels at one workgroup per CU)
-constexpr int kLuThreads = 512, kLuNB = 16, kLuMaxB = 320;
+// workgroup's LDS.  Blocked right-looking LU with partial pivoting, one
+// 1024-thread workgroup per element, in 64-column panels:
+//  1. the panel (every row, 64 columns) is held in registers: wave w owns
+//     columns 4w .. 4w+3, lane l rows l + 64 s.  A pivot step is one
+//     barrier: the wave owning the column picks the pivot (a DPP maximum of
+//     |value| keyed with the row), forms the multipliers and publishes them
+//     in LDS; every wave then updates its own columns, reading the pivot
+//     row's values from its own registers (readlane);
+//  2. rows never move in memory.  A chosen pivot row receives its rank (its
+//     logical row index); the trailing columns keep physical row order, and
+//     each panel is stored with its pivot rows at their ranks followed by
+//     the rows still to pivot in increasing physical order, so that the
+//     panel's multipliers below its first row are one contiguous range;
+//  3. the trailing columns are updated in slabs of 64: every row not
+//     pivoted before this panel (its pivot rows first, in pivot order) is
+//     updated by 16-column chunks of the multipliers, each chunk's pivot
+//     rows being finished first by a 16 x 16 unit-lower solve in LDS.  So
+//     U12 = L11^-1 A12 and A22 -= L21 U12 are one pass of 5 x 4 register
+//     tiles, with no 64-long sequential solve.
+// The first panel reads A = shift I + scale J straight from J (no separate
+// conversion pass).  The substitution recovers each panel's row positions
+// from the ranks.
+constexpr int kLuThreads = 1024, kLuNB = 64, kLuMaxB = 320, kLuQM = (kLuMaxB + 63) / 64;
+constexpr int kLuFree = 1 << 20;          // rank of a row not yet chosen as pivot
+constexpr int kLuSlab = 64;               // trailing columns per slab
 
 // Wave-uniform lane l's value of v.
 __device__ __forceinline__ double fr_readlane(double v, int l) {
@@ -425,278 +440,342 @@ __device__ __forceinline__ double fr_readlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// A = shift I + scale J (column-major, input type IT) factorized with partial
-// pivoting: unit lower L and upper U stored over A in LU (column-major);
-// piv[k] is the row exchanged with row k at step k.  Each panel's L columns
-// keep the row order reached at that panel (later exchanges are not applied
-// to them), so A = P_1 L_1 P_2 L_2 ... U with P_p the exchanges of panel p
-// and L_p the unit lower factor of its columns.  bad[n] = 1 when a pivot is
-// zero or not finite.
-template <class IT>
-__global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
-                                                         double* LU, int* piv, int* bad, const int* list) {
-  constexpr int LD = kLuMaxB;                         // panel leading dimension (constant offsets)
-  __shared__ double P[kLuMaxB * kLuNB];               // panel rows k0.., column-major
-  __shared__ double Ut[(kLuMaxB - kLuNB) * kLuNB];    // U12, column c at c * kLuNB
-  __shared__ double red_v[kLuThreads / 64];
-  __shared__ int red_i[kLuThreads / 64];
-  __shared__ int s_piv[kLuMaxB];                      // row exchanged with row k at step k
-  __shared__ int s_bad;
-  __shared__ int s_mv_dst[2 * kLuNB], s_mv_src[2 * kLuNB], s_nmv;   // a panel's row moves
-  const int n = list ? list[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
-  const long bb = (long)b * b;
-  const IT* Jn = J + (long)n * jstride;
-  double* A = LU + (long)n * bb;
-  for (long i = tid; i < bb; i += kLuThreads) {
-    const int c = (int)(i / b), r = (int)(i % b);
-    A[i] = scale * (double)Jn[i] + (r == c ? shift : 0.0);
+// Lane l's value of x[s] for wave-uniform s and l: every slot is read with
+// readlane and the slot chosen among the scalars (selecting the register
+// first would turn into an indexed access to scratch memory).
+template <int N>
+__device__ __forceinline__ double fr_lane_slot(const double (&x)[N], int s, int l) {
+  double v = fr_readlane(x[0], l);
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    const double o = fr_readlane(x[i], l);
+    v = s == i ? o : v;
   }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  for (int k0 = 0; k0 < b; k0 += kLuNB) {
-    const int w = min(kLuNB, b - k0), m = b - k0;
-    for (int i = tid; i < m * w; i += kLuThreads) {
-      const int j = i / m, r = i % m;
-      P[j * LD + r] = A[(long)(k0 + j) * b + k0 + r];
-    }
-    __syncthreads();
-    for (int j = 0; j < w; ++j) {
-      // pivot: the largest |P[r][j]|, r >= j (lowest index on ties)
-      double best = -1.0;
-      int bi = j;
-      for (int r = j + tid; r < m; r += kLuThreads) {
-        const double v = fabs(P[j * LD + r]);
-        if (v > best) { best = v; bi = r; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if ((tid & 63) == 0) { red_v[tid >> 6] = best; red_i[tid >> 6] = bi; }
-      __syncthreads();
-      best = red_v[0];
-      int p = red_i[0];
-      for (int q = 1; q < kLuThreads / 64; ++q)
-        if (red_v[q] > best || (red_v[q] == best && red_i[q] < p)) { best = red_v[q]; p = red_i[q]; }
-      if (tid == 0) {
-        s_piv[k0 + j] = k0 + p;
-        const double pv = P[j * LD + p];
-        if (!(fabs(pv) > 0.0) || !isfinite(pv)) s_bad = 1;
-      }
-      if (p != j && tid < w) {
-        const double t = P[tid * LD + j];
-        P[tid * LD + j] = P[tid * LD + p];
-        P[tid * LD + p] = t;
-      }
-      __syncthreads();
-      const double pv = P[j * LD + j];
-      const double ip = (pv != 0.0 && isfinite(pv)) ? 1.0 / pv : 0.0;
-      for (int r = j + 1 + tid; r < m; r += kLuThreads) P[j * LD + r] *= ip;
-      __syncthreads();
-      const int mr = m - j - 1;
-      for (int i = tid; i < (w - j - 1) * mr; i += kLuThreads) {
-        const int c = j + 1 + i / mr, r = j + 1 + i % mr;
-        P[c * LD + r] -= P[j * LD + r] * P[c * LD + j];
-      }
-      __syncthreads();
-    }
-    for (int i = tid; i < m * w; i += kLuThreads) {
-      const int j = i / m, r = i % m;
-      A[(long)(k0 + j) * b + k0 + r] = P[j * LD + r];
-    }
-    // the panel's row exchanges on the trailing columns (the factored L
-    // columns to the left keep the row order of their own panel; the
-    // substitution applies each panel's exchanges before its columns),
-    // composed into one row permutation: the list of (destination, source)
-    // moves (at most 2 kLuNB rows), then each column loads all its sources
-    // before storing (one memory round trip instead of a chain of dependent
-    // exchanges)
-    {
-      // the exchanges applied to the index of each row k0 .. b-1 (in the idle
-      // U12 buffer), then the moved rows compacted into the list
-      int* perm_k = reinterpret_cast<int*>(Ut);
-      for (int i = tid; i < m; i += kLuThreads) perm_k[i] = i;
-      if (tid == 0) s_nmv = 0;
-      __syncthreads();
-      if (tid == 0)
-        for (int j = 0; j < w; ++j) {
-          const int q = s_piv[k0 + j] - k0, t = perm_k[j];
-          perm_k[j] = perm_k[q];
-          perm_k[q] = t;
-        }
-      __syncthreads();
-      for (int i = tid; i < m; i += kLuThreads)
-        if (perm_k[i] != i) {
-          const int slot = atomicAdd(&s_nmv, 1);     // at most 2 kLuNB rows move
-          s_mv_dst[slot] = k0 + i;
-          s_mv_src[slot] = k0 + perm_k[i];
-        }
-    }
-    __syncthreads();
-    {
-      // one column per thread; its sources are staged in the idle U12
-      // buffer (nm slots per column, as many columns per pass as fit), so
-      // every load is issued before any store.  The panel buffer still holds
-      // L11 and L21 for what follows.
-      static_assert(kLuMaxB - kLuNB <= kLuThreads, "one column per thread");
-      const int nm = s_nmv, c = tid;
-      const int cpp = nm > 0 ? (kLuMaxB - kLuNB) * kLuNB / nm : kLuThreads;   // columns per pass
-      const int nc = b - k0 - w;                                         // trailing columns
-      for (int c0 = 0; c0 < nc; c0 += cpp) {                             // uniform trip count
-        if (c >= c0 && c < c0 + cpp && c < nc) {
-          double* Ac = A + (long)(k0 + w + c) * b;
-          double* st = Ut + (c - c0) * nm;
-          for (int i = 0; i < nm; ++i) st[i] = Ac[s_mv_src[i]];
-          for (int i = 0; i < nm; ++i) Ac[s_mv_dst[i]] = st[i];
-        }
-        __syncthreads();
-      }
-    }
-    const int n2 = b - k0 - w;
-    if (n2 > 0) {
-      // U12 = L11^-1 A12, one column per thread (L11[r][q] = P[q LD + r]);
-      // n2 < kLuThreads, so no thread takes two columns (a loop here would
-      // let the compiler hoist all of L11 into registers)
-      static_assert(kLuMaxB - kLuNB <= kLuThreads, "one U12 column per thread");
-      if (tid < n2) {
-        const int c = tid;
-        double* Ac = A + (long)(k0 + w + c) * b + k0;
-        double x[kLuNB];
-#pragma unroll
-        for (int r = 0; r < kLuNB; ++r) x[r] = r < w ? Ac[r] : 0.0;
-        // column-oriented: x[r] -= L11[r][q] x[q] for r > q, one column of
-        // L11 at a time (the fence keeps its loads from piling up)
-#pragma unroll
-        for (int q = 0; q < kLuNB - 1; ++q) {
-          const double xq = x[q];
-          // the column's base is opaque to the optimizer and depends on x[q]:
-          // its loads wait for x[q] instead of all 496 being issued (and
-          // spilled) first
-          int qo = q * LD;
-          asm volatile("" : "+v"(qo) : "v"(xq));
-          const double* Pq = P + qo;
-#pragma unroll
-          for (int r = q + 1; r < kLuNB; ++r) x[r] -= Pq[r] * xq;
-        }
-#pragma unroll
-        for (int r = 0; r < kLuNB; ++r) x[r] = r < w ? x[r] : 0.0;
-#pragma unroll
-        for (int r = 0; r < kLuNB; ++r)
-          if (r < w) { Ac[r] = x[r]; Ut[c * kLuNB + r] = x[r]; }
-      }
-      __syncthreads();
-      // A22 -= L21 U12 in 4 x 4 register tiles (threads along rows)
-      const int nt2 = (n2 + 3) / 4;
-      for (int ti = tid; ti < nt2 * nt2; ti += kLuThreads) {
-        const int i0 = (ti % nt2) * 4, c0 = (ti / nt2) * 4;
-        double acc[4][4];
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-            acc[a][cc] = (i0 + a < n2 && c0 + cc < n2) ? A[(long)(k0 + w + c0 + cc) * b + k0 + w + i0 + a] : 0.0;
-        for (int q = 0; q < w; ++q) {
-          double l[4], u[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) l[a] = i0 + a < n2 ? P[q * LD + w + i0 + a] : 0.0;
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc) u[cc] = c0 + cc < n2 ? Ut[(c0 + cc) * kLuNB + q] : 0.0;
-#pragma unroll
-          for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-            for (int a = 0; a < 4; ++a) acc[a][cc] -= l[a] * u[cc];
-        }
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-            if (i0 + a < n2 && c0 + cc < n2) A[(long)(k0 + w + c0 + cc) * b + k0 + w + i0 + a] = acc[a][cc];
-      }
-      __syncthreads();
-    }
-  }
-  if (tid == 0) bad[n] = s_bad;
-  for (int i = tid; i < b; i += kLuThreads) piv[(long)n * b + i] = s_piv[i];
+  return v;
 }
 
-// z_n = A_n^-1 r_n from the factors: one wavefront per element, rows
-// lane + 64 q of the vector in registers, each substitution step's value
-// broadcast from the lane that owns it (columns of L and U are contiguous
-// runs); each panel's row exchanges are applied to the vector just before
-// its columns eliminate (A = P_1 L_1 P_2 L_2 ... U).
-template <class VT>
-__global__ void __launch_bounds__(256) k_block_lu_apply(long ne, int b, const double* LU, const int* piv, const VT* r,
-                                                        VT* z) {
-  constexpr int QM = (kLuMaxB + 63) / 64;
-  static_assert(64 % kLuNB == 0, "a panel lies in one 64-row block of the vector");
-  const int lane = threadIdx.x & 63;
-  const long n = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (n >= ne) return;
-  const double* A = LU + n * b * b;
-  const int* pn = piv + n * b;
-  const VT* rn = r + n * b;
-  double y[QM];
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long fr_max_dpp(unsigned long long v) {
+  const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+  const unsigned lo2 = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const unsigned hi2 = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  const unsigned long long o = ((unsigned long long)hi2 << 32) | lo2;
+  return o > v ? o : v;
+}
+
+// Maximum over the wavefront by DPP: quad swaps, half-row and row mirrors
+// (every row of 16 lanes then holds its maximum), then the row broadcasts
+// 15 and 31 (lane 63 ends with the maximum of all four rows).
+__device__ __forceinline__ unsigned long long fr_wave_max_u64(unsigned long long v) {
+  v = fr_max_dpp<0xB1, 0xF>(v);
+  v = fr_max_dpp<0x4E, 0xF>(v);
+  v = fr_max_dpp<0x141, 0xF>(v);
+  v = fr_max_dpp<0x140, 0xF>(v);
+  v = fr_max_dpp<0x142, 0xA>(v);
+  v = fr_max_dpp<0x143, 0xC>(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// A = shift I + scale J (column-major, input type IT) factorized with partial
+// pivoting.  perm[i] = the row (of A) chosen as pivot at step i.  Storage
+// (column-major LU): column c of panel P (columns K .. K+w-1) holds at
+// position i < K+w the entry of row perm[i] (U above the diagonal, the unit
+// lower L's multipliers below it, the diagonal of U on it), and at position
+// K+w+m the multiplier of the m-th row, in increasing row order, among those
+// not pivoted by the end of panel P.  bad[n] = 1 when a pivot is zero or not
+// finite.
+template <class IT>
+__global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
+                                                         double* LU, int* perm, int* bad, const int* list) {
+  __shared__ int s_rank[kLuMaxB];
+  __shared__ int s_perm[kLuMaxB];
+  __shared__ int s_act[kLuMaxB];                  // rows still to pivot, increasing
+  __shared__ int s_apos[kLuMaxB];                 // a row's position in s_act
+  __shared__ double s_l[2][kLuQM * 64];           // multipliers of a pivot step (double-buffered)
+  __shared__ int s_p[2];
+  __shared__ int s_bad;
+  __shared__ double s_ls[16][kLuMaxB];            // a chunk of multipliers, rows in stored order
+  __shared__ double s_us[16][kLuSlab];            // a chunk of U rows over the slab
+  __shared__ double s_ld[16][16];                 // the chunk's diagonal block of L11
+  const int n = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const IT* Jn = J + (long)n * jstride;
+  double* A = LU + (long)n * b * b;
+  for (int i = tid; i < kLuMaxB; i += kLuThreads) s_rank[i] = kLuFree;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  for (int K = 0; K < b; K += kLuNB) {
+    const bool first = K == 0;                    // read A from J
+    auto src = [&](int r, int c) -> double {
+      return first ? scale * (double)Jn[(long)c * b + r] + (r == c ? shift : 0.0) : A[(long)c * b + r];
+    };
+    const int w = min(kLuNB, b - K);
+    // ---- 1. the panel in registers
+    double pa[kLuQM][4];
+    unsigned act = 0;                             // bit s: row lane + 64 s not pivoted yet
 #pragma unroll
-  for (int q = 0; q < QM; ++q) {
-    const int row = lane + 64 * q;
-    y[q] = row < b ? (double)rn[row] : 0.0;
-  }
+    for (int s = 0; s < kLuQM; ++s) {
+      const int r = lane + 64 * s;
+      if (r < b && s_rank[r] == kLuFree) act |= 1u << s;
 #pragma unroll
-  for (int q = 0; q < QM; ++q) {
-    const int jend = min(64, b - 64 * q);
-    for (int jl = 0; jl < jend; ++jl) {
-      const int j = 64 * q + jl;
-      if (jl % kLuNB == 0) {
-        // this panel's exchanges, in order (rows j .. j + kLuNB - 1 with their
-        // pivot rows, which lie at or below them)
-        const int je = min(j + kLuNB, b);
-        for (int jj = j; jj < je; ++jj) {
-          const int p = pn[jj];
-          if (p != jj) {
-            const int lj = jj & 63, qp = p >> 6, lp = p & 63;
-            const double a = fr_readlane(y[q], lj);
-            double ysel = y[q];
+      for (int c = 0; c < 4; ++c) pa[s][c] = (r < b && 4 * wv + c < w) ? src(r, K + 4 * wv + c) : 0.0;
+    }
+    for (int j4 = 0; j4 < w; j4 += 4)
 #pragma unroll
-            for (int qq = q + 1; qq < QM; ++qq)
-              if (qq == qp) ysel = y[qq];
-            const double bv = fr_readlane(ysel, lp);
-            if (lane == lj) y[q] = bv;
+    for (int cj = 0; cj < 4; ++cj) {
+      const int j = j4 + cj;                      // the column within the panel (cj: within its wave)
+      if (j >= w) break;
+      const int buf = j & 1;
+      if (wv == (j >> 2)) {
+        double colv[kLuQM];
 #pragma unroll
-            for (int qq = q; qq < QM; ++qq)
-              if (qq == qp && lane == lp) y[qq] = a;
+        for (int s = 0; s < kLuQM; ++s) colv[s] = pa[s][cj];
+        // pivot: the largest |value| among rows not pivoted; the key is the
+        // bit pattern of |value| (ordered like the value) with its lowest 9
+        // bits replaced by 511 - row (ties, to 2^-43 relative: the lowest
+        // row); not-a-number ranks first and is flagged below
+        unsigned long long key = 0;
+#pragma unroll
+        for (int s = 0; s < kLuQM; ++s)
+          if (act >> s & 1) {
+            const unsigned long long k = ((unsigned long long)__double_as_longlong(fabs(colv[s])) & ~0x1FFull) |
+                                         (unsigned long long)(511 - (lane + 64 * s));
+            key = k > key ? k : key;
           }
+        key = fr_wave_max_u64(key);
+        const int p = 511 - (int)(key & 0x1FFull);
+        const double pv = fr_lane_slot(colv, p >> 6, p & 63);
+        const bool ok = fabs(pv) > 0.0 && isfinite(pv);
+        const double ip = ok ? 1.0 / pv : 0.0;
+#pragma unroll
+        for (int s = 0; s < kLuQM; ++s) {
+          const int r = lane + 64 * s;
+          double l = 0.0;
+          if ((act >> s & 1) && r != p) {
+            l = colv[s] * ip;
+            pa[s][cj] = l;
+          }
+          s_l[buf][r] = l;
+        }
+        if (lane == 0) {
+          s_p[buf] = p;
+          if (!ok) s_bad = 1;
         }
       }
-      const double yj = fr_readlane(y[q], jl);
+      __syncthreads();
+      const int p = __builtin_amdgcn_readfirstlane(s_p[buf]);
+      if (tid == 0) {
+        s_perm[K + j] = p;
+        s_rank[p] = K + j;
+      }
+      if ((p & 63) == lane) act &= ~(1u << (p >> 6));
+      if (4 * wv + 3 > j) {
+        double u[4], l[kLuQM];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double col[kLuQM];
+#pragma unroll
+          for (int s = 0; s < kLuQM; ++s) col[s] = pa[s][c];
+          u[c] = fr_lane_slot(col, p >> 6, p & 63);
+        }
+#pragma unroll
+        for (int s = 0; s < kLuQM; ++s) l[s] = s_l[buf][lane + 64 * s];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (4 * wv + c > j)
+#pragma unroll
+            for (int s = 0; s < kLuQM; ++s) pa[s][c] -= l[s] * u[c];
+      }
+    }
+    __syncthreads();                              // the panel's ranks are complete
+    if (wv == 0) {
+      // rows still to pivot, in increasing order
+      int base = 0;
+#pragma unroll
+      for (int s = 0; s < kLuQM; ++s) {
+        const int r = lane + 64 * s;
+        const bool f = r < b && s_rank[r] == kLuFree;
+        const unsigned long long m = __ballot(f);
+        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (f) {
+          s_act[pos] = r;
+          s_apos[r] = pos;
+        }
+        base += __popcll(m);
+      }
+    }
+    __syncthreads();
+    const int na = b - K - w;                     // rows still to pivot = trailing columns
+#pragma unroll
+    for (int s = 0; s < kLuQM; ++s) {
+      const int r = lane + 64 * s;
+      if (r < b) {
+        const int rk = s_rank[r];
+        const int pos = rk != kLuFree ? rk : K + w + s_apos[r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (4 * wv + c < w) A[(long)(K + 4 * wv + c) * b + pos] = pa[s][c];
+      }
+    }
+    if (na == 0) break;
+    // ---- 3. the trailing columns, slab by slab: rows in stored order (the
+    // panel's pivot rows, then the rows still to pivot), 5 x 4 tiles: lane
+    // rows rg + 64 a, wave columns 4 wv .. 4 wv + 3 of the slab
+    const int nr = w + na;                        // rows updated (w = 64 here)
+    const int rg = lane;
+    for (int c0 = K + w; c0 < b; c0 += kLuSlab) {
+      __syncthreads();                            // the stored panel / the previous slab
+      int phys[kLuQM];
+#pragma unroll
+      for (int a = 0; a < kLuQM; ++a) {
+        const int i = rg + 64 * a;
+        phys[a] = i < w ? s_perm[K + i] : (i < nr ? s_act[i - w] : -1);
+      }
+      double acc[kLuQM][4];
+#pragma unroll
+      for (int a = 0; a < kLuQM; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int col = c0 + 4 * wv + cc;
+          acc[a][cc] = (phys[a] >= 0 && col < b) ? src(phys[a], col) : 0.0;
+        }
+      for (int q0 = 0; q0 < w; q0 += 16) {
+        // multipliers of columns K+q0 .. K+q0+15 for the rows after this
+        // chunk's pivot rows (zero for the pivot rows up to the chunk's
+        // last: the chunk's own are solved below, the earlier ones are done)
+        for (int e = tid; e < 16 * kLuMaxB; e += kLuThreads) {
+          const int q = e / kLuMaxB, i = e % kLuMaxB;
+          s_ls[q][i] = (i >= q0 + 16 && i < nr) ? A[(long)(K + q0 + q) * b + K + i] : 0.0;
+        }
+        if (tid < 256) {
+          const int q = tid >> 4, i = tid & 15;   // s_ld[i][q] = L11[q0 + i][q0 + q]
+          s_ld[i][q] = i > q ? A[(long)(K + q0 + q) * b + K + q0 + i] : 0.0;
+        }
+        if (rg >= q0 && rg < q0 + 16)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) s_us[rg - q0][4 * wv + cc] = acc[0][cc];
+        __syncthreads();
+        if (wv == 0) {
+          // the chunk's pivot rows: unit-lower solve, one column per lane
+          double x[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) x[i] = s_us[i][lane];
+#pragma unroll
+          for (int q = 0; q < 15; ++q) {
+            // the column index is made opaque and tied to x[q], so its loads
+            // wait for x[q] instead of all 120 being hoisted into registers
+            const double xq = x[q];
+            int qo = q;
+            asm volatile("" : "+v"(qo) : "v"(xq));
+#pragma unroll
+            for (int i = q + 1; i < 16; ++i) x[i] -= s_ld[i][qo] * xq;
+          }
+#pragma unroll
+          for (int i = 1; i < 16; ++i) s_us[i][lane] = x[i];
+        }
+        __syncthreads();
+        if (rg >= q0 && rg < q0 + 16)
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[0][cc] = s_us[rg - q0][4 * wv + cc];
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+          double l[kLuQM], u[4];
+#pragma unroll
+          for (int a = 0; a < kLuQM; ++a) l[a] = s_ls[q][rg + 64 * a];
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) u[cc] = s_us[q][4 * wv + cc];
+#pragma unroll
+          for (int a = 0; a < kLuQM; ++a)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) acc[a][cc] -= l[a] * u[cc];
+        }
+        __syncthreads();                          // s_ls / s_us / s_ld are rewritten next
+      }
+#pragma unroll
+      for (int a = 0; a < kLuQM; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int col = c0 + 4 * wv + cc;
+          if (phys[a] >= 0 && col < b) A[(long)col * b + phys[a]] = acc[a][cc];
+        }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) bad[n] = s_bad;
+  for (int i = tid; i < b; i += kLuThreads) perm[(long)n * b + i] = s_perm[i];
+}
+
+// z_n = A_n^-1 r_n from the factors: one wavefront per element, the vector in
+// registers in the rows' own order (lane l holds rows l + 64 s), each
+// substitution step's value read from the lane holding the pivot row.  Rows
+// still to pivot at the end of a panel sit after its pivot rows in
+// increasing order (their positions from a ballot prefix count), so the
+// forward sweep reads only positions below the diagonal and the backward
+// sweep only those above.
+template <class VT>
+__global__ void __launch_bounds__(256) k_block_lu_apply(long ne, int b, const double* LU, const int* perm, const VT* r,
+                                                        VT* z) {
+  __shared__ int s_perm[4][kLuMaxB];
+  __shared__ int s_rank[4][kLuMaxB];
+  const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+  const long n = (long)blockIdx.x * 4 + wl;
+  if (n >= ne) return;
+  const double* A = LU + n * b * b;
+  int* sp = s_perm[wl];
+  int* sr = s_rank[wl];
+  for (int i = lane; i < b; i += 64) {
+    const int p = perm[n * b + i];
+    sp[i] = p;
+    sr[p] = i;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  const VT* rn = r + n * b;
+  double y[kLuQM];
+  int rk[kLuQM];
+#pragma unroll
+  for (int s = 0; s < kLuQM; ++s) {
+    const int row = lane + 64 * s;
+    y[s] = row < b ? (double)rn[row] : 0.0;
+    rk[s] = row < b ? sr[row] : -1;
+  }
+  // forward: L y' = P r
+  for (int K = 0; K < b; K += kLuNB) {
+    const int w = min(kLuNB, b - K);
+    int pos[kLuQM];
+    int base = 0;
+#pragma unroll
+    for (int s = 0; s < kLuQM; ++s) {
+      const bool f = rk[s] >= K + w;
+      const unsigned long long m = __ballot(f);
+      pos[s] = f ? K + w + base + __popcll(m & ((1ull << lane) - 1ull)) : rk[s];
+      base += __popcll(m);
+    }
+    for (int j = K; j < K + w; ++j) {
+      const int p = __builtin_amdgcn_readfirstlane(sp[j]);
+      const double yj = fr_lane_slot(y, p >> 6, p & 63);
       const double* Lc = A + (long)j * b;
 #pragma unroll
-      for (int q2 = q; q2 < QM; ++q2) {
-        const int row = lane + 64 * q2;
-        if (row > j && row < b) y[q2] -= Lc[row] * yj;
-      }
+      for (int s = 0; s < kLuQM; ++s)
+        if (rk[s] > j) y[s] -= Lc[pos[s]] * yj;
+    }
+  }
+  // backward: U x = y'
+  for (int j = b - 1; j >= 0; --j) {
+    const int p = __builtin_amdgcn_readfirstlane(sp[j]);
+    const double* Uc = A + (long)j * b;
+    const double xj = fr_lane_slot(y, p >> 6, p & 63) / Uc[j];
+#pragma unroll
+    for (int s = 0; s < kLuQM; ++s) {
+      if (s == (p >> 6) && lane == (p & 63)) y[s] = xj;
+      if (rk[s] >= 0 && rk[s] < j) y[s] -= Uc[rk[s]] * xj;
     }
   }
 #pragma unroll
-  for (int q = QM - 1; q >= 0; --q) {
-    const int jend = min(64, b - 64 * q);
-    for (int jl = jend - 1; jl >= 0; --jl) {
-      const int j = 64 * q + jl;
-      const double* Uc = A + (long)j * b;
-      const double yj = fr_readlane(y[q], jl) / Uc[j];
-      if (lane == jl) y[q] = yj;
-#pragma unroll
-      for (int q2 = 0; q2 <= q; ++q2) {
-        const int row = lane + 64 * q2;
-        if (row < j) y[q2] -= Uc[row] * yj;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < QM; ++q) {
-    const int row = lane + 64 * q;
-    if (row < b) z[n * b + row] = (VT)y[q];
-  }
+  for (int s = 0; s < kLuQM; ++s)
+    if (rk[s] >= 0) z[n * b + rk[s]] = (VT)y[s];
 }
 
 // ------------------------------------------------------------ helpers
