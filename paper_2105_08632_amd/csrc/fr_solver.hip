@@ -423,7 +423,8 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
 //  3. the trailing columns are updated in slabs of 64: every row not
 //     pivoted before this panel (its pivot rows first, in pivot order) is
 //     updated by 16-column chunks of the multipliers, each chunk's pivot
-//     rows being finished first by a 16 x 16 unit-lower solve in LDS.  So
+//     rows being finished first by the inverse of its 16 x 16 diagonal
+//     block of L11 (the four inverses formed once per panel).  So
 //     U12 = L11^-1 A12 and A22 -= L21 U12 are one pass of 5 x 4 register
 //     tiles, with no 64-long sequential solve.
 // The first panel reads A = shift I + scale J straight from J (no separate
@@ -497,8 +498,9 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
   __shared__ int s_p[2];
   __shared__ int s_bad;
   __shared__ double s_ls[16][kLuMaxB];            // a chunk of multipliers, rows in stored order
-  __shared__ double s_us[16][kLuSlab];            // a chunk of U rows over the slab
-  __shared__ double s_ld[16][16];                 // the chunk's diagonal block of L11
+  __shared__ double s_us[16][kLuSlab];            // a chunk's pivot rows over the slab, as updated so far
+  __shared__ double s_uf[16][kLuSlab];            // the same rows finished (U)
+  __shared__ double s_li[4][16][16];              // inverses of L11's four 16 x 16 diagonal blocks
   const int n = list ? list[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const IT* Jn = J + (long)n * jstride;
@@ -548,7 +550,11 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
         const int p = 511 - (int)(key & 0x1FFull);
         const double pv = fr_lane_slot(colv, p >> 6, p & 63);
         const bool ok = fabs(pv) > 0.0 && isfinite(pv);
-        const double ip = ok ? 1.0 / pv : 0.0;
+        // 1 / pv: hardware reciprocal and two Newton steps
+        double ip = __builtin_amdgcn_rcp(pv);
+        ip = fma(ip, fma(-pv, ip, 1.0), ip);
+        ip = fma(ip, fma(-pv, ip, 1.0), ip);
+        ip = ok ? ip : 0.0;
 #pragma unroll
         for (int s = 0; s < kLuQM; ++s) {
           const int r = lane + 64 * s;
@@ -625,6 +631,27 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
     // rows rg + 64 a, wave columns 4 wv .. 4 wv + 3 of the slab
     const int nr = w + na;                        // rows updated (w = 64 here)
     const int rg = lane;
+    __syncthreads();                              // the stored panel is read below
+    if (tid < 64) {
+      // inverse of diagonal block tid / 16 of the unit-lower L11, column
+      // tid % 16, by forward substitution
+      const int d = tid >> 4, c = tid & 15;
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = i == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = 0; q < 15; ++q) {
+        // the column's address is made opaque and tied to x[q], so its loads
+        // wait for x[q] instead of all 120 being hoisted into registers
+        const double xq = x[q];
+        long co = (long)(K + 16 * d + q) * b + K + 16 * d;
+        asm volatile("" : "+v"(co) : "v"(xq));
+#pragma unroll
+        for (int i = q + 1; i < 16; ++i) x[i] -= A[co + i] * xq;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s_li[d][i][c] = x[i];
+    }
     for (int c0 = K + w; c0 < b; c0 += kLuSlab) {
       __syncthreads();                            // the stored panel / the previous slab
       int phys[kLuQM];
@@ -649,49 +676,36 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
           const int q = e / kLuMaxB, i = e % kLuMaxB;
           s_ls[q][i] = (i >= q0 + 16 && i < nr) ? A[(long)(K + q0 + q) * b + K + i] : 0.0;
         }
-        if (tid < 256) {
-          const int q = tid >> 4, i = tid & 15;   // s_ld[i][q] = L11[q0 + i][q0 + q]
-          s_ld[i][q] = i > q ? A[(long)(K + q0 + q) * b + K + q0 + i] : 0.0;
-        }
         if (rg >= q0 && rg < q0 + 16)
 #pragma unroll
           for (int cc = 0; cc < 4; ++cc) s_us[rg - q0][4 * wv + cc] = acc[0][cc];
         __syncthreads();
-        if (wv == 0) {
-          // the chunk's pivot rows: unit-lower solve, one column per lane
-          double x[16];
+        {
+          // the chunk's pivot rows finished: U = (diagonal block)^-1 x rows
+          const int i = tid >> 6, c = tid & 63;
+          const double(*li)[16] = s_li[q0 >> 4];
+          double v = 0.0;
 #pragma unroll
-          for (int i = 0; i < 16; ++i) x[i] = s_us[i][lane];
-#pragma unroll
-          for (int q = 0; q < 15; ++q) {
-            // the column index is made opaque and tied to x[q], so its loads
-            // wait for x[q] instead of all 120 being hoisted into registers
-            const double xq = x[q];
-            int qo = q;
-            asm volatile("" : "+v"(qo) : "v"(xq));
-#pragma unroll
-            for (int i = q + 1; i < 16; ++i) x[i] -= s_ld[i][qo] * xq;
-          }
-#pragma unroll
-          for (int i = 1; i < 16; ++i) s_us[i][lane] = x[i];
+          for (int q = 0; q < 16; ++q) v += li[i][q] * s_us[q][c];
+          s_uf[i][c] = v;
         }
         __syncthreads();
         if (rg >= q0 && rg < q0 + 16)
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) acc[0][cc] = s_us[rg - q0][4 * wv + cc];
+          for (int cc = 0; cc < 4; ++cc) acc[0][cc] = s_uf[rg - q0][4 * wv + cc];
 #pragma unroll 4
         for (int q = 0; q < 16; ++q) {
           double l[kLuQM], u[4];
 #pragma unroll
           for (int a = 0; a < kLuQM; ++a) l[a] = s_ls[q][rg + 64 * a];
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) u[cc] = s_us[q][4 * wv + cc];
+          for (int cc = 0; cc < 4; ++cc) u[cc] = s_uf[q][4 * wv + cc];
 #pragma unroll
           for (int a = 0; a < kLuQM; ++a)
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) acc[a][cc] -= l[a] * u[cc];
         }
-        __syncthreads();                          // s_ls / s_us / s_ld are rewritten next
+        __syncthreads();                          // s_ls / s_us / s_uf are rewritten next
       }
 #pragma unroll
       for (int a = 0; a < kLuQM; ++a)
