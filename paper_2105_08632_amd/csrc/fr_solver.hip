@@ -262,20 +262,34 @@ constexpr int kOrthBlocks = 512, kOrthThreads = 512, kMaxK = 32;
 
 // out[q] = sum over workgroups b < nblk of p[b][q], q < nq; every thread of
 // the workgroup gets the sums (through red, [waves][kMaxK] plus [kMaxK]).
+// NQ (>= nq) bounds the unrolled loads: all of a thread's loads are issued
+// before the first reduction.
+template <int NQ = kMaxK>
 __device__ __forceinline__ void orth_sum_partials(const double* p, int nblk, int nq, double (*red)[kMaxK],
                                                   double* sums) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int q = 0; q < nq; ++q) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kOrthThreads) v += p[(long)b * kMaxK + q];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wave][q] = v;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kOrthThreads) {
+    const double* pb = p + (long)b * kMaxK;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q < nq) v[q] += pb[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q < nq) {
+      double x = v[q];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) red[wave][q] = x;
+    }
   }
   __syncthreads();
   if (threadIdx.x < nq) {
-    double v = 0.0;
-    for (int wv = 0; wv < kOrthThreads / 64; ++wv) v += red[wv][threadIdx.x];
-    sums[threadIdx.x] = v;
+    double x = 0.0;
+    for (int wv = 0; wv < kOrthThreads / 64; ++wv) x += red[wv][threadIdx.x];
+    sums[threadIdx.x] = x;
   }
   __syncthreads();
 }
@@ -289,18 +303,13 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, 
   __shared__ double red[kOrthThreads / 64][kMaxK];
   __shared__ double hs[kMaxK];
   constexpr int NA = MODE == 2 ? 1 : K;
-  double acc[NA], hq[K];
+  double acc[NA];
   if constexpr (MODE >= 1) {
-    orth_sum_partials(pin, gridDim.x, K, red, hs);
+    orth_sum_partials<K>(pin, gridDim.x, K, red, hs);
     if (blockIdx.x == 0 && threadIdx.x < K) hout[threadIdx.x] = hs[threadIdx.x];
   }
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    if constexpr (MODE >= 1) hq[q] = hs[q];
-    else hq[q] = 0.0;
-  }
   for (long i = (long)blockIdx.x * kOrthThreads + threadIdx.x; i < n; i += (long)gridDim.x * kOrthThreads) {
     double vv[K];
     const double* Vi = V + i;
@@ -308,8 +317,13 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, 
     for (int q = 0; q < K; ++q) vv[q] = Vi[(long)q * ld];
     double wi = w[i];
     if constexpr (MODE >= 1) {
+      // the coefficients are read from LDS (broadcast) in every iteration
+      // (an opaque offset keeps the loads in the loop) rather than held in
+      // registers: K of them would cost 2 K registers and occupancy
+      int ho = 0;
+      asm volatile("" : "+v"(ho));
 #pragma unroll
-      for (int q = 0; q < K; ++q) wi -= hq[q] * vv[q];
+      for (int q = 0; q < K; ++q) wi -= hs[q + ho] * vv[q];
       w[i] = wi;
     }
     if constexpr (MODE <= 1) {
@@ -359,7 +373,7 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth_finish(long n, int j, int
                                                               double* v, double* H, double* dn) {
   __shared__ double red[kOrthThreads / 64][kMaxK];
   __shared__ double nn[1];
-  orth_sum_partials(p2, nblk, 1, red, nn);
+  orth_sum_partials<1>(p2, nblk, 1, red, nn);
   const double hn = sqrt(fmax(nn[0], 0.0));
   if (blockIdx.x == 0) {
     if (threadIdx.x <= j) H[threadIdx.x * m + j] = h1[threadIdx.x] + h2[threadIdx.x];
