@@ -502,6 +502,194 @@ def cpu_baseline(m, ph, p, U32, R_gpu, Jv_gpu, v, blocks, budget_s, log):
     return out, errors
 
 
+def _threads(omp, n):
+    if omp is not None:
+        omp.omp_set_num_threads(n)
+
+
+def cpu_table(torch, fr, I, log, budget_s):
+    """The oracle timed on one host thread and on all of them beside the
+    GPU, per workload: the 8x8 advection case (R and the full Jacobian), the
+    128^2 NS step (R and all blocks: the full residual plus a seeded sample of
+    elements, extrapolated), the 64-mesh mixed batch (the residuals of two
+    meshes and the blocks of a seeded sample of elements, extrapolated to the
+    64 meshes), and one backward-Euler Newton-GMRES step with block Jacobi
+    on a 64^2 NS mesh (the oracle's plain Newton-GMRES; the one-thread figure
+    from its first GMRES iterations, extrapolated).  Each row states its
+    sample.  The 24^3 hexahedral row is the main line's cpu_baseline."""
+    from oracle import newton as ON
+    from oracle import oracle as O
+    omp = _omp()
+    cores = omp.omp_get_max_threads() if omp else (os.cpu_count() or 1)
+    rows = {"cores": cores, "cpu_model": cpu_model()}
+
+    def clock(fn):
+        t0 = time.perf_counter()
+        r = fn()
+        return time.perf_counter() - t0, r
+
+    # ---- 8x8 periodic advection, p=2: R and the full 576x576 Jacobian (FP64)
+    p = 2
+    m = I.quad_mesh(8, degree=p)
+    ph = I.advection_physics((1.0, 0.5))
+    U = I.advection_state(m, p, seed=1).reshape(-1)
+    o = O.Oracle(m, ph, p)
+    t_all, J = clock(lambda: (o.rhs(U), o.jac_full(U)))
+    _threads(omp, 1)
+    t_one, _ = clock(lambda: (o.rhs(U), o.jac_full(U)))
+    _threads(omp, cores)
+    ctx = fr.Context(m, ph, "f64")
+    Ud = torch.from_numpy(U).cuda()
+    B = ctx.block_tensor("f64")
+    R = ctx.empty_state()
+
+    def step():
+        ctx.rhs(Ud, R)
+        ctx.jacobian_blocks(Ud, B, "f64")
+    wall, _, _ = _timed_steps(torch, ctx, step, 20, 3)
+    Bn = B.cpu().numpy().transpose(0, 1, 3, 2)
+    Jg = np.zeros((U.size, U.size))
+    b = Bn.shape[-1]
+    for n in range(m.n_elem):
+        for sl, k in enumerate([n] + [int(x) for x in m.nbr[n]]):
+            Jg[n * b:(n + 1) * b, k * b:(k + 1) * b] += Bn[n, sl]
+    rows["cfg0"] = {"workload": "2-D advection p=2, 8x8 periodic quads: R + full 576x576 Jacobian, FP64",
+                    "oracle_1core_dof_s": U.size / t_one, "oracle_allcore_dof_s": U.size / t_all,
+                    "gpu_dof_s": U.size * 20 / wall, "gpu_ms": 1e3 * wall / 20,
+                    "max_rel_error": max(_rel(R.cpu().numpy().reshape(-1), o.rhs(U)), _rel(Jg, J[1])),
+                    "sample": "whole workload"}
+    log(f"cpu table cfg0: {rows['cfg0']}")
+    del ctx, B, R, o
+
+    # ---- 128^2 NS p=3: full R + all blocks of a seeded element sample
+    m, ph, p, U = workload()
+    U32 = U.astype(np.float32).astype(np.float64)
+    o = O.Oracle(m, ph, p)
+    t_r, Rref = clock(lambda: o.rhs(U32))
+    rng = np.random.default_rng(1)
+    el = np.sort(rng.choice(m.n_elem, 64, replace=False))
+    b = U.shape[1] * U.shape[2]
+    t_b, Bref = clock(lambda: o.jac_blocks(U32, el, b, 4))
+    _threads(omp, 1)
+    t_b1, _ = clock(lambda: o.jac_blocks(U32, el[:4], b, 4))
+    t_r1, _ = clock(lambda: o.rhs(U32))
+    _threads(omp, cores)
+    per_all = t_r + t_b * m.n_elem / len(el)
+    per_one = t_r1 + t_b1 * m.n_elem / 4
+    ctx = fr.Context(m, ph, "f32")
+    Ud = torch.from_numpy(U32).float().cuda().contiguous()
+    B = ctx.block_tensor("f32")
+    R = ctx.empty_state()
+    ctx.rhs(Ud, R)
+    ctx.jacobian_blocks(Ud, B, "f32")
+    sel = torch.from_numpy(el).cuda()
+    Bg = B[sel].double().cpu().numpy().transpose(0, 1, 3, 2)
+    err = max(_rel(R.double().cpu().numpy().reshape(-1), Rref), max(_rel(Bg[i], Bref[i]) for i in range(len(el))))
+    rows["cfg1"] = {"workload": "2-D NS p=3, 128^2 jittered quads: R + the five 64x64 blocks per element; GPU FP32 "
+                                "blocks, oracle FP64 at the GPU's FP32 inputs",
+                    "oracle_1core_dof_s": U.size / per_one, "oracle_allcore_dof_s": U.size / per_all,
+                    "max_rel_error": err,
+                    "sample": f"full R; blocks of 64 seeded elements (all cores, {t_b:.1f} s) / 4 (one thread, "
+                              f"{t_b1:.1f} s), extrapolated to 16384"}
+    log(f"cpu table cfg1: {rows['cfg1']}")
+    del ctx, B, R, o
+
+    # ---- the 64-mesh mixed batch
+    meshes = I.mixed_batch()
+    errs = []
+    rng = np.random.default_rng(2)
+    picks = rng.choice(len(meshes), 2, replace=False)
+    frac_time_all = frac_time_one = 0.0
+    dof_sampled = 0
+    ph = I.euler_physics(2)
+    for mi in picks:
+        m, p, tp, Um = meshes[mi]
+        o = O.Oracle(m, ph, p, tp)
+        Uq = np.ascontiguousarray(Um.reshape(-1)).astype(np.float32).astype(np.float64)
+        t_r, Rref = clock(lambda: o.rhs(Uq))
+        el = np.sort(rng.choice(m.n_elem, 8, replace=False))
+        t_b = 0.0
+        refs = {}
+        for n in el:
+            nf = 3 if m.elem_type[n] == I.TRI else 4
+            bn = I.n_sol_points(int(m.elem_type[n]), p) * ph.nvars
+            t, r = clock(lambda n=n, nf=nf, bn=bn: [o.jac_block(Uq, int(n), k, bn, I.n_sol_points(
+                int(m.elem_type[k]), p) * ph.nvars) for k in [int(n)] + [int(x) for x in m.nbr[n, :nf]]])
+            t_b += t
+            refs[int(n)] = r
+        _threads(omp, 1)
+        t_r1, _ = clock(lambda: o.rhs(Uq))
+        n0 = int(el[0])
+        nf0 = 3 if m.elem_type[n0] == I.TRI else 4
+        bn0 = I.n_sol_points(int(m.elem_type[n0]), p) * ph.nvars
+        t_b1, _ = clock(lambda: [o.jac_block(Uq, n0, k, bn0, I.n_sol_points(int(m.elem_type[k]), p) * ph.nvars)
+                                 for k in [n0] + [int(x) for x in m.nbr[n0, :nf0]]])
+        _threads(omp, cores)
+        frac_time_all += t_r + t_b * m.n_elem / len(el)
+        frac_time_one += t_r1 + t_b1 * m.n_elem
+        dof_sampled += Um.size
+        ctx = fr.Context(m, ph, "f32", tri_pts=tp)
+        Ud = torch.from_numpy(Uq).float().cuda()
+        R = ctx.rhs(Ud)
+        B = ctx.jacobian_blocks(Ud)
+        ctx.sync()
+        errs.append(_rel(R.double().cpu().numpy().reshape(-1), Rref))
+        for n in el:
+            nf = 3 if m.elem_type[n] == I.TRI else 4
+            s0 = np.max(np.abs(refs[int(n)][0]))
+            for sl in range(1 + nf):
+                g = ctx.block(B, int(n), sl).double().cpu().numpy().T
+                errs.append(float(np.max(np.abs(g - refs[int(n)][sl])) / s0))
+        del ctx, B, R, o
+    rows["cfg3"] = {"workload": "64 mixed triangle/quadrilateral 2-D Euler meshes, p 1-4 (185k elements): R + all "
+                                "blocks; GPU FP32 (batched, tuned: the main line's batch entry), oracle FP64",
+                    "oracle_1core_dof_s": dof_sampled / frac_time_one, "oracle_allcore_dof_s": dof_sampled / frac_time_all,
+                    "max_rel_error": max(errs),
+                    "sample": f"meshes {sorted(int(x) for x in picks)}: full R, the blocks of 8 seeded elements each "
+                              "(one element on one thread), extrapolated per mesh; DOF/s over those two meshes"}
+    log(f"cpu table cfg3: {rows['cfg3']}")
+
+    # ---- one Newton-GMRES step with block Jacobi on 64^2 NS p=3
+    ph = I.ns_physics(2, reynolds=1000.0, prandtl=0.72)
+    p = 3
+    m = I.quad_mesh(64, degree=p, jitter=0.05)
+    U = I.ns2d_state(m, p, seeds=(8, 108, 208))
+    dt = _dt(m, U, 5.0)
+    b = U.shape[1] * U.shape[2]
+    o = O.Oracle(m, ph, p)
+    Uf = U.reshape(-1)
+
+    def setup():
+        return o.jac_blocks(Uf, np.arange(m.n_elem), b, 4)[:, 0]
+    t_set, blocks = clock(setup)
+    t_it, (Uc, hist, its) = clock(lambda: ON.newton_gmres(o, Uf, dt, b, precond_blocks=blocks, maxit=3000))
+    t_all = t_set + t_it
+    _threads(omp, 1)
+    t_set1, _ = clock(lambda: o.jac_blocks(Uf, np.arange(0, m.n_elem, 16), b, 4))
+    t_it1, (_, _, its5) = clock(lambda: ON.newton_gmres(o, Uf, dt, b, precond_blocks=blocks, maxit=5,
+                                                        newton_maxit=1))
+    _threads(omp, cores)
+    t_one = t_set1 * 16 + t_it1 / max(its5, 1) * its
+    ctx = fr.Context(m, ph, "f64")
+    Ud = torch.from_numpy(U).cuda()
+    sol = fr.Solver(ctx, restart=30)
+    pc = fr.Precond(ctx)
+    sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False)
+    rg = sol.newton_step(Ud, pc=pc, dt=dt, gmres_maxit=3000, newton_maxit=12, check=False)
+    torch.cuda.synchronize()
+    rows["cfg4"] = {"workload": "one backward-Euler Newton step to 1e-8 relative, GMRES(30) forcing 1e-3, FP64 block "
+                                "Jacobi, 2-D NS p=3 on 64^2 quads at CFL 5 (the 256^2 workload scaled down)",
+                    "oracle_allcore_s": t_all, "oracle_gmres_iters": its, "oracle_newton_iters": len(hist) - 1,
+                    "oracle_1core_s": t_one, "gpu_s": rg["ms"] / 1e3,
+                    "gpu_gmres_iters": rg["gmres_iters"], "gpu_newton_iters": rg["newton_iters"],
+                    "update_rel_difference": float(np.max(np.abs(rg["U"].cpu().numpy().reshape(-1) - Uc)) /
+                                                   max(np.max(np.abs(Uc - Uf)), 1e-300)),
+                    "sample": "all cores: the whole step; one thread: the diagonal blocks of every 16th element "
+                              "(x16) and the first 5 GMRES iterations (per iteration x the all-core count)"}
+    log(f"cpu table cfg4: {rows['cfg4']}")
+    return rows
+
+
 def budget_sample(ne, budget_s, per_elem_s, cores, rng):
     """Seeded element sample sized to about budget_s of oracle time."""
     n = int(max(cores, min(ne, budget_s * cores / per_elem_s)))
@@ -596,6 +784,10 @@ def main():
                          "step, the block-Jacobi LU of the 3-D blocks, or one LU-preconditioned Newton step "
                          "on 256x256 (host-driven, then graph-replayed; profiling runs)")
     ap.add_argument("--mlp-steps", type=int, default=24000)
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="time the oracle on one thread and on all host threads beside the GPU for the 8x8 "
+                         "advection case, the 128^2 step, the mixed batch and a 64^2 Newton step (prints one "
+                         "JSON line; a few minutes of host time)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the timed region, launch a plain device copy of MIB MiB three times "
                          "(calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE against known bytes)")
@@ -609,6 +801,9 @@ def main():
     from paper_2105_08632_amd import fr
     from paper_2105_08632_amd import inputs as I
 
+    if args.cpu_table:
+        print(json.dumps(cpu_table(torch, fr, I, log, args.cpu_seconds)), flush=True)
+        return
     if args.only == "newton":
         print(json.dumps(newton_step_profile(torch, fr, I, log)), flush=True)
         return
