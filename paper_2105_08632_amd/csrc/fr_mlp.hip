@@ -44,7 +44,7 @@ __host__ __device__ inline float bf2f(bfu h) { return __builtin_bit_cast(float, 
 // one 16-byte read; the next K tile is fetched into registers while the
 // current one is multiplied.
 constexpr int kGT = 128, kGK = 32, kLDK = kGK + 8;
-enum { EPI_BIAS_RELU = 0, EPI_BIAS = 1, EPI_MASK = 2, EPI_F32_ATOMIC = 3 };
+enum { EPI_BIAS_RELU = 0, EPI_BIAS = 1, EPI_MASK = 2, EPI_F32_ATOMIC = 3, EPI_F32_SLICE = 4 };
 
 struct GemmArgs {
   int M, N, K, kchunk;
@@ -53,6 +53,7 @@ struct GemmArgs {
   const float* bias;                    // [N]            EPI_BIAS_RELU, EPI_BIAS
   const bfu* mask; long ldm;         // C *= (mask > 0) EPI_MASK
   void* C; long ldc;                    // BF16, or FP32 accumulated atomically
+  long slice;                           // EPI_F32_SLICE: FP32 partial sums of k-chunk z at C + z * slice
 };
 
 template <bool TR>
@@ -139,6 +140,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         float v = acc[i][j][r];
         if (EPI == EPI_F32_ATOMIC) {
           atomicAdd((float*)g.C + (long)m * g.ldc + n, v);
+        } else if (EPI == EPI_F32_SLICE) {
+          ((float*)g.C)[blockIdx.z * g.slice + (long)m * g.ldc + n] = v;
         } else {
           if (EPI == EPI_BIAS_RELU || EPI == EPI_BIAS) v += g.bias[n];
           if (EPI == EPI_BIAS_RELU) v = v > 0.f ? v : 0.f;
@@ -234,6 +237,22 @@ __global__ void __launch_bounds__(256) k_colsum(const bfu* X, int rows, int cols
   float s = 0.f;
   for (int r = r0; r < r1; ++r) s += bf2f(X[(long)r * ld + c]);
   atomicAdd(out + c, s);
+}
+
+// C = epilogue(sum over the nz k-chunk slices of P, in slice order): the
+// split-K GEMM's deterministic reduction (P [nz][M][N] FP32, C BF16)
+template <int EPI>
+__global__ void __launch_bounds__(256) k_split_epi(int M, int N, int nz, const float* P, long slice, const float* bias,
+                                                   const bfu* mask, long ldm, bfu* C, long ldc) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < (long)M * N; i += (long)gridDim.x * 256) {
+    const int m = (int)(i / N), n = (int)(i % N);
+    float v = 0.f;
+    for (int z = 0; z < nz; ++z) v += P[z * slice + i];
+    if (EPI == EPI_BIAS_RELU || EPI == EPI_BIAS) v += bias[n];
+    if (EPI == EPI_BIAS_RELU) v = v > 0.f ? v : 0.f;
+    if (EPI == EPI_MASK) v = bf2f(mask[(long)m * ldm + n]) > 0.f ? v : 0.f;
+    C[(long)m * ldc + n] = f2bf(v);
+  }
 }
 
 __global__ void k_fill_f32(long n, float v, float* x) {
@@ -446,6 +465,7 @@ struct fr_mlp_s {
   bfu* wbf = nullptr;
   bfu *H1 = nullptr, *H2 = nullptr, *Y = nullptr, *dY = nullptr, *dZ2 = nullptr, *dZ1 = nullptr;
   float *res = nullptr, *loss = nullptr;
+  float* part = nullptr;                // split-K partial sums, [kSplit][max_batch][H]
   int step = 0;
   std::string err;
 };
@@ -468,7 +488,7 @@ static int egrid(long n) {
 template <bool AT, bool BT, int EPI>
 static fr_status gemm(fr_mlp_s* mm, hipStream_t st, int M, int N, int K, const bfu* A, long lda, const bfu* B,
                       long ldb, void* C, long ldc, const float* bias = nullptr, const bfu* mask = nullptr,
-                      long ldm = 0, int ksplit = 1) {
+                      long ldm = 0, int ksplit = 1, long slice = 0) {
   if (M <= 0) return FR_OK;
   // 16-byte operand rows: the contiguous dimension of each operand is a multiple of 8
   if (N % kGT || ((!AT || !BT) && K % 8) || lda % 8 || ldb % 8 || (AT && M % 8))
@@ -479,8 +499,37 @@ static fr_status gemm(fr_mlp_s* mm, hipStream_t st, int M, int N, int K, const b
   kc = (kc + kGK - 1) / kGK * kGK;
   g.kchunk = kc;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.bias = bias; g.mask = mask; g.ldm = ldm; g.C = C; g.ldc = ldc;
+  g.slice = slice;
   dim3 grid(N / kGT, (M + kGT - 1) / kGT, (K + kc - 1) / kc);
   hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), grid, dim3(256), 0, st, g);
+  MCHK(mm, hipGetLastError());
+  return FR_OK;
+}
+
+// A GEMM with a BF16 result of N = H columns: when its output has few
+// 128 x 128 tiles (a training batch) and K is long, the k range is split
+// over up to kSplit workgroups per tile, each writing FP32 partial sums to
+// its own slice, and k_split_epi adds the slices in order and applies the
+// epilogue (deterministic, unlike atomic accumulation).
+constexpr int kSplit = 16;
+template <bool AT, bool BT, int EPI>
+static fr_status gemm_narrow(fr_mlp_s* mm, hipStream_t st, int M, int N, int K, const bfu* A, long lda, const bfu* B,
+                             long ldb, bfu* C, long ldc, const float* bias = nullptr, const bfu* mask = nullptr,
+                             long ldm = 0) {
+  const long tiles = (long)((M + kGT - 1) / kGT) * (N / kGT);
+  int ks = (int)std::min<long>(kSplit, (256 + tiles - 1) / tiles);
+  ks = std::min(ks, std::max(1, K / (4 * kGK)));
+  if (ks <= 1 || M > mm->max_batch || N > mm->H)
+    return gemm<AT, BT, EPI>(mm, st, M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm);
+  int kc = (K + ks - 1) / ks;
+  kc = (kc + kGK - 1) / kGK * kGK;
+  const int nz = (K + kc - 1) / kc;
+  const long slice = (long)M * N;
+  fr_status r = gemm<AT, BT, EPI_F32_SLICE>(mm, st, M, N, K, A, lda, B, ldb, mm->part, N, nullptr, nullptr, 0, ks,
+                                            slice);
+  if (r) return r;
+  hipLaunchKernelGGL((k_split_epi<EPI>), dim3(egrid(slice)), dim3(256), 0, st, M, N, nz, mm->part, slice, bias, mask,
+                     ldm, C, ldc);
   MCHK(mm, hipGetLastError());
   return FR_OK;
 }
@@ -489,11 +538,11 @@ static fr_status gemm(fr_mlp_s* mm, hipStream_t st, int M, int N, int K, const b
 static fr_status mlp_forward(fr_mlp_s* mm, hipStream_t st, const bfu* X, long nb, bfu* Y) {
   const int H = mm->H, nin = mm->nin;
   fr_status r;
-  if ((r = gemm<false, false, EPI_BIAS_RELU>(mm, st, (int)nb, H, nin, X, nin, mm->wbf + mm->oW1, nin, mm->H1, H,
-                                             mm->w + mm->ob1)))
+  if ((r = gemm_narrow<false, false, EPI_BIAS_RELU>(mm, st, (int)nb, H, nin, X, nin, mm->wbf + mm->oW1, nin, mm->H1,
+                                                    H, mm->w + mm->ob1)))
     return r;
-  if ((r = gemm<false, false, EPI_BIAS_RELU>(mm, st, (int)nb, H, H, mm->H1, H, mm->wbf + mm->oW2, H, mm->H2, H,
-                                             mm->w + mm->ob2)))
+  if ((r = gemm_narrow<false, false, EPI_BIAS_RELU>(mm, st, (int)nb, H, H, mm->H1, H, mm->wbf + mm->oW2, H, mm->H2, H,
+                                                    mm->w + mm->ob2)))
     return r;
   return gemm<false, false, EPI_BIAS>(mm, st, (int)nb, nin, H, mm->H2, H, mm->wbf + mm->oW3, H, Y, nin,
                                       mm->w + mm->ob3);
@@ -511,23 +560,24 @@ static fr_status mlp_loss_grad(fr_mlp_s* mm, hipStream_t st, const bfu* X, long 
   hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, st, nb, res, 1.0f / (float)nb, loss);
   hipLaunchKernelGGL(k_fill_f32, dim3(egrid(mm->np)), dim3(256), 0, st, mm->np, 0.f, grad);
   const int ks = (int)((nb + 255) / 256);
-  const int rchunk = 256;
-  const dim3 cg_in((nin + 255) / 256, ks), cg_h((H + 255) / 256, ks);
+  const int rchunk = 16;                        // rows per column-sum workgroup
+  const int kr = (int)((nb + rchunk - 1) / rchunk);
+  const dim3 cg_in((nin + 255) / 256, kr), cg_h((H + 255) / 256, kr);
   // layer 3: dW3 = dY^T H2, db3 = sum dY, dZ2 = (dY W3) * (H2 > 0)
   if ((r = gemm<true, true, EPI_F32_ATOMIC>(mm, st, nin, H, (int)nb, mm->dY, nin, mm->H2, H, grad + mm->oW3, H,
                                             nullptr, nullptr, 0, ks)))
     return r;
   hipLaunchKernelGGL(k_colsum, cg_in, dim3(256), 0, st, mm->dY, (int)nb, nin, (long)nin, rchunk, grad + mm->ob3);
-  if ((r = gemm<false, true, EPI_MASK>(mm, st, (int)nb, H, nin, mm->dY, nin, mm->wbf + mm->oW3, H, mm->dZ2, H,
-                                       nullptr, mm->H2, H)))
+  if ((r = gemm_narrow<false, true, EPI_MASK>(mm, st, (int)nb, H, nin, mm->dY, nin, mm->wbf + mm->oW3, H, mm->dZ2,
+                                              H, nullptr, mm->H2, H)))
     return r;
   // layer 2
   if ((r = gemm<true, true, EPI_F32_ATOMIC>(mm, st, H, H, (int)nb, mm->dZ2, H, mm->H1, H, grad + mm->oW2, H, nullptr,
                                             nullptr, 0, ks)))
     return r;
   hipLaunchKernelGGL(k_colsum, cg_h, dim3(256), 0, st, mm->dZ2, (int)nb, H, (long)H, rchunk, grad + mm->ob2);
-  if ((r = gemm<false, true, EPI_MASK>(mm, st, (int)nb, H, H, mm->dZ2, H, mm->wbf + mm->oW2, H, mm->dZ1, H, nullptr,
-                                       mm->H1, H)))
+  if ((r = gemm_narrow<false, true, EPI_MASK>(mm, st, (int)nb, H, H, mm->dZ2, H, mm->wbf + mm->oW2, H, mm->dZ1, H,
+                                              nullptr, mm->H1, H)))
     return r;
   // layer 1
   if ((r = gemm<true, true, EPI_F32_ATOMIC>(mm, st, H, nin, (int)nb, mm->dZ1, H, X, nin, grad + mm->oW1, nin,
@@ -754,7 +804,7 @@ fr_status fr_mlp_create(int b, int hidden, uint64_t seed, int max_batch, void* h
   size_t off = 0;
   std::vector<size_t> o;
   for (size_t bytes : {np * 4, np * 4, np * 4, np * 4, np * 2, mb * H * 2, mb * H * 2, mb * nin * 2, mb * nin * 2,
-                       mb * H * 2, mb * H * 2, mb * 4, (size_t)256}) {
+                       mb * H * 2, mb * H * 2, mb * 4, (size_t)256, (size_t)kSplit * mb * H * 4}) {
     o.push_back(off);
     off += al(bytes);
   }
@@ -763,7 +813,7 @@ fr_status fr_mlp_create(int b, int hidden, uint64_t seed, int max_batch, void* h
   m->w = (float*)(p + o[0]); m->g = (float*)(p + o[1]); m->m = (float*)(p + o[2]); m->v = (float*)(p + o[3]);
   m->wbf = (bfu*)(p + o[4]); m->H1 = (bfu*)(p + o[5]); m->H2 = (bfu*)(p + o[6]); m->Y = (bfu*)(p + o[7]);
   m->dY = (bfu*)(p + o[8]); m->dZ2 = (bfu*)(p + o[9]); m->dZ1 = (bfu*)(p + o[10]);
-  m->res = (float*)(p + o[11]); m->loss = (float*)(p + o[12]);
+  m->res = (float*)(p + o[11]); m->loss = (float*)(p + o[12]); m->part = (float*)(p + o[13]);
   std::vector<float> w(np, 0.f);
   uint64_t x = seed;
   const double s1 = std::sqrt(2.0 / nin), s2 = std::sqrt(2.0 / H), s3 = 0.1 / std::sqrt((double)H);
