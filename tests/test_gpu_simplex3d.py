@@ -2,7 +2,8 @@
 meshes: R and the JVP for every system (FP64 1e-12, FP32 1e-5), the
 Jacobian blocks of tetrahedra where one element's assembly fits a
 workgroup (every block of sampled elements), blocks times a vector against
-the JVP for Euler, and the refusals (prism blocks, prisms of degree 4)."""
+the JVP for Euler, and the refusals (prism blocks, prisms of degree 4,
+tetrahedron blocks above degree 2)."""
 import numpy as np
 import pytest
 
@@ -110,4 +111,10 @@ def test_refusals():
     m4, ph4, tp4, qp4, U4 = _case("pri", "euler", 4)
     with pytest.raises(fr.FrError) as ei:
         fr.Context(m4, ph4, "f64", tri_pts=tp4)
+    assert ei.value.status == -2
+    # tetrahedron blocks above degree 2 exceed one workgroup's LDS
+    m3, ph3, tp3, qp3, U3 = _case("tet", "euler", 3)
+    ctx3 = fr.Context(m3, ph3, "f64", tri_pts=tp3, tet_pts=qp3)
+    with pytest.raises(fr.FrError) as ei:
+        ctx3.jacobian_blocks(torch.from_numpy(U3).cuda())
     assert ei.value.status == -2
