@@ -422,8 +422,10 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
 // ------------------------------------------------------------ large blocks
 // Blocks above 128 (hexahedra of degree 3: b = 320) do not fit one
 // workgroup's LDS.  Blocked right-looking LU with partial pivoting, one
-// 1024-thread workgroup per element, in 64-column panels:
-//  1. the panel (every row, 64 columns) is held in registers: wave w owns
+// 512-thread workgroup per element (two resident per CU, so that one
+// block's chain of pivot steps overlaps another's trailing update), in
+// 32-column panels:
+//  1. the panel (every row, 32 columns) is held in registers: wave w owns
 //     columns 4w .. 4w+3, lane l rows l + 64 s.  A pivot step is one
 //     barrier: the wave owning the column picks the pivot (a DPP maximum of
 //     |value| keyed with the row), forms the multipliers and publishes them
@@ -434,19 +436,21 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
 //     each panel is stored with its pivot rows at their ranks followed by
 //     the rows still to pivot in increasing physical order, so that the
 //     panel's multipliers below its first row are one contiguous range;
-//  3. the trailing columns are updated in slabs of 64: every row not
+//  3. the trailing columns are updated in slabs of 32: every row not
 //     pivoted before this panel (its pivot rows first, in pivot order) is
 //     updated by 16-column chunks of the multipliers, each chunk's pivot
 //     rows being finished first by the inverse of its 16 x 16 diagonal
-//     block of L11 (the four inverses formed once per panel).  So
+//     block of L11 (the inverses formed once per panel).  So
 //     U12 = L11^-1 A12 and A22 -= L21 U12 are one pass of 5 x 4 register
-//     tiles, with no 64-long sequential solve.
+//     tiles, with no long sequential solve.
 // The first panel reads A = shift I + scale J straight from J (no separate
 // conversion pass).  The substitution recovers each panel's row positions
 // from the ranks.
-constexpr int kLuThreads = 1024, kLuNB = 64, kLuMaxB = 320, kLuQM = (kLuMaxB + 63) / 64;
+constexpr int kLuThreads = 512, kLuNB = 32, kLuMaxB = 320, kLuQM = (kLuMaxB + 63) / 64;
 constexpr int kLuFree = 1 << 20;          // rank of a row not yet chosen as pivot
-constexpr int kLuSlab = 64;               // trailing columns per slab
+constexpr int kLuSlab = 32;               // trailing columns per slab
+static_assert(kLuNB == 4 * (kLuThreads / 64) && kLuSlab == 4 * (kLuThreads / 64), "four columns per wavefront");
+static_assert(kLuThreads == 16 * kLuSlab && kLuNB % 16 == 0, "chunk product: one thread per (row, column)");
 
 // Wave-uniform lane l's value of v.
 __device__ __forceinline__ double fr_readlane(double v, int l) {
@@ -502,7 +506,8 @@ __device__ __forceinline__ unsigned long long fr_wave_max_u64(unsigned long long
 // not pivoted by the end of panel P.  bad[n] = 1 when a pivot is zero or not
 // finite.
 template <class IT>
-__global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
+__global__ void __launch_bounds__(kLuThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_block_lu(const IT* J, long jstride, int b, double shift, double scale,
                                                          double* LU, int* perm, int* bad, const int* list) {
   __shared__ int s_rank[kLuMaxB];
   __shared__ int s_perm[kLuMaxB];
@@ -514,7 +519,7 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
   __shared__ double s_ls[16][kLuMaxB];            // a chunk of multipliers, rows in stored order
   __shared__ double s_us[16][kLuSlab];            // a chunk's pivot rows over the slab, as updated so far
   __shared__ double s_uf[16][kLuSlab];            // the same rows finished (U)
-  __shared__ double s_li[4][16][16];              // inverses of L11's four 16 x 16 diagonal blocks
+  __shared__ double s_li[kLuNB / 16][16][16];     // inverses of L11's 16 x 16 diagonal blocks
   const int n = list ? list[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const IT* Jn = J + (long)n * jstride;
@@ -646,7 +651,7 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
     const int nr = w + na;                        // rows updated (w = 64 here)
     const int rg = lane;
     __syncthreads();                              // the stored panel is read below
-    if (tid < 64) {
+    if (tid < kLuNB) {
       // inverse of diagonal block tid / 16 of the unit-lower L11, column
       // tid % 16, by forward substitution
       const int d = tid >> 4, c = tid & 15;
@@ -696,7 +701,7 @@ __global__ void __launch_bounds__(kLuThreads) k_block_lu(const IT* J, long jstri
         __syncthreads();
         {
           // the chunk's pivot rows finished: U = (diagonal block)^-1 x rows
-          const int i = tid >> 6, c = tid & 63;
+          const int i = tid / kLuSlab, c = tid % kLuSlab;
           const double(*li)[16] = s_li[q0 >> 4];
           double v = 0.0;
 #pragma unroll
