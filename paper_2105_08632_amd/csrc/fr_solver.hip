@@ -313,8 +313,9 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, 
   for (long i = (long)blockIdx.x * kOrthThreads + threadIdx.x; i < n; i += (long)gridDim.x * kOrthThreads) {
     double vv[K];
     const double* Vi = V + i;
+    // the basis is streamed (it does not fit the caches between sweeps)
 #pragma unroll
-    for (int q = 0; q < K; ++q) vv[q] = Vi[(long)q * ld];
+    for (int q = 0; q < K; ++q) vv[q] = __builtin_nontemporal_load(Vi + (long)q * ld);
     double wi = w[i];
     if constexpr (MODE >= 1) {
       // the coefficients are read from LDS (broadcast) in every iteration
