@@ -1031,7 +1031,13 @@ __device__ __forceinline__ void jac_mf_task(int n, int k, int mt, int nt, int z0
           const int c = (nt * 16 + cl / nbt) * NV + b0 + cl % nbt;
           const R* sp = stage + cl * SP + rr;
           if constexpr (std::is_same<OT, float>::value) {
-            *reinterpret_cast<float4*>(Bh + (long)c * BB + rr) = make_float4(sp[0], sp[1], sp[2], sp[3]);
+            // nontemporal 16-byte stores: the blocks are written once and
+            // not read back here (24^3 hexahedra, degree 3: 26.7 -> 25.4 ms);
+            // the BF16 blocks' 8-byte stores were 7% slower that way and
+            // stay plain
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const f4v v = {sp[0], sp[1], sp[2], sp[3]};
+            __builtin_nontemporal_store(v, reinterpret_cast<f4v*>(Bh + (long)c * BB + rr));
           } else {
             const OT q[4] = {to_out<OT>(sp[0]), to_out<OT>(sp[1]), to_out<OT>(sp[2]), to_out<OT>(sp[3])};
             uint2 w;

@@ -59,7 +59,9 @@ __device__ inline void block_matvec16(int b, const MT* M, const VT* r, double sc
     const int c = c0 + cg;
     if (c < b && row0 < b) {
       const double rc = (double)r[c] * sc;
-      const uint4 raw = *(const uint4*)(M + (long)c * b + row0);
+      // the inverses are streamed once per application (nontemporal)
+      typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+      const u4v raw = __builtin_nontemporal_load((const u4v*)(M + (long)c * b + row0));
       MT vals[V];
       __builtin_memcpy(vals, &raw, 16);
 #pragma unroll
