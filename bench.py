@@ -779,11 +779,11 @@ def main():
     ap.add_argument("--no-cfg1", action="store_true", help="skip the 2-D quadrilateral measurement")
     ap.add_argument("--no-lu", action="store_true", help="skip the block-Jacobi LU of the 3-D blocks")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 block assembly")
-    ap.add_argument("--only", choices=["cfg2", "cfg2_bf16", "cfg1", "lu", "newton", "mlp"], default=None,
+    ap.add_argument("--only", choices=["cfg2", "cfg2_bf16", "cfg1", "lu", "newton", "mlp", "batch"], default=None,
                     help="time only this workload's step: the 3-D step with FP32 or BF16 blocks, the 2-D "
                          "step, the block-Jacobi LU of the 3-D blocks, one LU-preconditioned Newton step "
-                         "on 256x256 (host-driven, then graph-replayed), or --mlp-steps steps of network "
-                         "training (profiling runs)")
+                         "on 256x256 (host-driven, then graph-replayed), --mlp-steps steps of network "
+                         "training, or the 64-mesh mixed batch (profiling runs)")
     ap.add_argument("--mlp-steps", type=int, default=24000)
     ap.add_argument("--cpu-table", action="store_true",
                     help="time the oracle on one thread and on all host threads beside the GPU for the 8x8 "
@@ -807,6 +807,9 @@ def main():
         return
     if args.only == "newton":
         print(json.dumps(newton_step_profile(torch, fr, I, log)), flush=True)
+        return
+    if args.only == "batch":
+        print(json.dumps(batch_bench(torch, fr, I, 5, log)), flush=True)
         return
     if args.only == "mlp":
         _, info = train_mlp(torch, fr, I, args.mlp_steps, log)
