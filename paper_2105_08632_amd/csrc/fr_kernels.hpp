@@ -242,16 +242,26 @@ FR_HD void grad_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, c
 
 // --------------------------------------------------------------------------
 // Pass 3: transformed flux, common flux, FR divergence, R = -div/detJ.
-template <class E, int NV, int SYS, class T, class R> constexpr int div_lds() {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+template <class E, int NV, int SYS, class T, class R, int TE = rhs_tile<E>()> constexpr int div_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC;
   return lds_bytes<int>(NF * WL) + lds_bytes<R>(NF * WL) + lds_bytes<int>(ND * NS * WL) + lds_bytes<R>(ND * NS * WL) +
          lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NF * ND) + lds_bytes<T>(TE * NS * ND * NV) +
          lds_bytes<T>(TE * NF * NV);
 }
-template <class E, int NV, int SYS, class T, class R, class IO, class Sync>
+// Elements per divergence tile: the flux and common-flux phases run one
+// thread per solution point and per flux point, so the tile is doubled while
+// those phases still fit the 256 threads and its LDS stays within 64 KB
+// (two workgroups per CU).
+template <class E, int NV, int SYS, class T, class R> constexpr int div_tile() {
+  constexpr int t = rhs_tile<E>();
+  constexpr int NP = E::NS > E::NF ? E::NS : E::NF;
+  if constexpr (2 * t * NP <= 256 && div_lds<E, NV, SYS, T, R, 2 * t>() <= 64 * 1024) return 2 * t;
+  else return t;
+}
+template <class E, int NV, int SYS, class T, class R, class IO, class Sync, int TE = rhs_tile<E>()>
 FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
                     const IO* U, const IO* V, const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, Sync sync) {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC;
   constexpr bool VISC = SysTraits<SYS>::kVisc;
   Lds L{lds};
   int* m0c = L.take<int>(NF * WL);
