@@ -8,6 +8,8 @@ specific part of it fails here:
 * the Stokes bulk term of the Newtonian stress (eq.
   "fluxOperatorNavierStokes"): a compressible manufactured field with
   div v != 0 whose exact residual -div f(u, grad u) is derived with sympy;
+  the same construction in 3-D on jittered hexahedra and in 2-D on jittered
+  triangles pins the Navier-Stokes residual pointwise on those elements;
 * the plain LU solve against numpy.linalg.solve on systems that need row
   exchanges;
 * triangles: consistency of the advection residual at the expected order;
@@ -131,6 +133,85 @@ def test_ns_compressible_stress_bulk_term():
         gaps.append(np.max(np.abs(wr - ex)))
     assert errs[1] < 0.05 * gaps[1], (errs, gaps)
     assert np.log2(errs[0] / errs[1]) > p - 1.3, errs
+
+
+def _ns_exact_residual_3d(mu, Pr, gam, bulk):
+    """The 3-D analogue of _ns_exact_residual: a manufactured primitive
+    field whose every velocity component depends on all three coordinates
+    and with div v != 0, differentiated by sympy."""
+    x, y, z = sp.symbols("x y z", real=True)
+    X = [x, y, z]
+    tp = 2 * sp.pi
+    rho = 1 + sp.Rational(1, 5) * sp.sin(tp * (x + y - z))
+    v = [sp.Rational(3, 10) * sp.sin(tp * x) + sp.Rational(1, 10) * sp.cos(tp * (y + z)),
+         sp.Rational(1, 5) * sp.cos(tp * y) - sp.Rational(1, 10) * sp.sin(tp * (x - z)),
+         sp.Rational(1, 5) * sp.sin(tp * (z + x)) + sp.Rational(1, 10) * sp.cos(tp * y)]
+    p = 5 + sp.Rational(3, 10) * sp.sin(tp * (x - y + z))
+    E = p / (gam - 1) + rho * sum(vi ** 2 for vi in v) / 2
+    divv = sum(sp.diff(v[i], X[i]) for i in range(3))
+    tau = [[mu * (sp.diff(v[i], X[d]) + sp.diff(v[d], X[i]) + (bulk * divv if i == d else 0)) for d in range(3)]
+           for i in range(3)]
+    kap = mu * gam / (Pr * (gam - 1))
+    Th = p / rho
+    F = [[rho * v[d]] + [rho * v[d] * v[i] + (p if d == i else 0) - tau[i][d] for i in range(3)]
+         + [(E + p) * v[d] - sum(tau[i][d] * v[i] for i in range(3)) - kap * sp.diff(Th, X[d])]
+         for d in range(3)]
+    R = [-sum(sp.diff(F[d][a], X[d]) for d in range(3)) for a in range(5)]
+    prim = [sp.lambdify((x, y, z), e, "numpy") for e in [rho] + v + [p]]
+    res = [sp.lambdify((x, y, z), e, "numpy") for e in R]
+    return prim, res
+
+
+def _manufactured_errors(mesh_of, Ns, p, nd, prim, exact, wrong, ph, gam, tri_pts=None):
+    """Max pointwise |R - exact| and |exact - wrong| at the solution points
+    of each mesh."""
+    errs, gaps = [], []
+    for N in Ns:
+        m = mesh_of(N)
+        o = O.Oracle(m, ph, p, tri_pts=tri_pts) if tri_pts is not None else O.Oracle(m, ph, p)
+        xs = I.sol_points_phys(m, p, tri_pts) if tri_pts is not None else I.sol_points_phys(m, p)
+        X = [xs[..., d] for d in range(nd)]
+        pr = [f(*X) * np.ones_like(X[0]) for f in prim]
+        U = I.conservative(pr[0], np.stack(pr[1:1 + nd], axis=-1), pr[-1], gam)
+        R = o.rhs(U).reshape(U.shape)
+        ex = np.stack([f(*X) * np.ones_like(X[0]) for f in exact], axis=-1)
+        wr = np.stack([f(*X) * np.ones_like(X[0]) for f in wrong], axis=-1)
+        errs.append(np.max(np.abs(R - ex)))
+        gaps.append(np.max(np.abs(wr - ex)))
+    return errs, gaps
+
+
+def test_ns_manufactured_hexahedra():
+    """3-D Navier-Stokes on jittered (trilinear) periodic hexahedra, p = 4:
+    the residual at the solution points tends to the exact -div f(u, grad u)
+    at order >= p - 1.3 (BR1 second derivatives lose one order), and the
+    error on the finer mesh is far below the effect of a -1/3 bulk
+    coefficient.  Pins the 3-D viscous terms pointwise (the z-components of
+    the stress, its work and the heat flux enter every variable)."""
+    mu, Pr, gam, p = 0.05, 0.72, 1.4, 4
+    prim, exact = _ns_exact_residual_3d(mu, Pr, gam, sp.Rational(-2, 3))
+    _, wrong = _ns_exact_residual_3d(mu, Pr, gam, sp.Rational(-1, 3))
+    ph = I.ns_physics(3, 1.0 / mu, Pr, gamma=gam)
+    errs, gaps = _manufactured_errors(lambda N: I.hex_mesh(N, degree=p, jitter=0.05, K=1), (4, 8), p, 3, prim,
+                                      exact, wrong, ph, gam)
+    assert np.log2(errs[0] / errs[1]) > p - 1.3, errs
+    assert errs[1] < 0.3 * gaps[1], (errs, gaps)
+
+
+def test_ns_manufactured_triangles():
+    """2-D Navier-Stokes on jittered split-cell triangle meshes with the
+    library's triangle point set, p = 4: the same convergence to the exact
+    residual at order >= p - 1.3, and the finer mesh's error far below the
+    effect of a -1/3 bulk coefficient."""
+    mu, Pr, gam, p = 0.05, 0.72, 1.4, 4
+    prim, exact = _ns_exact_residual(mu, Pr, gam, sp.Rational(-2, 3))
+    _, wrong = _ns_exact_residual(mu, Pr, gam, sp.Rational(-1, 3))
+    ph = I.ns_physics(2, 1.0 / mu, Pr, gamma=gam)
+    tp = I.tri_points(p)
+    errs, gaps = _manufactured_errors(lambda N: I.tri_mesh(N, degree=p, jitter=0.05, K=1, seed=3), (16, 32), p, 2,
+                                      prim, exact, wrong, ph, gam, tri_pts=tp)
+    assert np.log2(errs[0] / errs[1]) > p - 1.3, errs
+    assert errs[1] < 0.1 * gaps[1], (errs, gaps)
 
 
 # ------------------------------------------------------------- LU solve
