@@ -560,6 +560,7 @@ fr_status fr_ctx_create(const fr_mesh_desc* m, const fr_physics* ph, fr_precisio
     c->ks.mf_bytes = nullptr;
     c->ks.mf_setup = nullptr;
   }
+  c->jv_fused = c->scheme != FR_SCHEME_SDRT;   // the FR divergence pass takes the tangent shift
   if (fr_status us = upload_ops_geo(c, ref, geo, prec, ph->ldg_beta)) {
     release(c);
     return us;

@@ -43,6 +43,10 @@ struct fr_ctx_s {
   hipStream_t stream = nullptr;
   std::string err;
   KernelSet ks{};
+  // The tangent output of the FR-DG JVP is jv_a V + jv_b J V (jv_fused: the
+  // context's jvp honours them; the solver writes (I - dt J) v this way)
+  double jv_a = 0.0, jv_b = 1.0;
+  bool jv_fused = false;
   // device allocations owned by the context
   void* ops_mem = nullptr;
   void* geo_mem = nullptr;

@@ -24,11 +24,12 @@ __global__ void __launch_bounds__(kThreads) k_grad(OpsD<R> op, GeoD<R> geo, doub
 
 template <class E, int NV, int SYS, class T, class R, class IO>
 __global__ void __launch_bounds__(kThreads) k_div(OpsD<R> op, GeoD<R> geo, PhysP ph, const IO* U, const IO* V,
-                                                  const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan) {
+                                                  const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, double ta,
+                                                  double tb) {
   constexpr int TD = div_tile<E, NV, SYS, T, R>();
   __shared__ __align__(16) char lds[div_lds<E, NV, SYS, T, R, TD>()];
   div_body<E, NV, SYS, T, R, IO, DevSync, TD>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, ph, U, V, UF, Q, QF,
-                                              Rout, Rtan, DevSync());
+                                              Rout, Rtan, DevSync(), ta, tb);
 }
 
 template <class E, int NV, int SYS, class T, class R, class IO>
@@ -181,7 +182,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
     if (c->timing) fr_time_begin(c, 1);
     constexpr int TD = div_tile<E, NV, SYS, T, RC>();
     hipLaunchKernelGGL((k_div<E, NV, SYS, T, RC, IO>), dim3((ne + TD - 1) / TD), dim3(kThreads), 0, c->stream, op,
-                       geo, c->ph, U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan);
+                       geo, c->ph, U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan, c->jv_a, c->jv_b);
     FR_LAUNCH_CHECK(c);
     if (c->timing) fr_time_end(c, 1);
     return 0;
@@ -227,7 +228,7 @@ template <int ET, int P, int SYS, class R> struct Impl {
     } else {
       constexpr int TD = div_tile<E, NV, SYS, T, double>();
       hipLaunchKernelGGL((k_div<E, NV, SYS, T, double, IO>), dim3((ne + TD - 1) / TD), dim3(kThreads), 0, c->stream,
-                         op, geo, c->ph, U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan);
+                         op, geo, c->ph, U, V, (const T*)UF, (const T*)Q, (const T*)QF, Rout, Rtan, 0.0, 1.0);
     }
     FR_LAUNCH_CHECK(c);
     return 0;

@@ -258,9 +258,11 @@ template <class E, int NV, int SYS, class T, class R> constexpr int div_tile() {
   if constexpr (2 * t * NP <= 256 && div_lds<E, NV, SYS, T, R, 2 * t>() <= 64 * 1024) return 2 * t;
   else return t;
 }
+// Dual scalars: the tangent output is ta V + tb (J V).
 template <class E, int NV, int SYS, class T, class R, class IO, class Sync, int TE = rhs_tile<E>()>
 FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, const PhysP& ph,
-                    const IO* U, const IO* V, const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, Sync sync) {
+                    const IO* U, const IO* V, const T* UF, const T* Q, const T* QF, IO* Rout, IO* Rtan, Sync sync,
+                    double ta = 0.0, double tb = 1.0) {
   constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC;
   constexpr bool VISC = SysTraits<SYS>::kVisc;
   Lds L{lds};
@@ -358,8 +360,9 @@ FR_HD void div_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, co
     }
     if constexpr (!std::is_same<T, R>::value) {
       if (Rtan) {
-        Rtan[o] = IO(res.d);
-        if (!fr_finite(res.d)) fr_flag_nonfinite(geo.status, FR_NF_JVP, geo.e0 + n);
+        const R jv = (ta == 0.0 && tb == 1.0) ? res.d : R(ta * double(V[o]) + tb * double(res.d));
+        Rtan[o] = IO(jv);
+        if (!fr_finite(jv)) fr_flag_nonfinite(geo.status, FR_NF_JVP, geo.e0 + n);
       }
     }
   }

@@ -366,19 +366,50 @@ static void launch_orth(hipStream_t st, int k, long n, const double* V, long ld,
   launch_orth_k<MODE, 1>(st, k, n, V, ld, w, pin, pout, hout);
 }
 
-// The end of an Arnoldi step: |w| from the last sweep's partials; workgroup 0
-// writes the Hessenberg column H[i][j] = h1[i] + h2[i] (i <= j), H[j+1][j] =
-// |w| and dn = w.w; v_{j+1} = w / |w| (0 on breakdown).
+// The end of an Arnoldi step (graph-capturable: every scalar stays on the
+// device): |w| from the last sweep's partials and v_{j+1} = w / |w| (0 on
+// breakdown).  Workgroup 0 also completes the Hessenberg column, h[i] =
+// h1[i] + h2[i] (i <= j), h[j+1] = |w| (dn = w.w), and rotates it: the
+// previous Givens rotations, then the new one, which also rotates the
+// right-hand side g (est[j] = |g[j+1]|, the residual estimate).  The column
+// and the previous rotations are staged in LDS, so the one thread that
+// applies the rotations in sequence waits on LDS, not on memory.
 __global__ void __launch_bounds__(kOrthThreads) k_orth_finish(long n, int j, int m, const double* p2, int nblk,
                                                               const double* h1, const double* h2, const double* w,
-                                                              double* v, double* H, double* dn) {
+                                                              double* v, double* H, double* dn, double* cs,
+                                                              double* sn, double* g, double* est) {
   __shared__ double red[kOrthThreads / 64][kMaxK];
   __shared__ double nn[1];
+  __shared__ double col[kMaxK + 1], rc[kMaxK], rs[kMaxK];
   orth_sum_partials<1>(p2, nblk, 1, red, nn);
   const double hn = sqrt(fmax(nn[0], 0.0));
   if (blockIdx.x == 0) {
-    if (threadIdx.x <= j) H[threadIdx.x * m + j] = h1[threadIdx.x] + h2[threadIdx.x];
-    if (threadIdx.x == 0) { H[(j + 1) * m + j] = hn; *dn = nn[0]; }
+    const int t = threadIdx.x;
+    if (t <= j) col[t] = h1[t] + h2[t];
+    if (t == j + 1) col[t] = hn;
+    if (t < j) { rc[t] = cs[t]; rs[t] = sn[t]; }
+    if (t == 0) *dn = nn[0];
+    __syncthreads();
+    if (t == 0) {
+      for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = rc[i] * a + rs[i] * b;
+        col[i + 1] = -rs[i] * a + rc[i] * b;
+      }
+      const double a = col[j], b = col[j + 1];
+      const double r = hypot(a, b);
+      const double c = r > 0.0 ? a / r : 1.0, sv = r > 0.0 ? b / r : 0.0;
+      cs[j] = c;
+      sn[j] = sv;
+      col[j] = r;
+      col[j + 1] = 0.0;
+      const double gj = g[j];
+      g[j + 1] = -sv * gj;
+      g[j] = c * gj;
+      est[j] = fabs(sv * gj);
+    }
+    __syncthreads();
+    if (t <= j + 1) H[t * m + j] = col[t];
   }
   const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
   for (long i = (long)blockIdx.x * kOrthThreads + threadIdx.x; i < n; i += (long)gridDim.x * kOrthThreads)
@@ -396,28 +427,6 @@ __global__ void k_multi_axpy_add(long n, int k, const double* y, const double* Z
     for (int j = 0; j < k; ++j) acc += y[j] * Z[(long)j * ld + i];
     x[i] = acc;
   }
-}
-
-// ---- device-resident Arnoldi step pieces (graph-capturable: every scalar
-// stays on the device)
-// Givens rotations on Hessenberg column j (one thread): previous rotations,
-// then the new one; g is the rotated right-hand side, est[j] = |g[j+1]|.
-__global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* est) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = 0; i < j; ++i) {
-    const double a = H[i * m + j], b = H[(i + 1) * m + j];
-    H[i * m + j] = cs[i] * a + sn[i] * b;
-    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-  }
-  const double a = H[j * m + j], b = H[(j + 1) * m + j];
-  const double r = hypot(a, b);
-  cs[j] = r > 0.0 ? a / r : 1.0;
-  sn[j] = r > 0.0 ? b / r : 0.0;
-  H[j * m + j] = r;
-  H[(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  est[j] = fabs(g[j + 1]);
 }
 
 // ------------------------------------------------------------ large blocks
@@ -950,6 +959,14 @@ static fr_status axpby(fr_solver_s* s, double a, const double* x, double b, cons
 // out = A v = v - dt J(U) v (R(U) written to R_out when not null)
 static fr_status apply_A(fr_solver_s* s, const double* U, double dt, const double* v, double* out, double* R_out) {
   fr_ctx_s* c = s->ctx;
+  if (c->jv_fused) {   // the divergence pass writes v - dt J v itself
+    c->jv_a = 1.0;
+    c->jv_b = -dt;
+    const int rc = c->ks.jvp(c, U, v, out, R_out);
+    c->jv_a = 0.0;
+    c->jv_b = 1.0;
+    return (fr_status)rc;
+  }
   int rc = c->ks.jvp(c, U, v, s->tmp, R_out);
   if (rc) return (fr_status)rc;
   return axpby(s, 1.0, v, -dt, s->tmp, out);
@@ -989,8 +1006,7 @@ static fr_status arnoldi_step(fr_solver_s* s, fr_precond_s* pc, const double* U,
   launch_orth<2>(c->stream, j + 1, N, s->V, N, s->w, p1, p2, s->dh2);
   hipLaunchKernelGGL(k_orth_finish, dim3(kOrthBlocks), dim3(kOrthThreads), 0, c->stream, N, j, m, (const double*)p2,
                      kOrthBlocks, (const double*)s->dh1, (const double*)s->dh2, (const double*)s->w,
-                     s->V + (long)(j + 1) * N, s->dH, s->dn);
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, c->stream, j, m, s->dH, s->dcs, s->dsn, s->dg, s->dest);
+                     s->V + (long)(j + 1) * N, s->dH, s->dn, s->dcs, s->dsn, s->dg, s->dest);
   HIPCHK(c, hipGetLastError());
   return FR_OK;
 }
