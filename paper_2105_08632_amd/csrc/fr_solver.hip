@@ -247,18 +247,25 @@ __global__ void k_reduce_partials(int k, int nblk, const double* partial, double
   }
 }
 
-// ---- Arnoldi orthogonalisation: classical Gram-Schmidt with one
-// re-orthogonalisation, in three sweeps over the basis V_0 .. V_{K-1}:
-//   0: partial sums of V^T w
+// ---- Arnoldi orthogonalisation: classical Gram-Schmidt with selective
+// re-orthogonalisation, in up to three sweeps over the basis V_0 .. V_{K-1}:
+//   0: partial sums of V^T w and of w.w
 //   1: h1 = the sum of sweep 0's partials; w <- w - V h1, then partial sums of
-//      V^T w (each entry projected right after its update, so the basis is
-//      read once for both)
-//   2: h2 likewise; w <- w - V h2, partial sums of w.w
+//      V^T w and w.w (each entry projected right after its update, so the
+//      basis is read once for both)
+//   2: the second pass, run only where the first one cancelled: one pass
+//      leaves the new vector orthogonal to the basis up to about
+//      eps |w| / |w - V h1|, so with |w - V h1| >= |w| / 8 (the test of
+//      Daniel, Gragg, Kaufman and Stewart, with a looser bound) the sweep
+//      ends at once with h2 = 0 and the norm of sweep 1; otherwise h2 likewise,
+//      w <- w - V h2, partial sums of w.w.
 // Each workgroup of a sweep adds the previous sweep's per-workgroup partials
 // itself, in a fixed order (stream order guarantees they are complete), so
-// the results are deterministic, need no separate reduction launch and stay
-// on the device (graph-capturable).  Workgroup 0 stores h1 / h2.
+// the results, and the decision to re-orthogonalise, are the same in every
+// workgroup, need no separate reduction launch and stay on the device
+// (graph-capturable).  Workgroup 0 stores h1 / h2.
 constexpr int kOrthBlocks = 512, kOrthThreads = 512, kMaxK = 32;
+constexpr double kReorthRatio2 = 1.0 / 64.0;   // (1/8)^2: re-orthogonalise when |w - V h1|^2 < |w|^2 / 64
 
 // out[q] = sum over workgroups b < nblk of p[b][q], q < nq; every thread of
 // the workgroup gets the sums (through red, [waves][kMaxK] plus [kMaxK]).
@@ -296,17 +303,29 @@ __device__ __forceinline__ void orth_sum_partials(const double* p, int nblk, int
 
 // K = the basis size, a template argument: the K loads of an entry are issued
 // back to back without guards.
+// pw (sweep 2): sweep 0's partials, whose slot K holds w.w before the first
+// projection.
 template <int MODE, int K>
 __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, long ld, double* w, const double* pin,
-                                                       double* pout, double* hout) {
-  static_assert(K >= 1 && K <= kMaxK, "basis size");
+                                                       const double* pw, double* pout, double* hout) {
+  static_assert(K >= 1 && K < kMaxK, "basis size (slot K of the partials holds w.w)");
   __shared__ double red[kOrthThreads / 64][kMaxK];
   __shared__ double hs[kMaxK];
-  constexpr int NA = MODE == 2 ? 1 : K;
+  __shared__ double nw[1];
+  constexpr int NA = MODE == 2 ? 1 : K + 1;
   double acc[NA];
-  if constexpr (MODE >= 1) {
+  if constexpr (MODE == 1) {
     orth_sum_partials<K>(pin, gridDim.x, K, red, hs);
     if (blockIdx.x == 0 && threadIdx.x < K) hout[threadIdx.x] = hs[threadIdx.x];
+  } else if constexpr (MODE == 2) {
+    orth_sum_partials<K + 1>(pin, gridDim.x, K + 1, red, hs);   // h2, |w - V h1|^2
+    orth_sum_partials<1>(pw + K, gridDim.x, 1, red, nw);         // |w|^2
+    const bool once = hs[K] >= kReorthRatio2 * nw[0];
+    if (blockIdx.x == 0 && threadIdx.x < K) hout[threadIdx.x] = once ? 0.0 : hs[threadIdx.x];
+    if (once) {
+      if (threadIdx.x == 0) pout[(long)blockIdx.x * kMaxK] = blockIdx.x == 0 ? hs[K] : 0.0;
+      return;
+    }
   }
 #pragma unroll
   for (int q = 0; q < NA; ++q) acc[q] = 0.0;
@@ -330,6 +349,7 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, 
     if constexpr (MODE <= 1) {
 #pragma unroll
       for (int q = 0; q < K; ++q) acc[q] += vv[q] * wi;
+      acc[K] += wi * wi;
     } else {
       acc[0] += wi * wi;
     }
@@ -352,18 +372,19 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(long n, const double* V, 
 
 template <int MODE, int K>
 static void launch_orth_k(hipStream_t st, int k, long n, const double* V, long ld, double* w, const double* pin,
-                          double* pout, double* hout) {
-  if constexpr (K <= kMaxK) {
+                          const double* pw, double* pout, double* hout) {
+  if constexpr (K < kMaxK) {
     if (k == K)
-      hipLaunchKernelGGL((k_orth<MODE, K>), dim3(kOrthBlocks), dim3(kOrthThreads), 0, st, n, V, ld, w, pin, pout, hout);
+      hipLaunchKernelGGL((k_orth<MODE, K>), dim3(kOrthBlocks), dim3(kOrthThreads), 0, st, n, V, ld, w, pin, pw, pout,
+                         hout);
     else
-      launch_orth_k<MODE, K + 1>(st, k, n, V, ld, w, pin, pout, hout);
+      launch_orth_k<MODE, K + 1>(st, k, n, V, ld, w, pin, pw, pout, hout);
   }
 }
 template <int MODE>
 static void launch_orth(hipStream_t st, int k, long n, const double* V, long ld, double* w, const double* pin,
-                        double* pout, double* hout) {
-  launch_orth_k<MODE, 1>(st, k, n, V, ld, w, pin, pout, hout);
+                        const double* pw, double* pout, double* hout) {
+  launch_orth_k<MODE, 1>(st, k, n, V, ld, w, pin, pw, pout, hout);
 }
 
 // The end of an Arnoldi step (graph-capturable: every scalar stays on the
@@ -1001,9 +1022,9 @@ static fr_status arnoldi_step(fr_solver_s* s, fr_precond_s* pc, const double* U,
   double* p0 = s->opart;
   double* p1 = p0 + kOrthBlocks * kMaxK;
   double* p2 = p1 + kOrthBlocks * kMaxK;
-  launch_orth<0>(c->stream, j + 1, N, s->V, N, s->w, nullptr, p0, nullptr);
-  launch_orth<1>(c->stream, j + 1, N, s->V, N, s->w, p0, p1, s->dh1);
-  launch_orth<2>(c->stream, j + 1, N, s->V, N, s->w, p1, p2, s->dh2);
+  launch_orth<0>(c->stream, j + 1, N, s->V, N, s->w, nullptr, nullptr, p0, nullptr);
+  launch_orth<1>(c->stream, j + 1, N, s->V, N, s->w, p0, nullptr, p1, s->dh1);
+  launch_orth<2>(c->stream, j + 1, N, s->V, N, s->w, p1, p0, p2, s->dh2);
   hipLaunchKernelGGL(k_orth_finish, dim3(kOrthBlocks), dim3(kOrthThreads), 0, c->stream, N, j, m, (const double*)p2,
                      kOrthBlocks, (const double*)s->dh1, (const double*)s->dh2, (const double*)s->w,
                      s->V + (long)(j + 1) * N, s->dH, s->dn, s->dcs, s->dsn, s->dg, s->dest);

@@ -85,6 +85,27 @@ def test_newton_step_matches_dense_newton(use_pc):
     assert np.max(np.abs(Ug - Uref)) <= 1e-8 * np.max(np.abs(Uref - Ud_np))
 
 
+@pytest.mark.parametrize("use_pc", [True, False])
+def test_newton_step_with_tiny_time_step(use_pc):
+    """CFL 1e-3: A = I - dt J is close to the identity, so each new Krylov
+    vector nearly lies in the span of the basis (|w - V h1| / |w| is of the
+    order of the CFL number) and the Gram-Schmidt sweeps take their second
+    pass; the root still matches the dense oracle's."""
+    fr, m, ph, U, ctx, Ud = _setup(N=4, p=1)
+    dt = _dt(m, U, 1e-3)
+    sol = fr.Solver(ctx, restart=30)
+    pc = fr.Precond(ctx) if use_pc else None
+    res = sol.newton_step(Ud, pc=pc, dt=dt, newton_rtol=1e-10, gmres_rtol=1e-10, gmres_maxit=400)
+    assert res["converged"] == 1
+    Ug = res["U"].cpu().numpy().reshape(-1)
+    o = O.Oracle(m, ph, 1)
+    Ud_np = U.reshape(-1)
+    Uref, hist = ON.backward_euler_dense(o, Ud_np, dt, rtol=1e-12)
+    F = Ug - Ud_np - dt * o.rhs(Ug)
+    assert np.linalg.norm(F) <= 1e-9 * hist[0]
+    assert np.max(np.abs(Ug - Uref)) <= 1e-8 * np.max(np.abs(Uref - Ud_np))
+
+
 def test_preconditioner_reduces_gmres_iterations():
     fr, m, ph, U, ctx, Ud = _setup(N=8, p=3, Re=1000.0)
     dt = _dt(m, U, 1.0)
