@@ -18,8 +18,10 @@ __global__ void __launch_bounds__(kThreads) k_trace(OpsD<R> op, int ne, const IO
 template <class E, int NV, class T, class R, class IO>
 __global__ void __launch_bounds__(kThreads) k_grad(OpsD<R> op, GeoD<R> geo, double beta, const IO* U, const IO* V,
                                                    const T* UF, T* Q, T* QF) {
-  __shared__ __align__(16) char lds[grad_lds<E, NV, T, R>()];
-  grad_body<E, NV, T, R, IO>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, beta, U, V, UF, Q, QF, DevSync());
+  constexpr int GT = grad_tile<E, T>();
+  __shared__ __align__(16) char lds[grad_lds<E, NV, T, R, GT>()];
+  grad_body<E, NV, T, R, IO, DevSync, GT>(blockIdx.x, threadIdx.x, blockDim.x, lds, op, geo, beta, U, V, UF, Q, QF,
+                                          DevSync());
 }
 
 template <class E, int NV, int SYS, class T, class R, class IO>
@@ -144,8 +146,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
       hipLaunchKernelGGL((k_trace<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
       FR_LAUNCH_CHECK(c);
       if (c->visc) {
-        hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta,
-                           U, V, (const T*)UF, Q, QF);
+        constexpr int GT = grad_tile<E, T>();
+        hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3((ne + GT - 1) / GT), dim3(kThreads), 0, c->stream, op, geo,
+                           c->ph.beta, U, V, (const T*)UF, Q, QF);
         FR_LAUNCH_CHECK(c);
       }
       if (c->timing) fr_time_begin(c, 1);
@@ -175,8 +178,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
     hipLaunchKernelGGL((k_trace<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
     FR_LAUNCH_CHECK(c);
     if (c->visc) {
-      hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta, U,
-                         V, (const T*)UF, Q, QF);
+      constexpr int GT = grad_tile<E, T>();
+      hipLaunchKernelGGL((k_grad<E, NV, T, RC, IO>), dim3((ne + GT - 1) / GT), dim3(kThreads), 0, c->stream, op, geo,
+                         c->ph.beta, U, V, (const T*)UF, Q, QF);
       FR_LAUNCH_CHECK(c);
     }
     if (c->timing) fr_time_begin(c, 1);
@@ -223,8 +227,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
       hipLaunchKernelGGL((k_trace<E, NV, T, double, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, V, UF);
     } else if (which == 1) {
       if (!c->visc) return 0;
-      hipLaunchKernelGGL((k_grad<E, NV, T, double, IO>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta,
-                         U, V, (const T*)UF, Q, QF);
+      constexpr int GT = grad_tile<E, T>();
+      hipLaunchKernelGGL((k_grad<E, NV, T, double, IO>), dim3((ne + GT - 1) / GT), dim3(kThreads), 0, c->stream, op,
+                         geo, c->ph.beta, U, V, (const T*)UF, Q, QF);
     } else {
       constexpr int TD = div_tile<E, NV, SYS, T, double>();
       hipLaunchKernelGGL((k_div<E, NV, SYS, T, double, IO>), dim3((ne + TD - 1) / TD), dim3(kThreads), 0, c->stream,
@@ -318,8 +323,9 @@ template <int ET, int P, int SYS, class R> struct Impl {
     hipLaunchKernelGGL((k_trace<E, NV, R, R, R>), dim3(nt), dim3(kThreads), 0, c->stream, op, ne, U, (const R*)nullptr, UF);
     FR_LAUNCH_CHECK(c);
     if (c->visc) {
-      hipLaunchKernelGGL((k_grad<E, NV, R, R, R>), dim3(nt), dim3(kThreads), 0, c->stream, op, geo, c->ph.beta, U,
-                         (const R*)nullptr, (const R*)UF, Q, QF);
+      constexpr int GT = grad_tile<E, R>();
+      hipLaunchKernelGGL((k_grad<E, NV, R, R, R>), dim3((ne + GT - 1) / GT), dim3(kThreads), 0, c->stream, op, geo,
+                         c->ph.beta, U, (const R*)nullptr, (const R*)UF, Q, QF);
       FR_LAUNCH_CHECK(c);
     }
     if constexpr (kMfmaPath) {

@@ -173,16 +173,23 @@ FR_HD void trace_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, 
 // --------------------------------------------------------------------------
 // Pass 2 (viscous systems): corrected physical gradient q at solution points
 // and its face trace q^f = M0 q.
-template <class E, int NV, class T, class R> constexpr int grad_lds() {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+// Elements per gradient tile: 2-D dual-number tiles take half the residual
+// tile (their LDS is twice as large; with more workgroups per CU the 2-D
+// NS p=3 tangent pass ran 109 -> 96 us).
+template <class E, class T> constexpr int grad_tile() {
+  constexpr int t = rhs_tile<E>();
+  return (E::ND == 2 && sizeof(T) > 8 && t > 1) ? t / 2 : t;
+}
+template <class E, int NV, class T, class R, int TE = rhs_tile<E>()> constexpr int grad_lds() {
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC;
   return lds_bytes<int>(NF * WL) + lds_bytes<R>(NF * WL) + lds_bytes<int>(ND * NS * WL) + lds_bytes<R>(ND * NS * WL) +
          lds_bytes<int>(NS * WC) + lds_bytes<R>(NS * WC) + lds_bytes<R>(NF * ND) + lds_bytes<T>(TE * NS * NV) +
          lds_bytes<T>(TE * NF * NV) + lds_bytes<T>(TE * NS * ND * NV);
 }
-template <class E, int NV, class T, class R, class IO, class Sync>
+template <class E, int NV, class T, class R, class IO, class Sync, int TE = rhs_tile<E>()>
 FR_HD void grad_body(int tile, int tid, int nth, char* lds, const OpsD<R>& op, const GeoD<R>& geo, double beta,
                      const IO* U, const IO* V, const T* UF, T* Q, T* QF, Sync sync) {
-  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC, TE = rhs_tile<E>();
+  constexpr int NS = E::NS, NF = E::NF, ND = E::ND, WL = E::WL, WC = E::WC;
   Lds L{lds};
   int* m0c = L.take<int>(NF * WL);
   R* m0v = L.take<R>(NF * WL);
