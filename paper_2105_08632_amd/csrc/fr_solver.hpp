@@ -54,7 +54,9 @@ __device__ inline void block_matvec16(int b, const MT* M, const VT* r, double sc
   double a[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) a[i] = 0.0;
-#pragma unroll 4
+  // unrolled so that every load of a 64-row block can be in flight (FP32
+  // blocks: 65 536 applications 0.190 -> 0.172 ms; FP64 unchanged)
+#pragma unroll 16
   for (int c0 = 0; c0 < b; c0 += V) {
     const int c = c0 + cg;
     if (c < b && row0 < b) {
