@@ -112,6 +112,51 @@ __global__ void __launch_bounds__(kInvThreads) k_block_inverse(const IT* J, long
   if (tid == 0) bad[n] = s_bad;
 }
 
+// Wave-uniform lane l's value of v.
+__device__ __forceinline__ double fr_readlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane l's value of x[s] for wave-uniform s and l: every slot is read with
+// readlane and the slot chosen among the scalars (selecting the register
+// first would turn into an indexed access to scratch memory).
+template <int N>
+__device__ __forceinline__ double fr_lane_slot(const double (&x)[N], int s, int l) {
+  double v = fr_readlane(x[0], l);
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    const double o = fr_readlane(x[i], l);
+    v = s == i ? o : v;
+  }
+  return v;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long fr_max_dpp(unsigned long long v) {
+  const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+  const unsigned lo2 = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const unsigned hi2 = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  const unsigned long long o = ((unsigned long long)hi2 << 32) | lo2;
+  return o > v ? o : v;
+}
+
+// Maximum over the wavefront by DPP: quad swaps, half-row and row mirrors
+// (every row of 16 lanes then holds its maximum), then the row broadcasts
+// 15 and 31 (lane 63 ends with the maximum of all four rows).
+__device__ __forceinline__ unsigned long long fr_wave_max_u64(unsigned long long v) {
+  v = fr_max_dpp<0xB1, 0xF>(v);
+  v = fr_max_dpp<0x4E, 0xF>(v);
+  v = fr_max_dpp<0x141, 0xF>(v);
+  v = fr_max_dpp<0x140, 0xF>(v);
+  v = fr_max_dpp<0x142, 0xA>(v);
+  v = fr_max_dpp<0x143, 0xC>(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Blocks up to 64 x 64: one wavefront per element, row r of A_n held in the
 // registers of lane r.  Gauss-Jordan exchange steps without row
 // interchanges: step k takes as pivot the unused row p_k with the largest
@@ -147,19 +192,24 @@ __global__ void __launch_bounds__(256) k_block_inverse_w64(const IT* J, long jst
   for (int k = 0; k < b; ++k) {
     const double a0 = a[0];
     const double av = fabs(a0);
-    double v = used ? -2.0 : (av == av ? av : -1.0);   // NaN rows rank below zero rows
-    int idx = lane;
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      const double ov = __shfl_xor(v, m, 64);
-      const int oi = __shfl_xor(idx, m, 64);
-      if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-    }
-    const int p = __builtin_amdgcn_readfirstlane(idx);
-    const double pv = __shfl(a0, p, 64);
-    const bool ok = (v > 0.0) && isfinite(pv);
+    // pivot search as one DPP maximum over 64-bit keys, 63 - row in the
+    // lowest 6 bits (ties go to the lowest row): rows already used 0,
+    // not-a-number rows 0x40 | .. (below zero rows), others the bits of
+    // |value| above the lowest 8 (ties to 2^-44 relative) | 0x80 | ..
+    const unsigned long long lo6 = (unsigned long long)(63 - lane);
+    const unsigned long long key =
+        used ? 0ull
+             : (av == av ? ((unsigned long long)__double_as_longlong(av) & ~0xFFull) | 0x80ull | lo6 : 0x40ull | lo6);
+    const unsigned long long kmax = fr_wave_max_u64(key);
+    const int p = 63 - (int)(kmax & 0x3Full);
+    const double pv = fr_readlane(a0, p);
+    const bool ok = kmax >= 0x80ull && fabs(pv) > 0.0 && isfinite(pv);
     sbad |= !ok;
-    const double ip = ok ? 1.0 / pv : 0.0;
+    // 1 / pv: hardware reciprocal and two Newton steps
+    double ip = __builtin_amdgcn_rcp(pv);
+    ip = fma(ip, fma(-pv, ip, 1.0), ip);
+    ip = fma(ip, fma(-pv, ip, 1.0), ip);
+    ip = ok ? ip : 0.0;
     const bool is_p = lane == p;
     if (is_p) {
 #pragma unroll
@@ -491,51 +541,6 @@ constexpr int kLuFree = 1 << 20;          // rank of a row not yet chosen as piv
 constexpr int kLuSlab = 32;               // trailing columns per slab
 static_assert(kLuNB == 4 * (kLuThreads / 64) && kLuSlab == 4 * (kLuThreads / 64), "four columns per wavefront");
 static_assert(kLuThreads == 16 * kLuSlab && kLuNB % 16 == 0, "chunk product: one thread per (row, column)");
-
-// Wave-uniform lane l's value of v.
-__device__ __forceinline__ double fr_readlane(double v, int l) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)u, l), hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Lane l's value of x[s] for wave-uniform s and l: every slot is read with
-// readlane and the slot chosen among the scalars (selecting the register
-// first would turn into an indexed access to scratch memory).
-template <int N>
-__device__ __forceinline__ double fr_lane_slot(const double (&x)[N], int s, int l) {
-  double v = fr_readlane(x[0], l);
-#pragma unroll
-  for (int i = 1; i < N; ++i) {
-    const double o = fr_readlane(x[i], l);
-    v = s == i ? o : v;
-  }
-  return v;
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ unsigned long long fr_max_dpp(unsigned long long v) {
-  const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
-  const unsigned lo2 = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
-  const unsigned hi2 = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
-  const unsigned long long o = ((unsigned long long)hi2 << 32) | lo2;
-  return o > v ? o : v;
-}
-
-// Maximum over the wavefront by DPP: quad swaps, half-row and row mirrors
-// (every row of 16 lanes then holds its maximum), then the row broadcasts
-// 15 and 31 (lane 63 ends with the maximum of all four rows).
-__device__ __forceinline__ unsigned long long fr_wave_max_u64(unsigned long long v) {
-  v = fr_max_dpp<0xB1, 0xF>(v);
-  v = fr_max_dpp<0x4E, 0xF>(v);
-  v = fr_max_dpp<0x141, 0xF>(v);
-  v = fr_max_dpp<0x140, 0xF>(v);
-  v = fr_max_dpp<0x142, 0xA>(v);
-  v = fr_max_dpp<0x143, 0xC>(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
-  return ((unsigned long long)hi << 32) | lo;
-}
 
 // A = shift I + scale J (column-major, input type IT) factorized with partial
 // pivoting.  perm[i] = the row (of A) chosen as pivot at step i.  Storage
